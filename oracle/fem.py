@@ -1,0 +1,159 @@
+"""Element stiffness matrices of rectangular-prism Lagrange elements.
+
+Follows Sec. 2 eq. (1) (K^(e) = E * integral of B^T D B over the element) and
+Sec. 3.3 (the integral over [-1,1]^3 split into n^3 sub-boxes, one matrix
+K^(e_i) per density sub-element, each computed once for a regular mesh).
+
+* Shape functions: tensor-product Lagrange polynomials on equally spaced
+  nodes (degree 1: 8 nodes, 2: 27 nodes, 3: 64 nodes; Sec. 2.1).
+  Local node a = ax + (p+1)*(ay + (p+1)*az); local DOF = 3a + c.
+* D: isotropic linear elasticity, Voigt order (xx, yy, zz, xy, yz, zx),
+  engineering shear strains (textbook; the paper only names "the matrix of
+  elastic parameters").
+* Geometry: element of size 2l x 2h x 2w with xi = x/l etc., so
+  dOmega = l*h*w dxi deta dzeta (Sec. 3.3).  Unit elements: l = h = w = 1/2.
+* Sub-box i of the n^3 split covers [-1 + 2a/n, -1 + 2(a+1)/n] per axis in
+  local coordinates (the interval length is 2/n in local units, i.e. 1/n of
+  the element edge; see the reading listed with the oracle's design notes).
+* Quadrature: p+1 Gauss-Legendre points per axis on each sub-box, which is
+  exact for the polynomial integrand of degree <= 2p per axis.
+
+Pins (tests/test_oracle_fem.py): symmetry; rank 3*n_e - 6 (Table 1: 18, 75,
+186); six rigid-body modes in the null space; the hand-derived diagonal
+(D11 + 2G)/9 of the unit Q1 cube; the strain energy of a uniform strain field
+equals (volume) * eps^T D eps (closed form per strain state); sum of the
+sub-element matrices equals the single-element matrix; each sub-matrix
+carries exactly its sub-volume's share of a uniform-strain energy.
+"""
+
+import numpy as np
+
+
+def lagrange_1d(order):
+    """Nodes, values and derivatives of the 1-D Lagrange basis on [-1, 1]."""
+    nodes = np.linspace(-1.0, 1.0, order + 1)
+
+    def val(xi):
+        xi = np.asarray(xi, dtype=np.float64)
+        out = np.ones((order + 1,) + xi.shape)
+        for k in range(order + 1):
+            for m in range(order + 1):
+                if m != k:
+                    out[k] *= (xi - nodes[m]) / (nodes[k] - nodes[m])
+        return out
+
+    def der(xi):
+        xi = np.asarray(xi, dtype=np.float64)
+        out = np.zeros((order + 1,) + xi.shape)
+        for k in range(order + 1):
+            for j in range(order + 1):
+                if j == k:
+                    continue
+                term = np.ones(xi.shape) / (nodes[k] - nodes[j])
+                for m in range(order + 1):
+                    if m != k and m != j:
+                        term = term * (xi - nodes[m]) / (nodes[k] - nodes[m])
+                out[k] += term
+        return out
+
+    return nodes, val, der
+
+
+def elasticity_matrix(E=1.0, nu=0.3):
+    """Isotropic D in Voigt order (xx, yy, zz, xy, yz, zx), engineering shear."""
+    c = E / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    D = np.zeros((6, 6))
+    D[:3, :3] = c * nu
+    for i in range(3):
+        D[i, i] = c * (1.0 - nu)
+    for i in range(3, 6):
+        D[i, i] = E / (2.0 * (1.0 + nu))
+    return D
+
+
+def strain_displacement(order, xi, eta, zeta, half=(0.5, 0.5, 0.5)):
+    """B (6 x 3*n_e) at one local point of an element of half-sizes
+    (l, h, w)."""
+    _, val, der = lagrange_1d(order)
+    vx, vy, vz = val(xi), val(eta), val(zeta)
+    dx, dy, dz = der(xi) / half[0], der(eta) / half[1], der(zeta) / half[2]
+    p1 = order + 1
+    nen = p1 ** 3
+    B = np.zeros((6, 3 * nen))
+    for az in range(p1):
+        for ay in range(p1):
+            for ax in range(p1):
+                a = ax + p1 * (ay + p1 * az)
+                gx = dx[ax] * vy[ay] * vz[az]
+                gy = vx[ax] * dy[ay] * vz[az]
+                gz = vx[ax] * vy[ay] * dz[az]
+                u, v, w = 3 * a, 3 * a + 1, 3 * a + 2
+                B[0, u] = gx
+                B[1, v] = gy
+                B[2, w] = gz
+                B[3, u], B[3, v] = gy, gx
+                B[4, v], B[4, w] = gz, gy
+                B[5, w], B[5, u] = gx, gz
+    return B
+
+
+def sub_element_matrices(order, nsub, nu=0.3, E=1.0, half=(0.5, 0.5, 0.5)):
+    """The n^3 matrices K^(e_i) of one displacement element (Sec. 3.3), as an
+    array [n^3, 3n_e, 3n_e]; sub-element i = sx + n*(sy + n*sz)."""
+    D = elasticity_matrix(E, nu)
+    gp, gw = np.polynomial.legendre.leggauss(order + 1)
+    jac = half[0] * half[1] * half[2]
+    nen = (order + 1) ** 3
+    out = np.zeros((nsub ** 3, 3 * nen, 3 * nen))
+    edges = np.linspace(-1.0, 1.0, nsub + 1)
+    for sz in range(nsub):
+        for sy in range(nsub):
+            for sx in range(nsub):
+                K = np.zeros((3 * nen, 3 * nen))
+                lo = (edges[sx], edges[sy], edges[sz])
+                hi = (edges[sx + 1], edges[sy + 1], edges[sz + 1])
+                mid = [(a + b) / 2 for a, b in zip(lo, hi)]
+                rad = [(b - a) / 2 for a, b in zip(lo, hi)]
+                for qz, wz in zip(gp, gw):
+                    for qy, wy in zip(gp, gw):
+                        for qx, wx in zip(gp, gw):
+                            B = strain_displacement(
+                                order, mid[0] + rad[0] * qx, mid[1] + rad[1] * qy,
+                                mid[2] + rad[2] * qz, half)
+                            wgt = wx * wy * wz * rad[0] * rad[1] * rad[2] * jac
+                            K += wgt * (B.T @ D @ B)
+                out[sx + nsub * (sy + nsub * sz)] = K
+    return out
+
+
+def element_matrix(order, nu=0.3, E=1.0):
+    """Single-resolution element stiffness, integral over the whole element."""
+    return sub_element_matrices(order, 1, nu, E)[0]
+
+
+def local_node_coords(order):
+    """Physical coordinates (unit element, origin at the corner) of the local
+    nodes, shape [n_e, 3]."""
+    p1 = order + 1
+    t = np.linspace(0.0, 1.0, p1)
+    out = []
+    for az in range(p1):
+        for ay in range(p1):
+            for ax in range(p1):
+                out.append((t[ax], t[ay], t[az]))
+    return np.array(out)
+
+
+def rigid_body_modes(coords):
+    """Six rigid-body displacement fields (3 translations, 3 infinitesimal
+    rotations) sampled at the given node coordinates, shape [6, 3*n]."""
+    n = coords.shape[0]
+    R = np.zeros((6, 3 * n))
+    x, y, z = coords[:, 0], coords[:, 1], coords[:, 2]
+    for c in range(3):
+        R[c, c::3] = 1.0
+    # rotation about z: (-y, x, 0); about x: (0, -z, y); about y: (z, 0, -x)
+    R[3, 0::3], R[3, 1::3] = -y, x
+    R[4, 1::3], R[4, 2::3] = -z, y
+    R[5, 0::3], R[5, 2::3] = z, -x
+    return R

@@ -1,0 +1,96 @@
+"""Pins of the oracle's multigrid components."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import assemble, fem, multigrid, solve
+
+MAT = dict(E0=1.0, Emin=1e-9, penal=3.0)
+
+
+def test_prolongation_reproduces_multilinear_fields():
+    """Trilinear interpolation is exact for fields that are linear in each
+    coordinate separately."""
+    dc = (4, 3, 3)
+    P = multigrid.prolongation(dc)
+    df = tuple(2 * (d - 1) + 1 for d in dc)
+
+    def field(dims, scale):
+        nx, ny, nz = dims
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        x, y, z = i.ravel() * scale, j.ravel() * scale, k.ravel() * scale
+        return np.stack([(1 + 0.3 * x) * (2 - 0.1 * y) * (0.5 + z),
+                         x * y * z - 2 * x + 3,
+                         (x - 1) * (z + 0.25)], 1).ravel()
+
+    assert np.abs(P @ field(dc, 1.0) - field(df, 0.5)).max() < 1e-12
+    # each fine node's weights sum to one (partition of unity)
+    assert np.allclose(np.asarray(P.sum(1)).ravel(), 1.0)
+
+
+def test_galerkin_of_constant_modulus_is_rediscretisation():
+    """For uniform E and no supports, P^T K_h P equals the operator assembled
+    from elements of twice the size (which in 3-D is 2 * K0 per element)."""
+    nel = (4, 2, 2)
+    Ks = fem.sub_element_matrices(1, 1)
+    Kh = assemble.stiffness(np.ones((2, 2, 4)), nel, 1, 1, Ks, **MAT)
+    P = multigrid.prolongation(assemble.node_dims((2, 1, 1), 1))
+    KH = assemble.assemble(np.repeat(2.0 * Ks, 2, axis=0), (2, 1, 1), 1)
+    assert abs(P.T @ Kh @ P - KH).max() < 1e-13
+
+
+def test_galerkin_masked_definition():
+    """A_c = P~^T A_f P~ + (I - Z_c): symmetric, identity on coarse fixed DOFs,
+    and the coarse system restricted to free DOFs is positive definite."""
+    nel = (4, 4, 2)
+    mask, f = W.make_problem("mbb", *nel, 1, 1)
+    rho = W.uniform_field((2, 4, 4), 2, 0.1, 1.0)
+    K = assemble.stiffness(rho, nel, 1, 1, fem.sub_element_matrices(1, 1), **MAT)
+    A0 = assemble.level_operator(K, mask)
+    H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, 1), 2)
+    Ac = H.A[1].toarray()
+    assert np.abs(Ac - Ac.T).max() < 1e-15
+    mc = H.mask[1].astype(bool)
+    assert np.allclose(Ac[np.ix_(mc, mc)], np.eye(mc.sum()))
+    assert np.abs(Ac[np.ix_(mc, ~mc)]).max() == 0
+    assert np.linalg.eigvalsh(Ac[np.ix_(~mc, ~mc)]).min() > 0
+
+
+def test_vcycle_is_spd_with_convergent_smoother():
+    """With a convergent Jacobi smoother (omega < 2 / lambda_max(D^-1 A)) and
+    symmetric pre/post smoothing, the V-cycle is a symmetric positive
+    definite linear operator."""
+    nel = (4, 2, 2)
+    mask, f = W.make_problem("cantilever", *nel, 1, 1)
+    rho = W.uniform_field((2, 2, 4), 4, 0.5, 1.0)
+    K = assemble.stiffness(rho, nel, 1, 1, fem.sub_element_matrices(1, 1), **MAT)
+    H = multigrid.Hierarchy(assemble.level_operator(K, mask), mask,
+                            assemble.node_dims(nel, 1), 2)
+    n = H.A[0].shape[0]
+    free = np.flatnonzero(mask == 0)
+    Mm = np.zeros((n, n))
+    for i in free:
+        e = np.zeros(n)
+        e[i] = 1.0
+        Mm[:, i] = multigrid.vcycle(H, e, omega=0.4)
+    Mf = Mm[np.ix_(free, free)]
+    assert np.abs(Mf - Mf.T).max() < 1e-10 * np.abs(Mf).max()
+    assert np.linalg.eigvalsh(0.5 * (Mf + Mf.T)).min() > 0
+
+
+@pytest.mark.parametrize("kind,order,nel,nlev", [("cantilever", 1, (8, 4, 4), 3),
+                                                 ("mbb", 1, (8, 4, 4), 3),
+                                                 ("cantilever", 2, (4, 2, 2), 3)])
+def test_mgcg_matches_direct(kind, order, nel, nlev):
+    mask, f = W.make_problem(kind, *nel, order, 2)
+    rho = W.gaussian_random_field((nel[2] * 2, nel[1] * 2, nel[0] * 2), 7, corr=3.0)
+    Ks = fem.sub_element_matrices(order, 2)
+    K = assemble.stiffness(rho, nel, order, 2, Ks, **MAT)
+    ud = solve.solve_direct(K, mask, f)
+    um, info = solve.solve_mgcg(K, mask, f, assemble.node_dims(nel, order), nlev, rtol=1e-10,
+                                omega=0.5)
+    for l in range(2):
+        assert info[l][1] <= 1e-10
+        assert np.linalg.norm(um[l] - ud[l]) <= 1e-7 * np.linalg.norm(ud[l])

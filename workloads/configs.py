@@ -1,0 +1,105 @@
+"""The five synthetic workloads of the MGCG hot path (sizes, material, solver
+settings and seeds), plus the served request mix.
+
+Material of every workload: E0 = 1, Emin = 1e-9, nu = 0.3, SIMP p = 3
+(the paper's values for its adaptive runs; unit cube elements).
+"""
+
+import numpy as np
+
+from .fields import uniform_field, gaussian_random_field, perturb
+from .loads import make_problem
+
+MATERIAL = dict(E0=1.0, Emin=1e-9, nu=0.3, penal=3.0)
+
+CONFIGS = {
+    # plain FP64, single resolution, small (the oracle finishes it in seconds)
+    "c1": dict(name="cantilever Q1 24x12x12 n=1 fp64", kind="cantilever",
+               nel=(24, 12, 12), order=1, nsub=1, nlevels=3, nrhs=1,
+               precision="fp64", omega=0.6, pre=1, post=1,
+               field="uniform", seed=1),
+    # plain FP64 at scale, warm-started over 10 SLP-like perturbations
+    "c2": dict(name="cantilever Q1 96x48x48 n=1 fp64", kind="cantilever",
+               nel=(96, 48, 48), order=1, nsub=1, nlevels=5, nrhs=1,
+               precision="fp64", omega=0.6, pre=1, post=1,
+               field="grf", seed=2, perturb_seeds=list(range(2001, 2011))),
+    # multiresolution n=4 + mixed precision + adjoint
+    "c3": dict(name="cantilever Q1 64x32x32 n=4 mixed", kind="cantilever",
+               nel=(64, 32, 32), order=1, nsub=4, nlevels=5, nrhs=1,
+               precision="mixed", omega=0.6, pre=1, post=1,
+               field="grf", seed=3),
+    # quadratic elements, n=4, two load cases
+    "c4": dict(name="cantilever Q2 48x24x24 n=4 2rhs mixed", kind="cantilever",
+               nel=(48, 24, 24), order=2, nsub=4, nlevels=5, nrhs=2,
+               precision="mixed", omega=0.6, pre=1, post=1,
+               field="grf", seed=4),
+}
+
+SERVE_MESHES = [(32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48), (128, 64, 64)]
+SERVE_NSUB = [1, 2, 4]
+SERVE_KINDS = ["cantilever", "mbb", "torsion"]
+
+
+def config(name):
+    return dict(CONFIGS[name])
+
+
+def densities(cfg, seed=None):
+    """Density field of a workload, C-order (nz*n, ny*n, nx*n)."""
+    n = cfg["nsub"]
+    nx, ny, nz = cfg["nel"]
+    shape = (nz * n, ny * n, nx * n)
+    s = cfg["seed"] if seed is None else seed
+    if cfg["field"] == "uniform":
+        return uniform_field(shape, s, 0.05, 1.0)
+    return gaussian_random_field(shape, s, corr=6.0, rho_min=1e-3, volfrac=0.3)
+
+
+def problem(cfg):
+    nx, ny, nz = cfg["nel"]
+    return make_problem(cfg["kind"], nx, ny, nz, cfg["order"], cfg["nrhs"])
+
+
+def coarsest_levels(nel, order=1, max_coarse_dof=2500):
+    """Number of multigrid levels for a served mesh: halve while every
+    element count stays even and the coarse lattice is still large."""
+    nx, ny, nz = nel
+    levels = 2 if order == 2 else 1
+    cx, cy, cz = nx, ny, nz
+    while cx % 2 == 0 and cy % 2 == 0 and cz % 2 == 0 and \
+            3 * (cx + 1) * (cy + 1) * (cz + 1) > max_coarse_dof:
+        cx, cy, cz = cx // 2, cy // 2, cz // 2
+        levels += 1
+    return levels
+
+
+def serve_requests(n=256, seed=5, rate=None, solves_per_session=5):
+    """The served mix: Poisson arrivals (times in seconds for `rate` requests
+    per second; `None` leaves arrival times unset), uniform choices of
+    structure, mesh, density subdivision and 1-4 load cases."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for r in range(n):
+        if rate is not None:
+            t += rng.exponential(1.0 / rate)
+        kind = SERVE_KINDS[rng.integers(len(SERVE_KINDS))]
+        mesh = SERVE_MESHES[rng.integers(len(SERVE_MESHES))]
+        nsub = SERVE_NSUB[rng.integers(len(SERVE_NSUB))]
+        nrhs = int(rng.integers(1, 5))
+        out.append(dict(id=r, arrival=t if rate is not None else None, kind=kind,
+                        nel=mesh, nsub=nsub, nrhs=nrhs, order=1,
+                        nlevels=coarsest_levels(mesh),
+                        seed=50000 + r,
+                        perturb_seeds=[60000 + 10 * r + s for s in range(1, solves_per_session)]))
+    return out
+
+
+def request_densities(req):
+    n = req["nsub"]
+    nx, ny, nz = req["nel"]
+    return gaussian_random_field((nz * n, ny * n, nx * n), req["seed"])
+
+
+__all__ = ["MATERIAL", "CONFIGS", "config", "densities", "problem", "serve_requests",
+           "request_densities", "coarsest_levels", "perturb"]

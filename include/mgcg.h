@@ -1,0 +1,212 @@
+/*
+ * mgcg.h — C ABI of the MI355X (gfx950) multigrid-preconditioned conjugate
+ * gradient solver for the SIMP linear-elasticity equilibrium K(rho) u = f on
+ * structured hexahedral meshes, with compliance and density gradients.
+ *
+ * The operation (Vitorino & Gomes, "An efficient topology optimization
+ * algorithm for large-scale three-dimensional structures"):
+ *   - element stiffness with the modified SIMP law, Sec. 2 eq. (1):
+ *       K^(e) = (Emin + rho_e^p (E0 - Emin)) * integral of B^T D B;
+ *   - multiresolution elements holding n^3 density sub-elements, Sec. 3.3
+ *     eq. (7): K^(e) = sum_i (Emin + rho_{e_i}^p (E0 - Emin)) K^(e_i);
+ *   - global K by superposition, supported DOFs removed (Sec. 2, 3.3, 6.1);
+ *   - the solve by CG preconditioned with geometric multigrid (Sec. 2.3,
+ *     Algorithm 1 applied recursively as a V-cycle; coarse element = 2x2x2
+ *     fine elements, trilinear prolongation P, restriction R = P^T,
+ *     weighted-Jacobi smoothing, Galerkin coarse operators, dense Cholesky
+ *     on the coarsest mesh; stop on the relative residual, Sec. 7.2.1;
+ *     warm start from the previous solution, Sec. 7.2.1);
+ *   - compliance c = f^T u (problem (2)) and its gradient with respect to the
+ *     densities, Sec. 3.4: dc/drho_i = -p rho_i^{p-1} (E0 - Emin)
+ *     u_e^T K^(e_i) u_e (summed over load cases).
+ *
+ * Conventions
+ *   Node lattice of an order-p mesh with nelx x nely x nelz elements:
+ *   NX = p*nelx + 1 (same for y, z); node = i + NX*(j + NY*k), x fastest;
+ *   DOF = 3*node + c (c = x, y, z).  Vectors of several load cases are
+ *   stored one after another: [nrhs][ndof].  Densities: the C-order array
+ *   (n*nelz, n*nely, n*nelx), i.e. index ix + (n*nelx)*(iy + (n*nely)*iz).
+ *   Elements are unit cubes.
+ *
+ * Ownership
+ *   The caller owns every buffer it passes.  Input buffers are read before the
+ *   call returns (device inputs: read in stream order on the problem's
+ *   stream); output buffers are written before the call returns (device
+ *   outputs: written in stream order, complete once the stream is
+ *   synchronised — every call below that returns results on the host
+ *   synchronises the stream itself).  The library owns all hierarchy memory
+ *   and frees it in mgcg_problem_destroy.  One problem is used by one host
+ *   thread at a time.
+ *
+ * Errors
+ *   Every int-returning call returns MGCG_OK (0), MGCG_ENOTCONV (1: result
+ *   written but the tolerance was not reached) or a negative code; the
+ *   thread-local message of the last failure is returned by mgcg_last_error.
+ *   No C++ exception crosses this interface.
+ */
+#ifndef MGCG_H
+#define MGCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGCG_OK 0
+#define MGCG_ENOTCONV 1      /* max iterations reached; info and u written */
+#define MGCG_EINVAL (-1)     /* invalid argument or density (NaN, outside [0,1]) */
+#define MGCG_ENOMEM (-2)     /* device allocation failed */
+#define MGCG_EBUDGET (-3)    /* request larger than the server's HBM budget */
+#define MGCG_EBREAKDOWN (-4) /* CG breakdown: p^T A p <= 0 or non-finite */
+#define MGCG_EDEVICE (-5)    /* HIP runtime error */
+#define MGCG_EAGAIN (-6)     /* server: the request has not finished yet */
+#define MGCG_ESTATE (-7)     /* call out of order (e.g. solve before densities) */
+
+#define MGCG_FP64 0  /* FP64 everywhere */
+#define MGCG_MIXED 1 /* FP32 V-cycle inside an FP64 CG (FP64 coarsest Cholesky) */
+
+#define MGCG_MEM_HOST 0
+#define MGCG_MEM_DEVICE 1
+
+typedef struct mgcg_problem mgcg_problem;
+typedef struct mgcg_server mgcg_server;
+
+/* Problem description.  Elements are unit cubes. */
+typedef struct mgcg_desc {
+  int32_t nelx, nely, nelz; /* displacement elements per axis (>= 1) */
+  int32_t order;            /* 1: 8-node trilinear, 2: 27-node triquadratic */
+  int32_t nsub;             /* density sub-elements per axis per element (n_mr >= 1) */
+  int32_t nlevels;          /* multigrid levels including the finest (>= 1); every
+                               coarsening needs even element counts on every axis */
+  int32_t nrhs;             /* load cases, 1..4, solved as independent CG recurrences
+                               sharing every operator read */
+  int32_t precision;        /* MGCG_FP64 or MGCG_MIXED */
+  int32_t pre, post;        /* weighted-Jacobi sweeps before / after the coarse correction */
+  double E0, Emin, nu, penal; /* solid modulus, void modulus, Poisson ratio, SIMP p */
+  double omega;             /* Jacobi weight */
+} mgcg_desc;
+
+/* Result of one solve. */
+typedef struct mgcg_info {
+  int32_t status;        /* return code of the solve */
+  int32_t iters[4];      /* PCG iterations per load case */
+  double rel_res[4];     /* true ||f - K u|| / ||f|| per load case at exit (FP64) */
+  int32_t replacements;  /* residual replacements performed */
+  int32_t pad;
+  double t_setup_ms;     /* last mgcg_set_densities, device time */
+  double t_solve_ms;     /* this solve, host wall time */
+} mgcg_info;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* mgcg_last_error(void);
+int mgcg_version(void);
+
+/* Device bytes a problem allocates when it is first used (exactly what
+ * mgcg_problem_create + first use allocates).  0 on invalid desc. */
+size_t mgcg_problem_device_bytes(const mgcg_desc* desc);
+
+/* Validate desc and copy the supports and loads (host arrays):
+ *   fixed_mask  uint8[ndof]       nonzero = DOF fixed (Sec. 6.1);
+ *   f           double[nrhs*ndof] nodal loads (entries on fixed DOFs ignored).
+ * Device memory is allocated lazily on `device` at the first
+ * set_densities/solve (or by the server at admission). */
+int mgcg_problem_create(const mgcg_desc* desc, const uint8_t* fixed_mask, const double* f,
+                        int device, mgcg_problem** out);
+int mgcg_problem_destroy(mgcg_problem* p);
+
+/* Run all later work of this problem on `stream` (a hipStream_t, e.g. the
+ * current torch stream; NULL = the library's own stream). */
+int mgcg_set_stream(mgcg_problem* p, void* stream);
+
+/* Allocate the device hierarchy now (otherwise done on first use). */
+int mgcg_problem_allocate(mgcg_problem* p);
+
+/* Densities rho[n_rho] (FP64, host or device): SIMP moduli, fine operator,
+ * Galerkin coarse operators, Jacobi diagonals and the coarsest Cholesky
+ * factor (the multigrid refresh of Sec. 7.2).  MGCG_EINVAL if any density is
+ * NaN or outside [0, 1] (detected on the device; the previous operator is
+ * then invalid and must be refreshed before the next solve). */
+int mgcg_set_densities(mgcg_problem* p, const double* rho, int mem);
+
+/* Solve K u = f for every load case to ||f - K u|| <= rtol ||f|| (true FP64
+ * residual), at most maxit PCG iterations.  warm_start != 0 starts from the
+ * current u (the previous solution or mgcg_set_initial_guess), else from 0.
+ * info may be NULL.  Blocks until done. */
+int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_info* info);
+
+/* u[nrhs*ndof] FP64 (zero on fixed DOFs). */
+int mgcg_get_displacement(mgcg_problem* p, double* u, int mem);
+int mgcg_set_initial_guess(mgcg_problem* p, const double* u, int mem);
+
+/* Compliance and gradient of the current solution:
+ *   c   host double[nrhs+1]: f_l^T u_l per load case, then their sum;
+ *   dc  double[n_rho] (host or device, may be NULL): d(sum_l c_l)/d rho. */
+int mgcg_compliance_sensitivity(mgcg_problem* p, double* c, double* dc, int mem);
+
+/* ---- Inspection of the operators (for parity tests) ----
+ * level 0 is the finest.  prec: MGCG_FP64 = the FP64 operator, MGCG_MIXED =
+ * the V-cycle's FP32 copy (levels >= 1 exist only in the V-cycle precision).
+ * Vectors are FP64 [nrhs][ndof_level] in the given memory. */
+int mgcg_level_dims(mgcg_problem* p, int level, int32_t* dims3, int64_t* ndof);
+/* y = A_l x with A_l = Z K_l Z + (I - Z) (identity rows on fixed DOFs). */
+int mgcg_apply(mgcg_problem* p, int level, int prec, const double* x, double* y, int mem);
+/* diag(A_l)[ndof_level] */
+int mgcg_level_diag(mgcg_problem* p, int level, double* d, int mem);
+/* coarse = P~^T fine, fine = P~ coarse (P~ = trilinear prolongation with rows
+ * of fixed fine DOFs and columns of fixed coarse DOFs zeroed); level is the
+ * fine side (0 .. nlevels-2). */
+int mgcg_restrict(mgcg_problem* p, int level, const double* fine, double* coarse, int mem);
+int mgcg_prolong(mgcg_problem* p, int level, const double* coarse, double* fine, int mem);
+/* z = M r: one V-cycle in the problem's precision. */
+int mgcg_precondition(mgcg_problem* p, const double* r, double* z, int mem);
+/* x = A_c^{-1} b on the coarsest level via the Cholesky factor. */
+int mgcg_coarse_solve(mgcg_problem* p, const double* b, double* x, int mem);
+
+/* ---- Kernel timing (HIP events around each launch of one kernel) ----
+ * kernel ids: 0 = finest-level operator apply (all variants). */
+int mgcg_set_kernel_timing(mgcg_problem* p, int enable);
+int mgcg_get_kernel_timing(mgcg_problem* p, int kernel, double* total_ms, int64_t* launches);
+/* Plain device copy of `bytes` bytes on the problem's stream (calibration of
+ * memory-traffic counters). */
+int mgcg_copy_bytes(mgcg_problem* p, const void* src, void* dst, size_t bytes);
+
+/* ---- Serving: continuous batching of solves over one GPU ----
+ * A server keeps up to max_slots problems resident (hierarchy + warm-start u
+ * on the device) within hbm_budget bytes and advances every admitted solve
+ * a few PCG iterations per step on its own stream, so solves of different
+ * sizes overlap on the device.  Requests are admitted in submission order
+ * when a slot is free and the problem's device bytes fit the remaining
+ * budget; a problem submitted again while resident keeps its memory
+ * (warm start).  The server does not own problems. */
+int mgcg_server_create(int device, size_t hbm_budget, int max_slots, mgcg_server** out);
+int mgcg_server_destroy(mgcg_server* s);
+/* Queue one solve of p with densities rho (host FP64, copied now).
+ * MGCG_EBUDGET if p alone exceeds the budget. */
+int mgcg_server_submit(mgcg_server* s, mgcg_problem* p, const double* rho, double rtol,
+                       int maxit, int warm_start, uint64_t* ticket);
+/* Admit what fits, launch the next chunk of every active solve, retire the
+ * finished ones.  *active / *queued receive the counts after the step. */
+int mgcg_server_step(mgcg_server* s, int* active, int* queued);
+/* MGCG_EAGAIN until the ticket's solve has finished; then its info and the
+ * device time from admission to completion in *latency_ms. */
+int mgcg_server_poll(mgcg_server* s, uint64_t ticket, mgcg_info* info, double* latency_ms);
+/* Release a problem's device memory when it is not in use by a solve
+ * (end of a session); MGCG_ESTATE while it is queued or running. */
+int mgcg_server_release(mgcg_server* s, mgcg_problem* p);
+/* Bytes currently held by resident problems. */
+size_t mgcg_server_resident_bytes(mgcg_server* s);
+
+/* Pure admission policy (no device): given the budget, the bytes in use, the
+ * free slots and the queue's byte sizes in order, writes admit[i] = 1 for the
+ * requests admitted now (first-come-first-served; a request that does not fit
+ * blocks those behind it) and returns how many. */
+int mgcg_admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
+                        int nqueue, uint8_t* admit);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGCG_H */

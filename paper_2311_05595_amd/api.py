@@ -1,0 +1,282 @@
+"""Python binding over the C ABI: argument marshalling only.
+
+Every computation runs in the HIP library; numpy arrays are passed as host
+pointers, CUDA/HIP torch tensors as device pointers (FP64, contiguous) on the
+current torch stream.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import (MGCG_EAGAIN, MGCG_ENOTCONV, MGCG_FP64, MGCG_MEM_DEVICE, MGCG_MEM_HOST,
+                   MGCG_MIXED, MGCG_OK, check, load, mgcg_desc, mgcg_info)
+
+_PREC = {"fp64": MGCG_FP64, "mixed": MGCG_MIXED}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _is_device_tensor(a):
+    try:
+        torch = _torch()
+    except Exception:
+        return False
+    return isinstance(a, torch.Tensor) and a.is_cuda
+
+
+def _ptr(a, dtype=np.float64):
+    """(pointer, mem flag, keep-alive) for a numpy array or a device tensor."""
+    if _is_device_tensor(a):
+        torch = _torch()
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise TypeError("device tensors must be contiguous float64")
+        return C.c_void_p(a.data_ptr()), MGCG_MEM_DEVICE, a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return C.c_void_p(arr.ctypes.data), MGCG_MEM_HOST, arr
+
+
+def _info(i):
+    return dict(status=i.status, iters=list(i.iters), rel_res=list(i.rel_res),
+                replacements=i.replacements, t_setup_ms=i.t_setup_ms, t_solve_ms=i.t_solve_ms)
+
+
+def make_desc(nel, order=1, nsub=1, nlevels=3, nrhs=1, precision="fp64", E0=1.0, Emin=1e-9,
+              nu=0.3, penal=3.0, omega=0.6, pre=1, post=1):
+    return mgcg_desc(nel[0], nel[1], nel[2], order, nsub, nlevels, nrhs,
+                     _PREC[precision] if isinstance(precision, str) else int(precision),
+                     pre, post, E0, Emin, nu, penal, omega)
+
+
+def device_bytes(**kw):
+    return load().mgcg_problem_device_bytes(C.byref(make_desc(**kw)))
+
+
+class Problem:
+    """One equilibrium problem K(rho) u = f (all load cases) on one GPU."""
+
+    def __init__(self, nel, mask, f, order=1, nsub=1, nlevels=3, precision="fp64", E0=1.0,
+                 Emin=1e-9, nu=0.3, penal=3.0, omega=0.6, pre=1, post=1, device=0):
+        lib = load()
+        f = np.atleast_2d(np.ascontiguousarray(f, dtype=np.float64))
+        self.nrhs = f.shape[0]
+        self.nel = tuple(nel)
+        self.order, self.nsub, self.nlevels = order, nsub, nlevels
+        self.desc = make_desc(nel, order, nsub, nlevels, self.nrhs, precision, E0, Emin, nu,
+                              penal, omega, pre, post)
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.f = f
+        dims = [order * n + 1 for n in nel]
+        self.ndof = 3 * dims[0] * dims[1] * dims[2]
+        self.nrho = nel[0] * nel[1] * nel[2] * nsub ** 3
+        if self.mask.size != self.ndof or f.shape[1] != self.ndof:
+            raise ValueError("mask/f size does not match the mesh")
+        h = C.c_void_p()
+        check(lib.mgcg_problem_create(C.byref(self.desc), C.c_void_p(self.mask.ctypes.data),
+                                      C.c_void_p(f.ctypes.data), device, C.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mgcg_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_bytes(self):
+        return self._lib.mgcg_problem_device_bytes(C.byref(self.desc))
+
+    def allocate(self):
+        check(self._lib.mgcg_problem_allocate(self._h))
+
+    def set_stream(self, stream=None):
+        """stream: a torch.cuda.Stream, a raw hipStream_t (int) or None."""
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        check(self._lib.mgcg_set_stream(self._h, C.c_void_p(stream or 0)))
+
+    def use_torch_stream(self):
+        self.set_stream(_torch().cuda.current_stream().cuda_stream)
+
+    def set_densities(self, rho):
+        p, mem, keep = _ptr(rho)
+        if (keep.numel() if mem == MGCG_MEM_DEVICE else keep.size) != self.nrho:
+            raise ValueError("density count does not match the mesh")
+        check(self._lib.mgcg_set_densities(self._h, p, mem))
+
+    def solve(self, rtol=1e-8, maxit=1000, warm_start=True, allow_notconv=False):
+        info = mgcg_info()
+        allow = (MGCG_OK, MGCG_ENOTCONV) if allow_notconv else (MGCG_OK,)
+        check(self._lib.mgcg_solve(self._h, rtol, maxit, 1 if warm_start else 0, C.byref(info)),
+              allow)
+        return _info(info)
+
+    def displacement(self, out=None):
+        if out is None:
+            out = np.empty((self.nrhs, self.ndof))
+        p, mem, _ = _ptr(out) if _is_device_tensor(out) else (C.c_void_p(out.ctypes.data), MGCG_MEM_HOST, out)
+        check(self._lib.mgcg_get_displacement(self._h, p, mem))
+        return out
+
+    def set_initial_guess(self, u):
+        p, mem, _k = _ptr(u)
+        check(self._lib.mgcg_set_initial_guess(self._h, p, mem))
+
+    def compliance_sensitivity(self, dc_out=None, want_dc=True):
+        """Returns (c per load case + total [nrhs+1] numpy, dc or None)."""
+        c = np.zeros(self.nrhs + 1)
+        if want_dc and dc_out is None:
+            dc_out = np.empty(self.nrho)
+        if dc_out is None:
+            dp, mem = C.c_void_p(0), MGCG_MEM_HOST
+        elif _is_device_tensor(dc_out):
+            dp, mem, _ = _ptr(dc_out)
+        else:
+            dp, mem = C.c_void_p(dc_out.ctypes.data), MGCG_MEM_HOST
+        check(self._lib.mgcg_compliance_sensitivity(self._h, C.c_void_p(c.ctypes.data), dp, mem))
+        return c, dc_out
+
+    # ---- inspection (parity tests) ----
+    def level_dims(self, level):
+        d = (C.c_int32 * 3)()
+        n = C.c_int64()
+        check(self._lib.mgcg_level_dims(self._h, level, d, C.byref(n)))
+        return tuple(d), n.value
+
+    def _vec_op(self, fn, level, x, out_len, *extra):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(out_len)
+        check(fn(self._h, level, *extra, C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data),
+                 MGCG_MEM_HOST))
+        return y
+
+    def apply(self, level, x, precision="fp64"):
+        n = self.level_dims(level)[1] * self.nrhs
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        y = np.empty(n)
+        check(self._lib.mgcg_apply(self._h, level, _PREC[precision], C.c_void_p(x.ctypes.data),
+                                   C.c_void_p(y.ctypes.data), MGCG_MEM_HOST))
+        return y.reshape(self.nrhs, -1)
+
+    def diag(self, level):
+        n = self.level_dims(level)[1]
+        y = np.empty(n)
+        check(self._lib.mgcg_level_diag(self._h, level, C.c_void_p(y.ctypes.data), MGCG_MEM_HOST))
+        return y
+
+    def restrict(self, level, fine):
+        nc = self.level_dims(level + 1)[1] * self.nrhs
+        fine = np.ascontiguousarray(fine, dtype=np.float64).reshape(-1)
+        out = np.empty(nc)
+        check(self._lib.mgcg_restrict(self._h, level, C.c_void_p(fine.ctypes.data),
+                                      C.c_void_p(out.ctypes.data), MGCG_MEM_HOST))
+        return out.reshape(self.nrhs, -1)
+
+    def prolong(self, level, coarse):
+        nf = self.level_dims(level)[1] * self.nrhs
+        coarse = np.ascontiguousarray(coarse, dtype=np.float64).reshape(-1)
+        out = np.empty(nf)
+        check(self._lib.mgcg_prolong(self._h, level, C.c_void_p(coarse.ctypes.data),
+                                     C.c_void_p(out.ctypes.data), MGCG_MEM_HOST))
+        return out.reshape(self.nrhs, -1)
+
+    def precondition(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+        z = np.empty_like(r)
+        check(self._lib.mgcg_precondition(self._h, C.c_void_p(r.ctypes.data),
+                                          C.c_void_p(z.ctypes.data), MGCG_MEM_HOST))
+        return z.reshape(self.nrhs, -1)
+
+    def coarse_solve(self, b):
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+        x = np.empty_like(b)
+        check(self._lib.mgcg_coarse_solve(self._h, C.c_void_p(b.ctypes.data),
+                                          C.c_void_p(x.ctypes.data), MGCG_MEM_HOST))
+        return x.reshape(self.nrhs, -1)
+
+    def set_kernel_timing(self, kernel=0, enable=True):
+        check(self._lib.mgcg_set_kernel_timing(self._h, kernel + 1 if enable else 0))
+
+    def kernel_timing(self, kernel=0):
+        ms = C.c_double()
+        n = C.c_int64()
+        check(self._lib.mgcg_get_kernel_timing(self._h, kernel, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def copy_bytes(self, src_ptr, dst_ptr, nbytes):
+        check(self._lib.mgcg_copy_bytes(self._h, C.c_void_p(src_ptr), C.c_void_p(dst_ptr), nbytes))
+
+
+def admission_plan(budget, in_use, free_slots, queue_bytes):
+    lib = load()
+    q = np.ascontiguousarray(queue_bytes, dtype=np.uint64)
+    adm = np.zeros(len(q), dtype=np.uint8)
+    n = lib.mgcg_admission_plan(budget, in_use, free_slots, C.c_void_p(q.ctypes.data), len(q),
+                                C.c_void_p(adm.ctypes.data))
+    if n < 0:
+        check(n)
+    return adm.astype(bool)
+
+
+class Server:
+    """Continuous-batching server (see mgcg_server_* in include/mgcg.h)."""
+
+    def __init__(self, budget_bytes, max_slots=8, device=0):
+        lib = load()
+        h = C.c_void_p()
+        check(lib.mgcg_server_create(device, int(budget_bytes), int(max_slots), C.byref(h)))
+        self._h, self._lib = h, lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mgcg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, problem, rho, rtol=1e-8, maxit=1000, warm_start=True):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        t = C.c_uint64()
+        check(self._lib.mgcg_server_submit(self._h, problem.handle, C.c_void_p(rho.ctypes.data),
+                                           rtol, maxit, 1 if warm_start else 0, C.byref(t)))
+        return t.value
+
+    def step(self):
+        a, q = C.c_int(), C.c_int()
+        check(self._lib.mgcg_server_step(self._h, C.byref(a), C.byref(q)))
+        return a.value, q.value
+
+    def poll(self, ticket):
+        """None while running; else (status, info dict, latency ms)."""
+        info = mgcg_info()
+        lat = C.c_double()
+        st = self._lib.mgcg_server_poll(self._h, ticket, C.byref(info), C.byref(lat))
+        if st == MGCG_EAGAIN:
+            return None
+        return st, _info(info), lat.value
+
+    def release(self, problem):
+        check(self._lib.mgcg_server_release(self._h, problem.handle))
+
+    def resident_bytes(self):
+        return self._lib.mgcg_server_resident_bytes(self._h)
+
+
+__all__ = ["Problem", "Server", "admission_plan", "device_bytes", "make_desc", "_abi"]

@@ -1,0 +1,261 @@
+// extern "C" boundary: argument checks, exception-to-status translation and
+// the thread-local error message.
+#include <cstring>
+#include <string>
+
+#include "problem.h"
+#include "server.h"
+
+namespace mgcg {
+namespace {
+thread_local std::string g_err;
+}
+const char* set_error(const std::string& m) {
+  g_err = m;
+  return g_err.c_str();
+}
+const char* get_error() { return g_err.c_str(); }
+}  // namespace mgcg
+
+using mgcg::Error;
+using mgcg::Problem;
+
+#define GUARD(body)                                 \
+  try {                                             \
+    mgcg::set_error("");                            \
+    body                                            \
+  } catch (const Error& e) {                        \
+    mgcg::set_error(e.what());                      \
+    return e.code;                                  \
+  } catch (const std::exception& e) {               \
+    mgcg::set_error(e.what());                      \
+    return MGCG_EINVAL;                             \
+  } catch (...) {                                   \
+    mgcg::set_error("unknown error");               \
+    return MGCG_EINVAL;                             \
+  }
+
+#define NEED(ptr)                                                         \
+  if (!(ptr)) {                                                           \
+    mgcg::set_error(std::string("null argument: ") + #ptr);              \
+    return MGCG_EINVAL;                                                   \
+  }
+
+struct mgcg_problem {
+  Problem* impl;
+};
+
+extern "C" {
+
+const char* mgcg_last_error(void) { return mgcg::get_error(); }
+
+int mgcg_version(void) { return 10000; }
+
+size_t mgcg_problem_device_bytes(const mgcg_desc* d) {
+  if (!d) return 0;
+  try {
+    return Problem::device_bytes(*d);
+  } catch (...) {
+    return 0;
+  }
+}
+
+int mgcg_problem_create(const mgcg_desc* d, const uint8_t* mask, const double* f, int device,
+                        mgcg_problem** out) {
+  NEED(d);
+  NEED(mask);
+  NEED(f);
+  NEED(out);
+  GUARD({
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    if (device < 0 || (ndev > 0 && device >= ndev)) throw Error(MGCG_EINVAL, "bad device index");
+    auto* p = new mgcg_problem{nullptr};
+    try {
+      p->impl = new Problem(*d, mask, f, device);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_problem_destroy(mgcg_problem* p) {
+  if (!p) return MGCG_OK;
+  GUARD({
+    delete p->impl;
+    delete p;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_set_stream(mgcg_problem* p, void* stream) {
+  NEED(p);
+  GUARD({
+    p->impl->allocate();
+    p->impl->set_stream((hipStream_t)stream);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_problem_allocate(mgcg_problem* p) {
+  NEED(p);
+  GUARD({
+    p->impl->allocate();
+    return MGCG_OK;
+  })
+}
+
+int mgcg_set_densities(mgcg_problem* p, const double* rho, int mem) {
+  NEED(p);
+  NEED(rho);
+  GUARD({
+    p->impl->set_densities(rho, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_info* info) {
+  NEED(p);
+  GUARD({ return p->impl->solve(rtol, maxit, warm_start != 0, info); })
+}
+
+int mgcg_get_displacement(mgcg_problem* p, double* u, int mem) {
+  NEED(p);
+  NEED(u);
+  GUARD({
+    p->impl->get_u(u, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_set_initial_guess(mgcg_problem* p, const double* u, int mem) {
+  NEED(p);
+  NEED(u);
+  GUARD({
+    p->impl->set_u(u, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_compliance_sensitivity(mgcg_problem* p, double* c, double* dc, int mem) {
+  NEED(p);
+  NEED(c);
+  GUARD({
+    p->impl->compliance_sensitivity(c, dc, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_level_dims(mgcg_problem* p, int level, int32_t* dims3, int64_t* ndof) {
+  NEED(p);
+  GUARD({
+    p->impl->level_dims(level, dims3, ndof);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_apply(mgcg_problem* p, int level, int prec, const double* x, double* y, int mem) {
+  NEED(p);
+  NEED(x);
+  NEED(y);
+  GUARD({
+    p->impl->apply(level, prec, x, y, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_level_diag(mgcg_problem* p, int level, double* d, int mem) {
+  NEED(p);
+  NEED(d);
+  GUARD({
+    p->impl->diag(level, d, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_restrict(mgcg_problem* p, int level, const double* fine, double* coarse, int mem) {
+  NEED(p);
+  NEED(fine);
+  NEED(coarse);
+  GUARD({
+    p->impl->restrict_(level, fine, coarse, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_prolong(mgcg_problem* p, int level, const double* coarse, double* fine, int mem) {
+  NEED(p);
+  NEED(fine);
+  NEED(coarse);
+  GUARD({
+    p->impl->prolong(level, coarse, fine, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_precondition(mgcg_problem* p, const double* r, double* z, int mem) {
+  NEED(p);
+  NEED(r);
+  NEED(z);
+  GUARD({
+    p->impl->precondition(r, z, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_coarse_solve(mgcg_problem* p, const double* b, double* x, int mem) {
+  NEED(p);
+  NEED(b);
+  NEED(x);
+  GUARD({
+    p->impl->coarse_solve(b, x, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_set_kernel_timing(mgcg_problem* p, int enable) {
+  NEED(p);
+  GUARD({
+    p->impl->set_timing(enable > 0, enable > 0 ? enable - 1 : 0);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_get_kernel_timing(mgcg_problem* p, int kernel, double* total_ms, int64_t* launches) {
+  NEED(p);
+  GUARD({
+    long long n = 0;
+    p->impl->get_timing(kernel, total_ms, &n);
+    if (launches) *launches = n;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_copy_bytes(mgcg_problem* p, const void* src, void* dst, size_t bytes) {
+  NEED(p);
+  NEED(src);
+  NEED(dst);
+  GUARD({
+    p->impl->copy(src, dst, bytes);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
+                        int nqueue, uint8_t* admit) {
+  if (nqueue < 0 || (nqueue > 0 && (!queue_bytes || !admit))) {
+    mgcg::set_error("bad admission arguments");
+    return MGCG_EINVAL;
+  }
+  return mgcg::admission_plan(budget, in_use, free_slots, queue_bytes, nqueue, admit);
+}
+
+}  // extern "C"
+
+// accessor for the server
+namespace mgcg {
+Problem* problem_impl(mgcg_problem* p) { return p ? p->impl : nullptr; }
+}  // namespace mgcg

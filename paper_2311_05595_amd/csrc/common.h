@@ -1,0 +1,70 @@
+// Internal definitions shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace mgcg {
+
+// Thrown inside the library, caught at the C-ABI boundary.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define MGCG_HIP(call)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw ::mgcg::Error(-5, std::string(#call) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+// Operator kinds of a multigrid level.
+enum OpKind : int {
+  OP_MF_Q1 = 0,  // matrix-free trilinear elements: y = sum_e E_e K0 u_e (one density per element)
+  OP_ST27 = 1,   // assembled 27-point stencil of 3x3 blocks (Q1-type lattice), symmetric half
+  OP_EQ2 = 2,    // stored 81x81 element matrices of triquadratic elements
+};
+
+// Number of stored stencil blocks per node: the diagonal block and the 13
+// "forward" neighbour blocks (the other 13 are transposes of a neighbour's).
+constexpr int ST_BLOCKS = 14;
+constexpr int ST_COEF = ST_BLOCKS * 9;
+
+// Forward neighbour offsets d (block A_{i,i+d}); entry 0 is the diagonal.
+// Lexicographically positive offsets in (dz, dy, dx) order.
+struct Off3 { int dx, dy, dz; };
+__host__ __device__ constexpr Off3 st_offset(int b) {
+  // b = 0: (0,0,0); b = 1..13 enumerate the positive half of {-1,0,1}^3
+  // (dz > 0) or (dz == 0 && dy > 0) or (dz == 0 && dy == 0 && dx > 0).
+  constexpr Off3 tab[ST_BLOCKS] = {
+      {0, 0, 0},  {1, 0, 0},   {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},  {-1, -1, 1}, {0, -1, 1},
+      {1, -1, 1}, {-1, 0, 1},  {0, 0, 1},  {1, 0, 1},  {-1, 1, 1}, {0, 1, 1},   {1, 1, 1}};
+  return tab[b];
+}
+
+// Per load case CG scalars and state, resident on the device.
+enum CgState : int { CG_ACTIVE = 0, CG_CHECK = 1, CG_DONE = 2, CG_BREAKDOWN = 3, CG_MAXIT = 4 };
+
+struct CgScalars {
+  double ff;      // ||f||^2
+  double tol2;    // rtol^2 ||f||^2
+  double rr;      // ||r||^2 (recurrence, or true after a check)
+  double rz;      // r^T z of the current iterate
+  double alpha, beta;
+  double pq;
+  int iters;
+  int state;
+  int maxit;
+  int replacements;
+  int replace_every;
+  int flexible;    // 1: Polak-Ribiere beta (non-symmetric FP32 preconditioner)
+  double rr_best;  // smallest true ||r||^2 seen at a check
+  int stall;       // consecutive checks without progress
+  int pad;
+};
+
+}  // namespace mgcg

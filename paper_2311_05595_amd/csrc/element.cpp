@@ -1,0 +1,140 @@
+// Element stiffness of Lagrange hexahedra (Sec. 2 eq. (1); sub-box split of
+// Sec. 3.3), computed on the host once per problem.
+//
+// For an isotropic material with Lame constants lambda, mu the element
+// bilinear form, written per pair of shape-function gradients g_a, g_b, is
+//   K_(a,c),(b,e) = integral of  lambda g_a[c] g_b[e] + mu g_a[e] g_b[c]
+//                              + mu delta_ce (g_a . g_b),
+// which equals B^T D B for the Voigt D with engineering shear.  Each
+// sub-box of the n^3 split is integrated with (p+1)^3 Gauss-Legendre points
+// (exact for these polynomial integrands).  Unit element: x = xi / 2.
+#include "element.h"
+
+#include <cmath>
+#include <stdexcept>
+
+namespace mgcg {
+
+namespace {
+
+// Gauss-Legendre rule on [-1, 1] by Newton iteration on P_m.
+void gauss_legendre(int m, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(m, 0.0);
+  w.assign(m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (m + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= m; ++k) {
+        double pk = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      double dp = m * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= m; ++k) {
+      double pk = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = pk;
+    }
+    double dp = m * (t * p1 - p0) / (t * t - 1.0);
+    x[i] = t;
+    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+// 1-D Lagrange basis of degree p on equally spaced nodes of [-1, 1]:
+// values l[k] and derivatives d[k] at t.
+void basis_1d(int p, double t, double* l, double* d) {
+  double nodes[4];
+  for (int k = 0; k <= p; ++k) nodes[k] = -1.0 + 2.0 * k / p;
+  for (int k = 0; k <= p; ++k) {
+    double v = 1.0, dv = 0.0;
+    for (int m = 0; m <= p; ++m) {
+      if (m == k) continue;
+      double f = 1.0 / (nodes[k] - nodes[m]);
+      // product rule, accumulated incrementally
+      dv = dv * (t - nodes[m]) * f + v * f;
+      v = v * (t - nodes[m]) * f;
+    }
+    l[k] = v;
+    d[k] = dv;
+  }
+}
+
+}  // namespace
+
+std::vector<double> sub_element_matrices(int order, int nsub, double nu) {
+  if (order < 1 || order > 2 || nsub < 1) throw std::invalid_argument("element order/nsub");
+  const int p1 = order + 1;
+  const int nen = p1 * p1 * p1;
+  const int nd = 3 * nen;
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  const double dxi_dx = 2.0;       // unit element: x = xi / 2
+  const double jac = 0.125;        // dx dy dz = (1/8) dxi deta dzeta
+  std::vector<double> gx, gw;
+  gauss_legendre(p1, gx, gw);
+
+  const int ns3 = nsub * nsub * nsub;
+  std::vector<double> out((size_t)ns3 * nd * nd, 0.0);
+  std::vector<double> grad((size_t)nen * 3);
+  for (int sz = 0; sz < nsub; ++sz)
+    for (int sy = 0; sy < nsub; ++sy)
+      for (int sx = 0; sx < nsub; ++sx) {
+        double* K = &out[(size_t)(sx + nsub * (sy + nsub * sz)) * nd * nd];
+        const int s[3] = {sx, sy, sz};
+        double lo[3], half[3];
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = -1.0 + 2.0 * s[d] / nsub;
+          half[d] = 1.0 / nsub;  // half-length of the sub-interval (length 2/n)
+        }
+        for (int qz = 0; qz < p1; ++qz)
+          for (int qy = 0; qy < p1; ++qy)
+            for (int qx = 0; qx < p1; ++qx) {
+              const int q[3] = {qx, qy, qz};
+              double L[3][4], D[3][4];
+              double wq = jac;
+              for (int d = 0; d < 3; ++d) {
+                double t = lo[d] + half[d] * (gx[q[d]] + 1.0);
+                basis_1d(order, t, L[d], D[d]);
+                wq *= gw[q[d]] * half[d];
+              }
+              for (int az = 0; az < p1; ++az)
+                for (int ay = 0; ay < p1; ++ay)
+                  for (int ax = 0; ax < p1; ++ax) {
+                    int a = ax + p1 * (ay + p1 * az);
+                    grad[3 * a + 0] = dxi_dx * D[0][ax] * L[1][ay] * L[2][az];
+                    grad[3 * a + 1] = dxi_dx * L[0][ax] * D[1][ay] * L[2][az];
+                    grad[3 * a + 2] = dxi_dx * L[0][ax] * L[1][ay] * D[2][az];
+                  }
+              for (int a = 0; a < nen; ++a)
+                for (int b = 0; b < nen; ++b) {
+                  const double* ga = &grad[3 * a];
+                  const double* gb = &grad[3 * b];
+                  double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                  for (int c = 0; c < 3; ++c)
+                    for (int e = 0; e < 3; ++e) {
+                      double v = lam * ga[c] * gb[e] + mu * ga[e] * gb[c];
+                      if (c == e) v += mu * dot;
+                      K[(size_t)(3 * a + c) * nd + 3 * b + e] += wq * v;
+                    }
+                }
+            }
+      }
+  return out;
+}
+
+double trilinear_weight(int px, int py, int pz, int b) {
+  auto w1 = [](int pos, int bit) -> double {
+    if (pos == 1) return 0.5;
+    return (pos == 2 * bit) ? 1.0 : 0.0;
+  };
+  return w1(px, b & 1) * w1(py, (b >> 1) & 1) * w1(pz, (b >> 2) & 1);
+}
+
+}  // namespace mgcg

@@ -1,0 +1,20 @@
+// Host-side element matrices of Lagrange rectangular-prism elements.
+#pragma once
+
+#include <vector>
+
+namespace mgcg {
+
+// The n^3 sub-element stiffness matrices K^(e_i) of one unit displacement
+// element of the given order (1: 8 nodes, 2: 27 nodes) with modulus 1 and
+// Poisson ratio nu, as [n^3][nd][nd] row-major, nd = 3 * (order+1)^3.
+// Sub-element i = sx + n*(sy + n*sz); local node a = ax + (p+1)*(ay + (p+1)*az);
+// local DOF 3a + c.
+std::vector<double> sub_element_matrices(int order, int nsub, double nu);
+
+// Trilinear weight of coarse vertex b (bits x,y,z of b in {0,1}) at the
+// node with coarse-local lattice position (px,py,pz) in {0,1,2}^3 (spacing
+// 1/2 of the coarse element).
+double trilinear_weight(int px, int py, int pz, int b);
+
+}  // namespace mgcg

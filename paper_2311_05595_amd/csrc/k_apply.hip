@@ -1,0 +1,951 @@
+// Operator applies (node-centred gathers, no atomics), the CG recurrences
+// and the V-cycle level kernels.
+//
+// Every apply computes, for one output node per thread, the three rows of
+// A = Z K Z + (I - Z) (K assembled from element matrices, Sec. 3.3; Z keeps
+// free DOFs) by gathering its neighbours — the element-by-element product of
+// eq. (7) reorganised so that each output is written exactly once.  Fused
+// epilogues turn the product into a residual, a weighted-Jacobi update
+// (Algorithm 1, smoothing steps) or a CG step with its dot product.
+#include "devutil.h"
+
+namespace mgcg {
+
+// ------------------------------------------------------------------ inputs
+template <typename T>
+struct InPlain {
+  const T* x;
+  long ndof;
+  __device__ __forceinline__ void load(int r, long node, T v[3]) const {
+    const T* p = x + (size_t)r * ndof + 3 * node;
+    v[0] = p[0];
+    v[1] = p[1];
+    v[2] = p[2];
+  }
+};
+
+// x = omega * invD * b evaluated on the fly (first smoothing sweep from zero).
+template <typename T>
+struct InScaledB {
+  const T* b;
+  const T* invD;
+  T omega;
+  long ndof;
+  __device__ __forceinline__ void load(int r, long node, T v[3]) const {
+    const T* p = b + (size_t)r * ndof + 3 * node;
+    const T* d = invD + 3 * node;
+    v[0] = omega * d[0] * p[0];
+    v[1] = omega * d[1] * p[1];
+    v[2] = omega * d[2] * p[2];
+  }
+};
+
+// ------------------------------------------------------------ operators
+__device__ __forceinline__ void node_ijk(long node, const Lat& L, int& i, int& j, int& k) {
+  i = (int)(node % L.nx);
+  long t = node / L.nx;
+  j = (int)(t % L.ny);
+  k = (int)(t / L.ny);
+}
+
+// Matrix-free trilinear apply at node (i,j,k): the three rows of
+// sum_e E_e K0 u_e over the (up to) 8 elements around the node, K0 entries
+// taken from the 10 class values (scalar registers) with compile-time class
+// and sign.  Inputs vanish on fixed DOFs; fixed rows return 0 (= input).
+template <typename T, class In>
+__device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, int i, int j, int k,
+                                      T y[3]) {
+  const Lat L = op.L;
+  const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
+  T u[27][3];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int ii = i + dx - 1, jj = j + dy - 1, kk = k + dz - 1;
+        const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+                        (unsigned)kk < (unsigned)L.nz;
+        const int s = dx + 3 * (dy + 3 * dz);
+        if (ok) {
+          in.load(r, ii + (long)L.nx * (jj + (long)L.ny * kk), u[s]);
+        } else {
+          u[s][0] = u[s][1] = u[s][2] = T(0);
+        }
+      }
+  T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 2; ++ox) {
+        const int ex = i - 1 + ox, ey = j - 1 + oy, ez = k - 1 + oz;
+        const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
+                        (unsigned)ez < (unsigned)ez1;
+        const T Ee = ok ? op.E[ex + (long)ex1 * (ey + (long)ey1 * ez)] : T(0);
+        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+        T t[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+          const int s = (ox + bx) + 3 * ((oy + by) + 3 * (oz + bz));
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+              const int q = (3 * a + c) * 24 + 3 * b + e;
+              const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
+              t[c] = fma(kk, u[s][e], t[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = fma(Ee, t[c], acc[c]);
+      }
+  const uint8_t mself = op.mask[i + (long)L.nx * (j + (long)L.ny * k)];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[c] = ((mself >> c) & 1) ? T(0) : acc[c];
+}
+
+// Stencil apply (supports baked in).
+template <typename T, class In>
+__device__ __forceinline__ void ax_st(const OpST<T>& op, const In& in, int r, int i, int j, int k,
+                                      long node, T y[3]) {
+  const Lat L = op.L;
+  const long nn = L.nn();
+  T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int b = 0; b < ST_BLOCKS; ++b) {
+    const Off3 d = st_offset(b);
+    {
+      const int ii = i + d.dx, jj = j + d.dy, kk = k + d.dz;
+      if ((unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+          (unsigned)kk < (unsigned)L.nz) {
+        const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
+        T v[3];
+        in.load(r, nb, v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int e = 0; e < 3; ++e) acc[c] += op.coef[(size_t)(b * 9 + 3 * c + e) * nn + node] * v[e];
+      }
+    }
+    if (b > 0) {
+      const int ii = i - d.dx, jj = j - d.dy, kk = k - d.dz;
+      if ((unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+          (unsigned)kk < (unsigned)L.nz) {
+        const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
+        T v[3];
+        in.load(r, nb, v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int e = 0; e < 3; ++e) acc[c] += op.coef[(size_t)(b * 9 + 3 * e + c) * nn + nb] * v[e];
+      }
+    }
+  }
+  y[0] = acc[0];
+  y[1] = acc[1];
+  y[2] = acc[2];
+}
+
+// Stored triquadratic element matrices: gather over the 1..8 elements that
+// contain the node.
+template <typename T, class In>
+__device__ __forceinline__ void ax_eq2(const OpEQ2<T>& op, const In& in, int r, int i, int j, int k,
+                                       T y[3]) {
+  const Lat L = op.L;
+  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
+  int exs[2], axs[2], nxe = 0, eys[2], ays[2], nye = 0, ezs[2], azs[2], nze = 0;
+  auto axis = [](int p, int ne, int* es, int* as, int& n) {
+    if (p & 1) {
+      es[0] = (p - 1) / 2;
+      as[0] = 1;
+      n = 1;
+    } else {
+      n = 0;
+      if (p / 2 - 1 >= 0) { es[n] = p / 2 - 1; as[n] = 2; ++n; }
+      if (p / 2 < ne) { es[n] = p / 2; as[n] = 0; ++n; }
+    }
+  };
+  axis(i, nex, exs, axs, nxe);
+  axis(j, ney, eys, ays, nye);
+  axis(k, nez, ezs, azs, nze);
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int cz = 0; cz < nze; ++cz)
+    for (int cy = 0; cy < nye; ++cy)
+      for (int cx = 0; cx < nxe; ++cx) {
+        const int ex = exs[cx], ey = eys[cy], ez = ezs[cz];
+        const int a = axs[cx] + 3 * (ays[cy] + 3 * azs[cz]);
+        const T* Kr = op.Ke + ((size_t)(ex + (long)nex * (ey + (long)ney * ez)) * 81 + 3 * a) * 81;
+#pragma unroll 3
+        for (int bz = 0; bz < 3; ++bz)
+#pragma unroll 3
+          for (int by = 0; by < 3; ++by)
+#pragma unroll
+            for (int bx = 0; bx < 3; ++bx) {
+              const long nb = (2 * ex + bx) + (long)L.nx * ((2 * ey + by) + (long)L.ny * (2 * ez + bz));
+              const int bcol = 3 * (bx + 3 * (by + 3 * bz));
+              T v[3];
+              in.load(r, nb, v);
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) acc[c] += Kr[c * 81 + bcol + e] * v[e];
+            }
+      }
+  const long self = i + (long)L.nx * (j + (long)L.ny * k);
+  const uint8_t m = op.mask[self];
+  if (m) {
+    T v[3];
+    in.load(r, self, v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if ((m >> c) & 1) acc[c] = v[c];
+  }
+  y[0] = acc[0];
+  y[1] = acc[1];
+  y[2] = acc[2];
+}
+
+// Dispatch by operator struct type.
+template <typename T, class In>
+__device__ __forceinline__ void ax_any(const OpMF<T>& op, const In& in, int r, long node, T y[3]) {
+  int i, j, k;
+  node_ijk(node, op.L, i, j, k);
+  ax_mf(op, in, r, i, j, k, y);
+}
+template <typename T, class In>
+__device__ __forceinline__ void ax_any(const OpST<T>& op, const In& in, int r, long node, T y[3]) {
+  int i, j, k;
+  node_ijk(node, op.L, i, j, k);
+  ax_st(op, in, r, i, j, k, node, y);
+}
+template <typename T, class In>
+__device__ __forceinline__ void ax_any(const OpEQ2<T>& op, const In& in, int r, long node, T y[3]) {
+  int i, j, k;
+  node_ijk(node, op.L, i, j, k);
+  ax_eq2(op, in, r, i, j, k, y);
+}
+
+// ------------------------------------------------------------ epilogues
+template <typename T>
+struct EpStore {
+  T* y;
+  long ndof;
+  static constexpr bool RED = false;
+  __device__ bool rhs_on(int) const { return true; }
+  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+    T* p = y + (size_t)r * ndof + 3 * node;
+    p[0] = ax[0];
+    p[1] = ax[1];
+    p[2] = ax[2];
+  }
+};
+
+template <typename T>
+struct EpResid {  // r = b - A x
+  const T* b;
+  T* rout;
+  long ndof;
+  static constexpr bool RED = false;
+  __device__ bool rhs_on(int) const { return true; }
+  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+    const size_t o = (size_t)r * ndof + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) rout[o + c] = b[o + c] - ax[c];
+  }
+};
+
+template <typename T>
+struct EpResidX {  // r = b - A x, x = omega invD b stored
+  const T* b;
+  const T* invD;
+  T omega;
+  T* rout;
+  T* xout;
+  long ndof;
+  static constexpr bool RED = false;
+  __device__ bool rhs_on(int) const { return true; }
+  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+    const size_t o = (size_t)r * ndof + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T bb = b[o + c];
+      rout[o + c] = bb - ax[c];
+      xout[o + c] = omega * invD[3 * node + c] * bb;
+    }
+  }
+};
+
+template <typename T>
+struct EpJacobi {  // xo = x + omega invD (b - A x)
+  const T* b;
+  const T* x;
+  const T* invD;
+  T omega;
+  T* xo;
+  long ndof;
+  static constexpr bool RED = false;
+  __device__ bool rhs_on(int) const { return true; }
+  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+    const size_t o = (size_t)r * ndof + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      xo[o + c] = x[o + c] + omega * invD[3 * node + c] * (b[o + c] - ax[c]);
+  }
+};
+
+struct EpDotPQ {  // q = A p; acc[r] += p.q  (active load cases)
+  const double* p;
+  double* q;
+  long ndof;
+  const CgScalars* cs;
+  static constexpr bool RED = true;
+  __device__ bool rhs_on(int r) const { return cs[r].state == CG_ACTIVE; }
+  __device__ void put(int r, long node, const double ax[3], double& a0, double&) const {
+    const size_t o = (size_t)r * ndof + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q[o + c] = ax[c];
+      a0 += p[o + c] * ax[c];
+    }
+  }
+};
+
+struct EpInitResid {  // r = f - A x; acc[r] += r.r; acc[nrhs + r] += f.f
+  const double* f;
+  double* rout;
+  long ndof;
+  int nrhs;
+  static constexpr bool RED = true;
+  __device__ bool rhs_on(int) const { return true; }
+  __device__ void put(int r, long node, const double ax[3], double& a0, double& a1) const {
+    const size_t o = (size_t)r * ndof + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double rr = f[o + c] - ax[c];
+      rout[o + c] = rr;
+      a0 += rr * rr;
+      a1 += f[o + c] * f[o + c];
+    }
+  }
+};
+
+struct EpTrueResid {  // for load cases under check: r = f - A x; acc[r] += r.r
+  const double* f;
+  double* rout;
+  long ndof;
+  const CgScalars* cs;
+  static constexpr bool RED = true;
+  __device__ bool rhs_on(int r) const { return cs[r].state == CG_CHECK; }
+  __device__ void put(int r, long node, const double ax[3], double& a0, double&) const {
+    const size_t o = (size_t)r * ndof + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double rr = f[o + c] - ax[c];
+      rout[o + c] = rr;
+      a0 += rr * rr;
+    }
+  }
+};
+
+// ------------------------------------------------------------ finalisers
+struct FinNone {
+  __device__ void operator()(const double*) const {}
+};
+
+struct FinAlpha {
+  CgScalars* cs;
+  int nrhs;
+  __device__ void operator()(const double* tot) const {
+    for (int r = 0; r < nrhs; ++r) {
+      if (cs[r].state != CG_ACTIVE) continue;
+      const double pq = tot[r];
+      cs[r].pq = pq;
+      if (!(pq > 0.0) || !isfinite(pq))
+        cs[r].state = CG_BREAKDOWN;
+      else
+        cs[r].alpha = cs[r].rz / pq;
+    }
+  }
+};
+
+struct FinResid {
+  CgScalars* cs;
+  int nrhs;
+  __device__ void operator()(const double* tot) const {
+    for (int r = 0; r < nrhs; ++r) {
+      if (cs[r].state != CG_ACTIVE) continue;
+      const double rr = tot[r];
+      cs[r].rr = rr;
+      cs[r].iters += 1;
+      const int it = cs[r].iters;
+      if (!isfinite(rr))
+        cs[r].state = CG_BREAKDOWN;
+      else if (rr <= cs[r].tol2 || it >= cs[r].maxit ||
+               (cs[r].replace_every > 0 && it % cs[r].replace_every == 0))
+        cs[r].state = CG_CHECK;
+    }
+  }
+};
+
+// After a true-residual check: converged, out of iterations, stagnated
+// (three checks in a row without a 10% decrease of the true residual, i.e.
+// at the attainable accuracy), diverged, or continue with the residual
+// replaced by the true one.
+struct FinTrue {
+  CgScalars* cs;
+  int nrhs;
+  __device__ void operator()(const double* tot) const {
+    for (int r = 0; r < nrhs; ++r) {
+      if (cs[r].state != CG_CHECK) continue;
+      const double rr = tot[r];
+      cs[r].rr = rr;
+      cs[r].replacements += 1;
+      if (rr < 0.81 * cs[r].rr_best) {
+        cs[r].rr_best = rr;
+        cs[r].stall = 0;
+      } else {
+        cs[r].stall += 1;
+      }
+      if (!isfinite(rr) || rr > 1e30 * cs[r].ff)
+        cs[r].state = CG_BREAKDOWN;
+      else if (rr <= cs[r].tol2)
+        cs[r].state = CG_DONE;
+      else if (cs[r].iters >= cs[r].maxit || cs[r].stall >= 3)
+        cs[r].state = CG_MAXIT;
+      else
+        cs[r].state = CG_ACTIVE;  // continue from the true residual
+    }
+  }
+};
+
+struct FinInit {
+  CgScalars* cs;
+  int nrhs;
+  __device__ void operator()(const double* tot) const {
+    for (int r = 0; r < nrhs; ++r) {
+      const double rr = tot[r], ff = tot[nrhs + r];
+      cs[r].rr = rr;
+      cs[r].ff = ff;
+      cs[r].tol2 = cs[r].tol2 * ff;  // host stored rtol^2
+      cs[r].iters = 0;
+      cs[r].replacements = 0;
+      cs[r].rz = 0.0;
+      cs[r].beta = 0.0;
+      cs[r].rr_best = rr;
+      cs[r].stall = 0;
+      if (!isfinite(rr) || !isfinite(ff))
+        cs[r].state = CG_BREAKDOWN;
+      else if (ff == 0.0 || rr <= cs[r].tol2)
+        cs[r].state = CG_DONE;
+      else
+        cs[r].state = CG_ACTIVE;
+    }
+  }
+};
+
+struct FinBeta {
+  CgScalars* cs;
+  int nrhs;
+  __device__ void operator()(const double* tot) const {
+    for (int r = 0; r < nrhs; ++r) {
+      if (cs[r].state != CG_ACTIVE) continue;
+      const double rzn = tot[2 * r], rzm = tot[2 * r + 1];
+      if (!isfinite(rzn) || !isfinite(rzm)) {
+        cs[r].state = CG_BREAKDOWN;
+        continue;
+      }
+      // standard beta for the symmetric FP64 V-cycle, flexible
+      // (Polak-Ribiere) beta for the FP32 one; p = z after a (re)start
+      const double num = cs[r].flexible ? (rzn - rzm) : rzn;
+      cs[r].beta = (cs[r].rz == 0.0) ? 0.0 : num / cs[r].rz;
+      cs[r].rz = rzn;
+    }
+  }
+};
+
+// ------------------------------------------------------------ apply kernel
+// One output node per thread, one load case per grid row (blockIdx.y).
+// Register budgets: the matrix-free kernel keeps the 27-node neighbourhood in
+// registers (2 waves per SIMD); the stored-operator kernels stream their
+// coefficients (4 waves per SIMD).
+template <class Op> struct Waves { static constexpr int w = 4; };
+template <typename T> struct Waves<OpMF<T>> { static constexpr int w = 2; };
+
+template <typename T, class Op, class In, class Ep, class Fin>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(Waves<Op>::w)))
+void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_state, RedBuf red,
+             int slot, Fin fin) {
+  if (gate && !any_state(gate, nrhs, gate_state)) return;
+  const long node = (long)blockIdx.x * BS + threadIdx.x;
+  const int r = blockIdx.y;
+  double a0 = 0.0, a1 = 0.0;
+  if (node < op.L.nn() && ep.rhs_on(r)) {
+    T ax[3];
+    ax_any(op, in, r, node, ax);
+    ep.put(r, node, ax, a0, a1);
+  }
+  if constexpr (Ep::RED) grid_reduce_rhs(a0, a1, nrhs, red, slot, fin);
+}
+
+template <typename T, class Op, class In, class Ep, class Fin = FinNone>
+static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const CgScalars* gate,
+                      int gate_state, hipStream_t st, RedBuf red = RedBuf{nullptr, nullptr},
+                      int slot = 0, Fin fin = Fin{}) {
+  const long nn = op.L.nn();
+  const int nb = nblocks(nn);
+  if (Ep::RED && (long)nb * nrhs > MAX_BLOCKS)
+    throw Error(-1, "mesh too large for the reduction buffer");
+  hipLaunchKernelGGL((k_apply<T, Op, In, Ep, Fin>), dim3(nb, nrhs), dim3(BS), 0, st, op, in, ep,
+                     nrhs, gate, gate_state, red, slot, fin);
+  MGCG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_apply_mf(const OpMF<T>& op, const T* x, T* y, int nrhs, hipStream_t st) {
+  const long nd = op.L.ndof();
+  run_apply<T>(op, InPlain<T>{x, nd}, EpStore<T>{y, nd}, nrhs, nullptr, 0, st);
+}
+template <typename T>
+void launch_apply_st(const OpST<T>& op, const T* x, T* y, int nrhs, hipStream_t st) {
+  const long nd = op.L.ndof();
+  run_apply<T>(op, InPlain<T>{x, nd}, EpStore<T>{y, nd}, nrhs, nullptr, 0, st);
+}
+template <typename T>
+void launch_apply_eq2(const OpEQ2<T>& op, const T* x, T* y, int nrhs, hipStream_t st) {
+  const long nd = op.L.ndof();
+  run_apply<T>(op, InPlain<T>{x, nd}, EpStore<T>{y, nd}, nrhs, nullptr, 0, st);
+}
+template void launch_apply_mf<double>(const OpMF<double>&, const double*, double*, int, hipStream_t);
+template void launch_apply_mf<float>(const OpMF<float>&, const float*, float*, int, hipStream_t);
+template void launch_apply_st<double>(const OpST<double>&, const double*, double*, int, hipStream_t);
+template void launch_apply_st<float>(const OpST<float>&, const float*, float*, int, hipStream_t);
+template void launch_apply_eq2<double>(const OpEQ2<double>&, const double*, double*, int, hipStream_t);
+template void launch_apply_eq2<float>(const OpEQ2<float>&, const float*, float*, int, hipStream_t);
+
+// ------------------------------------------------------------ CG (FP64)
+template <class In, class Ep, class Fin>
+static void fine_dispatch(const FineOp& A, const In& in, const Ep& ep, int nrhs,
+                          const CgScalars* gate, int gate_state, hipStream_t st, RedBuf red,
+                          int slot, Fin fin) {
+  switch (A.kind) {
+    case OP_MF_Q1: run_apply<double>(A.mf, in, ep, nrhs, gate, gate_state, st, red, slot, fin); break;
+    case OP_ST27: run_apply<double>(A.st, in, ep, nrhs, gate, gate_state, st, red, slot, fin); break;
+    default: run_apply<double>(A.eq2, in, ep, nrhs, gate, gate_state, st, red, slot, fin); break;
+  }
+}
+
+void cg_init_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
+                      CgScalars* cs, RedBuf red, hipStream_t st) {
+  const long nd = A.lat().ndof();
+  fine_dispatch(A, InPlain<double>{x, nd}, EpInitResid{f, r, nd, nrhs}, nrhs, nullptr, 0, st, red,
+                0, FinInit{cs, nrhs});
+}
+
+void cg_apply_alpha(const FineOp& A, const double* p, double* q, int nrhs, CgScalars* cs,
+                    RedBuf red, hipStream_t st) {
+  const long nd = A.lat().ndof();
+  fine_dispatch(A, InPlain<double>{p, nd}, EpDotPQ{p, q, nd, cs}, nrhs, cs, CG_ACTIVE, st, red, 1,
+                FinAlpha{cs, nrhs});
+}
+
+void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
+                      CgScalars* cs, RedBuf red, hipStream_t st) {
+  const long nd = A.lat().ndof();
+  fine_dispatch(A, InPlain<double>{x, nd}, EpTrueResid{f, r, nd, cs}, nrhs, cs, CG_CHECK, st, red,
+                2, FinTrue{cs, nrhs});
+}
+
+__global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
+                                                  const double* __restrict__ q, double* x, double* r,
+                                                  long ndof, int nrhs, CgScalars* cs, RedBuf red) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  double acc[MAX_RED_VALUES];
+#pragma unroll
+  for (int v = 0; v < MAX_RED_VALUES; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
+    const double a = cs[rr].alpha;
+    const size_t o = (size_t)rr * ndof;
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
+      x[o + i] += a * p[o + i];
+      const double rn = r[o + i] - a * q[o + i];
+      r[o + i] = rn;
+      s += rn * rn;
+    }
+    acc[rr] = s;
+  }
+  grid_reduce(acc, nrhs, red, 3, FinResid{cs, nrhs});
+}
+
+void cg_update_xr(const double* p, const double* q, double* x, double* r, long ndof, int nrhs,
+                  CgScalars* cs, RedBuf red, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr, dim3(vec_grid(ndof)), dim3(BS), 0, st, p, q, x, r, ndof, nrhs, cs,
+                     red);
+  MGCG_HIP(hipGetLastError());
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
+                                             const double* __restrict__ rold,
+                                             const TZ* __restrict__ z, long ndof, int nrhs,
+                                             CgScalars* cs, RedBuf red) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  double acc[MAX_RED_VALUES];
+#pragma unroll
+  for (int v = 0; v < MAX_RED_VALUES; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
+    const size_t o = (size_t)rr * ndof;
+    double s0 = 0.0, s1 = 0.0;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
+      const double zz = (double)z[o + i];
+      s0 += r[o + i] * zz;
+      s1 += rold[o + i] * zz;
+    }
+    acc[2 * rr] = s0;
+    acc[2 * rr + 1] = s1;
+  }
+  grid_reduce(acc, 2 * nrhs, red, 4, FinBeta{cs, nrhs});
+}
+
+template <typename TZ>
+void cg_beta(const double* r, const double* rold, const TZ* z, long ndof, int nrhs, CgScalars* cs,
+             RedBuf red, hipStream_t st) {
+  hipLaunchKernelGGL(k_beta<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, r, rold, z, ndof, nrhs, cs,
+                     red);
+  MGCG_HIP(hipGetLastError());
+}
+template void cg_beta<double>(const double*, const double*, const double*, long, int, CgScalars*,
+                              RedBuf, hipStream_t);
+template void cg_beta<float>(const double*, const double*, const float*, long, int, CgScalars*,
+                             RedBuf, hipStream_t);
+
+template <typename TZ>
+__global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, double* p,
+                                                 const double* __restrict__ r, double* rold,
+                                                 long ndof, int nrhs, const CgScalars* cs) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  for (int rr = 0; rr < nrhs; ++rr) {
+    if (cs[rr].state != CG_ACTIVE) continue;
+    const double b = cs[rr].beta;
+    const size_t o = (size_t)rr * ndof;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
+      p[o + i] = (double)z[o + i] + b * p[o + i];
+      rold[o + i] = r[o + i];
+    }
+  }
+}
+
+template <typename TZ>
+void cg_update_p(const TZ* z, double* p, const double* r, double* rold, long ndof, int nrhs,
+                 const CgScalars* cs, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_p<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, z, p, r, rold, ndof,
+                     nrhs, cs);
+  MGCG_HIP(hipGetLastError());
+}
+template void cg_update_p<double>(const double*, double*, const double*, double*, long, int,
+                                  const CgScalars*, hipStream_t);
+template void cg_update_p<float>(const float*, double*, const double*, double*, long, int,
+                                 const CgScalars*, hipStream_t);
+
+// ------------------------------------------------------------ V-cycle
+template <typename T, class In, class Ep>
+static void v_dispatch(const VOps<T>& v, const In& in, const Ep& ep, int nrhs, const CgScalars* cs,
+                       hipStream_t st) {
+  switch (v.kind) {
+    case OP_MF_Q1: run_apply<T>(v.mf, in, ep, nrhs, cs, CG_ACTIVE, st); break;
+    case OP_ST27: run_apply<T>(v.st, in, ep, nrhs, cs, CG_ACTIVE, st); break;
+    default: run_apply<T>(v.eq2, in, ep, nrhs, cs, CG_ACTIVE, st); break;
+  }
+}
+
+template <typename T>
+void v_presmooth_residual(const VOps<T>& v, const T* b, T* x, T* r, T omega, int nrhs,
+                          const CgScalars* cs, hipStream_t st) {
+  const long nd = v.L.ndof();
+  v_dispatch(v, InScaledB<T>{b, v.invD, omega, nd}, EpResidX<T>{b, v.invD, omega, r, x, nd}, nrhs,
+             cs, st);
+}
+
+template <typename T>
+void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs,
+              const CgScalars* cs, hipStream_t st) {
+  const long nd = v.L.ndof();
+  v_dispatch(v, InPlain<T>{x, nd}, EpJacobi<T>{b, x, v.invD, omega, xo, nd}, nrhs, cs, st);
+}
+
+template <typename T>
+void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const CgScalars* cs,
+                hipStream_t st) {
+  const long nd = v.L.ndof();
+  v_dispatch(v, InPlain<T>{x, nd}, EpResid<T>{b, r, nd}, nrhs, cs, st);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_smooth0(const T* __restrict__ b, const T* __restrict__ invD,
+                                                T* x, T omega, long ndof, int nrhs,
+                                                const CgScalars* cs) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  for (int r = 0; r < nrhs; ++r) {
+    const size_t o = (size_t)r * ndof;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS)
+      x[o + i] = omega * invD[i] * b[o + i];
+  }
+}
+
+template <typename T>
+void v_smooth0(const T* b, const T* invD, T* x, T omega, long ndof, int nrhs, const CgScalars* cs,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_smooth0<T>, dim3(vec_grid(ndof)), dim3(BS), 0, st, b, invD, x, omega, ndof,
+                     nrhs, cs);
+  MGCG_HIP(hipGetLastError());
+}
+
+// Restriction: coarse DOF (I, c) gathers component c of the 3x3x3 fine nodes
+// around 2I with weights prod_d (1 - |offset_d| / 2); one thread per coarse
+// DOF.  Fine inputs vanish on fixed DOFs; fixed coarse DOFs get 0.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __restrict__ mf,
+                                                 const uint8_t* __restrict__ mc,
+                                                 const T* __restrict__ rf, T* bc, int nrhs,
+                                                 const CgScalars* cs) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  const long t = (long)blockIdx.x * BS + threadIdx.x;
+  const long cnd = C.ndof();
+  if (t >= cnd) return;
+  const long node = t / 3;
+  const int c = (int)(t % 3);
+  int I, J, K;
+  node_ijk(node, C, I, J, K);
+  const bool fixed = (mc[node] >> c) & 1;
+  const long fnd = F.ndof();
+  for (int r = 0; r < nrhs; ++r) {
+    T acc = T(0);
+    const T* src = rf + (size_t)r * fnd + c;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
+          if ((unsigned)i >= (unsigned)F.nx || (unsigned)j >= (unsigned)F.ny ||
+              (unsigned)k >= (unsigned)F.nz)
+            continue;
+          const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+          acc += w * src[3 * (i + (long)F.nx * (j + (long)F.ny * k))];
+        }
+    bc[(size_t)r * cnd + t] = fixed ? T(0) : acc;
+  }
+  (void)mf;
+}
+
+template <typename T>
+void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* rf,
+                T* bc, int nrhs, const CgScalars* cs, hipStream_t st) {
+  hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(coarse.ndof())), dim3(BS), 0, st, fine, coarse,
+                     mask_f, mask_c, rf, bc, nrhs, cs);
+  MGCG_HIP(hipGetLastError());
+}
+
+// Prolongation: fine node i interpolates the coarse nodes around i/2.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __restrict__ mf,
+                                                const uint8_t* __restrict__ mc,
+                                                const T* __restrict__ ec, T* xf, int nrhs,
+                                                int accumulate, const CgScalars* cs) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  const long node = (long)blockIdx.x * BS + threadIdx.x;
+  if (node >= F.nn()) return;
+  int i, j, k;
+  node_ijk(node, F, i, j, k);
+  const uint8_t mfn = mf[node];
+  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  const long fnd = F.ndof(), cnd = C.ndof();
+  for (int r = 0; r < nrhs; ++r) {
+    T acc[3] = {T(0), T(0), T(0)};
+    for (int c2 = 0; c2 < nk; ++c2)
+      for (int b2 = 0; b2 < nj; ++b2)
+        for (int a2 = 0; a2 < ni; ++a2) {
+          const long cn = (i0 + a2) + (long)C.nx * ((j0 + b2) + (long)C.ny * (k0 + c2));
+          const T w = wi * wj * wk;
+          const T* p = ec + (size_t)r * cnd + 3 * cn;  // vanishes on fixed coarse DOFs
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[c] += w * p[c];
+        }
+    T* q = xf + (size_t)r * fnd + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T v = ((mfn >> c) & 1) ? T(0) : acc[c];
+      q[c] = accumulate ? q[c] + v : v;
+    }
+  }
+}
+
+template <typename T>
+void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* ec,
+               T* xf, int nrhs, bool accumulate, const CgScalars* cs, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(fine.nn())), dim3(BS), 0, st, fine, coarse, mask_f,
+                     mask_c, ec, xf, nrhs, accumulate ? 1 : 0, cs);
+  MGCG_HIP(hipGetLastError());
+}
+
+// Coarsest solve: one wavefront per free DOF row of A_c^{-1}.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ Ainv,
+                                                     const int* __restrict__ freedof, int nc,
+                                                     long ndof, const T* __restrict__ b, T* x,
+                                                     int nrhs, const CgScalars* cs) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nc) return;
+  const double* a = Ainv + (size_t)row * nc;
+  for (int r = 0; r < nrhs; ++r) {
+    const T* bb = b + (size_t)r * ndof;
+    double s = 0.0;
+    for (int c = lane; c < nc; c += 64) s += a[c] * (double)bb[freedof[c]];
+    s = wave_sum(s);
+    if (lane == 0) x[(size_t)r * ndof + freedof[row]] = (T)s;
+  }
+}
+
+template <typename T>
+void v_coarse_solve(const double* Ainv, const int* freedof, int nc, long ndof, const T* b, T* x,
+                    int nrhs, const CgScalars* cs, hipStream_t st) {
+  if (nc == 0) return;
+  hipLaunchKernelGGL(k_coarse_solve<T>, dim3((nc + 3) / 4), dim3(BS), 0, st, Ainv, freedof, nc,
+                     ndof, b, x, nrhs, cs);
+  MGCG_HIP(hipGetLastError());
+}
+
+#define VINST(T)                                                                                  \
+  template void v_presmooth_residual<T>(const VOps<T>&, const T*, T*, T*, T, int, const CgScalars*, \
+                                        hipStream_t);                                             \
+  template void v_jacobi<T>(const VOps<T>&, const T*, const T*, T*, T, int, const CgScalars*,      \
+                            hipStream_t);                                                         \
+  template void v_residual<T>(const VOps<T>&, const T*, const T*, T*, int, const CgScalars*,       \
+                              hipStream_t);                                                       \
+  template void v_smooth0<T>(const T*, const T*, T*, T, long, int, const CgScalars*, hipStream_t); \
+  template void v_restrict<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, int,         \
+                              const CgScalars*, hipStream_t);                                     \
+  template void v_prolong<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, int, bool,    \
+                             const CgScalars*, hipStream_t);                                      \
+  template void v_coarse_solve<T>(const double*, const int*, int, long, const T*, T*, int,         \
+                                  const CgScalars*, hipStream_t);
+VINST(double)
+VINST(float)
+
+// ------------------------------------------------------------ inspection helpers
+__global__ void k_mask_copy(const double* __restrict__ x, double* xm, const uint8_t* __restrict__ m,
+                            long nn, int nrhs) {
+  const long n3 = 3 * nn;
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < n3 * nrhs; t += (long)gridDim.x * BS) {
+    const long i = t % n3;
+    xm[t] = ((m[i / 3] >> (i % 3)) & 1) ? 0.0 : x[t];
+  }
+}
+void mask_copy(const double* x, double* xm, const uint8_t* mask, long nn, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_mask_copy, dim3(vec_grid(3 * nn * nrhs)), dim3(BS), 0, st, x, xm, mask, nn,
+                     nrhs);
+  MGCG_HIP(hipGetLastError());
+}
+__global__ void k_identity_rows(const double* __restrict__ x, double* y,
+                                const uint8_t* __restrict__ m, long nn, int nrhs) {
+  const long n3 = 3 * nn;
+  for (long t = (long)blockIdx.x * BS + threadIdx.x; t < n3 * nrhs; t += (long)gridDim.x * BS) {
+    const long i = t % n3;
+    if ((m[i / 3] >> (i % 3)) & 1) y[t] = x[t];
+  }
+}
+void identity_rows(const double* x, double* y, const uint8_t* mask, long nn, int nrhs,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_identity_rows, dim3(vec_grid(3 * nn * nrhs)), dim3(BS), 0, st, x, y, mask,
+                     nn, nrhs);
+  MGCG_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ small utilities
+template <typename TA, typename TB>
+__global__ void k_convert(const TA* __restrict__ a, TB* b, long n) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) b[i] = (TB)a[i];
+}
+template <typename TA, typename TB>
+void convert(const TA* a, TB* b, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_convert<TA, TB>), dim3(vec_grid(n)), dim3(BS), 0, st, a, b, n);
+  MGCG_HIP(hipGetLastError());
+}
+template void convert<double, float>(const double*, float*, long, hipStream_t);
+template void convert<float, double>(const float*, double*, long, hipStream_t);
+template void convert<double, double>(const double*, double*, long, hipStream_t);
+
+template <typename T>
+__global__ void k_fill(T* a, T v, long n) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) a[i] = v;
+}
+template <typename T>
+void fill(T* a, T v, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(vec_grid(n)), dim3(BS), 0, st, a, v, n);
+  MGCG_HIP(hipGetLastError());
+}
+template void fill<double>(double*, double, long, hipStream_t);
+template void fill<float>(float*, float, long, hipStream_t);
+template void fill<int>(int*, int, long, hipStream_t);
+template void fill<unsigned>(unsigned*, unsigned, long, hipStream_t);
+
+__global__ void k_copy16(const uint4* __restrict__ a, uint4* b, long n) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) b[i] = a[i];
+}
+__global__ void k_copy1(const uint8_t* __restrict__ a, uint8_t* b, long n) {
+  for (long i = (long)blockIdx.x * BS + threadIdx.x; i < n; i += (long)gridDim.x * BS) b[i] = a[i];
+}
+void copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t st) {
+  const long n16 = (long)(bytes / 16);
+  if (n16 > 0) {
+    long g = (n16 + BS * 4 - 1) / (BS * 4);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_copy16, dim3(g), dim3(BS), 0, st, (const uint4*)src, (uint4*)dst, n16);
+  }
+  const long rem = (long)(bytes - 16 * (size_t)n16);
+  if (rem > 0)
+    hipLaunchKernelGGL(k_copy1, dim3(1), dim3(BS), 0, st, (const uint8_t*)src + 16 * n16,
+                       (uint8_t*)dst + 16 * n16, rem);
+  MGCG_HIP(hipGetLastError());
+}
+
+}  // namespace mgcg
+
+namespace mgcg {
+
+__global__ void k_cg_reset(CgScalars* cs, int nrhs, double rtol2, int maxit, int replace_every,
+                           int flexible) {
+  const int r = threadIdx.x;
+  if (r >= nrhs) return;
+  cs[r].flexible = flexible;
+  cs[r].tol2 = rtol2;  // scaled by ||f||^2 in the initial residual kernel
+  cs[r].maxit = maxit;
+  cs[r].replace_every = replace_every;
+  cs[r].state = CG_ACTIVE;
+  cs[r].iters = 0;
+  cs[r].replacements = 0;
+}
+
+void cg_reset(CgScalars* cs, int nrhs, double rtol2, int maxit, int replace_every, int flexible,
+              hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, st, cs, nrhs, rtol2, maxit, replace_every,
+                     flexible);
+  MGCG_HIP(hipGetLastError());
+}
+
+}  // namespace mgcg

@@ -1,0 +1,188 @@
+// Device-side operator views and kernel launchers (host-callable).
+#pragma once
+
+#include "common.h"
+#include "q1table.h"
+
+namespace mgcg {
+
+// Node lattice of a level.
+struct Lat {
+  int nx, ny, nz;
+  __host__ __device__ long nn() const { return (long)nx * ny * nz; }
+  __host__ __device__ long ndof() const { return 3L * nx * ny * nz; }
+};
+
+// Matrix-free trilinear operator: elements (nx-1)(ny-1)(nz-1), modulus E per
+// element, the shared unit element matrix as its 10 coefficient-class values
+// (kept in scalar registers), supports in mask (bit c of a node's byte =
+// component c fixed).  Inputs must vanish on fixed DOFs (every solver vector
+// does); fixed rows return the input (identity).
+template <typename T>
+struct OpMF {
+  Lat L;
+  const T* E;
+  Q1Vals<T> kv;
+  const uint8_t* mask;
+};
+
+// Assembled 27-point block stencil, symmetric half storage: coef[(b*9 + 3c + e) * nn + node]
+// holds A_{node, node + d_b}(c, e) for the 14 blocks of st_offset; supports are
+// baked in (identity rows/columns).
+template <typename T>
+struct OpST {
+  Lat L;
+  const T* coef;
+};
+
+// Stored triquadratic element matrices Ke[e][81*81] (supported rows/columns
+// zeroed), on the quadratic node lattice (nx = 2*nelx + 1, ...).
+template <typename T>
+struct OpEQ2 {
+  Lat L;
+  const T* Ke;
+  const uint8_t* mask;
+};
+
+// Reduction scratch: partials[slot][block], a ticket counter per slot.
+struct RedBuf {
+  double* partials;  // [MAX_RED_VALUES][MAX_BLOCKS]
+  unsigned* counter; // [8]
+};
+constexpr int MAX_BLOCKS = 16384;
+constexpr int MAX_RED_VALUES = 12;
+
+// ---------------- launchers ----------------
+// All launchers enqueue on `st`; nrhs vectors are stored back to back with
+// stride ndof of the level.
+
+// Generic apply y = A x (A = Z K Z + I - Z) for parity inspection.
+template <typename T> void launch_apply_mf(const OpMF<T>& op, const T* x, T* y, int nrhs, hipStream_t st);
+template <typename T> void launch_apply_st(const OpST<T>& op, const T* x, T* y, int nrhs, hipStream_t st);
+template <typename T> void launch_apply_eq2(const OpEQ2<T>& op, const T* x, T* y, int nrhs, hipStream_t st);
+
+// Fine-level FP64 CG operator, one of the three kinds.
+struct FineOp {
+  int kind;
+  OpMF<double> mf;
+  OpST<double> st;
+  OpEQ2<double> eq2;
+  Lat lat() const { return kind == OP_MF_Q1 ? mf.L : kind == OP_ST27 ? st.L : eq2.L; }
+};
+
+// CG kernels (FP64), state gated.
+void cg_reset(CgScalars* cs, int nrhs, double rtol2, int maxit, int replace_every, int flexible,
+              hipStream_t st);
+void cg_init_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
+                      CgScalars* cs, RedBuf red, hipStream_t st);
+void cg_apply_alpha(const FineOp& A, const double* p, double* q, int nrhs, CgScalars* cs,
+                    RedBuf red, hipStream_t st);
+void cg_update_xr(const double* p, const double* q, double* x, double* r, long ndof, int nrhs,
+                  CgScalars* cs, RedBuf red, hipStream_t st);
+void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
+                      CgScalars* cs, RedBuf red, hipStream_t st);
+template <typename TZ>
+void cg_beta(const double* r, const double* rold, const TZ* z, long ndof, int nrhs, CgScalars* cs,
+             RedBuf red, hipStream_t st);
+template <typename TZ>
+void cg_update_p(const TZ* z, double* p, const double* r, double* rold, long ndof, int nrhs,
+                 const CgScalars* cs, hipStream_t st);
+
+// V-cycle level kernels in precision T (gated by any active CG state; cs may be null).
+struct VLevelArgs;  // fwd
+template <typename T>
+struct VOps {
+  int kind;  // operator kind of this level
+  OpMF<T> mf;
+  OpST<T> st;
+  OpEQ2<T> eq2;
+  const T* invD;
+  const uint8_t* mask;
+  Lat L;
+};
+// x = omega invD b; r = b - A x (the first pre-smoothing sweep from zero, fused
+// with the residual).
+template <typename T>
+void v_presmooth_residual(const VOps<T>& v, const T* b, T* x, T* r, T omega, int nrhs,
+                          const CgScalars* cs, hipStream_t st);
+// xo = x + omega invD (b - A x)
+template <typename T>
+void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs,
+              const CgScalars* cs, hipStream_t st);
+// r = b - A x
+template <typename T>
+void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const CgScalars* cs,
+                hipStream_t st);
+// x = omega invD b
+template <typename T>
+void v_smooth0(const T* b, const T* invD, T* x, T omega, long ndof, int nrhs, const CgScalars* cs,
+               hipStream_t st);
+// coarse = P~^T fine
+template <typename T>
+void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* rf,
+                T* bc, int nrhs, const CgScalars* cs, hipStream_t st);
+// fine += P~ coarse  (accumulate=false: fine = P~ coarse)
+template <typename T>
+void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* ec,
+               T* xf, int nrhs, bool accumulate, const CgScalars* cs, hipStream_t st);
+// x = A_c^{-1} b on the coarsest level: Ainv [nc][nc] over the free DOF list.
+template <typename T>
+void v_coarse_solve(const double* Ainv, const int* freedof, int nc, long ndof, const T* b, T* x,
+                    int nrhs, const CgScalars* cs, hipStream_t st);
+
+// Zero the fixed DOFs of x (nrhs vectors): xm = Z x.
+void mask_copy(const double* x, double* xm, const uint8_t* mask, long nn, int nrhs, hipStream_t st);
+// Identity rows: y_i = x_i on fixed DOFs.
+void identity_rows(const double* x, double* y, const uint8_t* mask, long nn, int nrhs,
+                   hipStream_t st);
+
+// Type conversions and fills.
+template <typename TA, typename TB>
+void convert(const TA* a, TB* b, long n, hipStream_t st);
+template <typename T>
+void fill(T* a, T v, long n, hipStream_t st);
+
+// ---------------- set-up kernels ----------------
+// E_i = Emin + rho_i^p (E0 - Emin); writes bad[0] = 1 on NaN or out-of-range.
+void setup_simp(const double* rho, double* E, float* E32, long n, double E0, double Emin,
+                double penal, int* bad, hipStream_t st);
+// Effective element matrices Keff[e] = sum_s E[dens(e,s)] Ksub[s] (nd x nd),
+// rows/columns of supported DOFs zeroed.
+void setup_effective(int order, int nsub, int nelx, int nely, int nelz, const double* E,
+                     const double* Ksub, const uint8_t* mask, Lat L, double* Keff, hipStream_t st);
+// Galerkin coarse element matrices (24x24 Q1-type) of a coarse element grid.
+//  src kind OP_MF_Q1: children are E_c * K0 (child mask applied here);
+//  OP_ST27 (Q1-type elements with stored matrices Kc [nel_f][576], masks baked or applied);
+//  OP_EQ2: each coarse element is one quadratic fine element (81x81 -> 24x24).
+void setup_galerkin(int src_kind, Lat fine, const double* E, const double* K0, const double* Kc,
+                    const uint8_t* mask_f, int ncx, int ncy, int ncz, double* KE, hipStream_t st);
+// Assemble Q1-type element matrices into the half stencil, with the supports
+// of mask baked in, plus the Jacobi data wD_i = min(omega, theta A_ii /
+// sum_j |A_ij|) / A_ii (0 on fixed DOFs) and the plain diagonal.
+template <typename T>
+void setup_stencil(Lat L, const double* KE, const uint8_t* mask, T* coef, T* wD, double* diag64,
+                   double omega, double theta, hipStream_t st);
+// The same Jacobi data for the matrix-free / stored-Q2 fine operators.
+template <typename T>
+void setup_diag_mf(Lat L, const double* E, const double* K0, const uint8_t* mask, T* wD,
+                   double* diag64, double omega, double theta, hipStream_t st);
+template <typename T>
+void setup_diag_eq2(Lat L, const double* Ke, const uint8_t* mask, T* wD, double* diag64,
+                    double omega, double theta, hipStream_t st);
+// Coarsest level: dense A_ff from the element matrices, Cholesky, explicit inverse.
+void setup_dense(int src_kind, Lat L, const double* E, const double* K0, const double* KE,
+                 const int* freedof, const int* dofpos, int nc, double* A, hipStream_t st);
+void setup_cholesky_inverse(double* A, double* Linv, double* Ainv, int nc, int* bad,
+                            hipStream_t st);
+
+// Compliance and sensitivity.
+void comp_dot(const double* f, const double* u, long ndof, int nrhs, double* out, RedBuf red,
+              hipStream_t st);
+void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const double* rho,
+                 const double* u, long ndof, int nrhs, const double* Ksub, double scale_p,
+                 double E0mEmin, double penal, double* dc, hipStream_t st);
+
+// Timing-free plain copy (for traffic calibration).
+void copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t st);
+
+}  // namespace mgcg

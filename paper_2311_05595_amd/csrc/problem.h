@@ -1,0 +1,183 @@
+// Host runtime: a problem's hierarchy plan, device arena and solver.
+#pragma once
+
+#include <chrono>
+#include <memory>
+#include <vector>
+
+#include "../../include/mgcg.h"
+#include "kernels.h"
+
+namespace mgcg {
+
+struct LevelPlan {
+  Lat L;
+  int kind;          // OP_MF_Q1 / OP_ST27 / OP_EQ2
+  int ncx, ncy, ncz; // element grid of the level
+};
+
+// Device buffers of one level (V-cycle precision T for vectors and operator copies).
+struct LevelBufs {
+  uint8_t* mask = nullptr;
+  double* KE = nullptr;      // Q1-type element matrices [nel][576] (levels >= 1; level 0 ST27: Keff)
+  void* coefV = nullptr;     // stencil in V precision (levels >= 1, level 0 ST27)
+  double* coef64 = nullptr;  // FP64 stencil (level 0 ST27 when V precision is FP32)
+  void* invD = nullptr;      // [ndof] V precision
+  double* diag64 = nullptr;  // [ndof]
+  void* b = nullptr;         // [nrhs][ndof] V precision
+  void* xa = nullptr;
+  void* xb = nullptr;
+  void* r = nullptr;
+};
+
+// HIP events around every launch of one kernel (id): 0 = the CG operator
+// apply q = A p on the finest level, 1 = the finest-level pre-smoothing +
+// residual apply, 2 = the finest-level post-smoothing Jacobi apply.
+struct KernelTimer {
+  bool enabled = false;
+  int kernel = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  std::vector<int> recs;  // iteration index of each recorded launch
+  size_t used = 0;
+  double total_ms = 0.0;
+  long long launches = 0;
+};
+
+class Problem {
+ public:
+  Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int device);
+  ~Problem();
+
+  static void plan_levels(const mgcg_desc& d, std::vector<LevelPlan>& lv);
+  static size_t device_bytes(const mgcg_desc& d);
+
+  void allocate();
+  void release();
+  bool allocated() const { return arena_ != nullptr; }
+  size_t bytes() const { return bytes_; }
+
+  void set_stream(hipStream_t s);
+  hipStream_t stream() const { return stream_; }
+  int device() const { return device_; }
+
+  void set_densities(const double* rho, int mem);
+  // Enqueue the refresh without waiting; the density check happens when the
+  // next solve finishes.
+  void set_densities_async(const double* rho, int mem);
+  // Blocking solve.
+  int solve(double rtol, int maxit, bool warm, mgcg_info* info);
+  // Non-blocking pieces used by the server.
+  void solve_begin(double rtol, int maxit, bool warm);
+  void solve_chunk(int iters);             // enqueue iterations + state readback
+  bool solve_poll(bool block);             // true when every load case finished
+  int solve_finish(mgcg_info* info);       // fills info; returns status
+  int suggest_chunk() const;
+  bool solve_pending() const { return chunk_pending_; }
+
+  void get_u(double* u, int mem);
+  void set_u(const double* u, int mem);
+  void compliance_sensitivity(double* c, double* dc, int mem);
+
+  // inspection
+  void level_dims(int level, int32_t* dims, int64_t* ndof) const;
+  void apply(int level, int prec, const double* x, double* y, int mem);
+  void diag(int level, double* d, int mem);
+  void restrict_(int level, const double* f, double* c, int mem);
+  void prolong(int level, const double* c, double* f, int mem);
+  void precondition(const double* r, double* z, int mem);
+  void coarse_solve(const double* b, double* x, int mem);
+
+  void set_timing(bool on, int kernel = 0);
+  void get_timing(int kernel, double* ms, long long* launches);
+  void copy(const void* src, void* dst, size_t bytes);
+
+  const mgcg_desc& desc() const { return d_; }
+  static size_t layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, char* base, Problem* s);
+  long ndof0() const { return lv_[0].L.ndof(); }
+  long nrho() const;
+  double last_setup_ms() const { return setup_ms_; }
+
+ private:
+  template <typename T> void vcycle(const double* r_in, int gate);
+  template <typename T> VOps<T> vops(int level) const;
+  template <typename T> void do_set_densities();
+  template <typename T> void do_apply_v(int level, const double* x, double* y);
+  void iteration();
+  FineOp fine_op() const;
+  void sync();
+  void check_bad(int which);
+  void timed_begin(int id);
+  void timed_end(int id);
+  void harvest_timing(int itmax);
+
+  mgcg_desc d_;
+  int device_;
+  int vbytes_;  // 8 or 4
+  std::vector<LevelPlan> lv_;
+  std::vector<uint8_t> hmask_;  // per level node masks, concatenated
+  std::vector<size_t> hmask_off_;
+  std::vector<double> hf_;
+  std::vector<double> hKsub_;
+  std::vector<int> hfree_;      // coarsest free DOF list
+  std::vector<int> hdofpos_;
+
+  hipStream_t stream_ = nullptr;
+  hipStream_t own_stream_ = nullptr;
+  char* arena_ = nullptr;
+  size_t bytes_ = 0;
+
+  // device pointers
+  std::vector<LevelBufs> B_;
+  double* f_ = nullptr;
+  double* rho_ = nullptr;
+  double* E_ = nullptr;
+  float* E32_ = nullptr;
+  Q1Vals<double> kv64_{};   // unit trilinear element (10 class values)
+  Q1Vals<float> kv32_{};
+  double* Ksub_ = nullptr;   // [n^3][nd*nd]
+  double* K0_ = nullptr;     // [576] (MF)
+  float* K032_ = nullptr;
+  double* Keff_ = nullptr;   // level-0 effective element matrices (ST27: 576, EQ2: 6561)
+  float* Keff32_ = nullptr;  // EQ2 mixed copy
+  double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr, *rold_ = nullptr;
+  CgScalars* cs_ = nullptr;
+  RedBuf red_{nullptr, nullptr};
+  double* compout_ = nullptr;
+  int* bad_ = nullptr;
+  int* dfree_ = nullptr;
+  int* ddofpos_ = nullptr;
+  double *Ad_ = nullptr, *Linv_ = nullptr, *Ainv_ = nullptr;
+  double* tmp64_ = nullptr;  // [nrhs][ndof0] scratch for inspection
+  double* dcbuf_ = nullptr;  // [n_rho] sensitivity staging for host output
+  void* zbuf_ = nullptr;     // level-0 V-cycle output of the last cycle
+  CgScalars* hcs_ = nullptr; // pinned host copy
+
+  int nc_ = 0;
+  bool have_ops_ = false;
+  bool have_u_ = false;
+  double setup_ms_ = 0.0;
+  // solve state
+  double rtol_ = 0.0;
+  int maxit_ = 0;
+  int chunk_iters_done_ = 0;
+  std::chrono::steady_clock::time_point t0_;
+  hipEvent_t ev_chunk_ = nullptr;
+  hipEvent_t ev_s0_ = nullptr, ev_s1_ = nullptr;
+  bool chunk_pending_ = false;
+  int iter_launched_ = 0;
+  size_t timer_used_base_ = 0;
+  bool first_chunk_ = true;
+  bool prev_rr_valid_ = false;
+  double prev_worst_ = 0.0;
+  int prev_iters_ = 0;
+  double rate_log_ = 0.0;
+  bool active_ = false;
+  int replace_every_ = 0;  // periodic residual replacement off: only at convergence
+  bool pending_check_ = false;
+  KernelTimer timer_;
+};
+
+const char* set_error(const std::string& m);
+const char* get_error();
+
+}  // namespace mgcg

@@ -1,0 +1,933 @@
+// Host runtime of one problem: hierarchy plan, a single device arena sized
+// exactly as mgcg_problem_device_bytes reports, the operator refresh, the
+// V-cycle (Algorithm 1 applied recursively) and a device-gated PCG whose
+// convergence test never needs a host round trip inside a chunk.
+#include "problem.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "element.h"
+
+namespace mgcg {
+
+namespace {
+
+// Gershgorin cap of the per-DOF Jacobi weights (every row sum of W D^-1 A
+// stays below 2, so the smoother converges for any densities).
+constexpr double kTheta = 1.9;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Arena {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    size_t o = align256(off);
+    off = o + n * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+void validate(const mgcg_desc& d) {
+  auto bad = [](const char* m) { throw Error(MGCG_EINVAL, m); };
+  if (d.nelx < 1 || d.nely < 1 || d.nelz < 1) bad("element counts must be >= 1");
+  if (d.order != 1 && d.order != 2) bad("order must be 1 or 2");
+  if (d.nsub < 1 || d.nsub > 4) bad("nsub must be 1..4");
+  if (d.nlevels < 1 || d.nlevels > 12) bad("nlevels must be 1..12");
+  if (d.nrhs < 1 || d.nrhs > 4) bad("nrhs must be 1..4");
+  if (d.precision != MGCG_FP64 && d.precision != MGCG_MIXED) bad("precision must be FP64 or MIXED");
+  if (d.pre < 1 || d.pre > 8 || d.post < 0 || d.post > 8) bad("pre must be 1..8, post 0..8");
+  if (!(d.omega > 0.0 && d.omega < 2.0)) bad("omega must be in (0, 2)");
+  if (!(d.E0 > 0.0) || !(d.Emin >= 0.0) || !(d.Emin < d.E0)) bad("need E0 > Emin >= 0");
+  if (!(d.nu > -1.0 && d.nu < 0.5)) bad("nu must be in (-1, 0.5)");
+  if (!(d.penal >= 1.0 && d.penal <= 10.0)) bad("penal must be in [1, 10]");
+  if (d.order == 2 && d.nlevels < 2) bad("quadratic elements need nlevels >= 2");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ planning
+void Problem::plan_levels(const mgcg_desc& d, std::vector<LevelPlan>& lv) {
+  validate(d);
+  lv.clear();
+  LevelPlan l0;
+  const int p = d.order;
+  l0.L = Lat{p * d.nelx + 1, p * d.nely + 1, p * d.nelz + 1};
+  l0.kind = d.order == 2 ? OP_EQ2 : (d.nsub == 1 ? OP_MF_Q1 : OP_ST27);
+  l0.ncx = d.nelx;
+  l0.ncy = d.nely;
+  l0.ncz = d.nelz;
+  lv.push_back(l0);
+  int cx = d.nelx, cy = d.nely, cz = d.nelz;
+  for (int l = 1; l < d.nlevels; ++l) {
+    if (!(l == 1 && d.order == 2)) {
+      if (cx % 2 || cy % 2 || cz % 2)
+        throw Error(MGCG_EINVAL, "too many levels: element counts must be even to coarsen");
+      cx /= 2;
+      cy /= 2;
+      cz /= 2;
+    }
+    LevelPlan lp;
+    lp.L = Lat{cx + 1, cy + 1, cz + 1};
+    lp.kind = OP_ST27;
+    lp.ncx = cx;
+    lp.ncy = cy;
+    lp.ncz = cz;
+    lv.push_back(lp);
+  }
+}
+
+// One layout routine serves both the byte count and the pointer assignment.
+size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, char* base, Problem* s) {
+  Arena A{base};
+  const int R = d.nrhs;
+  const bool mixed = d.precision == MGCG_MIXED;
+  const size_t vb = mixed ? 4 : 8;
+  const long nd0 = lv[0].L.ndof();
+  const long nel0 = (long)d.nelx * d.nely * d.nelz;
+  const long ns3 = (long)d.nsub * d.nsub * d.nsub;
+  const long nrho = nel0 * ns3;
+  const int ndl = d.order == 1 ? 24 : 81;
+  const int L = (int)lv.size();
+#define TAKE(member, T, n)          \
+  do {                              \
+    auto p_ = A.take<T>((size_t)(n)); \
+    if (s) s->member = p_;          \
+  } while (0)
+  TAKE(f_, double, R * nd0);
+  TAKE(rho_, double, nrho);
+  TAKE(E_, double, nrho);
+  if (mixed && lv[0].kind == OP_MF_Q1) TAKE(E32_, float, nrho);
+  TAKE(Ksub_, double, ns3 * ndl * ndl);
+  TAKE(K0_, double, 576);
+  if (mixed) TAKE(K032_, float, 576);
+  TAKE(x_, double, R * nd0);
+  TAKE(r_, double, R * nd0);
+  TAKE(p_, double, R * nd0);
+  TAKE(q_, double, R * nd0);
+  TAKE(rold_, double, R * nd0);
+  TAKE(tmp64_, double, R * nd0);
+  TAKE(cs_, CgScalars, 4);
+  TAKE(red_.partials, double, (size_t)MAX_RED_VALUES * MAX_BLOCKS);
+  TAKE(red_.counter, unsigned, 16);
+  TAKE(compout_, double, 16);
+  TAKE(bad_, int, 4);
+  TAKE(dcbuf_, double, nrho);
+  if (lv[0].kind == OP_ST27) TAKE(Keff_, double, nel0 * 576);
+  if (lv[0].kind == OP_EQ2) {
+    TAKE(Keff_, double, nel0 * 6561);
+    if (mixed) TAKE(Keff32_, float, nel0 * 6561);
+  }
+  for (int l = 0; l < L; ++l) {
+    const long nn = lv[l].L.nn(), nd = lv[l].L.ndof();
+    const long nel = (long)lv[l].ncx * lv[l].ncy * lv[l].ncz;
+    LevelBufs* b = s ? &s->B_[l] : nullptr;
+    auto take_to = [&](auto*& dst, auto tag, size_t n) {
+      using T = decltype(tag);
+      T* p = A.take<T>(n);
+      if (b) dst = p;
+    };
+    uint8_t* um = nullptr;
+    double* dd = nullptr;
+    char* cv = nullptr;
+    take_to(um, uint8_t{}, nn);
+    if (b) b->mask = um;
+    if (l >= 1) {
+      take_to(dd, double{}, nel * 576);
+      if (b) b->KE = dd;
+    }
+    if (l >= 1 || lv[0].kind == OP_ST27) {
+      take_to(cv, char{}, (size_t)ST_COEF * nn * vb);
+      if (b) b->coefV = cv;
+      if (l == 0 && mixed) {
+        take_to(dd, double{}, (size_t)ST_COEF * nn);
+        if (b) b->coef64 = dd;
+      }
+    }
+    take_to(cv, char{}, nd * vb);
+    if (b) b->invD = cv;
+    take_to(dd, double{}, nd);
+    if (b) b->diag64 = dd;
+    take_to(cv, char{}, R * nd * vb);
+    if (b) b->b = cv;
+    take_to(cv, char{}, R * nd * vb);
+    if (b) b->xa = cv;
+    take_to(cv, char{}, R * nd * vb);
+    if (b) b->xb = cv;
+    take_to(cv, char{}, R * nd * vb);
+    if (b) b->r = cv;
+  }
+  const long ndc = lv[L - 1].L.ndof();  // upper bound of the coarsest free DOFs
+  TAKE(dfree_, int, ndc);
+  TAKE(ddofpos_, int, ndc);
+  TAKE(Ad_, double, ndc * ndc);
+  TAKE(Linv_, double, ndc * ndc);
+  TAKE(Ainv_, double, ndc * ndc);
+#undef TAKE
+  return align256(A.off);
+}
+
+size_t Problem::device_bytes(const mgcg_desc& d) {
+  std::vector<LevelPlan> lv;
+  plan_levels(d, lv);
+  return layout(d, lv, nullptr, nullptr);
+}
+
+long Problem::nrho() const {
+  return (long)d_.nelx * d_.nely * d_.nelz * d_.nsub * d_.nsub * d_.nsub;
+}
+
+// ------------------------------------------------------------------ lifetime
+Problem::Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int device)
+    : d_(d), device_(device) {
+  plan_levels(d_, lv_);
+  vbytes_ = d_.precision == MGCG_MIXED ? 4 : 8;
+  const long nd0 = lv_[0].L.ndof();
+  if (!mask || !f) throw Error(MGCG_EINVAL, "mask and f are required");
+  // node masks per level: bit c set when DOF c of the node is fixed; a coarse
+  // node inherits the mask of the fine node it coincides with.
+  hmask_off_.assign(lv_.size() + 1, 0);
+  for (size_t l = 0; l < lv_.size(); ++l) hmask_off_[l + 1] = hmask_off_[l] + lv_[l].L.nn();
+  hmask_.assign(hmask_off_.back(), 0);
+  for (long n = 0; n < lv_[0].L.nn(); ++n) {
+    uint8_t m = 0;
+    for (int c = 0; c < 3; ++c)
+      if (mask[3 * n + c]) m |= (uint8_t)(1 << c);
+    hmask_[n] = m;
+  }
+  for (size_t l = 1; l < lv_.size(); ++l) {
+    const Lat F = lv_[l - 1].L, C = lv_[l].L;
+    const int stride = 2;  // both Q1 halving and the Q2 -> vertex lattice step
+    for (int k = 0; k < C.nz; ++k)
+      for (int j = 0; j < C.ny; ++j)
+        for (int i = 0; i < C.nx; ++i) {
+          const long fn = (long)stride * i + (long)F.nx * ((long)stride * j + (long)F.ny * stride * k);
+          hmask_[hmask_off_[l] + i + (long)C.nx * (j + (long)C.ny * k)] = hmask_[hmask_off_[l - 1] + fn];
+        }
+  }
+  hf_.assign(f, f + (size_t)d_.nrhs * nd0);
+  for (int r = 0; r < d_.nrhs; ++r)
+    for (long i = 0; i < nd0; ++i)
+      if (mask[i]) hf_[(size_t)r * nd0 + i] = 0.0;
+  for (double v : hf_)
+    if (!std::isfinite(v)) throw Error(MGCG_EINVAL, "non-finite load");
+  // coarsest free DOF list
+  const LevelPlan& lc = lv_.back();
+  hdofpos_.assign(lc.L.ndof(), -1);
+  for (long n = 0; n < lc.L.nn(); ++n)
+    for (int c = 0; c < 3; ++c)
+      if (!((hmask_[hmask_off_[lv_.size() - 1] + n] >> c) & 1)) {
+        hdofpos_[3 * n + c] = (int)hfree_.size();
+        hfree_.push_back((int)(3 * n + c));
+      }
+  nc_ = (int)hfree_.size();
+  hKsub_ = sub_element_matrices(d_.order, d_.nsub, d_.nu);
+  B_.resize(lv_.size());
+  // unit trilinear element as 10 class values; must reproduce the quadrature
+  {
+    const double nu = d_.nu;
+    kv64_ = q1_values(nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), 1.0 / (2.0 * (1.0 + nu)));
+    for (int k = 0; k < 10; ++k) kv32_.v[k] = (float)kv64_.v[k];
+    const std::vector<double> k0 = sub_element_matrices(1, 1, nu);
+    double err = 0.0, mx = 0.0;
+    for (int q = 0; q < 576; ++q) {
+      const double v = kQ1.sgn[q] * kv64_.v[kQ1.cls[q]];
+      err = std::max(err, std::fabs(v - k0[q]));
+      mx = std::max(mx, std::fabs(k0[q]));
+    }
+    if (err > 1e-14 * mx) throw Error(MGCG_EINVAL, "element table does not match the quadrature");
+  }
+}
+
+Problem::~Problem() {
+  try {
+    release();
+  } catch (...) {
+  }
+}
+
+void Problem::release() {
+  if (!arena_) return;
+  hipSetDevice(device_);
+  if (stream_) hipStreamSynchronize(stream_);
+  for (auto& e : timer_.pool) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  timer_.pool.clear();
+  if (ev_chunk_) hipEventDestroy(ev_chunk_);
+  if (ev_s0_) hipEventDestroy(ev_s0_);
+  if (ev_s1_) hipEventDestroy(ev_s1_);
+  ev_chunk_ = ev_s0_ = ev_s1_ = nullptr;
+  if (hcs_) hipHostFree(hcs_);
+  hcs_ = nullptr;
+  hipFree(arena_);
+  arena_ = nullptr;
+  if (own_stream_) {
+    if (stream_ == own_stream_) stream_ = nullptr;
+    hipStreamDestroy(own_stream_);
+    own_stream_ = nullptr;
+  }
+  have_ops_ = have_u_ = false;
+  for (auto& b : B_) b = LevelBufs{};
+}
+
+void Problem::set_stream(hipStream_t s) {
+  MGCG_HIP(hipSetDevice(device_));
+  if (stream_) MGCG_HIP(hipStreamSynchronize(stream_));
+  stream_ = s ? s : own_stream_;
+}
+
+void Problem::allocate() {
+  if (arena_) return;
+  MGCG_HIP(hipSetDevice(device_));
+  if (!own_stream_) MGCG_HIP(hipStreamCreateWithFlags(&own_stream_, hipStreamNonBlocking));
+  if (!stream_) stream_ = own_stream_;
+  bytes_ = layout(d_, lv_, nullptr, nullptr);
+  char* base = nullptr;
+  if (hipMalloc(&base, bytes_) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(MGCG_ENOMEM, "device allocation of " + std::to_string(bytes_) + " bytes failed");
+  }
+  arena_ = base;
+  layout(d_, lv_, base, this);
+  MGCG_HIP(hipMemsetAsync(arena_, 0, bytes_, stream_));
+  MGCG_HIP(hipHostMalloc((void**)&hcs_, 4 * sizeof(CgScalars), hipHostMallocDefault));
+  MGCG_HIP(hipEventCreateWithFlags(&ev_chunk_, hipEventDisableTiming));
+  MGCG_HIP(hipEventCreate(&ev_s0_));
+  MGCG_HIP(hipEventCreate(&ev_s1_));
+  // static data
+  const long nd0 = lv_[0].L.ndof();
+  for (size_t l = 0; l < lv_.size(); ++l)
+    MGCG_HIP(hipMemcpyAsync(B_[l].mask, &hmask_[hmask_off_[l]], lv_[l].L.nn(), hipMemcpyHostToDevice,
+                            stream_));
+  MGCG_HIP(hipMemcpyAsync(f_, hf_.data(), hf_.size() * sizeof(double), hipMemcpyHostToDevice, stream_));
+  MGCG_HIP(hipMemcpyAsync(Ksub_, hKsub_.data(), hKsub_.size() * sizeof(double), hipMemcpyHostToDevice,
+                          stream_));
+  {
+    std::vector<double> k0 = sub_element_matrices(1, 1, d_.nu);
+    MGCG_HIP(hipMemcpyAsync(K0_, k0.data(), 576 * sizeof(double), hipMemcpyHostToDevice, stream_));
+    if (K032_) convert<double, float>(K0_, K032_, 576, stream_);
+  }
+  if (nc_ > 0) {
+    MGCG_HIP(hipMemcpyAsync(dfree_, hfree_.data(), hfree_.size() * sizeof(int), hipMemcpyHostToDevice,
+                            stream_));
+    MGCG_HIP(hipMemcpyAsync(ddofpos_, hdofpos_.data(), hdofpos_.size() * sizeof(int),
+                            hipMemcpyHostToDevice, stream_));
+  }
+  (void)nd0;
+  MGCG_HIP(hipStreamSynchronize(stream_));
+}
+
+void Problem::sync() { MGCG_HIP(hipStreamSynchronize(stream_)); }
+
+// ------------------------------------------------------------------ operators
+FineOp Problem::fine_op() const {
+  FineOp A{};
+  A.kind = lv_[0].kind;
+  const Lat L = lv_[0].L;
+  A.mf = OpMF<double>{L, E_, kv64_, B_[0].mask};
+  A.st = OpST<double>{L, vbytes_ == 8 ? (const double*)B_[0].coefV : B_[0].coef64};
+  A.eq2 = OpEQ2<double>{L, Keff_, B_[0].mask};
+  return A;
+}
+
+template <typename T>
+VOps<T> Problem::vops(int l) const {
+  VOps<T> v{};
+  v.kind = lv_[l].kind;
+  v.L = lv_[l].L;
+  v.mask = B_[l].mask;
+  v.invD = (const T*)B_[l].invD;
+  if constexpr (sizeof(T) == 8) {
+    v.mf = OpMF<T>{v.L, E_, kv64_, B_[l].mask};
+    v.eq2 = OpEQ2<T>{v.L, Keff_, B_[l].mask};
+  } else {
+    v.mf = OpMF<T>{v.L, E32_, kv32_, B_[l].mask};
+    v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask};
+  }
+  v.st = OpST<T>{v.L, (const T*)B_[l].coefV};
+  return v;
+}
+
+void Problem::check_bad(int which) {
+  int hb[4] = {0, 0, 0, 0};
+  MGCG_HIP(hipMemcpyAsync(hb, bad_, sizeof(hb), hipMemcpyDeviceToHost, stream_));
+  sync();
+  (void)which;
+  if (hb[0] & 1) {
+    have_ops_ = false;
+    throw Error(MGCG_EINVAL, "density outside [0, 1] or NaN");
+  }
+  if (hb[0] & 2) {
+    have_ops_ = false;
+    throw Error(MGCG_EBREAKDOWN, "coarsest-level matrix is not positive definite");
+  }
+}
+
+void Problem::set_densities(const double* rho, int mem) {
+  set_densities_async(rho, mem);
+  MGCG_HIP(hipEventSynchronize(ev_s1_));
+  float ms = 0.f;
+  MGCG_HIP(hipEventElapsedTime(&ms, ev_s0_, ev_s1_));
+  setup_ms_ = ms;
+  pending_check_ = false;
+  check_bad(0);
+}
+
+void Problem::set_densities_async(const double* rho, int mem) {
+  allocate();
+  MGCG_HIP(hipSetDevice(device_));
+  const long n = nrho();
+  MGCG_HIP(hipEventRecord(ev_s0_, stream_));
+  MGCG_HIP(hipMemcpyAsync(rho_, rho, n * sizeof(double),
+                          mem == MGCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          stream_));
+  fill<int>(bad_, 0, 4, stream_);
+  if (vbytes_ == 8)
+    do_set_densities<double>();
+  else
+    do_set_densities<float>();
+  MGCG_HIP(hipEventRecord(ev_s1_, stream_));
+  have_ops_ = true;
+  pending_check_ = true;
+}
+
+template <typename T>
+void Problem::do_set_densities() {
+  hipStream_t st = stream_;
+  const int L = (int)lv_.size();
+  const Lat L0 = lv_[0].L;
+  const bool mixed = sizeof(T) == 4;
+  setup_simp(rho_, E_, E32_, nrho(), d_.E0, d_.Emin, d_.penal, bad_, st);
+  switch (lv_[0].kind) {
+    case OP_MF_Q1:
+      setup_diag_mf<T>(L0, E_, K0_, B_[0].mask, (T*)B_[0].invD, B_[0].diag64, d_.omega, kTheta, st);
+      break;
+    case OP_ST27:
+      setup_effective(1, d_.nsub, d_.nelx, d_.nely, d_.nelz, E_, Ksub_, B_[0].mask, L0, Keff_, st);
+      if (mixed) {
+        // FP64 copy for the outer CG, FP32 one for the V-cycle
+        setup_stencil<double>(L0, Keff_, B_[0].mask, B_[0].coef64, (double*)tmp64_, B_[0].diag64, d_.omega, kTheta, st);
+        setup_stencil<float>(L0, Keff_, B_[0].mask, (float*)B_[0].coefV, (float*)B_[0].invD, nullptr, d_.omega, kTheta, st);
+      } else {
+        setup_stencil<double>(L0, Keff_, B_[0].mask, (double*)B_[0].coefV, (double*)B_[0].invD,
+                              B_[0].diag64, d_.omega, kTheta, st);
+      }
+      break;
+    default:
+      setup_effective(2, d_.nsub, d_.nelx, d_.nely, d_.nelz, E_, Ksub_, B_[0].mask, L0, Keff_, st);
+      setup_diag_eq2<T>(L0, Keff_, B_[0].mask, (T*)B_[0].invD, B_[0].diag64, d_.omega, kTheta, st);
+      if (mixed) convert<double, float>(Keff_, Keff32_, (long)d_.nelx * d_.nely * d_.nelz * 6561, st);
+      break;
+  }
+  for (int l = 1; l < L; ++l) {
+    const int src = (l == 1) ? lv_[0].kind : OP_ST27;
+    const double* Kc = (l == 1) ? Keff_ : B_[l - 1].KE;
+    setup_galerkin(src, lv_[l - 1].L, E_, K0_, Kc, B_[l - 1].mask, lv_[l].ncx, lv_[l].ncy, lv_[l].ncz,
+                   B_[l].KE, st);
+    setup_stencil<T>(lv_[l].L, B_[l].KE, B_[l].mask, (T*)B_[l].coefV, (T*)B_[l].invD, B_[l].diag64,
+                     d_.omega, kTheta, st);
+  }
+  // coarsest: dense Cholesky and explicit inverse
+  const int lc = L - 1;
+  const int src = (lc == 0) ? lv_[0].kind : OP_ST27;
+  const double* KE = (lc == 0) ? Keff_ : B_[lc].KE;
+  setup_dense(src, lv_[lc].L, E_, K0_, KE, dfree_, ddofpos_, nc_, Ad_, st);
+  setup_cholesky_inverse(Ad_, Linv_, Ainv_, nc_, bad_, st);
+}
+
+// ------------------------------------------------------------------ V-cycle
+template <typename T>
+void Problem::vcycle(const double* r_in, int gate) {
+  hipStream_t st = stream_;
+  const CgScalars* cs = gate ? cs_ : nullptr;
+  const int L = (int)lv_.size();
+  const int R = d_.nrhs;
+  const T omega = T(1);  // the Jacobi weights are folded into wD
+  const T* b0;
+  if constexpr (sizeof(T) == 8) {
+    b0 = (const T*)r_in;
+  } else {
+    convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
+    b0 = (const T*)B_[0].b;
+  }
+  std::vector<T*> cur(L), oth(L);
+  std::vector<const T*> bl(L);
+  bl[0] = b0;
+  for (int l = 0; l < L; ++l) {
+    cur[l] = (T*)B_[l].xa;
+    oth[l] = (T*)B_[l].xb;
+    if (l > 0) bl[l] = (const T*)B_[l].b;
+  }
+  for (int l = 0; l < L - 1; ++l) {
+    const VOps<T> v = vops<T>(l);
+    T* rl = (T*)B_[l].r;
+    if (d_.pre == 1) {
+      if (l == 0) timed_begin(1);
+      v_presmooth_residual<T>(v, bl[l], cur[l], rl, omega, R, cs, st);
+      if (l == 0) timed_end(1);
+    } else {
+      v_smooth0<T>(bl[l], (const T*)B_[l].invD, cur[l], omega, lv_[l].L.ndof(), R, cs, st);
+      for (int s = 1; s < d_.pre; ++s) {
+        v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
+        std::swap(cur[l], oth[l]);
+      }
+      v_residual<T>(v, bl[l], cur[l], rl, R, cs, st);
+    }
+    v_restrict<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, rl, (T*)B_[l + 1].b, R, cs, st);
+  }
+  v_coarse_solve<T>(Ainv_, dfree_, nc_, lv_[L - 1].L.ndof(), bl[L - 1], cur[L - 1], R, cs, st);
+  for (int l = L - 2; l >= 0; --l) {
+    const VOps<T> v = vops<T>(l);
+    v_prolong<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, cur[l + 1], cur[l], R, true, cs, st);
+    for (int s = 0; s < d_.post; ++s) {
+      if (l == 0) timed_begin(2);
+      v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
+      if (l == 0) timed_end(2);
+      std::swap(cur[l], oth[l]);
+    }
+  }
+  zbuf_ = cur[0];
+}
+
+// ------------------------------------------------------------------ PCG
+void Problem::iteration() {
+  hipStream_t st = stream_;
+  const FineOp A = fine_op();
+  const long nd = lv_[0].L.ndof();
+  const int R = d_.nrhs;
+  timed_begin(0);
+  cg_apply_alpha(A, p_, q_, R, cs_, red_, st);
+  timed_end(0);
+  cg_update_xr(p_, q_, x_, r_, nd, R, cs_, red_, st);
+  cg_true_residual(A, f_, x_, r_, R, cs_, red_, st);
+  if (vbytes_ == 8) {
+    vcycle<double>(r_, 1);
+    cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<double>((const double*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
+  } else {
+    vcycle<float>(r_, 1);
+    cg_beta<float>(r_, rold_, (const float*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<float>((const float*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
+  }
+  ++iter_launched_;
+}
+
+void Problem::solve_begin(double rtol, int maxit, bool warm) {
+  if (!have_ops_) throw Error(MGCG_ESTATE, "set_densities must precede solve");
+  if (!(rtol > 0.0) || maxit < 1) throw Error(MGCG_EINVAL, "need rtol > 0 and maxit >= 1");
+  MGCG_HIP(hipSetDevice(device_));
+  hipStream_t st = stream_;
+  const FineOp A = fine_op();
+  const long nd = lv_[0].L.ndof();
+  const int R = d_.nrhs;
+  rtol_ = rtol;
+  maxit_ = maxit;
+  t0_ = std::chrono::steady_clock::now();
+  if (!warm || !have_u_) fill<double>(x_, 0.0, R * nd, st);
+  cg_reset(cs_, R, rtol * rtol, maxit, replace_every_, vbytes_ == 4 ? 1 : 0, st);
+  cg_init_residual(A, f_, x_, r_, R, cs_, red_, st);
+  fill<double>(p_, 0.0, R * nd, st);
+  fill<double>(rold_, 0.0, R * nd, st);
+  iter_launched_ = -1;
+  timer_used_base_ = timer_.used;
+  if (vbytes_ == 8) {
+    vcycle<double>(r_, 1);
+    cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<double>((const double*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
+  } else {
+    vcycle<float>(r_, 1);
+    cg_beta<float>(r_, rold_, (const float*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<float>((const float*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
+  }
+  iter_launched_ = 0;
+  first_chunk_ = true;
+  // read the initial state
+  MGCG_HIP(hipMemcpyAsync(hcs_, cs_, 4 * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
+  MGCG_HIP(hipEventRecord(ev_chunk_, st));
+  chunk_pending_ = true;
+  prev_rr_valid_ = false;
+}
+
+void Problem::solve_chunk(int iters) {
+  hipStream_t st = stream_;
+  for (int i = 0; i < iters; ++i) iteration();
+  MGCG_HIP(hipMemcpyAsync(hcs_, cs_, 4 * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
+  MGCG_HIP(hipEventRecord(ev_chunk_, st));
+  chunk_pending_ = true;
+}
+
+bool Problem::solve_poll(bool block) {
+  if (chunk_pending_) {
+    if (block) {
+      MGCG_HIP(hipEventSynchronize(ev_chunk_));
+    } else {
+      hipError_t e = hipEventQuery(ev_chunk_);
+      if (e == hipErrorNotReady) return false;
+      if (e != hipSuccess) throw Error(MGCG_EDEVICE, hipGetErrorString(e));
+    }
+    chunk_pending_ = false;
+    // convergence-rate estimate for the next chunk length
+    double worst = 0.0;
+    int itmax = 0;
+    bool any = false;
+    for (int r = 0; r < d_.nrhs; ++r) {
+      const CgScalars& c = hcs_[r];
+      itmax = std::max(itmax, c.iters);
+      if (c.state == CG_ACTIVE || c.state == CG_CHECK) {
+        any = true;
+        const double ratio = (c.tol2 > 0 && c.rr > 0) ? c.rr / c.tol2 : 1.0;
+        worst = std::max(worst, ratio);
+      }
+    }
+    if (prev_rr_valid_ && any && itmax > prev_iters_ && worst > 0 && prev_worst_ > 0) {
+      const double f = std::log(worst / prev_worst_) / (itmax - prev_iters_);
+      if (f < -1e-3) rate_log_ = f;  // log of the per-iteration factor of rr
+    }
+    prev_worst_ = worst;
+    prev_iters_ = itmax;
+    prev_rr_valid_ = any;
+    active_ = any;
+  }
+  return !active_;
+}
+
+int Problem::suggest_chunk() const {
+  int n = 4;
+  if (prev_rr_valid_ && rate_log_ < 0 && prev_worst_ > 1.0)
+    n = (int)std::ceil(std::log(prev_worst_) / -rate_log_);
+  int left = maxit_ - prev_iters_;
+  n = std::max(1, std::min(n, 32));
+  return std::max(1, std::min(n, std::max(left, 1)));
+}
+
+int Problem::solve_finish(mgcg_info* info) {
+  const auto t1 = std::chrono::steady_clock::now();
+  int status = MGCG_OK;
+  if (pending_check_) {
+    pending_check_ = false;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev_s0_, ev_s1_) == hipSuccess) setup_ms_ = ms;
+    int hb[4] = {0, 0, 0, 0};
+    MGCG_HIP(hipMemcpyAsync(hb, bad_, sizeof(hb), hipMemcpyDeviceToHost, stream_));
+    sync();
+    if (hb[0] & 1) status = MGCG_EINVAL;
+    else if (hb[0] & 2) status = MGCG_EBREAKDOWN;
+  }
+  int itmax = 0;
+  for (int r = 0; r < d_.nrhs; ++r) {
+    const CgScalars& c = hcs_[r];
+    itmax = std::max(itmax, c.iters);
+    if (c.state == CG_BREAKDOWN && status >= 0) status = MGCG_EBREAKDOWN;
+    else if (c.state == CG_MAXIT && status == MGCG_OK) status = MGCG_ENOTCONV;
+  }
+  harvest_timing(itmax);
+  have_u_ = true;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    for (int r = 0; r < d_.nrhs && r < 4; ++r) {
+      const CgScalars& c = hcs_[r];
+      info->iters[r] = c.iters;
+      info->rel_res[r] = c.ff > 0 ? std::sqrt(std::max(c.rr, 0.0) / c.ff) : 0.0;
+      info->replacements += c.replacements;
+    }
+    info->t_setup_ms = setup_ms_;
+    info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0_).count();
+  }
+  return status;
+}
+
+int Problem::solve(double rtol, int maxit, bool warm, mgcg_info* info) {
+  solve_begin(rtol, maxit, warm);
+  solve_poll(true);
+  while (active_) {
+    solve_chunk(suggest_chunk());
+    solve_poll(true);
+  }
+  return solve_finish(info);
+}
+
+// ------------------------------------------------------------------ outputs
+void Problem::get_u(double* u, int mem) {
+  if (!arena_) throw Error(MGCG_ESTATE, "no solution");
+  const size_t n = (size_t)d_.nrhs * lv_[0].L.ndof();
+  MGCG_HIP(hipMemcpyAsync(u, x_, n * sizeof(double),
+                          mem == MGCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          stream_));
+  sync();
+}
+
+void Problem::set_u(const double* u, int mem) {
+  allocate();
+  const long nd = lv_[0].L.ndof();
+  const size_t n = (size_t)d_.nrhs * nd;
+  MGCG_HIP(hipMemcpyAsync(x_, u, n * sizeof(double),
+                          mem == MGCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          stream_));
+  // zero the fixed DOFs: identity rows of the system with zero load there
+  std::vector<double> h(n);
+  MGCG_HIP(hipMemcpyAsync(h.data(), x_, n * sizeof(double), hipMemcpyDeviceToHost, stream_));
+  sync();
+  for (int r = 0; r < d_.nrhs; ++r)
+    for (long i = 0; i < nd; ++i)
+      if ((hmask_[i / 3] >> (i % 3)) & 1) h[(size_t)r * nd + i] = 0.0;
+  MGCG_HIP(hipMemcpyAsync(x_, h.data(), n * sizeof(double), hipMemcpyHostToDevice, stream_));
+  sync();
+  have_u_ = true;
+}
+
+void Problem::compliance_sensitivity(double* c, double* dc, int mem) {
+  if (!have_u_ || !have_ops_) throw Error(MGCG_ESTATE, "solve first");
+  hipStream_t st = stream_;
+  const long nd = lv_[0].L.ndof();
+  const int R = d_.nrhs;
+  comp_dot(f_, x_, nd, R, compout_, red_, st);
+  if (dc) {
+    double* out = mem == MGCG_MEM_DEVICE ? dc : dcbuf_;
+    sens_kernel(d_.order, d_.nsub, d_.nelx, d_.nely, d_.nelz, lv_[0].L, rho_, x_, nd, R,
+                lv_[0].kind == OP_MF_Q1 ? K0_ : Ksub_, 0.0, d_.E0 - d_.Emin, d_.penal, out, st);
+    if (mem != MGCG_MEM_DEVICE)
+      MGCG_HIP(hipMemcpyAsync(dc, dcbuf_, nrho() * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  double h[16];
+  MGCG_HIP(hipMemcpyAsync(h, compout_, R * sizeof(double), hipMemcpyDeviceToHost, st));
+  sync();
+  double s = 0.0;
+  for (int r = 0; r < R; ++r) {
+    c[r] = h[r];
+    s += h[r];
+  }
+  c[R] = s;
+}
+
+// ------------------------------------------------------------------ inspection
+void Problem::level_dims(int level, int32_t* dims, int64_t* ndof) const {
+  if (level < 0 || level >= (int)lv_.size()) throw Error(MGCG_EINVAL, "level out of range");
+  const Lat L = lv_[level].L;
+  if (dims) {
+    dims[0] = L.nx;
+    dims[1] = L.ny;
+    dims[2] = L.nz;
+  }
+  if (ndof) *ndof = L.ndof();
+}
+
+namespace {
+struct DevTmp {
+  std::vector<void*> ptrs;
+  ~DevTmp() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  template <class T>
+  T* get(size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+      throw Error(MGCG_ENOMEM, "inspection scratch allocation failed");
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+};
+}  // namespace
+
+static void to_dev(const double* src, double* dst, size_t n, int mem, hipStream_t st) {
+  MGCG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          mem == MGCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+}
+static void from_dev(const double* src, double* dst, size_t n, int mem, hipStream_t st) {
+  MGCG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double),
+                          mem == MGCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+}
+
+template <typename T>
+void Problem::do_apply_v(int level, const double* x, double* y) {
+  DevTmp tmp;
+  const long nd = lv_[level].L.ndof();
+  const int R = d_.nrhs;
+  const VOps<T> v = vops<T>(level);
+  const T* xt;
+  T* yt;
+  if constexpr (sizeof(T) == 8) {
+    xt = x;
+    yt = y;
+  } else {
+    T* a = tmp.get<T>(R * nd);
+    T* b = tmp.get<T>(R * nd);
+    convert<double, float>(x, a, R * nd, stream_);
+    xt = a;
+    yt = b;
+  }
+  switch (v.kind) {
+    case OP_MF_Q1: launch_apply_mf<T>(v.mf, xt, yt, R, stream_); break;
+    case OP_ST27: launch_apply_st<T>(v.st, xt, yt, R, stream_); break;
+    default: launch_apply_eq2<T>(v.eq2, xt, yt, R, stream_); break;
+  }
+  if constexpr (sizeof(T) == 4) convert<float, double>(yt, y, R * nd, stream_);
+  sync();
+}
+
+void Problem::apply(int level, int prec, const double* x, double* y, int mem) {
+  if (!have_ops_) throw Error(MGCG_ESTATE, "set_densities first");
+  if (level < 0 || level >= (int)lv_.size()) throw Error(MGCG_EINVAL, "level out of range");
+  DevTmp tmp;
+  const long nd = lv_[level].L.ndof();
+  const size_t n = (size_t)d_.nrhs * nd;
+  double* xraw = tmp.get<double>(n);
+  double* xd = tmp.get<double>(n);
+  double* yd = tmp.get<double>(n);
+  to_dev(x, xraw, n, mem, stream_);
+  // A = Z K Z + (I - Z): the kernels take inputs that vanish on fixed DOFs
+  mask_copy(xraw, xd, B_[level].mask, lv_[level].L.nn(), d_.nrhs, stream_);
+  if (level == 0 && (prec == MGCG_FP64 || vbytes_ == 8)) {
+    const FineOp A = fine_op();
+    switch (A.kind) {
+      case OP_MF_Q1: launch_apply_mf<double>(A.mf, xd, yd, d_.nrhs, stream_); break;
+      case OP_ST27: launch_apply_st<double>(A.st, xd, yd, d_.nrhs, stream_); break;
+      default: launch_apply_eq2<double>(A.eq2, xd, yd, d_.nrhs, stream_); break;
+    }
+  } else if (vbytes_ == 8) {
+    do_apply_v<double>(level, xd, yd);
+  } else {
+    do_apply_v<float>(level, xd, yd);
+  }
+  identity_rows(xraw, yd, B_[level].mask, lv_[level].L.nn(), d_.nrhs, stream_);
+  from_dev(yd, y, n, mem, stream_);
+  sync();
+}
+
+void Problem::diag(int level, double* d, int mem) {
+  if (!have_ops_) throw Error(MGCG_ESTATE, "set_densities first");
+  if (level < 0 || level >= (int)lv_.size()) throw Error(MGCG_EINVAL, "level out of range");
+  from_dev(B_[level].diag64, d, lv_[level].L.ndof(), mem, stream_);
+  sync();
+}
+
+void Problem::restrict_(int level, const double* f, double* c, int mem) {
+  if (!arena_) allocate();
+  if (level < 0 || level + 1 >= (int)lv_.size()) throw Error(MGCG_EINVAL, "level out of range");
+  DevTmp tmp;
+  const long nf = (long)d_.nrhs * lv_[level].L.ndof(), ncd = (long)d_.nrhs * lv_[level + 1].L.ndof();
+  double* fraw = tmp.get<double>(nf);
+  double* fd = tmp.get<double>(nf);
+  double* cd = tmp.get<double>(ncd);
+  to_dev(f, fraw, nf, mem, stream_);
+  mask_copy(fraw, fd, B_[level].mask, lv_[level].L.nn(), d_.nrhs, stream_);
+  v_restrict<double>(lv_[level].L, lv_[level + 1].L, B_[level].mask, B_[level + 1].mask, fd, cd,
+                     d_.nrhs, nullptr, stream_);
+  from_dev(cd, c, ncd, mem, stream_);
+  sync();
+}
+
+void Problem::prolong(int level, const double* c, double* f, int mem) {
+  if (!arena_) allocate();
+  if (level < 0 || level + 1 >= (int)lv_.size()) throw Error(MGCG_EINVAL, "level out of range");
+  DevTmp tmp;
+  const long nf = (long)d_.nrhs * lv_[level].L.ndof(), ncd = (long)d_.nrhs * lv_[level + 1].L.ndof();
+  double* fd = tmp.get<double>(nf);
+  double* craw = tmp.get<double>(ncd);
+  double* cd = tmp.get<double>(ncd);
+  to_dev(c, craw, ncd, mem, stream_);
+  mask_copy(craw, cd, B_[level + 1].mask, lv_[level + 1].L.nn(), d_.nrhs, stream_);
+  v_prolong<double>(lv_[level].L, lv_[level + 1].L, B_[level].mask, B_[level + 1].mask, cd, fd,
+                    d_.nrhs, false, nullptr, stream_);
+  from_dev(fd, f, nf, mem, stream_);
+  sync();
+}
+
+void Problem::precondition(const double* r, double* z, int mem) {
+  if (!have_ops_) throw Error(MGCG_ESTATE, "set_densities first");
+  const long n = (long)d_.nrhs * lv_[0].L.ndof();
+  to_dev(r, tmp64_, n, mem, stream_);
+  if (vbytes_ == 8) {
+    vcycle<double>(tmp64_, 0);
+    from_dev((const double*)zbuf_, z, n, mem, stream_);
+  } else {
+    vcycle<float>(tmp64_, 0);
+    DevTmp tmp;
+    double* zd = tmp.get<double>(n);
+    convert<float, double>((const float*)zbuf_, zd, n, stream_);
+    from_dev(zd, z, n, mem, stream_);
+    sync();
+  }
+  sync();
+}
+
+void Problem::coarse_solve(const double* b, double* x, int mem) {
+  if (!have_ops_) throw Error(MGCG_ESTATE, "set_densities first");
+  DevTmp tmp;
+  const int lc = (int)lv_.size() - 1;
+  const long n = (long)d_.nrhs * lv_[lc].L.ndof();
+  double* bd = tmp.get<double>(n);
+  double* xd = tmp.get<double>(n);
+  to_dev(b, bd, n, mem, stream_);
+  fill<double>(xd, 0.0, n, stream_);
+  v_coarse_solve<double>(Ainv_, dfree_, nc_, lv_[lc].L.ndof(), bd, xd, d_.nrhs, nullptr, stream_);
+  from_dev(xd, x, n, mem, stream_);
+  sync();
+}
+
+// ------------------------------------------------------------------ timing
+void Problem::set_timing(bool on, int kernel) {
+  timer_.enabled = on;
+  timer_.kernel = kernel;
+  timer_.total_ms = 0.0;
+  timer_.launches = 0;
+  timer_.recs.clear();
+}
+
+void Problem::timed_begin(int id) {
+  if (!timer_.enabled || id != timer_.kernel) return;
+  if (timer_.used >= timer_.pool.size()) {
+    hipEvent_t a, b;
+    MGCG_HIP(hipEventCreate(&a));
+    MGCG_HIP(hipEventCreate(&b));
+    timer_.pool.push_back({a, b});
+  }
+  MGCG_HIP(hipEventRecord(timer_.pool[timer_.used].first, stream_));
+}
+
+void Problem::timed_end(int id) {
+  if (!timer_.enabled || id != timer_.kernel) return;
+  MGCG_HIP(hipEventRecord(timer_.pool[timer_.used].second, stream_));
+  timer_.recs.push_back(iter_launched_);
+  ++timer_.used;
+}
+
+void Problem::harvest_timing(int itmax) {
+  if (!timer_.enabled) {
+    timer_.used = 0;
+    return;
+  }
+  // launches of iterations after every load case converged were no-ops
+  for (size_t i = timer_used_base_; i < timer_.used; ++i) {
+    const int it = timer_.recs[i];
+    // the CG apply of iteration i works iff some load case needs i+1 iterations;
+    // the V-cycle of iteration i (i = -1: the initial one) iff one needs i+2
+    if (timer_.kernel == 0 && it >= itmax) continue;
+    if (timer_.kernel != 0 && it >= itmax - 1) continue;
+    float ms = 0.f;
+    MGCG_HIP(hipEventElapsedTime(&ms, timer_.pool[i].first, timer_.pool[i].second));
+    timer_.total_ms += ms;
+    timer_.launches += 1;
+  }
+  timer_.used = 0;
+  timer_.recs.clear();
+}
+
+void Problem::get_timing(int kernel, double* ms, long long* launches) {
+  (void)kernel;
+  if (ms) *ms = timer_.total_ms;
+  if (launches) *launches = timer_.launches;
+}
+
+void Problem::copy(const void* src, void* dst, size_t bytes) {
+  allocate();
+  copy_bytes(src, dst, bytes, stream_);
+  sync();
+}
+
+}  // namespace mgcg

@@ -1,0 +1,59 @@
+// Continuous-batching server over one GPU.
+#pragma once
+
+#include <chrono>
+#include <deque>
+#include <map>
+#include <set>
+#include <vector>
+
+#include "problem.h"
+
+struct mgcg_problem;
+
+namespace mgcg {
+
+Problem* problem_impl(mgcg_problem* p);
+
+// First-come-first-served admission: a request that does not fit (slots or
+// bytes) blocks the ones behind it.  Returns the number admitted.
+int admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
+                   int nqueue, uint8_t* admit);
+
+class Server {
+ public:
+  Server(int device, size_t budget, int max_slots);
+  ~Server();
+  uint64_t submit(Problem* p, const double* rho, double rtol, int maxit, int warm);
+  void step(int* active, int* queued);
+  int poll(uint64_t ticket, mgcg_info* info, double* latency_ms);
+  void release(Problem* p);
+  size_t resident_bytes() const { return in_use_; }
+
+ private:
+  struct Req {
+    uint64_t ticket;
+    Problem* p;
+    std::vector<double> rho;
+    double rtol;
+    int maxit;
+    int warm;
+    int status = 0;
+    mgcg_info info{};
+    std::chrono::steady_clock::time_point t_submit, t_done;
+  };
+  bool busy(Problem* p) const;
+  void admit();
+
+  int device_;
+  size_t budget_;
+  int max_slots_;
+  size_t in_use_ = 0;
+  uint64_t next_ = 1;
+  std::deque<Req*> queue_;
+  std::vector<Req*> running_;
+  std::map<uint64_t, Req*> done_;
+  std::map<Problem*, size_t> resident_;
+};
+
+}  // namespace mgcg

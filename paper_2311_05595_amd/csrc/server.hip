@@ -1,0 +1,231 @@
+// Continuous batching of MGCG solves: admission by device-memory budget and
+// free slots, one stream per resident problem so that solves of different
+// sizes overlap on the device, and a step that advances every running solve
+// by one chunk of PCG iterations without waiting on any of them.
+#include "server.h"
+
+#include <algorithm>
+
+namespace mgcg {
+
+int admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
+                   int nqueue, uint8_t* admit) {
+  int n = 0;
+  for (int i = 0; i < nqueue; ++i) admit[i] = 0;
+  for (int i = 0; i < nqueue; ++i) {
+    if (free_slots <= 0) break;
+    if (queue_bytes[i] > budget || in_use + queue_bytes[i] > budget) break;
+    admit[i] = 1;
+    in_use += queue_bytes[i];
+    --free_slots;
+    ++n;
+  }
+  return n;
+}
+
+Server::Server(int device, size_t budget, int max_slots)
+    : device_(device), budget_(budget), max_slots_(max_slots) {
+  if (max_slots < 1) throw Error(MGCG_EINVAL, "max_slots must be >= 1");
+}
+
+Server::~Server() {
+  for (Req* r : queue_) delete r;
+  for (Req* r : running_) {
+    try {
+      while (!r->p->solve_poll(true)) {
+      }
+    } catch (...) {
+    }
+    delete r;
+  }
+  for (auto& kv : done_) delete kv.second;
+}
+
+bool Server::busy(Problem* p) const {
+  for (Req* r : running_)
+    if (r->p == p) return true;
+  return false;
+}
+
+uint64_t Server::submit(Problem* p, const double* rho, double rtol, int maxit, int warm) {
+  if (p->device() != device_) throw Error(MGCG_EINVAL, "problem lives on another device");
+  const size_t need = Problem::device_bytes(p->desc());
+  if (need > budget_) throw Error(MGCG_EBUDGET, "problem exceeds the server's memory budget");
+  Req* r = new Req;
+  r->ticket = next_++;
+  r->p = p;
+  r->rho.assign(rho, rho + p->nrho());
+  r->rtol = rtol;
+  r->maxit = maxit;
+  r->warm = warm;
+  r->t_submit = std::chrono::steady_clock::now();
+  queue_.push_back(r);
+  return r->ticket;
+}
+
+void Server::admit() {
+  std::vector<size_t> bytes;
+  for (Req* r : queue_) {
+    if (busy(r->p)) {
+      bytes.push_back(budget_ + 1);  // cannot start while its previous solve runs
+      continue;
+    }
+    bytes.push_back(resident_.count(r->p) ? 0 : Problem::device_bytes(r->p->desc()));
+  }
+  // a problem queued twice in a row cannot both start now
+  std::vector<uint8_t> adm(queue_.size(), 0);
+  const int free_slots = max_slots_ - (int)running_.size();
+  const int n = admission_plan(budget_, in_use_, free_slots, bytes.data(), (int)bytes.size(), adm.data());
+  for (int i = 0; i < n; ++i) {
+    Req* r = queue_.front();
+    queue_.pop_front();
+    if (busy(r->p)) {  // duplicate of a problem admitted in this same step
+      queue_.push_front(r);
+      break;
+    }
+    if (!resident_.count(r->p)) {
+      r->p->allocate();
+      resident_[r->p] = r->p->bytes();
+      in_use_ += r->p->bytes();
+    }
+    try {
+      r->p->set_densities_async(r->rho.data(), MGCG_MEM_HOST);
+      r->p->solve_begin(r->rtol, r->maxit, r->warm != 0);
+      running_.push_back(r);
+    } catch (const Error& e) {
+      r->status = e.code;
+      r->t_done = std::chrono::steady_clock::now();
+      done_[r->ticket] = r;
+    }
+  }
+}
+
+void Server::step(int* active, int* queued) {
+  admit();
+  for (size_t i = 0; i < running_.size();) {
+    Req* r = running_[i];
+    bool finished = false;
+    try {
+      if (r->p->solve_poll(false)) {
+        r->status = r->p->solve_finish(&r->info);
+        finished = true;
+      } else if (!r->p->solve_pending()) {
+        r->p->solve_chunk(r->p->suggest_chunk());
+      }
+    } catch (const Error& e) {
+      r->status = e.code;
+      finished = true;
+    }
+    if (finished) {
+      r->t_done = std::chrono::steady_clock::now();
+      r->info.status = r->status;
+      done_[r->ticket] = r;
+      running_.erase(running_.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  admit();
+  if (active) *active = (int)running_.size();
+  if (queued) *queued = (int)queue_.size();
+}
+
+int Server::poll(uint64_t ticket, mgcg_info* info, double* latency_ms) {
+  auto it = done_.find(ticket);
+  if (it == done_.end()) return MGCG_EAGAIN;
+  Req* r = it->second;
+  if (info) *info = r->info;
+  if (latency_ms)
+    *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  const int st = r->status;
+  done_.erase(it);
+  delete r;
+  return st;
+}
+
+void Server::release(Problem* p) {
+  for (Req* r : queue_)
+    if (r->p == p) throw Error(MGCG_ESTATE, "problem is queued");
+  if (busy(p)) throw Error(MGCG_ESTATE, "problem is running");
+  auto it = resident_.find(p);
+  if (it == resident_.end()) return;
+  in_use_ -= it->second;
+  resident_.erase(it);
+  p->release();
+}
+
+}  // namespace mgcg
+
+struct mgcg_server {
+  mgcg::Server* impl;
+};
+
+using mgcg::Error;
+
+#define SGUARD(body)                    \
+  try {                                 \
+    mgcg::set_error("");                \
+    body                                \
+  } catch (const Error& e) {            \
+    mgcg::set_error(e.what());          \
+    return e.code;                      \
+  } catch (const std::exception& e) {   \
+    mgcg::set_error(e.what());          \
+    return MGCG_EINVAL;                 \
+  }
+
+extern "C" {
+
+int mgcg_server_create(int device, size_t hbm_budget, int max_slots, mgcg_server** out) {
+  if (!out) return MGCG_EINVAL;
+  SGUARD({
+    *out = new mgcg_server{new mgcg::Server(device, hbm_budget, max_slots)};
+    return MGCG_OK;
+  })
+}
+
+int mgcg_server_destroy(mgcg_server* s) {
+  if (!s) return MGCG_OK;
+  SGUARD({
+    delete s->impl;
+    delete s;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_server_submit(mgcg_server* s, mgcg_problem* p, const double* rho, double rtol, int maxit,
+                       int warm_start, uint64_t* ticket) {
+  if (!s || !p || !rho || !ticket) {
+    mgcg::set_error("null argument");
+    return MGCG_EINVAL;
+  }
+  SGUARD({
+    *ticket = s->impl->submit(mgcg::problem_impl(p), rho, rtol, maxit, warm_start);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_server_step(mgcg_server* s, int* active, int* queued) {
+  if (!s) return MGCG_EINVAL;
+  SGUARD({
+    s->impl->step(active, queued);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_server_poll(mgcg_server* s, uint64_t ticket, mgcg_info* info, double* latency_ms) {
+  if (!s) return MGCG_EINVAL;
+  SGUARD({ return s->impl->poll(ticket, info, latency_ms); })
+}
+
+int mgcg_server_release(mgcg_server* s, mgcg_problem* p) {
+  if (!s || !p) return MGCG_EINVAL;
+  SGUARD({
+    s->impl->release(mgcg::problem_impl(p));
+    return MGCG_OK;
+  })
+}
+
+size_t mgcg_server_resident_bytes(mgcg_server* s) { return s ? s->impl->resident_bytes() : 0; }
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol the header declares, validates descriptions, sizes problems and
+plans admissions."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2311_05595_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libmgcg.so not built (run __graft_entry__.build())")
+    return _abi.load(), _abi
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "mgcg.h")).read()
+    return sorted(set(re.findall(r"\b(mgcg_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib, abi = _lib()
+    names = _header_symbols()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(abi.EXPORTS), set(names) ^ set(abi.EXPORTS)
+
+
+def test_desc_validation_and_sizes():
+    from paper_2311_05595_amd import api
+    lib, abi = _lib()
+    good = api.make_desc((24, 12, 12), nlevels=3)
+    assert api.device_bytes(nel=(24, 12, 12), nlevels=3) > 0
+    # odd element counts cannot be coarsened
+    assert api.device_bytes(nel=(3, 2, 2), nlevels=2) == 0
+    assert api.device_bytes(nel=(24, 12, 12), nrhs=5) == 0
+    assert api.device_bytes(nel=(24, 12, 12), order=3) == 0
+    assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=1) == 0
+    # bytes grow with precision, nrhs and nsub
+    b64 = api.device_bytes(nel=(32, 16, 16), nlevels=3)
+    b2 = api.device_bytes(nel=(32, 16, 16), nlevels=3, nrhs=2)
+    assert b2 > b64
+    assert api.device_bytes(nel=(32, 16, 16), nlevels=3, nsub=2) > b64
+    del good
+
+
+def test_problem_create_rejects_bad_input():
+    from paper_2311_05595_amd import api
+    from paper_2311_05595_amd._abi import MGCGError
+    _lib()
+    mask, f = W.make_problem("cantilever", 4, 2, 2, 1, 1)
+    p = api.Problem((4, 2, 2), mask, f, nlevels=2)
+    p.close()
+    with pytest.raises(ValueError):
+        api.Problem((4, 2, 2), mask[:-1], f, nlevels=2)
+    bad = f.copy()
+    bad[0, 5] = np.nan
+    with pytest.raises(MGCGError):
+        api.Problem((4, 2, 2), mask, bad, nlevels=2)
+    with pytest.raises(MGCGError):
+        api.Problem((4, 2, 2), mask, f, nlevels=2, omega=2.5)
+
+
+def test_admission_plan_is_fcfs_and_respects_budget():
+    from paper_2311_05595_amd import api
+    _lib()
+    adm = api.admission_plan(100, 10, 3, [30, 50, 20, 5])
+    assert adm.tolist() == [True, True, False, False]  # 3rd would exceed, blocks the 4th
+    adm = api.admission_plan(100, 0, 2, [10, 10, 10])
+    assert adm.tolist() == [True, True, False]          # slots
+    adm = api.admission_plan(100, 0, 4, [])
+    assert adm.tolist() == []
+    adm = api.admission_plan(100, 0, 4, [0, 0, 0])      # resident problems cost nothing
+    assert adm.tolist() == [True, True, True]
+    # never over budget, whatever the queue
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        q = rng.integers(0, 60, size=rng.integers(0, 10))
+        used = int(rng.integers(0, 100))
+        adm = api.admission_plan(100, used, int(rng.integers(0, 5)), q)
+        assert used + int(q[adm].sum()) <= 100 or adm.sum() == 0
+        # admitted ones form a prefix
+        k = int(adm.sum())
+        assert adm[:k].all() and not adm[k:].any()

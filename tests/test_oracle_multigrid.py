@@ -58,26 +58,53 @@ def test_galerkin_masked_definition():
     assert np.linalg.eigvalsh(Ac[np.ix_(~mc, ~mc)]).min() > 0
 
 
-def test_vcycle_is_spd_with_convergent_smoother():
-    """With a convergent Jacobi smoother (omega < 2 / lambda_max(D^-1 A)) and
-    symmetric pre/post smoothing, the V-cycle is a symmetric positive
-    definite linear operator."""
-    nel = (4, 2, 2)
-    mask, f = W.make_problem("cantilever", *nel, 1, 1)
-    rho = W.uniform_field((2, 2, 4), 4, 0.5, 1.0)
-    K = assemble.stiffness(rho, nel, 1, 1, fem.sub_element_matrices(1, 1), **MAT)
-    H = multigrid.Hierarchy(assemble.level_operator(K, mask), mask,
-                            assemble.node_dims(nel, 1), 2)
+def _vcycle_matrix(H, mask, omega):
     n = H.A[0].shape[0]
     free = np.flatnonzero(mask == 0)
     Mm = np.zeros((n, n))
     for i in free:
         e = np.zeros(n)
         e[i] = 1.0
-        Mm[:, i] = multigrid.vcycle(H, e, omega=0.4)
-    Mf = Mm[np.ix_(free, free)]
+        Mm[:, i] = multigrid.vcycle(H, e, omega=omega)
+    return Mm[np.ix_(free, free)]
+
+
+def test_capped_smoother_converges_where_plain_omega_diverges():
+    """On an i.i.d. rough field lambda_max(D^-1 A) > 2/0.6: the plain sweep
+    with omega = 0.6 has spectral radius > 1, the capped one < 1, and the
+    V-cycle built on it is symmetric positive definite."""
+    nel = (4, 2, 2)
+    mask, f = W.make_problem("cantilever", *nel, 1, 1)
+    rho = W.uniform_field((2, 2, 4), 4, 0.001, 1.0)
+    K = assemble.stiffness(rho, nel, 1, 1, fem.sub_element_matrices(1, 1), **MAT)
+    H = multigrid.Hierarchy(assemble.level_operator(K, mask), mask,
+                            assemble.node_dims(nel, 1), 2)
+    free = np.flatnonzero(mask == 0)
+    A = H.A[0].toarray()[np.ix_(free, free)]
+    d = np.diag(A)
+    plain = np.eye(len(free)) - 0.6 * A / d[:, None]
+    assert np.abs(np.linalg.eigvals(plain)).max() > 1.0
+    wd = multigrid.smoother_weights(H, 0.6)[0][free]
+    capped = np.eye(len(free)) - wd[:, None] * A
+    assert np.abs(np.linalg.eigvals(capped)).max() < 1.0
+    # weights never exceed omega and keep it where the bound allows
+    w = wd * d
+    assert np.all(w <= 0.6 + 1e-15) and np.all(w > 0)
+    Mf = _vcycle_matrix(H, mask, 0.6)
     assert np.abs(Mf - Mf.T).max() < 1e-10 * np.abs(Mf).max()
     assert np.linalg.eigvalsh(0.5 * (Mf + Mf.T)).min() > 0
+
+
+def test_capped_weights_keep_omega_on_smooth_operators():
+    """Where sum_j |A_ij| <= theta A_ii / omega the weight is omega itself."""
+    A = sp.csr_matrix(np.array([[4.0, -1.0, 0.0], [-1.0, 4.0, -1.0], [0.0, -1.0, 4.0]]))
+
+    class _H:
+        pass
+    H = _H()
+    H.A, H.diag, H.mask, H.nlevels = [A], [A.diagonal()], [np.zeros(3, np.uint8)], 1
+    wd = multigrid.smoother_weights(H, 0.6)[0]
+    assert np.allclose(wd * 4.0, 0.6)
 
 
 @pytest.mark.parametrize("kind,order,nel,nlev", [("cantilever", 1, (8, 4, 4), 3),

@@ -53,7 +53,7 @@ struct CgScalars {
   double ff;      // ||f||^2
   double tol2;    // rtol^2 ||f||^2
   double rr;      // ||r||^2 (recurrence, or true after a check)
-  double rz;      // r^T z of the current iterate
+  double rzs[2];  // r^T z, double-buffered by iteration parity
   double alpha, beta;
   double pq;
   int iters;
@@ -64,7 +64,7 @@ struct CgScalars {
   int flexible;    // 1: Polak-Ribiere beta (non-symmetric FP32 preconditioner)
   double rr_best;  // smallest true ||r||^2 seen at a check
   int stall;       // consecutive checks without progress
-  int pad;
+  int bad;         // non-finite r^T z seen
 };
 
 }  // namespace mgcg

@@ -7,126 +7,92 @@ namespace mgcg {
 
 constexpr int BS = 256;  // threads per block of the node-parallel kernels
 
+// ---- buffer loads: one VGPR byte offset shared by many loads, a scalar
+// offset per load, and hardware bounds checks (an offset past the buffer
+// returns 0).  Word 3 of the resource: raw (untyped) 32-bit dword access.
+constexpr int kBufOOB = 0x7FFF0000;  // voffset marking "outside": loads return 0
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+// Three consecutive values (a node's x, y, z) at byte offset voff.
+template <typename T>
+__device__ __forceinline__ void bload3(__amdgpu_buffer_rsrc_t r, int voff, T v[3]) {
+  v[0] = bload<T>(r, voff, 0);
+  v[1] = bload<T>(r, voff + (int)sizeof(T), 0);
+  v[2] = bload<T>(r, voff + 2 * (int)sizeof(T), 0);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
 
-// Coherent (L1-bypassing) load of a value written by another workgroup of
-// the same kernel.
-__device__ __forceinline__ double load_coherent(const double* p) {
-  unsigned long long b =
-      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)b);
+// Deterministic block-wide sum of p[0..n) (fixed order for a fixed n);
+// every thread receives the result.  sh: BS/64 doubles of shared memory.
+__device__ __forceinline__ double block_sum(const double* __restrict__ p, int n, double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += BS) s += p[i];
+  s = wave_sum(s);
+  if (lane == 0) sh[wid] = s;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < BS / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
 }
 
-// Sum nv per-thread values over the whole grid in a fixed order; the last
-// block to finish calls fin(totals) from thread 0.  Every block of the grid
-// must call this exactly once (blockDim.x == BS).
-template <class Fin>
-__device__ void grid_reduce(const double* acc, int nv, RedBuf red, int slot, const Fin& fin) {
-  __shared__ double sh[MAX_RED_VALUES][BS / 64];
-  __shared__ double tot[MAX_RED_VALUES];
-  __shared__ int last;
+// Block sums of one / two per-thread values written to dst0 / dst1 by
+// thread 0 (one partial per block; no atomics).
+__device__ __forceinline__ void block_partial1(double a, double* dst) {
+  __shared__ double sh1[BS / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int v = 0; v < MAX_RED_VALUES; ++v) {
-    if (v < nv) {
-      double s = wave_sum(acc[v]);
-      if (lane == 0) sh[v][wid] = s;
-    }
-  }
+  a = wave_sum(a);
+  if (lane == 0) sh1[wid] = a;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int v = 0; v < nv; ++v) {
-      double s = 0.0;
+    double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < BS / 64; ++w) s += sh[v][w];
-      red.partials[(size_t)v * MAX_BLOCKS + blockIdx.x] = s;
-    }
-    __threadfence();
-    unsigned t = atomicAdd(&red.counter[slot], 1u);
-    last = (t == gridDim.x - 1);
+    for (int w = 0; w < BS / 64; ++w) t += sh1[w];
+    *dst = t;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int v = 0; v < nv; ++v) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += BS)
-      s += load_coherent(&red.partials[(size_t)v * MAX_BLOCKS + b]);
-    s = wave_sum(s);
-    if (lane == 0) sh[v][wid] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int v = 0; v < nv; ++v) {
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < BS / 64; ++w) s += sh[v][w];
-      tot[v] = s;
-    }
-    fin(tot);
-    atomicExch(&red.counter[slot], 0u);
-  }
 }
 
-// Grid reduction of two per-thread values for grids whose y index is the load
-// case: tot[r] = sum over the blocks of row r of value 0, tot[nrhs + r] of
-// value 1.  The last block calls fin(tot).
-template <class Fin>
-__device__ void grid_reduce_rhs(double a0, double a1, int nrhs, RedBuf red, int slot,
-                                const Fin& fin) {
-  __shared__ double sh[2][BS / 64];
-  __shared__ double tot[2 * 4];
-  __shared__ int last;
+__device__ __forceinline__ void block_partial2(double a0, double a1, double* d0, double* d1) {
+  __shared__ double sh2[2][BS / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nbx = gridDim.x;
-  const int bid = blockIdx.x + nbx * blockIdx.y;
   a0 = wave_sum(a0);
   a1 = wave_sum(a1);
   if (lane == 0) {
-    sh[0][wid] = a0;
-    sh[1][wid] = a1;
+    sh2[0][wid] = a0;
+    sh2[1][wid] = a1;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0;
+    double t0 = 0.0, t1 = 0.0;
 #pragma unroll
     for (int w = 0; w < BS / 64; ++w) {
-      s0 += sh[0][w];
-      s1 += sh[1][w];
+      t0 += sh2[0][w];
+      t1 += sh2[1][w];
     }
-    red.partials[bid] = s0;
-    red.partials[MAX_BLOCKS + bid] = s1;
-    __threadfence();
-    unsigned t = atomicAdd(&red.counter[slot], 1u);
-    last = (t == gridDim.x * gridDim.y - 1);
+    *d0 = t0;
+    *d1 = t1;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int v = 0; v < 2 * nrhs; ++v) {
-    const int r = v % nrhs, which = v / nrhs;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nbx; b += BS)
-      s += load_coherent(&red.partials[(size_t)which * MAX_BLOCKS + b + (size_t)nbx * r]);
-    s = wave_sum(s);
-    if (lane == 0) sh[0][wid] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-#pragma unroll
-      for (int w = 0; w < BS / 64; ++w) t += sh[0][w];
-      tot[v] = t;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    fin(tot);
-    atomicExch(&red.counter[slot], 0u);
-  }
 }
 
 __device__ __forceinline__ bool any_state(const CgScalars* cs, int nrhs, int state) {
@@ -138,12 +104,12 @@ __device__ __forceinline__ bool any_state(const CgScalars* cs, int nrhs, int sta
 
 inline int nblocks(long n, int per = BS) { return (int)((n + per - 1) / per); }
 
-// Grid for grid-stride vector kernels: bounded so that reductions fit the
-// partials buffer; fixed for a given length (deterministic summation order).
+// Grid for grid-stride vector kernels: at most 512 blocks (two per CU), so
+// that the per-block partial sums stay few for the kernels that re-sum them.
 inline int vec_grid(long n) {
   long b = (n + BS - 1) / BS;
   if (b < 1) b = 1;
-  if (b > 8192) b = 8192;
+  if (b > 512) b = 512;
   return (int)b;
 }
 

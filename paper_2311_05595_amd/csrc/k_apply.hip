@@ -7,6 +7,8 @@
 // eq. (7) reorganised so that each output is written exactly once.  Fused
 // epilogues turn the product into a residual, a weighted-Jacobi update
 // (Algorithm 1, smoothing steps) or a CG step with its dot product.
+#include <type_traits>
+
 #include "devutil.h"
 
 namespace mgcg {
@@ -21,6 +23,14 @@ struct InPlain {
     v[0] = p[0];
     v[1] = p[1];
     v[2] = p[2];
+  }
+  // buffer view of load case r: load(voff) reads the node at byte offset voff
+  struct Buf {
+    __amdgpu_buffer_rsrc_t rx;
+    __device__ __forceinline__ void load(int voff, T v[3]) const { bload3<T>(rx, voff, v); }
+  };
+  __device__ __forceinline__ Buf buf(int r) const {
+    return Buf{make_rsrc(x + (size_t)r * ndof, ndof * sizeof(T))};
   }
 };
 
@@ -37,6 +47,22 @@ struct InScaledB {
     v[0] = omega * d[0] * p[0];
     v[1] = omega * d[1] * p[1];
     v[2] = omega * d[2] * p[2];
+  }
+  struct Buf {
+    __amdgpu_buffer_rsrc_t rb, rd;
+    T omega;
+    __device__ __forceinline__ void load(int voff, T v[3]) const {
+      T bb[3], dd[3];
+      bload3<T>(rb, voff, bb);
+      bload3<T>(rd, voff, dd);
+      v[0] = omega * dd[0] * bb[0];
+      v[1] = omega * dd[1] * bb[1];
+      v[2] = omega * dd[2] * bb[2];
+    }
+  };
+  __device__ __forceinline__ Buf buf(int r) const {
+    return Buf{make_rsrc(b + (size_t)r * ndof, ndof * sizeof(T)),
+               make_rsrc(invD, ndof * sizeof(T)), omega};
   }
 };
 
@@ -57,6 +83,7 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
                                       T y[3]) {
   const Lat L = op.L;
   const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
+  const auto xb = in.buf(r);
   T u[27][3];
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz)
@@ -68,81 +95,183 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
         const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
                         (unsigned)kk < (unsigned)L.nz;
         const int s = dx + 3 * (dy + 3 * dz);
-        if (ok) {
-          in.load(r, ii + (long)L.nx * (jj + (long)L.ny * kk), u[s]);
-        } else {
-          u[s][0] = u[s][1] = u[s][2] = T(0);
-        }
+        // buffer loads: a neighbour outside the lattice reads zeros
+        const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T))
+                          : kBufOOB;
+        xb.load(xo, u[s]);
       }
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
   T acc[3] = {T(0), T(0), T(0)};
+  if constexpr (sizeof(T) == 8) {
+    // FP64 (occupancy 2 either way): 24 independent accumulators (8 elements
+    // x 3 rows), local node b outermost, so consecutive FMAs never depend on
+    // each other
+    T t[8][3];
 #pragma unroll
-  for (int oz = 0; oz < 2; ++oz)
+    for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = T(0);
 #pragma unroll
-    for (int oy = 0; oy < 2; ++oy)
+    for (int b = 0; b < 8; ++b) {
+      const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
 #pragma unroll
-      for (int ox = 0; ox < 2; ++ox) {
-        const int ex = i - 1 + ox, ey = j - 1 + oy, ez = k - 1 + oz;
-        const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
-                        (unsigned)ez < (unsigned)ez1;
-        const T Ee = ok ? op.E[ex + (long)ex1 * (ey + (long)ey1 * ez)] : T(0);
-        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
-        T t[3] = {T(0), T(0), T(0)};
+      for (int e = 0; e < 3; ++e)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+        for (int o = 0; o < 8; ++o) {
+          const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+          const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
           const int s = (ox + bx) + 3 * ((oy + by) + 3 * (oz + bz));
 #pragma unroll
-          for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-              const int q = (3 * a + c) * 24 + 3 * b + e;
-              const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
-              t[c] = fma(kk, u[s][e], t[c]);
-            }
+          for (int c = 0; c < 3; ++c) {
+            const int q = (3 * a + c) * 24 + 3 * b + e;
+            const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
+            t[o][c] = fma(kk, u[s][e], t[o][c]);
+          }
         }
+    }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] = fma(Ee, t[c], acc[c]);
+    for (int o = 0; o < 8; ++o) {
+      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+      const int ex = i - 1 + ox, ey = j - 1 + oy, ez = k - 1 + oz;
+      const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
+                      (unsigned)ez < (unsigned)ez1;
+      const T Ee = bload<T>(re, ok ? (int)((ex + (long)ex1 * (ey + (long)ey1 * ez)) * sizeof(T))
+                                   : kBufOOB, 0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] = fma(Ee, t[o][c], acc[c]);
+    }
+  } else {
+    // FP32: element by element keeps registers low (occupancy 8)
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+      const int ex = i - 1 + ox, ey = j - 1 + oy, ez = k - 1 + oz;
+      const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
+                      (unsigned)ez < (unsigned)ez1;
+      const T Ee = bload<T>(re, ok ? (int)((ex + (long)ex1 * (ey + (long)ey1 * ez)) * sizeof(T))
+                                   : kBufOOB, 0);
+      const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+      T t[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+        const int s = (ox + bx) + 3 * ((oy + by) + 3 * (oz + bz));
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            const int q = (3 * a + c) * 24 + 3 * b + e;
+            const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
+            t[c] = fma(kk, u[s][e], t[c]);
+          }
       }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] = fma(Ee, t[c], acc[c]);
+    }
+  }
   const uint8_t mself = op.mask[i + (long)L.nx * (j + (long)L.ny * k)];
 #pragma unroll
   for (int c = 0; c < 3; ++c) y[c] = ((mself >> c) & 1) ? T(0) : acc[c];
 }
 
-// Stencil apply (supports baked in).
+// Stencil apply (supports baked in).  All loads are buffer loads: the
+// coefficient of (block, row, column) sits at a scalar offset from the node's
+// byte offset, so 243 coefficient loads share two address registers per
+// neighbour; out-of-range neighbours use an offset past the buffer and read 0.
 template <typename T, class In>
 __device__ __forceinline__ void ax_st(const OpST<T>& op, const In& in, int r, int i, int j, int k,
                                       long node, T y[3]) {
   const Lat L = op.L;
   const long nn = L.nn();
+  const auto xb = in.buf(r);
+  const __amdgpu_buffer_rsrc_t rc = make_rsrc(op.coef, (size_t)ST_COEF * nn * sizeof(T));
+  const int row = (int)(nn * sizeof(T));  // bytes between coefficient rows
+  const int vself = (int)(node * sizeof(T));
   T acc[3] = {T(0), T(0), T(0)};
-#pragma unroll
+  // two blocks (four neighbours, ~50 loads) per iteration: enough loads in
+  // flight per thread, bounded register pressure
+#pragma unroll 2
   for (int b = 0; b < ST_BLOCKS; ++b) {
     const Off3 d = st_offset(b);
     {
+      // forward block A_{i, i+d}, stored at this node (zero when i+d is
+      // outside the lattice)
       const int ii = i + d.dx, jj = j + d.dy, kk = k + d.dz;
-      if ((unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
-          (unsigned)kk < (unsigned)L.nz) {
-        const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
-        T v[3];
-        in.load(r, nb, v);
+      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+                      (unsigned)kk < (unsigned)L.nz;
+      const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T)) : kBufOOB;
+      T v[3];
+      xb.load(xo, v);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int e = 0; e < 3; ++e) acc[c] += op.coef[(size_t)(b * 9 + 3 * c + e) * nn + node] * v[e];
-      }
+        for (int e = 0; e < 3; ++e)
+          acc[c] = fma(bload<T>(rc, vself, (b * 9 + 3 * c + e) * row), v[e], acc[c]);
+    }
+    if (b > 0) {
+      // backward block A_{i, i-d} = A_{i-d, i}^T, stored at node i-d
+      const int ii = i - d.dx, jj = j - d.dy, kk = k - d.dz;
+      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+                      (unsigned)kk < (unsigned)L.nz;
+      const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
+      const int xo = ok ? (int)(nb * 3 * sizeof(T)) : kBufOOB;
+      const int co = ok ? (int)(nb * sizeof(T)) : kBufOOB;
+      T v[3];
+      xb.load(xo, v);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          acc[c] = fma(bload<T>(rc, co, (b * 9 + 3 * e + c) * row), v[e], acc[c]);
+    }
+  }
+  y[0] = acc[0];
+  y[1] = acc[1];
+  y[2] = acc[2];
+}
+
+// The blocks b = part, part + LPN, ... of the stencil apply (partial sum of
+// one node's rows).
+template <int LPN, typename T, class In>
+__device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int r, int i, int j,
+                                           int k, long node, int part, T y[3]) {
+  const Lat L = op.L;
+  const long nn = L.nn();
+  const auto xb = in.buf(r);
+  const __amdgpu_buffer_rsrc_t rc = make_rsrc(op.coef, (size_t)ST_COEF * nn * sizeof(T));
+  const int row = (int)(nn * sizeof(T));
+  const int vself = (int)(node * sizeof(T));
+  T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < (ST_BLOCKS + LPN - 1) / LPN; ++q) {
+    const int b = part + q * LPN;
+    if (b >= ST_BLOCKS) break;
+    const Off3 d = st_offset(b);
+    {
+      const int ii = i + d.dx, jj = j + d.dy, kk = k + d.dz;
+      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+                      (unsigned)kk < (unsigned)L.nz;
+      const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T)) : kBufOOB;
+      T v[3];
+      xb.load(xo, v);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          acc[c] = fma(bload<T>(rc, vself, (b * 9 + 3 * c + e) * row), v[e], acc[c]);
     }
     if (b > 0) {
       const int ii = i - d.dx, jj = j - d.dy, kk = k - d.dz;
-      if ((unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
-          (unsigned)kk < (unsigned)L.nz) {
-        const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
-        T v[3];
-        in.load(r, nb, v);
+      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+                      (unsigned)kk < (unsigned)L.nz;
+      const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
+      const int xo = ok ? (int)(nb * 3 * sizeof(T)) : kBufOOB;
+      const int co = ok ? (int)(nb * sizeof(T)) : kBufOOB;
+      T v[3];
+      xb.load(xo, v);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-          for (int e = 0; e < 3; ++e) acc[c] += op.coef[(size_t)(b * 9 + 3 * e + c) * nn + nb] * v[e];
-      }
+        for (int e = 0; e < 3; ++e)
+          acc[c] = fma(bload<T>(rc, co, (b * 9 + 3 * e + c) * row), v[e], acc[c]);
     }
   }
   y[0] = acc[0];
@@ -280,7 +409,7 @@ struct EpResidX {  // r = b - A x, x = omega invD b stored
 };
 
 template <typename T>
-struct EpJacobi {  // xo = x + omega invD (b - A x)
+struct EpJacobi {  // xo = x + wD (b - A x)  (weights folded into wD)
   const T* b;
   const T* x;
   const T* invD;
@@ -294,6 +423,32 @@ struct EpJacobi {  // xo = x + omega invD (b - A x)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       xo[o + c] = x[o + c] + omega * invD[3 * node + c] * (b[o + c] - ax[c]);
+  }
+};
+
+// The last finest-level sweep of the V-cycle: its output is z, so the CG dot
+// products r.z and r_old.z (partials per block) are accumulated here.
+template <typename T>
+struct EpJacobiDot {
+  const T* b;
+  const T* x;
+  const T* invD;
+  T omega;
+  T* xo;
+  long ndof;
+  const double* r;
+  const double* rold;
+  static constexpr bool RED = true;
+  __device__ bool rhs_on(int) const { return true; }
+  __device__ void put(int rr, long node, const T ax[3], double& a0, double& a1) const {
+    const size_t o = (size_t)rr * ndof + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T z = x[o + c] + omega * invD[3 * node + c] * (b[o + c] - ax[c]);
+      xo[o + c] = z;
+      a0 += r[o + c] * (double)z;
+      a1 += rold[o + c] * (double)z;
+    }
   }
 };
 
@@ -351,134 +506,19 @@ struct EpTrueResid {  // for load cases under check: r = f - A x; acc[r] += r.r
   }
 };
 
-// ------------------------------------------------------------ finalisers
-struct FinNone {
-  __device__ void operator()(const double*) const {}
-};
-
-struct FinAlpha {
-  CgScalars* cs;
-  int nrhs;
-  __device__ void operator()(const double* tot) const {
-    for (int r = 0; r < nrhs; ++r) {
-      if (cs[r].state != CG_ACTIVE) continue;
-      const double pq = tot[r];
-      cs[r].pq = pq;
-      if (!(pq > 0.0) || !isfinite(pq))
-        cs[r].state = CG_BREAKDOWN;
-      else
-        cs[r].alpha = cs[r].rz / pq;
-    }
-  }
-};
-
-struct FinResid {
-  CgScalars* cs;
-  int nrhs;
-  __device__ void operator()(const double* tot) const {
-    for (int r = 0; r < nrhs; ++r) {
-      if (cs[r].state != CG_ACTIVE) continue;
-      const double rr = tot[r];
-      cs[r].rr = rr;
-      cs[r].iters += 1;
-      const int it = cs[r].iters;
-      if (!isfinite(rr))
-        cs[r].state = CG_BREAKDOWN;
-      else if (rr <= cs[r].tol2 || it >= cs[r].maxit ||
-               (cs[r].replace_every > 0 && it % cs[r].replace_every == 0))
-        cs[r].state = CG_CHECK;
-    }
-  }
-};
-
-// After a true-residual check: converged, out of iterations, stagnated
-// (three checks in a row without a 10% decrease of the true residual, i.e.
-// at the attainable accuracy), diverged, or continue with the residual
-// replaced by the true one.
-struct FinTrue {
-  CgScalars* cs;
-  int nrhs;
-  __device__ void operator()(const double* tot) const {
-    for (int r = 0; r < nrhs; ++r) {
-      if (cs[r].state != CG_CHECK) continue;
-      const double rr = tot[r];
-      cs[r].rr = rr;
-      cs[r].replacements += 1;
-      if (rr < 0.81 * cs[r].rr_best) {
-        cs[r].rr_best = rr;
-        cs[r].stall = 0;
-      } else {
-        cs[r].stall += 1;
-      }
-      if (!isfinite(rr) || rr > 1e30 * cs[r].ff)
-        cs[r].state = CG_BREAKDOWN;
-      else if (rr <= cs[r].tol2)
-        cs[r].state = CG_DONE;
-      else if (cs[r].iters >= cs[r].maxit || cs[r].stall >= 3)
-        cs[r].state = CG_MAXIT;
-      else
-        cs[r].state = CG_ACTIVE;  // continue from the true residual
-    }
-  }
-};
-
-struct FinInit {
-  CgScalars* cs;
-  int nrhs;
-  __device__ void operator()(const double* tot) const {
-    for (int r = 0; r < nrhs; ++r) {
-      const double rr = tot[r], ff = tot[nrhs + r];
-      cs[r].rr = rr;
-      cs[r].ff = ff;
-      cs[r].tol2 = cs[r].tol2 * ff;  // host stored rtol^2
-      cs[r].iters = 0;
-      cs[r].replacements = 0;
-      cs[r].rz = 0.0;
-      cs[r].beta = 0.0;
-      cs[r].rr_best = rr;
-      cs[r].stall = 0;
-      if (!isfinite(rr) || !isfinite(ff))
-        cs[r].state = CG_BREAKDOWN;
-      else if (ff == 0.0 || rr <= cs[r].tol2)
-        cs[r].state = CG_DONE;
-      else
-        cs[r].state = CG_ACTIVE;
-    }
-  }
-};
-
-struct FinBeta {
-  CgScalars* cs;
-  int nrhs;
-  __device__ void operator()(const double* tot) const {
-    for (int r = 0; r < nrhs; ++r) {
-      if (cs[r].state != CG_ACTIVE) continue;
-      const double rzn = tot[2 * r], rzm = tot[2 * r + 1];
-      if (!isfinite(rzn) || !isfinite(rzm)) {
-        cs[r].state = CG_BREAKDOWN;
-        continue;
-      }
-      // standard beta for the symmetric FP64 V-cycle, flexible
-      // (Polak-Ribiere) beta for the FP32 one; p = z after a (re)start
-      const double num = cs[r].flexible ? (rzn - rzm) : rzn;
-      cs[r].beta = (cs[r].rz == 0.0) ? 0.0 : num / cs[r].rz;
-      cs[r].rz = rzn;
-    }
-  }
-};
-
 // ------------------------------------------------------------ apply kernel
 // One output node per thread, one load case per grid row (blockIdx.y).
 // Register budgets: the matrix-free kernel keeps the 27-node neighbourhood in
 // registers (2 waves per SIMD); the stored-operator kernels stream their
-// coefficients (4 waves per SIMD).
+// coefficients (4 waves per SIMD).  Reducing epilogues write one partial sum
+// per block (value a0 at row r, a1 at row 4 + r of the region); the
+// consumers sum them in a fixed order (no atomics).
 template <class Op> struct Waves { static constexpr int w = 4; };
 template <typename T> struct Waves<OpMF<T>> { static constexpr int w = 2; };
 
-template <typename T, class Op, class In, class Ep, class Fin>
+template <typename T, class Op, class In, class Ep>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(Waves<Op>::w)))
-void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_state, RedBuf red,
-             int slot, Fin fin) {
+void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_state, double* part) {
   if (gate && !any_state(gate, nrhs, gate_state)) return;
   const long node = (long)blockIdx.x * BS + threadIdx.x;
   const int r = blockIdx.y;
@@ -488,19 +528,70 @@ void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_stat
     ax_any(op, in, r, node, ax);
     ep.put(r, node, ax, a0, a1);
   }
-  if constexpr (Ep::RED) grid_reduce_rhs(a0, a1, nrhs, red, slot, fin);
+  if constexpr (Ep::RED) {
+    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + blockIdx.x,
+                   part + (size_t)(4 + r) * MAX_BLOCKS + blockIdx.x);
+  }
 }
 
-template <typename T, class Op, class In, class Ep, class Fin = FinNone>
+// Stencil operators: the 4 waves of a block share 64 consecutive nodes, wave
+// w summing the stencil blocks b = w (mod 4) (coalesced loads, a quarter of
+// the load chain per lane, 4x the waves of one-thread-per-node); the four
+// partial rows meet in LDS and wave 0 runs the epilogue.
+constexpr int ST_LPN = 4;
+constexpr int ST_NODES = BS / ST_LPN;  // nodes per block
+
+template <typename T, class In, class Ep>
+__global__ __launch_bounds__(BS) void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
+                                                 const CgScalars* gate, int gate_state,
+                                                 double* part) {
+  if (gate && !any_state(gate, nrhs, gate_state)) return;
+  __shared__ T red[ST_LPN - 1][3][ST_NODES];
+  const int wave = threadIdx.x / ST_NODES, lane = threadIdx.x % ST_NODES;
+  const long node = (long)blockIdx.x * ST_NODES + lane;
+  const int r = blockIdx.y;
+  double a0 = 0.0, a1 = 0.0;
+  const bool on = node < op.L.nn() && ep.rhs_on(r);
+  T ax[3] = {T(0), T(0), T(0)};
+  if (on) {
+    int i, j, k;
+    node_ijk(node, op.L, i, j, k);
+    ax_st_part<ST_LPN>(op, in, r, i, j, k, node, wave, ax);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) red[wave - 1][c][lane] = ax[c];
+  }
+  __syncthreads();
+  if (wave == 0 && on) {
+#pragma unroll
+    for (int w = 0; w < ST_LPN - 1; ++w)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ax[c] += red[w][c][lane];
+    ep.put(r, node, ax, a0, a1);
+  }
+  if constexpr (Ep::RED) {
+    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + blockIdx.x,
+                   part + (size_t)(4 + r) * MAX_BLOCKS + blockIdx.x);
+  }
+}
+
+template <typename T, class Op, class In, class Ep>
 static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const CgScalars* gate,
-                      int gate_state, hipStream_t st, RedBuf red = RedBuf{nullptr, nullptr},
-                      int slot = 0, Fin fin = Fin{}) {
+                      int gate_state, hipStream_t st, double* part = nullptr) {
   const long nn = op.L.nn();
+  if constexpr (std::is_same<Op, OpST<T>>::value) {
+    const int nb = (int)((nn + ST_NODES - 1) / ST_NODES);
+    if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+    hipLaunchKernelGGL((k_apply_st<T, In, Ep>), dim3(nb, nrhs), dim3(BS), 0, st, op, in, ep, nrhs,
+                       gate, gate_state, part);
+    MGCG_HIP(hipGetLastError());
+    return;
+  }
   const int nb = nblocks(nn);
-  if (Ep::RED && (long)nb * nrhs > MAX_BLOCKS)
-    throw Error(-1, "mesh too large for the reduction buffer");
-  hipLaunchKernelGGL((k_apply<T, Op, In, Ep, Fin>), dim3(nb, nrhs), dim3(BS), 0, st, op, in, ep,
-                     nrhs, gate, gate_state, red, slot, fin);
+  if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+  hipLaunchKernelGGL((k_apply<T, Op, In, Ep>), dim3(nb, nrhs), dim3(BS), 0, st, op, in, ep, nrhs,
+                     gate, gate_state, part);
   MGCG_HIP(hipGetLastError());
 }
 
@@ -527,49 +618,94 @@ template void launch_apply_eq2<double>(const OpEQ2<double>&, const double*, doub
 template void launch_apply_eq2<float>(const OpEQ2<float>&, const float*, float*, int, hipStream_t);
 
 // ------------------------------------------------------------ CG (FP64)
-template <class In, class Ep, class Fin>
+// Per iteration (load cases in parallel, each with its own scalars):
+//   q = A p              [apply, partials p.q]
+//   x += a p, r -= a q   [every block re-sums p.q -> a; partials r.r]
+//   state                [1 block: r.r -> converged? -> CHECK]
+//   r = f - A x          [only for load cases under CHECK; partials]
+//   state                [1 block: true residual -> DONE / continue]
+//   z = M r              [V-cycle]
+//   r.z, r_old.z         [partials]
+//   p = z + b p          [every block re-sums -> b]
+// The scalar r.z is double-buffered by iteration parity so that no kernel
+// reads a value another block of the same kernel writes.
+template <class In, class Ep>
 static void fine_dispatch(const FineOp& A, const In& in, const Ep& ep, int nrhs,
-                          const CgScalars* gate, int gate_state, hipStream_t st, RedBuf red,
-                          int slot, Fin fin) {
+                          const CgScalars* gate, int gate_state, hipStream_t st, double* part) {
   switch (A.kind) {
-    case OP_MF_Q1: run_apply<double>(A.mf, in, ep, nrhs, gate, gate_state, st, red, slot, fin); break;
-    case OP_ST27: run_apply<double>(A.st, in, ep, nrhs, gate, gate_state, st, red, slot, fin); break;
-    default: run_apply<double>(A.eq2, in, ep, nrhs, gate, gate_state, st, red, slot, fin); break;
+    case OP_MF_Q1: run_apply<double>(A.mf, in, ep, nrhs, gate, gate_state, st, part); break;
+    case OP_ST27: run_apply<double>(A.st, in, ep, nrhs, gate, gate_state, st, part); break;
+    default: run_apply<double>(A.eq2, in, ep, nrhs, gate, gate_state, st, part); break;
+  }
+}
+
+static int fine_blocks(const FineOp& A) {
+  return A.kind == OP_ST27 ? (int)((A.lat().nn() + ST_NODES - 1) / ST_NODES)
+                           : nblocks(A.lat().nn());
+}
+
+__global__ void k_fin_init(CgScalars* cs, int nrhs, const double* part, int nb) {
+  __shared__ double sh[BS / 64];
+  for (int r = 0; r < nrhs; ++r) {
+    const double rr = block_sum(part + (size_t)r * MAX_BLOCKS, nb, sh);
+    const double ff = block_sum(part + (size_t)(4 + r) * MAX_BLOCKS, nb, sh);
+    if (threadIdx.x == 0) {
+      CgScalars& c = cs[r];
+      c.rr = rr;
+      c.ff = ff;
+      c.tol2 = c.tol2 * ff;  // cg_reset stored rtol^2
+      c.iters = 0;
+      c.replacements = 0;
+      c.rzs[0] = c.rzs[1] = 0.0;
+      c.beta = 0.0;
+      c.rr_best = rr;
+      c.stall = 0;
+      c.bad = 0;
+      if (!isfinite(rr) || !isfinite(ff))
+        c.state = CG_BREAKDOWN;
+      else if (ff == 0.0 || rr <= c.tol2)
+        c.state = CG_DONE;
+      else
+        c.state = CG_ACTIVE;
+    }
   }
 }
 
 void cg_init_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
                       CgScalars* cs, RedBuf red, hipStream_t st) {
   const long nd = A.lat().ndof();
-  fine_dispatch(A, InPlain<double>{x, nd}, EpInitResid{f, r, nd, nrhs}, nrhs, nullptr, 0, st, red,
-                0, FinInit{cs, nrhs});
+  double* part = red.partials + RED_INIT * RED_REGION;
+  fine_dispatch(A, InPlain<double>{x, nd}, EpInitResid{f, r, nd, nrhs}, nrhs, nullptr, 0, st, part);
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, st, cs, nrhs, part, fine_blocks(A));
+  MGCG_HIP(hipGetLastError());
 }
 
 void cg_apply_alpha(const FineOp& A, const double* p, double* q, int nrhs, CgScalars* cs,
                     RedBuf red, hipStream_t st) {
   const long nd = A.lat().ndof();
-  fine_dispatch(A, InPlain<double>{p, nd}, EpDotPQ{p, q, nd, cs}, nrhs, cs, CG_ACTIVE, st, red, 1,
-                FinAlpha{cs, nrhs});
+  fine_dispatch(A, InPlain<double>{p, nd}, EpDotPQ{p, q, nd, cs}, nrhs, cs, CG_ACTIVE, st,
+                red.partials + RED_PQ * RED_REGION);
 }
 
-void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
-                      CgScalars* cs, RedBuf red, hipStream_t st) {
-  const long nd = A.lat().ndof();
-  fine_dispatch(A, InPlain<double>{x, nd}, EpTrueResid{f, r, nd, cs}, nrhs, cs, CG_CHECK, st, red,
-                2, FinTrue{cs, nrhs});
-}
-
+// x += a p, r -= a q with a = r.z / p.q re-summed by every block.
 __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
                                                   const double* __restrict__ q, double* x, double* r,
-                                                  long ndof, int nrhs, CgScalars* cs, RedBuf red) {
+                                                  long ndof, int nrhs, CgScalars* cs,
+                                                  const double* __restrict__ ppq, int nbq,
+                                                  double* prr) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
-  double acc[MAX_RED_VALUES];
-#pragma unroll
-  for (int v = 0; v < MAX_RED_VALUES; ++v) acc[v] = 0.0;
+  __shared__ double sh[BS / 64];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
-    const double a = cs[rr].alpha;
+    const double pq = block_sum(ppq + (size_t)rr * MAX_BLOCKS, nbq, sh);
+    const int par = (cs[rr].iters + 1) & 1;
+    const double a = (pq > 0.0 && isfinite(pq)) ? cs[rr].rzs[par] / pq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      cs[rr].pq = pq;
+      cs[rr].alpha = a;
+    }
     const size_t o = (size_t)rr * ndof;
     double s = 0.0;
     for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
@@ -580,13 +716,82 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
     }
     acc[rr] = s;
   }
-  grid_reduce(acc, nrhs, red, 3, FinResid{cs, nrhs});
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+    if (rr < nrhs) block_partial1(acc[rr], prr + (size_t)rr * MAX_BLOCKS + blockIdx.x);
+}
+
+// Convergence test of the recurrence residual (one block).
+__global__ void k_fin_rr(CgScalars* cs, int nrhs, const double* part, int nb) {
+  __shared__ double sh[BS / 64];
+  for (int r = 0; r < nrhs; ++r) {
+    if (cs[r].state != CG_ACTIVE) continue;  // uniform
+    const double rr = block_sum(part + (size_t)r * MAX_BLOCKS, nb, sh);
+    if (threadIdx.x == 0) {
+      CgScalars& c = cs[r];
+      c.rr = rr;
+      c.iters += 1;
+      const int it = c.iters;
+      if (!(c.pq > 0.0) || !isfinite(c.pq) || c.bad || !isfinite(rr))
+        c.state = CG_BREAKDOWN;
+      else if (rr <= c.tol2 || it >= c.maxit ||
+               (c.replace_every > 0 && it % c.replace_every == 0))
+        c.state = CG_CHECK;
+    }
+    __syncthreads();
+  }
 }
 
 void cg_update_xr(const double* p, const double* q, double* x, double* r, long ndof, int nrhs,
-                  CgScalars* cs, RedBuf red, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_xr, dim3(vec_grid(ndof)), dim3(BS), 0, st, p, q, x, r, ndof, nrhs, cs,
-                     red);
+                  CgScalars* cs, RedBuf red, int nbq, hipStream_t st) {
+  double* prr = red.partials + RED_RR * RED_REGION;
+  const int g = vec_grid(ndof);
+  hipLaunchKernelGGL(k_update_xr, dim3(g), dim3(BS), 0, st, p, q, x, r, ndof, nrhs, cs,
+                     red.partials + RED_PQ * RED_REGION, nbq, prr);
+  MGCG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(BS), 0, st, cs, nrhs, prr, g);
+  MGCG_HIP(hipGetLastError());
+}
+
+// After a true-residual check: converged, out of iterations, stagnated
+// (three checks in a row without a 10% decrease of the true residual, i.e.
+// at the attainable accuracy), diverged, or continue with the residual
+// replaced by the true one.
+__global__ void k_fin_true(CgScalars* cs, int nrhs, const double* part, int nb) {
+  if (!any_state(cs, nrhs, CG_CHECK)) return;
+  __shared__ double sh[BS / 64];
+  for (int r = 0; r < nrhs; ++r) {
+    if (cs[r].state != CG_CHECK) continue;
+    const double rr = block_sum(part + (size_t)r * MAX_BLOCKS, nb, sh);
+    if (threadIdx.x == 0) {
+      CgScalars& c = cs[r];
+      c.rr = rr;
+      c.replacements += 1;
+      if (rr < 0.81 * c.rr_best) {
+        c.rr_best = rr;
+        c.stall = 0;
+      } else {
+        c.stall += 1;
+      }
+      if (!isfinite(rr) || rr > 1e30 * c.ff)
+        c.state = CG_BREAKDOWN;
+      else if (rr <= c.tol2)
+        c.state = CG_DONE;
+      else if (c.iters >= c.maxit || c.stall >= 3)
+        c.state = CG_MAXIT;
+      else
+        c.state = CG_ACTIVE;
+    }
+    __syncthreads();
+  }
+}
+
+void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
+                      CgScalars* cs, RedBuf red, hipStream_t st) {
+  const long nd = A.lat().ndof();
+  double* part = red.partials + RED_TR * RED_REGION;
+  fine_dispatch(A, InPlain<double>{x, nd}, EpTrueResid{f, r, nd, cs}, nrhs, cs, CG_CHECK, st, part);
+  hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(BS), 0, st, cs, nrhs, part, fine_blocks(A));
   MGCG_HIP(hipGetLastError());
 }
 
@@ -594,11 +799,9 @@ template <typename TZ>
 __global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
                                              const double* __restrict__ rold,
                                              const TZ* __restrict__ z, long ndof, int nrhs,
-                                             CgScalars* cs, RedBuf red) {
+                                             const CgScalars* cs, double* part) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
-  double acc[MAX_RED_VALUES];
-#pragma unroll
-  for (int v = 0; v < MAX_RED_VALUES; ++v) acc[v] = 0.0;
+  double a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
@@ -609,17 +812,23 @@ __global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
       s0 += r[o + i] * zz;
       s1 += rold[o + i] * zz;
     }
-    acc[2 * rr] = s0;
-    acc[2 * rr + 1] = s1;
+    a0[rr] = s0;
+    a1[rr] = s1;
   }
-  grid_reduce(acc, 2 * nrhs, red, 4, FinBeta{cs, nrhs});
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+    if (rr < nrhs)
+      block_partial2(a0[rr], a1[rr], part + (size_t)rr * MAX_BLOCKS + blockIdx.x,
+                     part + (size_t)(4 + rr) * MAX_BLOCKS + blockIdx.x);
 }
+
+int cg_beta_blocks(long ndof) { return vec_grid(ndof); }
 
 template <typename TZ>
 void cg_beta(const double* r, const double* rold, const TZ* z, long ndof, int nrhs, CgScalars* cs,
              RedBuf red, hipStream_t st) {
   hipLaunchKernelGGL(k_beta<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, r, rold, z, ndof, nrhs, cs,
-                     red);
+                     red.partials + RED_RZ * RED_REGION);
   MGCG_HIP(hipGetLastError());
 }
 template void cg_beta<double>(const double*, const double*, const double*, long, int, CgScalars*,
@@ -627,14 +836,31 @@ template void cg_beta<double>(const double*, const double*, const double*, long,
 template void cg_beta<float>(const double*, const double*, const float*, long, int, CgScalars*,
                              RedBuf, hipStream_t);
 
+// p = z + b p, r_old = r; b re-summed by every block: standard beta for the
+// symmetric FP64 V-cycle, flexible (Polak-Ribiere) beta for the FP32 one,
+// b = 0 for the first direction.
 template <typename TZ>
 __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, double* p,
                                                  const double* __restrict__ r, double* rold,
-                                                 long ndof, int nrhs, const CgScalars* cs) {
+                                                 long ndof, int nrhs, CgScalars* cs,
+                                                 const double* __restrict__ part, int nbz) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
-  for (int rr = 0; rr < nrhs; ++rr) {
-    if (cs[rr].state != CG_ACTIVE) continue;
-    const double b = cs[rr].beta;
+  __shared__ double sh[BS / 64];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
+    const double rzn = block_sum(part + (size_t)rr * MAX_BLOCKS, nbz, sh);
+    const double rzm = block_sum(part + (size_t)(4 + rr) * MAX_BLOCKS, nbz, sh);
+    const int par = cs[rr].iters & 1;
+    const double rzo = cs[rr].rzs[par];
+    const bool ok = isfinite(rzn) && isfinite(rzm);
+    const double num = cs[rr].flexible ? (rzn - rzm) : rzn;
+    const double b = (!ok || rzo == 0.0) ? 0.0 : num / rzo;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      cs[rr].rzs[par ^ 1] = rzn;
+      cs[rr].beta = b;
+      if (!ok) cs[rr].bad = 1;
+    }
     const size_t o = (size_t)rr * ndof;
     for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
       p[o + i] = (double)z[o + i] + b * p[o + i];
@@ -645,15 +871,15 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
 
 template <typename TZ>
 void cg_update_p(const TZ* z, double* p, const double* r, double* rold, long ndof, int nrhs,
-                 const CgScalars* cs, hipStream_t st) {
+                 CgScalars* cs, RedBuf red, int nbz, hipStream_t st) {
   hipLaunchKernelGGL(k_update_p<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, z, p, r, rold, ndof,
-                     nrhs, cs);
+                     nrhs, cs, red.partials + RED_RZ * RED_REGION, nbz);
   MGCG_HIP(hipGetLastError());
 }
 template void cg_update_p<double>(const double*, double*, const double*, double*, long, int,
-                                  const CgScalars*, hipStream_t);
+                                  CgScalars*, RedBuf, int, hipStream_t);
 template void cg_update_p<float>(const float*, double*, const double*, double*, long, int,
-                                 const CgScalars*, hipStream_t);
+                                 CgScalars*, RedBuf, int, hipStream_t);
 
 // ------------------------------------------------------------ V-cycle
 template <typename T, class In, class Ep>
@@ -667,14 +893,6 @@ static void v_dispatch(const VOps<T>& v, const In& in, const Ep& ep, int nrhs, c
 }
 
 template <typename T>
-void v_presmooth_residual(const VOps<T>& v, const T* b, T* x, T* r, T omega, int nrhs,
-                          const CgScalars* cs, hipStream_t st) {
-  const long nd = v.L.ndof();
-  v_dispatch(v, InScaledB<T>{b, v.invD, omega, nd}, EpResidX<T>{b, v.invD, omega, r, x, nd}, nrhs,
-             cs, st);
-}
-
-template <typename T>
 void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs,
               const CgScalars* cs, hipStream_t st) {
   const long nd = v.L.ndof();
@@ -682,10 +900,48 @@ void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs
 }
 
 template <typename T>
+void v_jacobi_dot(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, const double* r,
+                  const double* rold, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st) {
+  const long nd = v.L.ndof();
+  const EpJacobiDot<T> ep{b, x, v.invD, omega, xo, nd, r, rold};
+  double* part = red.partials + RED_RZ * RED_REGION;
+  switch (v.kind) {
+    case OP_MF_Q1: run_apply<T>(v.mf, InPlain<T>{x, nd}, ep, nrhs, cs, CG_ACTIVE, st, part); break;
+    case OP_ST27: run_apply<T>(v.st, InPlain<T>{x, nd}, ep, nrhs, cs, CG_ACTIVE, st, part); break;
+    default: run_apply<T>(v.eq2, InPlain<T>{x, nd}, ep, nrhs, cs, CG_ACTIVE, st, part); break;
+  }
+}
+
+template <typename T>
 void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const CgScalars* cs,
                 hipStream_t st) {
   const long nd = v.L.ndof();
   v_dispatch(v, InPlain<T>{x, nd}, EpResid<T>{b, r, nd}, nrhs, cs, st);
+}
+
+// Level-0 input of the V-cycle: b0 = r in the V-cycle precision (only stored
+// when it differs from FP64) and the first smoothing sweep x0 = W D^-1 b0.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prepare0(const double* __restrict__ r, T* b0,
+                                                 const T* __restrict__ wD, T* x0, long ndof,
+                                                 int nrhs, const CgScalars* cs) {
+  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  for (int rr = 0; rr < nrhs; ++rr) {
+    const size_t o = (size_t)rr * ndof;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
+      const T b = (T)r[o + i];
+      if (b0) b0[o + i] = b;
+      x0[o + i] = wD[i] * b;
+    }
+  }
+}
+
+template <typename T>
+void v_prepare0(const double* r, T* b0, const T* wD, T* x0, long ndof, int nrhs,
+                const CgScalars* cs, hipStream_t st) {
+  hipLaunchKernelGGL(k_prepare0<T>, dim3(vec_grid(ndof)), dim3(BS), 0, st, r, b0, wD, x0, ndof,
+                     nrhs, cs);
+  MGCG_HIP(hipGetLastError());
 }
 
 template <typename T>
@@ -714,7 +970,8 @@ void v_smooth0(const T* b, const T* invD, T* x, T omega, long ndof, int nrhs, co
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __restrict__ mf,
                                                  const uint8_t* __restrict__ mc,
-                                                 const T* __restrict__ rf, T* bc, int nrhs,
+                                                 const T* __restrict__ rf, T* bc,
+                                                 const T* __restrict__ wDc, T* xc, int nrhs,
                                                  const CgScalars* cs) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   const long t = (long)blockIdx.x * BS + threadIdx.x;
@@ -742,16 +999,19 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
           const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
           acc += w * src[3 * (i + (long)F.nx * (j + (long)F.ny * k))];
         }
-    bc[(size_t)r * cnd + t] = fixed ? T(0) : acc;
+    const T bv = fixed ? T(0) : acc;
+    bc[(size_t)r * cnd + t] = bv;
+    // first smoothing sweep of the coarse level from zero: x = W D^-1 b
+    if (xc) xc[(size_t)r * cnd + t] = wDc[t] * bv;
   }
   (void)mf;
 }
 
 template <typename T>
 void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* rf,
-                T* bc, int nrhs, const CgScalars* cs, hipStream_t st) {
+                T* bc, const T* wDc, T* xc, int nrhs, const CgScalars* cs, hipStream_t st) {
   hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(coarse.ndof())), dim3(BS), 0, st, fine, coarse,
-                     mask_f, mask_c, rf, bc, nrhs, cs);
+                     mask_f, mask_c, rf, bc, wDc, xc, nrhs, cs);
   MGCG_HIP(hipGetLastError());
 }
 
@@ -828,16 +1088,149 @@ void v_coarse_solve(const double* Ainv, const int* freedof, int nc, long ndof, c
   MGCG_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------ V-cycle tail
+constexpr int TAIL_BS = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(TAIL_BS) void k_tail(TailArgs<T> a, const CgScalars* cs) {
+  if (!any_state(cs, a.nrhs, CG_ACTIVE)) return;
+  const int tid = threadIdx.x;
+  const int R = a.nrhs;
+  // x of every level as a pointer pair (current, other) swapped by sweeps
+  T* cur[TAIL_MAX];
+  T* oth[TAIL_MAX];
+  for (int l = 0; l < a.nlev; ++l) {
+    cur[l] = a.lv[l].x;
+    oth[l] = a.lv[l].xalt;
+  }
+  auto jacobi = [&](int l, const T* xin, T* xout) {
+    const TailLevel<T>& v = a.lv[l];
+    const OpST<T> op{v.L, v.coef};
+    const long nn = v.L.nn(), nd = v.L.ndof();
+    for (int r = 0; r < R; ++r)
+      for (long node = tid; node < nn; node += TAIL_BS) {
+        int i, j, k;
+        node_ijk(node, v.L, i, j, k);
+        T ax[3];
+        ax_st(op, InPlain<T>{xin, nd}, r, i, j, k, node, ax);
+        const size_t o = (size_t)r * nd + 3 * node;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xout[o + c] = xin[o + c] + v.wD[3 * node + c] * (v.b[o + c] - ax[c]);
+      }
+    __syncthreads();
+  };
+  const int lc = a.nlev - 1;
+  for (int l = 0; l < lc; ++l) {
+    const TailLevel<T>& v = a.lv[l];
+    const OpST<T> op{v.L, v.coef};
+    const long nn = v.L.nn(), nd = v.L.ndof();
+    for (int s = 1; s < a.pre; ++s) {
+      jacobi(l, cur[l], oth[l]);
+      T* t = cur[l]; cur[l] = oth[l]; oth[l] = t;
+    }
+    for (int r = 0; r < R; ++r)
+      for (long node = tid; node < nn; node += TAIL_BS) {
+        int i, j, k;
+        node_ijk(node, v.L, i, j, k);
+        T ax[3];
+        ax_st(op, InPlain<T>{cur[l], nd}, r, i, j, k, node, ax);
+        const size_t o = (size_t)r * nd + 3 * node;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v.r[o + c] = v.b[o + c] - ax[c];
+      }
+    __syncthreads();
+    // restriction to level l+1 (and its first sweep unless it is the coarsest)
+    const TailLevel<T>& w = a.lv[l + 1];
+    const long cnd = w.L.ndof(), fnd = nd;
+    for (int r = 0; r < R; ++r)
+      for (long t = tid; t < cnd; t += TAIL_BS) {
+        const long cn = t / 3;
+        const int c = (int)(t % 3);
+        int I, J, K;
+        node_ijk(cn, w.L, I, J, K);
+        T acc = T(0);
+        const T* src = v.r + (size_t)r * fnd + c;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
+              if ((unsigned)fi >= (unsigned)v.L.nx || (unsigned)fj >= (unsigned)v.L.ny ||
+                  (unsigned)fk >= (unsigned)v.L.nz)
+                continue;
+              const T wgt = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+              acc += wgt * src[3 * (fi + (long)v.L.nx * (fj + (long)v.L.ny * fk))];
+            }
+        const T bv = ((w.mask[cn] >> c) & 1) ? T(0) : acc;
+        w.b[(size_t)r * cnd + t] = bv;
+        if (l + 1 < lc) cur[l + 1][(size_t)r * cnd + t] = w.wD[t] * bv;
+      }
+    __syncthreads();
+  }
+  // coarsest: x = A_c^{-1} b over the free DOFs (fixed entries stay 0)
+  {
+    const TailLevel<T>& v = a.lv[lc];
+    const long nd = v.L.ndof();
+    for (int r = 0; r < R; ++r)
+      for (int row = tid; row < a.nc; row += TAIL_BS) {
+        const double* arow = a.Ainv + (size_t)row * a.nc;
+        double sacc = 0.0;
+        for (int c = 0; c < a.nc; ++c) sacc += arow[c] * (double)v.b[(size_t)r * nd + a.freedof[c]];
+        cur[lc][(size_t)r * nd + a.freedof[row]] = (T)sacc;
+      }
+    __syncthreads();
+  }
+  for (int l = lc - 1; l >= 0; --l) {
+    const TailLevel<T>& v = a.lv[l];
+    const TailLevel<T>& w = a.lv[l + 1];
+    const long nn = v.L.nn(), nd = v.L.ndof(), cnd = w.L.ndof();
+    for (int r = 0; r < R; ++r)
+      for (long node = tid; node < nn; node += TAIL_BS) {
+        int i, j, k;
+        node_ijk(node, v.L, i, j, k);
+        const uint8_t m = v.mask[node];
+        const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+        const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+        const T wgt = T(((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) * ((k & 1) ? 0.5 : 1.0));
+        T acc[3] = {T(0), T(0), T(0)};
+        for (int c2 = 0; c2 < nk; ++c2)
+          for (int b2 = 0; b2 < nj; ++b2)
+            for (int a2 = 0; a2 < ni; ++a2) {
+              const long cn = (i0 + a2) + (long)w.L.nx * ((j0 + b2) + (long)w.L.ny * (k0 + c2));
+              const T* pp = cur[l + 1] + (size_t)r * cnd + 3 * cn;
+              for (int c = 0; c < 3; ++c) acc[c] += wgt * pp[c];
+            }
+        T* q = cur[l] + (size_t)r * nd + 3 * node;
+        for (int c = 0; c < 3; ++c)
+          if (!((m >> c) & 1)) q[c] += acc[c];
+      }
+    __syncthreads();
+    for (int s = 0; s < a.post; ++s) {
+      jacobi(l, cur[l], oth[l]);
+      T* t = cur[l]; cur[l] = oth[l]; oth[l] = t;
+    }
+  }
+}
+
+template <typename T>
+void v_tail(const TailArgs<T>& a, const CgScalars* cs, hipStream_t st) {
+  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TAIL_BS), 0, st, a, cs);
+  MGCG_HIP(hipGetLastError());
+}
+template void v_tail<double>(const TailArgs<double>&, const CgScalars*, hipStream_t);
+template void v_tail<float>(const TailArgs<float>&, const CgScalars*, hipStream_t);
+
 #define VINST(T)                                                                                  \
-  template void v_presmooth_residual<T>(const VOps<T>&, const T*, T*, T*, T, int, const CgScalars*, \
-                                        hipStream_t);                                             \
   template void v_jacobi<T>(const VOps<T>&, const T*, const T*, T*, T, int, const CgScalars*,      \
                             hipStream_t);                                                         \
+  template void v_jacobi_dot<T>(const VOps<T>&, const T*, const T*, T*, T, const double*,          \
+                                const double*, int, const CgScalars*, RedBuf, hipStream_t);       \
   template void v_residual<T>(const VOps<T>&, const T*, const T*, T*, int, const CgScalars*,       \
                               hipStream_t);                                                       \
   template void v_smooth0<T>(const T*, const T*, T*, T, long, int, const CgScalars*, hipStream_t); \
-  template void v_restrict<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, int,         \
-                              const CgScalars*, hipStream_t);                                     \
+  template void v_restrict<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, const T*,   \
+                              T*, int, const CgScalars*, hipStream_t);                            \
+  template void v_prepare0<T>(const double*, T*, const T*, T*, long, int, const CgScalars*,        \
+                              hipStream_t);                                                       \
   template void v_prolong<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, int, bool,    \
                              const CgScalars*, hipStream_t);                                      \
   template void v_coarse_solve<T>(const double*, const int*, int, long, const T*, T*, int,         \

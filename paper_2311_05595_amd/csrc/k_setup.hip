@@ -112,12 +112,13 @@ __global__ __launch_bounds__(BS) void k_galerkin(int src_kind, Lat F, const doub
                                                  const double* __restrict__ K0,
                                                  const double* __restrict__ Kc,
                                                  const uint8_t* __restrict__ mask_f, int ncx,
-                                                 int ncy, int ncz, double* KE) {
+                                                 int ncy, int ncz, double* KE,
+                                                 const int* __restrict__ elist) {
   __shared__ double sK[81 * 81];
   __shared__ double sT[81 * 24];
   __shared__ double sW[27 * 8];
   __shared__ uint8_t sFix[81];
-  const long E_id = blockIdx.x;
+  const long E_id = elist ? elist[blockIdx.x] : blockIdx.x;
   const int EX = (int)(E_id % ncx), EY = (int)((E_id / ncx) % ncy), EZ = (int)(E_id / ((long)ncx * ncy));
   const bool q2 = (src_kind == OP_EQ2);
   const int nen = q2 ? 27 : 8, nd = 3 * nen, p1 = q2 ? 3 : 2;
@@ -188,10 +189,62 @@ __global__ __launch_bounds__(BS) void k_galerkin(int src_kind, Lat F, const doub
 }
 
 void setup_galerkin(int src_kind, Lat fine, const double* E, const double* K0, const double* Kc,
-                    const uint8_t* mask_f, int ncx, int ncy, int ncz, double* KE, hipStream_t st) {
-  const long nce = (long)ncx * ncy * ncz;
+                    const uint8_t* mask_f, int ncx, int ncy, int ncz, double* KE,
+                    const int* elist, int n_elist, hipStream_t st) {
+  const long nce = elist ? n_elist : (long)ncx * ncy * ncz;
+  if (nce <= 0) return;
   hipLaunchKernelGGL(k_galerkin, dim3((unsigned)nce), dim3(BS), 0, st, src_kind, fine, E, K0, Kc,
-                     mask_f, ncx, ncy, ncz, KE);
+                     mask_f, ncx, ncy, ncz, KE, elist);
+  MGCG_HIP(hipGetLastError());
+}
+
+// One block = 576 threads (one per matrix entry) x GB coarse elements; the
+// moduli of the GB elements sit in LDS, every G entry is read once per block.
+constexpr int GB = 8;
+__global__ __launch_bounds__(576) void k_galerkin_lin(const double* __restrict__ E,
+                                                      const double* __restrict__ G, int B,
+                                                      int nsub, int nelx, int nely, int ncx,
+                                                      int ncy, int ncz, double* KE) {
+  extern __shared__ double sE[];  // [GB][M]
+  const int M = B * B * B;
+  const long nce = (long)ncx * ncy * ncz;
+  const long e0 = (long)blockIdx.x * GB;
+  const long ndx = (long)nsub * nelx, ndy = (long)nsub * nely;
+  for (int t = threadIdx.x; t < GB * M; t += 576) {
+    const int b = t / M, m = t % M;
+    const long e = e0 + b;
+    double v = 0.0;
+    if (e < nce) {
+      const int EX = (int)(e % ncx), EY = (int)((e / ncx) % ncy), EZ = (int)(e / ((long)ncx * ncy));
+      const int px = m % B, py = (m / B) % B, pz = m / (B * B);
+      v = E[(B * (long)EX + px) + ndx * ((B * (long)EY + py) + ndy * (B * (long)EZ + pz))];
+    }
+    sE[t] = v;
+  }
+  __syncthreads();
+  const int q = threadIdx.x;
+  double acc[GB];
+#pragma unroll
+  for (int b = 0; b < GB; ++b) acc[b] = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const double g = G[(size_t)m * 576 + q];
+#pragma unroll
+    for (int b = 0; b < GB; ++b) acc[b] += sE[b * M + m] * g;
+  }
+#pragma unroll
+  for (int b = 0; b < GB; ++b) {
+    const long e = e0 + b;
+    if (e < nce) KE[(size_t)e * 576 + q] = acc[b];
+  }
+}
+
+void setup_galerkin_lin(const double* E, const double* G, int B, int nsub, int nelx, int nely,
+                        int ncx, int ncy, int ncz, double* KE, hipStream_t st) {
+  const long nce = (long)ncx * ncy * ncz;
+  const int M = B * B * B;
+  hipLaunchKernelGGL(k_galerkin_lin, dim3((unsigned)((nce + GB - 1) / GB)), dim3(576),
+                     (size_t)GB * M * sizeof(double), st, E, G, B, nsub, nelx, nely, ncx, ncy, ncz,
+                     KE);
   MGCG_HIP(hipGetLastError());
 }
 
@@ -485,6 +538,69 @@ __global__ __launch_bounds__(1024) void k_cholesky(double* A, int n, int* bad) {
   }
 }
 
+// Left-looking panel Cholesky A = L L^T (lower triangle, in place), one
+// workgroup: each panel of NB columns is first updated with the finished
+// columns to its left (a parallel dot-product pass over L2-resident rows),
+// then factored column by column inside LDS.  Dynamic LDS: rows x NB doubles.
+template <int NB>
+__global__ __launch_bounds__(1024) void k_cholesky_panel(double* A, int n, int* bad) {
+  extern __shared__ double P[];  // [n - p0][NB], row-major
+  __shared__ double sd;
+  const int tid = threadIdx.x;
+  for (int p0 = 0; p0 < n; p0 += NB) {
+    const int w = min(NB, n - p0), rows = n - p0;
+    // load + left-looking update of the panel (lower part r >= c)
+    for (int t = tid; t < rows * NB; t += 1024) {
+      const int r = t / NB, c = t % NB;
+      double v = 0.0;
+      if (c < w && r >= c) {
+        const double* ai = A + (size_t)(p0 + r) * n;
+        const double* aj = A + (size_t)(p0 + c) * n;
+        v = ai[p0 + c];
+        double s0 = 0.0, s1 = 0.0;
+        int k = 0;
+        for (; k + 1 < p0; k += 2) {
+          s0 += ai[k] * aj[k];
+          s1 += ai[k + 1] * aj[k + 1];
+        }
+        if (k < p0) s0 += ai[k] * aj[k];
+        v -= s0 + s1;
+      }
+      P[t] = v;
+    }
+    __syncthreads();
+    for (int c = 0; c < w; ++c) {
+      if (tid == 0) {
+        double d = P[c * NB + c];
+        if (!(d > 0.0) || !isfinite(d)) {
+          atomicOr(bad, 2);
+          d = 1.0;
+        }
+        d = sqrt(d);
+        P[c * NB + c] = d;
+        sd = d;
+      }
+      __syncthreads();
+      const double inv = 1.0 / sd;
+      for (int r = c + 1 + tid; r < rows; r += 1024) P[r * NB + c] *= inv;
+      __syncthreads();
+      const int wc = w - c - 1;
+      if (wc > 0) {
+        for (int t = tid; t < (rows - c - 1) * wc; t += 1024) {
+          const int r = c + 1 + t / wc, c2 = c + 1 + t % wc;
+          if (r >= c2) P[r * NB + c2] -= P[r * NB + c] * P[c2 * NB + c];
+        }
+      }
+      __syncthreads();
+    }
+    for (int t = tid; t < rows * NB; t += 1024) {
+      const int r = t / NB, c = t % NB;
+      if (c < w && r >= c) A[(size_t)(p0 + r) * n + p0 + c] = P[t];
+    }
+    __syncthreads();
+  }
+}
+
 // Column j of L^{-1} by forward substitution (one workgroup per column).
 __global__ __launch_bounds__(BS) void k_trinv(const double* __restrict__ Lf, double* Linv, int n) {
   extern __shared__ double w[];
@@ -514,7 +630,19 @@ __global__ __launch_bounds__(BS) void k_ltl(const double* __restrict__ Linv, dou
 void setup_cholesky_inverse(double* A, double* Linv, double* Ainv, int nc, int* bad,
                             hipStream_t st) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, nc, bad);
+  // panel in at most 64 KB of LDS
+  const size_t lim = 64 * 1024;
+  if ((size_t)nc * 32 * sizeof(double) <= lim)
+    hipLaunchKernelGGL(k_cholesky_panel<32>, dim3(1), dim3(1024), (size_t)nc * 32 * sizeof(double),
+                       st, A, nc, bad);
+  else if ((size_t)nc * 16 * sizeof(double) <= lim)
+    hipLaunchKernelGGL(k_cholesky_panel<16>, dim3(1), dim3(1024), (size_t)nc * 16 * sizeof(double),
+                       st, A, nc, bad);
+  else if ((size_t)nc * 8 * sizeof(double) <= lim)
+    hipLaunchKernelGGL(k_cholesky_panel<8>, dim3(1), dim3(1024), (size_t)nc * 8 * sizeof(double),
+                       st, A, nc, bad);
+  else
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, nc, bad);
   MGCG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_trinv, dim3(nc), dim3(BS), nc * sizeof(double), st, A, Linv, nc);
   MGCG_HIP(hipGetLastError());
@@ -523,19 +651,8 @@ void setup_cholesky_inverse(double* A, double* Linv, double* Ainv, int nc, int* 
 }
 
 // ------------------------------------------------------------ compliance
-struct FinStore {
-  double* out;
-  int n;
-  __device__ void operator()(const double* tot) const {
-    for (int v = 0; v < n; ++v) out[v] = tot[v];
-  }
-};
-
 __global__ __launch_bounds__(BS) void k_comp(const double* __restrict__ f, const double* __restrict__ u,
-                                             long ndof, int nrhs, double* out, RedBuf red) {
-  double acc[MAX_RED_VALUES];
-#pragma unroll
-  for (int v = 0; v < MAX_RED_VALUES; ++v) acc[v] = 0.0;
+                                             long ndof, int nrhs, double* part) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     if (r >= nrhs) continue;
@@ -543,14 +660,25 @@ __global__ __launch_bounds__(BS) void k_comp(const double* __restrict__ f, const
     double s = 0.0;
     for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS)
       s += f[o + i] * u[o + i];
-    acc[r] = s;
+    block_partial1(s, part + (size_t)r * MAX_BLOCKS + blockIdx.x);
   }
-  grid_reduce(acc, nrhs, red, 5, FinStore{out, nrhs});
+}
+
+__global__ void k_comp_fin(const double* part, int nb, int nrhs, double* out) {
+  __shared__ double sh[BS / 64];
+  for (int r = 0; r < nrhs; ++r) {
+    const double s = block_sum(part + (size_t)r * MAX_BLOCKS, nb, sh);
+    if (threadIdx.x == 0) out[r] = s;
+  }
 }
 
 void comp_dot(const double* f, const double* u, long ndof, int nrhs, double* out, RedBuf red,
               hipStream_t st) {
-  hipLaunchKernelGGL(k_comp, dim3(vec_grid(ndof)), dim3(BS), 0, st, f, u, ndof, nrhs, out, red);
+  double* part = red.partials + RED_COMP * RED_REGION;
+  const int g = vec_grid(ndof);
+  hipLaunchKernelGGL(k_comp, dim3(g), dim3(BS), 0, st, f, u, ndof, nrhs, part);
+  MGCG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_comp_fin, dim3(1), dim3(BS), 0, st, part, g, nrhs, out);
   MGCG_HIP(hipGetLastError());
 }
 

@@ -44,13 +44,16 @@ struct OpEQ2 {
   const uint8_t* mask;
 };
 
-// Reduction scratch: partials[slot][block], a ticket counter per slot.
+// Reduction scratch: one partial sum per block and value, in regions that
+// stay untouched until their consumer has read them:
+//   partials[region * RED_REGION + v * MAX_BLOCKS + block], v < 8.
 struct RedBuf {
-  double* partials;  // [MAX_RED_VALUES][MAX_BLOCKS]
-  unsigned* counter; // [8]
+  double* partials;
 };
 constexpr int MAX_BLOCKS = 16384;
-constexpr int MAX_RED_VALUES = 12;
+constexpr long RED_REGION = 8L * MAX_BLOCKS;
+enum RedRegion : int { RED_PQ = 0, RED_RR = 1, RED_TR = 2, RED_INIT = 3, RED_RZ = 4, RED_COMP = 5,
+                       RED_NREGIONS = 6 };
 
 // ---------------- launchers ----------------
 // All launchers enqueue on `st`; nrhs vectors are stored back to back with
@@ -77,16 +80,20 @@ void cg_init_residual(const FineOp& A, const double* f, const double* x, double*
                       CgScalars* cs, RedBuf red, hipStream_t st);
 void cg_apply_alpha(const FineOp& A, const double* p, double* q, int nrhs, CgScalars* cs,
                     RedBuf red, hipStream_t st);
+// nbq: blocks per load case of the apply that produced the p.q partials.
 void cg_update_xr(const double* p, const double* q, double* x, double* r, long ndof, int nrhs,
-                  CgScalars* cs, RedBuf red, hipStream_t st);
+                  CgScalars* cs, RedBuf red, int nbq, hipStream_t st);
 void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
                       CgScalars* cs, RedBuf red, hipStream_t st);
 template <typename TZ>
 void cg_beta(const double* r, const double* rold, const TZ* z, long ndof, int nrhs, CgScalars* cs,
              RedBuf red, hipStream_t st);
+// nbz: number of r.z partials per load case (cg_beta_blocks, or the blocks of
+// the finest-level fused Jacobi sweep).
 template <typename TZ>
 void cg_update_p(const TZ* z, double* p, const double* r, double* rold, long ndof, int nrhs,
-                 const CgScalars* cs, hipStream_t st);
+                 CgScalars* cs, RedBuf red, int nbz, hipStream_t st);
+int cg_beta_blocks(long ndof);
 
 // V-cycle level kernels in precision T (gated by any active CG state; cs may be null).
 struct VLevelArgs;  // fwd
@@ -100,15 +107,19 @@ struct VOps {
   const uint8_t* mask;
   Lat L;
 };
-// x = omega invD b; r = b - A x (the first pre-smoothing sweep from zero, fused
-// with the residual).
+// Level-0 V-cycle input: b0 = r in precision T (b0 may be null when T is
+// FP64 and r serves directly) and x0 = W D^-1 b0 (first sweep from zero).
 template <typename T>
-void v_presmooth_residual(const VOps<T>& v, const T* b, T* x, T* r, T omega, int nrhs,
-                          const CgScalars* cs, hipStream_t st);
+void v_prepare0(const double* r, T* b0, const T* wD, T* x0, long ndof, int nrhs,
+                const CgScalars* cs, hipStream_t st);
 // xo = x + omega invD (b - A x)
 template <typename T>
 void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs,
               const CgScalars* cs, hipStream_t st);
+// xo = x + wD (b - A x) and the CG partials r.z, r_old.z of xo (= z)
+template <typename T>
+void v_jacobi_dot(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, const double* r,
+                  const double* rold, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st);
 // r = b - A x
 template <typename T>
 void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const CgScalars* cs,
@@ -117,10 +128,11 @@ void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const 
 template <typename T>
 void v_smooth0(const T* b, const T* invD, T* x, T omega, long ndof, int nrhs, const CgScalars* cs,
                hipStream_t st);
-// coarse = P~^T fine
+// coarse = P~^T fine; when xc is given also xc = wDc * coarse (the coarse
+// level's first smoothing sweep from zero)
 template <typename T>
 void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* rf,
-                T* bc, int nrhs, const CgScalars* cs, hipStream_t st);
+                T* bc, const T* wDc, T* xc, int nrhs, const CgScalars* cs, hipStream_t st);
 // fine += P~ coarse  (accumulate=false: fine = P~ coarse)
 template <typename T>
 void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* ec,
@@ -135,6 +147,35 @@ void mask_copy(const double* x, double* xm, const uint8_t* mask, long nn, int nr
 // Identity rows: y_i = x_i on fixed DOFs.
 void identity_rows(const double* x, double* y, const uint8_t* mask, long nn, int nrhs,
                    hipStream_t st);
+
+// The V-cycle below a small level lt, in one workgroup (levels lt..L-1,
+// barriers instead of kernel launches).  Entry: b and x = W D^-1 b of level
+// lt; exit: x of level lt after the coarse correction and post-smoothing
+// (in x when `post` is even, else in xalt).
+constexpr int TAIL_MAX = 8;
+template <typename T>
+struct TailLevel {
+  Lat L;
+  const T* coef;    // stencil (all tail levels but the coarsest)
+  const T* wD;
+  const uint8_t* mask;
+  T* b;
+  T* x;
+  T* xalt;
+  T* r;
+};
+template <typename T>
+struct TailArgs {
+  int nlev;  // levels in the tail, the last one is the coarsest
+  TailLevel<T> lv[TAIL_MAX];
+  const double* Ainv;
+  const int* freedof;
+  int nc;
+  int pre, post;
+  int nrhs;
+};
+template <typename T>
+void v_tail(const TailArgs<T>& a, const CgScalars* cs, hipStream_t st);
 
 // Type conversions and fills.
 template <typename TA, typename TB>
@@ -154,8 +195,17 @@ void setup_effective(int order, int nsub, int nelx, int nely, int nelz, const do
 //  src kind OP_MF_Q1: children are E_c * K0 (child mask applied here);
 //  OP_ST27 (Q1-type elements with stored matrices Kc [nel_f][576], masks baked or applied);
 //  OP_EQ2: each coarse element is one quadratic fine element (81x81 -> 24x24).
+// elist (optional): ids of the coarse elements to compute (count n_elist);
+// null computes all of them.
 void setup_galerkin(int src_kind, Lat fine, const double* E, const double* K0, const double* Kc,
-                    const uint8_t* mask_f, int ncx, int ncy, int ncz, double* KE, hipStream_t st);
+                    const uint8_t* mask_f, int ncx, int ncy, int ncz, double* KE,
+                    const int* elist, int n_elist, hipStream_t st);
+// First coarse level as a linear combination of precomputed matrices:
+// KE[e] = sum_m E[dens(e, m)] G[m], m over the B^3 density cells of a coarse
+// element (B = 2 nsub for trilinear children, nsub for one quadratic
+// element); valid where no child DOF is supported.
+void setup_galerkin_lin(const double* E, const double* G, int B, int nsub, int nelx, int nely,
+                        int ncx, int ncy, int ncz, double* KE, hipStream_t st);
 // Assemble Q1-type element matrices into the half stencil, with the supports
 // of mask baked in, plus the Jacobi data wD_i = min(omega, theta A_ii /
 // sum_j |A_ij|) / A_ii (0 on fixed DOFs) and the plain diagonal.

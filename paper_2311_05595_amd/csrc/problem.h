@@ -98,12 +98,15 @@ class Problem {
   double last_setup_ms() const { return setup_ms_; }
 
  private:
-  template <typename T> void vcycle(const double* r_in, int gate);
+  template <typename T> void vcycle(const double* r_in, int gate, bool fuse_dot);
+  void precondition_and_direction();
   template <typename T> VOps<T> vops(int level) const;
   template <typename T> void do_set_densities();
   template <typename T> void do_apply_v(int level, const double* x, double* y);
   void iteration();
+  void build_linear_galerkin();
   FineOp fine_op() const;
+  int nblocks_fine() const;
   void sync();
   void check_bad(int which);
   void timed_begin(int id);
@@ -119,6 +122,9 @@ class Problem {
   std::vector<double> hf_;
   std::vector<double> hKsub_;
   std::vector<int> hfree_;      // coarsest free DOF list
+  std::vector<double> hG_;      // linear Galerkin matrices of the first coarse level [M][576]
+  std::vector<int> hmasked_;    // first-coarse-level elements with supported child DOFs
+  int gB_ = 0;                  // density cells per axis of a first-level coarse element
   std::vector<int> hdofpos_;
 
   hipStream_t stream_ = nullptr;
@@ -141,12 +147,14 @@ class Problem {
   float* Keff32_ = nullptr;  // EQ2 mixed copy
   double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr, *rold_ = nullptr;
   CgScalars* cs_ = nullptr;
-  RedBuf red_{nullptr, nullptr};
+  RedBuf red_{nullptr};
   double* compout_ = nullptr;
   int* bad_ = nullptr;
   int* dfree_ = nullptr;
   int* ddofpos_ = nullptr;
   double *Ad_ = nullptr, *Linv_ = nullptr, *Ainv_ = nullptr;
+  double* G_ = nullptr;
+  int* dmasked_ = nullptr;
   double* tmp64_ = nullptr;  // [nrhs][ndof0] scratch for inspection
   double* dcbuf_ = nullptr;  // [n_rho] sensitivity staging for host output
   void* zbuf_ = nullptr;     // level-0 V-cycle output of the last cycle

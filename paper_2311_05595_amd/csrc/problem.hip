@@ -17,6 +17,10 @@ namespace {
 // Gershgorin cap of the per-DOF Jacobi weights (every row sum of W D^-1 A
 // stays below 2, so the smoother converges for any densities).
 constexpr double kTheta = 1.9;
+// Levels with at most this many nodes run in the single-workgroup tail (0:
+// only the coarsest solve; one CU is latency-bound on the small levels, so
+// separate kernels are faster on this hierarchy).
+constexpr long kTailNodes = 0;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -111,8 +115,7 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   TAKE(rold_, double, R * nd0);
   TAKE(tmp64_, double, R * nd0);
   TAKE(cs_, CgScalars, 4);
-  TAKE(red_.partials, double, (size_t)MAX_RED_VALUES * MAX_BLOCKS);
-  TAKE(red_.counter, unsigned, 16);
+  TAKE(red_.partials, double, (size_t)RED_NREGIONS * RED_REGION);
   TAKE(compout_, double, 16);
   TAKE(bad_, int, 4);
   TAKE(dcbuf_, double, nrho);
@@ -159,6 +162,11 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
     if (b) b->xb = cv;
     take_to(cv, char{}, R * nd * vb);
     if (b) b->r = cv;
+  }
+  if (L >= 2) {
+    const int B = d.order == 2 ? d.nsub : 2 * d.nsub;
+    TAKE(G_, double, (size_t)B * B * B * 576);
+    TAKE(dmasked_, int, (long)lv[1].ncx * lv[1].ncy * lv[1].ncz);
   }
   const long ndc = lv[L - 1].L.ndof();  // upper bound of the coarsest free DOFs
   TAKE(dfree_, int, ndc);
@@ -226,6 +234,7 @@ Problem::Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int d
   nc_ = (int)hfree_.size();
   hKsub_ = sub_element_matrices(d_.order, d_.nsub, d_.nu);
   B_.resize(lv_.size());
+  if (lv_.size() >= 2) build_linear_galerkin();
   // unit trilinear element as 10 class values; must reproduce the quadrature
   {
     const double nu = d_.nu;
@@ -312,6 +321,12 @@ void Problem::allocate() {
     MGCG_HIP(hipMemcpyAsync(K0_, k0.data(), 576 * sizeof(double), hipMemcpyHostToDevice, stream_));
     if (K032_) convert<double, float>(K0_, K032_, 576, stream_);
   }
+  if (G_) {
+    MGCG_HIP(hipMemcpyAsync(G_, hG_.data(), hG_.size() * sizeof(double), hipMemcpyHostToDevice, stream_));
+    if (!hmasked_.empty())
+      MGCG_HIP(hipMemcpyAsync(dmasked_, hmasked_.data(), hmasked_.size() * sizeof(int),
+                              hipMemcpyHostToDevice, stream_));
+  }
   if (nc_ > 0) {
     MGCG_HIP(hipMemcpyAsync(dfree_, hfree_.data(), hfree_.size() * sizeof(int), hipMemcpyHostToDevice,
                             stream_));
@@ -325,6 +340,74 @@ void Problem::allocate() {
 void Problem::sync() { MGCG_HIP(hipStreamSynchronize(stream_)); }
 
 // ------------------------------------------------------------------ operators
+// First coarse level as K_E = sum_m E_m G_m: G_m = P^T K^(e_s) P for the
+// density cell m of the coarse element (child c, sub-element s), where P
+// interpolates the coarse element's 8 vertices trilinearly onto the child's
+// nodes (Sec. 2.3).  Elements with a supported child DOF are listed for the
+// explicit masked product.
+void Problem::build_linear_galerkin() {
+  const int n = d_.nsub, p = d_.order;
+  const bool q2 = p == 2;
+  const int B = q2 ? n : 2 * n;
+  gB_ = B;
+  const int p1 = p + 1, nen = p1 * p1 * p1, nd = 3 * nen;
+  const int M = B * B * B;
+  hG_.assign((size_t)M * 576, 0.0);
+  std::vector<double> W((size_t)nen * 8);
+  for (int m = 0; m < M; ++m) {
+    const int px = m % B, py = (m / B) % B, pz = m / (B * B);
+    const int cx = q2 ? 0 : px / n, cy = q2 ? 0 : py / n, cz = q2 ? 0 : pz / n;
+    const int sx = q2 ? px : px % n, sy = q2 ? py : py % n, sz = q2 ? pz : pz % n;
+    const double* K = &hKsub_[(size_t)(sx + n * (sy + n * sz)) * nd * nd];
+    for (int a = 0; a < nen; ++a) {
+      const int ax = a % p1, ay = (a / p1) % p1, az = a / (p1 * p1);
+      for (int b = 0; b < 8; ++b)
+        W[(size_t)a * 8 + b] = q2 ? trilinear_weight(ax, ay, az, b)
+                                  : trilinear_weight(cx + ax, cy + ay, cz + az, b);
+    }
+    double* G = &hG_[(size_t)m * 576];
+    for (int b = 0; b < 8; ++b)
+      for (int i = 0; i < 3; ++i)
+        for (int b2 = 0; b2 < 8; ++b2)
+          for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int a = 0; a < nen; ++a) {
+              const double wa = W[(size_t)a * 8 + b];
+              if (wa == 0.0) continue;
+              for (int a2 = 0; a2 < nen; ++a2) {
+                const double wb = W[(size_t)a2 * 8 + b2];
+                if (wb == 0.0) continue;
+                s += wa * K[(size_t)(3 * a + i) * nd + 3 * a2 + j] * wb;
+              }
+            }
+            G[(3 * b + i) * 24 + 3 * b2 + j] = s;
+          }
+  }
+  // coarse elements whose fine nodes (lattice 2E..2E+2) carry a support
+  const Lat F = lv_[0].L;
+  const LevelPlan& c1 = lv_[1];
+  hmasked_.clear();
+  for (int EZ = 0; EZ < c1.ncz; ++EZ)
+    for (int EY = 0; EY < c1.ncy; ++EY)
+      for (int EX = 0; EX < c1.ncx; ++EX) {
+        bool any = false;
+        for (int dz = 0; dz <= 2 && !any; ++dz)
+          for (int dy = 0; dy <= 2 && !any; ++dy)
+            for (int dx = 0; dx <= 2 && !any; ++dx) {
+              const long fn = (2 * EX + dx) + (long)F.nx * ((2 * EY + dy) + (long)F.ny * (2 * EZ + dz));
+              if (hmask_[fn]) any = true;
+            }
+        if (any) hmasked_.push_back(EX + c1.ncx * (EY + c1.ncy * EZ));
+      }
+}
+
+// Blocks per load case of the finest-level apply (the number of per-block
+// partial sums its reducing epilogues produce).
+int Problem::nblocks_fine() const {
+  const long nn = lv_[0].L.nn();
+  return (int)(lv_[0].kind == OP_ST27 ? (nn + 63) / 64 : (nn + 255) / 256);
+}
+
 FineOp Problem::fine_op() const {
   FineOp A{};
   A.kind = lv_[0].kind;
@@ -427,8 +510,15 @@ void Problem::do_set_densities() {
   for (int l = 1; l < L; ++l) {
     const int src = (l == 1) ? lv_[0].kind : OP_ST27;
     const double* Kc = (l == 1) ? Keff_ : B_[l - 1].KE;
-    setup_galerkin(src, lv_[l - 1].L, E_, K0_, Kc, B_[l - 1].mask, lv_[l].ncx, lv_[l].ncy, lv_[l].ncz,
-                   B_[l].KE, st);
+    if (l == 1) {
+      setup_galerkin_lin(E_, G_, gB_, d_.nsub, d_.nelx, d_.nely, lv_[1].ncx, lv_[1].ncy, lv_[1].ncz,
+                         B_[1].KE, st);
+      setup_galerkin(src, lv_[0].L, E_, K0_, Kc, B_[0].mask, lv_[1].ncx, lv_[1].ncy, lv_[1].ncz,
+                     B_[1].KE, dmasked_, (int)hmasked_.size(), st);
+    } else {
+      setup_galerkin(src, lv_[l - 1].L, E_, K0_, Kc, B_[l - 1].mask, lv_[l].ncx, lv_[l].ncy,
+                     lv_[l].ncz, B_[l].KE, nullptr, 0, st);
+    }
     setup_stencil<T>(lv_[l].L, B_[l].KE, B_[l].mask, (T*)B_[l].coefV, (T*)B_[l].invD, B_[l].diag64,
                      d_.omega, kTheta, st);
   }
@@ -442,7 +532,7 @@ void Problem::do_set_densities() {
 
 // ------------------------------------------------------------------ V-cycle
 template <typename T>
-void Problem::vcycle(const double* r_in, int gate) {
+void Problem::vcycle(const double* r_in, int gate, bool fuse_dot) {
   hipStream_t st = stream_;
   const CgScalars* cs = gate ? cs_ : nullptr;
   const int L = (int)lv_.size();
@@ -452,7 +542,6 @@ void Problem::vcycle(const double* r_in, int gate) {
   if constexpr (sizeof(T) == 8) {
     b0 = (const T*)r_in;
   } else {
-    convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
     b0 = (const T*)B_[0].b;
   }
   std::vector<T*> cur(L), oth(L);
@@ -463,30 +552,65 @@ void Problem::vcycle(const double* r_in, int gate) {
     oth[l] = (T*)B_[l].xb;
     if (l > 0) bl[l] = (const T*)B_[l].b;
   }
-  for (int l = 0; l < L - 1; ++l) {
+  // level-0 input and its first sweep from zero (the coarse levels get theirs
+  // from the restriction)
+  if (L > 1)
+    v_prepare0<T>(r_in, sizeof(T) == 8 ? nullptr : (T*)B_[0].b, (const T*)B_[0].invD, cur[0],
+                  lv_[0].L.ndof(), R, cs, st);
+  else if constexpr (sizeof(T) == 4)
+    convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
+  // levels at and below lt run inside one workgroup (the "tail")
+  int lt = L;
+  for (int l = 1; l < L; ++l)
+    if (lv_[l].L.nn() <= kTailNodes) {
+      lt = l;
+      break;
+    }
+  if (lt == L && L > 1) lt = L - 1;  // at least the coarsest solve
+  for (int l = 0; l < std::min(lt, L - 1); ++l) {
     const VOps<T> v = vops<T>(l);
     T* rl = (T*)B_[l].r;
-    if (d_.pre == 1) {
-      if (l == 0) timed_begin(1);
-      v_presmooth_residual<T>(v, bl[l], cur[l], rl, omega, R, cs, st);
-      if (l == 0) timed_end(1);
-    } else {
-      v_smooth0<T>(bl[l], (const T*)B_[l].invD, cur[l], omega, lv_[l].L.ndof(), R, cs, st);
-      for (int s = 1; s < d_.pre; ++s) {
-        v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
-        std::swap(cur[l], oth[l]);
-      }
-      v_residual<T>(v, bl[l], cur[l], rl, R, cs, st);
+    for (int s = 1; s < d_.pre; ++s) {
+      v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
+      std::swap(cur[l], oth[l]);
     }
-    v_restrict<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, rl, (T*)B_[l + 1].b, R, cs, st);
+    if (l == 0) timed_begin(1);
+    v_residual<T>(v, bl[l], cur[l], rl, R, cs, st);
+    if (l == 0) timed_end(1);
+    const bool coarsest_next = (l + 1 == L - 1);
+    v_restrict<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, rl, (T*)B_[l + 1].b,
+                  (const T*)B_[l + 1].invD, coarsest_next ? nullptr : cur[l + 1], R, cs, st);
   }
-  v_coarse_solve<T>(Ainv_, dfree_, nc_, lv_[L - 1].L.ndof(), bl[L - 1], cur[L - 1], R, cs, st);
-  for (int l = L - 2; l >= 0; --l) {
+  if (L == 1 || lt == L - 1) {
+    v_coarse_solve<T>(Ainv_, dfree_, nc_, lv_[L - 1].L.ndof(), bl[L - 1], cur[L - 1], R, cs, st);
+  } else {
+    TailArgs<T> ta{};
+    ta.nlev = L - lt;
+    if (ta.nlev > TAIL_MAX) throw Error(MGCG_EINVAL, "too many small levels");
+    for (int q = 0; q < ta.nlev; ++q) {
+      const int l = lt + q;
+      ta.lv[q] = TailLevel<T>{lv_[l].L, (const T*)B_[l].coefV, (const T*)B_[l].invD, B_[l].mask,
+                              (T*)B_[l].b, cur[l], oth[l], (T*)B_[l].r};
+    }
+    ta.Ainv = Ainv_;
+    ta.freedof = dfree_;
+    ta.nc = nc_;
+    ta.pre = d_.pre;
+    ta.post = d_.post;
+    ta.nrhs = R;
+    v_tail<T>(ta, cs, st);
+    // the tail's pre/post sweeps ping-pong the finest tail level's buffers
+    if ((d_.pre - 1 + d_.post) % 2 == 1 && lt < L - 1) std::swap(cur[lt], oth[lt]);
+  }
+  for (int l = std::min(lt, L - 1) - 1; l >= 0; --l) {
     const VOps<T> v = vops<T>(l);
     v_prolong<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, cur[l + 1], cur[l], R, true, cs, st);
     for (int s = 0; s < d_.post; ++s) {
       if (l == 0) timed_begin(2);
-      v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
+      if (l == 0 && fuse_dot && s == d_.post - 1)
+        v_jacobi_dot<T>(v, bl[l], cur[l], oth[l], omega, r_in, rold_, R, cs, red_, st);
+      else
+        v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
       if (l == 0) timed_end(2);
       std::swap(cur[l], oth[l]);
     }
@@ -495,6 +619,26 @@ void Problem::vcycle(const double* r_in, int gate) {
 }
 
 // ------------------------------------------------------------------ PCG
+// z = M r, then the new search direction p = z + beta p.  With a post-smoothing
+// sweep on a multilevel hierarchy the r.z products come fused out of the last
+// finest-level sweep; otherwise a separate dot kernel computes them.
+void Problem::precondition_and_direction() {
+  hipStream_t st = stream_;
+  const long nd = lv_[0].L.ndof();
+  const int R = d_.nrhs;
+  const bool fuse = d_.post >= 1 && lv_.size() > 1;
+  const int nbz = fuse ? nblocks_fine() : cg_beta_blocks(nd);
+  if (vbytes_ == 8) {
+    vcycle<double>(r_, 1, fuse);
+    if (!fuse) cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<double>((const double*)zbuf_, p_, r_, rold_, nd, R, cs_, red_, nbz, st);
+  } else {
+    vcycle<float>(r_, 1, fuse);
+    if (!fuse) cg_beta<float>(r_, rold_, (const float*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<float>((const float*)zbuf_, p_, r_, rold_, nd, R, cs_, red_, nbz, st);
+  }
+}
+
 void Problem::iteration() {
   hipStream_t st = stream_;
   const FineOp A = fine_op();
@@ -503,17 +647,9 @@ void Problem::iteration() {
   timed_begin(0);
   cg_apply_alpha(A, p_, q_, R, cs_, red_, st);
   timed_end(0);
-  cg_update_xr(p_, q_, x_, r_, nd, R, cs_, red_, st);
+  cg_update_xr(p_, q_, x_, r_, nd, R, cs_, red_, nblocks_fine(), st);
   cg_true_residual(A, f_, x_, r_, R, cs_, red_, st);
-  if (vbytes_ == 8) {
-    vcycle<double>(r_, 1);
-    cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
-    cg_update_p<double>((const double*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
-  } else {
-    vcycle<float>(r_, 1);
-    cg_beta<float>(r_, rold_, (const float*)zbuf_, nd, R, cs_, red_, st);
-    cg_update_p<float>((const float*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
-  }
+  precondition_and_direction();
   ++iter_launched_;
 }
 
@@ -535,15 +671,7 @@ void Problem::solve_begin(double rtol, int maxit, bool warm) {
   fill<double>(rold_, 0.0, R * nd, st);
   iter_launched_ = -1;
   timer_used_base_ = timer_.used;
-  if (vbytes_ == 8) {
-    vcycle<double>(r_, 1);
-    cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
-    cg_update_p<double>((const double*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
-  } else {
-    vcycle<float>(r_, 1);
-    cg_beta<float>(r_, rold_, (const float*)zbuf_, nd, R, cs_, red_, st);
-    cg_update_p<float>((const float*)zbuf_, p_, r_, rold_, nd, R, cs_, st);
-  }
+  precondition_and_direction();
   iter_launched_ = 0;
   first_chunk_ = true;
   // read the initial state
@@ -817,6 +945,7 @@ void Problem::restrict_(int level, const double* f, double* c, int mem) {
   to_dev(f, fraw, nf, mem, stream_);
   mask_copy(fraw, fd, B_[level].mask, lv_[level].L.nn(), d_.nrhs, stream_);
   v_restrict<double>(lv_[level].L, lv_[level + 1].L, B_[level].mask, B_[level + 1].mask, fd, cd,
+                     nullptr, nullptr,
                      d_.nrhs, nullptr, stream_);
   from_dev(cd, c, ncd, mem, stream_);
   sync();
@@ -843,10 +972,10 @@ void Problem::precondition(const double* r, double* z, int mem) {
   const long n = (long)d_.nrhs * lv_[0].L.ndof();
   to_dev(r, tmp64_, n, mem, stream_);
   if (vbytes_ == 8) {
-    vcycle<double>(tmp64_, 0);
+    vcycle<double>(tmp64_, 0, false);
     from_dev((const double*)zbuf_, z, n, mem, stream_);
   } else {
-    vcycle<float>(tmp64_, 0);
+    vcycle<float>(tmp64_, 0, false);
     DevTmp tmp;
     double* zd = tmp.get<double>(n);
     convert<float, double>((const float*)zbuf_, zd, n, stream_);

@@ -9,9 +9,12 @@ fields are generated and uploaded before timing; steps cycle through them.
 
 Prints one JSON line (see the fields below).  `--config c3|c4` times the
 other single-GPU workloads the same way (not the default line).
+`--copy-probe MIB` only runs the library's plain copy kernel on MIB MiB
+(the calibration run for the HBM byte counters) and exits.
 """
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -31,6 +34,61 @@ PEAK_FP64_TFLOPS = 78.6
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# Sources that make up the finest-level apply kernel; the committed HBM
+# traffic figure is reported only while they are unchanged.
+KERNEL_SOURCES = ["k_apply.hip", "kernels.h", "devutil.h", "common.h", "q1table.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mf_q1_apply_cantilever_96x48x48.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_05595_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic():
+    """HBM bytes per launch of the finest-level apply from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    the summary is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    import torch
+    import workloads as W
+    from paper_2311_05595_amd import api
+    n = mib * 1024 * 1024
+    dev = torch.device("cuda:0")
+    a = torch.ones(n // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    mask, f = W.make_problem("cantilever", 4, 2, 2, 1, 1)
+    prob = api.Problem((4, 2, 2), mask, f, nlevels=1)
+    prob.use_torch_stream()
+    for _ in range(5):
+        prob.copy_bytes(a.data_ptr(), b.data_ptr(), n)
+    torch.cuda.synchronize()
+    assert bool((b == 1).all())
+    prob.close()
+    print(json.dumps({"copy_probe_bytes": n, "launches": 5}), flush=True)
 
 
 def fine_apply_work(nel, nsub, order, nrhs=1):
@@ -159,7 +217,7 @@ def run(args):
     achieved = flops / avg_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": None,
+                "traffic": committed_traffic(),
                 "kernel": "finest-level CG apply q = A p (matrix-free trilinear, FP64)",
                 "avg_us": round(avg_s * 1e6, 3), "launches": kn,
                 "alg_flop_per_launch": flops, "alg_bytes_per_launch": bytes_,
@@ -202,7 +260,11 @@ def main():
     ap.add_argument("--maxit", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     run(args)
 
 

@@ -46,6 +46,36 @@ __host__ __device__ constexpr Off3 st_offset(int b) {
   return tab[b];
 }
 
+// The same table for a run-time (wave-uniform) block index, decoded from two
+// immediates instead of a table in memory: 6-bit codes (dx+1, dy+1, dz+1 as
+// 2-bit fields), built from st_offset.
+__host__ __device__ constexpr unsigned long long st_pack(int first, int count) {
+  unsigned long long v = 0;
+  for (int b = 0; b < count; ++b) {
+    const Off3 d = st_offset(first + b);
+    const unsigned long long code =
+        (unsigned long long)((d.dx + 1) | ((d.dy + 1) << 2) | ((d.dz + 1) << 4));
+    v |= code << (6 * b);
+  }
+  return v;
+}
+
+__host__ __device__ constexpr Off3 st_offset_rt(int b) {
+  constexpr unsigned long long lo = st_pack(0, 10), hi = st_pack(10, ST_BLOCKS - 10);
+  const unsigned code = b < 10 ? (unsigned)((lo >> (6 * b)) & 63ull)
+                               : (unsigned)((hi >> (6 * (b - 10))) & 63ull);
+  return Off3{(int)(code & 3) - 1, (int)((code >> 2) & 3) - 1, (int)((code >> 4) & 3) - 1};
+}
+
+constexpr bool st_tables_agree() {
+  for (int b = 0; b < ST_BLOCKS; ++b) {
+    const Off3 a = st_offset(b), r = st_offset_rt(b);
+    if (a.dx != r.dx || a.dy != r.dy || a.dz != r.dz) return false;
+  }
+  return true;
+}
+static_assert(st_tables_agree(), "packed stencil offset table");
+
 // Per load case CG scalars and state, resident on the device.
 enum CgState : int { CG_ACTIVE = 0, CG_CHECK = 1, CG_DONE = 2, CG_BREAKDOWN = 3, CG_MAXIT = 4 };
 

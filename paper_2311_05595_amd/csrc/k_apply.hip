@@ -229,7 +229,10 @@ __device__ __forceinline__ void ax_st(const OpST<T>& op, const In& in, int r, in
 }
 
 // The blocks b = part, part + LPN, ... of the stencil apply (partial sum of
-// one node's rows).
+// one node's rows).  `part` is wave-uniform, so every coefficient row offset
+// is a scalar.  The loop has no branches: a block index past the table (and
+// the transpose of the diagonal block) reads through out-of-range offsets,
+// which return 0, so all of a wave's loads can be in flight together.
 template <int LPN, typename T, class In>
 __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int r, int i, int j,
                                            int k, long node, int part, T y[3]) {
@@ -242,26 +245,28 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
   T acc[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int q = 0; q < (ST_BLOCKS + LPN - 1) / LPN; ++q) {
-    const int b = part + q * LPN;
-    if (b >= ST_BLOCKS) break;
-    const Off3 d = st_offset(b);
+    const int b0 = part + q * LPN;
+    const bool valid = b0 < ST_BLOCKS;
+    const int b = valid ? b0 : 0;
+    const Off3 d = st_offset_rt(b);
     {
       const int ii = i + d.dx, jj = j + d.dy, kk = k + d.dz;
-      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
+      const bool ok = valid && (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
                       (unsigned)kk < (unsigned)L.nz;
       const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T)) : kBufOOB;
+      const int co = ok ? vself : kBufOOB;
       T v[3];
       xb.load(xo, v);
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int e = 0; e < 3; ++e)
-          acc[c] = fma(bload<T>(rc, vself, (b * 9 + 3 * c + e) * row), v[e], acc[c]);
+          acc[c] = fma(bload<T>(rc, co, (b * 9 + 3 * c + e) * row), v[e], acc[c]);
     }
-    if (b > 0) {
+    {
       const int ii = i - d.dx, jj = j - d.dy, kk = k - d.dz;
-      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
-                      (unsigned)kk < (unsigned)L.nz;
+      const bool ok = valid && b > 0 && (unsigned)ii < (unsigned)L.nx &&
+                      (unsigned)jj < (unsigned)L.ny && (unsigned)kk < (unsigned)L.nz;
       const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
       const int xo = ok ? (int)(nb * 3 * sizeof(T)) : kBufOOB;
       const int co = ok ? (int)(nb * sizeof(T)) : kBufOOB;
@@ -547,7 +552,11 @@ __global__ __launch_bounds__(BS) void k_apply_st(OpST<T> op, In in, Ep ep, int n
                                                  double* part) {
   if (gate && !any_state(gate, nrhs, gate_state)) return;
   __shared__ T red[ST_LPN - 1][3][ST_NODES];
-  const int wave = threadIdx.x / ST_NODES, lane = threadIdx.x % ST_NODES;
+  // the wave index must be provably uniform: it selects the coefficient
+  // rows through the scalar offset of every buffer load (a divergent value
+  // there turns each load into a serialised readfirstlane loop)
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / ST_NODES);
+  const int lane = threadIdx.x % ST_NODES;
   const long node = (long)blockIdx.x * ST_NODES + lane;
   const int r = blockIdx.y;
   double a0 = 0.0, a1 = 0.0;

@@ -22,6 +22,11 @@ struct Error : std::runtime_error {
       throw ::mgcg::Error(-5, std::string(#call) + ": " + hipGetErrorString(e_));           \
   } while (0)
 
+// Device buffers are read through 32-bit buffer offsets; an offset at or
+// past this value marks "outside" (the load returns 0), so no buffer that a
+// kernel addresses this way may reach it.
+constexpr long kMaxBufferBytes = 0x7FFF0000;
+
 // Operator kinds of a multigrid level.
 enum OpKind : int {
   OP_MF_Q1 = 0,  // matrix-free trilinear elements: y = sum_e E_e K0 u_e (one density per element)

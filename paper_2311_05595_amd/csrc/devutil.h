@@ -10,7 +10,7 @@ constexpr int BS = 256;  // threads per block of the node-parallel kernels
 // ---- buffer loads: one VGPR byte offset shared by many loads, a scalar
 // offset per load, and hardware bounds checks (an offset past the buffer
 // returns 0).  Word 3 of the resource: raw (untyped) 32-bit dword access.
-constexpr int kBufOOB = 0x7FFF0000;  // voffset marking "outside": loads return 0
+constexpr int kBufOOB = (int)kMaxBufferBytes;  // voffset marking "outside": loads return 0
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, size_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
@@ -41,10 +41,21 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Deterministic block-wide sum of p[0..n) (fixed order for a fixed n);
 // every thread receives the result.  sh: BS/64 doubles of shared memory.
+// Four independent buffer loads per thread and pass (reads past n return 0),
+// so a few hundred partials cost one memory round trip.
 __device__ __forceinline__ double block_sum(const double* __restrict__ p, int n, double* sh) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(p, (size_t)n * sizeof(double));
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += BS) s += p[i];
+  for (int b = 0; b < n; b += 4 * BS) {
+    const int o = (b + (int)threadIdx.x) * (int)sizeof(double);
+    // (the whole offset in the vector operand: the range check covers it)
+    const double v0 = bload<double>(rp, o, 0);
+    const double v1 = bload<double>(rp, o + BS * 8, 0);
+    const double v2 = bload<double>(rp, o + 2 * BS * 8, 0);
+    const double v3 = bload<double>(rp, o + 3 * BS * 8, 0);
+    s += (v0 + v1) + (v2 + v3);
+  }
   s = wave_sum(s);
   if (lane == 0) sh[wid] = s;
   __syncthreads();
@@ -104,12 +115,15 @@ __device__ __forceinline__ bool any_state(const CgScalars* cs, int nrhs, int sta
 
 inline int nblocks(long n, int per = BS) { return (int)((n + per - 1) / per); }
 
-// Grid for grid-stride vector kernels: at most 512 blocks (two per CU), so
-// that the per-block partial sums stay few for the kernels that re-sum them.
+// Vector kernels: each thread handles VU elements i0 + k BS (k < VU) per
+// pass, loads first; the grid is at most 1024 blocks (four per CU), so the
+// per-block partial sums stay few for the kernels that re-sum them, and a
+// level-0 vector of up to 1M entries takes one pass.
+constexpr int VU = 4;
 inline int vec_grid(long n) {
-  long b = (n + BS - 1) / BS;
+  long b = (n + (long)BS * VU - 1) / ((long)BS * VU);
   if (b < 1) b = 1;
-  if (b > 512) b = 512;
+  if (b > 1024) b = 1024;
   return (int)b;
 }
 

@@ -68,10 +68,14 @@ struct InScaledB {
 
 // ------------------------------------------------------------ operators
 __device__ __forceinline__ void node_ijk(long node, const Lat& L, int& i, int& j, int& k) {
-  i = (int)(node % L.nx);
-  long t = node / L.nx;
-  j = (int)(t % L.ny);
-  k = (int)(t / L.ny);
+  // 32-bit divisions: node counts are bounded far below 2^32 by the buffer
+  // offsets (see Problem::Problem)
+  const unsigned n = (unsigned)node, nx = (unsigned)L.nx, ny = (unsigned)L.ny;
+  const unsigned t = n / nx;
+  i = (int)(n - t * nx);
+  const unsigned kk = t / ny;
+  j = (int)(t - kk * ny);
+  k = (int)kk;
 }
 
 // Matrix-free trilinear apply at node (i,j,k): the three rows of
@@ -239,7 +243,6 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
   const Lat L = op.L;
   const long nn = L.nn();
   const auto xb = in.buf(r);
-  const __amdgpu_buffer_rsrc_t rc = make_rsrc(op.coef, (size_t)ST_COEF * nn * sizeof(T));
   const int row = (int)(nn * sizeof(T));
   const int vself = (int)(node * sizeof(T));
   T acc[3] = {T(0), T(0), T(0)};
@@ -249,6 +252,10 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
     const bool valid = b0 < ST_BLOCKS;
     const int b = valid ? b0 : 0;
     const Off3 d = st_offset_rt(b);
+    // the block's 9 coefficient rows (a resource per block keeps every
+    // offset below 9 rows)
+    const __amdgpu_buffer_rsrc_t rc =
+        make_rsrc(op.coef + (size_t)b * 9 * nn, (size_t)9 * nn * sizeof(T));
     {
       const int ii = i + d.dx, jj = j + d.dy, kk = k + d.dz;
       const bool ok = valid && (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
@@ -261,7 +268,7 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int e = 0; e < 3; ++e)
-          acc[c] = fma(bload<T>(rc, co, (b * 9 + 3 * c + e) * row), v[e], acc[c]);
+          acc[c] = fma(bload<T>(rc, co, (3 * c + e) * row), v[e], acc[c]);
     }
     {
       const int ii = i - d.dx, jj = j - d.dy, kk = k - d.dz;
@@ -276,7 +283,7 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int e = 0; e < 3; ++e)
-          acc[c] = fma(bload<T>(rc, co, (b * 9 + 3 * e + c) * row), v[e], acc[c]);
+          acc[c] = fma(bload<T>(rc, co, (3 * e + c) * row), v[e], acc[c]);
     }
   }
   y[0] = acc[0];
@@ -705,23 +712,48 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   __shared__ double sh[BS / 64];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const long step = (long)gridDim.x * BS * VU;
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
-    const double pq = block_sum(ppq + (size_t)rr * MAX_BLOCKS, nbq, sh);
     const int par = (cs[rr].iters + 1) & 1;
-    const double a = (pq > 0.0 && isfinite(pq)) ? cs[rr].rzs[par] / pq : 0.0;
+    const double rz = cs[rr].rzs[par];
+    const size_t o = (size_t)rr * ndof;
+    const size_t nb = (size_t)ndof * sizeof(double);
+    const __amdgpu_buffer_rsrc_t bp = make_rsrc(p + o, nb), bq = make_rsrc(q + o, nb),
+                                 bx = make_rsrc(x + o, nb), br = make_rsrc(r + o, nb);
+    double pv[VU], qv[VU], xv[VU], rv[VU];
+    auto fetch = [&](long i0) {
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        const int off = (int)((i0 + k * BS) * sizeof(double));  // past ndof: reads 0
+        pv[k] = bload<double>(bp, off, 0);
+        qv[k] = bload<double>(bq, off, 0);
+        xv[k] = bload<double>(bx, off, 0);
+        rv[k] = bload<double>(br, off, 0);
+      }
+    };
+    long i0 = (long)blockIdx.x * BS * VU + threadIdx.x;
+    fetch(i0);  // the first pass's operands travel with the partial sums
+    const double pq = block_sum(ppq + (size_t)rr * MAX_BLOCKS, nbq, sh);
+    const double a = (pq > 0.0 && isfinite(pq)) ? rz / pq : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cs[rr].pq = pq;
       cs[rr].alpha = a;
     }
-    const size_t o = (size_t)rr * ndof;
     double s = 0.0;
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
-      x[o + i] += a * p[o + i];
-      const double rn = r[o + i] - a * q[o + i];
-      r[o + i] = rn;
-      s += rn * rn;
+    for (; i0 < ndof; i0 += step) {
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        const long i = i0 + k * BS;
+        const double rn = rv[k] - a * qv[k];
+        s += rn * rn;
+        if (i < ndof) {
+          x[o + i] = xv[k] + a * pv[k];
+          r[o + i] = rn;
+        }
+      }
+      if (i0 + step < ndof) fetch(i0 + step);
     }
     acc[rr] = s;
   }
@@ -815,11 +847,25 @@ __global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
   for (int rr = 0; rr < 4; ++rr) {
     if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
     const size_t o = (size_t)rr * ndof;
+    const size_t nb = (size_t)ndof * sizeof(double);
+    const __amdgpu_buffer_rsrc_t br = make_rsrc(r + o, nb), bo = make_rsrc(rold + o, nb),
+                                 bz = make_rsrc(z + o, (size_t)ndof * sizeof(TZ));
     double s0 = 0.0, s1 = 0.0;
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
-      const double zz = (double)z[o + i];
-      s0 += r[o + i] * zz;
-      s1 += rold[o + i] * zz;
+    for (long i0 = (long)blockIdx.x * BS * VU + threadIdx.x; i0 < ndof;
+         i0 += (long)gridDim.x * BS * VU) {
+      double rv[VU], ov[VU], zv[VU];
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        const long i = i0 + k * BS;
+        rv[k] = bload<double>(br, (int)(i * sizeof(double)), 0);
+        ov[k] = bload<double>(bo, (int)(i * sizeof(double)), 0);
+        zv[k] = (double)bload<TZ>(bz, (int)(i * sizeof(TZ)), 0);
+      }
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        s0 += rv[k] * zv[k];
+        s1 += ov[k] * zv[k];
+      }
     }
     a0[rr] = s0;
     a1[rr] = s1;
@@ -855,25 +901,49 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
                                                  const double* __restrict__ part, int nbz) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   __shared__ double sh[BS / 64];
+  const long step = (long)gridDim.x * BS * VU;
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
-    const double rzn = block_sum(part + (size_t)rr * MAX_BLOCKS, nbz, sh);
-    const double rzm = block_sum(part + (size_t)(4 + rr) * MAX_BLOCKS, nbz, sh);
     const int par = cs[rr].iters & 1;
     const double rzo = cs[rr].rzs[par];
+    const bool flexible = cs[rr].flexible != 0;  // r_old only feeds the flexible beta
+    const size_t o = (size_t)rr * ndof;
+    const size_t nb = (size_t)ndof * sizeof(double);
+    const __amdgpu_buffer_rsrc_t bp = make_rsrc(p + o, nb), br = make_rsrc(r + o, nb),
+                                 bz = make_rsrc(z + o, (size_t)ndof * sizeof(TZ));
+    double pv[VU], zv[VU], rv[VU];
+    auto fetch = [&](long i0) {
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        const long i = i0 + k * BS;
+        pv[k] = bload<double>(bp, (int)(i * sizeof(double)), 0);
+        zv[k] = (double)bload<TZ>(bz, (int)(i * sizeof(TZ)), 0);
+        rv[k] = flexible ? bload<double>(br, (int)(i * sizeof(double)), 0) : 0.0;
+      }
+    };
+    long i0 = (long)blockIdx.x * BS * VU + threadIdx.x;
+    fetch(i0);
+    const double rzn = block_sum(part + (size_t)rr * MAX_BLOCKS, nbz, sh);
+    const double rzm = flexible ? block_sum(part + (size_t)(4 + rr) * MAX_BLOCKS, nbz, sh) : 0.0;
     const bool ok = isfinite(rzn) && isfinite(rzm);
-    const double num = cs[rr].flexible ? (rzn - rzm) : rzn;
+    const double num = flexible ? (rzn - rzm) : rzn;
     const double b = (!ok || rzo == 0.0) ? 0.0 : num / rzo;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cs[rr].rzs[par ^ 1] = rzn;
       cs[rr].beta = b;
       if (!ok) cs[rr].bad = 1;
     }
-    const size_t o = (size_t)rr * ndof;
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
-      p[o + i] = (double)z[o + i] + b * p[o + i];
-      rold[o + i] = r[o + i];
+    for (; i0 < ndof; i0 += step) {
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        const long i = i0 + k * BS;
+        if (i < ndof) {
+          p[o + i] = zv[k] + b * pv[k];
+          if (flexible) rold[o + i] = rv[k];
+        }
+      }
+      if (i0 + step < ndof) fetch(i0 + step);
     }
   }
 }
@@ -937,10 +1007,25 @@ __global__ __launch_bounds__(BS) void k_prepare0(const double* __restrict__ r, T
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   for (int rr = 0; rr < nrhs; ++rr) {
     const size_t o = (size_t)rr * ndof;
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
-      const T b = (T)r[o + i];
-      if (b0) b0[o + i] = b;
-      x0[o + i] = wD[i] * b;
+    const __amdgpu_buffer_rsrc_t br = make_rsrc(r + o, (size_t)ndof * sizeof(double)),
+                                 bw = make_rsrc(wD, (size_t)ndof * sizeof(T));
+    for (long i0 = (long)blockIdx.x * BS * VU + threadIdx.x; i0 < ndof;
+         i0 += (long)gridDim.x * BS * VU) {
+      T bv[VU], wv[VU];
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        const long i = i0 + k * BS;
+        bv[k] = (T)bload<double>(br, (int)(i * sizeof(double)), 0);
+        wv[k] = bload<T>(bw, (int)(i * sizeof(T)), 0);
+      }
+#pragma unroll
+      for (int k = 0; k < VU; ++k) {
+        const long i = i0 + k * BS;
+        if (i < ndof) {
+          if (b0) b0[o + i] = bv[k];
+          x0[o + i] = wv[k] * bv[k];
+        }
+      }
     }
   }
 }
@@ -987,27 +1072,32 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
   const long cnd = C.ndof();
   if (t >= cnd) return;
   const long node = t / 3;
-  const int c = (int)(t % 3);
+  const int c = (int)(t - 3 * node);
   int I, J, K;
   node_ijk(node, C, I, J, K);
-  const bool fixed = (mc[node] >> c) & 1;
   const long fnd = F.ndof();
-  for (int r = 0; r < nrhs; ++r) {
+  // byte offsets of the 27 fine neighbours (out-of-range ones read 0); no
+  // branches, so all 27 loads are issued back to back
+  int off[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int i = 2 * I + q % 3 - 1, j = 2 * J + (q / 3) % 3 - 1, k = 2 * K + q / 9 - 1;
+    const bool ok = (unsigned)i < (unsigned)F.nx && (unsigned)j < (unsigned)F.ny &&
+                    (unsigned)k < (unsigned)F.nz;
+    off[q] = ok ? (int)((3 * (i + (long)F.nx * (j + (long)F.ny * k)) + c) * sizeof(T)) : kBufOOB;
+  }
+  {
+    const int r = blockIdx.y;  // load case
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(rf + (size_t)r * fnd, (size_t)fnd * sizeof(T));
     T acc = T(0);
-    const T* src = rf + (size_t)r * fnd + c;
 #pragma unroll
-    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-      for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int i = 2 * I + dx, j = 2 * J + dy, k = 2 * K + dz;
-          if ((unsigned)i >= (unsigned)F.nx || (unsigned)j >= (unsigned)F.ny ||
-              (unsigned)k >= (unsigned)F.nz)
-            continue;
-          const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
-          acc += w * src[3 * (i + (long)F.nx * (j + (long)F.ny * k))];
-        }
+    for (int q = 0; q < 27; ++q) {
+      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+      const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+      acc = fma(w, bload<T>(rb, off[q], 0), acc);
+    }
+    // (mask read after the gathers so that all loads are in flight together)
+    const bool fixed = (mc[node] >> c) & 1;
     const T bv = fixed ? T(0) : acc;
     bc[(size_t)r * cnd + t] = bv;
     // first smoothing sweep of the coarse level from zero: x = W D^-1 b
@@ -1019,7 +1109,7 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
 template <typename T>
 void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* rf,
                 T* bc, const T* wDc, T* xc, int nrhs, const CgScalars* cs, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(coarse.ndof())), dim3(BS), 0, st, fine, coarse,
+  hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(coarse.ndof()), nrhs), dim3(BS), 0, st, fine, coarse,
                      mask_f, mask_c, rf, bc, wDc, xc, nrhs, cs);
   MGCG_HIP(hipGetLastError());
 }
@@ -1035,35 +1125,49 @@ __global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __r
   if (node >= F.nn()) return;
   int i, j, k;
   node_ijk(node, F, i, j, k);
-  const uint8_t mfn = mf[node];
   const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-  const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-  const T wi = (i & 1) ? T(0.5) : T(1), wj = (j & 1) ? T(0.5) : T(1), wk = (k & 1) ? T(0.5) : T(1);
+  const bool oi = i & 1, oj = j & 1, ok = k & 1;
+  const T w = (oi ? T(0.5) : T(1)) * (oj ? T(0.5) : T(1)) * (ok ? T(0.5) : T(1));
+  // the 8 coarse corners i0 + {0,1} x ...; a second corner only on an odd
+  // coordinate (otherwise read through an out-of-range offset, giving 0)
+  int off[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
+    const bool use = (!a || oi) && (!b || oj) && (!cc || ok);
+    off[q] = use ? (int)(3 * ((i0 + a) + (long)C.nx * ((j0 + b) + (long)C.ny * (k0 + cc))) *
+                         sizeof(T))
+                 : kBufOOB;
+  }
   const long fnd = F.ndof(), cnd = C.ndof();
-  for (int r = 0; r < nrhs; ++r) {
-    T acc[3] = {T(0), T(0), T(0)};
-    for (int c2 = 0; c2 < nk; ++c2)
-      for (int b2 = 0; b2 < nj; ++b2)
-        for (int a2 = 0; a2 < ni; ++a2) {
-          const long cn = (i0 + a2) + (long)C.nx * ((j0 + b2) + (long)C.ny * (k0 + c2));
-          const T w = wi * wj * wk;
-          const T* p = ec + (size_t)r * cnd + 3 * cn;  // vanishes on fixed coarse DOFs
+  {
+    const int r = blockIdx.y;  // load case
+    // coarse corrections vanish on fixed coarse DOFs
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(ec + (size_t)r * cnd, (size_t)cnd * sizeof(T));
+    // the old fine value (accumulate) is read branch-free together with
+    // the corners: an out-of-range offset gives 0 when overwriting
+    const __amdgpu_buffer_rsrc_t rq = make_rsrc(xf + (size_t)r * fnd, (size_t)fnd * sizeof(T));
+    T acc[3], old[3];
+    bload3<T>(rq, accumulate ? (int)(3 * node * sizeof(T)) : kBufOOB, old);
+    acc[0] = acc[1] = acc[2] = T(0);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) acc[c] += w * p[c];
-        }
-    T* q = xf + (size_t)r * fnd + 3 * node;
+    for (int q = 0; q < 8; ++q) {
+      T v[3];
+      bload3<T>(rb, off[q], v);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T v = ((mfn >> c) & 1) ? T(0) : acc[c];
-      q[c] = accumulate ? q[c] + v : v;
+      for (int c = 0; c < 3; ++c) acc[c] += v[c];
     }
+    const uint8_t mfn = mf[node];
+    T* qv = xf + (size_t)r * fnd + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) qv[c] = old[c] + (((mfn >> c) & 1) ? T(0) : w * acc[c]);
   }
 }
 
 template <typename T>
 void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* ec,
                T* xf, int nrhs, bool accumulate, const CgScalars* cs, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(fine.nn())), dim3(BS), 0, st, fine, coarse, mask_f,
+  hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(fine.nn()), nrhs), dim3(BS), 0, st, fine, coarse, mask_f,
                      mask_c, ec, xf, nrhs, accumulate ? 1 : 0, cs);
   MGCG_HIP(hipGetLastError());
 }

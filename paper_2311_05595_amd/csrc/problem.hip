@@ -82,6 +82,16 @@ void Problem::plan_levels(const mgcg_desc& d, std::vector<LevelPlan>& lv) {
     lp.ncz = cz;
     lv.push_back(lp);
   }
+  // kernels address a level vector (per load case), a stencil block's nine
+  // coefficient rows and the element moduli through 32-bit buffer offsets
+  for (const LevelPlan& l : lv) {
+    if (l.L.ndof() * 8 >= kMaxBufferBytes)
+      throw Error(MGCG_EINVAL, "mesh too large: a level vector would exceed 2 GiB");
+    if (l.kind == OP_ST27 && 9 * l.L.nn() * 8 >= kMaxBufferBytes)
+      throw Error(MGCG_EINVAL, "mesh too large: stencil coefficient rows would exceed 2 GiB");
+  }
+  if ((long)d.nelx * d.nely * d.nelz * d.nsub * d.nsub * d.nsub * 8 >= kMaxBufferBytes)
+    throw Error(MGCG_EINVAL, "mesh too large: the density field would exceed 2 GiB");
 }
 
 // One layout routine serves both the byte count and the pointer assignment.

@@ -88,6 +88,7 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
   const Lat L = op.L;
   const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
   const auto xb = in.buf(r);
+  const uint8_t mself = op.mask[i + (long)L.nx * (j + (long)L.ny * k)];
   T u[27][3];
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz)
@@ -104,7 +105,18 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
                           : kBufOOB;
         xb.load(xo, u[s]);
       }
+  // the 8 element moduli, loaded with the nodal values (elements outside
+  // the mesh read 0)
   const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
+  T Ev[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int ex = i - 1 + (o & 1), ey = j - 1 + ((o >> 1) & 1), ez = k - 1 + (o >> 2);
+    const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
+                    (unsigned)ez < (unsigned)ez1;
+    Ev[o] = bload<T>(re, ok ? (int)((ex + (long)ex1 * (ey + (long)ey1 * ez)) * sizeof(T)) : kBufOOB,
+                     0);
+  }
   T acc[3] = {T(0), T(0), T(0)};
   if constexpr (sizeof(T) == 8) {
     // FP64 (occupancy 2 either way): 24 independent accumulators (8 elements
@@ -132,26 +144,15 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
         }
     }
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-      const int ex = i - 1 + ox, ey = j - 1 + oy, ez = k - 1 + oz;
-      const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
-                      (unsigned)ez < (unsigned)ez1;
-      const T Ee = bload<T>(re, ok ? (int)((ex + (long)ex1 * (ey + (long)ey1 * ez)) * sizeof(T))
-                                   : kBufOOB, 0);
+    for (int o = 0; o < 8; ++o)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] = fma(Ee, t[o][c], acc[c]);
-    }
+      for (int c = 0; c < 3; ++c) acc[c] = fma(Ev[o], t[o][c], acc[c]);
   } else {
     // FP32: element by element keeps registers low (occupancy 8)
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
       const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-      const int ex = i - 1 + ox, ey = j - 1 + oy, ez = k - 1 + oz;
-      const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
-                      (unsigned)ez < (unsigned)ez1;
-      const T Ee = bload<T>(re, ok ? (int)((ex + (long)ex1 * (ey + (long)ey1 * ez)) * sizeof(T))
-                                   : kBufOOB, 0);
+      const T Ee = Ev[o];
       const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
       T t[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -171,7 +172,6 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
       for (int c = 0; c < 3; ++c) acc[c] = fma(Ee, t[c], acc[c]);
     }
   }
-  const uint8_t mself = op.mask[i + (long)L.nx * (j + (long)L.ny * k)];
 #pragma unroll
   for (int c = 0; c < 3; ++c) y[c] = ((mself >> c) & 1) ? T(0) : acc[c];
 }
@@ -371,13 +371,43 @@ __device__ __forceinline__ void ax_any(const OpEQ2<T>& op, const In& in, int r, 
 }
 
 // ------------------------------------------------------------ epilogues
+// pre(r, node) loads the epilogue's operands and is called before the
+// operator's gathers, so that those loads travel with them; put() then only
+// computes and stores.  (Loading them after the output store would also force
+// one round trip per value: the output may alias them.)
+template <typename T>
+struct Pre3 {
+  T v[3];
+};
+template <typename T>
+__device__ __forceinline__ Pre3<T> ld3(const T* p) {
+  return Pre3<T>{{p[0], p[1], p[2]}};
+}
+
+// Writes the V-cycle input for residual value rn of DOF i (offset oi of its
+// load case); wd is W D^-1 at DOF i in the V-cycle precision.
+__device__ __forceinline__ void vprep_put(const VPrep& vp, size_t oi, double rn, double wd) {
+  if (vp.f32) {
+    const float b = (float)rn;
+    ((float*)vp.b0)[oi] = b;
+    ((float*)vp.x0)[oi] = (float)wd * b;
+  } else {
+    ((double*)vp.x0)[oi] = wd * rn;
+  }
+}
+__device__ __forceinline__ double vprep_wd(const VPrep& vp, size_t i) {
+  return vp.f32 ? (double)((const float*)vp.wD)[i] : ((const double*)vp.wD)[i];
+}
+
 template <typename T>
 struct EpStore {
   T* y;
   long ndof;
   static constexpr bool RED = false;
+  struct Pre {};
   __device__ bool rhs_on(int) const { return true; }
-  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+  __device__ Pre pre(int, long) const { return Pre{}; }
+  __device__ void put(int r, long node, const T ax[3], const Pre&, double&, double&) const {
     T* p = y + (size_t)r * ndof + 3 * node;
     p[0] = ax[0];
     p[1] = ax[1];
@@ -391,11 +421,15 @@ struct EpResid {  // r = b - A x
   T* rout;
   long ndof;
   static constexpr bool RED = false;
+  struct Pre {
+    Pre3<T> b;
+  };
   __device__ bool rhs_on(int) const { return true; }
-  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+  __device__ Pre pre(int r, long node) const { return Pre{ld3(b + (size_t)r * ndof + 3 * node)}; }
+  __device__ void put(int r, long node, const T ax[3], const Pre& pv, double&, double&) const {
     const size_t o = (size_t)r * ndof + 3 * node;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) rout[o + c] = b[o + c] - ax[c];
+    for (int c = 0; c < 3; ++c) rout[o + c] = pv.b.v[c] - ax[c];
   }
 };
 
@@ -408,14 +442,20 @@ struct EpResidX {  // r = b - A x, x = omega invD b stored
   T* xout;
   long ndof;
   static constexpr bool RED = false;
+  struct Pre {
+    Pre3<T> b, d;
+  };
   __device__ bool rhs_on(int) const { return true; }
-  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+  __device__ Pre pre(int r, long node) const {
+    return Pre{ld3(b + (size_t)r * ndof + 3 * node), ld3(invD + 3 * node)};
+  }
+  __device__ void put(int r, long node, const T ax[3], const Pre& pv, double&, double&) const {
     const size_t o = (size_t)r * ndof + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T bb = b[o + c];
+      const T bb = pv.b.v[c];
       rout[o + c] = bb - ax[c];
-      xout[o + c] = omega * invD[3 * node + c] * bb;
+      xout[o + c] = omega * pv.d.v[c] * bb;
     }
   }
 };
@@ -429,12 +469,19 @@ struct EpJacobi {  // xo = x + wD (b - A x)  (weights folded into wD)
   T* xo;
   long ndof;
   static constexpr bool RED = false;
+  struct Pre {
+    Pre3<T> b, x, d;
+  };
   __device__ bool rhs_on(int) const { return true; }
-  __device__ void put(int r, long node, const T ax[3], double&, double&) const {
+  __device__ Pre pre(int r, long node) const {
+    const size_t o = (size_t)r * ndof + 3 * node;
+    return Pre{ld3(b + o), ld3(x + o), ld3(invD + 3 * node)};
+  }
+  __device__ void put(int r, long node, const T ax[3], const Pre& pv, double&, double&) const {
     const size_t o = (size_t)r * ndof + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      xo[o + c] = x[o + c] + omega * invD[3 * node + c] * (b[o + c] - ax[c]);
+      xo[o + c] = pv.x.v[c] + omega * pv.d.v[c] * (pv.b.v[c] - ax[c]);
   }
 };
 
@@ -451,15 +498,24 @@ struct EpJacobiDot {
   const double* r;
   const double* rold;
   static constexpr bool RED = true;
+  struct Pre {
+    Pre3<T> b, x, d;
+    Pre3<double> r, ro;
+  };
   __device__ bool rhs_on(int) const { return true; }
-  __device__ void put(int rr, long node, const T ax[3], double& a0, double& a1) const {
+  __device__ Pre pre(int rr, long node) const {
+    const size_t o = (size_t)rr * ndof + 3 * node;
+    return Pre{ld3(b + o), ld3(x + o), ld3(invD + 3 * node), ld3(r + o), ld3(rold + o)};
+  }
+  __device__ void put(int rr, long node, const T ax[3], const Pre& pv, double& a0,
+                      double& a1) const {
     const size_t o = (size_t)rr * ndof + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T z = x[o + c] + omega * invD[3 * node + c] * (b[o + c] - ax[c]);
+      const T z = pv.x.v[c] + omega * pv.d.v[c] * (pv.b.v[c] - ax[c]);
       xo[o + c] = z;
-      a0 += r[o + c] * (double)z;
-      a1 += rold[o + c] * (double)z;
+      a0 += pv.r.v[c] * (double)z;
+      a1 += pv.ro.v[c] * (double)z;
     }
   }
 };
@@ -470,13 +526,18 @@ struct EpDotPQ {  // q = A p; acc[r] += p.q  (active load cases)
   long ndof;
   const CgScalars* cs;
   static constexpr bool RED = true;
+  struct Pre {
+    Pre3<double> p;
+  };
   __device__ bool rhs_on(int r) const { return cs[r].state == CG_ACTIVE; }
-  __device__ void put(int r, long node, const double ax[3], double& a0, double&) const {
+  __device__ Pre pre(int r, long node) const { return Pre{ld3(p + (size_t)r * ndof + 3 * node)}; }
+  __device__ void put(int r, long node, const double ax[3], const Pre& pv, double& a0,
+                      double&) const {
     const size_t o = (size_t)r * ndof + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       q[o + c] = ax[c];
-      a0 += p[o + c] * ax[c];
+      a0 += pv.p.v[c] * ax[c];
     }
   }
 };
@@ -487,15 +548,20 @@ struct EpInitResid {  // r = f - A x; acc[r] += r.r; acc[nrhs + r] += f.f
   long ndof;
   int nrhs;
   static constexpr bool RED = true;
+  struct Pre {
+    Pre3<double> f;
+  };
   __device__ bool rhs_on(int) const { return true; }
-  __device__ void put(int r, long node, const double ax[3], double& a0, double& a1) const {
+  __device__ Pre pre(int r, long node) const { return Pre{ld3(f + (size_t)r * ndof + 3 * node)}; }
+  __device__ void put(int r, long node, const double ax[3], const Pre& pv, double& a0,
+                      double& a1) const {
     const size_t o = (size_t)r * ndof + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double rr = f[o + c] - ax[c];
+      const double rr = pv.f.v[c] - ax[c];
       rout[o + c] = rr;
       a0 += rr * rr;
-      a1 += f[o + c] * f[o + c];
+      a1 += pv.f.v[c] * pv.f.v[c];
     }
   }
 };
@@ -505,15 +571,28 @@ struct EpTrueResid {  // for load cases under check: r = f - A x; acc[r] += r.r
   double* rout;
   long ndof;
   const CgScalars* cs;
+  VPrep vp;  // the replaced residual is the next V-cycle's input
   static constexpr bool RED = true;
+  struct Pre {
+    Pre3<double> f;
+    double wd[3];
+  };
   __device__ bool rhs_on(int r) const { return cs[r].state == CG_CHECK; }
-  __device__ void put(int r, long node, const double ax[3], double& a0, double&) const {
+  __device__ Pre pre(int r, long node) const {
+    Pre pv{ld3(f + (size_t)r * ndof + 3 * node), {0.0, 0.0, 0.0}};
+    if (vp.x0)
+      for (int c = 0; c < 3; ++c) pv.wd[c] = vprep_wd(vp, 3 * node + c);
+    return pv;
+  }
+  __device__ void put(int r, long node, const double ax[3], const Pre& pv, double& a0,
+                      double&) const {
     const size_t o = (size_t)r * ndof + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double rr = f[o + c] - ax[c];
+      const double rr = pv.f.v[c] - ax[c];
       rout[o + c] = rr;
       a0 += rr * rr;
+      if (vp.x0) vprep_put(vp, o + c, rr, pv.wd[c]);
     }
   }
 };
@@ -536,9 +615,10 @@ void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_stat
   const int r = blockIdx.y;
   double a0 = 0.0, a1 = 0.0;
   if (node < op.L.nn() && ep.rhs_on(r)) {
+    const typename Ep::Pre pv = ep.pre(r, node);
     T ax[3];
     ax_any(op, in, r, node, ax);
-    ep.put(r, node, ax, a0, a1);
+    ep.put(r, node, ax, pv, a0, a1);
   }
   if constexpr (Ep::RED) {
     block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + blockIdx.x,
@@ -553,8 +633,11 @@ void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_stat
 constexpr int ST_LPN = 4;
 constexpr int ST_NODES = BS / ST_LPN;  // nodes per block
 
+// Two waves per SIMD (up to 256 registers): at a tighter register target the
+// compiler serialises the last coefficient loads behind one register pair.
 template <typename T, class In, class Ep>
-__global__ __launch_bounds__(BS) void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
                                                  const CgScalars* gate, int gate_state,
                                                  double* part) {
   if (gate && !any_state(gate, nrhs, gate_state)) return;
@@ -569,6 +652,11 @@ __global__ __launch_bounds__(BS) void k_apply_st(OpST<T> op, In in, Ep ep, int n
   double a0 = 0.0, a1 = 0.0;
   const bool on = node < op.L.nn() && ep.rhs_on(r);
   T ax[3] = {T(0), T(0), T(0)};
+  // epilogue operands (used by wave 0), loaded without a branch: a value
+  // merged from a conditional load would have to arrive before the gathers
+  // start
+  const long nn = op.L.nn();
+  const typename Ep::Pre pv = ep.pre(r, node < nn ? node : nn - 1);
   if (on) {
     int i, j, k;
     node_ijk(node, op.L, i, j, k);
@@ -584,7 +672,7 @@ __global__ __launch_bounds__(BS) void k_apply_st(OpST<T> op, In in, Ep ep, int n
     for (int w = 0; w < ST_LPN - 1; ++w)
 #pragma unroll
       for (int c = 0; c < 3; ++c) ax[c] += red[w][c][lane];
-    ep.put(r, node, ax, a0, a1);
+    ep.put(r, node, ax, pv, a0, a1);
   }
   if constexpr (Ep::RED) {
     block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + blockIdx.x,
@@ -708,7 +796,7 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
                                                   const double* __restrict__ q, double* x, double* r,
                                                   long ndof, int nrhs, CgScalars* cs,
                                                   const double* __restrict__ ppq, int nbq,
-                                                  double* prr) {
+                                                  double* prr, VPrep vp) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   __shared__ double sh[BS / 64];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -722,7 +810,9 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
     const size_t nb = (size_t)ndof * sizeof(double);
     const __amdgpu_buffer_rsrc_t bp = make_rsrc(p + o, nb), bq = make_rsrc(q + o, nb),
                                  bx = make_rsrc(x + o, nb), br = make_rsrc(r + o, nb);
-    double pv[VU], qv[VU], xv[VU], rv[VU];
+    const __amdgpu_buffer_rsrc_t bw =
+        make_rsrc(vp.wD, (size_t)ndof * (vp.f32 ? sizeof(float) : sizeof(double)));
+    double pv[VU], qv[VU], xv[VU], rv[VU], wv[VU];
     auto fetch = [&](long i0) {
 #pragma unroll
       for (int k = 0; k < VU; ++k) {
@@ -731,6 +821,9 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
         qv[k] = bload<double>(bq, off, 0);
         xv[k] = bload<double>(bx, off, 0);
         rv[k] = bload<double>(br, off, 0);
+        wv[k] = !vp.x0 ? 0.0
+                : vp.f32 ? (double)bload<float>(bw, (int)((i0 + k * BS) * sizeof(float)), 0)
+                         : bload<double>(bw, off, 0);
       }
     };
     long i0 = (long)blockIdx.x * BS * VU + threadIdx.x;
@@ -751,6 +844,7 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
         if (i < ndof) {
           x[o + i] = xv[k] + a * pv[k];
           r[o + i] = rn;
+          if (vp.x0) vprep_put(vp, o + i, rn, wv[k]);
         }
       }
       if (i0 + step < ndof) fetch(i0 + step);
@@ -784,11 +878,11 @@ __global__ void k_fin_rr(CgScalars* cs, int nrhs, const double* part, int nb) {
 }
 
 void cg_update_xr(const double* p, const double* q, double* x, double* r, long ndof, int nrhs,
-                  CgScalars* cs, RedBuf red, int nbq, hipStream_t st) {
+                  CgScalars* cs, RedBuf red, int nbq, VPrep vp, hipStream_t st) {
   double* prr = red.partials + RED_RR * RED_REGION;
   const int g = vec_grid(ndof);
   hipLaunchKernelGGL(k_update_xr, dim3(g), dim3(BS), 0, st, p, q, x, r, ndof, nrhs, cs,
-                     red.partials + RED_PQ * RED_REGION, nbq, prr);
+                     red.partials + RED_PQ * RED_REGION, nbq, prr, vp);
   MGCG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(BS), 0, st, cs, nrhs, prr, g);
   MGCG_HIP(hipGetLastError());
@@ -828,10 +922,11 @@ __global__ void k_fin_true(CgScalars* cs, int nrhs, const double* part, int nb) 
 }
 
 void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
-                      CgScalars* cs, RedBuf red, hipStream_t st) {
+                      CgScalars* cs, RedBuf red, VPrep vp, hipStream_t st) {
   const long nd = A.lat().ndof();
   double* part = red.partials + RED_TR * RED_REGION;
-  fine_dispatch(A, InPlain<double>{x, nd}, EpTrueResid{f, r, nd, cs}, nrhs, cs, CG_CHECK, st, part);
+  fine_dispatch(A, InPlain<double>{x, nd}, EpTrueResid{f, r, nd, cs, vp}, nrhs, cs, CG_CHECK, st,
+                part);
   hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(BS), 0, st, cs, nrhs, part, fine_blocks(A));
   MGCG_HIP(hipGetLastError());
 }
@@ -1172,165 +1267,43 @@ void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_
   MGCG_HIP(hipGetLastError());
 }
 
-// Coarsest solve: one wavefront per free DOF row of A_c^{-1}.
+// Coarsest solve x = A_c^{-1} b: one wavefront per row, the lanes split the
+// columns (all loads of a row issued together; past ndof they read 0).
 template <typename T>
-__global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ Ainv,
-                                                     const int* __restrict__ freedof, int nc,
+__global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ Ainv, int ld,
                                                      long ndof, const T* __restrict__ b, T* x,
                                                      int nrhs, const CgScalars* cs) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= nc) return;
-  const double* a = Ainv + (size_t)row * nc;
-  for (int r = 0; r < nrhs; ++r) {
-    const T* bb = b + (size_t)r * ndof;
-    double s = 0.0;
-    for (int c = lane; c < nc; c += 64) s += a[c] * (double)bb[freedof[c]];
-    s = wave_sum(s);
-    if (lane == 0) x[(size_t)r * ndof + freedof[row]] = (T)s;
+  if (row >= ndof) return;
+  const int r = blockIdx.y;  // load case
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(Ainv + (size_t)row * ld, (size_t)ndof * 8);
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(b + (size_t)r * ndof, (size_t)ndof * sizeof(T));
+  double s = 0.0;
+  for (int c0 = 0; c0 < ndof; c0 += 8 * 64) {
+    double a[8], v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int c = c0 + lane + 64 * q;
+      a[q] = bload<double>(ra, c * 8, 0);
+      v[q] = (double)bload<T>(rb, c * (int)sizeof(T), 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s = fma(a[q], v[q], s);
   }
+  s = wave_sum(s);
+  if (lane == 0) x[(size_t)r * ndof + row] = (T)s;
 }
 
 template <typename T>
-void v_coarse_solve(const double* Ainv, const int* freedof, int nc, long ndof, const T* b, T* x,
-                    int nrhs, const CgScalars* cs, hipStream_t st) {
-  if (nc == 0) return;
-  hipLaunchKernelGGL(k_coarse_solve<T>, dim3((nc + 3) / 4), dim3(BS), 0, st, Ainv, freedof, nc,
-                     ndof, b, x, nrhs, cs);
+void v_coarse_solve(const double* Ainv, int ld, long ndof, const T* b, T* x, int nrhs,
+                    const CgScalars* cs, hipStream_t st) {
+  if (ndof == 0) return;
+  hipLaunchKernelGGL(k_coarse_solve<T>, dim3((int)((ndof + 3) / 4), nrhs), dim3(BS), 0, st, Ainv,
+                     ld, ndof, b, x, nrhs, cs);
   MGCG_HIP(hipGetLastError());
 }
-
-// ------------------------------------------------------------ V-cycle tail
-constexpr int TAIL_BS = 1024;
-
-template <typename T>
-__global__ __launch_bounds__(TAIL_BS) void k_tail(TailArgs<T> a, const CgScalars* cs) {
-  if (!any_state(cs, a.nrhs, CG_ACTIVE)) return;
-  const int tid = threadIdx.x;
-  const int R = a.nrhs;
-  // x of every level as a pointer pair (current, other) swapped by sweeps
-  T* cur[TAIL_MAX];
-  T* oth[TAIL_MAX];
-  for (int l = 0; l < a.nlev; ++l) {
-    cur[l] = a.lv[l].x;
-    oth[l] = a.lv[l].xalt;
-  }
-  auto jacobi = [&](int l, const T* xin, T* xout) {
-    const TailLevel<T>& v = a.lv[l];
-    const OpST<T> op{v.L, v.coef};
-    const long nn = v.L.nn(), nd = v.L.ndof();
-    for (int r = 0; r < R; ++r)
-      for (long node = tid; node < nn; node += TAIL_BS) {
-        int i, j, k;
-        node_ijk(node, v.L, i, j, k);
-        T ax[3];
-        ax_st(op, InPlain<T>{xin, nd}, r, i, j, k, node, ax);
-        const size_t o = (size_t)r * nd + 3 * node;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xout[o + c] = xin[o + c] + v.wD[3 * node + c] * (v.b[o + c] - ax[c]);
-      }
-    __syncthreads();
-  };
-  const int lc = a.nlev - 1;
-  for (int l = 0; l < lc; ++l) {
-    const TailLevel<T>& v = a.lv[l];
-    const OpST<T> op{v.L, v.coef};
-    const long nn = v.L.nn(), nd = v.L.ndof();
-    for (int s = 1; s < a.pre; ++s) {
-      jacobi(l, cur[l], oth[l]);
-      T* t = cur[l]; cur[l] = oth[l]; oth[l] = t;
-    }
-    for (int r = 0; r < R; ++r)
-      for (long node = tid; node < nn; node += TAIL_BS) {
-        int i, j, k;
-        node_ijk(node, v.L, i, j, k);
-        T ax[3];
-        ax_st(op, InPlain<T>{cur[l], nd}, r, i, j, k, node, ax);
-        const size_t o = (size_t)r * nd + 3 * node;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v.r[o + c] = v.b[o + c] - ax[c];
-      }
-    __syncthreads();
-    // restriction to level l+1 (and its first sweep unless it is the coarsest)
-    const TailLevel<T>& w = a.lv[l + 1];
-    const long cnd = w.L.ndof(), fnd = nd;
-    for (int r = 0; r < R; ++r)
-      for (long t = tid; t < cnd; t += TAIL_BS) {
-        const long cn = t / 3;
-        const int c = (int)(t % 3);
-        int I, J, K;
-        node_ijk(cn, w.L, I, J, K);
-        T acc = T(0);
-        const T* src = v.r + (size_t)r * fnd + c;
-        for (int dz = -1; dz <= 1; ++dz)
-          for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-              const int fi = 2 * I + dx, fj = 2 * J + dy, fk = 2 * K + dz;
-              if ((unsigned)fi >= (unsigned)v.L.nx || (unsigned)fj >= (unsigned)v.L.ny ||
-                  (unsigned)fk >= (unsigned)v.L.nz)
-                continue;
-              const T wgt = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
-              acc += wgt * src[3 * (fi + (long)v.L.nx * (fj + (long)v.L.ny * fk))];
-            }
-        const T bv = ((w.mask[cn] >> c) & 1) ? T(0) : acc;
-        w.b[(size_t)r * cnd + t] = bv;
-        if (l + 1 < lc) cur[l + 1][(size_t)r * cnd + t] = w.wD[t] * bv;
-      }
-    __syncthreads();
-  }
-  // coarsest: x = A_c^{-1} b over the free DOFs (fixed entries stay 0)
-  {
-    const TailLevel<T>& v = a.lv[lc];
-    const long nd = v.L.ndof();
-    for (int r = 0; r < R; ++r)
-      for (int row = tid; row < a.nc; row += TAIL_BS) {
-        const double* arow = a.Ainv + (size_t)row * a.nc;
-        double sacc = 0.0;
-        for (int c = 0; c < a.nc; ++c) sacc += arow[c] * (double)v.b[(size_t)r * nd + a.freedof[c]];
-        cur[lc][(size_t)r * nd + a.freedof[row]] = (T)sacc;
-      }
-    __syncthreads();
-  }
-  for (int l = lc - 1; l >= 0; --l) {
-    const TailLevel<T>& v = a.lv[l];
-    const TailLevel<T>& w = a.lv[l + 1];
-    const long nn = v.L.nn(), nd = v.L.ndof(), cnd = w.L.ndof();
-    for (int r = 0; r < R; ++r)
-      for (long node = tid; node < nn; node += TAIL_BS) {
-        int i, j, k;
-        node_ijk(node, v.L, i, j, k);
-        const uint8_t m = v.mask[node];
-        const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-        const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-        const T wgt = T(((i & 1) ? 0.5 : 1.0) * ((j & 1) ? 0.5 : 1.0) * ((k & 1) ? 0.5 : 1.0));
-        T acc[3] = {T(0), T(0), T(0)};
-        for (int c2 = 0; c2 < nk; ++c2)
-          for (int b2 = 0; b2 < nj; ++b2)
-            for (int a2 = 0; a2 < ni; ++a2) {
-              const long cn = (i0 + a2) + (long)w.L.nx * ((j0 + b2) + (long)w.L.ny * (k0 + c2));
-              const T* pp = cur[l + 1] + (size_t)r * cnd + 3 * cn;
-              for (int c = 0; c < 3; ++c) acc[c] += wgt * pp[c];
-            }
-        T* q = cur[l] + (size_t)r * nd + 3 * node;
-        for (int c = 0; c < 3; ++c)
-          if (!((m >> c) & 1)) q[c] += acc[c];
-      }
-    __syncthreads();
-    for (int s = 0; s < a.post; ++s) {
-      jacobi(l, cur[l], oth[l]);
-      T* t = cur[l]; cur[l] = oth[l]; oth[l] = t;
-    }
-  }
-}
-
-template <typename T>
-void v_tail(const TailArgs<T>& a, const CgScalars* cs, hipStream_t st) {
-  hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(TAIL_BS), 0, st, a, cs);
-  MGCG_HIP(hipGetLastError());
-}
-template void v_tail<double>(const TailArgs<double>&, const CgScalars*, hipStream_t);
-template void v_tail<float>(const TailArgs<float>&, const CgScalars*, hipStream_t);
 
 #define VINST(T)                                                                                  \
   template void v_jacobi<T>(const VOps<T>&, const T*, const T*, T*, T, int, const CgScalars*,      \
@@ -1346,8 +1319,8 @@ template void v_tail<float>(const TailArgs<float>&, const CgScalars*, hipStream_
                               hipStream_t);                                                       \
   template void v_prolong<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, int, bool,    \
                              const CgScalars*, hipStream_t);                                      \
-  template void v_coarse_solve<T>(const double*, const int*, int, long, const T*, T*, int,         \
-                                  const CgScalars*, hipStream_t);
+  template void v_coarse_solve<T>(const double*, int, long, const T*, T*, int, const CgScalars*,   \
+                                  hipStream_t);
 VINST(double)
 VINST(float)
 

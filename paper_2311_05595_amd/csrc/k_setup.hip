@@ -2,6 +2,8 @@
 // the system matrix of every mesh level and the Cholesky factor of the
 // coarsest one are recomputed at each optimisation iteration), plus the
 // compliance and sensitivity kernels (Sec. 3.4).
+#include <utility>
+
 #include "devutil.h"
 
 namespace mgcg {
@@ -465,22 +467,25 @@ template void setup_diag_eq2<float>(Lat, const double*, const uint8_t*, float*, 
                                     double, hipStream_t);
 
 // ------------------------------------------------------------ coarsest level
-// Dense A_ff (row-major, nc x nc) from Q1-type FP64 element matrices of the
-// level (src OP_MF_Q1: E_e K0; otherwise KE[e]); one thread per row
-// accumulates the contributions of the elements around its node, so every
-// entry has a single writer (A must be zeroed before).
+// Dense operator of the coarsest level (row-major, stride ld) from its
+// Q1-type FP64 element matrices (src OP_MF_Q1: E_e K0; otherwise KE[e]): one
+// thread per free DOF accumulates the contributions of the elements around
+// its node into its row, so every entry has a single writer; columns of
+// fixed DOFs are skipped (A must be zeroed before).
 __global__ __launch_bounds__(BS) void k_dense(int src_kind, Lat L, const double* __restrict__ E,
                                               const double* __restrict__ K0,
                                               const double* __restrict__ KE,
                                               const int* __restrict__ freedof,
-                                              const int* __restrict__ dofpos, int nc, double* A) {
+                                              const int* __restrict__ dofpos, int nfree, int ld,
+                                              double* A) {
   const int I = blockIdx.x * BS + threadIdx.x;
-  if (I >= nc) return;
+  if (I >= nfree) return;
   const int gdof = freedof[I];
   const long node = gdof / 3;
   const int c = gdof % 3;
   const int i = (int)(node % L.nx), j = (int)((node / L.nx) % L.ny), k = (int)(node / ((long)L.nx * L.ny));
   const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
+  double* row = A + (size_t)gdof * ld;
   for (int o = 0; o < 8; ++o) {
     const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
     const int ex = i - 1 + ox, ey = j - 1 + oy, ez = k - 1 + oz;
@@ -492,162 +497,153 @@ __global__ __launch_bounds__(BS) void k_dense(int src_kind, Lat L, const double*
       const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
       const long nb = (ex + bx) + (long)L.nx * ((ey + by) + (long)L.ny * (ez + bz));
       for (int e2 = 0; e2 < 3; ++e2) {
-        const int J = dofpos[3 * nb + e2];
-        if (J < 0) continue;
+        if (dofpos[3 * nb + e2] < 0) continue;  // fixed column
         const int kk = (3 * a + c) * 24 + 3 * b + e2;
         const double v = src_kind == OP_MF_Q1 ? E[e] * K0[kk] : KE[(size_t)e * 576 + kk];
-        A[(size_t)I * nc + J] += v;
+        row[3 * nb + e2] += v;
       }
     }
   }
+}
+
+// Unit diagonal on fixed DOFs and on the padding rows.
+__global__ void k_dense_unit(const int* __restrict__ dofpos, long ndof, int ld, double* A) {
+  const int g = blockIdx.x * BS + threadIdx.x;
+  if (g >= ld) return;
+  if (g >= ndof || dofpos[g] < 0) A[(size_t)g * ld + g] = 1.0;
 }
 
 void setup_dense(int src_kind, Lat L, const double* E, const double* K0, const double* KE,
-                 const int* freedof, const int* dofpos, int nc, double* A, hipStream_t st) {
-  fill<double>(A, 0.0, (long)nc * nc, st);
-  if (nc == 0) return;
-  hipLaunchKernelGGL(k_dense, dim3(nblocks(nc)), dim3(BS), 0, st, src_kind, L, E, K0, KE, freedof,
-                     dofpos, nc, A);
+                 const int* freedof, const int* dofpos, int nfree, int ld, double* A,
+                 hipStream_t st) {
+  fill<double>(A, 0.0, (long)ld * ld, st);
+  if (nfree > 0) {
+    hipLaunchKernelGGL(k_dense, dim3(nblocks(nfree)), dim3(BS), 0, st, src_kind, L, E, K0, KE,
+                       freedof, dofpos, nfree, ld, A);
+    MGCG_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_dense_unit, dim3(nblocks(ld)), dim3(BS), 0, st, dofpos, L.ndof(), ld, A);
   MGCG_HIP(hipGetLastError());
 }
 
-// Right-looking Cholesky A = L L^T in place (lower triangle), one workgroup.
-__global__ __launch_bounds__(1024) void k_cholesky(double* A, int n, int* bad) {
-  __shared__ double sd;
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      double d = A[(size_t)k * n + k];
-      if (!(d > 0.0) || !isfinite(d)) {
-        atomicOr(bad, 2);
-        d = 1.0;
-      }
-      d = sqrt(d);
-      A[(size_t)k * n + k] = d;
-      sd = d;
-    }
-    __syncthreads();
-    const double inv = 1.0 / sd;
-    for (int i = k + 1 + threadIdx.x; i < n; i += 1024) A[(size_t)i * n + k] *= inv;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (long idx = threadIdx.x; idx < (long)m * m; idx += 1024) {
-      const int i = k + 1 + (int)(idx / m), j = k + 1 + (int)(idx % m);
-      if (j <= i) A[(size_t)i * n + j] -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-    }
-    __syncthreads();
-  }
+// ------------------------------------------------------------ coarsest inverse
+// Blocked Gauss-Jordan elimination: sweeping pivot block k maps
+//   A_kk -> D = A_kk^{-1},  A_kj -> D A_kj,  A_ik -> -A_ik D,
+//   A_ij -> A_ij - A_ik D A_kj          (i, j != k),
+// and after all blocks the matrix holds A^{-1}.  For a symmetric positive
+// definite A every pivot block is a Schur complement of A, hence SPD itself:
+// no pivoting is needed, and a pivot that is not clearly positive (relative
+// to the original diagonal entry) means A is singular or indefinite.
+
+__global__ void k_diag0(const double* __restrict__ A, int ld, double* diag0) {
+  const int g = blockIdx.x * BS + threadIdx.x;
+  if (g < ld) diag0[g] = A[(size_t)g * ld + g];
 }
 
-// Left-looking panel Cholesky A = L L^T (lower triangle, in place), one
-// workgroup: each panel of NB columns is first updated with the finished
-// columns to its left (a parallel dot-product pass over L2-resident rows),
-// then factored column by column inside LDS.  Dynamic LDS: rows x NB doubles.
-template <int NB>
-__global__ __launch_bounds__(1024) void k_cholesky_panel(double* A, int n, int* bad) {
-  extern __shared__ double P[];  // [n - p0][NB], row-major
-  __shared__ double sd;
-  const int tid = threadIdx.x;
-  for (int p0 = 0; p0 < n; p0 += NB) {
-    const int w = min(NB, n - p0), rows = n - p0;
-    // load + left-looking update of the panel (lower part r >= c)
-    for (int t = tid; t < rows * NB; t += 1024) {
-      const int r = t / NB, c = t % NB;
-      double v = 0.0;
-      if (c < w && r >= c) {
-        const double* ai = A + (size_t)(p0 + r) * n;
-        const double* aj = A + (size_t)(p0 + c) * n;
-        v = ai[p0 + c];
-        double s0 = 0.0, s1 = 0.0;
-        int k = 0;
-        for (; k + 1 < p0; k += 2) {
-          s0 += ai[k] * aj[k];
-          s1 += ai[k + 1] * aj[k + 1];
-        }
-        if (k < p0) s0 += ai[k] * aj[k];
-        v -= s0 + s1;
-      }
-      P[t] = v;
-    }
-    __syncthreads();
-    for (int c = 0; c < w; ++c) {
-      if (tid == 0) {
-        double d = P[c * NB + c];
-        if (!(d > 0.0) || !isfinite(d)) {
-          atomicOr(bad, 2);
-          d = 1.0;
-        }
-        d = sqrt(d);
-        P[c * NB + c] = d;
-        sd = d;
-      }
-      __syncthreads();
-      const double inv = 1.0 / sd;
-      for (int r = c + 1 + tid; r < rows; r += 1024) P[r * NB + c] *= inv;
-      __syncthreads();
-      const int wc = w - c - 1;
-      if (wc > 0) {
-        for (int t = tid; t < (rows - c - 1) * wc; t += 1024) {
-          const int r = c + 1 + t / wc, c2 = c + 1 + t % wc;
-          if (r >= c2) P[r * NB + c2] -= P[r * NB + c] * P[c2 * NB + c];
-        }
-      }
-      __syncthreads();
-    }
-    for (int t = tid; t < rows * NB; t += 1024) {
-      const int r = t / NB, c = t % NB;
-      if (c < w && r >= c) A[(size_t)(p0 + r) * n + p0 + c] = P[t];
-    }
-    __syncthreads();
-  }
-}
-
-// Column j of L^{-1} by forward substitution (one workgroup per column).
-__global__ __launch_bounds__(BS) void k_trinv(const double* __restrict__ Lf, double* Linv, int n) {
-  extern __shared__ double w[];
-  const int j = blockIdx.x;
-  for (int i = threadIdx.x; i < n; i += BS) w[i] = (i == j) ? 1.0 : 0.0;
+// D = A_kk^{-1} by unblocked Gauss-Jordan in LDS (one thread per entry).
+__global__ __launch_bounds__(GJ_B * GJ_B) void k_gj_diag(const double* __restrict__ A, int ld,
+                                                          int k, const double* __restrict__ diag0,
+                                                          double* D, int* bad) {
+  __shared__ double M[GJ_B][GJ_B + 1];
+  const int r = threadIdx.x / GJ_B, c = threadIdx.x % GJ_B;
+  const int k0 = k * GJ_B;
+  M[r][c] = A[(size_t)(k0 + r) * ld + k0 + c];
   __syncthreads();
-  for (int k = j; k < n; ++k) {
-    const double wk = w[k] / Lf[(size_t)k * n + k];
+  for (int p = 0; p < GJ_B; ++p) {
+    double piv = M[p][p];
+    if (!(piv > 1e-13 * diag0[k0 + p]) || !isfinite(piv)) {
+      if (threadIdx.x == 0) atomicOr(bad, 2);
+      piv = 1.0;
+    }
+    const double ip = 1.0 / piv;
+    double v;
+    if (r == p && c == p)
+      v = ip;
+    else if (r == p)
+      v = ip * M[p][c];
+    else if (c == p)
+      v = -M[r][p] * ip;
+    else
+      v = M[r][c] - M[r][p] * ip * M[p][c];
     __syncthreads();
-    if (threadIdx.x == 0) w[k] = wk;
-    for (int i = k + 1 + threadIdx.x; i < n; i += BS) w[i] -= Lf[(size_t)i * n + k] * wk;
+    M[r][c] = v;
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += BS) Linv[(size_t)i * n + j] = (i >= j) ? w[i] : 0.0;
+  D[r * GJ_B + c] = M[r][c];
 }
 
-// Ainv = Linv^T Linv.
-__global__ __launch_bounds__(BS) void k_ltl(const double* __restrict__ Linv, double* Ainv, int n) {
-  const long t = (long)blockIdx.x * BS + threadIdx.x;
-  if (t >= (long)n * n) return;
-  const int i = (int)(t / n), j = (int)(t % n);
-  double s = 0.0;
-  for (int k = (i > j ? i : j); k < n; ++k) s += Linv[(size_t)k * n + i] * Linv[(size_t)k * n + j];
-  Ainv[t] = s;
+// Tile (I, J) of the matrix after sweeping block k: reads A, writes B.
+__global__ __launch_bounds__(BS) void k_gj_update(const double* __restrict__ A, double* B, int ld,
+                                                  int k, const double* __restrict__ D) {
+  __shared__ double sD[GJ_B][GJ_B + 1], sR[GJ_B][GJ_B + 1], sC[GJ_B][GJ_B + 1],
+      sT[GJ_B][GJ_B + 1];
+  const int I = blockIdx.y, J = blockIdx.x;
+  const int c = threadIdx.x % GJ_B, r0 = threadIdx.x / GJ_B;  // rows r0 + 8 q
+  constexpr int RS = BS / GJ_B;
+  const size_t k0 = (size_t)k * GJ_B, i0 = (size_t)I * GJ_B, j0 = (size_t)J * GJ_B;
+  for (int q = 0; q < GJ_B / RS; ++q) {
+    const int r = r0 + RS * q;
+    sD[r][c] = D[r * GJ_B + c];
+    sR[r][c] = A[(k0 + r) * ld + j0 + c];  // A_kJ
+    sC[r][c] = A[(i0 + r) * ld + k0 + c];  // A_Ik
+  }
+  __syncthreads();
+  if (I == k && J == k) {
+    for (int q = 0; q < GJ_B / RS; ++q) {
+      const int r = r0 + RS * q;
+      B[(i0 + r) * ld + j0 + c] = sD[r][c];
+    }
+    return;
+  }
+  if (I == k) {  // D A_kJ
+    for (int q = 0; q < GJ_B / RS; ++q) {
+      const int r = r0 + RS * q;
+      double s = 0.0;
+      for (int m = 0; m < GJ_B; ++m) s += sD[r][m] * sR[m][c];
+      B[(i0 + r) * ld + j0 + c] = s;
+    }
+    return;
+  }
+  if (J == k) {  // -A_Ik D
+    for (int q = 0; q < GJ_B / RS; ++q) {
+      const int r = r0 + RS * q;
+      double s = 0.0;
+      for (int m = 0; m < GJ_B; ++m) s += sC[r][m] * sD[m][c];
+      B[(i0 + r) * ld + j0 + c] = -s;
+    }
+    return;
+  }
+  // A_IJ - A_Ik (D A_kJ)
+  double aij[GJ_B / RS];
+  for (int q = 0; q < GJ_B / RS; ++q) aij[q] = A[(i0 + r0 + RS * q) * ld + j0 + c];
+  for (int q = 0; q < GJ_B / RS; ++q) {
+    const int r = r0 + RS * q;
+    double s = 0.0;
+    for (int m = 0; m < GJ_B; ++m) s += sD[r][m] * sR[m][c];
+    sT[r][c] = s;
+  }
+  __syncthreads();
+  for (int q = 0; q < GJ_B / RS; ++q) {
+    const int r = r0 + RS * q;
+    double s = 0.0;
+    for (int m = 0; m < GJ_B; ++m) s += sC[r][m] * sT[m][c];
+    B[(i0 + r) * ld + j0 + c] = aij[q] - s;
+  }
 }
 
-void setup_cholesky_inverse(double* A, double* Linv, double* Ainv, int nc, int* bad,
-                            hipStream_t st) {
-  if (nc == 0) return;
-  // panel in at most 64 KB of LDS
-  const size_t lim = 64 * 1024;
-  if ((size_t)nc * 32 * sizeof(double) <= lim)
-    hipLaunchKernelGGL(k_cholesky_panel<32>, dim3(1), dim3(1024), (size_t)nc * 32 * sizeof(double),
-                       st, A, nc, bad);
-  else if ((size_t)nc * 16 * sizeof(double) <= lim)
-    hipLaunchKernelGGL(k_cholesky_panel<16>, dim3(1), dim3(1024), (size_t)nc * 16 * sizeof(double),
-                       st, A, nc, bad);
-  else if ((size_t)nc * 8 * sizeof(double) <= lim)
-    hipLaunchKernelGGL(k_cholesky_panel<8>, dim3(1), dim3(1024), (size_t)nc * 8 * sizeof(double),
-                       st, A, nc, bad);
-  else
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, st, A, nc, bad);
+double* setup_coarse_inverse(double* A, double* B, double* D, double* diag0, int ld, int* bad,
+                             hipStream_t st) {
+  const int nb = ld / GJ_B;
+  hipLaunchKernelGGL(k_diag0, dim3(nblocks(ld)), dim3(BS), 0, st, A, ld, diag0);
   MGCG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_trinv, dim3(nc), dim3(BS), nc * sizeof(double), st, A, Linv, nc);
-  MGCG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_ltl, dim3(nblocks((long)nc * nc)), dim3(BS), 0, st, Linv, Ainv, nc);
-  MGCG_HIP(hipGetLastError());
+  for (int k = 0; k < nb; ++k) {
+    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(GJ_B * GJ_B), 0, st, A, ld, k, diag0, D, bad);
+    MGCG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gj_update, dim3(nb, nb), dim3(BS), 0, st, A, B, ld, k, D);
+    MGCG_HIP(hipGetLastError());
+    std::swap(A, B);
+  }
+  return A;
 }
 
 // ------------------------------------------------------------ compliance
@@ -683,9 +679,18 @@ void comp_dot(const double* f, const double* u, long ndof, int nrhs, double* out
 }
 
 // ------------------------------------------------------------ sensitivity
-// One thread per (sub-element s, displacement element e), threads of a
-// wavefront share s (uniform Ksub[s] reads):
+// One thread per (sub-element s, displacement element e); s = blockIdx.y is
+// uniform, so the sub-element matrix Ksub[s] is read through scalar loads:
 //   dc = -p rho^{p-1} (E0 - Emin) sum_l u_{l,e}^T K^(e_s) u_{l,e}.
+// ue[i] for a run-time i without dynamic register indexing.
+template <int N>
+__device__ __forceinline__ double select_row(const double (&v)[N], int i) {
+  double out = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) out = (k == i) ? v[k] : out;
+  return out;
+}
+
 template <int ORDER>
 __global__ __launch_bounds__(BS) void k_sens(int nsub, int nelx, int nely, int nelz, Lat L,
                                              const double* __restrict__ rho,
@@ -694,11 +699,9 @@ __global__ __launch_bounds__(BS) void k_sens(int nsub, int nelx, int nely, int n
                                              double penal, double* dc) {
   constexpr int P1 = ORDER + 1, NEN = P1 * P1 * P1, ND = 3 * NEN;
   const long nel = (long)nelx * nely * nelz;
-  const long t = (long)blockIdx.x * BS + threadIdx.x;
-  const int ns3 = nsub * nsub * nsub;
-  if (t >= nel * ns3) return;
-  const int s = (int)(t / nel);
-  const long e = t % nel;
+  const long e = (long)blockIdx.x * BS + threadIdx.x;
+  if (e >= nel) return;
+  const int s = blockIdx.y;
   const int ex = (int)(e % nelx), ey = (int)((e / nelx) % nely), ez = (int)(e / ((long)nelx * nely));
   const double* K = Ksub + (size_t)s * ND * ND;
   double w = 0.0;
@@ -711,11 +714,13 @@ __global__ __launch_bounds__(BS) void k_sens(int nsub, int nelx, int nely, int n
 #pragma unroll
       for (int c = 0; c < 3; ++c) ue[3 * a + c] = u[(size_t)r * ndof + 3 * node + c];
     }
+    // rows one at a time (a row of K in scalar registers), u^T (K u)
+#pragma unroll 1
     for (int i = 0; i < ND; ++i) {
       double ti = 0.0;
 #pragma unroll
       for (int jj = 0; jj < ND; ++jj) ti += K[i * ND + jj] * ue[jj];
-      w += ue[i] * ti;
+      w += select_row(ue, i) * ti;
     }
   }
   const int sx = s % nsub, sy = (s / nsub) % nsub, sz = s / (nsub * nsub);
@@ -727,13 +732,13 @@ __global__ __launch_bounds__(BS) void k_sens(int nsub, int nelx, int nely, int n
 void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const double* rho,
                  const double* u, long ndof, int nrhs, const double* Ksub, double /*scale_p*/,
                  double E0mEmin, double penal, double* dc, hipStream_t st) {
-  const long n = (long)nelx * nely * nelz * nsub * nsub * nsub;
+  const dim3 grid(nblocks((long)nelx * nely * nelz), nsub * nsub * nsub);
   if (order == 1)
-    hipLaunchKernelGGL(k_sens<1>, dim3(nblocks(n)), dim3(BS), 0, st, nsub, nelx, nely, nelz, L, rho,
-                       u, ndof, nrhs, Ksub, E0mEmin, penal, dc);
+    hipLaunchKernelGGL(k_sens<1>, grid, dim3(BS), 0, st, nsub, nelx, nely, nelz, L, rho, u, ndof,
+                       nrhs, Ksub, E0mEmin, penal, dc);
   else
-    hipLaunchKernelGGL(k_sens<2>, dim3(nblocks(n)), dim3(BS), 0, st, nsub, nelx, nely, nelz, L, rho,
-                       u, ndof, nrhs, Ksub, E0mEmin, penal, dc);
+    hipLaunchKernelGGL(k_sens<2>, grid, dim3(BS), 0, st, nsub, nelx, nely, nelz, L, rho, u, ndof,
+                       nrhs, Ksub, E0mEmin, penal, dc);
   MGCG_HIP(hipGetLastError());
 }
 

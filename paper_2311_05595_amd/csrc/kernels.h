@@ -81,10 +81,19 @@ void cg_init_residual(const FineOp& A, const double* f, const double* x, double*
 void cg_apply_alpha(const FineOp& A, const double* p, double* q, int nrhs, CgScalars* cs,
                     RedBuf red, hipStream_t st);
 // nbq: blocks per load case of the apply that produced the p.q partials.
+// The level-0 input of the next V-cycle, written by the kernels that produce
+// the residual r: the first smoothing sweep from zero x0 = W D^-1 r (and, for
+// an FP32 V-cycle, b0 = r rounded to FP32).  x0 == nullptr: not written.
+struct VPrep {
+  const void* wD;  // per DOF, V-cycle precision
+  void* x0;
+  void* b0;        // FP32 V-cycle only
+  int f32;
+};
 void cg_update_xr(const double* p, const double* q, double* x, double* r, long ndof, int nrhs,
-                  CgScalars* cs, RedBuf red, int nbq, hipStream_t st);
+                  CgScalars* cs, RedBuf red, int nbq, VPrep vp, hipStream_t st);
 void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
-                      CgScalars* cs, RedBuf red, hipStream_t st);
+                      CgScalars* cs, RedBuf red, VPrep vp, hipStream_t st);
 template <typename TZ>
 void cg_beta(const double* r, const double* rold, const TZ* z, long ndof, int nrhs, CgScalars* cs,
              RedBuf red, hipStream_t st);
@@ -137,45 +146,18 @@ void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask
 template <typename T>
 void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* ec,
                T* xf, int nrhs, bool accumulate, const CgScalars* cs, hipStream_t st);
-// x = A_c^{-1} b on the coarsest level: Ainv [nc][nc] over the free DOF list.
+// x = A_c^{-1} b on the coarsest level: Ainv is the dense inverse over all
+// of the level's DOFs (identity rows and columns at fixed DOFs), row stride
+// ld >= ndof.
 template <typename T>
-void v_coarse_solve(const double* Ainv, const int* freedof, int nc, long ndof, const T* b, T* x,
-                    int nrhs, const CgScalars* cs, hipStream_t st);
+void v_coarse_solve(const double* Ainv, int ld, long ndof, const T* b, T* x, int nrhs,
+                    const CgScalars* cs, hipStream_t st);
 
 // Zero the fixed DOFs of x (nrhs vectors): xm = Z x.
 void mask_copy(const double* x, double* xm, const uint8_t* mask, long nn, int nrhs, hipStream_t st);
 // Identity rows: y_i = x_i on fixed DOFs.
 void identity_rows(const double* x, double* y, const uint8_t* mask, long nn, int nrhs,
                    hipStream_t st);
-
-// The V-cycle below a small level lt, in one workgroup (levels lt..L-1,
-// barriers instead of kernel launches).  Entry: b and x = W D^-1 b of level
-// lt; exit: x of level lt after the coarse correction and post-smoothing
-// (in x when `post` is even, else in xalt).
-constexpr int TAIL_MAX = 8;
-template <typename T>
-struct TailLevel {
-  Lat L;
-  const T* coef;    // stencil (all tail levels but the coarsest)
-  const T* wD;
-  const uint8_t* mask;
-  T* b;
-  T* x;
-  T* xalt;
-  T* r;
-};
-template <typename T>
-struct TailArgs {
-  int nlev;  // levels in the tail, the last one is the coarsest
-  TailLevel<T> lv[TAIL_MAX];
-  const double* Ainv;
-  const int* freedof;
-  int nc;
-  int pre, post;
-  int nrhs;
-};
-template <typename T>
-void v_tail(const TailArgs<T>& a, const CgScalars* cs, hipStream_t st);
 
 // Type conversions and fills.
 template <typename TA, typename TB>
@@ -219,11 +201,19 @@ void setup_diag_mf(Lat L, const double* E, const double* K0, const uint8_t* mask
 template <typename T>
 void setup_diag_eq2(Lat L, const double* Ke, const uint8_t* mask, T* wD, double* diag64,
                     double omega, double theta, hipStream_t st);
-// Coarsest level: dense A_ff from the element matrices, Cholesky, explicit inverse.
+// Coarsest level: the dense operator over all of the level's DOFs (row
+// stride ld, a multiple of GJ_B; identity rows/columns at fixed DOFs and in
+// the padding) from its element matrices, and its inverse by blocked
+// Gauss-Jordan elimination.  setup_coarse_inverse works on A and B in turn
+// and returns the one holding the inverse; D: GJ_B^2 doubles, diag0: ld
+// doubles of scratch.
+constexpr int GJ_B = 32;
+inline int coarse_ld(long ndof) { return (int)((ndof + GJ_B - 1) / GJ_B * GJ_B); }
 void setup_dense(int src_kind, Lat L, const double* E, const double* K0, const double* KE,
-                 const int* freedof, const int* dofpos, int nc, double* A, hipStream_t st);
-void setup_cholesky_inverse(double* A, double* Linv, double* Ainv, int nc, int* bad,
-                            hipStream_t st);
+                 const int* freedof, const int* dofpos, int nfree, int ld, double* A,
+                 hipStream_t st);
+double* setup_coarse_inverse(double* A, double* B, double* D, double* diag0, int ld, int* bad,
+                             hipStream_t st);
 
 // Compliance and sensitivity.
 void comp_dot(const double* f, const double* u, long ndof, int nrhs, double* out, RedBuf red,

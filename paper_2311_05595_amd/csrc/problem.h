@@ -98,8 +98,10 @@ class Problem {
   double last_setup_ms() const { return setup_ms_; }
 
  private:
-  template <typename T> void vcycle(const double* r_in, int gate, bool fuse_dot);
-  void precondition_and_direction();
+  template <typename T> void vcycle(const double* r_in, int gate, bool fuse_dot,
+                                    bool x0_ready = false);
+  void precondition_and_direction(bool x0_ready = false);
+  VPrep vprep() const;
   template <typename T> VOps<T> vops(int level) const;
   template <typename T> void do_set_densities();
   template <typename T> void do_apply_v(int level, const double* x, double* y);
@@ -152,7 +154,8 @@ class Problem {
   int* bad_ = nullptr;
   int* dfree_ = nullptr;
   int* ddofpos_ = nullptr;
-  double *Ad_ = nullptr, *Linv_ = nullptr, *Ainv_ = nullptr;
+  double *Ad_ = nullptr, *Ad2_ = nullptr, *Dgj_ = nullptr, *diag0_ = nullptr;
+  double* Ainv_ = nullptr;  // Ad_ or Ad2_, whichever holds the inverse
   double* G_ = nullptr;
   int* dmasked_ = nullptr;
   double* tmp64_ = nullptr;  // [nrhs][ndof0] scratch for inspection

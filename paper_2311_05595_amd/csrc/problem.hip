@@ -17,11 +17,6 @@ namespace {
 // Gershgorin cap of the per-DOF Jacobi weights (every row sum of W D^-1 A
 // stays below 2, so the smoother converges for any densities).
 constexpr double kTheta = 1.9;
-// Levels with at most this many nodes run in the single-workgroup tail (0:
-// only the coarsest solve; one CU is latency-bound on the small levels, so
-// separate kernels are faster on this hierarchy).
-constexpr long kTailNodes = 0;
-
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Arena {
@@ -181,9 +176,11 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   const long ndc = lv[L - 1].L.ndof();  // upper bound of the coarsest free DOFs
   TAKE(dfree_, int, ndc);
   TAKE(ddofpos_, int, ndc);
-  TAKE(Ad_, double, ndc * ndc);
-  TAKE(Linv_, double, ndc * ndc);
-  TAKE(Ainv_, double, ndc * ndc);
+  const long ldc = coarse_ld(ndc);  // dense coarsest operator and its inverse, padded
+  TAKE(Ad_, double, ldc * ldc);
+  TAKE(Ad2_, double, ldc * ldc);
+  TAKE(Dgj_, double, GJ_B * GJ_B);
+  TAKE(diag0_, double, ldc);
 #undef TAKE
   return align256(A.off);
 }
@@ -536,13 +533,14 @@ void Problem::do_set_densities() {
   const int lc = L - 1;
   const int src = (lc == 0) ? lv_[0].kind : OP_ST27;
   const double* KE = (lc == 0) ? Keff_ : B_[lc].KE;
-  setup_dense(src, lv_[lc].L, E_, K0_, KE, dfree_, ddofpos_, nc_, Ad_, st);
-  setup_cholesky_inverse(Ad_, Linv_, Ainv_, nc_, bad_, st);
+  const int ld = coarse_ld(lv_[lc].L.ndof());
+  setup_dense(src, lv_[lc].L, E_, K0_, KE, dfree_, ddofpos_, nc_, ld, Ad_, st);
+  Ainv_ = setup_coarse_inverse(Ad_, Ad2_, Dgj_, diag0_, ld, bad_, st);
 }
 
 // ------------------------------------------------------------------ V-cycle
 template <typename T>
-void Problem::vcycle(const double* r_in, int gate, bool fuse_dot) {
+void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready) {
   hipStream_t st = stream_;
   const CgScalars* cs = gate ? cs_ : nullptr;
   const int L = (int)lv_.size();
@@ -564,20 +562,12 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot) {
   }
   // level-0 input and its first sweep from zero (the coarse levels get theirs
   // from the restriction)
-  if (L > 1)
+  if (L > 1 && !x0_ready)
     v_prepare0<T>(r_in, sizeof(T) == 8 ? nullptr : (T*)B_[0].b, (const T*)B_[0].invD, cur[0],
                   lv_[0].L.ndof(), R, cs, st);
   else if constexpr (sizeof(T) == 4)
     convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
-  // levels at and below lt run inside one workgroup (the "tail")
-  int lt = L;
-  for (int l = 1; l < L; ++l)
-    if (lv_[l].L.nn() <= kTailNodes) {
-      lt = l;
-      break;
-    }
-  if (lt == L && L > 1) lt = L - 1;  // at least the coarsest solve
-  for (int l = 0; l < std::min(lt, L - 1); ++l) {
+  for (int l = 0; l < L - 1; ++l) {
     const VOps<T> v = vops<T>(l);
     T* rl = (T*)B_[l].r;
     for (int s = 1; s < d_.pre; ++s) {
@@ -591,28 +581,10 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot) {
     v_restrict<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, rl, (T*)B_[l + 1].b,
                   (const T*)B_[l + 1].invD, coarsest_next ? nullptr : cur[l + 1], R, cs, st);
   }
-  if (L == 1 || lt == L - 1) {
-    v_coarse_solve<T>(Ainv_, dfree_, nc_, lv_[L - 1].L.ndof(), bl[L - 1], cur[L - 1], R, cs, st);
-  } else {
-    TailArgs<T> ta{};
-    ta.nlev = L - lt;
-    if (ta.nlev > TAIL_MAX) throw Error(MGCG_EINVAL, "too many small levels");
-    for (int q = 0; q < ta.nlev; ++q) {
-      const int l = lt + q;
-      ta.lv[q] = TailLevel<T>{lv_[l].L, (const T*)B_[l].coefV, (const T*)B_[l].invD, B_[l].mask,
-                              (T*)B_[l].b, cur[l], oth[l], (T*)B_[l].r};
-    }
-    ta.Ainv = Ainv_;
-    ta.freedof = dfree_;
-    ta.nc = nc_;
-    ta.pre = d_.pre;
-    ta.post = d_.post;
-    ta.nrhs = R;
-    v_tail<T>(ta, cs, st);
-    // the tail's pre/post sweeps ping-pong the finest tail level's buffers
-    if ((d_.pre - 1 + d_.post) % 2 == 1 && lt < L - 1) std::swap(cur[lt], oth[lt]);
-  }
-  for (int l = std::min(lt, L - 1) - 1; l >= 0; --l) {
+  const int lc = L - 1;
+  v_coarse_solve<T>(Ainv_, coarse_ld(lv_[lc].L.ndof()), lv_[lc].L.ndof(), bl[lc], cur[lc], R, cs,
+                    st);
+  for (int l = L - 2; l >= 0; --l) {
     const VOps<T> v = vops<T>(l);
     v_prolong<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, cur[l + 1], cur[l], R, true, cs, st);
     for (int s = 0; s < d_.post; ++s) {
@@ -632,18 +604,24 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot) {
 // z = M r, then the new search direction p = z + beta p.  With a post-smoothing
 // sweep on a multilevel hierarchy the r.z products come fused out of the last
 // finest-level sweep; otherwise a separate dot kernel computes them.
-void Problem::precondition_and_direction() {
+VPrep Problem::vprep() const {
+  // the residual producers write the V-cycle's level-0 input (multilevel only)
+  if (lv_.size() < 2) return VPrep{nullptr, nullptr, nullptr, 0};
+  return VPrep{B_[0].invD, B_[0].xa, vbytes_ == 4 ? B_[0].b : nullptr, vbytes_ == 4 ? 1 : 0};
+}
+
+void Problem::precondition_and_direction(bool x0_ready) {
   hipStream_t st = stream_;
   const long nd = lv_[0].L.ndof();
   const int R = d_.nrhs;
   const bool fuse = d_.post >= 1 && lv_.size() > 1;
   const int nbz = fuse ? nblocks_fine() : cg_beta_blocks(nd);
   if (vbytes_ == 8) {
-    vcycle<double>(r_, 1, fuse);
+    vcycle<double>(r_, 1, fuse, x0_ready);
     if (!fuse) cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
     cg_update_p<double>((const double*)zbuf_, p_, r_, rold_, nd, R, cs_, red_, nbz, st);
   } else {
-    vcycle<float>(r_, 1, fuse);
+    vcycle<float>(r_, 1, fuse, x0_ready);
     if (!fuse) cg_beta<float>(r_, rold_, (const float*)zbuf_, nd, R, cs_, red_, st);
     cg_update_p<float>((const float*)zbuf_, p_, r_, rold_, nd, R, cs_, red_, nbz, st);
   }
@@ -657,9 +635,10 @@ void Problem::iteration() {
   timed_begin(0);
   cg_apply_alpha(A, p_, q_, R, cs_, red_, st);
   timed_end(0);
-  cg_update_xr(p_, q_, x_, r_, nd, R, cs_, red_, nblocks_fine(), st);
-  cg_true_residual(A, f_, x_, r_, R, cs_, red_, st);
-  precondition_and_direction();
+  const VPrep vp = vprep();
+  cg_update_xr(p_, q_, x_, r_, nd, R, cs_, red_, nblocks_fine(), vp, st);
+  cg_true_residual(A, f_, x_, r_, R, cs_, red_, vp, st);
+  precondition_and_direction(vp.x0 != nullptr);
   ++iter_launched_;
 }
 
@@ -1004,7 +983,8 @@ void Problem::coarse_solve(const double* b, double* x, int mem) {
   double* xd = tmp.get<double>(n);
   to_dev(b, bd, n, mem, stream_);
   fill<double>(xd, 0.0, n, stream_);
-  v_coarse_solve<double>(Ainv_, dfree_, nc_, lv_[lc].L.ndof(), bd, xd, d_.nrhs, nullptr, stream_);
+  v_coarse_solve<double>(Ainv_, coarse_ld(lv_[lc].L.ndof()), lv_[lc].L.ndof(), bd, xd, d_.nrhs,
+                         nullptr, stream_);
   from_dev(xd, x, n, mem, stream_);
   sync();
 }

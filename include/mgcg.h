@@ -190,7 +190,8 @@ int mgcg_server_submit(mgcg_server* s, mgcg_problem* p, const double* rho, doubl
  * finished ones.  *active / *queued receive the counts after the step. */
 int mgcg_server_step(mgcg_server* s, int* active, int* queued);
 /* MGCG_EAGAIN until the ticket's solve has finished; then its info and the
- * device time from admission to completion in *latency_ms. */
+ * wall time from submission to the step that saw it finish in *latency_ms
+ * (queueing included). */
 int mgcg_server_poll(mgcg_server* s, uint64_t ticket, mgcg_info* info, double* latency_ms);
 /* Release a problem's device memory when it is not in use by a solve
  * (end of a session); MGCG_ESTATE while it is queued or running. */
@@ -200,8 +201,11 @@ size_t mgcg_server_resident_bytes(mgcg_server* s);
 
 /* Pure admission policy (no device): given the budget, the bytes in use, the
  * free slots and the queue's byte sizes in order, writes admit[i] = 1 for the
- * requests admitted now (first-come-first-served; a request that does not fit
- * blocks those behind it) and returns how many. */
+ * requests admitted now and returns how many.  In queue order while slots
+ * are free: a 0-byte request (its problem already resident) is admitted;
+ * requests needing memory are first-come-first-served among themselves (the
+ * first that does not fit blocks the memory-needing ones behind it); an
+ * entry of SIZE_MAX (cannot start now) is skipped. */
 int mgcg_admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
                         int nqueue, uint8_t* admit);
 

@@ -84,6 +84,26 @@ def stiffness(rho, nel, order, nsub, Ksub, E0=1.0, Emin=1e-9, penal=3.0):
     return assemble(element_matrices(rho, nel, nsub, Ksub, E0, Emin, penal), nel, order)
 
 
+def apply(rho, nel, order, nsub, Ksub, u, E0=1.0, Emin=1e-9, penal=3.0, chunk=2048):
+    """K u without forming K: the superposition of K^(e) u_e over the
+    elements (the same sum that assembles K), element chunks at a time to
+    bound memory.  u: [ndof] or [nrhs, ndof]."""
+    u = np.atleast_2d(np.asarray(u, dtype=np.float64))
+    edofs = element_dofs(nel, order)
+    E = simp_modulus(np.ravel(rho), E0, Emin, penal)
+    didx = density_index(nel, nsub)
+    nd = Ksub.shape[1]
+    Kflat = Ksub.reshape(Ksub.shape[0], nd * nd)
+    y = np.zeros_like(u)
+    for e0 in range(0, edofs.shape[0], chunk):
+        ed = edofs[e0:e0 + chunk]
+        Ke = (E[didx[e0:e0 + chunk]] @ Kflat).reshape(-1, nd, nd)
+        for l in range(u.shape[0]):
+            ye = np.einsum("eab,eb->ea", Ke, u[l][ed])
+            y[l] += np.bincount(ed.ravel(), weights=ye.ravel(), minlength=u.shape[1])
+    return y
+
+
 def level_operator(K, mask):
     """Z K Z + (I - Z), Z = diag(free): the supported system written on all
     DOFs with identity rows at fixed DOFs."""

@@ -15,8 +15,15 @@ namespace mgcg {
 
 Problem* problem_impl(mgcg_problem* p);
 
-// First-come-first-served admission: a request that does not fit (slots or
-// bytes) blocks the ones behind it.  Returns the number admitted.
+// Queue entry meaning "cannot start now" (its problem's previous solve still
+// runs): skipped without blocking anything.
+constexpr size_t kCannotStart = ~(size_t)0;
+
+// Admission in queue order while slots are free: a request whose problem is
+// already resident (0 bytes) starts at once; requests that need memory are
+// first-come-first-served among themselves (one that does not fit blocks the
+// memory-needing requests behind it, so large requests are not starved).
+// Returns the number admitted.
 int admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
                    int nqueue, uint8_t* admit);
 

@@ -11,12 +11,20 @@ namespace mgcg {
 int admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
                    int nqueue, uint8_t* admit) {
   int n = 0;
+  bool blocked = false;  // a request needing memory did not fit
   for (int i = 0; i < nqueue; ++i) admit[i] = 0;
-  for (int i = 0; i < nqueue; ++i) {
-    if (free_slots <= 0) break;
-    if (queue_bytes[i] > budget || in_use + queue_bytes[i] > budget) break;
+  for (int i = 0; i < nqueue && free_slots > 0; ++i) {
+    const size_t b = queue_bytes[i];
+    if (b == kCannotStart) continue;
+    if (b > 0) {
+      if (blocked) continue;
+      if (b > budget || in_use + b > budget) {
+        blocked = true;
+        continue;
+      }
+    }
     admit[i] = 1;
-    in_use += queue_bytes[i];
+    in_use += b;
     --free_slots;
     ++n;
   }
@@ -66,22 +74,22 @@ uint64_t Server::submit(Problem* p, const double* rho, double rtol, int maxit, i
 void Server::admit() {
   std::vector<size_t> bytes;
   for (Req* r : queue_) {
-    if (busy(r->p)) {
-      bytes.push_back(budget_ + 1);  // cannot start while its previous solve runs
-      continue;
-    }
-    bytes.push_back(resident_.count(r->p) ? 0 : Problem::device_bytes(r->p->desc()));
+    if (busy(r->p))
+      bytes.push_back(kCannotStart);  // its previous solve is still running
+    else
+      bytes.push_back(resident_.count(r->p) ? 0 : Problem::device_bytes(r->p->desc()));
   }
-  // a problem queued twice in a row cannot both start now
   std::vector<uint8_t> adm(queue_.size(), 0);
   const int free_slots = max_slots_ - (int)running_.size();
-  const int n = admission_plan(budget_, in_use_, free_slots, bytes.data(), (int)bytes.size(), adm.data());
-  for (int i = 0; i < n; ++i) {
-    Req* r = queue_.front();
-    queue_.pop_front();
-    if (busy(r->p)) {  // duplicate of a problem admitted in this same step
-      queue_.push_front(r);
-      break;
+  if (admission_plan(budget_, in_use_, free_slots, bytes.data(), (int)bytes.size(), adm.data()) == 0)
+    return;
+  std::deque<Req*> rest;
+  size_t i = 0;
+  for (Req* r : queue_) {
+    const bool take = adm[i++] && !busy(r->p);  // a problem queued twice starts once per step
+    if (!take) {
+      rest.push_back(r);
+      continue;
     }
     if (!resident_.count(r->p)) {
       r->p->allocate();
@@ -98,6 +106,7 @@ void Server::admit() {
       done_[r->ticket] = r;
     }
   }
+  queue_.swap(rest);
 }
 
 void Server::step(int* active, int* queued) {

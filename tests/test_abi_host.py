@@ -69,7 +69,7 @@ def test_problem_create_rejects_bad_input():
         api.Problem((4, 2, 2), mask, f, nlevels=2, omega=2.5)
 
 
-def test_admission_plan_is_fcfs_and_respects_budget():
+def test_admission_plan_respects_budget_and_order():
     from paper_2311_05595_amd import api
     _lib()
     adm = api.admission_plan(100, 10, 3, [30, 50, 20, 5])
@@ -80,6 +80,15 @@ def test_admission_plan_is_fcfs_and_respects_budget():
     assert adm.tolist() == []
     adm = api.admission_plan(100, 0, 4, [0, 0, 0])      # resident problems cost nothing
     assert adm.tolist() == [True, True, True]
+    # a resident problem's next solve does not wait behind a request that
+    # needs memory; memory-needing requests stay first-come-first-served
+    adm = api.admission_plan(100, 80, 4, [50, 0, 10, 0])
+    assert adm.tolist() == [False, True, False, True]
+    big = np.iinfo(np.uint64).max                        # "cannot start now"
+    adm = api.admission_plan(100, 0, 4, [big, 30, big, 0])
+    assert adm.tolist() == [False, True, False, True]
+    adm = api.admission_plan(100, 0, 1, [0, 0])         # slots still bound
+    assert adm.tolist() == [True, False]
     # never over budget, whatever the queue
     rng = np.random.default_rng(0)
     for _ in range(200):
@@ -87,6 +96,7 @@ def test_admission_plan_is_fcfs_and_respects_budget():
         used = int(rng.integers(0, 100))
         adm = api.admission_plan(100, used, int(rng.integers(0, 5)), q)
         assert used + int(q[adm].sum()) <= 100 or adm.sum() == 0
-        # admitted ones form a prefix
-        k = int(adm.sum())
-        assert adm[:k].all() and not adm[k:].any()
+        # among requests needing memory, the admitted ones form a prefix
+        need = adm[q > 0]
+        k = int(need.sum())
+        assert need[:k].all() and not need[k:].any()

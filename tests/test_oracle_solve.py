@@ -152,3 +152,43 @@ def test_rigid_modes_of_unsupported_assembly():
     # and the supported operator is positive definite
     A = assemble.level_operator(K, W.make_problem("cantilever", *nel, 1, 1)[0])
     assert spla.eigsh(A, k=1, which="SA", return_eigenvectors=False)[0] > 0
+
+
+@pytest.mark.parametrize("order,nsub", [(1, 1), (1, 2), (2, 2)])
+def test_elementwise_apply(order, nsub):
+    """K u without forming K: rigid-body modes give zero force, a linear
+    field gives zero force at interior nodes (patch test), the map is
+    symmetric, and it equals the assembled K (small chunks exercise the
+    chunk loop)."""
+    nel = (3, 2, 2)
+    mask, f, rho, Ks = _setup(nel, order, nsub, seed=4)
+    dims = assemble.node_dims(nel, order)
+    nx, ny, nz = dims
+    z, y, x = np.meshgrid(*(np.arange(d, dtype=float) / (d - 1) for d in (nz, ny, nx)),
+                          indexing="ij")
+    x, y, z = x.ravel() * nel[0], y.ravel() * nel[1], z.ravel() * nel[2]
+    modes = []
+    for c in range(3):
+        m = np.zeros((x.size, 3))
+        m[:, c] = 1.0
+        modes.append(m.ravel())
+    for a, b, p, q in [(0, 1, x, y), (1, 2, y, z), (2, 0, z, x)]:
+        m = np.zeros((x.size, 3))
+        m[:, a], m[:, b] = -q, p
+        modes.append(m.ravel())
+    for m in modes:
+        r = assemble.apply(rho, nel, order, nsub, Ks, m, chunk=5, **MAT)
+        assert np.abs(r).max() <= 1e-12 * np.abs(m).max()
+    # patch test: a linear field (uniform strain) balances at interior nodes
+    lin = np.stack([0.3 * x - 0.2 * y, 0.1 * y + 0.4 * z, -0.25 * z + 0.05 * x], axis=1).ravel()
+    r = assemble.apply(np.ones_like(rho), nel, order, nsub, Ks, lin, **MAT).reshape(-1, 3)
+    interior = ((x > 0) & (x < nel[0]) & (y > 0) & (y < nel[1]) & (z > 0) & (z < nel[2]))
+    assert interior.any()
+    assert np.abs(r[interior]).max() <= 1e-12 * np.abs(r).max()
+    rng = np.random.default_rng(0)
+    u, v = rng.standard_normal((2, lin.size))
+    Ku = assemble.apply(rho, nel, order, nsub, Ks, u, chunk=7, **MAT)[0]
+    Kv = assemble.apply(rho, nel, order, nsub, Ks, v, **MAT)[0]
+    assert abs(v @ Ku - u @ Kv) <= 1e-12 * abs(v @ Ku)
+    K = assemble.stiffness(rho, nel, order, nsub, Ks, **MAT)
+    assert np.abs(Ku - K @ u).max() <= 1e-12 * np.abs(Ku).max()

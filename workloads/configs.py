@@ -60,7 +60,7 @@ def problem(cfg):
     return make_problem(cfg["kind"], nx, ny, nz, cfg["order"], cfg["nrhs"])
 
 
-def coarsest_levels(nel, order=1, max_coarse_dof=2500):
+def coarsest_levels(nel, order=1, max_coarse_dof=700):
     """Number of multigrid levels for a served mesh: halve while every
     element count stays even and the coarse lattice is still large."""
     nx, ny, nz = nel

@@ -91,16 +91,35 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n, "launches": 5}), flush=True)
 
 
-def fine_apply_work(nel, nsub, order, nrhs=1):
-    """Algorithmic flops and bytes of one finest-level operator apply
-    (trilinear, one density per element: the element matvec 24x24 per element
-    = 1152 flop; bytes: read x and E, write y)."""
+def fine_apply_model(nel, nsub, order, nrhs=1):
+    """The finest-level operator of a workload and the algorithmic work of one
+    CG apply q = A p with it (per launch = all elements and load cases):
+    * trilinear, one density per element (matrix-free, unit element matrix
+      scaled per element): 24x24 matvec per element = 1152 flop; bytes: read
+      p and E, write q.  Bound: FP64 ALU.
+    * trilinear with n^3 densities per element (assembled 27-point stencil,
+      symmetric half: 14 blocks of 3x3 per node): bytes: the 126 stencil
+      coefficients per node, read p, write q.  Bound: HBM.
+    * triquadratic (stored 81x81 element matrices): bytes: 6561 coefficients
+      per element, read p, write q.  Bound: HBM."""
     nx, ny, nz = nel
     nelem = nx * ny * nz
-    ndof = 3 * (order * nx + 1) * (order * ny + 1) * (order * nz + 1)
-    flops = 1152.0 * nelem * nrhs
-    bytes_ = 8.0 * (2 * ndof * nrhs + nelem)
-    return flops, bytes_
+    nn = (order * nx + 1) * (order * ny + 1) * (order * nz + 1)
+    ndof = 3 * nn
+    vec = 8.0 * 2 * ndof * nrhs
+    if order == 1 and nsub == 1:
+        return dict(bound="alu", flops=1152.0 * nelem * nrhs, bytes=vec + 8.0 * nelem,
+                    kernel="finest-level CG apply q = A p, matrix-free trilinear (FP64)",
+                    per_unit="1152 flop per element and load case")
+    if order == 1:
+        return dict(bound="hbm", flops=2.0 * 243 * nn * nrhs, bytes=vec + 8.0 * 126 * nn,
+                    kernel="finest-level CG apply q = A p, 27-point stencil (FP64)",
+                    per_unit="126 x 8 B of coefficients per node + 48 B of vectors per node "
+                             "and load case")
+    return dict(bound="hbm", flops=2.0 * 6561 * nelem * nrhs, bytes=vec + 8.0 * 6561 * nelem,
+                kernel="finest-level CG apply q = A p, stored 81x81 element matrices (FP64)",
+                per_unit="6561 x 8 B of element matrix per element + 48 B of vectors per node "
+                         "and load case")
 
 
 def cpu_baseline(cfg, rho_fields, budget_s=25.0):
@@ -114,13 +133,13 @@ def cpu_baseline(cfg, rho_fields, budget_s=25.0):
     import scipy.linalg as sla  # noqa: F401
     from workloads import configs as CF
     mask, f = CF.problem(cfg)
-    nel = cfg["nel"]
+    nel, order, nsub = cfg["nel"], cfg["order"], cfg["nsub"]
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        Ks = fem.sub_element_matrices(1, 1)
-        K = assemble.stiffness(rho_fields[0], nel, 1, 1, Ks)
+        Ks = fem.sub_element_matrices(order, nsub)
+        K = assemble.stiffness(rho_fields[0], nel, order, nsub, Ks)
         A0 = assemble.level_operator(K, mask)
-        H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, 1), cfg["nlevels"])
+        H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, order), cfg["nlevels"])
         weights = multigrid.smoother_weights(H, cfg["omega"])
         t_setup = time.perf_counter() - t0
         # preconditioned CG, same stopping rule, timed per iteration
@@ -154,8 +173,11 @@ def cpu_baseline(cfg, rho_fields, budget_s=25.0):
         rate = (math.log(hist[-1]) - math.log(hist[k])) / max(it - k, 1)
         need = it + (math.log(1e-8) - math.log(hist[-1])) / rate if rate < 0 else float("inf")
     t_solve = t_setup + need * t_iter
+    if cfg["nrhs"] > 1:
+        t_solve *= cfg["nrhs"]  # load cases solved one after the other
     return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
-                sample=(f"oracle (NumPy/SciPy FP64, 1 thread) on the same 96x48x48 system: "
+                sample=(f"oracle (NumPy/SciPy FP64, 1 thread) on the same system "
+                        f"({cfg['name']}, load case 1 timed, x{cfg['nrhs']} load cases): "
                         f"assembly+Galerkin hierarchy {t_setup:.1f} s, {it} MG-preconditioned "
                         f"CG iterations timed ({t_iter:.3f} s each, rel. residual "
                         f"{hist[-1]:.1e}); solve time extrapolated to 1e-8 "
@@ -212,16 +234,20 @@ def run(args):
     kms, kn = prob.kernel_timing(0)
     prob.set_kernel_timing(0, False)
 
-    flops, bytes_ = fine_apply_work(cfg["nel"], cfg["nsub"], cfg["order"], prob.nrhs)
+    m = fine_apply_model(cfg["nel"], cfg["nsub"], cfg["order"], prob.nrhs)
     avg_s = (kms / kn) * 1e-3 if kn else float("nan")
-    achieved = flops / avg_s / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": committed_traffic(),
-                "kernel": "finest-level CG apply q = A p (matrix-free trilinear, FP64)",
+    if m["bound"] == "alu":
+        achieved, peak, unit = m["flops"] / avg_s / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+    else:
+        achieved, peak, unit = m["bytes"] / avg_s / 1e9, PEAK_HBM_GBS, "GB/s"
+    traffic = committed_traffic() if cfg["name"] == CF.config("c2")["name"] else None
+    roofline = {"bound": m["bound"], "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel": m["kernel"], "per_unit": m["per_unit"],
                 "avg_us": round(avg_s * 1e6, 3), "launches": kn,
-                "alg_flop_per_launch": flops, "alg_bytes_per_launch": bytes_,
-                "hbm_GBs_alg": round(bytes_ / avg_s / 1e9, 1)}
+                "alg_flop_per_launch": m["flops"], "alg_bytes_per_launch": m["bytes"],
+                "alg_GBs": round(m["bytes"] / avg_s / 1e9, 1),
+                "alg_TFLOPs": round(m["flops"] / avg_s / 1e12, 3)}
     lat_s = sorted(lat)
     out = {
         "metric": "MGCG solves/s and DOF·CG-iter/s at 1e-8 rel. residual; p50/p99 solve latency",

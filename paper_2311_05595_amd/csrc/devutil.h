@@ -115,6 +115,21 @@ __device__ __forceinline__ bool any_state(const CgScalars* cs, int nrhs, int sta
 
 inline int nblocks(long n, int per = BS) { return (int)((n + per - 1) / per); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Remapping the linear workgroup id so that XCD x walks one contiguous
+// range of tiles keeps the neighbour halos of consecutive tiles in the same
+// L2 (a bijection of [0, gx*gy) for any grid size).  Returns the tile
+// (bx, by) this workgroup handles.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  constexpr int NX = 8;
+  const int gx = gridDim.x, n = gx * gridDim.y;
+  const int b = blockIdx.x + gx * blockIdx.y;
+  const int x = b % NX, i = b / NX, per = n / NX, rem = n % NX;
+  const int t = x * per + (x < rem ? x : rem) + i;
+  bx = t % gx;
+  by = t / gx;
+}
+
 // Vector kernels: each thread handles VU elements i0 + k BS (k < VU) per
 // pass, loads first; the grid is at most 1024 blocks (four per CU), so the
 // per-block partial sums stay few for the kernels that re-sum them, and a

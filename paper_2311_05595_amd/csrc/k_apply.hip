@@ -9,6 +9,8 @@
 // (Algorithm 1, smoothing steps) or a CG step with its dot product.
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "devutil.h"
 
 namespace mgcg {
@@ -88,34 +90,43 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
   const Lat L = op.L;
   const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
   const auto xb = in.buf(r);
-  const uint8_t mself = op.mask[i + (long)L.nx * (j + (long)L.ny * k)];
+  const int node = i + L.nx * (j + L.ny * k);
+  const uint8_t mself = op.mask[node];
+  // Neighbour (dx, dy, dz) sits at a fixed offset from the node; no bounds
+  // checks: a neighbour off the lattice either lies outside the buffer (reads
+  // 0) or wraps onto a finite value of another row, and in both cases it only
+  // enters elements outside the mesh, whose moduli are 0 below.  Per (dy, dz)
+  // row the centre offset is the base (never negative when the row is inside
+  // the lattice), the right neighbour an immediate offset on it, the left one
+  // its own subtraction.
+  // (The byte strides come from the host, so that the compiler keeps one
+  // add per row instead of re-associating into a multiply per row.)
+  constexpr int SN = 3 * sizeof(T);
+  const int sy = op.sy, sz = op.sz;
+  const int noff = node * SN;
   T u[27][3];
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int ii = i + dx - 1, jj = j + dy - 1, kk = k + dz - 1;
-        const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
-                        (unsigned)kk < (unsigned)L.nz;
-        const int s = dx + 3 * (dy + 3 * dz);
-        // buffer loads: a neighbour outside the lattice reads zeros
-        const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T))
-                          : kBufOOB;
-        xb.load(xo, u[s]);
-      }
-  // the 8 element moduli, loaded with the nodal values (elements outside
-  // the mesh read 0)
+    for (int dy = 0; dy < 3; ++dy) {
+      const int c = noff + ((dz - 1) * sz + (dy - 1) * sy);
+      const int s = 3 * (dy + 3 * dz);
+      xb.load(c - SN, u[s]);
+      xb.load(c, u[s + 1]);
+      xb.load(c + SN, u[s + 2]);
+    }
+  // the 8 element moduli, loaded with the nodal values; elements outside
+  // the mesh read 0 (the only place where the mesh boundary is tested)
   const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
+  const bool vx[2] = {i >= 1, i < ex1}, vy[2] = {j >= 1, j < ey1}, vz[2] = {k >= 1, k < ez1};
+  const int eoff = ((i - 1) + ex1 * ((j - 1) + ey1 * (k - 1))) * (int)sizeof(T);
+  const int ey_ = op.ey, ez_ = op.ez;
   T Ev[8];
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
-    const int ex = i - 1 + (o & 1), ey = j - 1 + ((o >> 1) & 1), ez = k - 1 + (o >> 2);
-    const bool ok = (unsigned)ex < (unsigned)ex1 && (unsigned)ey < (unsigned)ey1 &&
-                    (unsigned)ez < (unsigned)ez1;
-    Ev[o] = bload<T>(re, ok ? (int)((ex + (long)ex1 * (ey + (long)ey1 * ez)) * sizeof(T)) : kBufOOB,
-                     0);
+    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+    const bool ok = vx[ox] && vy[oy] && vz[oz];
+    Ev[o] = bload<T>(re, ok ? eoff + (ox * (int)sizeof(T) + oy * ey_ + oz * ez_) : kBufOOB, 0);
   }
   T acc[3] = {T(0), T(0), T(0)};
   if constexpr (sizeof(T) == 8) {
@@ -611,8 +622,9 @@ template <typename T, class Op, class In, class Ep>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(Waves<Op>::w)))
 void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_state, double* part) {
   if (gate && !any_state(gate, nrhs, gate_state)) return;
-  const long node = (long)blockIdx.x * BS + threadIdx.x;
-  const int r = blockIdx.y;
+  int bx, r;
+  xcd_tile(bx, r);
+  const long node = (long)bx * BS + threadIdx.x;
   double a0 = 0.0, a1 = 0.0;
   if (node < op.L.nn() && ep.rhs_on(r)) {
     const typename Ep::Pre pv = ep.pre(r, node);
@@ -621,8 +633,8 @@ void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_stat
     ep.put(r, node, ax, pv, a0, a1);
   }
   if constexpr (Ep::RED) {
-    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + blockIdx.x,
-                   part + (size_t)(4 + r) * MAX_BLOCKS + blockIdx.x);
+    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
+                   part + (size_t)(4 + r) * MAX_BLOCKS + bx);
   }
 }
 
@@ -647,8 +659,9 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
   // there turns each load into a serialised readfirstlane loop)
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / ST_NODES);
   const int lane = threadIdx.x % ST_NODES;
-  const long node = (long)blockIdx.x * ST_NODES + lane;
-  const int r = blockIdx.y;
+  int bx, r;
+  xcd_tile(bx, r);
+  const long node = (long)bx * ST_NODES + lane;
   double a0 = 0.0, a1 = 0.0;
   const bool on = node < op.L.nn() && ep.rhs_on(r);
   T ax[3] = {T(0), T(0), T(0)};
@@ -675,9 +688,29 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
     ep.put(r, node, ax, pv, a0, a1);
   }
   if constexpr (Ep::RED) {
-    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + blockIdx.x,
-                   part + (size_t)(4 + r) * MAX_BLOCKS + blockIdx.x);
+    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
+                   part + (size_t)(4 + r) * MAX_BLOCKS + bx);
   }
+}
+
+// Instrumentation: events attached to the next operator launch receive the
+// kernel's own start and end timestamps (the dispatch packet's, as a
+// profiler's kernel trace records them), not those of separate markers.
+static thread_local hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
+void time_next_apply(hipEvent_t start, hipEvent_t stop) {
+  g_time_start = start;
+  g_time_stop = stop;
+}
+
+template <typename K, typename... Args>
+static void launch_op(K kernel, dim3 grid, hipStream_t st, Args... args) {
+  if (g_time_start) {
+    hipExtLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, g_time_start, g_time_stop, 0, args...);
+    g_time_start = g_time_stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, args...);
+  }
+  MGCG_HIP(hipGetLastError());
 }
 
 template <typename T, class Op, class In, class Ep>
@@ -687,16 +720,12 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
   if constexpr (std::is_same<Op, OpST<T>>::value) {
     const int nb = (int)((nn + ST_NODES - 1) / ST_NODES);
     if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-    hipLaunchKernelGGL((k_apply_st<T, In, Ep>), dim3(nb, nrhs), dim3(BS), 0, st, op, in, ep, nrhs,
-                       gate, gate_state, part);
-    MGCG_HIP(hipGetLastError());
+    launch_op(k_apply_st<T, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
     return;
   }
   const int nb = nblocks(nn);
   if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-  hipLaunchKernelGGL((k_apply<T, Op, In, Ep>), dim3(nb, nrhs), dim3(BS), 0, st, op, in, ep, nrhs,
-                     gate, gate_state, part);
-  MGCG_HIP(hipGetLastError());
+  launch_op(k_apply<T, Op, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
 }
 
 template <typename T>
@@ -1163,7 +1192,9 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
                                                  const T* __restrict__ wDc, T* xc, int nrhs,
                                                  const CgScalars* cs) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
-  const long t = (long)blockIdx.x * BS + threadIdx.x;
+  int bx, r;
+  xcd_tile(bx, r);  // r: load case
+  const long t = (long)bx * BS + threadIdx.x;
   const long cnd = C.ndof();
   if (t >= cnd) return;
   const long node = t / 3;
@@ -1182,7 +1213,6 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
     off[q] = ok ? (int)((3 * (i + (long)F.nx * (j + (long)F.ny * k)) + c) * sizeof(T)) : kBufOOB;
   }
   {
-    const int r = blockIdx.y;  // load case
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(rf + (size_t)r * fnd, (size_t)fnd * sizeof(T));
     T acc = T(0);
 #pragma unroll
@@ -1216,7 +1246,9 @@ __global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __r
                                                 const T* __restrict__ ec, T* xf, int nrhs,
                                                 int accumulate, const CgScalars* cs) {
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
-  const long node = (long)blockIdx.x * BS + threadIdx.x;
+  int bx, r;
+  xcd_tile(bx, r);  // r: load case
+  const long node = (long)bx * BS + threadIdx.x;
   if (node >= F.nn()) return;
   int i, j, k;
   node_ijk(node, F, i, j, k);
@@ -1236,7 +1268,6 @@ __global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __r
   }
   const long fnd = F.ndof(), cnd = C.ndof();
   {
-    const int r = blockIdx.y;  // load case
     // coarse corrections vanish on fixed coarse DOFs
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(ec + (size_t)r * cnd, (size_t)cnd * sizeof(T));
     // the old fine value (accumulate) is read branch-free together with

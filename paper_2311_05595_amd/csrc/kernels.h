@@ -24,6 +24,14 @@ struct OpMF {
   const T* E;
   Q1Vals<T> kv;
   const uint8_t* mask;
+  // byte strides between nodes of neighbouring rows / planes of a vector and
+  // between elements of neighbouring rows / planes of E (set by make())
+  int sy, sz, ey, ez;
+  static OpMF make(Lat L, const T* E, Q1Vals<T> kv, const uint8_t* mask) {
+    const int sn = 3 * (int)sizeof(T);
+    return OpMF{L, E, kv, mask, L.nx * sn, L.nx * L.ny * sn, (L.nx - 1) * (int)sizeof(T),
+                (L.nx - 1) * (L.ny - 1) * (int)sizeof(T)};
+  }
 };
 
 // Assembled 27-point block stencil, symmetric half storage: coef[(b*9 + 3c + e) * nn + node]
@@ -47,6 +55,10 @@ struct OpEQ2 {
 // Reduction scratch: one partial sum per block and value, in regions that
 // stay untouched until their consumer has read them:
 //   partials[region * RED_REGION + v * MAX_BLOCKS + block], v < 8.
+// Attach the events to the next operator launch on this thread (they then
+// hold that kernel's own start and end timestamps).
+void time_next_apply(hipEvent_t start, hipEvent_t stop);
+
 struct RedBuf {
   double* partials;
 };

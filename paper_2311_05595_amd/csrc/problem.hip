@@ -419,7 +419,7 @@ FineOp Problem::fine_op() const {
   FineOp A{};
   A.kind = lv_[0].kind;
   const Lat L = lv_[0].L;
-  A.mf = OpMF<double>{L, E_, kv64_, B_[0].mask};
+  A.mf = OpMF<double>::make(L, E_, kv64_, B_[0].mask);
   A.st = OpST<double>{L, vbytes_ == 8 ? (const double*)B_[0].coefV : B_[0].coef64};
   A.eq2 = OpEQ2<double>{L, Keff_, B_[0].mask};
   return A;
@@ -433,10 +433,10 @@ VOps<T> Problem::vops(int l) const {
   v.mask = B_[l].mask;
   v.invD = (const T*)B_[l].invD;
   if constexpr (sizeof(T) == 8) {
-    v.mf = OpMF<T>{v.L, E_, kv64_, B_[l].mask};
+    v.mf = OpMF<T>::make(v.L, E_, kv64_, B_[l].mask);
     v.eq2 = OpEQ2<T>{v.L, Keff_, B_[l].mask};
   } else {
-    v.mf = OpMF<T>{v.L, E32_, kv32_, B_[l].mask};
+    v.mf = OpMF<T>::make(v.L, E32_, kv32_, B_[l].mask);
     v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask};
   }
   v.st = OpST<T>{v.L, (const T*)B_[l].coefV};
@@ -1006,12 +1006,11 @@ void Problem::timed_begin(int id) {
     MGCG_HIP(hipEventCreate(&b));
     timer_.pool.push_back({a, b});
   }
-  MGCG_HIP(hipEventRecord(timer_.pool[timer_.used].first, stream_));
+  time_next_apply(timer_.pool[timer_.used].first, timer_.pool[timer_.used].second);
 }
 
 void Problem::timed_end(int id) {
   if (!timer_.enabled || id != timer_.kernel) return;
-  MGCG_HIP(hipEventRecord(timer_.pool[timer_.used].second, stream_));
   timer_.recs.push_back(iter_launched_);
   ++timer_.used;
 }

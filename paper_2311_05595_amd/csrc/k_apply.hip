@@ -80,6 +80,39 @@ __device__ __forceinline__ void node_ijk(long node, const Lat& L, int& i, int& j
   k = (int)kk;
 }
 
+// sum_e E_e (K0 u_e) rows of the node for the 8 elements around it, FP64:
+// 24 independent accumulators (8 elements x 3 rows), local node b outermost,
+// so consecutive FMAs never depend on each other.  u: the 3x3x3 neighbour
+// values (index dx + 3 (dy + 3 dz)); E: moduli of the elements (ox, oy, oz).
+__device__ __forceinline__ void mf_rows_fp64(const Q1Vals<double>& kv, const double (&u)[27][3],
+                                             const double (&Ev)[8], double acc[3]) {
+  double t[8][3];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = 0.0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+        const int s = (ox + bx) + 3 * ((oy + by) + 3 * (oz + bz));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int q = (3 * a + c) * 24 + 3 * b + e;
+          const double kk = kQ1.sgn[q] > 0 ? kv.v[kQ1.cls[q]] : -kv.v[kQ1.cls[q]];
+          t[o][c] = fma(kk, u[s][e], t[o][c]);
+        }
+      }
+  }
+#pragma unroll
+  for (int o = 0; o < 8; ++o)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = fma(Ev[o], t[o][c], acc[c]);
+}
+
 // Matrix-free trilinear apply at node (i,j,k): the three rows of
 // sum_e E_e K0 u_e over the (up to) 8 elements around the node, K0 entries
 // taken from the 10 class values (scalar registers) with compile-time class
@@ -130,34 +163,7 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
   }
   T acc[3] = {T(0), T(0), T(0)};
   if constexpr (sizeof(T) == 8) {
-    // FP64 (occupancy 2 either way): 24 independent accumulators (8 elements
-    // x 3 rows), local node b outermost, so consecutive FMAs never depend on
-    // each other
-    T t[8][3];
-#pragma unroll
-    for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = T(0);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
-#pragma unroll
-      for (int e = 0; e < 3; ++e)
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-          const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-          const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
-          const int s = (ox + bx) + 3 * ((oy + by) + 3 * (oz + bz));
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const int q = (3 * a + c) * 24 + 3 * b + e;
-            const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
-            t[o][c] = fma(kk, u[s][e], t[o][c]);
-          }
-        }
-    }
-#pragma unroll
-    for (int o = 0; o < 8; ++o)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] = fma(Ev[o], t[o][c], acc[c]);
+    mf_rows_fp64(op.kv, u, Ev, acc);
   } else {
     // FP32: element by element keeps registers low (occupancy 8)
 #pragma unroll
@@ -638,6 +644,154 @@ void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_stat
   }
 }
 
+// FP64 matrix-free apply with the block's neighbourhood staged in LDS.  The
+// 256 consecutive nodes of a block touch, on each of the three node planes
+// around them, one contiguous range of 256 + 2 nx + 2 nodes.  The block
+// loads those three ranges with coalesced loads (about 16 per thread instead
+// of the 27 two-part gathers per node that keep the address unit busy), and
+// every thread then reads its 27 neighbours from LDS.  Off-lattice
+// neighbours: as in ax_mf (they only meet elements of zero modulus).
+// Dynamic LDS: 3 planes x 3 lr doubles; the staging covers up to
+// MF_LDS_VALS x BS values per plane.
+constexpr int MF_LDS_VALS = 8;
+inline int mf_lds_range(const Lat& L) { return BS + 2 * L.nx + 2; }
+inline bool mf_lds_fits(const Lat& L) { return 3 * mf_lds_range(L) <= MF_LDS_VALS * BS; }
+
+template <class Ep>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_apply_mf_lds(OpMF<double> op, InPlain<double> in, Ep ep, int nrhs, const CgScalars* gate,
+                    int gate_state, double* part) {
+  if (gate && !any_state(gate, nrhs, gate_state)) return;
+  extern __shared__ double sh[];
+  int bx, r;
+  xcd_tile(bx, r);
+  const Lat L = op.L;
+  const int nn = (int)L.nn();
+  const int nx = L.nx, P = L.nx * L.ny;
+  const int lr = BS + 2 * nx + 2, nd3 = 3 * lr;
+  const int n0 = bx * BS;
+  const int t_ = threadIdx.x;
+  // stage: plane sgi (dz = sgi - 1) holds nodes [n0 + dz P - nx - 1, + lr)
+  {
+    const __amdgpu_buffer_rsrc_t rx =
+        make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(double));
+    // 8-byte loads: each value is range-checked on its own (values off the
+    // vector read exactly 0)
+    // (a value past its plane's range is still loaded, from the vector or as
+    // 0 beyond it, and simply not stored: no per-load select)
+    double v[3][MF_LDS_VALS];
+    const int off0 = (3 * (n0 - P - nx - 1) + t_) * (int)sizeof(double);  // may be negative
+    const int pstride = 3 * P * (int)sizeof(double);
+#pragma unroll
+    for (int sgi = 0; sgi < 3; ++sgi)
+#pragma unroll
+      for (int m = 0; m < MF_LDS_VALS; ++m)
+        v[sgi][m] = bload<double>(rx, off0 + (sgi * pstride + m * BS * (int)sizeof(double)), 0);
+#pragma unroll
+    for (int sgi = 0; sgi < 3; ++sgi)
+#pragma unroll
+      for (int m = 0; m < MF_LDS_VALS; ++m) {
+        const int q = t_ + m * BS;
+        if (q < nd3) sh[sgi * nd3 + q] = v[sgi][m];
+      }
+  }
+  const int node = n0 + t_;
+  const int nodec = node < nn ? node : nn - 1;  // tail threads compute a copy, store nothing
+  int i, j, k;
+  node_ijk(nodec, L, i, j, k);
+  const uint8_t mself = op.mask[nodec];
+  // small epilogue operand sets (three values) are loaded with the stage, so
+  // that their latency hides behind the arithmetic; larger ones would push
+  // the kernel past 128 registers and load after it
+  constexpr bool kEarly = sizeof(typename Ep::Pre) <= 3 * sizeof(double);
+  typename Ep::Pre pv{};
+  if constexpr (kEarly) pv = ep.pre(r, nodec);
+  // the 8 element moduli (elements outside the mesh read 0)
+  const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(double));
+  const bool vx[2] = {i >= 1, i < ex1}, vy[2] = {j >= 1, j < ey1}, vz[2] = {k >= 1, k < ez1};
+  const int eoff = ((i - 1) + ex1 * ((j - 1) + ey1 * (k - 1))) * (int)sizeof(double);
+  double Ev[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+    const bool ok = vx[ox] && vy[oy] && vz[oz];
+    Ev[o] = bload<double>(re, ok ? eoff + (ox * (int)sizeof(double) + oy * op.ey + oz * op.ez)
+                                 : kBufOOB, 0);
+  }
+  __syncthreads();
+  // Neighbour rows (dy, dz) of 3 nodes are read from LDS one at a time and
+  // folded into the 24 element partial sums, so only one row is live in
+  // registers (four waves fit per SIMD: every wave of a 0.7M-DOF apply is
+  // resident at once).  Node (dx, dy, dz) is local node b = s - o of each
+  // element o that contains it.
+  // One row of lookahead: the reads of row w + 1 are issued before the
+  // arithmetic of row w; compiler memory fences keep further reads from
+  // being hoisted (which would make all 27 nodes live again).
+  double t[8][3];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = 0.0;
+  auto read_row = [&](int w, double (&ur)[3][3]) {
+    const int dz = w / 3, dy = w % 3;
+    const double* row = sh + dz * nd3 + 3 * (t_ + nx + (dy - 1) * nx);
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ur[dx][c] = row[3 * dx + c];
+  };
+  double ur[2][3][3];
+  read_row(0, ur[0]);
+#pragma unroll
+  for (int w = 0; w < 9; ++w) {
+    if (w + 1 < 9) read_row(w + 1, ur[(w + 1) & 1]);
+    asm volatile("" ::: "memory");
+    const int dz = w / 3, dy = w % 3;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+        const int bx = dx - ox, by = dy - oy, bz = dz - oz;
+        if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+        const int b = bx + 2 * by + 4 * bz;
+        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int q = (3 * a + c) * 24 + 3 * b + e;
+            const double kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
+            t[o][c] = fma(kk, ur[w & 1][dx][e], t[o][c]);
+          }
+      }
+    // the fence consumes the accumulators: this row's arithmetic completes
+    // before the next reads are issued
+    asm volatile(""
+                 : "+v"(t[0][0]), "+v"(t[0][1]), "+v"(t[0][2]), "+v"(t[1][0]), "+v"(t[1][1]),
+                   "+v"(t[1][2]), "+v"(t[2][0]), "+v"(t[2][1]), "+v"(t[2][2]), "+v"(t[3][0]),
+                   "+v"(t[3][1]), "+v"(t[3][2]), "+v"(t[4][0]), "+v"(t[4][1]), "+v"(t[4][2]),
+                   "+v"(t[5][0]), "+v"(t[5][1]), "+v"(t[5][2]), "+v"(t[6][0]), "+v"(t[6][1]),
+                   "+v"(t[6][2]), "+v"(t[7][0]), "+v"(t[7][1]), "+v"(t[7][2])
+                 :
+                 : "memory");
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int o = 0; o < 8; ++o)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = fma(Ev[o], t[o][c], acc[c]);
+  if constexpr (!kEarly) pv = ep.pre(r, nodec);
+  double ax[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ax[c] = ((mself >> c) & 1) ? 0.0 : acc[c];
+  double a0 = 0.0, a1 = 0.0;
+  if (node < nn && ep.rhs_on(r)) ep.put(r, node, ax, pv, a0, a1);
+  if constexpr (Ep::RED) {
+    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
+                   part + (size_t)(4 + r) * MAX_BLOCKS + bx);
+  }
+}
+
 // Stencil operators: the 4 waves of a block share 64 consecutive nodes, wave
 // w summing the stencil blocks b = w (mod 4) (coalesced loads, a quarter of
 // the load chain per lane, 4x the waves of one-thread-per-node); the four
@@ -693,6 +847,12 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
   }
 }
 
+int apply_blocks(int kind, long nn, bool fp64) {
+  (void)fp64;  // every matrix-free variant in use maps one node per thread
+  if (kind == OP_ST27) return (int)((nn + ST_NODES - 1) / ST_NODES);
+  return nblocks(nn);
+}
+
 // Instrumentation: events attached to the next operator launch receive the
 // kernel's own start and end timestamps (the dispatch packet's, as a
 // profiler's kernel trace records them), not those of separate markers.
@@ -700,6 +860,18 @@ static thread_local hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
 void time_next_apply(hipEvent_t start, hipEvent_t stop) {
   g_time_start = start;
   g_time_stop = stop;
+}
+
+template <typename K, typename... Args>
+static void launch_op_lds(K kernel, dim3 grid, size_t lds, hipStream_t st, Args... args) {
+  if (g_time_start) {
+    hipExtLaunchKernelGGL(kernel, grid, dim3(BS), (uint32_t)lds, st, g_time_start, g_time_stop, 0,
+                          args...);
+    g_time_start = g_time_stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, dim3(BS), lds, st, args...);
+  }
+  MGCG_HIP(hipGetLastError());
 }
 
 template <typename K, typename... Args>
@@ -722,6 +894,16 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
     if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
     launch_op(k_apply_st<T, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
     return;
+  }
+  if constexpr (std::is_same<Op, OpMF<double>>::value && std::is_same<In, InPlain<double>>::value) {
+    if (mf_lds_fits(op.L)) {
+      const int nb = nblocks(nn);
+      if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+      const size_t lds = (size_t)9 * mf_lds_range(op.L) * sizeof(double);
+      launch_op_lds(k_apply_mf_lds<Ep>, dim3(nb, nrhs), lds, st, op, in, ep, nrhs, gate,
+                    gate_state, part);
+      return;
+    }
   }
   const int nb = nblocks(nn);
   if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
@@ -772,10 +954,7 @@ static void fine_dispatch(const FineOp& A, const In& in, const Ep& ep, int nrhs,
   }
 }
 
-static int fine_blocks(const FineOp& A) {
-  return A.kind == OP_ST27 ? (int)((A.lat().nn() + ST_NODES - 1) / ST_NODES)
-                           : nblocks(A.lat().nn());
-}
+static int fine_blocks(const FineOp& A) { return apply_blocks(A.kind, A.lat().nn(), true); }
 
 __global__ void k_fin_init(CgScalars* cs, int nrhs, const double* part, int nb) {
   __shared__ double sh[BS / 64];

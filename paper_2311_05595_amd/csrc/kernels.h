@@ -55,6 +55,10 @@ struct OpEQ2 {
 // Reduction scratch: one partial sum per block and value, in regions that
 // stay untouched until their consumer has read them:
 //   partials[region * RED_REGION + v * MAX_BLOCKS + block], v < 8.
+// Workgroups (and hence reduction partials) of one operator apply on a
+// lattice of nn nodes: kind OpKind, fp64 = the FP64 instantiation.
+int apply_blocks(int kind, long nn, bool fp64);
+
 // Attach the events to the next operator launch on this thread (they then
 // hold that kernel's own start and end timestamps).
 void time_next_apply(hipEvent_t start, hipEvent_t stop);

@@ -108,7 +108,7 @@ class Problem {
   void iteration();
   void build_linear_galerkin();
   FineOp fine_op() const;
-  int nblocks_fine() const;
+  int nblocks_fine(bool fp64) const;
   void sync();
   void check_bad(int which);
   void timed_begin(int id);

@@ -409,10 +409,10 @@ void Problem::build_linear_galerkin() {
 }
 
 // Blocks per load case of the finest-level apply (the number of per-block
-// partial sums its reducing epilogues produce).
-int Problem::nblocks_fine() const {
-  const long nn = lv_[0].L.nn();
-  return (int)(lv_[0].kind == OP_ST27 ? (nn + 63) / 64 : (nn + 255) / 256);
+// partial sums its reducing epilogues produce), in FP64 or in the V-cycle
+// precision.
+int Problem::nblocks_fine(bool fp64) const {
+  return apply_blocks(lv_[0].kind, lv_[0].L.nn(), fp64);
 }
 
 FineOp Problem::fine_op() const {
@@ -615,7 +615,7 @@ void Problem::precondition_and_direction(bool x0_ready) {
   const long nd = lv_[0].L.ndof();
   const int R = d_.nrhs;
   const bool fuse = d_.post >= 1 && lv_.size() > 1;
-  const int nbz = fuse ? nblocks_fine() : cg_beta_blocks(nd);
+  const int nbz = fuse ? nblocks_fine(vbytes_ == 8) : cg_beta_blocks(nd);
   if (vbytes_ == 8) {
     vcycle<double>(r_, 1, fuse, x0_ready);
     if (!fuse) cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
@@ -636,7 +636,7 @@ void Problem::iteration() {
   cg_apply_alpha(A, p_, q_, R, cs_, red_, st);
   timed_end(0);
   const VPrep vp = vprep();
-  cg_update_xr(p_, q_, x_, r_, nd, R, cs_, red_, nblocks_fine(), vp, st);
+  cg_update_xr(p_, q_, x_, r_, nd, R, cs_, red_, nblocks_fine(true), vp, st);
   cg_true_residual(A, f_, x_, r_, R, cs_, red_, vp, st);
   precondition_and_direction(vp.x0 != nullptr);
   ++iter_launched_;

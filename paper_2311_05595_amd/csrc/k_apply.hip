@@ -644,7 +644,8 @@ void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_stat
   }
 }
 
-// FP64 matrix-free apply with the block's neighbourhood staged in LDS.  The
+// Matrix-free apply (FP64 or FP32) with the block's neighbourhood staged in
+// LDS.  The
 // 256 consecutive nodes of a block touch, on each of the three node planes
 // around them, one contiguous range of 256 + 2 nx + 2 nodes.  The block
 // loads those three ranges with coalesced loads (about 16 per thread instead
@@ -657,12 +658,13 @@ constexpr int MF_LDS_VALS = 8;
 inline int mf_lds_range(const Lat& L) { return BS + 2 * L.nx + 2; }
 inline bool mf_lds_fits(const Lat& L) { return 3 * mf_lds_range(L) <= MF_LDS_VALS * BS; }
 
-template <class Ep>
+template <typename T, class Ep>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void k_apply_mf_lds(OpMF<double> op, InPlain<double> in, Ep ep, int nrhs, const CgScalars* gate,
+void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars* gate,
                     int gate_state, double* part) {
   if (gate && !any_state(gate, nrhs, gate_state)) return;
-  extern __shared__ double sh[];
+  extern __shared__ __align__(16) unsigned char sh_raw[];
+  T* sh = reinterpret_cast<T*>(sh_raw);
   int bx, r;
   xcd_tile(bx, r);
   const Lat L = op.L;
@@ -674,19 +676,19 @@ void k_apply_mf_lds(OpMF<double> op, InPlain<double> in, Ep ep, int nrhs, const 
   // stage: plane sgi (dz = sgi - 1) holds nodes [n0 + dz P - nx - 1, + lr)
   {
     const __amdgpu_buffer_rsrc_t rx =
-        make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(double));
+        make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
     // 8-byte loads: each value is range-checked on its own (values off the
     // vector read exactly 0)
     // (a value past its plane's range is still loaded, from the vector or as
     // 0 beyond it, and simply not stored: no per-load select)
-    double v[3][MF_LDS_VALS];
-    const int off0 = (3 * (n0 - P - nx - 1) + t_) * (int)sizeof(double);  // may be negative
-    const int pstride = 3 * P * (int)sizeof(double);
+    T v[3][MF_LDS_VALS];
+    const int off0 = (3 * (n0 - P - nx - 1) + t_) * (int)sizeof(T);  // may be negative
+    const int pstride = 3 * P * (int)sizeof(T);
 #pragma unroll
     for (int sgi = 0; sgi < 3; ++sgi)
 #pragma unroll
       for (int m = 0; m < MF_LDS_VALS; ++m)
-        v[sgi][m] = bload<double>(rx, off0 + (sgi * pstride + m * BS * (int)sizeof(double)), 0);
+        v[sgi][m] = bload<T>(rx, off0 + (sgi * pstride + m * BS * (int)sizeof(T)), 0);
 #pragma unroll
     for (int sgi = 0; sgi < 3; ++sgi)
 #pragma unroll
@@ -703,21 +705,20 @@ void k_apply_mf_lds(OpMF<double> op, InPlain<double> in, Ep ep, int nrhs, const 
   // small epilogue operand sets (three values) are loaded with the stage, so
   // that their latency hides behind the arithmetic; larger ones would push
   // the kernel past 128 registers and load after it
-  constexpr bool kEarly = sizeof(typename Ep::Pre) <= 3 * sizeof(double);
+  constexpr bool kEarly = sizeof(typename Ep::Pre) <= 3 * sizeof(double);  // 3 FP64 / 6 FP32
   typename Ep::Pre pv{};
   if constexpr (kEarly) pv = ep.pre(r, nodec);
   // the 8 element moduli (elements outside the mesh read 0)
   const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
-  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(double));
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
   const bool vx[2] = {i >= 1, i < ex1}, vy[2] = {j >= 1, j < ey1}, vz[2] = {k >= 1, k < ez1};
-  const int eoff = ((i - 1) + ex1 * ((j - 1) + ey1 * (k - 1))) * (int)sizeof(double);
-  double Ev[8];
+  const int eoff = ((i - 1) + ex1 * ((j - 1) + ey1 * (k - 1))) * (int)sizeof(T);
+  T Ev[8];
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
     const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
     const bool ok = vx[ox] && vy[oy] && vz[oz];
-    Ev[o] = bload<double>(re, ok ? eoff + (ox * (int)sizeof(double) + oy * op.ey + oz * op.ez)
-                                 : kBufOOB, 0);
+    Ev[o] = bload<T>(re, ok ? eoff + (ox * (int)sizeof(T) + oy * op.ey + oz * op.ez) : kBufOOB, 0);
   }
   __syncthreads();
   // Neighbour rows (dy, dz) of 3 nodes are read from LDS one at a time and
@@ -728,18 +729,18 @@ void k_apply_mf_lds(OpMF<double> op, InPlain<double> in, Ep ep, int nrhs, const 
   // One row of lookahead: the reads of row w + 1 are issued before the
   // arithmetic of row w; compiler memory fences keep further reads from
   // being hoisted (which would make all 27 nodes live again).
-  double t[8][3];
+  T t[8][3];
 #pragma unroll
-  for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = 0.0;
-  auto read_row = [&](int w, double (&ur)[3][3]) {
+  for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = T(0);
+  auto read_row = [&](int w, T (&ur)[3][3]) {
     const int dz = w / 3, dy = w % 3;
-    const double* row = sh + dz * nd3 + 3 * (t_ + nx + (dy - 1) * nx);
+    const T* row = sh + dz * nd3 + 3 * (t_ + nx + (dy - 1) * nx);
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
       for (int c = 0; c < 3; ++c) ur[dx][c] = row[3 * dx + c];
   };
-  double ur[2][3][3];
+  T ur[2][3][3];
   read_row(0, ur[0]);
 #pragma unroll
   for (int w = 0; w < 9; ++w) {
@@ -760,7 +761,7 @@ void k_apply_mf_lds(OpMF<double> op, InPlain<double> in, Ep ep, int nrhs, const 
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const int q = (3 * a + c) * 24 + 3 * b + e;
-            const double kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
+            const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
             t[o][c] = fma(kk, ur[w & 1][dx][e], t[o][c]);
           }
       }
@@ -775,15 +776,15 @@ void k_apply_mf_lds(OpMF<double> op, InPlain<double> in, Ep ep, int nrhs, const 
                  :
                  : "memory");
   }
-  double acc[3] = {0.0, 0.0, 0.0};
+  T acc[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int o = 0; o < 8; ++o)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] = fma(Ev[o], t[o][c], acc[c]);
   if constexpr (!kEarly) pv = ep.pre(r, nodec);
-  double ax[3];
+  T ax[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) ax[c] = ((mself >> c) & 1) ? 0.0 : acc[c];
+  for (int c = 0; c < 3; ++c) ax[c] = ((mself >> c) & 1) ? T(0) : acc[c];
   double a0 = 0.0, a1 = 0.0;
   if (node < nn && ep.rhs_on(r)) ep.put(r, node, ax, pv, a0, a1);
   if constexpr (Ep::RED) {
@@ -895,12 +896,12 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
     launch_op(k_apply_st<T, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
     return;
   }
-  if constexpr (std::is_same<Op, OpMF<double>>::value && std::is_same<In, InPlain<double>>::value) {
+  if constexpr (std::is_same<Op, OpMF<T>>::value && std::is_same<In, InPlain<T>>::value) {
     if (mf_lds_fits(op.L)) {
       const int nb = nblocks(nn);
       if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-      const size_t lds = (size_t)9 * mf_lds_range(op.L) * sizeof(double);
-      launch_op_lds(k_apply_mf_lds<Ep>, dim3(nb, nrhs), lds, st, op, in, ep, nrhs, gate,
+      const size_t lds = (size_t)9 * mf_lds_range(op.L) * sizeof(T);
+      launch_op_lds(k_apply_mf_lds<T, Ep>, dim3(nb, nrhs), lds, st, op, in, ep, nrhs, gate,
                     gate_state, part);
       return;
     }

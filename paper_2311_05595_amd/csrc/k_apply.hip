@@ -387,6 +387,116 @@ __device__ __forceinline__ void ax_any(const OpEQ2<T>& op, const In& in, int r, 
   ax_eq2(op, in, r, i, j, k, y);
 }
 
+// Second pass of the stored-matrix triquadratic apply: a node sums the rows
+// of the element products K_e u_e (first pass) of the 1..8 elements that
+// contain it; fixed rows return the input (identity rows).
+template <typename T>
+struct OpEQ2Y {
+  Lat L;
+  const T* Y;
+  const uint8_t* mask;
+};
+template <typename T, class In>
+__device__ __forceinline__ void ax_any(const OpEQ2Y<T>& op, const In& in, int r, long node, T y[3]) {
+  const Lat L = op.L;
+  int i, j, k;
+  node_ijk(node, L, i, j, k);
+  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
+  const long nel = (long)nex * ney * nez;
+  int es[3][2], as[3][2], ne[3];
+  const int p[3] = {i, j, k}, nmax[3] = {nex, ney, nez};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ne[d] = 0;
+    if (p[d] & 1) {
+      es[d][0] = (p[d] - 1) / 2;
+      as[d][0] = 1;
+      ne[d] = 1;
+    } else {
+      if (p[d] / 2 - 1 >= 0) { es[d][ne[d]] = p[d] / 2 - 1; as[d][ne[d]] = 2; ++ne[d]; }
+      if (p[d] / 2 < nmax[d]) { es[d][ne[d]] = p[d] / 2; as[d][ne[d]] = 0; ++ne[d]; }
+    }
+  }
+  T acc[3] = {T(0), T(0), T(0)};
+  const T* Yr = op.Y + (size_t)r * nel * 81;
+  for (int cz = 0; cz < ne[2]; ++cz)
+    for (int cy = 0; cy < ne[1]; ++cy)
+      for (int cx = 0; cx < ne[0]; ++cx) {
+        const long e = es[0][cx] + (long)nex * (es[1][cy] + (long)ney * es[2][cz]);
+        const int a = as[0][cx] + 3 * (as[1][cy] + 3 * as[2][cz]);
+        const T* ye = Yr + e * 81 + 3 * a;
+        acc[0] += ye[0];
+        acc[1] += ye[1];
+        acc[2] += ye[2];
+      }
+  const uint8_t m = op.mask[node];
+  if (m) {
+    T v[3];
+    in.load(r, node, v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if ((m >> c) & 1) acc[c] = v[c];
+  }
+  y[0] = acc[0];
+  y[1] = acc[1];
+  y[2] = acc[2];
+}
+
+// First pass: y_e = K_e u_e for every element and load case, one thread per
+// (element, row), three elements per block.  K_e is symmetric, so its stored
+// rows are also its columns: thread `row` reads K_e[col][row] for col =
+// 0..80 and the 81 threads of an element read 81 consecutive values per step
+// (coalesced streaming of the 6561 coefficients, the apply's dominant
+// traffic); each coefficient read serves every load case.  u_e of every load
+// case is staged in LDS and read as a broadcast.
+constexpr int EQ_EPB = 3;  // elements per block (243 of 256 threads busy)
+template <typename T, int NR, class In>
+__global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
+                                                  const CgScalars* gate, int gate_state) {
+  if (gate && !any_state(gate, nrhs, gate_state)) return;
+  __shared__ T ue[NR][EQ_EPB][81];
+  int bx, by;
+  xcd_tile(bx, by);
+  const Lat L = op.L;
+  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
+  const long nel = (long)nex * ney * nez;
+  const int le = threadIdx.x / 81, row = threadIdx.x - 81 * le;
+  const long e = (long)bx * EQ_EPB + le;
+  const bool on = le < EQ_EPB && e < nel;
+  if (on) {
+    const int ex = (int)(e % nex), ey = (int)((e / nex) % ney), ez = (int)(e / ((long)nex * ney));
+    const int b = row / 3, comp = row - 3 * b;
+    const int bxl = b % 3, byl = (b / 3) % 3, bzl = b / 9;
+    const long node = (2 * ex + bxl) + (long)L.nx * ((2 * ey + byl) + (long)L.ny * (2 * ez + bzl));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T v[3];
+      in.load(r, node, v);
+      ue[r][le][row] = v[comp];
+    }
+  }
+  __syncthreads();
+  if (!on) return;
+  const T* Kc = op.Ke + (size_t)e * 6561 + row;
+  T acc[NR][2];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r][0] = acc[r][1] = T(0);
+#pragma unroll 9
+  for (int col = 0; col < 80; col += 2) {
+    const T k0 = Kc[(size_t)col * 81], k1 = Kc[(size_t)(col + 1) * 81];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      acc[r][0] = fma(k0, ue[r][le][col], acc[r][0]);
+      acc[r][1] = fma(k1, ue[r][le][col + 1], acc[r][1]);
+    }
+  }
+  const T k80 = Kc[(size_t)80 * 81];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    op.Y[((size_t)r * nel + e) * 81 + row] = fma(k80, ue[r][le][80], acc[r][0] + acc[r][1]);
+  (void)by;
+}
+
 // ------------------------------------------------------------ epilogues
 // pre(r, node) loads the epilogue's operands and is called before the
 // operator's gathers, so that those loads travel with them; put() then only
@@ -865,7 +975,7 @@ void time_next_apply(hipEvent_t start, hipEvent_t stop) {
 
 template <typename K, typename... Args>
 static void launch_op_lds(K kernel, dim3 grid, size_t lds, hipStream_t st, Args... args) {
-  if (g_time_start) {
+  if (g_time_start || g_time_stop) {
     hipExtLaunchKernelGGL(kernel, grid, dim3(BS), (uint32_t)lds, st, g_time_start, g_time_stop, 0,
                           args...);
     g_time_start = g_time_stop = nullptr;
@@ -877,7 +987,7 @@ static void launch_op_lds(K kernel, dim3 grid, size_t lds, hipStream_t st, Args.
 
 template <typename K, typename... Args>
 static void launch_op(K kernel, dim3 grid, hipStream_t st, Args... args) {
-  if (g_time_start) {
+  if (g_time_start || g_time_stop) {
     hipExtLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, g_time_start, g_time_stop, 0, args...);
     g_time_start = g_time_stop = nullptr;
   } else {
@@ -894,6 +1004,27 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
     const int nb = (int)((nn + ST_NODES - 1) / ST_NODES);
     if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
     launch_op(k_apply_st<T, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
+    return;
+  }
+  if constexpr (std::is_same<Op, OpEQ2<T>>::value) {
+    // two passes: element products, then the node gather with the epilogue
+    // (timing events, when set, span both)
+    const int ne = (int)(((long)(op.L.nx - 1) / 2 * ((op.L.ny - 1) / 2) * ((op.L.nz - 1) / 2) +
+                          EQ_EPB - 1) / EQ_EPB);
+    hipEvent_t t_stop = g_time_stop;
+    g_time_stop = nullptr;
+    switch (nrhs) {
+      case 1: launch_op(k_eq2_elem<T, 1, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+      case 2: launch_op(k_eq2_elem<T, 2, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+      case 3: launch_op(k_eq2_elem<T, 3, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+      default: launch_op(k_eq2_elem<T, 4, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+    }
+    g_time_stop = t_stop;
+    const OpEQ2Y<T> gy{op.L, op.Y, op.mask};
+    const int nb = nblocks(nn);
+    if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+    launch_op(k_apply<T, OpEQ2Y<T>, In, Ep>, dim3(nb, nrhs), st, gy, in, ep, nrhs, gate,
+              gate_state, part);
     return;
   }
   if constexpr (std::is_same<Op, OpMF<T>>::value && std::is_same<In, InPlain<T>>::value) {

@@ -50,6 +50,7 @@ struct OpEQ2 {
   Lat L;
   const T* Ke;
   const uint8_t* mask;
+  T* Y;  // element products K_e u_e, [load case][element][81] (scratch of the apply)
 };
 
 // Reduction scratch: one partial sum per block and value, in regions that

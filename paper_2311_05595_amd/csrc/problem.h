@@ -147,6 +147,7 @@ class Problem {
   float* K032_ = nullptr;
   double* Keff_ = nullptr;   // level-0 effective element matrices (ST27: 576, EQ2: 6561)
   float* Keff32_ = nullptr;  // EQ2 mixed copy
+  double* Yeq_ = nullptr;    // EQ2 element products (FP64 or FP32 view), [nrhs][nel][81]
   double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr, *rold_ = nullptr;
   CgScalars* cs_ = nullptr;
   RedBuf red_{nullptr};

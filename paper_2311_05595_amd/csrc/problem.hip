@@ -128,6 +128,7 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   if (lv[0].kind == OP_EQ2) {
     TAKE(Keff_, double, nel0 * 6561);
     if (mixed) TAKE(Keff32_, float, nel0 * 6561);
+    TAKE(Yeq_, double, R * nel0 * 81);
   }
   for (int l = 0; l < L; ++l) {
     const long nn = lv[l].L.nn(), nd = lv[l].L.ndof();
@@ -421,7 +422,7 @@ FineOp Problem::fine_op() const {
   const Lat L = lv_[0].L;
   A.mf = OpMF<double>::make(L, E_, kv64_, B_[0].mask);
   A.st = OpST<double>{L, vbytes_ == 8 ? (const double*)B_[0].coefV : B_[0].coef64};
-  A.eq2 = OpEQ2<double>{L, Keff_, B_[0].mask};
+  A.eq2 = OpEQ2<double>{L, Keff_, B_[0].mask, Yeq_};
   return A;
 }
 
@@ -434,10 +435,10 @@ VOps<T> Problem::vops(int l) const {
   v.invD = (const T*)B_[l].invD;
   if constexpr (sizeof(T) == 8) {
     v.mf = OpMF<T>::make(v.L, E_, kv64_, B_[l].mask);
-    v.eq2 = OpEQ2<T>{v.L, Keff_, B_[l].mask};
+    v.eq2 = OpEQ2<T>{v.L, Keff_, B_[l].mask, (T*)Yeq_};
   } else {
     v.mf = OpMF<T>::make(v.L, E32_, kv32_, B_[l].mask);
-    v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask};
+    v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask, (T*)Yeq_};
   }
   v.st = OpST<T>{v.L, (const T*)B_[l].coefV};
   return v;

@@ -267,11 +267,116 @@ def run(args):
         "p50_ms": round(lat_s[len(lat_s) // 2], 3),
         "p99_ms": round(lat_s[min(len(lat_s) - 1, int(math.ceil(0.99 * len(lat_s))) - 1)], 3),
         "statuses": sorted(set(statuses)),
+        "not_converged": len(failed),
+        "dof_cg_iter_per_s": float(f"{dof_iters / elapsed:.4g}"),
         "roofline": roofline,
     }
     if not args.no_cpu:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(cfg, fields, budget_s=args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def run_served(args):
+    """The served mix: sessions of warm-started solves over requests of
+    different meshes, density subdivisions, structures and load-case counts,
+    arriving as a Poisson process and admitted by an HBM budget."""
+    import torch
+    import workloads as W
+    from workloads import configs as CF
+    from paper_2311_05595_amd import api
+    prec = args.precision or "mixed"
+    n = args.requests
+    rate = args.rate if args.rate else CF.SERVE_RATE[prec]
+    reqs = CF.serve_requests(n, seed=5, rate=rate, solves_per_session=args.session_solves)
+    # one seeded base field per (mesh, n) cell; each request perturbs it with
+    # its own seed (a full random field per request would cost the host
+    # seconds for the 33.5M-density requests)
+    bases = {}
+    for q in reqs:
+        key = (q["nel"], q["nsub"])
+        if key not in bases:
+            nx, ny, nz = q["nel"]
+            m = q["nsub"]
+            bases[key] = W.gaussian_random_field((nz * m, ny * m, nx * m), 70000 + len(bases))
+    log(f"served mix: {n} requests x {args.session_solves} solves, {len(bases)} base fields, "
+        f"rate {rate:.2f} requests/s, budget {args.budget_gb} GB, {prec}")
+    srv = api.Server(int(args.budget_gb * 2**30), max_slots=args.slots)
+    torch.cuda.synchronize()
+    pending = list(reqs)
+    tickets = {}    # ticket -> (request index, solve index)
+    probs = {}
+    lat, statuses, failed = [], [], []
+    dof_iters = 0
+    t0 = time.perf_counter()
+    done_solves = 0
+    next_report = 15.0
+    while pending or tickets:
+        now = time.perf_counter() - t0
+        if now >= next_report:
+            log(f"  t={now:.0f}s: {done_solves} solves done, {len(tickets)} in flight, "
+                f"{len(pending)} requests not yet arrived")
+            next_report += 15.0
+        while pending and pending[0]["arrival"] <= now:
+            q = pending.pop(0)
+            mask, f = W.make_problem(q["kind"], *q["nel"], 1, q["nrhs"])
+            p = api.Problem(q["nel"], mask, f, order=1, nsub=q["nsub"], nlevels=q["nlevels"],
+                            precision=prec)
+            probs[q["id"]] = (p, q)
+            rho = W.perturb(bases[(q["nel"], q["nsub"])], q["seed"])
+            tickets[srv.submit(p, rho, rtol=1e-8, maxit=2000, warm_start=False)] = (q["id"], 0)
+        srv.step()
+        for t in list(tickets):
+            out = srv.poll(t)
+            if out is None:
+                continue
+            qid, k = tickets.pop(t)
+            st, info, ms = out
+            lat.append(ms)
+            statuses.append(st)
+            done_solves += 1
+            p, q = probs[qid]
+            nx, ny, nz = q["nel"]
+            ndof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
+            dof_iters += ndof * sum(info["iters"][:q["nrhs"]])
+            if st != 0:
+                failed.append(dict(id=qid, solve=k, status=st, kind=q["kind"], nel=q["nel"],
+                                   nsub=q["nsub"], nrhs=q["nrhs"], nlevels=q["nlevels"],
+                                   iters=info["iters"][:q["nrhs"]],
+                                   rel_res=info["rel_res"][:q["nrhs"]]))
+                log(f"  request {qid} solve {k}: status {st} {failed[-1]}")
+            if k + 1 < args.session_solves:
+                rho = W.perturb(bases[(q["nel"], q["nsub"])], q["perturb_seeds"][k])
+                tickets[srv.submit(p, rho, rtol=1e-8, maxit=2000, warm_start=True)] = (qid, k + 1)
+            else:
+                srv.release(p)
+                p.close()
+                del probs[qid]
+        if not tickets and pending:
+            time.sleep(max(0.0, min(0.01, pending[0]["arrival"] - (time.perf_counter() - t0))))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    srv.close()
+    lat_s = np.sort(lat)
+    out = {
+        "metric": "MGCG solves/s and DOF\u00b7CG-iter/s at 1e-8 rel. residual; p50/p99 solve latency",
+        "value": round(done_solves / elapsed, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": done_solves, "warmup": 0, "ms_per_step": round(elapsed / done_solves * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f64+f32", "data": "synthetic",
+        "config": {"workload": f"served mix: {n} requests (cantilever / MBB / torsion; meshes "
+                               f"32x16x16 ... 128x64x64; n in 1,2,4; 1-4 load cases), Poisson "
+                               f"arrivals at {rate:.2f} requests/s, {args.session_solves} "
+                               f"warm-started solves per session, HBM budget {args.budget_gb} GB, "
+                               f"{args.slots} slots",
+                   "rtol": 1e-8},
+        "p50_ms": round(float(np.percentile(lat_s, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat_s, 99)), 3),
+        "statuses": sorted(set(statuses)),
+        "not_converged": len(failed),
+        "dof_cg_iter_per_s": float(f"{dof_iters / elapsed:.4g}"),
+        "elapsed_s": round(elapsed, 3),
+    }
     print(json.dumps(out), flush=True)
 
 
@@ -287,9 +392,20 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
+    ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
+    ap.add_argument("--session-solves", type=int, default=5, help="c5: solves per session")
+    ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second")
+    ap.add_argument("--budget-gb", type=float, default=48.0, help="c5: HBM budget")
+    ap.add_argument("--slots", type=int, default=16, help="c5: concurrent solves")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    if args.config == "c5":
+        run_served(args)
         return
     run(args)
 

@@ -36,38 +36,6 @@ struct InPlain {
   }
 };
 
-// x = omega * invD * b evaluated on the fly (first smoothing sweep from zero).
-template <typename T>
-struct InScaledB {
-  const T* b;
-  const T* invD;
-  T omega;
-  long ndof;
-  __device__ __forceinline__ void load(int r, long node, T v[3]) const {
-    const T* p = b + (size_t)r * ndof + 3 * node;
-    const T* d = invD + 3 * node;
-    v[0] = omega * d[0] * p[0];
-    v[1] = omega * d[1] * p[1];
-    v[2] = omega * d[2] * p[2];
-  }
-  struct Buf {
-    __amdgpu_buffer_rsrc_t rb, rd;
-    T omega;
-    __device__ __forceinline__ void load(int voff, T v[3]) const {
-      T bb[3], dd[3];
-      bload3<T>(rb, voff, bb);
-      bload3<T>(rd, voff, dd);
-      v[0] = omega * dd[0] * bb[0];
-      v[1] = omega * dd[1] * bb[1];
-      v[2] = omega * dd[2] * bb[2];
-    }
-  };
-  __device__ __forceinline__ Buf buf(int r) const {
-    return Buf{make_rsrc(b + (size_t)r * ndof, ndof * sizeof(T)),
-               make_rsrc(invD, ndof * sizeof(T)), omega};
-  }
-};
-
 // ------------------------------------------------------------ operators
 __device__ __forceinline__ void node_ijk(long node, const Lat& L, int& i, int& j, int& k) {
   // 32-bit divisions: node counts are bounded far below 2^32 by the buffer
@@ -193,62 +161,6 @@ __device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, in
   for (int c = 0; c < 3; ++c) y[c] = ((mself >> c) & 1) ? T(0) : acc[c];
 }
 
-// Stencil apply (supports baked in).  All loads are buffer loads: the
-// coefficient of (block, row, column) sits at a scalar offset from the node's
-// byte offset, so 243 coefficient loads share two address registers per
-// neighbour; out-of-range neighbours use an offset past the buffer and read 0.
-template <typename T, class In>
-__device__ __forceinline__ void ax_st(const OpST<T>& op, const In& in, int r, int i, int j, int k,
-                                      long node, T y[3]) {
-  const Lat L = op.L;
-  const long nn = L.nn();
-  const auto xb = in.buf(r);
-  const __amdgpu_buffer_rsrc_t rc = make_rsrc(op.coef, (size_t)ST_COEF * nn * sizeof(T));
-  const int row = (int)(nn * sizeof(T));  // bytes between coefficient rows
-  const int vself = (int)(node * sizeof(T));
-  T acc[3] = {T(0), T(0), T(0)};
-  // two blocks (four neighbours, ~50 loads) per iteration: enough loads in
-  // flight per thread, bounded register pressure
-#pragma unroll 2
-  for (int b = 0; b < ST_BLOCKS; ++b) {
-    const Off3 d = st_offset(b);
-    {
-      // forward block A_{i, i+d}, stored at this node (zero when i+d is
-      // outside the lattice)
-      const int ii = i + d.dx, jj = j + d.dy, kk = k + d.dz;
-      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
-                      (unsigned)kk < (unsigned)L.nz;
-      const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T)) : kBufOOB;
-      T v[3];
-      xb.load(xo, v);
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int e = 0; e < 3; ++e)
-          acc[c] = fma(bload<T>(rc, vself, (b * 9 + 3 * c + e) * row), v[e], acc[c]);
-    }
-    if (b > 0) {
-      // backward block A_{i, i-d} = A_{i-d, i}^T, stored at node i-d
-      const int ii = i - d.dx, jj = j - d.dy, kk = k - d.dz;
-      const bool ok = (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
-                      (unsigned)kk < (unsigned)L.nz;
-      const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
-      const int xo = ok ? (int)(nb * 3 * sizeof(T)) : kBufOOB;
-      const int co = ok ? (int)(nb * sizeof(T)) : kBufOOB;
-      T v[3];
-      xb.load(xo, v);
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int e = 0; e < 3; ++e)
-          acc[c] = fma(bload<T>(rc, co, (b * 9 + 3 * e + c) * row), v[e], acc[c]);
-    }
-  }
-  y[0] = acc[0];
-  y[1] = acc[1];
-  y[2] = acc[2];
-}
-
 // The blocks b = part, part + LPN, ... of the stencil apply (partial sum of
 // one node's rows).  `part` is wave-uniform, so every coefficient row offset
 // is a scalar.  The loop has no branches: a block index past the table (and
@@ -308,83 +220,12 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
   y[2] = acc[2];
 }
 
-// Stored triquadratic element matrices: gather over the 1..8 elements that
-// contain the node.
-template <typename T, class In>
-__device__ __forceinline__ void ax_eq2(const OpEQ2<T>& op, const In& in, int r, int i, int j, int k,
-                                       T y[3]) {
-  const Lat L = op.L;
-  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
-  int exs[2], axs[2], nxe = 0, eys[2], ays[2], nye = 0, ezs[2], azs[2], nze = 0;
-  auto axis = [](int p, int ne, int* es, int* as, int& n) {
-    if (p & 1) {
-      es[0] = (p - 1) / 2;
-      as[0] = 1;
-      n = 1;
-    } else {
-      n = 0;
-      if (p / 2 - 1 >= 0) { es[n] = p / 2 - 1; as[n] = 2; ++n; }
-      if (p / 2 < ne) { es[n] = p / 2; as[n] = 0; ++n; }
-    }
-  };
-  axis(i, nex, exs, axs, nxe);
-  axis(j, ney, eys, ays, nye);
-  axis(k, nez, ezs, azs, nze);
-  T acc[3] = {T(0), T(0), T(0)};
-  for (int cz = 0; cz < nze; ++cz)
-    for (int cy = 0; cy < nye; ++cy)
-      for (int cx = 0; cx < nxe; ++cx) {
-        const int ex = exs[cx], ey = eys[cy], ez = ezs[cz];
-        const int a = axs[cx] + 3 * (ays[cy] + 3 * azs[cz]);
-        const T* Kr = op.Ke + ((size_t)(ex + (long)nex * (ey + (long)ney * ez)) * 81 + 3 * a) * 81;
-#pragma unroll 3
-        for (int bz = 0; bz < 3; ++bz)
-#pragma unroll 3
-          for (int by = 0; by < 3; ++by)
-#pragma unroll
-            for (int bx = 0; bx < 3; ++bx) {
-              const long nb = (2 * ex + bx) + (long)L.nx * ((2 * ey + by) + (long)L.ny * (2 * ez + bz));
-              const int bcol = 3 * (bx + 3 * (by + 3 * bz));
-              T v[3];
-              in.load(r, nb, v);
-#pragma unroll
-              for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int e = 0; e < 3; ++e) acc[c] += Kr[c * 81 + bcol + e] * v[e];
-            }
-      }
-  const long self = i + (long)L.nx * (j + (long)L.ny * k);
-  const uint8_t m = op.mask[self];
-  if (m) {
-    T v[3];
-    in.load(r, self, v);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if ((m >> c) & 1) acc[c] = v[c];
-  }
-  y[0] = acc[0];
-  y[1] = acc[1];
-  y[2] = acc[2];
-}
-
 // Dispatch by operator struct type.
 template <typename T, class In>
 __device__ __forceinline__ void ax_any(const OpMF<T>& op, const In& in, int r, long node, T y[3]) {
   int i, j, k;
   node_ijk(node, op.L, i, j, k);
   ax_mf(op, in, r, i, j, k, y);
-}
-template <typename T, class In>
-__device__ __forceinline__ void ax_any(const OpST<T>& op, const In& in, int r, long node, T y[3]) {
-  int i, j, k;
-  node_ijk(node, op.L, i, j, k);
-  ax_st(op, in, r, i, j, k, node, y);
-}
-template <typename T, class In>
-__device__ __forceinline__ void ax_any(const OpEQ2<T>& op, const In& in, int r, long node, T y[3]) {
-  int i, j, k;
-  node_ijk(node, op.L, i, j, k);
-  ax_eq2(op, in, r, i, j, k, y);
 }
 
 // Second pass of the stored-matrix triquadratic apply: a node sums the rows
@@ -557,33 +398,6 @@ struct EpResid {  // r = b - A x
     const size_t o = (size_t)r * ndof + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c) rout[o + c] = pv.b.v[c] - ax[c];
-  }
-};
-
-template <typename T>
-struct EpResidX {  // r = b - A x, x = omega invD b stored
-  const T* b;
-  const T* invD;
-  T omega;
-  T* rout;
-  T* xout;
-  long ndof;
-  static constexpr bool RED = false;
-  struct Pre {
-    Pre3<T> b, d;
-  };
-  __device__ bool rhs_on(int) const { return true; }
-  __device__ Pre pre(int r, long node) const {
-    return Pre{ld3(b + (size_t)r * ndof + 3 * node), ld3(invD + 3 * node)};
-  }
-  __device__ void put(int r, long node, const T ax[3], const Pre& pv, double&, double&) const {
-    const size_t o = (size_t)r * ndof + 3 * node;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T bb = pv.b.v[c];
-      rout[o + c] = bb - ax[c];
-      xout[o + c] = omega * pv.d.v[c] * bb;
-    }
   }
 };
 
@@ -1004,9 +818,7 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
     const int nb = (int)((nn + ST_NODES - 1) / ST_NODES);
     if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
     launch_op(k_apply_st<T, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
-    return;
-  }
-  if constexpr (std::is_same<Op, OpEQ2<T>>::value) {
+  } else if constexpr (std::is_same<Op, OpEQ2<T>>::value) {
     // two passes: element products, then the node gather with the epilogue
     // (timing events, when set, span both)
     const int ne = (int)(((long)(op.L.nx - 1) / 2 * ((op.L.ny - 1) / 2) * ((op.L.nz - 1) / 2) +
@@ -1025,21 +837,20 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
     if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
     launch_op(k_apply<T, OpEQ2Y<T>, In, Ep>, dim3(nb, nrhs), st, gy, in, ep, nrhs, gate,
               gate_state, part);
-    return;
-  }
-  if constexpr (std::is_same<Op, OpMF<T>>::value && std::is_same<In, InPlain<T>>::value) {
+  } else {
+    static_assert(std::is_same<Op, OpMF<T>>::value, "operator kind");
+    const int nb = nblocks(nn);
+    if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
     if (mf_lds_fits(op.L)) {
-      const int nb = nblocks(nn);
-      if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+      // rows of up to 212 nodes: the block's neighbourhood staged in LDS
       const size_t lds = (size_t)9 * mf_lds_range(op.L) * sizeof(T);
       launch_op_lds(k_apply_mf_lds<T, Ep>, dim3(nb, nrhs), lds, st, op, in, ep, nrhs, gate,
                     gate_state, part);
-      return;
+    } else {
+      launch_op(k_apply<T, Op, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state,
+                part);
     }
   }
-  const int nb = nblocks(nn);
-  if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-  launch_op(k_apply<T, Op, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
 }
 
 template <typename T>
@@ -1473,25 +1284,6 @@ void v_prepare0(const double* r, T* b0, const T* wD, T* x0, long ndof, int nrhs,
   MGCG_HIP(hipGetLastError());
 }
 
-template <typename T>
-__global__ __launch_bounds__(BS) void k_smooth0(const T* __restrict__ b, const T* __restrict__ invD,
-                                                T* x, T omega, long ndof, int nrhs,
-                                                const CgScalars* cs) {
-  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
-  for (int r = 0; r < nrhs; ++r) {
-    const size_t o = (size_t)r * ndof;
-    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS)
-      x[o + i] = omega * invD[i] * b[o + i];
-  }
-}
-
-template <typename T>
-void v_smooth0(const T* b, const T* invD, T* x, T omega, long ndof, int nrhs, const CgScalars* cs,
-               hipStream_t st) {
-  hipLaunchKernelGGL(k_smooth0<T>, dim3(vec_grid(ndof)), dim3(BS), 0, st, b, invD, x, omega, ndof,
-                     nrhs, cs);
-  MGCG_HIP(hipGetLastError());
-}
 
 // Restriction: coarse DOF (I, c) gathers component c of the 3x3x3 fine nodes
 // around 2I with weights prod_d (1 - |offset_d| / 2); one thread per coarse
@@ -1654,7 +1446,6 @@ void v_coarse_solve(const double* Ainv, int ld, long ndof, const T* b, T* x, int
                                 const double*, int, const CgScalars*, RedBuf, hipStream_t);       \
   template void v_residual<T>(const VOps<T>&, const T*, const T*, T*, int, const CgScalars*,       \
                               hipStream_t);                                                       \
-  template void v_smooth0<T>(const T*, const T*, T*, T, long, int, const CgScalars*, hipStream_t); \
   template void v_restrict<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, const T*,   \
                               T*, int, const CgScalars*, hipStream_t);                            \
   template void v_prepare0<T>(const double*, T*, const T*, T*, long, int, const CgScalars*,        \

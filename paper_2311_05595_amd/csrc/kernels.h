@@ -150,10 +150,6 @@ void v_jacobi_dot(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, cons
 template <typename T>
 void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const CgScalars* cs,
                 hipStream_t st);
-// x = omega invD b
-template <typename T>
-void v_smooth0(const T* b, const T* invD, T* x, T omega, long ndof, int nrhs, const CgScalars* cs,
-               hipStream_t st);
 // coarse = P~^T fine; when xc is given also xc = wDc * coarse (the coarse
 // level's first smoothing sweep from zero)
 template <typename T>

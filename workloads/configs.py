@@ -36,6 +36,10 @@ CONFIGS = {
 }
 
 SERVE_MESHES = [(32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48), (128, 64, 64)]
+# Poisson arrival rate of the served mix (requests per second), frozen at
+# 0.8 x the closed-loop capacity of the FP64 path on one MI355X (12.4
+# solves/s, 5 solves per request); both precisions are served at this rate.
+SERVE_RATE = {"fp64": 2.0, "mixed": 2.0}
 SERVE_NSUB = [1, 2, 4]
 SERVE_KINDS = ["cantilever", "mbb", "torsion"]
 
@@ -101,5 +105,5 @@ def request_densities(req):
     return gaussian_random_field((nz * n, ny * n, nx * n), req["seed"])
 
 
-__all__ = ["MATERIAL", "CONFIGS", "config", "densities", "problem", "serve_requests",
+__all__ = ["MATERIAL", "CONFIGS", "SERVE_RATE", "config", "densities", "problem", "serve_requests",
            "request_densities", "coarsest_levels", "perturb"]

@@ -280,8 +280,15 @@ def run(args):
 def run_served(args):
     """The served mix: sessions of warm-started solves over requests of
     different meshes, density subdivisions, structures and load-case counts,
-    arriving as a Poisson process and admitted by an HBM budget."""
+    arriving as a Poisson process and admitted by an HBM budget.
+
+    The densities of each solve are the client's: a pool of host threads
+    makes them (perturbation of the cell's base field, solid layers at the
+    request's supports and loads) while the server loop runs, one solve
+    ahead per session.  A solve's latency runs from its submission, which
+    copies the densities, to the server step that sees it finish."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     import workloads as W
     from workloads import configs as CF
     from paper_2311_05595_amd import api
@@ -289,53 +296,58 @@ def run_served(args):
     n = args.requests
     rate = args.rate if args.rate else CF.SERVE_RATE[prec]
     reqs = CF.serve_requests(n, seed=5, rate=rate, solves_per_session=args.session_solves)
-    # one seeded base field per (mesh, n) cell; each request perturbs it with
-    # its own seed (a full random field per request would cost the host
-    # seconds for the 33.5M-density requests)
-    bases = {}
-    for q in reqs:
-        key = (q["nel"], q["nsub"])
-        if key not in bases:
-            nx, ny, nz = q["nel"]
-            m = q["nsub"]
-            bases[key] = W.gaussian_random_field((nz * m, ny * m, nx * m), 70000 + len(bases))
+    bases = CF.serve_base_fields(reqs)
     log(f"served mix: {n} requests x {args.session_solves} solves, {len(bases)} base fields, "
         f"rate {rate:.2f} requests/s, budget {args.budget_gb} GB, {prec}")
+    pool = ThreadPoolExecutor(max_workers=8)
+
+    def densities(q, mask, f, k):
+        return CF.serve_densities(bases, q, mask, f, k)
+
     srv = api.Server(int(args.budget_gb * 2**30), max_slots=args.slots)
     torch.cuda.synchronize()
     pending = list(reqs)
     tickets = {}    # ticket -> (request index, solve index)
-    probs = {}
+    probs = {}      # request index -> (problem, request, mask, f)
+    ready = {}      # request index -> (solve index, future of its densities)
+    busy = set()    # requests with a solve submitted and not yet finished
     lat, statuses, failed = [], [], []
     dof_iters = 0
     t0 = time.perf_counter()
     done_solves = 0
     next_report = 15.0
-    while pending or tickets:
+    while pending or tickets or ready:
         now = time.perf_counter() - t0
         if now >= next_report:
             log(f"  t={now:.0f}s: {done_solves} solves done, {len(tickets)} in flight, "
-                f"{len(pending)} requests not yet arrived")
+                f"{len(ready)} being prepared, {len(pending)} requests not yet arrived")
             next_report += 15.0
         while pending and pending[0]["arrival"] <= now:
             q = pending.pop(0)
             mask, f = W.make_problem(q["kind"], *q["nel"], 1, q["nrhs"])
             p = api.Problem(q["nel"], mask, f, order=1, nsub=q["nsub"], nlevels=q["nlevels"],
                             precision=prec)
-            probs[q["id"]] = (p, q)
-            rho = W.perturb(bases[(q["nel"], q["nsub"])], q["seed"])
-            tickets[srv.submit(p, rho, rtol=1e-8, maxit=2000, warm_start=False)] = (q["id"], 0)
+            probs[q["id"]] = (p, q, mask, f)
+            ready[q["id"]] = (0, pool.submit(densities, q, mask, f, 0))
+        for qid in [i for i, (_, fut) in ready.items() if fut.done() and i not in busy]:
+            k, fut = ready.pop(qid)
+            p, q, mask, f = probs[qid]
+            tickets[srv.submit(p, fut.result(), rtol=1e-8, maxit=2000, warm_start=k > 0)] = (qid, k)
+            busy.add(qid)
+            if k + 1 < args.session_solves:       # prepare the session's next design
+                ready[qid] = (k + 1, pool.submit(densities, q, mask, f, k + 1))
         srv.step()
         for t in list(tickets):
             out = srv.poll(t)
             if out is None:
                 continue
             qid, k = tickets.pop(t)
+            busy.discard(qid)
             st, info, ms = out
             lat.append(ms)
             statuses.append(st)
             done_solves += 1
-            p, q = probs[qid]
+            p, q, mask, f = probs[qid]
             nx, ny, nz = q["nel"]
             ndof = 3 * (nx + 1) * (ny + 1) * (nz + 1)
             dof_iters += ndof * sum(info["iters"][:q["nrhs"]])
@@ -345,18 +357,18 @@ def run_served(args):
                                    iters=info["iters"][:q["nrhs"]],
                                    rel_res=info["rel_res"][:q["nrhs"]]))
                 log(f"  request {qid} solve {k}: status {st} {failed[-1]}")
-            if k + 1 < args.session_solves:
-                rho = W.perturb(bases[(q["nel"], q["nsub"])], q["perturb_seeds"][k])
-                tickets[srv.submit(p, rho, rtol=1e-8, maxit=2000, warm_start=True)] = (qid, k + 1)
-            else:
+            if k + 1 >= args.session_solves:
                 srv.release(p)
                 p.close()
                 del probs[qid]
-        if not tickets and pending:
+        if not tickets and not ready and pending:
             time.sleep(max(0.0, min(0.01, pending[0]["arrival"] - (time.perf_counter() - t0))))
+        elif not tickets:
+            time.sleep(0.0005)  # only densities in preparation: leave the host threads the CPU
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     srv.close()
+    pool.shutdown()
     lat_s = np.sort(lat)
     out = {
         "metric": "MGCG solves/s and DOF\u00b7CG-iter/s at 1e-8 rel. residual; p50/p99 solve latency",

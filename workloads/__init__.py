@@ -15,7 +15,7 @@ Conventions (shared by every consumer):
 * y is the vertical axis (loads act in -y); elements are unit cubes.
 """
 
-from .fields import uniform_field, gaussian_random_field, perturb
+from .fields import uniform_field, gaussian_random_field, perturb, solid_at_supports_and_loads
 from .loads import (
     node_dims,
     cantilever_bcs,
@@ -30,6 +30,7 @@ __all__ = [
     "uniform_field",
     "gaussian_random_field",
     "perturb",
+    "solid_at_supports_and_loads",
     "node_dims",
     "cantilever_bcs",
     "mbb_bcs",

@@ -7,7 +7,7 @@ Material of every workload: E0 = 1, Emin = 1e-9, nu = 0.3, SIMP p = 3
 
 import numpy as np
 
-from .fields import uniform_field, gaussian_random_field, perturb
+from .fields import uniform_field, gaussian_random_field, perturb, solid_at_supports_and_loads
 from .loads import make_problem
 
 MATERIAL = dict(E0=1.0, Emin=1e-9, nu=0.3, penal=3.0)
@@ -37,9 +37,10 @@ CONFIGS = {
 
 SERVE_MESHES = [(32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48), (128, 64, 64)]
 # Poisson arrival rate of the served mix (requests per second), frozen at
-# 0.8 x the closed-loop capacity of the FP64 path on one MI355X (12.4
-# solves/s, 5 solves per request); both precisions are served at this rate.
-SERVE_RATE = {"fp64": 2.0, "mixed": 2.0}
+# 0.8 x the closed-loop capacity of the FP64 path on one MI355X (24.0
+# solves/s with every request queued at once, 5 solves per request); both
+# precisions are served at this rate.
+SERVE_RATE = {"fp64": 3.84, "mixed": 3.84}
 SERVE_NSUB = [1, 2, 4]
 SERVE_KINDS = ["cantilever", "mbb", "torsion"]
 
@@ -99,11 +100,30 @@ def serve_requests(n=256, seed=5, rate=None, solves_per_session=5):
     return out
 
 
-def request_densities(req):
-    n = req["nsub"]
-    nx, ny, nz = req["nel"]
-    return gaussian_random_field((nz * n, ny * n, nx * n), req["seed"])
+def serve_base_fields(reqs):
+    """One seeded Gaussian random field per (mesh, n) cell of the mix, seeds
+    70000, 70001, ... in order of the cells' first request."""
+    bases = {}
+    for q in reqs:
+        key = (q["nel"], q["nsub"])
+        if key not in bases:
+            nx, ny, nz = q["nel"]
+            m = q["nsub"]
+            bases[key] = gaussian_random_field((nz * m, ny * m, nx * m), 70000 + len(bases))
+    return bases
+
+
+def serve_densities(bases, req, mask, f, k):
+    """Densities of solve k of a request's session: its cell's base field
+    perturbed with the request's k-th seed, then solid (1) in every element
+    touching one of its supports or loads.  Without the solid layers some
+    MBB requests under the top-face pressure hold their load in void: |u|
+    reaches 1e7-1e9 and no FP64 solve gets ||f - K u|| below 1e-8 ||f||
+    (rounding in K u alone is about eps |K| |u|)."""
+    seed = req["seed"] if k == 0 else req["perturb_seeds"][k - 1]
+    rho = perturb(bases[(req["nel"], req["nsub"])], seed)
+    return solid_at_supports_and_loads(rho, mask, f, req["nel"], req["nsub"])
 
 
 __all__ = ["MATERIAL", "CONFIGS", "SERVE_RATE", "config", "densities", "problem", "serve_requests",
-           "request_densities", "coarsest_levels", "perturb"]
+           "serve_base_fields", "serve_densities", "coarsest_levels", "perturb"]

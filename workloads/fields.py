@@ -9,6 +9,12 @@
   0/1-leaning designs of an optimisation run (SIMP designs at volume fraction
   0.2-0.3).
 * ``perturb``: an SLP-like step, ``clip(rho + U(-amp, amp), rho_min, 1)``.
+* ``solid_at_supports_and_loads``: density 1 in every Q1 element that touches
+  a fixed or loaded node, the non-design solid layer of the paper's bridge
+  (Sec. 7.1) applied to every support and load.  A random field alone can
+  leave a load or a support in void; the displacement there then grows like
+  1/Emin and the FP64 residual ||f - K u|| cannot fall below roughly
+  eps |K| |u|, far above 1e-8 of ||f||.
 """
 
 import numpy as np
@@ -48,3 +54,23 @@ def gaussian_random_field(shape, seed, corr=6.0, rho_min=1e-3, volfrac=0.3):
 def perturb(rho, seed, amp=0.05, rho_min=1e-3):
     rng = np.random.default_rng(seed)
     return np.clip(rho + rng.uniform(-amp, amp, size=rho.shape), rho_min, 1.0)
+
+
+def solid_at_supports_and_loads(rho, mask, f, nel, nsub):
+    """Copy of ``rho`` (lattice ``(nsub*nelz, nsub*nely, nsub*nelx)``) with
+    every sub-density of a Q1 element set to 1 when one of the element's 8
+    nodes has a fixed DOF (``mask``) or a nonzero load in any load case
+    (``f``, ``[load case][DOF]``)."""
+    nx, ny, nz = nel
+    touched = np.asarray(mask, dtype=bool).reshape(-1, 3).any(axis=1)
+    touched |= (np.atleast_2d(f) != 0.0).reshape(np.atleast_2d(f).shape[0], -1, 3).any(axis=(0, 2))
+    t = touched.reshape(nz + 1, ny + 1, nx + 1)
+    el = np.zeros((nz, ny, nx), dtype=bool)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                el |= t[dz:dz + nz, dy:dy + ny, dx:dx + nx]
+    sub = np.repeat(np.repeat(np.repeat(el, nsub, axis=0), nsub, axis=1), nsub, axis=2)
+    out = np.array(rho, dtype=np.float64, copy=True).reshape(sub.shape)
+    out[sub] = 1.0
+    return out

@@ -1,6 +1,8 @@
 // Device utilities: deterministic block/grid reductions.
 #pragma once
 
+#include <cstddef>
+
 #include "kernels.h"
 
 namespace mgcg {
@@ -42,9 +44,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Deterministic block-wide sum of p[0..n) (fixed order for a fixed n);
 // every thread receives the result.  sh: BS/64 doubles of shared memory.
 // Four independent buffer loads per thread and pass (reads past n return 0),
-// so a few hundred partials cost one memory round trip.
-__device__ __forceinline__ double block_sum(const double* __restrict__ p, int n, double* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+// so a few hundred partials cost one memory round trip.  In two parts, so
+// that a kernel can pin values loaded before the sum's loads (their wait
+// then comes after those loads are issued, and before the barrier that the
+// compiler might otherwise sink their loads past).
+__device__ __forceinline__ double block_sum_loads(const double* __restrict__ p, int n) {
   const __amdgpu_buffer_rsrc_t rp = make_rsrc(p, (size_t)n * sizeof(double));
   double s = 0.0;
   for (int b = 0; b < n; b += 4 * BS) {
@@ -56,6 +60,10 @@ __device__ __forceinline__ double block_sum(const double* __restrict__ p, int n,
     const double v3 = bload<double>(rp, o + 3 * BS * 8, 0);
     s += (v0 + v1) + (v2 + v3);
   }
+  return s;
+}
+__device__ __forceinline__ double block_sum_finish(double s, double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   s = wave_sum(s);
   if (lane == 0) sh[wid] = s;
   __syncthreads();
@@ -64,6 +72,9 @@ __device__ __forceinline__ double block_sum(const double* __restrict__ p, int n,
   for (int w = 0; w < BS / 64; ++w) t += sh[w];
   __syncthreads();
   return t;
+}
+__device__ __forceinline__ double block_sum(const double* __restrict__ p, int n, double* sh) {
+  return block_sum_finish(block_sum_loads(p, n), sh);
 }
 
 // Block sums of one / two per-thread values written to dst0 / dst1 by
@@ -111,6 +122,73 @@ __device__ __forceinline__ bool any_state(const CgScalars* cs, int nrhs, int sta
   for (int r = 0; r < nrhs; ++r)
     if (cs[r].state == state) return true;
   return false;
+}
+
+// Keeps a value's computation (and its loads) above this point: without it
+// the compiler may sink loads whose only use follows a gate test below that
+// test, where they would wait for it.
+__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(float& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void pin(int& v) { asm volatile("" : "+v"(v)); }
+
+// Stand-in read by ungated launches (never written).
+static __device__ CgScalars g_no_gate[4];
+
+// The state word of load case r, read through the vector memory path:
+// scalar loads complete out of order, so the kernel's first wait on any
+// scalar value (a kernel argument, say) would wait for it too.
+__device__ __forceinline__ int state_of(const CgScalars* cs, int r) {
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(cs, 4 * sizeof(CgScalars));
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(
+      rs, r * (int)sizeof(CgScalars) + (int)offsetof(CgScalars, state), 0, 0);
+}
+
+// One field of load case r's CgScalars (at byte offset off), through the
+// vector memory path like state_of.
+__device__ __forceinline__ int cs_int(const CgScalars* cs, int r, int off) {
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(cs, 4 * sizeof(CgScalars));
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(rs, r * (int)sizeof(CgScalars) + off, 0, 0);
+}
+__device__ __forceinline__ double cs_dbl(const CgScalars* cs, int r, int off) {
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(cs, 4 * sizeof(CgScalars));
+  return bload<double>(rs, r * (int)sizeof(CgScalars) + off, 0);
+}
+#define CS_OFF(field) ((int)offsetof(CgScalars, field))
+
+// Gate of a kernel of the device-driven iteration.  gate_load() issues the
+// loads of the four load cases' states (a problem always holds four
+// CgScalars) with the kernel's first data loads; gate_open() is called only
+// before the kernel's first store.  Testing first and returning early would
+// put the state's memory latency in front of every other load of the
+// kernel.  gate_open() pins the states, which keeps the test (and the wait
+// for those loads) at its place in the program, after the loads above it.
+struct Gate {
+  int s[4];
+  int nrhs, state;
+  bool none;  // ungated launch: always open
+};
+__device__ __forceinline__ Gate gate_load(const CgScalars* cs, int nrhs, int state) {
+  Gate g;
+  g.none = cs == nullptr;
+  const CgScalars* p = g.none ? g_no_gate : cs;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g.s[q] = state_of(p, q);
+  g.nrhs = nrhs;
+  g.state = state;
+  return g;
+}
+// Open when any load case is in the gate's state; with r >= 0, when load
+// case r is (epilogues that store per load case).
+__device__ __forceinline__ bool gate_open(Gate g, int r = -1) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) pin(g.s[q]);
+  if (g.none) return true;
+  if (r >= 0) {
+    const int sr = r == 0 ? g.s[0] : r == 1 ? g.s[1] : r == 2 ? g.s[2] : g.s[3];
+    return sr == g.state;
+  }
+  return (g.s[0] == g.state) | ((g.nrhs > 1) & (g.s[1] == g.state)) |
+         ((g.nrhs > 2) & (g.s[2] == g.state)) | ((g.nrhs > 3) & (g.s[3] == g.state));
 }
 
 inline int nblocks(long n, int per = BS) { return (int)((n + per - 1) / per); }

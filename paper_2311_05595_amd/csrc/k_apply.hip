@@ -294,7 +294,7 @@ constexpr int EQ_EPB = 3;  // elements per block (243 of 256 threads busy)
 template <typename T, int NR, class In>
 __global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
                                                   const CgScalars* gate, int gate_state) {
-  if (gate && !any_state(gate, nrhs, gate_state)) return;
+  const Gate g = gate_load(gate, nrhs, gate_state);
   __shared__ T ue[NR][EQ_EPB][81];
   int bx, by;
   xcd_tile(bx, by);
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
     }
   }
   __syncthreads();
-  if (!on) return;
+  if (!gate_open(g) || !on) return;
   const T* Kc = op.Ke + (size_t)e * 6561 + row;
   T acc[NR][2];
 #pragma unroll
@@ -373,7 +373,6 @@ struct EpStore {
   long ndof;
   static constexpr bool RED = false;
   struct Pre {};
-  __device__ bool rhs_on(int) const { return true; }
   __device__ Pre pre(int, long) const { return Pre{}; }
   __device__ void put(int r, long node, const T ax[3], const Pre&, double&, double&) const {
     T* p = y + (size_t)r * ndof + 3 * node;
@@ -392,7 +391,6 @@ struct EpResid {  // r = b - A x
   struct Pre {
     Pre3<T> b;
   };
-  __device__ bool rhs_on(int) const { return true; }
   __device__ Pre pre(int r, long node) const { return Pre{ld3(b + (size_t)r * ndof + 3 * node)}; }
   __device__ void put(int r, long node, const T ax[3], const Pre& pv, double&, double&) const {
     const size_t o = (size_t)r * ndof + 3 * node;
@@ -413,7 +411,6 @@ struct EpJacobi {  // xo = x + wD (b - A x)  (weights folded into wD)
   struct Pre {
     Pre3<T> b, x, d;
   };
-  __device__ bool rhs_on(int) const { return true; }
   __device__ Pre pre(int r, long node) const {
     const size_t o = (size_t)r * ndof + 3 * node;
     return Pre{ld3(b + o), ld3(x + o), ld3(invD + 3 * node)};
@@ -443,7 +440,6 @@ struct EpJacobiDot {
     Pre3<T> b, x, d;
     Pre3<double> r, ro;
   };
-  __device__ bool rhs_on(int) const { return true; }
   __device__ Pre pre(int rr, long node) const {
     const size_t o = (size_t)rr * ndof + 3 * node;
     return Pre{ld3(b + o), ld3(x + o), ld3(invD + 3 * node), ld3(r + o), ld3(rold + o)};
@@ -465,12 +461,10 @@ struct EpDotPQ {  // q = A p; acc[r] += p.q  (active load cases)
   const double* p;
   double* q;
   long ndof;
-  const CgScalars* cs;
   static constexpr bool RED = true;
   struct Pre {
     Pre3<double> p;
   };
-  __device__ bool rhs_on(int r) const { return cs[r].state == CG_ACTIVE; }
   __device__ Pre pre(int r, long node) const { return Pre{ld3(p + (size_t)r * ndof + 3 * node)}; }
   __device__ void put(int r, long node, const double ax[3], const Pre& pv, double& a0,
                       double&) const {
@@ -492,7 +486,6 @@ struct EpInitResid {  // r = f - A x; acc[r] += r.r; acc[nrhs + r] += f.f
   struct Pre {
     Pre3<double> f;
   };
-  __device__ bool rhs_on(int) const { return true; }
   __device__ Pre pre(int r, long node) const { return Pre{ld3(f + (size_t)r * ndof + 3 * node)}; }
   __device__ void put(int r, long node, const double ax[3], const Pre& pv, double& a0,
                       double& a1) const {
@@ -511,14 +504,12 @@ struct EpTrueResid {  // for load cases under check: r = f - A x; acc[r] += r.r
   const double* f;
   double* rout;
   long ndof;
-  const CgScalars* cs;
   VPrep vp;  // the replaced residual is the next V-cycle's input
   static constexpr bool RED = true;
   struct Pre {
     Pre3<double> f;
     double wd[3];
   };
-  __device__ bool rhs_on(int r) const { return cs[r].state == CG_CHECK; }
   __device__ Pre pre(int r, long node) const {
     Pre pv{ld3(f + (size_t)r * ndof + 3 * node), {0.0, 0.0, 0.0}};
     if (vp.x0)
@@ -538,6 +529,17 @@ struct EpTrueResid {  // for load cases under check: r = f - A x; acc[r] += r.r
   }
 };
 
+// Epilogues of kernels that usually find their gate closed (a true-residual
+// check runs on few iterations) test it first and return at once; every
+// other kernel tests it just before its first store.
+template <class Ep> struct GateEarly { static constexpr bool v = false; };
+template <> struct GateEarly<EpTrueResid> { static constexpr bool v = true; };
+// Epilogues that store only for the load cases in the gate's state (the
+// others store for every load case while any is).
+template <class Ep> struct PerRhs { static constexpr bool v = false; };
+template <> struct PerRhs<EpDotPQ> { static constexpr bool v = true; };
+template <> struct PerRhs<EpTrueResid> { static constexpr bool v = true; };
+
 // ------------------------------------------------------------ apply kernel
 // One output node per thread, one load case per grid row (blockIdx.y).
 // Register budgets: the matrix-free kernel keeps the 27-node neighbourhood in
@@ -551,17 +553,24 @@ template <typename T> struct Waves<OpMF<T>> { static constexpr int w = 2; };
 template <typename T, class Op, class In, class Ep>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(Waves<Op>::w)))
 void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_state, double* part) {
-  if (gate && !any_state(gate, nrhs, gate_state)) return;
   int bx, r;
   xcd_tile(bx, r);
-  const long node = (long)bx * BS + threadIdx.x;
-  double a0 = 0.0, a1 = 0.0;
-  if (node < op.L.nn() && ep.rhs_on(r)) {
-    const typename Ep::Pre pv = ep.pre(r, node);
-    T ax[3];
-    ax_any(op, in, r, node, ax);
-    ep.put(r, node, ax, pv, a0, a1);
+  const Gate g = gate_load(gate, nrhs, gate_state);
+  const int gr = PerRhs<Ep>::v ? r : -1;
+  if constexpr (GateEarly<Ep>::v) {
+    if (!gate_open(g, gr)) return;
   }
+  const long node = (long)bx * BS + threadIdx.x;
+  const long nn = op.L.nn();
+  const long nodec = node < nn ? node : nn - 1;  // tail threads compute a copy, store nothing
+  double a0 = 0.0, a1 = 0.0;
+  const typename Ep::Pre pv = ep.pre(r, nodec);
+  T ax[3];
+  ax_any(op, in, r, nodec, ax);
+  // the gathers complete before the gate test (kept from sinking into it)
+  asm volatile("" : "+v"(ax[0]), "+v"(ax[1]), "+v"(ax[2]));
+  if (!gate_open(g, gr)) return;
+  if (node < nn) ep.put(r, node, ax, pv, a0, a1);
   if constexpr (Ep::RED) {
     block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
                    part + (size_t)(4 + r) * MAX_BLOCKS + bx);
@@ -586,11 +595,15 @@ template <typename T, class Ep>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars* gate,
                     int gate_state, double* part) {
-  if (gate && !any_state(gate, nrhs, gate_state)) return;
   extern __shared__ __align__(16) unsigned char sh_raw[];
   T* sh = reinterpret_cast<T*>(sh_raw);
   int bx, r;
   xcd_tile(bx, r);
+  const Gate g = gate_load(gate, nrhs, gate_state);
+  const int gr = PerRhs<Ep>::v ? r : -1;
+  if constexpr (GateEarly<Ep>::v) {
+    if (!gate_open(g, gr)) return;
+  }
   const Lat L = op.L;
   const int nn = (int)L.nn();
   const int nx = L.nx, P = L.nx * L.ny;
@@ -598,29 +611,20 @@ void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars*
   const int n0 = bx * BS;
   const int t_ = threadIdx.x;
   // stage: plane sgi (dz = sgi - 1) holds nodes [n0 + dz P - nx - 1, + lr)
-  {
-    const __amdgpu_buffer_rsrc_t rx =
-        make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
-    // 8-byte loads: each value is range-checked on its own (values off the
-    // vector read exactly 0)
-    // (a value past its plane's range is still loaded, from the vector or as
-    // 0 beyond it, and simply not stored: no per-load select)
-    T v[3][MF_LDS_VALS];
-    const int off0 = (3 * (n0 - P - nx - 1) + t_) * (int)sizeof(T);  // may be negative
-    const int pstride = 3 * P * (int)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rx =
+      make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
+  // 8-byte loads: each value is range-checked on its own (values off the
+  // vector read exactly 0)
+  // (a value past its plane's range is still loaded, from the vector or as
+  // 0 beyond it, and simply not stored: no per-load select)
+  T v[3][MF_LDS_VALS];
+  const int off0 = (3 * (n0 - P - nx - 1) + t_) * (int)sizeof(T);  // may be negative
+  const int pstride = 3 * P * (int)sizeof(T);
 #pragma unroll
-    for (int sgi = 0; sgi < 3; ++sgi)
+  for (int sgi = 0; sgi < 3; ++sgi)
 #pragma unroll
-      for (int m = 0; m < MF_LDS_VALS; ++m)
-        v[sgi][m] = bload<T>(rx, off0 + (sgi * pstride + m * BS * (int)sizeof(T)), 0);
-#pragma unroll
-    for (int sgi = 0; sgi < 3; ++sgi)
-#pragma unroll
-      for (int m = 0; m < MF_LDS_VALS; ++m) {
-        const int q = t_ + m * BS;
-        if (q < nd3) sh[sgi * nd3 + q] = v[sgi][m];
-      }
-  }
+    for (int m = 0; m < MF_LDS_VALS; ++m)
+      v[sgi][m] = bload<T>(rx, off0 + (sgi * pstride + m * BS * (int)sizeof(T)), 0);
   const int node = n0 + t_;
   const int nodec = node < nn ? node : nn - 1;  // tail threads compute a copy, store nothing
   int i, j, k;
@@ -644,7 +648,17 @@ void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars*
     const bool ok = vx[ox] && vy[oy] && vz[oz];
     Ev[o] = bload<T>(re, ok ? eoff + (ox * (int)sizeof(T) + oy * op.ey + oz * op.ez) : kBufOOB, 0);
   }
+  // the stage's LDS writes come after every global load of the prologue, so
+  // that all of those loads are in flight together
+#pragma unroll
+  for (int sgi = 0; sgi < 3; ++sgi)
+#pragma unroll
+    for (int m = 0; m < MF_LDS_VALS; ++m) {
+      const int q = t_ + m * BS;
+      if (q < nd3) sh[sgi * nd3 + q] = v[sgi][m];
+    }
   __syncthreads();
+  if (!gate_open(g, gr)) return;  // uniform: the block's loads are done
   // Neighbour rows (dy, dz) of 3 nodes are read from LDS one at a time and
   // folded into the 24 element partial sums, so only one row is live in
   // registers (four waves fit per SIMD: every wave of a 0.7M-DOF apply is
@@ -710,7 +724,7 @@ void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars*
 #pragma unroll
   for (int c = 0; c < 3; ++c) ax[c] = ((mself >> c) & 1) ? T(0) : acc[c];
   double a0 = 0.0, a1 = 0.0;
-  if (node < nn && ep.rhs_on(r)) ep.put(r, node, ax, pv, a0, a1);
+  if (node < nn) ep.put(r, node, ax, pv, a0, a1);
   if constexpr (Ep::RED) {
     block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
                    part + (size_t)(4 + r) * MAX_BLOCKS + bx);
@@ -731,7 +745,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
                                                  const CgScalars* gate, int gate_state,
                                                  double* part) {
-  if (gate && !any_state(gate, nrhs, gate_state)) return;
   __shared__ T red[ST_LPN - 1][3][ST_NODES];
   // the wave index must be provably uniform: it selects the coefficient
   // rows through the scalar offset of every buffer load (a divergent value
@@ -740,9 +753,14 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
   const int lane = threadIdx.x % ST_NODES;
   int bx, r;
   xcd_tile(bx, r);
+  const Gate g = gate_load(gate, nrhs, gate_state);
+  const int gr = PerRhs<Ep>::v ? r : -1;
+  if constexpr (GateEarly<Ep>::v) {
+    if (!gate_open(g, gr)) return;
+  }
   const long node = (long)bx * ST_NODES + lane;
   double a0 = 0.0, a1 = 0.0;
-  const bool on = node < op.L.nn() && ep.rhs_on(r);
+  const bool on = node < op.L.nn();
   T ax[3] = {T(0), T(0), T(0)};
   // epilogue operands (used by wave 0), loaded without a branch: a value
   // merged from a conditional load would have to arrive before the gathers
@@ -759,6 +777,7 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
     for (int c = 0; c < 3; ++c) red[wave - 1][c][lane] = ax[c];
   }
   __syncthreads();
+  if (!gate_open(g, gr)) return;  // uniform
   if (wave == 0 && on) {
 #pragma unroll
     for (int w = 0; w < ST_LPN - 1; ++w)
@@ -938,31 +957,34 @@ void cg_init_residual(const FineOp& A, const double* f, const double* x, double*
 void cg_apply_alpha(const FineOp& A, const double* p, double* q, int nrhs, CgScalars* cs,
                     RedBuf red, hipStream_t st) {
   const long nd = A.lat().ndof();
-  fine_dispatch(A, InPlain<double>{p, nd}, EpDotPQ{p, q, nd, cs}, nrhs, cs, CG_ACTIVE, st,
+  fine_dispatch(A, InPlain<double>{p, nd}, EpDotPQ{p, q, nd}, nrhs, cs, CG_ACTIVE, st,
                 red.partials + RED_PQ * RED_REGION);
 }
 
 // x += a p, r -= a q with a = r.z / p.q re-summed by every block.
+// WB: bytes of a W D^-1 value of the V-cycle input written with r (0: none),
+// a template parameter so that the operand loads carry no branch.
+template <int WB>
 __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
                                                   const double* __restrict__ q, double* x, double* r,
                                                   long ndof, int nrhs, CgScalars* cs,
                                                   const double* __restrict__ ppq, int nbq,
                                                   double* prr, VPrep vp) {
-  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   __shared__ double sh[BS / 64];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const long step = (long)gridDim.x * BS * VU;
+  // the load case's scalars are loaded first and tested once its first
+  // operands and partial sums are on their way
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
-    if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
-    const int par = (cs[rr].iters + 1) & 1;
-    const double rz = cs[rr].rzs[par];
+    if (rr >= nrhs) continue;
+    int state = state_of(cs, rr), it = cs_int(cs, rr, CS_OFF(iters));
+    double rz0 = cs_dbl(cs, rr, CS_OFF(rzs)), rz1 = cs_dbl(cs, rr, CS_OFF(rzs) + 8);
     const size_t o = (size_t)rr * ndof;
     const size_t nb = (size_t)ndof * sizeof(double);
     const __amdgpu_buffer_rsrc_t bp = make_rsrc(p + o, nb), bq = make_rsrc(q + o, nb),
                                  bx = make_rsrc(x + o, nb), br = make_rsrc(r + o, nb);
-    const __amdgpu_buffer_rsrc_t bw =
-        make_rsrc(vp.wD, (size_t)ndof * (vp.f32 ? sizeof(float) : sizeof(double)));
+    const __amdgpu_buffer_rsrc_t bw = make_rsrc(vp.wD, (size_t)ndof * (WB ? WB : 8));
     double pv[VU], qv[VU], xv[VU], rv[VU], wv[VU];
     auto fetch = [&](long i0) {
 #pragma unroll
@@ -972,14 +994,24 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
         qv[k] = bload<double>(bq, off, 0);
         xv[k] = bload<double>(bx, off, 0);
         rv[k] = bload<double>(br, off, 0);
-        wv[k] = !vp.x0 ? 0.0
-                : vp.f32 ? (double)bload<float>(bw, (int)((i0 + k * BS) * sizeof(float)), 0)
-                         : bload<double>(bw, off, 0);
+        if constexpr (WB == 4)
+          wv[k] = (double)bload<float>(bw, (int)((i0 + k * BS) * sizeof(float)), 0);
+        else if constexpr (WB == 8)
+          wv[k] = bload<double>(bw, off, 0);
+        else
+          wv[k] = 0.0;
       }
     };
     long i0 = (long)blockIdx.x * BS * VU + threadIdx.x;
     fetch(i0);  // the first pass's operands travel with the partial sums
-    const double pq = block_sum(ppq + (size_t)rr * MAX_BLOCKS, nbq, sh);
+    const double spq = block_sum_loads(ppq + (size_t)rr * MAX_BLOCKS, nbq);
+    pin(state);
+    pin(it);
+    pin(rz0);
+    pin(rz1);
+    const double pq = block_sum_finish(spq, sh);
+    if (state != CG_ACTIVE) continue;  // uniform
+    const double rz = ((it + 1) & 1) ? rz1 : rz0;
     const double a = (pq > 0.0 && isfinite(pq)) ? rz / pq : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cs[rr].pq = pq;
@@ -995,7 +1027,13 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
         if (i < ndof) {
           x[o + i] = xv[k] + a * pv[k];
           r[o + i] = rn;
-          if (vp.x0) vprep_put(vp, o + i, rn, wv[k]);
+          if constexpr (WB == 4) {
+            const float b = (float)rn;
+            ((float*)vp.b0)[o + i] = b;
+            ((float*)vp.x0)[o + i] = (float)wv[k] * b;
+          } else if constexpr (WB == 8) {
+            ((double*)vp.x0)[o + i] = wv[k] * rn;
+          }
         }
       }
       if (i0 + step < ndof) fetch(i0 + step);
@@ -1011,17 +1049,29 @@ __global__ __launch_bounds__(BS) void k_update_xr(const double* __restrict__ p,
 __global__ void k_fin_rr(CgScalars* cs, int nrhs, const double* part, int nb) {
   __shared__ double sh[BS / 64];
   for (int r = 0; r < nrhs; ++r) {
-    if (cs[r].state != CG_ACTIVE) continue;  // uniform
-    const double rr = block_sum(part + (size_t)r * MAX_BLOCKS, nb, sh);
+    // the scalars the test needs travel with the partial sums
+    int state = state_of(cs, r), it = cs_int(cs, r, CS_OFF(iters)),
+        bad = cs_int(cs, r, CS_OFF(bad)), maxit = cs_int(cs, r, CS_OFF(maxit)),
+        every = cs_int(cs, r, CS_OFF(replace_every));
+    double pq = cs_dbl(cs, r, CS_OFF(pq)), tol2 = cs_dbl(cs, r, CS_OFF(tol2));
+    const double s = block_sum_loads(part + (size_t)r * MAX_BLOCKS, nb);
+    pin(state);
+    pin(it);
+    pin(bad);
+    pin(maxit);
+    pin(every);
+    pin(pq);
+    pin(tol2);
+    const double rr = block_sum_finish(s, sh);
+    if (state != CG_ACTIVE) continue;  // uniform
     if (threadIdx.x == 0) {
       CgScalars& c = cs[r];
       c.rr = rr;
-      c.iters += 1;
-      const int it = c.iters;
-      if (!(c.pq > 0.0) || !isfinite(c.pq) || c.bad || !isfinite(rr))
+      it += 1;
+      c.iters = it;
+      if (!(pq > 0.0) || !isfinite(pq) || bad || !isfinite(rr))
         c.state = CG_BREAKDOWN;
-      else if (rr <= c.tol2 || it >= c.maxit ||
-               (c.replace_every > 0 && it % c.replace_every == 0))
+      else if (rr <= tol2 || it >= maxit || (every > 0 && it % every == 0))
         c.state = CG_CHECK;
     }
     __syncthreads();
@@ -1032,7 +1082,8 @@ void cg_update_xr(const double* p, const double* q, double* x, double* r, long n
                   CgScalars* cs, RedBuf red, int nbq, VPrep vp, hipStream_t st) {
   double* prr = red.partials + RED_RR * RED_REGION;
   const int g = vec_grid(ndof);
-  hipLaunchKernelGGL(k_update_xr, dim3(g), dim3(BS), 0, st, p, q, x, r, ndof, nrhs, cs,
+  auto kern = !vp.x0 ? k_update_xr<0> : vp.f32 ? k_update_xr<4> : k_update_xr<8>;
+  hipLaunchKernelGGL(kern, dim3(g), dim3(BS), 0, st, p, q, x, r, ndof, nrhs, cs,
                      red.partials + RED_PQ * RED_REGION, nbq, prr, vp);
   MGCG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(BS), 0, st, cs, nrhs, prr, g);
@@ -1076,7 +1127,7 @@ void cg_true_residual(const FineOp& A, const double* f, const double* x, double*
                       CgScalars* cs, RedBuf red, VPrep vp, hipStream_t st) {
   const long nd = A.lat().ndof();
   double* part = red.partials + RED_TR * RED_REGION;
-  fine_dispatch(A, InPlain<double>{x, nd}, EpTrueResid{f, r, nd, cs, vp}, nrhs, cs, CG_CHECK, st,
+  fine_dispatch(A, InPlain<double>{x, nd}, EpTrueResid{f, r, nd, vp}, nrhs, cs, CG_CHECK, st,
                 part);
   hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(BS), 0, st, cs, nrhs, part, fine_blocks(A));
   MGCG_HIP(hipGetLastError());
@@ -1145,15 +1196,16 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
                                                  const double* __restrict__ r, double* rold,
                                                  long ndof, int nrhs, CgScalars* cs,
                                                  const double* __restrict__ part, int nbz) {
-  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   __shared__ double sh[BS / 64];
   const long step = (long)gridDim.x * BS * VU;
+  // the FP32 V-cycle is the flexible one; r_old only feeds the flexible beta
+  constexpr bool flexible = sizeof(TZ) == 4;
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
-    if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
-    const int par = cs[rr].iters & 1;
-    const double rzo = cs[rr].rzs[par];
-    const bool flexible = cs[rr].flexible != 0;  // r_old only feeds the flexible beta
+    if (rr >= nrhs) continue;
+    // scalars loaded first, tested once the first operands are on their way
+    int state = state_of(cs, rr), it = cs_int(cs, rr, CS_OFF(iters));
+    double rz0 = cs_dbl(cs, rr, CS_OFF(rzs)), rz1 = cs_dbl(cs, rr, CS_OFF(rzs) + 8);
     const size_t o = (size_t)rr * ndof;
     const size_t nb = (size_t)ndof * sizeof(double);
     const __amdgpu_buffer_rsrc_t bp = make_rsrc(p + o, nb), br = make_rsrc(r + o, nb),
@@ -1170,8 +1222,17 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
     };
     long i0 = (long)blockIdx.x * BS * VU + threadIdx.x;
     fetch(i0);
-    const double rzn = block_sum(part + (size_t)rr * MAX_BLOCKS, nbz, sh);
-    const double rzm = flexible ? block_sum(part + (size_t)(4 + rr) * MAX_BLOCKS, nbz, sh) : 0.0;
+    const double sn = block_sum_loads(part + (size_t)rr * MAX_BLOCKS, nbz);
+    const double sm = flexible ? block_sum_loads(part + (size_t)(4 + rr) * MAX_BLOCKS, nbz) : 0.0;
+    pin(state);
+    pin(it);
+    pin(rz0);
+    pin(rz1);
+    const double rzn = block_sum_finish(sn, sh);
+    const double rzm = flexible ? block_sum_finish(sm, sh) : 0.0;
+    if (state != CG_ACTIVE) continue;  // uniform
+    const int par = it & 1;
+    const double rzo = par ? rz1 : rz0;
     const bool ok = isfinite(rzn) && isfinite(rzm);
     const double num = flexible ? (rzn - rzm) : rzn;
     const double b = (!ok || rzo == 0.0) ? 0.0 : num / rzo;
@@ -1294,7 +1355,7 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
                                                  const T* __restrict__ rf, T* bc,
                                                  const T* __restrict__ wDc, T* xc, int nrhs,
                                                  const CgScalars* cs) {
-  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  const Gate g = gate_load(cs, nrhs, CG_ACTIVE);
   int bx, r;
   xcd_tile(bx, r);  // r: load case
   const long t = (long)bx * BS + threadIdx.x;
@@ -1325,11 +1386,17 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
       acc = fma(w, bload<T>(rb, off[q], 0), acc);
     }
     // (mask read after the gathers so that all loads are in flight together)
-    const bool fixed = (mc[node] >> c) & 1;
+    int mcn = mc[node];
+    T wd = xc ? wDc[t] : T(0);
+    pin(acc);
+    pin(mcn);
+    pin(wd);
+    if (!gate_open(g)) return;
+    const bool fixed = (mcn >> c) & 1;
     const T bv = fixed ? T(0) : acc;
     bc[(size_t)r * cnd + t] = bv;
     // first smoothing sweep of the coarse level from zero: x = W D^-1 b
-    if (xc) xc[(size_t)r * cnd + t] = wDc[t] * bv;
+    if (xc) xc[(size_t)r * cnd + t] = wd * bv;
   }
   (void)mf;
 }
@@ -1348,7 +1415,7 @@ __global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __r
                                                 const uint8_t* __restrict__ mc,
                                                 const T* __restrict__ ec, T* xf, int nrhs,
                                                 int accumulate, const CgScalars* cs) {
-  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  const Gate g = gate_load(cs, nrhs, CG_ACTIVE);
   int bx, r;
   xcd_tile(bx, r);  // r: load case
   const long node = (long)bx * BS + threadIdx.x;
@@ -1386,7 +1453,14 @@ __global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __r
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[c] += v[c];
     }
-    const uint8_t mfn = mf[node];
+    int mfn = mf[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pin(acc[c]);
+      pin(old[c]);
+    }
+    pin(mfn);
+    if (!gate_open(g)) return;
     T* qv = xf + (size_t)r * fnd + 3 * node;
 #pragma unroll
     for (int c = 0; c < 3; ++c) qv[c] = old[c] + (((mfn >> c) & 1) ? T(0) : w * acc[c]);
@@ -1407,7 +1481,7 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ Ainv, int ld,
                                                      long ndof, const T* __restrict__ b, T* x,
                                                      int nrhs, const CgScalars* cs) {
-  if (!any_state(cs, nrhs, CG_ACTIVE)) return;
+  const Gate g = gate_load(cs, nrhs, CG_ACTIVE);
   const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= ndof) return;
@@ -1426,6 +1500,8 @@ __global__ __launch_bounds__(BS) void k_coarse_solve(const double* __restrict__ 
 #pragma unroll
     for (int q = 0; q < 8; ++q) s = fma(a[q], v[q], s);
   }
+  pin(s);
+  if (!gate_open(g)) return;
   s = wave_sum(s);
   if (lane == 0) x[(size_t)r * ndof + row] = (T)s;
 }

@@ -30,11 +30,48 @@ struct InPlain {
   struct Buf {
     __amdgpu_buffer_rsrc_t rx;
     __device__ __forceinline__ void load(int voff, T v[3]) const { bload3<T>(rx, voff, v); }
+    // node (i, j, k), dz above or below the centre's plane, at byte offset
+    // voff (kBufOOB: off the lattice, reads 0)
+    __device__ __forceinline__ void load_node(int, int, int, int, int voff, T v[3]) const {
+      bload3<T>(rx, voff, v);
+    }
   };
   __device__ __forceinline__ Buf buf(int r) const {
     return Buf{make_rsrc(x + (size_t)r * ndof, ndof * sizeof(T))};
   }
 };
+
+// Trilinear prolongation of a coarse field at fine node (i, j, k): the sum of
+// the 1, 2, 4 or 8 coarse nodes around it (a second corner per odd
+// coordinate) times 1/2 per odd coordinate.  Unused corners, and every corner
+// when !ok, read through out-of-range offsets (0), so there are no branches.
+// Coarse values vanish on fixed coarse DOFs; the caller masks fixed fine ones.
+template <typename T>
+__device__ __forceinline__ void prolong_at(const Lat& C, __amdgpu_buffer_rsrc_t re, int i, int j,
+                                           int k, bool ok, T pe[3]) {
+  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+  const bool oi = i & 1, oj = j & 1, ok_ = k & 1;
+  const T w = (oi ? T(0.5) : T(1)) * (oj ? T(0.5) : T(1)) * (ok_ ? T(0.5) : T(1));
+  T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
+    const bool use = ok && (!a || oi) && (!b || oj) && (!cc || ok_);
+    const int off =
+        use ? 3 * ((i0 + a) + C.nx * ((j0 + b) + C.ny * (k0 + cc))) * (int)sizeof(T) : kBufOOB;
+    T v[3];
+    bload3<T>(re, off, v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += v[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) pe[c] = w * acc[c];
+}
+
+__device__ __forceinline__ int bload_u8(__amdgpu_buffer_rsrc_t r, int voff) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b8(r, voff, 0, 0);
+}
+
 
 // ------------------------------------------------------------ operators
 __device__ __forceinline__ void node_ijk(long node, const Lat& L, int& i, int& j, int& k) {
@@ -192,7 +229,7 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
       const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T)) : kBufOOB;
       const int co = ok ? vself : kBufOOB;
       T v[3];
-      xb.load(xo, v);
+      xb.load_node(ii, jj, kk, d.dz, xo, v);
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -207,7 +244,7 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
       const int xo = ok ? (int)(nb * 3 * sizeof(T)) : kBufOOB;
       const int co = ok ? (int)(nb * sizeof(T)) : kBufOOB;
       T v[3];
-      xb.load(xo, v);
+      xb.load_node(ii, jj, kk, -d.dz, xo, v);
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -1285,6 +1322,110 @@ void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs
   v_dispatch(v, InPlain<T>{x, nd}, EpJacobi<T>{b, x, v.invD, omega, xo, nd}, nrhs, cs, st);
 }
 
+// First post-smoothing sweep of a small stencil level fused with the
+// prolongation of the coarse correction.  The block's 64 nodes read their
+// neighbours from LDS, where the block has staged y = x + P~ e over the three
+// node ranges around it (plane dz holds nodes [n0 + dz P - nx - 1, + lr)),
+// the prolongation done once per staged node.
+template <typename T>
+struct InLds {
+  const T* sh;
+  int n0, nx, ny, P, lr;
+  struct Buf {
+    const T* sh;
+    int n0, nx, ny, P, lr;
+    __device__ __forceinline__ void load_node(int ii, int jj, int kk, int dz, int voff,
+                                              T v[3]) const {
+      const int nb = ii + nx * (jj + ny * kk);
+      const int q = (dz + 1) * lr + (nb - (n0 + dz * P - nx - 1));
+      const bool ok = voff != kBufOOB;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = ok ? sh[3 * q + c] : T(0);
+    }
+  };
+  __device__ __forceinline__ Buf buf(int) const { return Buf{sh, n0, nx, ny, P, lr}; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_st_jacobi_prolong(OpST<T> op, const T* __restrict__ x, const T* __restrict__ e, Lat C,
+                         const uint8_t* __restrict__ mf, const T* __restrict__ b,
+                         const T* __restrict__ wD, T omega, T* xo, int nrhs,
+                         const CgScalars* gate) {
+  extern __shared__ __align__(16) unsigned char sh_raw[];
+  T* sh = reinterpret_cast<T*>(sh_raw);
+  __shared__ T red[ST_LPN - 1][3][ST_NODES];
+  const Gate g = gate_load(gate, nrhs, CG_ACTIVE);
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / ST_NODES);
+  const int lane = threadIdx.x % ST_NODES;
+  int bx, r;
+  xcd_tile(bx, r);
+  const Lat L = op.L;
+  const int nn = (int)L.nn(), nd = (int)L.ndof(), cnd = (int)C.ndof();
+  const int nx = L.nx, P = L.nx * L.ny, lr = ST_NODES + 2 * L.nx + 2;
+  const int n0 = bx * ST_NODES;
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(x + (size_t)r * nd, (size_t)nd * sizeof(T)),
+                               re = make_rsrc(e + (size_t)r * cnd, (size_t)cnd * sizeof(T)),
+                               rm = make_rsrc(mf, (size_t)nn);
+  for (int q = threadIdx.x; q < 3 * lr; q += BS) {
+    const int plane = q / lr;
+    const int node = n0 + (plane - 1) * P - nx - 1 + (q - plane * lr);
+    const bool ok = node >= 0 && node < nn;
+    int i, j, k;
+    node_ijk(ok ? node : 0, L, i, j, k);
+    T v[3], pe[3];
+    bload3<T>(rx, ok ? 3 * node * (int)sizeof(T) : kBufOOB, v);
+    prolong_at<T>(C, re, i, j, k, ok, pe);
+    const int mfn = bload_u8(rm, ok ? node : kBufOOB);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sh[3 * q + c] = v[c] + (((mfn >> c) & 1) ? T(0) : pe[c]);
+  }
+  const int node = n0 + lane;
+  const bool on = node < nn;
+  const int nodec = on ? node : nn - 1;
+  // epilogue operands (wave 0)
+  const Pre3<T> bv = ld3(b + (size_t)r * nd + 3 * nodec), dv = ld3(wD + 3 * nodec);
+  __syncthreads();
+  T ax[3] = {T(0), T(0), T(0)};
+  if (on) {
+    int i, j, k;
+    node_ijk(node, L, i, j, k);
+    ax_st_part<ST_LPN>(op, InLds<T>{sh, n0, nx, L.ny, P, lr}, r, i, j, k, node, wave, ax);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) red[wave - 1][c][lane] = ax[c];
+  }
+  __syncthreads();
+  if (!gate_open(g)) return;  // uniform
+  if (wave == 0 && on) {
+#pragma unroll
+    for (int w = 0; w < ST_LPN - 1; ++w)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ax[c] += red[w][c][lane];
+    const int qc = lr + nx + 1 + lane;  // the node itself: plane dz = 0
+    T* out = xo + (size_t)r * nd + 3 * node;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T y = sh[3 * qc + c];
+      out[c] = y + omega * dv.v[c] * (bv.v[c] - ax[c]);
+    }
+  }
+}
+
+template <typename T>
+void v_jacobi_prolong(const VOps<T>& v, const VOps<T>& vc, const T* b, const T* x, T* xo,
+                      T omega, const T* e, int nrhs, const CgScalars* cs, hipStream_t st) {
+  if (v.kind != OP_ST27) throw Error(-1, "fused prolongation needs a stencil level");
+  const long nn = v.L.nn();
+  const int lr = ST_NODES + 2 * v.L.nx + 2;
+  const size_t lds = (size_t)9 * lr * sizeof(T);
+  if (lds > 64 * 1024) throw Error(-1, "level too wide for the fused prolongation");
+  hipLaunchKernelGGL(k_st_jacobi_prolong<T>, dim3(apply_blocks(OP_ST27, nn, sizeof(T) == 8), nrhs),
+                     dim3(BS), lds, st, v.st, x, e, vc.L, v.mask, b, v.invD, omega, xo, nrhs, cs);
+  MGCG_HIP(hipGetLastError());
+}
+
 template <typename T>
 void v_jacobi_dot(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, const double* r,
                   const double* rold, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st) {
@@ -1347,8 +1488,36 @@ void v_prepare0(const double* r, T* b0, const T* wD, T* x0, long ndof, int nrhs,
 
 
 // Restriction: coarse DOF (I, c) gathers component c of the 3x3x3 fine nodes
-// around 2I with weights prod_d (1 - |offset_d| / 2); one thread per coarse
-// DOF.  Fine inputs vanish on fixed DOFs; fixed coarse DOFs get 0.
+// around 2I with weights prod_d (1 - |offset_d| / 2).  Fine inputs vanish on
+// fixed DOFs; the caller zeroes fixed coarse DOFs.  Out-of-range neighbours
+// read through out-of-range offsets (0): no branches, so all 27 loads are
+// issued back to back.
+template <typename T>
+__device__ __forceinline__ T restrict_at(const Lat& F, __amdgpu_buffer_rsrc_t rb, int I, int J,
+                                         int K, int c) {
+  int off[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int i = 2 * I + q % 3 - 1, j = 2 * J + (q / 3) % 3 - 1, k = 2 * K + q / 9 - 1;
+    const bool ok = (unsigned)i < (unsigned)F.nx && (unsigned)j < (unsigned)F.ny &&
+                    (unsigned)k < (unsigned)F.nz;
+    off[q] = ok ? (3 * (i + F.nx * (j + F.ny * k)) + c) * (int)sizeof(T) : kBufOOB;
+  }
+  T v[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) v[q] = bload<T>(rb, off[q], 0);
+  T acc = T(0);
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+    const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+    acc = fma(w, v[q], acc);
+  }
+  return acc;
+}
+
+// One thread per coarse DOF; also the coarse level's first smoothing sweep
+// from zero, x = W D^-1 b, when xc is given.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __restrict__ mf,
                                                  const uint8_t* __restrict__ mc,
@@ -1366,38 +1535,18 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
   int I, J, K;
   node_ijk(node, C, I, J, K);
   const long fnd = F.ndof();
-  // byte offsets of the 27 fine neighbours (out-of-range ones read 0); no
-  // branches, so all 27 loads are issued back to back
-  int off[27];
-#pragma unroll
-  for (int q = 0; q < 27; ++q) {
-    const int i = 2 * I + q % 3 - 1, j = 2 * J + (q / 3) % 3 - 1, k = 2 * K + q / 9 - 1;
-    const bool ok = (unsigned)i < (unsigned)F.nx && (unsigned)j < (unsigned)F.ny &&
-                    (unsigned)k < (unsigned)F.nz;
-    off[q] = ok ? (int)((3 * (i + (long)F.nx * (j + (long)F.ny * k)) + c) * sizeof(T)) : kBufOOB;
-  }
-  {
-    const __amdgpu_buffer_rsrc_t rb = make_rsrc(rf + (size_t)r * fnd, (size_t)fnd * sizeof(T));
-    T acc = T(0);
-#pragma unroll
-    for (int q = 0; q < 27; ++q) {
-      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
-      const T w = T((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
-      acc = fma(w, bload<T>(rb, off[q], 0), acc);
-    }
-    // (mask read after the gathers so that all loads are in flight together)
-    int mcn = mc[node];
-    T wd = xc ? wDc[t] : T(0);
-    pin(acc);
-    pin(mcn);
-    pin(wd);
-    if (!gate_open(g)) return;
-    const bool fixed = (mcn >> c) & 1;
-    const T bv = fixed ? T(0) : acc;
-    bc[(size_t)r * cnd + t] = bv;
-    // first smoothing sweep of the coarse level from zero: x = W D^-1 b
-    if (xc) xc[(size_t)r * cnd + t] = wd * bv;
-  }
+  T acc = restrict_at<T>(F, make_rsrc(rf + (size_t)r * fnd, (size_t)fnd * sizeof(T)), I, J, K, c);
+  // (mask read after the gathers so that all loads are in flight together)
+  int mcn = mc[node];
+  T wd = xc ? wDc[t] : T(0);
+  pin(acc);
+  pin(mcn);
+  pin(wd);
+  if (!gate_open(g)) return;
+  const bool fixed = (mcn >> c) & 1;
+  const T bv = fixed ? T(0) : acc;
+  bc[(size_t)r * cnd + t] = bv;
+  if (xc) xc[(size_t)r * cnd + t] = wd * bv;
   (void)mf;
 }
 
@@ -1422,49 +1571,24 @@ __global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __r
   if (node >= F.nn()) return;
   int i, j, k;
   node_ijk(node, F, i, j, k);
-  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-  const bool oi = i & 1, oj = j & 1, ok = k & 1;
-  const T w = (oi ? T(0.5) : T(1)) * (oj ? T(0.5) : T(1)) * (ok ? T(0.5) : T(1));
-  // the 8 coarse corners i0 + {0,1} x ...; a second corner only on an odd
-  // coordinate (otherwise read through an out-of-range offset, giving 0)
-  int off[8];
+  const int fnd = (int)F.ndof(), cnd = (int)C.ndof();
+  // the old fine value (accumulate) is read branch-free together with the
+  // corners: an out-of-range offset gives 0 when overwriting
+  const __amdgpu_buffer_rsrc_t rq = make_rsrc(xf + (size_t)r * fnd, (size_t)fnd * sizeof(T));
+  T pe[3], old[3];
+  bload3<T>(rq, accumulate ? 3 * (int)node * (int)sizeof(T) : kBufOOB, old);
+  prolong_at<T>(C, make_rsrc(ec + (size_t)r * cnd, (size_t)cnd * sizeof(T)), i, j, k, true, pe);
+  int mfn = mf[node];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
-    const bool use = (!a || oi) && (!b || oj) && (!cc || ok);
-    off[q] = use ? (int)(3 * ((i0 + a) + (long)C.nx * ((j0 + b) + (long)C.ny * (k0 + cc))) *
-                         sizeof(T))
-                 : kBufOOB;
+  for (int c = 0; c < 3; ++c) {
+    pin(pe[c]);
+    pin(old[c]);
   }
-  const long fnd = F.ndof(), cnd = C.ndof();
-  {
-    // coarse corrections vanish on fixed coarse DOFs
-    const __amdgpu_buffer_rsrc_t rb = make_rsrc(ec + (size_t)r * cnd, (size_t)cnd * sizeof(T));
-    // the old fine value (accumulate) is read branch-free together with
-    // the corners: an out-of-range offset gives 0 when overwriting
-    const __amdgpu_buffer_rsrc_t rq = make_rsrc(xf + (size_t)r * fnd, (size_t)fnd * sizeof(T));
-    T acc[3], old[3];
-    bload3<T>(rq, accumulate ? (int)(3 * node * sizeof(T)) : kBufOOB, old);
-    acc[0] = acc[1] = acc[2] = T(0);
+  pin(mfn);
+  if (!gate_open(g)) return;
+  T* qv = xf + (size_t)r * fnd + 3 * node;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      T v[3];
-      bload3<T>(rb, off[q], v);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] += v[c];
-    }
-    int mfn = mf[node];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      pin(acc[c]);
-      pin(old[c]);
-    }
-    pin(mfn);
-    if (!gate_open(g)) return;
-    T* qv = xf + (size_t)r * fnd + 3 * node;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) qv[c] = old[c] + (((mfn >> c) & 1) ? T(0) : w * acc[c]);
-  }
+  for (int c = 0; c < 3; ++c) qv[c] = old[c] + (((mfn >> c) & 1) ? T(0) : pe[c]);
 }
 
 template <typename T>
@@ -1515,6 +1639,62 @@ void v_coarse_solve(const double* Ainv, int ld, long ndof, const T* b, T* x, int
   MGCG_HIP(hipGetLastError());
 }
 
+// Coarsest solve fused with the last restriction: b = P~^T r_f is computed by
+// every block into LDS (at most CS_FUSE_MAX values, 27 L2 reads each), then
+// the block's waves take one row of x = A_c^{-1} b each.  Saves a launch on
+// a level where the launch costs more than the redundant restriction.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_coarse_solve_r(const double* __restrict__ Ainv, int ld,
+                                                       Lat F, Lat C, const uint8_t* __restrict__ mc,
+                                                       const T* __restrict__ rf, T* x, int nrhs,
+                                                       const CgScalars* cs) {
+  __shared__ double bsh[CS_FUSE_MAX];
+  const Gate g = gate_load(cs, nrhs, CG_ACTIVE);
+  const int r = blockIdx.y;  // load case
+  const int ndof = (int)C.ndof(), fnd = (int)F.ndof();
+  const __amdgpu_buffer_rsrc_t rb = make_rsrc(rf + (size_t)r * fnd, (size_t)fnd * sizeof(T));
+  for (int t = threadIdx.x; t < ndof; t += BS) {
+    const int node = t / 3, c = t - 3 * node;
+    int I, J, K;
+    node_ijk(node, C, I, J, K);
+    const T acc = restrict_at<T>(F, rb, I, J, K, c);
+    bsh[t] = ((mc[node] >> c) & 1) ? 0.0 : (double)acc;
+  }
+  __syncthreads();
+  const int row = blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  if (row < ndof) {
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(Ainv + (size_t)row * ld, (size_t)ndof * 8);
+    for (int c0 = 0; c0 < ndof; c0 += 4 * 64) {
+      double a[4], v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c0 + lane + 64 * q;
+        a[q] = bload<double>(ra, c * 8, 0);
+        v[q] = c < ndof ? bsh[c] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s = fma(a[q], v[q], s);
+    }
+  }
+  pin(s);
+  if (!gate_open(g) || row >= ndof) return;
+  s = wave_sum(s);
+  if (lane == 0) x[(size_t)r * ndof + row] = (T)s;
+}
+
+template <typename T>
+void v_coarse_solve_r(const double* Ainv, int ld, Lat fine, Lat coarse, const uint8_t* mask_c,
+                      const T* rf, T* x, int nrhs, const CgScalars* cs, hipStream_t st) {
+  const long ndof = coarse.ndof();
+  if (ndof == 0) return;
+  if (ndof > CS_FUSE_MAX) throw Error(-1, "coarsest level too large for the fused solve");
+  hipLaunchKernelGGL(k_coarse_solve_r<T>, dim3((int)((ndof + 3) / 4), nrhs), dim3(BS), 0, st,
+                     Ainv, ld, fine, coarse, mask_c, rf, x, nrhs, cs);
+  MGCG_HIP(hipGetLastError());
+}
+
 #define VINST(T)                                                                                  \
   template void v_jacobi<T>(const VOps<T>&, const T*, const T*, T*, T, int, const CgScalars*,      \
                             hipStream_t);                                                         \
@@ -1529,7 +1709,11 @@ void v_coarse_solve(const double* Ainv, int ld, long ndof, const T* b, T* x, int
   template void v_prolong<T>(Lat, Lat, const uint8_t*, const uint8_t*, const T*, T*, int, bool,    \
                              const CgScalars*, hipStream_t);                                      \
   template void v_coarse_solve<T>(const double*, int, long, const T*, T*, int, const CgScalars*,   \
-                                  hipStream_t);
+                                  hipStream_t);                                                   \
+  template void v_coarse_solve_r<T>(const double*, int, Lat, Lat, const uint8_t*, const T*, T*,    \
+                                    int, const CgScalars*, hipStream_t);                          \
+  template void v_jacobi_prolong<T>(const VOps<T>&, const VOps<T>&, const T*, const T*, T*, T,     \
+                                    const T*, int, const CgScalars*, hipStream_t);
 VINST(double)
 VINST(float)
 

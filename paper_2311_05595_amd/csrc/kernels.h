@@ -146,6 +146,14 @@ void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs
 template <typename T>
 void v_jacobi_dot(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, const double* r,
                   const double* rold, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st);
+// First post-smoothing sweep of a small stencil level fused with the
+// prolongation: xo = y + wD (b - A y) with y = x + P~ e (e on the coarser
+// level vc); y itself is not stored.
+template <typename T>
+void v_jacobi_prolong(const VOps<T>& v, const VOps<T>& vc, const T* b, const T* x, T* xo,
+                      T omega, const T* e, int nrhs, const CgScalars* cs, hipStream_t st);
+// Levels at most this many nodes take the fused sweep above.
+constexpr long PROLONG_FUSE_MAX_NODES = 16384;
 // r = b - A x
 template <typename T>
 void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const CgScalars* cs,
@@ -155,6 +163,12 @@ void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const 
 template <typename T>
 void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* rf,
                 T* bc, const T* wDc, T* xc, int nrhs, const CgScalars* cs, hipStream_t st);
+// Coarsest solve with the last restriction fused in: x = A_c^{-1} P~^T r_f,
+// for coarsest levels of at most CS_FUSE_MAX DOFs.
+constexpr int CS_FUSE_MAX = 1024;
+template <typename T>
+void v_coarse_solve_r(const double* Ainv, int ld, Lat fine, Lat coarse, const uint8_t* mask_c,
+                      const T* rf, T* x, int nrhs, const CgScalars* cs, hipStream_t st);
 // fine += P~ coarse  (accumulate=false: fine = P~ coarse)
 template <typename T>
 void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* ec,

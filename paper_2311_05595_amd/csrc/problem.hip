@@ -553,6 +553,8 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
   } else {
     b0 = (const T*)B_[0].b;
   }
+  // a small coarsest level takes the last restriction inside its solve
+  const bool fuse_cs = L > 1 && lv_[L - 1].L.ndof() <= CS_FUSE_MAX;
   std::vector<T*> cur(L), oth(L);
   std::vector<const T*> bl(L);
   bl[0] = b0;
@@ -579,18 +581,32 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
     v_residual<T>(v, bl[l], cur[l], rl, R, cs, st);
     if (l == 0) timed_end(1);
     const bool coarsest_next = (l + 1 == L - 1);
+    // a small coarsest level takes its restriction inside the coarse solve
+    if (coarsest_next && fuse_cs) continue;
     v_restrict<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, rl, (T*)B_[l + 1].b,
                   (const T*)B_[l + 1].invD, coarsest_next ? nullptr : cur[l + 1], R, cs, st);
   }
   const int lc = L - 1;
-  v_coarse_solve<T>(Ainv_, coarse_ld(lv_[lc].L.ndof()), lv_[lc].L.ndof(), bl[lc], cur[lc], R, cs,
-                    st);
+  if (fuse_cs)
+    v_coarse_solve_r<T>(Ainv_, coarse_ld(lv_[lc].L.ndof()), lv_[lc - 1].L, lv_[lc].L, B_[lc].mask,
+                        (const T*)B_[lc - 1].r, cur[lc], R, cs, st);
+  else
+    v_coarse_solve<T>(Ainv_, coarse_ld(lv_[lc].L.ndof()), lv_[lc].L.ndof(), bl[lc], cur[lc], R,
+                      cs, st);
   for (int l = L - 2; l >= 0; --l) {
     const VOps<T> v = vops<T>(l);
-    v_prolong<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, cur[l + 1], cur[l], R, true, cs, st);
+    // small stencil levels take the prolongation inside their first
+    // post-smoothing sweep
+    const bool fuse_p = d_.post >= 1 && v.kind == OP_ST27 &&
+                        lv_[l].L.nn() <= PROLONG_FUSE_MAX_NODES && !(l == 0 && fuse_dot);
+    if (!fuse_p)
+      v_prolong<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, cur[l + 1], cur[l], R, true,
+                   cs, st);
     for (int s = 0; s < d_.post; ++s) {
       if (l == 0) timed_begin(2);
-      if (l == 0 && fuse_dot && s == d_.post - 1)
+      if (s == 0 && fuse_p)
+        v_jacobi_prolong<T>(v, vops<T>(l + 1), bl[l], cur[l], oth[l], omega, cur[l + 1], R, cs, st);
+      else if (l == 0 && fuse_dot && s == d_.post - 1)
         v_jacobi_dot<T>(v, bl[l], cur[l], oth[l], omega, r_in, rold_, R, cs, red_, st);
       else
         v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);

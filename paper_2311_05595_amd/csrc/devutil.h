@@ -191,6 +191,12 @@ __device__ __forceinline__ bool gate_open(Gate g, int r = -1) {
          ((g.nrhs > 2) & (g.s[2] == g.state)) | ((g.nrhs > 3) & (g.s[3] == g.state));
 }
 
+// Linear node index i + nx (j + ny k) with 24-bit multiplies (every lattice
+// dimension and plane index is far below 2^24).
+__device__ __forceinline__ int lat_index(const Lat& L, int i, int j, int k) {
+  return i + __mul24(L.nx, j + __mul24(L.ny, k));
+}
+
 inline int nblocks(long n, int per = BS) { return (int)((n + per - 1) / per); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own

@@ -53,12 +53,16 @@ __device__ __forceinline__ void prolong_at(const Lat& C, __amdgpu_buffer_rsrc_t 
   const bool oi = i & 1, oj = j & 1, ok_ = k & 1;
   const T w = (oi ? T(0.5) : T(1)) * (oj ? T(0.5) : T(1)) * (ok_ ? T(0.5) : T(1));
   T acc[3] = {T(0), T(0), T(0)};
+  // the corner index is kept opaque: left to itself the compiler folds the
+  // eight corners into full 32-bit multiplies (see lat_index)
+  int base = lat_index(C, i0, j0, k0);
+  asm volatile("" : "+v"(base));
+  const int sy = C.nx, sz = C.nx * C.ny;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
     const bool use = ok && (!a || oi) && (!b || oj) && (!cc || ok_);
-    const int off =
-        use ? 3 * ((i0 + a) + C.nx * ((j0 + b) + C.ny * (k0 + cc))) * (int)sizeof(T) : kBufOOB;
+    const int off = use ? 3 * (base + a + b * sy + cc * sz) * (int)sizeof(T) : kBufOOB;
     T v[3];
     bload3<T>(re, off, v);
 #pragma unroll
@@ -226,7 +230,11 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
       const int ii = i + d.dx, jj = j + d.dy, kk = k + d.dz;
       const bool ok = valid && (unsigned)ii < (unsigned)L.nx && (unsigned)jj < (unsigned)L.ny &&
                       (unsigned)kk < (unsigned)L.nz;
-      const int xo = ok ? (int)((ii + (long)L.nx * (jj + (long)L.ny * kk)) * 3 * sizeof(T)) : kBufOOB;
+      // 32-bit offsets (the host bounds every level vector below 2 GiB),
+      // with 24-bit multiplies: a full 32-bit multiply-add is emitted as a
+      // 64-bit one whose unused upper input half can alias a register with a
+      // load in flight, and the wait for that load then stalls the gathers
+      const int xo = ok ? lat_index(L, ii, jj, kk) * 3 * (int)sizeof(T) : kBufOOB;
       const int co = ok ? vself : kBufOOB;
       T v[3];
       xb.load_node(ii, jj, kk, d.dz, xo, v);
@@ -240,9 +248,9 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
       const int ii = i - d.dx, jj = j - d.dy, kk = k - d.dz;
       const bool ok = valid && b > 0 && (unsigned)ii < (unsigned)L.nx &&
                       (unsigned)jj < (unsigned)L.ny && (unsigned)kk < (unsigned)L.nz;
-      const long nb = ii + (long)L.nx * (jj + (long)L.ny * kk);
-      const int xo = ok ? (int)(nb * 3 * sizeof(T)) : kBufOOB;
-      const int co = ok ? (int)(nb * sizeof(T)) : kBufOOB;
+      const int nb = lat_index(L, ii, jj, kk);
+      const int xo = ok ? nb * 3 * (int)sizeof(T) : kBufOOB;
+      const int co = ok ? nb * (int)sizeof(T) : kBufOOB;
       T v[3];
       xb.load_node(ii, jj, kk, -d.dz, xo, v);
 #pragma unroll
@@ -768,17 +776,16 @@ void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars*
   }
 }
 
-// Stencil operators: the 4 waves of a block share 64 consecutive nodes, wave
-// w summing the stencil blocks b = w (mod 4) (coalesced loads, a quarter of
-// the load chain per lane, 4x the waves of one-thread-per-node); the four
-// partial rows meet in LDS and wave 0 runs the epilogue.
-constexpr int ST_LPN = 4;
-constexpr int ST_NODES = BS / ST_LPN;  // nodes per block
+// Stencil operators: the 7 waves of a block share 64 consecutive nodes, wave
+// w summing the stencil blocks w and w + 7 (coalesced loads, two of the 14
+// blocks per lane, 7x the waves of one-thread-per-node); the partial rows
+// meet in LDS and wave 0 runs the epilogue.
+constexpr int ST_LPN = 7;
+constexpr int ST_NODES = 64;  // nodes per block
+constexpr int ST_THREADS = ST_LPN * ST_NODES;
 
-// Two waves per SIMD (up to 256 registers): at a tighter register target the
-// compiler serialises the last coefficient loads behind one register pair.
 template <typename T, class In, class Ep>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(ST_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
                                                  const CgScalars* gate, int gate_state,
                                                  double* part) {
@@ -823,8 +830,15 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
     ep.put(r, node, ax, pv, a0, a1);
   }
   if constexpr (Ep::RED) {
-    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
-                   part + (size_t)(4 + r) * MAX_BLOCKS + bx);
+    // only wave 0 holds epilogue sums
+    if (wave == 0) {
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      if (lane == 0) {
+        part[(size_t)r * MAX_BLOCKS + bx] = a0;
+        part[(size_t)(4 + r) * MAX_BLOCKS + bx] = a1;
+      }
+    }
   }
 }
 
@@ -856,14 +870,18 @@ static void launch_op_lds(K kernel, dim3 grid, size_t lds, hipStream_t st, Args.
 }
 
 template <typename K, typename... Args>
-static void launch_op(K kernel, dim3 grid, hipStream_t st, Args... args) {
+static void launch_op_b(K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args) {
   if (g_time_start || g_time_stop) {
-    hipExtLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, g_time_start, g_time_stop, 0, args...);
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, g_time_start, g_time_stop, 0, args...);
     g_time_start = g_time_stop = nullptr;
   } else {
-    hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, args...);
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
   }
   MGCG_HIP(hipGetLastError());
+}
+template <typename K, typename... Args>
+static void launch_op(K kernel, dim3 grid, hipStream_t st, Args... args) {
+  launch_op_b(kernel, grid, dim3(BS), st, args...);
 }
 
 template <typename T, class Op, class In, class Ep>
@@ -873,7 +891,8 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
   if constexpr (std::is_same<Op, OpST<T>>::value) {
     const int nb = (int)((nn + ST_NODES - 1) / ST_NODES);
     if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-    launch_op(k_apply_st<T, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state, part);
+    launch_op_b(k_apply_st<T, In, Ep>, dim3(nb, nrhs), dim3(ST_THREADS), st, op, in, ep, nrhs,
+                gate, gate_state, part);
   } else if constexpr (std::is_same<Op, OpEQ2<T>>::value) {
     // two passes: element products, then the node gather with the epilogue
     // (timing events, when set, span both)
@@ -1336,7 +1355,7 @@ struct InLds {
     int n0, nx, ny, P, lr;
     __device__ __forceinline__ void load_node(int ii, int jj, int kk, int dz, int voff,
                                               T v[3]) const {
-      const int nb = ii + nx * (jj + ny * kk);
+      const int nb = ii + __mul24(nx, jj + __mul24(ny, kk));
       const int q = (dz + 1) * lr + (nb - (n0 + dz * P - nx - 1));
       const bool ok = voff != kBufOOB;
 #pragma unroll
@@ -1347,7 +1366,7 @@ struct InLds {
 };
 
 template <typename T>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(ST_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_st_jacobi_prolong(OpST<T> op, const T* __restrict__ x, const T* __restrict__ e, Lat C,
                          const uint8_t* __restrict__ mf, const T* __restrict__ b,
                          const T* __restrict__ wD, T omega, T* xo, int nrhs,
@@ -1367,7 +1386,7 @@ void k_st_jacobi_prolong(OpST<T> op, const T* __restrict__ x, const T* __restric
   const __amdgpu_buffer_rsrc_t rx = make_rsrc(x + (size_t)r * nd, (size_t)nd * sizeof(T)),
                                re = make_rsrc(e + (size_t)r * cnd, (size_t)cnd * sizeof(T)),
                                rm = make_rsrc(mf, (size_t)nn);
-  for (int q = threadIdx.x; q < 3 * lr; q += BS) {
+  for (int q = threadIdx.x; q < 3 * lr; q += ST_THREADS) {
     const int plane = q / lr;
     const int node = n0 + (plane - 1) * P - nx - 1 + (q - plane * lr);
     const bool ok = node >= 0 && node < nn;
@@ -1422,7 +1441,7 @@ void v_jacobi_prolong(const VOps<T>& v, const VOps<T>& vc, const T* b, const T* 
   const size_t lds = (size_t)9 * lr * sizeof(T);
   if (lds > 64 * 1024) throw Error(-1, "level too wide for the fused prolongation");
   hipLaunchKernelGGL(k_st_jacobi_prolong<T>, dim3(apply_blocks(OP_ST27, nn, sizeof(T) == 8), nrhs),
-                     dim3(BS), lds, st, v.st, x, e, vc.L, v.mask, b, v.invD, omega, xo, nrhs, cs);
+                     dim3(ST_THREADS), lds, st, v.st, x, e, vc.L, v.mask, b, v.invD, omega, xo, nrhs, cs);
   MGCG_HIP(hipGetLastError());
 }
 
@@ -1501,7 +1520,7 @@ __device__ __forceinline__ T restrict_at(const Lat& F, __amdgpu_buffer_rsrc_t rb
     const int i = 2 * I + q % 3 - 1, j = 2 * J + (q / 3) % 3 - 1, k = 2 * K + q / 9 - 1;
     const bool ok = (unsigned)i < (unsigned)F.nx && (unsigned)j < (unsigned)F.ny &&
                     (unsigned)k < (unsigned)F.nz;
-    off[q] = ok ? (3 * (i + F.nx * (j + F.ny * k)) + c) * (int)sizeof(T) : kBufOOB;
+    off[q] = ok ? (3 * lat_index(F, i, j, k) + c) * (int)sizeof(T) : kBufOOB;
   }
   T v[27];
 #pragma unroll

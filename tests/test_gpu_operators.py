@@ -16,6 +16,9 @@ CASES = [
     ("torsion", (8, 4, 6), 1, 2, 2, 1),
     ("cantilever", (6, 2, 4), 2, 2, 3, 2),
     ("mbb", (4, 4, 2), 2, 1, 2, 1),
+    # a stencil level above the fused-prolongation size and a coarsest level
+    # above the fused-restriction size: the separate transfer kernels
+    ("torsion", (40, 20, 20), 1, 2, 3, 1),
 ]
 
 

@@ -100,8 +100,8 @@ def fine_apply_model(nel, nsub, order, nrhs=1):
     * trilinear with n^3 densities per element (assembled 27-point stencil,
       symmetric half: 14 blocks of 3x3 per node): bytes: the 126 stencil
       coefficients per node, read p, write q.  Bound: HBM.
-    * triquadratic (stored 81x81 element matrices): bytes: 6561 coefficients
-      per element, read p, write q.  Bound: HBM."""
+    * triquadratic (stored symmetric 81x81 element matrices): bytes: the
+      3321 distinct coefficients per element, read p, write q.  Bound: HBM."""
     nx, ny, nz = nel
     nelem = nx * ny * nz
     nn = (order * nx + 1) * (order * ny + 1) * (order * nz + 1)
@@ -116,10 +116,11 @@ def fine_apply_model(nel, nsub, order, nrhs=1):
                     kernel="finest-level CG apply q = A p, 27-point stencil (FP64)",
                     per_unit="126 x 8 B of coefficients per node + 48 B of vectors per node "
                              "and load case")
-    return dict(bound="hbm", flops=2.0 * 6561 * nelem * nrhs, bytes=vec + 8.0 * 6561 * nelem,
-                kernel="finest-level CG apply q = A p, stored 81x81 element matrices (FP64)",
-                per_unit="6561 x 8 B of element matrix per element + 48 B of vectors per node "
-                         "and load case")
+    return dict(bound="hbm", flops=2.0 * 6561 * nelem * nrhs, bytes=vec + 8.0 * 3321 * nelem,
+                kernel="finest-level CG apply q = A p, stored symmetric 81x81 element matrices "
+                       "(FP64)",
+                per_unit="3321 x 8 B of element matrix (distinct entries) per element + 48 B of "
+                         "vectors per node and load case")
 
 
 def cpu_baseline(cfg, rho_fields, budget_s=25.0):

@@ -329,12 +329,14 @@ __device__ __forceinline__ void ax_any(const OpEQ2Y<T>& op, const In& in, int r,
 }
 
 // First pass: y_e = K_e u_e for every element and load case, one thread per
-// (element, row), three elements per block.  K_e is symmetric, so its stored
-// rows are also its columns: thread `row` reads K_e[col][row] for col =
-// 0..80 and the 81 threads of an element read 81 consecutive values per step
-// (coalesced streaming of the 6561 coefficients, the apply's dominant
-// traffic); each coefficient read serves every load case.  u_e of every load
-// case is staged in LDS and read as a broadcast.
+// (element, row), three elements per block.  K_e is symmetric and stored by
+// wrapped diagonals, D[s][i] = K_e[i][(i + s) mod 81] for s = 0..40 (3321
+// values, every entry once: half the bytes of the full matrix).  Row i is
+// D[0][i], D[s][i] (column i + s) and D[s][i - s] (column i - s, by
+// symmetry), s = 1..40, mod 81: at step s the 81 threads of an element read
+// the 81 consecutive values D[s][*] once from memory (the rotated second
+// read hits the same lines).  Each coefficient read serves every load case;
+// u_e of every load case is staged in LDS.
 constexpr int EQ_EPB = 3;  // elements per block (243 of 256 threads busy)
 template <typename T, int NR, class In>
 __global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
@@ -363,23 +365,47 @@ __global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
   }
   __syncthreads();
   if (!gate_open(g) || !on) return;
-  const T* Kc = op.Ke + (size_t)e * 6561 + row;
+  const T* D = op.Ke + (size_t)e * Q2_PACKED;
   T acc[NR][2];
+  const T d0 = D[row];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r][0] = acc[r][1] = T(0);
-#pragma unroll 9
-  for (int col = 0; col < 80; col += 2) {
-    const T k0 = Kc[(size_t)col * 81], k1 = Kc[(size_t)(col + 1) * 81];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      acc[r][0] = fma(k0, ue[r][le][col], acc[r][0]);
-      acc[r][1] = fma(k1, ue[r][le][col + 1], acc[r][1]);
-    }
+  for (int r = 0; r < NR; ++r) {
+    acc[r][0] = d0 * ue[r][le][row];
+    acc[r][1] = T(0);
   }
-  const T k80 = Kc[(size_t)80 * 81];
+  // 5 batches of 8 diagonals: the 16 coefficient loads of a batch are
+  // issued before its arithmetic
+#pragma unroll 1
+  for (int s0 = 1; s0 <= 40; s0 += 8) {
+    T kp[8], km[8];
+    int jp[8], jm[8];
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
-    op.Y[((size_t)r * nel + e) * 81 + row] = fma(k80, ue[r][le][80], acc[r][0] + acc[r][1]);
+    for (int q = 0; q < 8; ++q) {
+      const int s = s0 + q;
+      jp[q] = row + s;
+      jm[q] = row - s;
+      jp[q] -= jp[q] >= 81 ? 81 : 0;
+      jm[q] += jm[q] < 0 ? 81 : 0;
+      kp[q] = D[s * 81 + row];
+      km[q] = D[s * 81 + jm[q]];
+    }
+    // (pinned: otherwise the compiler interleaves the loads with the
+    // arithmetic and leaves only a few in flight)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      pin(kp[q]);
+      pin(km[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        acc[r][0] = fma(kp[q], ue[r][le][jp[q]], acc[r][0]);
+        acc[r][1] = fma(km[q], ue[r][le][jm[q]], acc[r][1]);
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) op.Y[((size_t)r * nel + e) * 81 + row] = acc[r][0] + acc[r][1];
   (void)by;
 }
 

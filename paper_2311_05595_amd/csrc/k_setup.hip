@@ -102,6 +102,30 @@ void setup_effective(int order, int nsub, int nelx, int nely, int nelz, const do
   MGCG_HIP(hipGetLastError());
 }
 
+// Wrapped-diagonal copy of symmetric Q2 element matrices: D[e][s][i] =
+// K[e][i][(i + s) mod 81], s = 0..40 (one thread per stored value; writes
+// coalesced, reads within the element's matrix).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pack_q2(const double* __restrict__ K, T* D, long nel) {
+  const long t = (long)blockIdx.x * BS + threadIdx.x;
+  if (t >= nel * Q2_PACKED) return;
+  const long e = t / Q2_PACKED;
+  const int q = (int)(t - e * Q2_PACKED), s = q / 81, i = q - 81 * s;
+  int j = i + s;
+  j -= j >= 81 ? 81 : 0;
+  D[t] = (T)K[(size_t)e * 6561 + 81 * i + j];
+}
+
+template <typename T>
+void setup_pack_q2(const double* K, T* D, long nel, hipStream_t st) {
+  const long n = nel * Q2_PACKED;
+  hipLaunchKernelGGL(k_pack_q2<T>, dim3((unsigned)((n + BS - 1) / BS)), dim3(BS), 0, st, K, D,
+                     nel);
+  MGCG_HIP(hipGetLastError());
+}
+template void setup_pack_q2<double>(const double*, double*, long, hipStream_t);
+template void setup_pack_q2<float>(const double*, float*, long, hipStream_t);
+
 // ------------------------------------------------------------ Galerkin
 // One block per coarse element.  Children have nodes at coarse-local lattice
 // positions in {0,1,2}^3; W[a][b] = trilinear weight of coarse vertex b at

@@ -43,8 +43,11 @@ struct OpST {
   const T* coef;
 };
 
-// Stored triquadratic element matrices Ke[e][81*81] (supported rows/columns
-// zeroed), on the quadratic node lattice (nx = 2*nelx + 1, ...).
+// Stored triquadratic element matrices (supported rows/columns zeroed), on
+// the quadratic node lattice (nx = 2*nelx + 1, ...), by wrapped diagonals:
+// Ke[e][s][i] = K_e[i][(i + s) mod 81] for s = 0..40, i = 0..80 (each entry
+// of the symmetric matrix once).
+constexpr int Q2_PACKED = 41 * 81;
 template <typename T>
 struct OpEQ2 {
   Lat L;
@@ -198,6 +201,9 @@ void setup_simp(const double* rho, double* E, float* E32, long n, double E0, dou
                 double penal, int* bad, hipStream_t st);
 // Effective element matrices Keff[e] = sum_s E[dens(e,s)] Ksub[s] (nd x nd),
 // rows/columns of supported DOFs zeroed.
+// Full symmetric 81x81 element matrices K[e] -> wrapped diagonals (OpEQ2).
+template <typename T>
+void setup_pack_q2(const double* K, T* D, long nel, hipStream_t st);
 void setup_effective(int order, int nsub, int nelx, int nely, int nelz, const double* E,
                      const double* Ksub, const uint8_t* mask, Lat L, double* Keff, hipStream_t st);
 // Galerkin coarse element matrices (24x24 Q1-type) of a coarse element grid.

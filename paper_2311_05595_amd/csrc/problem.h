@@ -146,6 +146,7 @@ class Problem {
   double* K0_ = nullptr;     // [576] (MF)
   float* K032_ = nullptr;
   double* Keff_ = nullptr;   // level-0 effective element matrices (ST27: 576, EQ2: 6561)
+  double* Kq2_ = nullptr;    // EQ2: the same by wrapped diagonals (Q2_PACKED per element)
   float* Keff32_ = nullptr;  // EQ2 mixed copy
   double* Yeq_ = nullptr;    // EQ2 element products (FP64 or FP32 view), [nrhs][nel][81]
   double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr, *rold_ = nullptr;

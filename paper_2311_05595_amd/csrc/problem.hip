@@ -126,8 +126,9 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   TAKE(dcbuf_, double, nrho);
   if (lv[0].kind == OP_ST27) TAKE(Keff_, double, nel0 * 576);
   if (lv[0].kind == OP_EQ2) {
-    TAKE(Keff_, double, nel0 * 6561);
-    if (mixed) TAKE(Keff32_, float, nel0 * 6561);
+    TAKE(Keff_, double, nel0 * 6561);           // full matrices (setup)
+    TAKE(Kq2_, double, nel0 * Q2_PACKED);       // wrapped diagonals (applies)
+    if (mixed) TAKE(Keff32_, float, nel0 * Q2_PACKED);
     TAKE(Yeq_, double, R * nel0 * 81);
   }
   for (int l = 0; l < L; ++l) {
@@ -422,7 +423,7 @@ FineOp Problem::fine_op() const {
   const Lat L = lv_[0].L;
   A.mf = OpMF<double>::make(L, E_, kv64_, B_[0].mask);
   A.st = OpST<double>{L, vbytes_ == 8 ? (const double*)B_[0].coefV : B_[0].coef64};
-  A.eq2 = OpEQ2<double>{L, Keff_, B_[0].mask, Yeq_};
+  A.eq2 = OpEQ2<double>{L, Kq2_, B_[0].mask, Yeq_};
   return A;
 }
 
@@ -435,7 +436,7 @@ VOps<T> Problem::vops(int l) const {
   v.invD = (const T*)B_[l].invD;
   if constexpr (sizeof(T) == 8) {
     v.mf = OpMF<T>::make(v.L, E_, kv64_, B_[l].mask);
-    v.eq2 = OpEQ2<T>{v.L, Keff_, B_[l].mask, (T*)Yeq_};
+    v.eq2 = OpEQ2<T>{v.L, Kq2_, B_[l].mask, (T*)Yeq_};
   } else {
     v.mf = OpMF<T>::make(v.L, E32_, kv32_, B_[l].mask);
     v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask, (T*)Yeq_};
@@ -512,7 +513,11 @@ void Problem::do_set_densities() {
     default:
       setup_effective(2, d_.nsub, d_.nelx, d_.nely, d_.nelz, E_, Ksub_, B_[0].mask, L0, Keff_, st);
       setup_diag_eq2<T>(L0, Keff_, B_[0].mask, (T*)B_[0].invD, B_[0].diag64, d_.omega, kTheta, st);
-      if (mixed) convert<double, float>(Keff_, Keff32_, (long)d_.nelx * d_.nely * d_.nelz * 6561, st);
+      {
+        const long nel0 = (long)d_.nelx * d_.nely * d_.nelz;
+        setup_pack_q2<double>(Keff_, Kq2_, nel0, st);
+        if (mixed) setup_pack_q2<float>(Keff_, Keff32_, nel0, st);
+      }
       break;
   }
   for (int l = 1; l < L; ++l) {

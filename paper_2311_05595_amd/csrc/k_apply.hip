@@ -342,6 +342,8 @@ template <typename T, int NR, class In>
 __global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
                                                   const CgScalars* gate, int gate_state) {
   const Gate g = gate_load(gate, nrhs, gate_state);
+  // the true-residual check's gate is usually closed: test it first there
+  if (gate_state == CG_CHECK && !gate_open(g)) return;
   __shared__ T ue[NR][EQ_EPB][81];
   int bx, by;
   xcd_tile(bx, by);
@@ -373,36 +375,39 @@ __global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
     acc[r][0] = d0 * ue[r][le][row];
     acc[r][1] = T(0);
   }
-  // 5 batches of 8 diagonals: the 16 coefficient loads of a batch are
-  // issued before its arithmetic
-#pragma unroll 1
-  for (int s0 = 1; s0 <= 40; s0 += 8) {
-    T kp[8], km[8];
-    int jp[8], jm[8];
+  // 5 batches of 8 diagonals, double-buffered: the 16 coefficient loads of
+  // batch b + 1 are issued before the arithmetic of batch b
+  T kb[2][16];
+  auto issue = [&](int b, T (&k)[16]) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int s = s0 + q;
-      jp[q] = row + s;
-      jm[q] = row - s;
-      jp[q] -= jp[q] >= 81 ? 81 : 0;
-      jm[q] += jm[q] < 0 ? 81 : 0;
-      kp[q] = D[s * 81 + row];
-      km[q] = D[s * 81 + jm[q]];
+      const int sd = 1 + 8 * b + q;
+      int jm = row - sd;
+      jm += jm < 0 ? 81 : 0;
+      k[2 * q] = D[sd * 81 + row];
+      k[2 * q + 1] = D[sd * 81 + jm];
     }
-    // (pinned: otherwise the compiler interleaves the loads with the
-    // arithmetic and leaves only a few in flight)
+  };
+  issue(0, kb[0]);
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    if (b + 1 < 5) issue(b + 1, kb[(b + 1) & 1]);
+    // (pinned: the wait covers this batch only, and the compiler does not
+    // interleave the loads with the arithmetic)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pin(kb[b & 1][q]);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      pin(kp[q]);
-      pin(km[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
+      const int sd = 1 + 8 * b + q;
+      int jp = row + sd, jm = row - sd;
+      jp -= jp >= 81 ? 81 : 0;
+      jm += jm < 0 ? 81 : 0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        acc[r][0] = fma(kp[q], ue[r][le][jp[q]], acc[r][0]);
-        acc[r][1] = fma(km[q], ue[r][le][jm[q]], acc[r][1]);
+        acc[r][0] = fma(kb[b & 1][2 * q], ue[r][le][jp], acc[r][0]);
+        acc[r][1] = fma(kb[b & 1][2 * q + 1], ue[r][le][jm], acc[r][1]);
       }
+    }
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) op.Y[((size_t)r * nel + e) * 81 + row] = acc[r][0] + acc[r][1];

@@ -156,7 +156,7 @@ template <typename T>
 void v_jacobi_prolong(const VOps<T>& v, const VOps<T>& vc, const T* b, const T* x, T* xo,
                       T omega, const T* e, int nrhs, const CgScalars* cs, hipStream_t st);
 // Levels at most this many nodes take the fused sweep above.
-constexpr long PROLONG_FUSE_MAX_NODES = 16384;
+constexpr long PROLONG_FUSE_MAX_NODES = 65536;
 // r = b - A x
 template <typename T>
 void v_residual(const VOps<T>& v, const T* b, const T* x, T* r, int nrhs, const CgScalars* cs,

@@ -18,7 +18,7 @@ CASES = [
     ("mbb", (4, 4, 2), 2, 1, 2, 1),
     # a stencil level above the fused-prolongation size and a coarsest level
     # above the fused-restriction size: the separate transfer kernels
-    ("torsion", (40, 20, 20), 1, 2, 3, 1),
+    ("torsion", (64, 32, 32), 1, 2, 3, 1),
 ]
 
 

@@ -807,19 +807,32 @@ void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars*
   }
 }
 
-// Stencil operators: the 7 waves of a block share 64 consecutive nodes, wave
-// w summing the stencil blocks w and w + 7 (coalesced loads, two of the 14
-// blocks per lane, 7x the waves of one-thread-per-node); the partial rows
-// meet in LDS and wave 0 runs the epilogue.
-constexpr int ST_LPN = 7;
+// Stencil operators: the LPN waves of a block share 64 consecutive nodes,
+// wave w summing the stencil blocks w, w + LPN, ... (coalesced loads, part of
+// the load chain per lane, LPN x the waves of one-thread-per-node); the
+// partial rows meet in LDS and wave 0 runs the epilogue.  Two shapes:
+// 7 waves (two blocks each, 4 waves per SIMD) and 4 waves (3-4 blocks each,
+// 2 waves per SIMD with up to 256 registers).  Measured: 7 waves win on
+// FP32 levels and on small FP64 levels (+2 % on the 96x48x48 cantilever,
+// latency-bound), 4 waves on large FP64 levels (+5 % on the 64x32x32 n = 4
+// cantilever in FP64, +8 % on the FP64 served mix).
 constexpr int ST_NODES = 64;  // nodes per block
-constexpr int ST_THREADS = ST_LPN * ST_NODES;
+constexpr long ST_BIG_FP64_NODES = 65536;
+template <int LPN>
+struct StShape {
+  static constexpr int threads = LPN * ST_NODES;
+  static constexpr int waves_per_eu = LPN == 7 ? 4 : 2;
+};
+template <typename T>
+inline int st_lpn(long nn) { return (sizeof(T) == 8 && nn > ST_BIG_FP64_NODES) ? 4 : 7; }
 
-template <typename T, class In, class Ep>
-__global__ __launch_bounds__(ST_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4)))
+template <typename T, class In, class Ep, int LPN>
+__global__ __launch_bounds__(StShape<LPN>::threads)
+__attribute__((amdgpu_waves_per_eu(StShape<LPN>::waves_per_eu, StShape<LPN>::waves_per_eu)))
 void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
                                                  const CgScalars* gate, int gate_state,
                                                  double* part) {
+  constexpr int ST_LPN = LPN;
   __shared__ T red[ST_LPN - 1][3][ST_NODES];
   // the wave index must be provably uniform: it selects the coefficient
   // rows through the scalar offset of every buffer load (a divergent value
@@ -837,11 +850,12 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
   double a0 = 0.0, a1 = 0.0;
   const bool on = node < op.L.nn();
   T ax[3] = {T(0), T(0), T(0)};
-  // epilogue operands (used by wave 0), loaded without a branch: a value
-  // merged from a conditional load would have to arrive before the gathers
-  // start
+  // epilogue operands, loaded by wave 0 only (which runs the epilogue) under
+  // a wave-uniform branch, before its gathers; for the other six waves they
+  // would be redundant loads
   const long nn = op.L.nn();
-  const typename Ep::Pre pv = ep.pre(r, node < nn ? node : nn - 1);
+  typename Ep::Pre pv{};
+  if (wave == 0) pv = ep.pre(r, node < nn ? node : nn - 1);
   if (on) {
     int i, j, k;
     node_ijk(node, op.L, i, j, k);
@@ -922,8 +936,12 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
   if constexpr (std::is_same<Op, OpST<T>>::value) {
     const int nb = (int)((nn + ST_NODES - 1) / ST_NODES);
     if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-    launch_op_b(k_apply_st<T, In, Ep>, dim3(nb, nrhs), dim3(ST_THREADS), st, op, in, ep, nrhs,
-                gate, gate_state, part);
+    if (st_lpn<T>(nn) == 7)
+      launch_op_b(k_apply_st<T, In, Ep, 7>, dim3(nb, nrhs), dim3(StShape<7>::threads), st, op, in,
+                  ep, nrhs, gate, gate_state, part);
+    else
+      launch_op_b(k_apply_st<T, In, Ep, 4>, dim3(nb, nrhs), dim3(StShape<4>::threads), st, op, in,
+                  ep, nrhs, gate, gate_state, part);
   } else if constexpr (std::is_same<Op, OpEQ2<T>>::value) {
     // two passes: element products, then the node gather with the epilogue
     // (timing events, when set, span both)
@@ -1397,11 +1415,12 @@ struct InLds {
 };
 
 template <typename T>
-__global__ __launch_bounds__(ST_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ __launch_bounds__(StShape<7>::threads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_st_jacobi_prolong(OpST<T> op, const T* __restrict__ x, const T* __restrict__ e, Lat C,
                          const uint8_t* __restrict__ mf, const T* __restrict__ b,
                          const T* __restrict__ wD, T omega, T* xo, int nrhs,
                          const CgScalars* gate) {
+  constexpr int ST_LPN = 7, ST_THREADS = StShape<7>::threads;  // small levels
   extern __shared__ __align__(16) unsigned char sh_raw[];
   T* sh = reinterpret_cast<T*>(sh_raw);
   __shared__ T red[ST_LPN - 1][3][ST_NODES];
@@ -1433,8 +1452,12 @@ void k_st_jacobi_prolong(OpST<T> op, const T* __restrict__ x, const T* __restric
   const int node = n0 + lane;
   const bool on = node < nn;
   const int nodec = on ? node : nn - 1;
-  // epilogue operands (wave 0)
-  const Pre3<T> bv = ld3(b + (size_t)r * nd + 3 * nodec), dv = ld3(wD + 3 * nodec);
+  // epilogue operands (wave 0 only: uniform branch)
+  Pre3<T> bv{}, dv{};
+  if (wave == 0) {
+    bv = ld3(b + (size_t)r * nd + 3 * nodec);
+    dv = ld3(wD + 3 * nodec);
+  }
   __syncthreads();
   T ax[3] = {T(0), T(0), T(0)};
   if (on) {
@@ -1472,7 +1495,8 @@ void v_jacobi_prolong(const VOps<T>& v, const VOps<T>& vc, const T* b, const T* 
   const size_t lds = (size_t)9 * lr * sizeof(T);
   if (lds > 64 * 1024) throw Error(-1, "level too wide for the fused prolongation");
   hipLaunchKernelGGL(k_st_jacobi_prolong<T>, dim3(apply_blocks(OP_ST27, nn, sizeof(T) == 8), nrhs),
-                     dim3(ST_THREADS), lds, st, v.st, x, e, vc.L, v.mask, b, v.invD, omega, xo, nrhs, cs);
+                     dim3(StShape<7>::threads), lds, st, v.st, x, e, vc.L, v.mask, b, v.invD, omega,
+                     xo, nrhs, cs);
   MGCG_HIP(hipGetLastError());
 }
 

@@ -22,7 +22,11 @@ What it computes (the plain definitions, in FP64):
                weighted-Jacobi sweep and Algorithm 1 applied recursively
                (the preconditioner M as a plain linear operator), plus the
                paper's preconditioned CG used as a reference solver where a
-               direct factorisation is too large.
+               direct factorisation is too large;
+* ``projection`` the weighted-average projection of design variables onto
+               densities (Sec. 3.2 eq. (5), weights of Sec. 2.2 eq. (4); the
+               density filter when both lattices coincide) and its transpose,
+               the chain rule of Sec. 3.4.
 
 Parity status of every function is listed in its module docstring.
 """

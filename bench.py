@@ -11,6 +11,12 @@ Prints one JSON line (see the fields below).  `--config c3|c4` times the
 other single-GPU workloads the same way (not the default line).
 `--copy-probe MIB` only runs the library's plain copy kernel on MIB MiB
 (the calibration run for the HBM byte counters) and exits.
+
+`--projection` times the design-variable projection rho = W x and its
+transpose W^T g (Sec. 3.2 eq. (5), Sec. 3.4) on the 64x32x32 mesh with 4^3
+density and 2^3 design cells per element, rmin = 1.5, and prints its own
+JSON line (kernel rooflines and the oracle's single-entry evaluation timed
+on a sample).
 """
 
 import argparse
@@ -392,6 +398,124 @@ def run_served(args):
     print(json.dumps(out), flush=True)
 
 
+PROJ_WORKLOAD = dict(nel=(64, 32, 32), nsub=4, ndes=2, rmin=1.5)
+
+
+def proj_nnz(nel, n, d, rmin):
+    """Nonzeros of W (pairs of density and design cells within rmin), counted
+    per axis: the squared centre offsets m^2 (in units of 1/(2nd)^2) of every
+    axis pair, then the triples with m_x^2 + m_y^2 + m_z^2 <= (2 n d rmin)^2."""
+    R2 = (2.0 * n * d * rmin) ** 2
+
+    def axis(ne):
+        i = np.arange(ne * n)[:, None]
+        j = np.arange(ne * d)[None, :]
+        m2 = (((2 * i + 1) * d - (2 * j + 1) * n) ** 2).astype(np.float64)
+        return m2[m2 <= R2]
+    mz, my, mx = axis(nel[2]), axis(nel[1]), np.sort(axis(nel[0]))
+    uz, cz = np.unique(mz, return_counts=True)
+    uy, cy = np.unique(my, return_counts=True)
+    total = 0
+    for a, ca in zip(uz, cz):
+        for b, cb in zip(uy, cy):
+            if a + b <= R2:
+                total += int(ca) * int(cb) * int(np.searchsorted(mx, R2 - a - b, side="right"))
+    return total
+
+
+def run_projection(args):
+    import torch
+    from paper_2311_05595_amd import api
+
+    wl = PROJ_WORKLOAD
+    nel, n, d, rmin = wl["nel"], wl["nsub"], wl["ndes"], wl["rmin"]
+    dev = torch.device("cuda:0")
+    pr = api.Projection(nel, n, d, rmin)
+    gen = torch.Generator(device=dev).manual_seed(17)
+    x = torch.rand(pr.nx, dtype=torch.float64, device=dev, generator=gen)
+    g = torch.randn(pr.nrho, dtype=torch.float64, device=dev, generator=gen)
+    rho = torch.empty(pr.nrho, dtype=torch.float64, device=dev)
+    gx = torch.empty(pr.nx, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        pr.apply(x, out=rho)
+        pr.apply_transpose(g, out=gx)
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_f = timed(lambda: pr.apply(x, out=rho), args.steps)
+    t_t = timed(lambda: pr.apply_transpose(g, out=gx), args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pr.apply(x, out=rho)
+        pr.apply_transpose(g, out=gx)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nnz = proj_nnz(nel, n, d, rmin)
+    flops = 2.0 * nnz                       # one multiply-add per nonzero of W
+    bytes_f = 8.0 * (pr.nx + 2 * pr.nrho)   # x read, 1/omega read, rho written
+    bytes_t = 8.0 * (2 * pr.nrho + pr.nx)   # g and 1/omega read, W^T g written
+
+    def roof(t, nbytes):
+        alu = flops / (PEAK_FP64_TFLOPS * 1e12) >= nbytes / (PEAK_HBM_GBS * 1e9)
+        if alu:
+            a, p, u = flops / t / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+        else:
+            a, p, u = nbytes / t / 1e9, PEAK_HBM_GBS, "GB/s"
+        return {"bound": "alu" if alu else "hbm", "achieved": round(a, 3), "peak": p, "unit": u,
+                "frac": round(a / p, 4), "traffic": None, "avg_us": round(t * 1e6, 2),
+                "alg_flop_per_launch": flops, "alg_bytes_per_launch": nbytes,
+                "alg_GBs": round(nbytes / t / 1e9, 1)}
+    out = {
+        "metric": "design-variable projections/s (rho = W x and W^T g, one pair per step)",
+        "value": round(args.steps / elapsed, 2), "unit": "projections/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"projection {nel[0]}x{nel[1]}x{nel[2]} elements, n={n} density "
+                               f"and d={d} design cells per element, rmin={rmin}",
+                   "n_rho": pr.nrho, "n_x": pr.nx, "nnz_W": nnz},
+        "roofline": roof(t_f, bytes_f),
+        "roofline_transpose": roof(t_t, bytes_t),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = proj_cpu_baseline(x.cpu().numpy(), pr, budget_s=args.cpu_budget)
+    pr.close()
+    print(json.dumps(out), flush=True)
+
+
+def proj_cpu_baseline(x, pr, budget_s=10.0):
+    """The oracle's plain single-entry projection timed on a bounded sample of
+    density cells, scaled to one full projection (forward only)."""
+    from oracle import projection as P
+    wl = PROJ_WORKLOAD
+    nel, n, d, rmin = wl["nel"], wl["nsub"], wl["ndes"], wl["rmin"]
+    Sr = P.lattice_shape(nel, n)
+    rng = np.random.default_rng(3)
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < budget_s and done < 20000:
+        flat = int(rng.integers(pr.nrho))
+        P.project_at(x, (flat % Sr[2], (flat // Sr[2]) % Sr[1], flat // (Sr[2] * Sr[1])),
+                     nel, n, d, rmin)
+        done += 1
+    dt = time.perf_counter() - t0
+    per_proj = dt / done * pr.nrho
+    return {"value": round(1.0 / per_proj, 8), "unit": "projections/s (forward)", "cores": 1,
+            "kind": "oracle",
+            "sample": f"oracle single-entry evaluation of rho_i for {done} random density cells "
+                      f"in {dt:.1f} s on 1 host thread, scaled to all {pr.nrho} cells"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +528,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
+    ap.add_argument("--projection", action="store_true",
+                    help="time the design-variable projection and its transpose")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
     ap.add_argument("--session-solves", type=int, default=5, help="c5: solves per session")
     ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second")
@@ -412,6 +538,12 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.projection:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        run_projection(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

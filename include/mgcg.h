@@ -209,6 +209,58 @@ size_t mgcg_server_resident_bytes(mgcg_server* s);
 int mgcg_admission_plan(size_t budget, size_t in_use, int free_slots, const size_t* queue_bytes,
                         int nqueue, uint8_t* admit);
 
+/* ---- Projection of design variables onto densities, and the density filter ----
+ *
+ * The operation (Sec. 3.2 eq. (5), with the weights of Sec. 2.2 eq. (4)):
+ * design variables x live on a lattice of d x d x d cells per displacement
+ * element, densities rho on n x n x n cells per element (the same unit
+ * elements, so the density cells have edge 1/n and the design cells 1/d);
+ *     rho_i = sum_j (omega_ij / omega_i) x_j,   omega_i = sum_j omega_ij,
+ *     omega_ij = exp(-dist(i,j)^2 / (2 (rmin/3)^2)) / (2 pi rmin/3)
+ * for dist(i,j) <= rmin (distance between the cells' centres, in element
+ * edges), 0 otherwise; the sums run over the design cells of the domain.
+ * With d = n the operation is the weighted-average density filter of Sec. 2.2.
+ * The transpose gives the chain rule of Sec. 3.4: with g = d f / d rho,
+ * (W^T g)_k = sum_i g_i omega_ik / omega_i = d f / d x_k; with g_i = the
+ * density cells' volumes, W^T g is the volume constraint's gradient.
+ * The test dist <= rmin is exact: along an axis the centres of density cell
+ * i and design cell j lie m / (2 n d) apart with the integer
+ * m = (2i + 1) d - (2j + 1) n, and a pair is inside when
+ * m_x^2 + m_y^2 + m_z^2 <= (2 n d rmin)^2, the right side in FP64.
+ *
+ * Layout: x is the C-order array (d*nelz, d*nely, d*nelx), rho the array
+ * (n*nelz, n*nely, n*nelx), both FP64, x fastest.  A projection object holds
+ * 1/omega_i for every density cell on its device (mgcg_proj_device_bytes);
+ * host-memory calls stage their vectors through temporary device buffers and
+ * return when the result is on the host; device-memory calls are ordered on
+ * the object's stream (the null stream unless set, i.e. torch's default
+ * stream) and return at once.  Errors: MGCG_EINVAL for a
+ * non-positive size, nsub or ndes outside 1..64, rmin not positive and
+ * finite or so large that 2 n d rmin exceeds 4096, a lattice above 2^31 - 1
+ * cells or 2^20 cells along an axis, or a radius that leaves some density cell without a design cell
+ * inside its ball; MGCG_ENOMEM / MGCG_EDEVICE as elsewhere. */
+typedef struct mgcg_proj mgcg_proj;
+typedef struct mgcg_proj_desc {
+  int32_t nelx, nely, nelz; /* displacement elements per axis */
+  int32_t nsub;             /* n: density cells per element and axis */
+  int32_t ndes;             /* d: design cells per element and axis */
+  int32_t pad;
+  double rmin;              /* ball radius, in element edges */
+} mgcg_proj_desc;
+
+/* Device bytes a projection object holds (0 on an invalid desc). */
+size_t mgcg_proj_device_bytes(const mgcg_proj_desc* desc);
+/* Validate desc, allocate on `device` and compute 1/omega_i (blocking). */
+int mgcg_proj_create(const mgcg_proj_desc* desc, int device, mgcg_proj** out);
+int mgcg_proj_destroy(mgcg_proj* pr);
+/* Run later calls on `stream` (a hipStream_t; NULL = the null stream, the
+ * default).  Waits for the work already queued on the previous stream. */
+int mgcg_proj_set_stream(mgcg_proj* pr, void* stream);
+/* rho[n_rho] = W x[n_x] (eq. (5)). */
+int mgcg_proj_apply(mgcg_proj* pr, const double* x, double* rho, int mem);
+/* gx[n_x] = W^T g[n_rho] (the chain rule of Sec. 3.4). */
+int mgcg_proj_apply_transpose(mgcg_proj* pr, const double* g, double* gx, int mem);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,6 +43,12 @@ class mgcg_info(C.Structure):
                 ("t_solve_ms", C.c_double)]
 
 
+class mgcg_proj_desc(C.Structure):
+    _fields_ = [("nelx", C.c_int32), ("nely", C.c_int32), ("nelz", C.c_int32),
+                ("nsub", C.c_int32), ("ndes", C.c_int32), ("pad", C.c_int32),
+                ("rmin", C.c_double)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "mgcg_last_error": (C.c_char_p, []),
@@ -81,6 +87,12 @@ EXPORTS = {
     "mgcg_server_resident_bytes": (C.c_size_t, [C.c_void_p]),
     "mgcg_admission_plan": (C.c_int, [C.c_size_t, C.c_size_t, C.c_int, C.c_void_p, C.c_int,
                                       C.c_void_p]),
+    "mgcg_proj_device_bytes": (C.c_size_t, [C.POINTER(mgcg_proj_desc)]),
+    "mgcg_proj_create": (C.c_int, [C.POINTER(mgcg_proj_desc), C.c_int, C.POINTER(C.c_void_p)]),
+    "mgcg_proj_destroy": (C.c_int, [C.c_void_p]),
+    "mgcg_proj_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mgcg_proj_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "mgcg_proj_apply_transpose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 }
 
 _lib = None

@@ -40,6 +40,14 @@ def _ptr(a, dtype=np.float64):
     return C.c_void_p(arr.ctypes.data), MGCG_MEM_HOST, arr
 
 
+def _inputs_ready(mem):
+    """A problem runs on its own stream unless given a non-default torch
+    stream, and that stream does not wait for torch's default (null) stream:
+    finish the torch work that produced a device input before handing it over."""
+    if mem == MGCG_MEM_DEVICE:
+        _torch().cuda.current_stream().synchronize()
+
+
 def _info(i):
     return dict(status=i.status, iters=list(i.iters), rel_res=list(i.rel_res),
                 replacements=i.replacements, t_setup_ms=i.t_setup_ms, t_solve_ms=i.t_solve_ms)
@@ -113,6 +121,7 @@ class Problem:
 
     def set_densities(self, rho):
         p, mem, keep = _ptr(rho)
+        _inputs_ready(mem)
         if (keep.numel() if mem == MGCG_MEM_DEVICE else keep.size) != self.nrho:
             raise ValueError("density count does not match the mesh")
         check(self._lib.mgcg_set_densities(self._h, p, mem))
@@ -133,6 +142,7 @@ class Problem:
 
     def set_initial_guess(self, u):
         p, mem, _k = _ptr(u)
+        _inputs_ready(mem)
         check(self._lib.mgcg_set_initial_guess(self._h, p, mem))
 
     def compliance_sensitivity(self, dc_out=None, want_dc=True):
@@ -279,4 +289,72 @@ class Server:
         return self._lib.mgcg_server_resident_bytes(self._h)
 
 
-__all__ = ["Problem", "Server", "admission_plan", "device_bytes", "make_desc", "_abi"]
+def make_proj_desc(nel, nsub, ndes, rmin):
+    return _abi.mgcg_proj_desc(int(nel[0]), int(nel[1]), int(nel[2]), int(nsub), int(ndes), 0,
+                               float(rmin))
+
+
+def proj_device_bytes(nel, nsub, ndes, rmin):
+    return load().mgcg_proj_device_bytes(C.byref(make_proj_desc(nel, nsub, ndes, rmin)))
+
+
+class Projection:
+    """Design variables -> densities, rho = W x, and the chain rule g_x = W^T g
+    (mgcg_proj_* in include/mgcg.h).  Vectors: numpy arrays (host) or
+    contiguous float64 device tensors (run on the current torch stream)."""
+
+    def __init__(self, nel, nsub, ndes, rmin, device=0):
+        lib = load()
+        self.nel, self.nsub, self.ndes, self.rmin = tuple(nel), int(nsub), int(ndes), float(rmin)
+        self.desc = make_proj_desc(nel, nsub, ndes, rmin)
+        h = C.c_void_p()
+        check(lib.mgcg_proj_create(C.byref(self.desc), int(device), C.byref(h)))
+        self._h, self._lib = h, lib
+        self.nrho = int(np.prod(nel)) * self.nsub ** 3
+        self.nx = int(np.prod(nel)) * self.ndes ** 3
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mgcg_proj_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        check(self._lib.mgcg_proj_set_stream(self._h, C.c_void_p(stream or 0)))
+
+    def _run(self, fn, v, nin, nout, out):
+        p, mem, keep = _ptr(v)
+        if (keep.numel() if mem == MGCG_MEM_DEVICE else keep.size) != nin:
+            raise ValueError("vector length does not match the lattice")
+        if mem == MGCG_MEM_DEVICE:
+            torch = _torch()
+            # torch's current stream, the default (null) stream included
+            cur = torch.cuda.current_stream().cuda_stream
+            if cur != getattr(self, "_stream", 0):
+                self.set_stream(cur)
+                self._stream = cur
+            if out is None:
+                out = torch.empty(nout, dtype=torch.float64, device=keep.device)
+            q, _, _ = _ptr(out)
+        else:
+            out = np.empty(nout) if out is None else out
+            q = C.c_void_p(out.ctypes.data)
+        check(fn(self._h, p, q, mem))
+        return out
+
+    def apply(self, x, out=None):
+        return self._run(self._lib.mgcg_proj_apply, x, self.nx, self.nrho, out)
+
+    def apply_transpose(self, g, out=None):
+        return self._run(self._lib.mgcg_proj_apply_transpose, g, self.nrho, self.nx, out)
+
+
+__all__ = ["Problem", "Server", "Projection", "admission_plan", "device_bytes", "make_desc",
+           "make_proj_desc", "proj_device_bytes", "_abi"]

@@ -35,3 +35,28 @@ class Compliance(torch.autograd.Function):
 
 def compliance(rho, problem, rtol=1e-10, maxit=2000, warm_start=True):
     return Compliance.apply(rho, problem, rtol, maxit, warm_start)
+
+
+class Project(torch.autograd.Function):
+    """rho = W x (Sec. 3.2 eq. (5)) on the device; backward: W^T g, the chain
+    rule of Sec. 3.4, by the library's transpose kernel."""
+
+    @staticmethod
+    def forward(ctx, x, proj):
+        if not x.is_cuda:
+            raise TypeError("x must live on the GPU")
+        ctx.proj = proj
+        ctx.shape = x.shape
+        ctx.dtype = x.dtype
+        xv = x.detach().to(torch.float64).contiguous().view(-1)
+        return proj.apply(xv)
+
+    @staticmethod
+    def backward(ctx, g):
+        gx = ctx.proj.apply_transpose(g.detach().to(torch.float64).contiguous().view(-1))
+        return gx.view(ctx.shape).to(ctx.dtype), None
+
+
+def project(x, proj):
+    return Project.apply(x, proj)
+

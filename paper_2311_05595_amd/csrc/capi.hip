@@ -259,3 +259,80 @@ int mgcg_admission_plan(size_t budget, size_t in_use, int free_slots, const size
 namespace mgcg {
 Problem* problem_impl(mgcg_problem* p) { return p ? p->impl : nullptr; }
 }  // namespace mgcg
+
+// ---- projection / density filter
+#include "proj.h"
+
+struct mgcg_proj {
+  mgcg::Proj* impl;
+};
+
+extern "C" {
+
+size_t mgcg_proj_device_bytes(const mgcg_proj_desc* d) {
+  if (!d) return 0;
+  try {
+    return mgcg::Proj::device_bytes(*d);
+  } catch (...) {
+    return 0;
+  }
+}
+
+int mgcg_proj_create(const mgcg_proj_desc* d, int device, mgcg_proj** out) {
+  NEED(d);
+  NEED(out);
+  GUARD({
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    if (device < 0 || (ndev > 0 && device >= ndev)) throw Error(MGCG_EINVAL, "bad device index");
+    (void)mgcg::Proj::geometry(*d);
+    auto* p = new mgcg_proj{nullptr};
+    try {
+      p->impl = new mgcg::Proj(*d, device);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_proj_destroy(mgcg_proj* pr) {
+  NEED(pr);
+  GUARD({
+    delete pr->impl;
+    delete pr;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_proj_set_stream(mgcg_proj* pr, void* stream) {
+  NEED(pr);
+  GUARD({
+    pr->impl->set_stream((hipStream_t)stream);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_proj_apply(mgcg_proj* pr, const double* x, double* rho, int mem) {
+  NEED(pr);
+  NEED(x);
+  NEED(rho);
+  GUARD({
+    pr->impl->run(false, x, rho, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_proj_apply_transpose(mgcg_proj* pr, const double* g, double* gx, int mem) {
+  NEED(pr);
+  NEED(g);
+  NEED(gx);
+  GUARD({
+    pr->impl->run(true, g, gx, mem);
+    return MGCG_OK;
+  })
+}
+
+}  // extern "C"

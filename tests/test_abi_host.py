@@ -100,3 +100,22 @@ def test_admission_plan_respects_budget_and_order():
         need = adm[q > 0]
         k = int(need.sum())
         assert need[:k].all() and not need[k:].any()
+
+
+def test_projection_desc_validation():
+    """Projection sizes and the host-side checks (no device needed)."""
+    from paper_2311_05595_amd import api
+    _lib()
+    b = api.proj_device_bytes((64, 32, 32), 4, 2, 1.5)
+    # 1/omega per density cell plus the weight-factor table (2 n d rmin + 2 entries)
+    assert b == (64 * 32 * 32 * 64 + 26) * 8
+    assert api.proj_device_bytes((2, 2, 2), 1, 1, 0.5) > 0
+    # rejected: empty balls (nearest design centre 0.125 sqrt(3) away), bad sizes
+    assert api.proj_device_bytes((1, 1, 1), 4, 2, 0.2) == 0
+    assert api.proj_device_bytes((1, 1, 1), 4, 2, 0.2166) > 0
+    assert api.proj_device_bytes((0, 1, 1), 1, 1, 1.0) == 0
+    assert api.proj_device_bytes((1, 1, 1), 65, 1, 1.0) == 0
+    assert api.proj_device_bytes((1, 1, 1), 1, 1, -1.0) == 0
+    assert api.proj_device_bytes((1, 1, 1), 1, 1, float("nan")) == 0
+    assert api.proj_device_bytes((1, 1, 1), 64, 64, 1.0) == 0  # 2 n d rmin > 4096
+    assert api.proj_device_bytes((1 << 19, 1, 1), 4, 1, 1.0) == 0  # axis above 2^20 cells

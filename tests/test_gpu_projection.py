@@ -2,6 +2,10 @@
 eq. (5) with the weights of Sec. 2.2 eq. (4)) and its transpose (the chain
 rule of Sec. 3.4) against the oracle, through the C ABI.
 
+Two kernel paths are covered: tiled gathers over precomputed phase stencils
+(n a multiple of d, stencils within 4 design cells) and plain per-cell
+searches (the other cases: d not dividing n, very large radii).
+
 Tolerances: every output is a sum of at most a few thousand positive-weight
 FP64 products, evaluated in a different order (and with the weight as a
 product of three per-axis factors instead of one exponential), so outputs
@@ -28,6 +32,8 @@ CASES = [
     ((3, 1, 1), 1, 1, 1.0),      # neighbours exactly on the ball's boundary
     ((1, 1, 1), 4, 2, 0.25),     # one element
     ((3, 2, 2), 2, 1, 10.0),     # every ball holds the whole domain
+    ((9, 5, 3), 4, 2, 1.5),      # several tiles with ragged edges, the benchmark's stencil
+    ((17, 9, 5), 2, 2, 1.0),
 ]
 
 

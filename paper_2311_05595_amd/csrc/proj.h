@@ -8,10 +8,14 @@ namespace mgcg {
 
 #include <vector>
 
-// One stencil entry of a phase: the weight and the LDS offset of the design
-// cell j + o relative to j in the staged tile.
-struct ProjEntry {
-  double w;
+// One entry of a gather table of the tiled kernels: the LDS offset of a
+// stencil offset in the staged tile and the weights of the G outputs a
+// thread accumulates from it (zero where an output's stencil misses it).
+// 16-byte aligned, so that the kernels load an entry as whole 16-byte words
+// and a batch of entries as one run of wide scalar loads.
+template <int G>
+struct alignas(16) ProjEntryG {
+  double w[G];
   int rel;
   int pad;
 };
@@ -26,10 +30,19 @@ struct ProjGeom {
   long nrho, nxv;    // cells of each lattice
   std::vector<double> tab;  // e(|m|) = exp(-9 m^2 / (8 n^2 d^2 rmin^2))
   // tiled kernels (q > 0 when d divides n and the stencils reach at most 4
-  // design cells): q^3 phase stencils, phase-major, and the halo h
-  int q = 0, np = 0, h = 0;
-  std::vector<ProjEntry> ent;
-  std::vector<int> start;
+  // design cells): halo h, forward tables per group of gf phases (gf = 4 when
+  // the q^3 phases split into fours, else 1), transpose tables per phase
+  // (the mirrored stencils)
+  int q = 0, np = 0, h = 0, gf = 0;
+  std::vector<ProjEntryG<1>> fwd1;
+  std::vector<ProjEntryG<4>> fwd4;
+  std::vector<ProjEntryG<1>> trg;
+  std::vector<int> start_f, start_t;
+  size_t table_bytes() const {
+    return fwd1.size() * sizeof(ProjEntryG<1>) + fwd4.size() * sizeof(ProjEntryG<4>) +
+           trg.size() * sizeof(ProjEntryG<1>) +
+           (start_f.size() + start_t.size()) * sizeof(int);
+  }
 };
 
 class Proj {
@@ -52,8 +65,10 @@ class Proj {
   hipStream_t stream_ = nullptr;  // the null stream unless set
   double* invw_ = nullptr;  // 1 / omega_i per density cell
   double* tab_ = nullptr;   // e(|m|)
-  ProjEntry* ent_ = nullptr;
-  int* start_ = nullptr;
+  void* fwd_ent_ = nullptr;  // forward table (ProjEntryG<gf>)
+  void* tr_ent_ = nullptr;   // transpose table (ProjEntryG<4>)
+  int* start_f_ = nullptr;
+  int* start_t_ = nullptr;
 };
 
 }  // namespace mgcg

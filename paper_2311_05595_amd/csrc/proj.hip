@@ -13,7 +13,10 @@
 // omega_ij / omega_i and is left out.
 #include <algorithm>
 #include <cmath>
+#include <array>
 #include <cstdlib>
+#include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -133,21 +136,36 @@ __global__ __launch_bounds__(PROJ_BS) void k_proj_t(ProjArgs a, const double* __
 // Density cell i = q j + p (per axis, p < q) has the design cell j under its
 // centre, and the squared centre offsets to design cell j + o depend on p and
 // o only: m = (2p + 1) d - n - 2 n o.  So each of the q^3 phases p has one
-// stencil, a list of (offset o, weight) shared by every cell of that phase.
-// A block stages an 8 x 8 x 4 tile of design cells with an h-cell halo in LDS
-// and each thread, one design cell, gathers the q^3 densities over it from
-// the tables, read with wave-uniform indices.  The transpose is the sum over
-// phases of the mirrored gather: design cell k collects g_i / omega_i from
-// the density cells i = q (k - o) + p, staged phase by phase.
-constexpr int PT_X = 8, PT_Y = 8, PT_Z = 4;  // design cells per block (one per thread)
-static_assert(PT_X * PT_Y * PT_Z == PROJ_BS, "one design cell per thread");
+// stencil S_p, a list of (offset o, weight) shared by every cell of that
+// phase.  Blocks stage a tile of the design lattice with an h-cell halo in
+// LDS and gather from tables whose entries hold an LDS offset and G weights,
+// one per output accumulated from that offset (zero where an output's
+// stencil misses it):
+// * forward: a thread owns PF_Z design cells along z and, for each, G
+//   phases' densities at a time, the table the union of their stencils; one
+//   entry feeds PF_Z LDS reads and PF_Z * G fused multiply-adds;
+// * transpose: design cell k collects g_i / omega_i over the density cells
+//   i = q (k - o) + p from the mirrored stencils, one phase's sub-lattice
+//   staged at a time (its loads issued before the barrier that frees the
+//   region).
+// Table entries are read with wave-uniform indices (scalar loads) a batch
+// ahead, so the wait for a batch's LDS reads does not also wait for them.
+constexpr int PT_X = 8, PT_Y = 8, PT_Z = 4;  // threads of a block per axis
+static_assert(PT_X * PT_Y * PT_Z == PROJ_BS, "one thread per tile column");
+constexpr int PF_Z = 2;  // design cells per forward thread along z
 
 struct ProjTileArgs {
   int nr[3], nx[3];
   int q, np, h;
   int S[3];          // staged region per axis: tile + 2h
+  int P0;            // LDS row pitch of the region (>= S[0], = 8 mod 16)
   int ntile[3];      // tiles per axis
 };
+
+// LDS row pitch of a region S0 cells wide: 8 (mod 16) doubles, so that the
+// two 8-lane rows of a 16-lane group of a wave land on disjoint halves of
+// the 32 four-byte banks.
+constexpr int lds_pitch(int S0) { return S0 <= 8 ? 8 : ((S0 + 7) / 16) * 16 + 8; }
 
 __device__ __forceinline__ void tile_origin(const ProjTileArgs& a, int& bx, int& by, int& bz) {
   const int b = blockIdx.x;
@@ -156,65 +174,86 @@ __device__ __forceinline__ void tile_origin(const ProjTileArgs& a, int& bx, int&
   bz = b / (a.ntile[0] * a.ntile[1]);
 }
 
-// Sum of w_e * sh[base + sign * rel_e] over the entries [e0, e1) of one phase
-// (a multiple of PT_BATCH, zero-weight padded): table entries are read with
-// wave-uniform indices (scalar loads) a batch ahead, so the wait for a batch's
-// LDS reads does not also wait for its table loads.
-constexpr int PT_BATCH = 8;
-template <int SIGN>
-__device__ __forceinline__ double phase_gather(const ProjEntry* __restrict__ ent, int e0, int e1,
-                                               const double* sh, int base) {
-  double acc0 = 0.0, acc1 = 0.0;
-  e0 = __builtin_amdgcn_readfirstlane(e0);
-  e1 = __builtin_amdgcn_readfirstlane(e1);
-  if (e0 >= e1) return 0.0;
-  ProjEntry cur[PT_BATCH];
+template <int G>
+struct PtBatch {
+  static constexpr int value = G == 1 ? 8 : 4;
+};
+
+// One table entry read as whole 16-byte words (contiguous, so that the
+// loads of a batch merge into wide scalar loads).
+template <int G>
+__device__ __forceinline__ ProjEntryG<G> load_entry(const ProjEntryG<G>* p) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  constexpr int NV = sizeof(ProjEntryG<G>) / 16;
+  union {
+    ProjEntryG<G> e;
+    d2 v[NV];
+  } u;
+  const d2* s = reinterpret_cast<const d2*>(p);
 #pragma unroll
-  for (int k = 0; k < PT_BATCH; ++k) cur[k] = ent[e0 + k];
-  for (int e = e0; e < e1; e += PT_BATCH) {
-    ProjEntry nxt[PT_BATCH];
-    const int en = e + PT_BATCH < e1 ? e + PT_BATCH : e;
-#pragma unroll
-    for (int k = 0; k < PT_BATCH; ++k) nxt[k] = ent[en + k];
-    double xv[PT_BATCH];
-#pragma unroll
-    for (int k = 0; k < PT_BATCH; ++k) xv[k] = sh[base + SIGN * cur[k].rel];
-    // the next batch's entries are needed here: their loads are issued
-    // before this batch's arithmetic and share its wait
-    asm volatile(""
-                 :
-                 : "s"(nxt[0].w), "s"(nxt[1].w), "s"(nxt[2].w), "s"(nxt[3].w), "s"(nxt[4].w),
-                   "s"(nxt[5].w), "s"(nxt[6].w), "s"(nxt[7].w), "s"(nxt[0].rel), "s"(nxt[1].rel),
-                   "s"(nxt[2].rel), "s"(nxt[3].rel), "s"(nxt[4].rel), "s"(nxt[5].rel),
-                   "s"(nxt[6].rel), "s"(nxt[7].rel));
-#pragma unroll
-    for (int k = 0; k < PT_BATCH; k += 2) {
-      acc0 = fma(cur[k].w, xv[k], acc0);
-      acc1 = fma(cur[k + 1].w, xv[k + 1], acc1);
-    }
-#pragma unroll
-    for (int k = 0; k < PT_BATCH; ++k) cur[k] = nxt[k];
-  }
-  return acc0 + acc1;
+  for (int i = 0; i < NV; ++i) u.v[i] = s[i];
+  return u.e;
 }
 
-// Stages the block's region (tile + halo, S[0] x S[1] x S[2] cells of the
-// design lattice starting at (rx, ry, rz)) in LDS, every load issued before
-// the first store: design values x_j (TRANS false) or, for phase (px, py, pz),
-// g_i / omega_i at the density cells i = q j + p (TRANS true); 0 outside the
-// domain.  The region holds at most PT_STAGE * PROJ_BS cells (h <= 4).
+// acc[b][c] += sum_e w_e[c] * sh[base[b] + SIGN * rel_e] over the entries
+// [e0, e1) (a multiple of the batch size, zero-weight padded).
+template <int SIGN, int G, int NB>
+__device__ __forceinline__ void grouped_gather(const ProjEntryG<G>* __restrict__ ent, int e0, int e1,
+                                               const double* sh, const int (&base)[NB],
+                                               double (&acc)[NB][G]) {
+  constexpr int B = PtBatch<G>::value;
+  e0 = __builtin_amdgcn_readfirstlane(e0);
+  e1 = __builtin_amdgcn_readfirstlane(e1);
+  if (e0 >= e1) return;
+  ProjEntryG<G> cur[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) cur[k] = load_entry(ent + e0 + k);
+  for (int e = e0; e < e1; e += B) {
+    ProjEntryG<G> nxt[B];
+    const int en = e + B < e1 ? e + B : e;
+#pragma unroll
+    for (int k = 0; k < B; ++k) nxt[k] = load_entry(ent + en + k);
+    double xv[B][NB];
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) xv[k][b] = sh[base[b] + SIGN * cur[k].rel];
+    // the next batch's entries are needed here: their loads are issued
+    // before this batch's arithmetic and share its wait
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      asm volatile("" : : "s"(nxt[k].rel));
+#pragma unroll
+      for (int c = 0; c < G; ++c) asm volatile("" : : "s"(nxt[k].w[c]));
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < G; ++c) acc[b][c] = fma(cur[k].w[c], xv[k][b], acc[b][c]);
+#pragma unroll
+    for (int k = 0; k < B; ++k) cur[k] = nxt[k];
+  }
+}
+
+// Staging of the block's region (S[0] x S[1] x S[2] cells of the design
+// lattice from (rx, ry, rz)): values of design cells x_j (TRANS false) or,
+// for phase (px, py, pz), g_i / omega_i at the density cells i = q j + p
+// (TRANS true); 0 outside the domain.  stage_load issues the loads of cells
+// p0 + threadIdx.x + u * PROJ_BS (u < PT_STAGE) into registers, branch-free
+// (cells outside the region or the domain load entry 0 and are masked), and
+// stage_store writes them to LDS.
 constexpr int PT_STAGE = 12;
 template <bool TRANS>
-__device__ __forceinline__ void stage_region(const ProjTileArgs& a, int rx, int ry, int rz, int px,
-                                             int py, int pz, const double* __restrict__ src,
-                                             const double* __restrict__ invw, double* sh) {
+__device__ __forceinline__ void stage_load(const ProjTileArgs& a, int p0, int rx, int ry, int rz,
+                                           int px, int py, int pz, const double* __restrict__ src,
+                                           const double* __restrict__ invw,
+                                           double (&v)[PT_STAGE]) {
   const int nreg = a.S[0] * a.S[1] * a.S[2];
-  double v[PT_STAGE];
-  // branch-free: cells outside the region or the domain load entry 0 and
-  // are masked to 0, so every load of the thread is issued back to back
 #pragma unroll
   for (int u = 0; u < PT_STAGE; ++u) {
-    const int idx = (int)threadIdx.x + u * PROJ_BS;
+    const int idx = p0 + (int)threadIdx.x + u * PROJ_BS;
     const int vx = idx % a.S[0], vy = (idx / a.S[0]) % a.S[1], vz = idx / (a.S[0] * a.S[1]);
     const int jx = rx + vx, jy = ry + vy, jz = rz + vz;
     const bool in = idx < nreg && (unsigned)jx < (unsigned)a.nx[0] &&
@@ -231,18 +270,27 @@ __device__ __forceinline__ void stage_region(const ProjTileArgs& a, int rx, int 
       v[u] = in ? xv : 0.0;
     }
   }
+}
+__device__ __forceinline__ int lds_index(const ProjTileArgs& a, int idx) {
+  const int vx = idx % a.S[0], r = idx / a.S[0];
+  return vx + a.P0 * r;  // r = vy + S[1] vz: rows of the region
+}
+__device__ __forceinline__ void stage_store(const ProjTileArgs& a, int p0, const double (&v)[PT_STAGE],
+                                            double* sh) {
+  const int nreg = a.S[0] * a.S[1] * a.S[2];
 #pragma unroll
   for (int u = 0; u < PT_STAGE; ++u) {
-    const int idx = (int)threadIdx.x + u * PROJ_BS;
-    if (idx < nreg) sh[idx] = v[u];
+    const int idx = p0 + (int)threadIdx.x + u * PROJ_BS;
+    if (idx < nreg) sh[lds_index(a, idx)] = v[u];
   }
 }
 
 // (the tables are separate no-alias parameters: the compiler then reads them
 // through the scalar cache, which it may not do for memory the kernel's
 // stores might alias)
+template <int G>
 __global__ __launch_bounds__(PROJ_BS) void k_proj_fwd_tile(ProjTileArgs a,
-                                                            const ProjEntry* __restrict__ ent,
+                                                            const ProjEntryG<G>* __restrict__ ent,
                                                             const int* __restrict__ start,
                                                             const double* __restrict__ x,
                                                             const double* __restrict__ invw,
@@ -251,41 +299,65 @@ __global__ __launch_bounds__(PROJ_BS) void k_proj_fwd_tile(ProjTileArgs a,
   int bx, by, bz;
   tile_origin(a, bx, by, bz);
   const int t = threadIdx.x;
-  const int rx = bx * PT_X - a.h, ry = by * PT_Y - a.h, rz = bz * PT_Z - a.h;
-  stage_region<false>(a, rx, ry, rz, 0, 0, 0, x, nullptr, sh);
+  const int rx = bx * PT_X - a.h, ry = by * PT_Y - a.h, rz = bz * PT_Z * PF_Z - a.h;
+  const int nreg = a.S[0] * a.S[1] * a.S[2];
+  for (int p0 = 0; p0 < nreg; p0 += PT_STAGE * PROJ_BS) {
+    double v[PT_STAGE];
+    stage_load<false>(a, p0, rx, ry, rz, 0, 0, 0, x, nullptr, v);
+    stage_store(a, p0, v, sh);
+  }
   __syncthreads();
   const int lx = t % PT_X, ly = (t / PT_X) % PT_Y, lz = t / (PT_X * PT_Y);
-  const int jx = bx * PT_X + lx, jy = by * PT_Y + ly, jz = bz * PT_Z + lz;
-  const bool on = jx < a.nx[0] && jy < a.nx[1] && jz < a.nx[2];
-  const int base = (lx + a.h) + a.S[0] * ((ly + a.h) + a.S[1] * (lz + a.h));
-  // phases in groups of 8: the gathers first, then the group's 1/omega loads
-  // together, then its stores
-  constexpr int G = 8;
+  const int jx = bx * PT_X + lx, jy = by * PT_Y + ly;
+  int jz[PF_Z], base[PF_Z];
+  bool on[PF_Z];
+#pragma unroll
+  for (int b = 0; b < PF_Z; ++b) {
+    const int zl = PF_Z * lz + b;
+    jz[b] = bz * PT_Z * PF_Z + zl;
+    on[b] = jx < a.nx[0] && jy < a.nx[1] && jz[b] < a.nx[2];
+    base[b] = (lx + a.h) + a.P0 * ((ly + a.h) + a.S[1] * (zl + a.h));
+  }
   for (int p0 = 0; p0 < a.np; p0 += G) {
-    double acc[G];
-    long idx[G];
+    double acc[PF_Z][G];
 #pragma unroll
-    for (int u = 0; u < G; ++u) {
-      const int p = p0 + u < a.np ? p0 + u : p0;
-      const int px = p % a.q, py = (p / a.q) % a.q, pz = p / (a.q * a.q);
-      acc[u] = p0 + u < a.np ? phase_gather<1>(ent, start[p], start[p + 1], sh, base) : 0.0;
-      idx[u] = on ? (long)(a.q * jx + px) +
-                        (long)a.nr[0] * ((long)(a.q * jy + py) + (long)a.nr[1] * (a.q * jz + pz))
-                  : 0L;
-    }
-    double w[G];
+    for (int b = 0; b < PF_Z; ++b)
 #pragma unroll
-    for (int u = 0; u < G; ++u) w[u] = invw[idx[u]];
-    if (on) {
+      for (int c = 0; c < G; ++c) acc[b][c] = 0.0;
+    grouped_gather<1, G, PF_Z>(ent, start[p0 / G], start[p0 / G + 1], sh, base, acc);
+    // the group's 1/omega loads together, then its stores
+    long idx[PF_Z][G];
+    double w[PF_Z][G];
 #pragma unroll
-      for (int u = 0; u < G; ++u)
-        if (p0 + u < a.np) out[idx[u]] = acc[u] * w[u];
-    }
+    for (int b = 0; b < PF_Z; ++b)
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        const int p = p0 + c;
+        const int px = p % a.q, py = (p / a.q) % a.q, pz = p / (a.q * a.q);
+        idx[b][c] = on[b] ? (long)(a.q * jx + px) +
+                                (long)a.nr[0] *
+                                    ((long)(a.q * jy + py) + (long)a.nr[1] * (a.q * jz[b] + pz))
+                          : 0L;
+        w[b][c] = invw[idx[b][c]];
+      }
+#pragma unroll
+    for (int b = 0; b < PF_Z; ++b)
+      if (on[b]) {
+#pragma unroll
+        for (int c = 0; c < G; ++c) out[idx[b][c]] = acc[b][c] * w[b][c];
+      }
   }
 }
 
+// Transpose: a thread owns PT_ZT design cells along z (each table entry then
+// serves PT_ZT LDS reads).  The region's cells of this thread (cells
+// threadIdx.x + u * PROJ_BS, one staging pass) are decomposed once; for phase
+// p the density cell of region cell (vx, vy, vz) is cell0 + px + nr0 (py +
+// nr1 pz) with cell0 = q (rx + vx) + nr0 (q (ry + vy) + nr1 q (rz + vz)).
+constexpr int PT_ZT = 2;
+constexpr int PT_STAGE_T = 16;  // region cells per thread: (8 + 2h)^2 (8 + 2h) <= 4096, h <= 4
 __global__ __launch_bounds__(PROJ_BS) void k_proj_t_tile(ProjTileArgs a,
-                                                          const ProjEntry* __restrict__ ent,
+                                                          const ProjEntryG<1>* __restrict__ ent,
                                                           const int* __restrict__ start,
                                                           const double* __restrict__ g,
                                                           const double* __restrict__ invw,
@@ -294,20 +366,56 @@ __global__ __launch_bounds__(PROJ_BS) void k_proj_t_tile(ProjTileArgs a,
   int bx, by, bz;
   tile_origin(a, bx, by, bz);
   const int t = threadIdx.x;
-  const int rx = bx * PT_X - a.h, ry = by * PT_Y - a.h, rz = bz * PT_Z - a.h;
+  const int rx = bx * PT_X - a.h, ry = by * PT_Y - a.h, rz = bz * PT_Z * PT_ZT - a.h;
   const int lx = t % PT_X, ly = (t / PT_X) % PT_Y, lz = t / (PT_X * PT_Y);
-  const int kx = bx * PT_X + lx, ky = by * PT_Y + ly, kz = bz * PT_Z + lz;
-  const bool on = kx < a.nx[0] && ky < a.nx[1] && kz < a.nx[2];
-  const int base = (lx + a.h) + a.S[0] * ((ly + a.h) + a.S[1] * (lz + a.h));
-  double acc = 0.0;
+  const int kx = bx * PT_X + lx, ky = by * PT_Y + ly;
+  const int nreg = a.S[0] * a.S[1] * a.S[2];
+  int base[PT_ZT];
+#pragma unroll
+  for (int b = 0; b < PT_ZT; ++b)
+    base[b] = (lx + a.h) + a.P0 * ((ly + a.h) + a.S[1] * (PT_ZT * lz + b + a.h));
+  long cell0[PT_STAGE_T];
+  int slot[PT_STAGE_T];
+  unsigned inmask = 0;
+#pragma unroll
+  for (int u = 0; u < PT_STAGE_T; ++u) {
+    const int idx = t + u * PROJ_BS;
+    const int vx = idx % a.S[0], vy = (idx / a.S[0]) % a.S[1], vz = idx / (a.S[0] * a.S[1]);
+    const int jx = rx + vx, jy = ry + vy, jz = rz + vz;
+    const bool in = idx < nreg && (unsigned)jx < (unsigned)a.nx[0] &&
+                    (unsigned)jy < (unsigned)a.nx[1] && (unsigned)jz < (unsigned)a.nx[2];
+    cell0[u] = in ? (long)(a.q * jx) + (long)a.nr[0] * ((long)(a.q * jy) + (long)a.nr[1] * (a.q * jz))
+                  : 0L;
+    inmask |= in ? 1u << u : 0u;
+    slot[u] = idx < nreg ? lds_index(a, idx) : -1;
+  }
+  double acc[PT_ZT][1];
+#pragma unroll
+  for (int b = 0; b < PT_ZT; ++b) acc[b][0] = 0.0;
   for (int p = 0; p < a.np; ++p) {
     const int px = p % a.q, py = (p / a.q) % a.q, pz = p / (a.q * a.q);
+    const long poff = px + (long)a.nr[0] * (py + (long)a.nr[1] * pz);
+    double v[PT_STAGE_T];
+#pragma unroll
+    for (int u = 0; u < PT_STAGE_T; ++u) {
+      const bool in = (inmask >> u) & 1u;
+      const long i = in ? cell0[u] + poff : 0L;
+      const double gv = g[i], wv = invw[i];
+      v[u] = in ? gv * wv : 0.0;
+    }
     __syncthreads();  // the previous phase's reads are done
-    stage_region<true>(a, rx, ry, rz, px, py, pz, g, invw, sh);
+#pragma unroll
+    for (int u = 0; u < PT_STAGE_T; ++u)
+      if (slot[u] >= 0) sh[slot[u]] = v[u];
     __syncthreads();
-    acc += phase_gather<-1>(ent, start[p], start[p + 1], sh, base);
+    grouped_gather<-1, 1, PT_ZT>(ent, start[p], start[p + 1], sh, base, acc);
   }
-  if (on) out[kx + (long)a.nx[0] * (ky + (long)a.nx[1] * kz)] = acc;
+#pragma unroll
+  for (int b = 0; b < PT_ZT; ++b) {
+    const int kz = bz * PT_Z * PT_ZT + PT_ZT * lz + b;
+    if (kx < a.nx[0] && ky < a.nx[1] && kz < a.nx[2])
+      out[kx + (long)a.nx[0] * (ky + (long)a.nx[1] * kz)] = acc[b][0];
+  }
 }
 
 // Largest per-axis squared offset from a density centre to its nearest
@@ -369,23 +477,30 @@ ProjGeom Proj::geometry(const mgcg_proj_desc& d) {
   return g;
 }
 
-// The q^3 phase stencils of the tiled kernels (left empty, q = 0, when d does
-// not divide n, the phases are too many or a stencil reaches past 4 cells).
+// The gather tables of the tiled kernels (left empty, q = 0, when d does not
+// divide n, the phases are too many or a stencil reaches past 4 cells).
+template <int G>
+static void pad_batch(std::vector<ProjEntryG<G>>& v) {
+  while (v.size() % PtBatch<G>::value) v.push_back(ProjEntryG<G>{});
+}
+
 void Proj::phase_tables(ProjGeom& g) {
-  g.q = g.np = g.h = 0;
-  g.ent.clear();
-  g.start.clear();
+  g.q = g.np = g.h = g.gf = 0;
+  g.fwd1.clear();
+  g.fwd4.clear();
+  g.trg.clear();
+  g.start_f.clear();
+  g.start_t.clear();
   if (g.n % g.d != 0) return;
   const int q = g.n / g.d;
   if (q > 8) return;
-  struct Raw {
-    int o[3];
-    double w;
-  };
-  std::vector<std::vector<Raw>> ph(q * q * q);
+  const int np = q * q * q;
+  // stencil of each phase: offset (ordered z, y, x) -> weight
+  using Key = std::array<int, 3>;  // (oz, oy, ox)
+  std::vector<std::map<Key, double>> S(np);
   int h = 0;
   long total = 0;
-  for (int p = 0; p < q * q * q; ++p) {
+  for (int p = 0; p < np; ++p) {
     const int pp[3] = {p % q, (p / q) % q, p / (q * q)};
     int m0[3];
     for (int a = 0; a < 3; ++a) m0[a] = (2 * pp[a] + 1) * g.d - g.n;  // m at o = 0
@@ -396,49 +511,94 @@ void Proj::phase_tables(ProjGeom& g) {
                      mz = m0[2] - 2L * g.n * oz;
           if ((double)(mx * mx + my * my + mz * mz) > g.R2) continue;
           // the generic kernels' product order: (e(mz) e(my)) e(mx)
-          const double w = g.tab[std::labs(mx)] * (g.tab[std::labs(mz)] * g.tab[std::labs(my)]);
-          ph[p].push_back(Raw{{ox, oy, oz}, w});
+          S[p][Key{oz, oy, ox}] =
+              g.tab[std::labs(mx)] * (g.tab[std::labs(mz)] * g.tab[std::labs(my)]);
           h = std::max({h, std::abs(ox), std::abs(oy), std::abs(oz)});
         }
-    total += (long)ph[p].size();
+    total += (long)S[p].size();
   }
-  if (h > 4 || total > 65536) return;  // (h <= 4: the region fits PT_STAGE * PROJ_BS cells)
+  if (h > 4 || total > 65536) return;
   g.q = q;
-  g.np = q * q * q;
+  g.np = np;
   g.h = h;
-  const int SX = PT_X + 2 * h, SY = PT_Y + 2 * h;  // the tile's x and y extents with halo
-  g.start.push_back(0);
-  for (int p = 0; p < g.np; ++p) {
-    for (const Raw& r : ph[p]) g.ent.push_back(ProjEntry{r.w, r.o[0] + SX * (r.o[1] + SY * r.o[2]), 0});
-    // zero-weight padding to whole batches of the gather loop
-    while (g.ent.size() % PT_BATCH) g.ent.push_back(ProjEntry{0.0, 0, 0});
-    g.start.push_back((int)g.ent.size());
+  g.gf = np % 4 == 0 ? 4 : 1;
+  // forward: groups of gf consecutive phases, the union of their stencils
+  const int SXf = lds_pitch(PT_X + 2 * h), SYf = PT_Y + 2 * h;
+  g.start_f.push_back(0);
+  for (int p0 = 0; p0 < np; p0 += g.gf) {
+    std::set<Key> U;
+    for (int c = 0; c < g.gf; ++c)
+      for (const auto& kv : S[p0 + c]) U.insert(kv.first);
+    for (const Key& u : U) {
+      const int rel = u[2] + SXf * (u[1] + SYf * u[0]);
+      if (g.gf == 4) {
+        ProjEntryG<4> e{};
+        for (int c = 0; c < 4; ++c) {
+          auto it = S[p0 + c].find(u);
+          e.w[c] = it == S[p0 + c].end() ? 0.0 : it->second;
+        }
+        e.rel = rel;
+        g.fwd4.push_back(e);
+      } else {
+        ProjEntryG<1> e{};
+        e.w[0] = S[p0].at(u);
+        e.rel = rel;
+        g.fwd1.push_back(e);
+      }
+    }
+    if (g.gf == 4) {
+      pad_batch(g.fwd4);
+      g.start_f.push_back((int)g.fwd4.size());
+    } else {
+      pad_batch(g.fwd1);
+      g.start_f.push_back((int)g.fwd1.size());
+    }
+  }
+  // transpose: per phase, the mirrored stencil (read at k - o)
+  const int SXt = lds_pitch(PT_X + 2 * h), SYt = PT_Y + 2 * h;
+  g.start_t.push_back(0);
+  for (int p = 0; p < np; ++p) {
+    for (const auto& kv : S[p]) {
+      ProjEntryG<1> e{};
+      e.w[0] = kv.second;
+      e.rel = kv.first[2] + SXt * (kv.first[1] + SYt * kv.first[0]);
+      g.trg.push_back(e);
+    }
+    pad_batch(g.trg);
+    g.start_t.push_back((int)g.trg.size());
   }
 }
 
 size_t Proj::device_bytes(const mgcg_proj_desc& d) {
   const ProjGeom g = geometry(d);
-  return ((size_t)g.nrho + (size_t)g.ntab) * sizeof(double) + g.ent.size() * sizeof(ProjEntry) +
-         g.start.size() * sizeof(int);
+  return ((size_t)g.nrho + (size_t)g.ntab) * sizeof(double) + g.table_bytes();
 }
 
 Proj::Proj(const mgcg_proj_desc& d, int device) : g_(geometry(d)), device_(device) {
   MGCG_HIP(hipSetDevice(device_));
   (void)d;
   try {
+    const size_t fwd_bytes = g_.gf == 4 ? g_.fwd4.size() * sizeof(ProjEntryG<4>)
+                                        : g_.fwd1.size() * sizeof(ProjEntryG<1>);
+    const size_t tr_bytes = g_.trg.size() * sizeof(ProjEntryG<1>);
     if (hipMalloc(&invw_, (size_t)g_.nrho * sizeof(double)) != hipSuccess ||
         hipMalloc(&tab_, g_.tab.size() * sizeof(double)) != hipSuccess ||
-        (g_.q > 0 && (hipMalloc(&ent_, g_.ent.size() * sizeof(ProjEntry)) != hipSuccess ||
-                      hipMalloc(&start_, g_.start.size() * sizeof(int)) != hipSuccess))) {
+        (g_.q > 0 && (hipMalloc(&fwd_ent_, fwd_bytes) != hipSuccess ||
+                      hipMalloc(&tr_ent_, tr_bytes) != hipSuccess ||
+                      hipMalloc(&start_f_, g_.start_f.size() * sizeof(int)) != hipSuccess ||
+                      hipMalloc(&start_t_, g_.start_t.size() * sizeof(int)) != hipSuccess))) {
       (void)hipGetLastError();
       throw Error(MGCG_ENOMEM, "projection allocation failed");
     }
     MGCG_HIP(hipMemcpyAsync(tab_, g_.tab.data(), g_.tab.size() * sizeof(double),
                             hipMemcpyHostToDevice, stream_));
     if (g_.q > 0) {
-      MGCG_HIP(hipMemcpyAsync(ent_, g_.ent.data(), g_.ent.size() * sizeof(ProjEntry),
+      const void* fsrc = g_.gf == 4 ? (const void*)g_.fwd4.data() : (const void*)g_.fwd1.data();
+      MGCG_HIP(hipMemcpyAsync(fwd_ent_, fsrc, fwd_bytes, hipMemcpyHostToDevice, stream_));
+      MGCG_HIP(hipMemcpyAsync(tr_ent_, g_.trg.data(), tr_bytes, hipMemcpyHostToDevice, stream_));
+      MGCG_HIP(hipMemcpyAsync(start_f_, g_.start_f.data(), g_.start_f.size() * sizeof(int),
                               hipMemcpyHostToDevice, stream_));
-      MGCG_HIP(hipMemcpyAsync(start_, g_.start.data(), g_.start.size() * sizeof(int),
+      MGCG_HIP(hipMemcpyAsync(start_t_, g_.start_t.data(), g_.start_t.size() * sizeof(int),
                               hipMemcpyHostToDevice, stream_));
     }
     launch_norm();
@@ -456,11 +616,11 @@ void Proj::release() {
   (void)hipStreamSynchronize(stream_);
   if (invw_) (void)hipFree(invw_);
   if (tab_) (void)hipFree(tab_);
-  if (ent_) (void)hipFree(ent_);
-  if (start_) (void)hipFree(start_);
+  for (void* q : {fwd_ent_, tr_ent_, (void*)start_f_, (void*)start_t_})
+    if (q) (void)hipFree(q);
   invw_ = tab_ = nullptr;
-  ent_ = nullptr;
-  start_ = nullptr;
+  fwd_ent_ = tr_ent_ = nullptr;
+  start_f_ = start_t_ = nullptr;
 }
 
 void Proj::set_stream(hipStream_t s) {
@@ -533,22 +693,29 @@ void Proj::run(bool transpose, const double* in, double* out, int mem) {
     a.q = g_.q;
     a.np = g_.np;
     a.h = g_.h;
-    const int T[3] = {PT_X, PT_Y, PT_Z};
+    // design cells per block tile: PF_Z (forward) or PT_ZT (transpose) per
+    // thread along z
+    const int T[3] = {PT_X, PT_Y, PT_Z * (transpose ? PT_ZT : PF_Z)};
     long nb = 1;
     for (int i = 0; i < 3; ++i) {
       a.S[i] = T[i] + 2 * g_.h;
       a.ntile[i] = (g_.nx[i] + T[i] - 1) / T[i];
       nb *= a.ntile[i];
     }
-    const size_t lds = (size_t)a.S[0] * a.S[1] * a.S[2] * sizeof(double);
+    a.P0 = lds_pitch(a.S[0]);
+    const size_t lds = (size_t)a.P0 * a.S[1] * a.S[2] * sizeof(double);
     if (transpose)
       hipLaunchKernelGGL(k_proj_t_tile, dim3((unsigned)nb), dim3(PROJ_BS), lds, stream_, a,
-                         (const ProjEntry*)ent_, (const int*)start_, din, (const double*)invw_,
-                         dout);
+                         (const ProjEntryG<1>*)tr_ent_, (const int*)start_t_, din,
+                         (const double*)invw_, dout);
+    else if (g_.gf == 4)
+      hipLaunchKernelGGL(k_proj_fwd_tile<4>, dim3((unsigned)nb), dim3(PROJ_BS), lds, stream_, a,
+                         (const ProjEntryG<4>*)fwd_ent_, (const int*)start_f_, din,
+                         (const double*)invw_, dout);
     else
-      hipLaunchKernelGGL(k_proj_fwd_tile, dim3((unsigned)nb), dim3(PROJ_BS), lds, stream_, a,
-                         (const ProjEntry*)ent_, (const int*)start_, din, (const double*)invw_,
-                         dout);
+      hipLaunchKernelGGL(k_proj_fwd_tile<1>, dim3((unsigned)nb), dim3(PROJ_BS), lds, stream_, a,
+                         (const ProjEntryG<1>*)fwd_ent_, (const int*)start_f_, din,
+                         (const double*)invw_, dout);
   } else {
     const int nb = (int)((nout + PROJ_BS - 1) / PROJ_BS);
     if (transpose)

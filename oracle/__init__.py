@@ -26,7 +26,10 @@ What it computes (the plain definitions, in FP64):
 * ``projection`` the weighted-average projection of design variables onto
                densities (Sec. 3.2 eq. (5), weights of Sec. 2.2 eq. (4); the
                density filter when both lattices coincide) and its transpose,
-               the chain rule of Sec. 3.4.
+               the chain rule of Sec. 3.4;
+* ``slp``      the SLP step of Sec. 4: the LP subproblem with the volume
+               constraint and the trust region (a fractional knapsack), the
+               artificial problem, and the step control of Algorithm 2.
 
 Parity status of every function is listed in its module docstring.
 """

@@ -261,6 +261,68 @@ int mgcg_proj_apply(mgcg_proj* pr, const double* x, double* rho, int mem);
 /* gx[n_x] = W^T g[n_rho] (the chain rule of Sec. 3.4). */
 int mgcg_proj_apply_transpose(mgcg_proj* pr, const double* g, double* gx, int mem);
 
+/* ---- The SLP step (Sec. 4): LP subproblem and step control ----
+ *
+ * The LP subproblem (Sec. 4.1, problem (Pstar)) for the topology problem's
+ * one linear constraint, the volume, whose gradient a is positive:
+ *     min g^T s  s.t.  a^T s = b,  l <= s <= u,
+ *     l_i = max(-delta, x_l - x_i),  u_i = min(delta, x_u - x_i)
+ * (the volume constraint taken as an equality, the form of problem (P)).
+ * With one constraint and a box it is a fractional knapsack: from s = l the
+ * variables are raised in order of the ratio -g_i / a_i, highest first and
+ * equal ratios in index order, each to u, until the budget B = b - a^T l is
+ * used; the first variable (with u > l) whose running capacity a (u - l)
+ * reaches B is raised partially and its ratio is the constraint's multiplier
+ * lambda.  When B < 0 or B exceeds the total capacity the LP has no solution
+ * and s is the artificial problem's (Pstar2, the box shrunk to 0.8 delta):
+ * its lower end if B < 0, its upper end otherwise; info->feasible is then 0
+ * and lambda NaN.
+ *
+ * An LP object holds device scratch for n variables (mgcg_lp_device_bytes);
+ * g, a, x, s are FP64 [n] in host or device memory (mem); device-memory calls
+ * run on the object's stream (the null stream unless set) and return when
+ * the results are written (the call reads the budget back once).  Errors:
+ * MGCG_EINVAL for n outside 1..2^31, delta not positive, non-finite b,
+ * x_l > x_u, or any a_i <= 0 or non-finite input. */
+typedef struct mgcg_lp mgcg_lp;
+typedef struct mgcg_lp_info {
+  double lambda;   /* multiplier of the constraint (the critical ratio) */
+  double gts;      /* g^T s */
+  double ats;      /* a^T s */
+  double s_inf;    /* max_i |s_i| */
+  double budget;   /* B = b - a^T l */
+  int32_t feasible;
+  int32_t pad;
+} mgcg_lp_info;
+size_t mgcg_lp_device_bytes(int64_t n);
+int mgcg_lp_create(int64_t n, int device, mgcg_lp** out);
+int mgcg_lp_destroy(mgcg_lp* lp);
+int mgcg_lp_set_stream(mgcg_lp* lp, void* stream);
+int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x, double b,
+                  double delta, double x_l, double x_u, double* s, mgcg_lp_info* info, int mem);
+
+/* Step control of Algorithm 2 (host only).  After a trial step s of the LP:
+ * f0 = f(x), f1 = f(x + s), c0 = c(x), c1 = c(x + s) (the constraint's value),
+ * gts = g^T s, ats = a^T s, s_inf = |s|_inf.  Computes theta_k =
+ * min(theta_large, theta_sup, theta_max) (eqs. (theta1), (theta2), with
+ * P_fsb = M(x, 0) - M(x, s), M = (a^T s + c)^2 / 2, and P_opt = g^T s), the
+ * actual and predicted reductions of psi = theta f + (1 - theta) |c|^2 / 2,
+ * and rejects (A_red < 0.1 P_red: delta = min(0.25 s_inf, 0.1 delta),
+ * theta_max = theta_k) or accepts (delta doubled up to box_inf when A_red >=
+ * 0.5 P_red, then at least delta_min; theta_max = 1; k + 1; the history
+ * minimum takes theta_k).  Returns 1 if accepted, 0 if rejected, MGCG_EINVAL
+ * for a NULL ctrl.  Start from delta = delta_0, theta_max = theta_min_hist =
+ * 1, k = 0. */
+typedef struct mgcg_slp_ctrl {
+  double delta, delta_min, box_inf; /* radius, its floor, |x_u - x_l|_inf */
+  double theta_max, theta_min_hist; /* theta_max and min(theta_0 .. theta_{k-1}) */
+  double N;                         /* the constant of eq. (theta1), 1e6 in the paper */
+  int32_t k;                        /* outer iteration */
+  int32_t pad;
+} mgcg_slp_ctrl;
+int mgcg_slp_decide(mgcg_slp_ctrl* ctrl, double f0, double f1, double c0, double c1, double gts,
+                    double ats, double s_inf, double* theta, double* a_red, double* p_red);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,8 +15,13 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   used up; the variable that crosses the budget is raised partially.  Ties in
   r are taken in increasing index order (any order gives the same objective).
   The multiplier of the equality is the critical ratio lambda = r_k (the
-  Lagrangian g + lambda a is <= 0 on the raised variables, >= 0 on the rest).
-* Infeasible LP (B < 0 or B above the total capacity): the artificial problem
+  Lagrangian g + lambda a is <= 0 on the raised variables, >= 0 on the rest;
+  the critical variable is the first, in the order, with positive capacity
+  u - l whose running capacity reaches B).
+* Infeasible LP (B < 0 or B above the total capacity, beyond the rounding
+  allowance 2 n eps (sum |a_i l_i| + sum a_i (u_i - l_i)) of the sums that
+  give them; a budget inside the allowance is clamped to the boundary): the
+  artificial problem
   (Pstar2) with the box shrunk to 0.8 delta; with one constraint its solution
   is the end of the shrunk box that leaves the least violation, s = l' if
   B < 0, s = u' if B exceeds the capacity.  Reading: the upper bound of the
@@ -55,26 +60,36 @@ def lp_step(g, a, x, b, delta, xl=0.0, xu=1.0):
     l, u = lp_bounds(x, delta, xl, xu)
     B = b - float(np.dot(a, l))
     cap = a * (u - l)
-    if B < 0.0 or B > cap.sum():
+    # a budget within the rounding of its sums of 0 or of the capacity is the
+    # boundary itself
+    tau = 2 * g.size * np.finfo(np.float64).eps * (float(np.abs(a * l).sum()) + float(cap.sum()))
+    if B < -tau or B > cap.sum() + tau:
         # artificial problem with the box shrunk to 0.8 delta
         l2, u2 = lp_bounds(x, 0.8 * delta, xl, xu)
         return (l2.copy() if B < 0.0 else u2.copy()), float("nan"), False
+    B = min(max(B, 0.0), float(cap.sum()))
     r = -g / a
     order = sorted(range(g.size), key=lambda i: (-r[i], i))
     s = l.copy()
     left = B
-    lam = r[order[-1]] if order else 0.0
+    lam = None
+    last = None
     for i in order:
-        if left <= 0.0:
-            break
-        if cap[i] <= left:
+        if cap[i] <= 0.0:
+            continue  # u = l
+        last = i
+        if cap[i] < left:
             s[i] = u[i]
             left -= cap[i]
-            lam = r[i]
-        else:
-            s[i] = l[i] + left / a[i]
-            left = 0.0
-            lam = r[i]
+            continue
+        # the critical variable: the first whose running capacity reaches B
+        s[i] = u[i] if cap[i] == left else l[i] + left / a[i]
+        lam = r[i]
+        break
+    if lam is None:
+        # rounding left the budget above the capacity: the last variable with
+        # capacity; with none at all, the first in the order
+        lam = r[last] if last is not None else r[order[0]]
     return s, lam, True
 
 

@@ -49,6 +49,18 @@ class mgcg_proj_desc(C.Structure):
                 ("rmin", C.c_double)]
 
 
+class mgcg_lp_info(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("gts", C.c_double), ("ats", C.c_double),
+                ("s_inf", C.c_double), ("budget", C.c_double), ("feasible", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class mgcg_slp_ctrl(C.Structure):
+    _fields_ = [("delta", C.c_double), ("delta_min", C.c_double), ("box_inf", C.c_double),
+                ("theta_max", C.c_double), ("theta_min_hist", C.c_double), ("N", C.c_double),
+                ("k", C.c_int32), ("pad", C.c_int32)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "mgcg_last_error": (C.c_char_p, []),
@@ -93,6 +105,17 @@ EXPORTS = {
     "mgcg_proj_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgcg_proj_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "mgcg_proj_apply_transpose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "mgcg_lp_device_bytes": (C.c_size_t, [C.c_int64]),
+    "mgcg_lp_create": (C.c_int, [C.c_int64, C.c_int, C.POINTER(C.c_void_p)]),
+    "mgcg_lp_destroy": (C.c_int, [C.c_void_p]),
+    "mgcg_lp_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mgcg_lp_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                C.POINTER(mgcg_lp_info), C.c_int]),
+    "mgcg_slp_decide": (C.c_int, [C.POINTER(mgcg_slp_ctrl), C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.c_double, C.c_double, C.c_double,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]),
 }
 
 _lib = None

@@ -356,5 +356,71 @@ class Projection:
         return self._run(self._lib.mgcg_proj_apply_transpose, g, self.nrho, self.nx, out)
 
 
-__all__ = ["Problem", "Server", "Projection", "admission_plan", "device_bytes", "make_desc",
+class LP:
+    """The LP subproblem of the SLP step (mgcg_lp_* in include/mgcg.h) for n
+    variables.  solve() returns (s, info dict); vectors are numpy arrays or
+    contiguous float64 device tensors (then run on the current torch stream)."""
+
+    def __init__(self, n, device=0):
+        lib = load()
+        h = C.c_void_p()
+        check(lib.mgcg_lp_create(int(n), int(device), C.byref(h)))
+        self._h, self._lib, self.n = h, lib, int(n)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.mgcg_lp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, g, a, x, b, delta, x_l=0.0, x_u=1.0, out=None):
+        pg, mem, kg = _ptr(g)
+        pa, _, ka = _ptr(a)
+        px, _, kx = _ptr(x)
+        for k in (kg, ka, kx):
+            if (k.numel() if mem == MGCG_MEM_DEVICE else k.size) != self.n:
+                raise ValueError("vector length does not match the LP size")
+        if mem == MGCG_MEM_DEVICE:
+            torch = _torch()
+            cur = torch.cuda.current_stream().cuda_stream
+            if cur != getattr(self, "_stream", 0):
+                check(self._lib.mgcg_lp_set_stream(self._h, C.c_void_p(cur)))
+                self._stream = cur
+            if out is None:
+                out = torch.empty(self.n, dtype=torch.float64, device=kg.device)
+            ps = C.c_void_p(out.data_ptr())
+        else:
+            out = np.empty(self.n) if out is None else out
+            ps = C.c_void_p(out.ctypes.data)
+        info = _abi.mgcg_lp_info()
+        check(self._lib.mgcg_lp_solve(self._h, pg, pa, px, float(b), float(delta), float(x_l),
+                                      float(x_u), ps, C.byref(info), mem))
+        return out, {"lambda": info.lambda_, "gts": info.gts, "ats": info.ats,
+                     "s_inf": info.s_inf, "budget": info.budget,
+                     "feasible": bool(info.feasible)}
+
+
+def slp_ctrl(delta0, delta_min=1e-3, box_inf=1.0, N=1e6):
+    """Initial step-control state of Algorithm 2."""
+    return _abi.mgcg_slp_ctrl(float(delta0), float(delta_min), float(box_inf), 1.0, 1.0,
+                              float(N), 0, 0)
+
+
+def slp_decide(ctrl, f0, f1, c0, c1, gts, ats, s_inf):
+    """One accept/reject decision of Algorithm 2 (updates ctrl in place);
+    returns (accepted, theta, A_red, P_red)."""
+    th, ar, pr = C.c_double(), C.c_double(), C.c_double()
+    r = load().mgcg_slp_decide(C.byref(ctrl), f0, f1, c0, c1, gts, ats, s_inf, C.byref(th),
+                               C.byref(ar), C.byref(pr))
+    if r < 0:
+        check(r)
+    return bool(r), th.value, ar.value, pr.value
+
+
+__all__ = ["Problem", "Server", "Projection", "LP", "slp_ctrl", "slp_decide", "admission_plan", "device_bytes", "make_desc",
            "make_proj_desc", "proj_device_bytes", "_abi"]

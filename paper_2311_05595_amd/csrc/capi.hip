@@ -336,3 +336,69 @@ int mgcg_proj_apply_transpose(mgcg_proj* pr, const double* g, double* gx, int me
 }
 
 }  // extern "C"
+
+// ---- SLP step
+#include "lp.h"
+
+struct mgcg_lp {
+  mgcg::Lp* impl;
+};
+
+extern "C" {
+
+size_t mgcg_lp_device_bytes(int64_t n) {
+  if (n < 1 || n > (1LL << 31)) return 0;
+  return mgcg::Lp::device_bytes((long)n);
+}
+
+int mgcg_lp_create(int64_t n, int device, mgcg_lp** out) {
+  NEED(out);
+  GUARD({
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    if (device < 0 || (ndev > 0 && device >= ndev)) throw Error(MGCG_EINVAL, "bad device index");
+    auto* p = new mgcg_lp{nullptr};
+    try {
+      p->impl = new mgcg::Lp((long)n, device);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_lp_destroy(mgcg_lp* lp) {
+  NEED(lp);
+  GUARD({
+    delete lp->impl;
+    delete lp;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_lp_set_stream(mgcg_lp* lp, void* stream) {
+  NEED(lp);
+  GUARD({
+    lp->impl->set_stream((hipStream_t)stream);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x, double b,
+                  double delta, double x_l, double x_u, double* s, mgcg_lp_info* info, int mem) {
+  NEED(lp);
+  GUARD({
+    lp->impl->solve(g, a, x, b, delta, x_l, x_u, s, info, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_slp_decide(mgcg_slp_ctrl* ctrl, double f0, double f1, double c0, double c1, double gts,
+                    double ats, double s_inf, double* theta, double* a_red, double* p_red) {
+  NEED(ctrl);
+  return mgcg::slp_decide(ctrl, f0, f1, c0, c1, gts, ats, s_inf, theta, a_red, p_red);
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Host runtime of the SLP step: the LP subproblem on the device and the step
+// control of Algorithm 2 on the host.
+#pragma once
+
+#include "../../include/mgcg.h"
+#include "common.h"
+
+namespace mgcg {
+
+class Lp {
+ public:
+  Lp(long n, int device);
+  ~Lp();
+  static size_t device_bytes(long n);
+  void set_stream(hipStream_t s);
+  void solve(const double* g, const double* a, const double* x, double b, double delta, double xl,
+             double xu, double* s, mgcg_lp_info* info, int mem);
+  long size() const { return n_; }
+
+ private:
+  static double key_ratio_host(unsigned long long k);
+  long n_;
+  int device_;
+  int nb_ = 0, nr_ = 0;
+  size_t bytes_ = 0;
+  hipStream_t stream_ = nullptr;  // the null stream unless set
+  void* arena_ = nullptr;
+  unsigned long long* key_ = nullptr;
+  double *cap_ = nullptr, *part_ = nullptr, *bins_ = nullptr, *red_ = nullptr, *tsum_ = nullptr,
+         *info_ = nullptr;
+  void* st_ = nullptr;
+  void* hst_ = nullptr;  // pinned host copy of the state and the info
+};
+
+int slp_decide(mgcg_slp_ctrl* c, double f0, double f1, double c0, double c1, double gts, double ats,
+               double s_inf, double* theta, double* a_red, double* p_red);
+
+}  // namespace mgcg

@@ -1,0 +1,547 @@
+// The LP subproblem of the SLP step (Sec. 4.1, problem (Pstar)) for one linear
+// constraint with a positive gradient (the volume):
+//     min g^T s  s.t.  a^T s = b,  l <= s <= u,
+//     l = max(-delta, x_l - x),  u = min(delta, x_u - x).
+// From s = l the variables are raised in order of the ratio r = -g / a
+// (highest first, equal ratios in index order), each to u, until the volume
+// budget B = b - a^T l is used; the variable that reaches it is raised
+// partially, and its ratio is the multiplier of the constraint.
+//
+// The order is never sorted.  The critical ratio is found by a radix select
+// over 64-bit keys that order the ratios from high to low: eight passes of
+// eight bits, each building per-block sums of the capacities a (u - l) per
+// key digit (a thread per digit walks the block's items in index order, so
+// the sums are fixed-order), reducing them in a fixed order and picking the
+// digit where the running capacity reaches the remaining budget.  Variables
+// above the critical key go to u, below to l; the tied group at the key shares
+// what is left of the budget in index order through a block-wise scan.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "lp.h"
+
+namespace mgcg {
+
+namespace {
+
+constexpr int LP_BS = 256;    // threads per block; also items per block
+constexpr int LP_ROWS = 64;   // partial-bin rows summed per block of the first reduction
+
+struct LpState {
+  unsigned long long prefix;  // key digits picked so far (high bits)
+  double remaining;           // budget still to place within the prefix's items
+  double budget, capsum;      // B (clamped to [0, capsum] when feasible) and the total capacity
+  int bad;                    // a non-positive or non-finite a, or non-finite g, x
+  int feasible;               // B within [0, capsum] up to the rounding of its sums
+};
+
+__device__ __forceinline__ unsigned long long ratio_key(double r) {
+  if (r == 0.0) r = 0.0;  // one key for +0 and -0
+  unsigned long long u = (unsigned long long)__double_as_longlong(r);
+  u = (u >> 63) ? ~u : (u | 0x8000000000000000ull);  // ascending with r
+  return ~u;                                         // ascending key = descending ratio
+}
+__device__ __forceinline__ double key_ratio(unsigned long long k) {
+  unsigned long long u = ~k;
+  u = (u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+  return __longlong_as_double((long long)u);
+}
+
+// Fixed-order sum of one value per thread (thread 0 gets it).
+__device__ __forceinline__ double block_sum_lp(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < LP_BS / 64; ++i) t += sh[i];
+  return t;
+}
+
+__global__ __launch_bounds__(LP_BS) void k_lp_prep(long n, const double* __restrict__ g,
+                                                   const double* __restrict__ a,
+                                                   const double* __restrict__ x, double delta,
+                                                   double xl, double xu,
+                                                   unsigned long long* __restrict__ key,
+                                                   double* __restrict__ cap,
+                                                   double* __restrict__ part, LpState* st) {
+  __shared__ double sh[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  double al = 0.0, c = 0.0, aal = 0.0;
+  if (i < n) {
+    const double gi = g[i], ai = a[i], xi = x[i];
+    const double l = fmax(-delta, xl - xi), u = fmin(delta, xu - xi);
+    const bool ok = ai > 0.0 && isfinite(ai) && isfinite(gi) && isfinite(xi) && l <= u;
+    if (!ok) st->bad = 1;
+    c = ok ? ai * (u - l) : 0.0;
+    al = ok ? ai * l : 0.0;
+    aal = fabs(al);
+    key[i] = ratio_key(ok ? -gi / ai : 0.0);
+    cap[i] = c;
+  }
+  const double s0 = block_sum_lp(al, sh);
+  const double s1 = block_sum_lp(c, sh);
+  const double s2 = block_sum_lp(aal, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s0;
+    part[gridDim.x + blockIdx.x] = s1;
+    part[2 * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// B = b - a^T l and the total capacity, summed in block order.  A budget
+// within the rounding allowance 2 n eps (sum |a l| + capacity) of 0 or of the
+// capacity is the boundary itself (clamped); beyond it the LP has no solution.
+__global__ __launch_bounds__(LP_BS) void k_lp_budget(long n, int nb, double b,
+                                                     const double* __restrict__ part, LpState* st) {
+  __shared__ double sh[LP_BS / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int j = threadIdx.x; j < nb; j += LP_BS) {
+    s0 += part[j];
+    s1 += part[nb + j];
+    s2 += part[2 * nb + j];
+  }
+  const double al = block_sum_lp(s0, sh);
+  const double cs = block_sum_lp(s1, sh);
+  const double aal = block_sum_lp(s2, sh);
+  if (threadIdx.x == 0) {
+    const double B = b - al;
+    const double tau = 2.0 * (double)n * 2.220446049250313e-16 * (aal + cs);
+    const int ok = B >= -tau && B <= cs + tau;
+    const double Bc = fmin(fmax(B, 0.0), cs);
+    st->budget = ok ? Bc : B;
+    st->capsum = cs;
+    st->remaining = Bc;
+    st->feasible = ok;
+    st->prefix = 0ull;
+  }
+}
+
+// Pass over digit d (bits 63 - 8d .. 56 - 8d): per block, the capacity sum of
+// the items whose higher digits equal the prefix, per value of digit d.
+__global__ __launch_bounds__(LP_BS) void k_lp_hist(long n, int d,
+                                                   const unsigned long long* __restrict__ key,
+                                                   const double* __restrict__ cap,
+                                                   const LpState* st, double* __restrict__ bins) {
+  __shared__ unsigned long long sk[LP_BS];
+  __shared__ double sc[LP_BS];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  const unsigned long long pre = st->prefix;
+  const int shift = 56 - 8 * d;
+  unsigned long long k = ~0ull;
+  double c = 0.0;
+  if (i < n) {
+    k = key[i];
+    c = cap[i];
+  }
+  // items outside the prefix get an impossible digit (256)
+  const bool match = i < n && (d == 0 || (k >> (shift + 8)) == (pre >> (shift + 8)));
+  sk[threadIdx.x] = match ? ((k >> shift) & 255ull) : 256ull;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  const unsigned long long mine = threadIdx.x;
+  double s = 0.0;
+  for (int j = 0; j < LP_BS; ++j) s += sk[j] == mine ? sc[j] : 0.0;
+  bins[(long)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// Rows [LP_ROWS j, LP_ROWS (j + 1)) of the per-block bins summed per digit.
+__global__ __launch_bounds__(LP_BS) void k_lp_reduce(int nb, const double* __restrict__ bins,
+                                                     double* __restrict__ out) {
+  const int r0 = blockIdx.x * LP_ROWS;
+  const int r1 = min(r0 + LP_ROWS, nb);
+  double s = 0.0;
+  for (int r = r0; r < r1; ++r) s += bins[(long)r * 256 + threadIdx.x];
+  out[(long)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// Digit d of the critical key: the first digit (ascending key, i.e. highest
+// ratios first) whose running capacity reaches the remaining budget.
+__global__ __launch_bounds__(LP_BS) void k_lp_pick(int nrows, int d, const double* __restrict__ part,
+                                                   LpState* st) {
+  __shared__ double tot[256];
+  double s = 0.0;
+  for (int r = 0; r < nrows; ++r) s += part[(long)r * 256 + threadIdx.x];
+  tot[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // the first digit with capacity whose running capacity reaches the
+    // remaining budget; if rounding leaves none, the last digit with
+    // capacity; with no capacity at all, digit 0
+    const double rem = st->remaining;
+    double before = 0.0, before_last = 0.0;
+    int pick = -1, last = -1;
+    for (int b = 0; b < 256; ++b) {
+      if (tot[b] > 0.0) {
+        if (pick < 0 && before + tot[b] >= rem) {
+          pick = b;
+          st->remaining = rem - before;
+        }
+        last = b;
+        before_last = before;
+      }
+      before += tot[b];
+    }
+    if (pick < 0) {
+      pick = last < 0 ? 0 : last;
+      st->remaining = last < 0 ? rem : rem - before_last;
+    }
+    st->prefix |= (unsigned long long)pick << (56 - 8 * d);
+  }
+}
+
+// Capacity of the tied items (key == the critical key) per block.
+__global__ __launch_bounds__(LP_BS) void k_lp_tiesum(long n, const unsigned long long* __restrict__ key,
+                                                     const double* __restrict__ cap,
+                                                     const LpState* st, double* __restrict__ tsum) {
+  __shared__ double sh[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  const unsigned long long T = st->prefix;
+  const double c = (i < n && key[i] == T) ? cap[i] : 0.0;
+  const double s = block_sum_lp(c, sh);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+
+// Exclusive scan of the per-block tied capacities (one block, in order).
+__global__ __launch_bounds__(LP_BS) void k_lp_tiescan(int nb, double* __restrict__ tsum) {
+  __shared__ double chunk[LP_BS];
+  const int per = (nb + LP_BS - 1) / LP_BS;
+  const int j0 = threadIdx.x * per, j1 = min(j0 + per, nb);
+  double s = 0.0;
+  for (int j = j0; j < j1; ++j) s += tsum[j];
+  chunk[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int t = 0; t < LP_BS; ++t) {
+      const double v = chunk[t];
+      chunk[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double run = chunk[threadIdx.x];
+  for (int j = j0; j < j1; ++j) {
+    const double v = tsum[j];
+    tsum[j] = run;
+    run += v;
+  }
+}
+
+// s from the critical key: u above it, l below it, the tied items in index
+// order up to the remaining budget; block partials of g^T s, a^T s, |s|_inf.
+__global__ __launch_bounds__(LP_BS) void k_lp_fill(long n, const double* __restrict__ g,
+                                                   const double* __restrict__ a,
+                                                   const double* __restrict__ x, double delta,
+                                                   double xl, double xu,
+                                                   const unsigned long long* __restrict__ key,
+                                                   const double* __restrict__ cap,
+                                                   const double* __restrict__ toff,
+                                                   const LpState* st, double* __restrict__ s,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[LP_BS / 64];
+  __shared__ double wsum[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  const unsigned long long T = st->prefix;
+  const double R = st->remaining;
+  double gi = 0.0, ai = 0.0, l = 0.0, u = 0.0, c = 0.0;
+  unsigned long long k = ~0ull;
+  if (i < n) {
+    gi = g[i];
+    ai = a[i];
+    const double xi = x[i];
+    l = fmax(-delta, xl - xi);
+    u = fmin(delta, xu - xi);
+    k = key[i];
+    c = cap[i];
+  }
+  // exclusive scan of the tied capacities in index order within the block
+  const double tc = (i < n && k == T) ? c : 0.0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double incl = tc;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  double before = toff[blockIdx.x];
+  for (int j = 0; j < w; ++j) before += wsum[j];
+  before += incl - tc;
+  double si = 0.0;
+  if (i < n) {
+    if (k < T) {
+      si = u;
+    } else if (k > T) {
+      si = l;
+    } else {
+      const double take = fmin(c, fmax(0.0, R - before));
+      si = take >= c ? u : l + take / ai;
+    }
+    s[i] = si;
+  }
+  const double p0 = block_sum_lp(gi * si, sh);
+  const double p1 = block_sum_lp(ai * si, sh);
+  double m = fabs(si);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  __syncthreads();
+  if (lane == 0) sh[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0;
+    for (int j = 0; j < LP_BS / 64; ++j) mm = fmax(mm, sh[j]);
+    part[blockIdx.x] = p0;
+    part[gridDim.x + blockIdx.x] = p1;
+    part[2 * gridDim.x + blockIdx.x] = mm;
+  }
+}
+
+// The shrunk box end of the artificial problem (Sec. 4.1.2): s = l' (upper
+// false) or u' (upper true) with the radius 0.8 delta.
+__global__ __launch_bounds__(LP_BS) void k_lp_box(long n, const double* __restrict__ g,
+                                                  const double* __restrict__ a,
+                                                  const double* __restrict__ x, double delta,
+                                                  double xl, double xu, int upper,
+                                                  double* __restrict__ s,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  double gi = 0.0, ai = 0.0, si = 0.0;
+  if (i < n) {
+    gi = g[i];
+    ai = a[i];
+    const double xi = x[i];
+    si = upper ? fmin(0.8 * delta, xu - xi) : fmax(-0.8 * delta, xl - xi);
+    s[i] = si;
+  }
+  const double p0 = block_sum_lp(gi * si, sh);
+  const double p1 = block_sum_lp(ai * si, sh);
+  double m = fabs(si);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0;
+    for (int j = 0; j < LP_BS / 64; ++j) mm = fmax(mm, sh[j]);
+    part[blockIdx.x] = p0;
+    part[gridDim.x + blockIdx.x] = p1;
+    part[2 * gridDim.x + blockIdx.x] = mm;
+  }
+}
+
+// g^T s, a^T s and |s|_inf from the block partials, in block order.
+__global__ __launch_bounds__(LP_BS) void k_lp_info(int nb, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[LP_BS / 64];
+  double s0 = 0.0, s1 = 0.0, m = 0.0;
+  for (int j = threadIdx.x; j < nb; j += LP_BS) {
+    s0 += part[j];
+    s1 += part[nb + j];
+    m = fmax(m, part[2 * nb + j]);
+  }
+  const double gts = block_sum_lp(s0, sh);
+  const double ats = block_sum_lp(s1, sh);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0;
+    for (int j = 0; j < LP_BS / 64; ++j) mm = fmax(mm, sh[j]);
+    out[0] = gts;
+    out[1] = ats;
+    out[2] = mm;
+  }
+}
+
+}  // namespace
+
+Lp::Lp(long n, int device) : n_(n), device_(device) {
+  if (n < 1 || n > (1L << 31)) throw Error(MGCG_EINVAL, "LP size must lie in 1..2^31");
+  nb_ = (int)((n + LP_BS - 1) / LP_BS);
+  nr_ = (nb_ + LP_ROWS - 1) / LP_ROWS;
+  MGCG_HIP(hipSetDevice(device_));
+  bytes_ = device_bytes(n);
+  if (hipMalloc(&arena_, bytes_) != hipSuccess) {
+    (void)hipGetLastError();
+    arena_ = nullptr;
+    throw Error(MGCG_ENOMEM, "LP scratch allocation failed");
+  }
+  char* p = (char*)arena_;
+  auto take = [&](size_t b) {
+    char* q = p;
+    p += (b + 255) / 256 * 256;
+    return (void*)q;
+  };
+  key_ = (unsigned long long*)take((size_t)n * 8);
+  cap_ = (double*)take((size_t)n * 8);
+  part_ = (double*)take((size_t)nb_ * 3 * 8);
+  bins_ = (double*)take((size_t)nb_ * 256 * 8);
+  red_ = (double*)take((size_t)nr_ * 256 * 8);
+  tsum_ = (double*)take((size_t)nb_ * 8);
+  info_ = (double*)take(4 * 8);
+  st_ = take(sizeof(LpState));
+  if (hipHostMalloc((void**)&hst_, 256, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(arena_);
+    arena_ = nullptr;
+    throw Error(MGCG_ENOMEM, "LP host buffer allocation failed");
+  }
+}
+
+size_t Lp::device_bytes(long n) {
+  const long nb = (n + LP_BS - 1) / LP_BS, nr = (nb + LP_ROWS - 1) / LP_ROWS;
+  auto r = [](size_t b) { return (b + 255) / 256 * 256; };
+  return r((size_t)n * 8) * 2 + r((size_t)nb * 24) + r((size_t)nb * 2048) + r((size_t)nr * 2048) +
+         r((size_t)nb * 8) + r(32) + r(sizeof(LpState));
+}
+
+Lp::~Lp() {
+  (void)hipSetDevice(device_);
+  (void)hipStreamSynchronize(stream_);
+  if (arena_) (void)hipFree(arena_);
+  if (hst_) (void)hipHostFree(hst_);
+}
+
+void Lp::set_stream(hipStream_t s) {
+  MGCG_HIP(hipSetDevice(device_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  stream_ = s;
+}
+
+void Lp::solve(const double* g, const double* a, const double* x, double b, double delta, double xl,
+               double xu, double* s, mgcg_lp_info* info, int mem) {
+  if (!g || !a || !x || !s) throw Error(MGCG_EINVAL, "null vector");
+  if (mem != MGCG_MEM_HOST && mem != MGCG_MEM_DEVICE) throw Error(MGCG_EINVAL, "bad mem flag");
+  if (!(delta > 0.0) || !std::isfinite(delta) || !std::isfinite(b) || !std::isfinite(xl) ||
+      !std::isfinite(xu) || !(xl <= xu))
+    throw Error(MGCG_EINVAL, "bad LP scalars (delta > 0, finite b, x_l <= x_u)");
+  MGCG_HIP(hipSetDevice(device_));
+  const double *dg = g, *da = a, *dx = x;
+  double* ds = s;
+  void* stage = nullptr;
+  struct Free {
+    void*& p;
+    ~Free() {
+      if (p) (void)hipFree(p);
+    }
+  } fr{stage};
+  if (mem == MGCG_MEM_HOST) {
+    if (hipMalloc(&stage, (size_t)n_ * 8 * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      stage = nullptr;
+      throw Error(MGCG_ENOMEM, "LP staging allocation failed");
+    }
+    double* base = (double*)stage;
+    MGCG_HIP(hipMemcpyAsync(base, g, (size_t)n_ * 8, hipMemcpyHostToDevice, stream_));
+    MGCG_HIP(hipMemcpyAsync(base + n_, a, (size_t)n_ * 8, hipMemcpyHostToDevice, stream_));
+    MGCG_HIP(hipMemcpyAsync(base + 2 * n_, x, (size_t)n_ * 8, hipMemcpyHostToDevice, stream_));
+    dg = base;
+    da = base + n_;
+    dx = base + 2 * n_;
+    ds = base + 3 * n_;
+  }
+  LpState* st = (LpState*)st_;
+  MGCG_HIP(hipMemsetAsync(st, 0, sizeof(LpState), stream_));
+  hipLaunchKernelGGL(k_lp_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
+                     key_, cap_, part_, st);
+  hipLaunchKernelGGL(k_lp_budget, dim3(1), dim3(LP_BS), 0, stream_, n_, nb_, b,
+                     (const double*)part_, st);
+  MGCG_HIP(hipGetLastError());
+  MGCG_HIP(hipMemcpyAsync(hst_, st, sizeof(LpState), hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  LpState h;
+  std::memcpy(&h, hst_, sizeof(LpState));
+  if (h.bad) throw Error(MGCG_EINVAL, "LP input with a non-positive constraint gradient or a non-finite value");
+  const bool feasible = h.feasible != 0;
+  if (feasible) {
+    for (int d = 0; d < 8; ++d) {
+      hipLaunchKernelGGL(k_lp_hist, dim3(nb_), dim3(LP_BS), 0, stream_, n_, d,
+                         (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
+                         bins_);
+      hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nb_,
+                         (const double*)bins_, red_);
+      hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_,
+                         st);
+    }
+    hipLaunchKernelGGL(k_lp_tiesum, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
+                       (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
+                       tsum_);
+    hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_);
+    hipLaunchKernelGGL(k_lp_fill, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
+                       (const unsigned long long*)key_, (const double*)cap_, (const double*)tsum_,
+                       (const LpState*)st, ds, part_);
+  } else {
+    hipLaunchKernelGGL(k_lp_box, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
+                       h.budget > h.capsum ? 1 : 0, ds, part_);
+  }
+  hipLaunchKernelGGL(k_lp_info, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, info_);
+  MGCG_HIP(hipGetLastError());
+  if (mem == MGCG_MEM_HOST)
+    MGCG_HIP(hipMemcpyAsync(s, ds, (size_t)n_ * 8, hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipMemcpyAsync(hst_, info_, 3 * 8, hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipMemcpyAsync((char*)hst_ + 64, st, sizeof(LpState), hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  if (info) {
+    double v[3];
+    std::memcpy(v, hst_, sizeof v);
+    LpState e;
+    std::memcpy(&e, (char*)hst_ + 64, sizeof e);
+    info->gts = v[0];
+    info->ats = v[1];
+    info->s_inf = v[2];
+    info->feasible = feasible ? 1 : 0;
+    info->budget = h.budget;
+    info->lambda = feasible ? key_ratio_host(e.prefix) : std::nan("");
+  }
+}
+
+double Lp::key_ratio_host(unsigned long long k) {
+  unsigned long long u = ~k;
+  u = (u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+  double r;
+  std::memcpy(&r, &u, 8);
+  return r;
+}
+
+// ---- step control of Algorithm 2 (host)
+
+int slp_decide(mgcg_slp_ctrl* c, double f0, double f1, double c0, double c1, double gts, double ats,
+               double s_inf, double* theta, double* a_red, double* p_red) {
+  // predicted reductions of the linear model: M(x, s) = (a^T s + c)^2 / 2
+  const double m0 = 0.5 * c0 * c0, m1 = 0.5 * (ats + c0) * (ats + c0);
+  const double p_fsb = m0 - m1, p_opt = gts;
+  // eqs. (theta1), (theta2)
+  const double large = (1.0 + c->N / std::pow((double)c->k + 1.0, 1.1)) * c->theta_min_hist;
+  const double sup = p_opt <= 0.5 * p_fsb ? 0.5 * p_fsb / (p_fsb - p_opt) : 1.0;
+  const double th = std::fmin(std::fmin(large, sup), c->theta_max);
+  const double ar = th * (f0 - f1) + (1.0 - th) * (0.5 * c0 * c0 - 0.5 * c1 * c1);
+  const double pr = -th * gts + (1.0 - th) * p_fsb;
+  if (theta) *theta = th;
+  if (a_red) *a_red = ar;
+  if (p_red) *p_red = pr;
+  if (ar < 0.1 * pr) {  // reject: shrink the trust region
+    c->delta = std::fmin(0.25 * s_inf, 0.1 * c->delta);
+    c->theta_max = th;
+    return 0;
+  }
+  if (ar >= 0.5 * pr) c->delta = std::fmin(2.0 * c->delta, c->box_inf);
+  c->delta = std::fmax(c->delta, c->delta_min);
+  c->theta_min_hist = std::fmin(c->theta_min_hist, th);
+  c->theta_max = 1.0;
+  c->k += 1;
+  return 1;
+}
+
+}  // namespace mgcg

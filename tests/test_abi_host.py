@@ -121,3 +121,42 @@ def test_projection_desc_validation():
     assert api.proj_device_bytes((1, 1, 1), 1, 1, float("nan")) == 0
     assert api.proj_device_bytes((1, 1, 1), 64, 64, 1.0) == 0  # 2 n d rmin > 4096
     assert api.proj_device_bytes((1 << 19, 1, 1), 4, 1, 1.0) == 0  # axis above 2^20 cells
+
+
+def test_slp_step_control_matches_oracle():
+    """mgcg_slp_decide (host) against the oracle's theta, merit and trust-region
+    rules of Algorithm 2 over a seeded sequence of trial steps."""
+    from paper_2311_05595_amd import api
+    from oracle import slp
+    _lib()
+    rng = np.random.default_rng(12)
+    ctrl = api.slp_ctrl(0.2, delta_min=1e-3, box_inf=1.0)
+    delta, tmax, hist, k = 0.2, 1.0, [1.0], 0
+    for _ in range(40):
+        n = 20
+        g = -rng.exponential(1.0, n)
+        a = rng.uniform(0.5, 1.5, n)
+        s = rng.uniform(-delta, delta, n)
+        f0 = rng.uniform(1.0, 2.0)
+        f1 = f0 - rng.uniform(-0.5, 1.0) * abs(g @ s)
+        c0, c1 = rng.normal(0, 0.01), rng.normal(0, 0.01)
+        gts, ats, sinf = float(g @ s), float(a @ s), float(np.abs(s).max())
+        acc, th, ar, pr = api.slp_decide(ctrl, f0, f1, c0, c1, gts, ats, sinf)
+        # oracle
+        _, _, pf, po = slp.merit_reductions(1.0, f0, f1, g, s, c0, c1, a)
+        th_o = slp.theta_update(k, hist, tmax, pf, po)
+        ar_o, pr_o, _, _ = slp.merit_reductions(th_o, f0, f1, g, s, c0, c1, a)
+        acc_o, delta_o = slp.trust_update(ar_o, pr_o, delta, sinf, 1.0, 1e-3)
+        assert th == pytest.approx(th_o, rel=1e-13) and acc == acc_o
+        assert ar == pytest.approx(ar_o, rel=1e-12, abs=1e-15)
+        assert pr == pytest.approx(pr_o, rel=1e-12, abs=1e-15)
+        assert ctrl.delta == pytest.approx(delta_o, rel=1e-14)
+        delta = delta_o
+        if acc_o:
+            hist.append(th_o)
+            tmax, k = 1.0, k + 1
+        else:
+            tmax = th_o
+        assert ctrl.k == k
+    assert api._abi.load().mgcg_lp_device_bytes(0) == 0
+    assert api._abi.load().mgcg_lp_device_bytes(524288) > 524288 * 16

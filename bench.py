@@ -17,6 +17,9 @@ transpose W^T g (Sec. 3.2 eq. (5), Sec. 3.4) on the 64x32x32 mesh with 4^3
 density and 2^3 design cells per element, rmin = 1.5, and prints its own
 JSON line (kernel rooflines and the oracle's single-entry evaluation timed
 on a sample).
+
+`--lp` times the SLP step's LP subproblem (Sec. 4.1) over the 524,288 design
+variables of that lattice and prints its own JSON line.
 """
 
 import argparse
@@ -516,6 +519,59 @@ def proj_cpu_baseline(x, pr, budget_s=10.0):
                       f"in {dt:.1f} s on 1 host thread, scaled to all {pr.nrho} cells"}
 
 
+def run_lp(args):
+    import torch
+    from paper_2311_05595_amd import api
+
+    n = 64 * 32 * 32 * 8  # the design lattice of the 64x32x32 mesh, 2^3 cells per element
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0.0, 1.0, n)
+    g = -rng.exponential(1.0, n)
+    a = rng.uniform(0.5, 1.5, n) / 8.0
+    delta = 0.05
+    l, u = np.maximum(-delta, -x), np.minimum(delta, 1.0 - x)
+    b = float(a @ l + 0.4 * (a @ (u - l)))
+    dev = torch.device("cuda:0")
+    gd, ad, xd = (torch.tensor(v, device=dev) for v in (g, a, x))
+    sd = torch.empty(n, dtype=torch.float64, device=dev)
+    lp = api.LP(n)
+    for _ in range(args.warmup):
+        lp.solve(gd, ad, xd, b, delta, out=sd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, info = lp.solve(gd, ad, xd, b, delta, out=sd)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    nbytes = 8.0 * 4 * n  # g, a, x read, s written
+    out = {
+        "metric": "SLP LP subproblem solves/s (volume constraint, trust region)",
+        "value": round(1.0 / t, 1), "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"LP step over {n} design variables (64x32x32 elements, 2^3 "
+                               f"design cells each), delta={delta}", "feasible": info["feasible"]},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 5),
+                     "traffic": None, "avg_us": round(t * 1e6, 1), "alg_bytes_per_launch": nbytes,
+                     "note": "whole call: 30 kernel launches (8 radix passes of 3) and two "
+                             "host reads of the budget and the result"},
+    }
+    if not args.no_cpu:
+        from oracle import slp
+        t1 = time.perf_counter()
+        slp.lp_step(g, a, x, b, delta)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 4), "unit": "solves/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the oracle's LP step on the same {n} variables, "
+                                         f"once ({dt:.2f} s, 1 host thread)"}
+    lp.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -530,6 +586,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--projection", action="store_true",
                     help="time the design-variable projection and its transpose")
+    ap.add_argument("--lp", action="store_true", help="time the SLP step's LP subproblem")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
     ap.add_argument("--session-solves", type=int, default=5, help="c5: solves per session")
     ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second")
@@ -538,6 +595,12 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.lp:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        run_lp(args)
         return
     if args.projection:
         if args.gpus != 1:

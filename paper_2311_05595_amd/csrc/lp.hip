@@ -145,6 +145,7 @@ __global__ __launch_bounds__(LP_BS) void k_lp_hist(long n, int d,
   __syncthreads();
   const unsigned long long mine = threadIdx.x;
   double s = 0.0;
+#pragma unroll 16
   for (int j = 0; j < LP_BS; ++j) s += sk[j] == mine ? sc[j] : 0.0;
   bins[(long)blockIdx.x * 256 + threadIdx.x] = s;
 }
@@ -155,7 +156,14 @@ __global__ __launch_bounds__(LP_BS) void k_lp_reduce(int nb, const double* __res
   const int r0 = blockIdx.x * LP_ROWS;
   const int r1 = min(r0 + LP_ROWS, nb);
   double s = 0.0;
-  for (int r = r0; r < r1; ++r) s += bins[(long)r * 256 + threadIdx.x];
+  // loads of 16 rows in flight, summed in row order
+  for (int r = r0; r < r1; r += 16) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = r + q < r1 ? bins[(long)(r + q) * 256 + threadIdx.x] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += v[q];
+  }
   out[(long)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
@@ -163,33 +171,55 @@ __global__ __launch_bounds__(LP_BS) void k_lp_reduce(int nb, const double* __res
 // ratios first) whose running capacity reaches the remaining budget.
 __global__ __launch_bounds__(LP_BS) void k_lp_pick(int nrows, int d, const double* __restrict__ part,
                                                    LpState* st) {
-  __shared__ double tot[256];
-  double s = 0.0;
-  for (int r = 0; r < nrows; ++r) s += part[(long)r * 256 + threadIdx.x];
-  tot[threadIdx.x] = s;
+  __shared__ double wtot[LP_BS / 64];
+  __shared__ int first[LP_BS / 64], lastb[LP_BS / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // this digit's capacity, the rows summed in order with their loads in flight
+  double tot = 0.0;
+  for (int r = 0; r < nrows; r += 16) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = r + q < nrows ? part[(long)(r + q) * 256 + t] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tot += v[q];
+  }
+  // running capacity before this digit (ascending digits): a scan within the
+  // wave, then the totals of the waves before it
+  double incl = tot;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wtot[w] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // the first digit with capacity whose running capacity reaches the
-    // remaining budget; if rounding leaves none, the last digit with
-    // capacity; with no capacity at all, digit 0
-    const double rem = st->remaining;
-    double before = 0.0, before_last = 0.0;
-    int pick = -1, last = -1;
-    for (int b = 0; b < 256; ++b) {
-      if (tot[b] > 0.0) {
-        if (pick < 0 && before + tot[b] >= rem) {
-          pick = b;
-          st->remaining = rem - before;
-        }
-        last = b;
-        before_last = before;
-      }
-      before += tot[b];
-    }
-    if (pick < 0) {
-      pick = last < 0 ? 0 : last;
-      st->remaining = last < 0 ? rem : rem - before_last;
-    }
+  double before = incl - tot;
+  for (int j = 0; j < w; ++j) before += wtot[j];
+  const double rem = st->remaining;
+  // the first digit with capacity whose running capacity reaches rem, and the
+  // last digit with capacity (the fallback when rounding leaves none)
+  const bool hit = tot > 0.0 && before + tot >= rem;
+  int f = hit ? t : 1 << 30, l = tot > 0.0 ? t : -1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    f = min(f, __shfl_down(f, off, 64));
+    l = max(l, __shfl_down(l, off, 64));
+  }
+  if (lane == 0) {
+    first[w] = f;
+    lastb[w] = l;
+  }
+  __syncthreads();
+  int pick = 1 << 30, last = -1;
+  for (int j = 0; j < LP_BS / 64; ++j) {
+    pick = min(pick, first[j]);
+    last = max(last, lastb[j]);
+  }
+  const bool fallback = pick == (1 << 30);
+  if (fallback) pick = last < 0 ? 0 : last;
+  __syncthreads();
+  if (t == pick) {
+    st->remaining = (fallback && last < 0) ? rem : rem - before;
     st->prefix |= (unsigned long long)pick << (56 - 8 * d);
   }
 }

@@ -305,7 +305,8 @@ int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x
  * f0 = f(x), f1 = f(x + s), c0 = c(x), c1 = c(x + s) (the constraint's value),
  * gts = g^T s, ats = a^T s, s_inf = |s|_inf.  Computes theta_k =
  * min(theta_large, theta_sup, theta_max) (eqs. (theta1), (theta2), with
- * P_fsb = M(x, 0) - M(x, s), M = (a^T s + c)^2 / 2, and P_opt = g^T s), the
+ * P_fsb = M(x, 0) - M(x, s), M = (a^T s + c)^2 / 2, and P_opt = -g^T s, the
+ * predicted reduction of f), the
  * actual and predicted reductions of psi = theta f + (1 - theta) |c|^2 / 2,
  * and rejects (A_red < 0.1 P_red: delta = min(0.25 s_inf, 0.1 delta),
  * theta_max = theta_k) or accepts (delta doubled up to box_inf when A_red >=

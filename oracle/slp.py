@@ -30,7 +30,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * Step control of Algorithm 2: the predicted and actual reductions of the
   merit function psi = theta f + (1 - theta) phi, phi = |c|^2 / 2, the penalty
   parameter update (eqs. (theta1), (theta2)) and the trust-region radius
-  update, in the order of the algorithm.
+  update, in the order of the algorithm.  Reading: P_red^opt is the predicted
+  reduction of f, -g^T s (printed without the minus sign), so that
+  P_red = theta P_red^opt + (1 - theta) P_red^fsb as printed, and theta_sup
+  is the largest theta with P_red >= P_red^fsb / 2.
 
 Pins (tests/test_oracle_slp.py): the LP optimum against an enumeration of all
 vertices of the feasible polytope on tiny instances and against scipy's
@@ -101,7 +104,9 @@ def merit_reductions(theta, f0, f1, g, s, c0, c1, a):
     gs = float(np.dot(g, s))
     a_red = theta * (f0 - f1) + (1.0 - theta) * (phi0 - phi1)
     p_fsb = m0 - m1
-    p_opt = gs
+    # the predicted reduction of f (printed as g^T s without the sign; with the
+    # sign, P_red = theta P_opt + (1 - theta) P_fsb as printed for P_red)
+    p_opt = -gs
     p_red = -theta * gs + (1.0 - theta) * p_fsb
     return a_red, p_red, p_fsb, p_opt
 

@@ -551,7 +551,9 @@ int slp_decide(mgcg_slp_ctrl* c, double f0, double f1, double c0, double c1, dou
                double s_inf, double* theta, double* a_red, double* p_red) {
   // predicted reductions of the linear model: M(x, s) = (a^T s + c)^2 / 2
   const double m0 = 0.5 * c0 * c0, m1 = 0.5 * (ats + c0) * (ats + c0);
-  const double p_fsb = m0 - m1, p_opt = gts;
+  // P_opt is the predicted reduction of f, -g^T s (P_red = theta P_opt +
+  // (1 - theta) P_fsb)
+  const double p_fsb = m0 - m1, p_opt = -gts;
   // eqs. (theta1), (theta2)
   const double large = (1.0 + c->N / std::pow((double)c->k + 1.0, 1.1)) * c->theta_min_hist;
   const double sup = p_opt <= 0.5 * p_fsb ? 0.5 * p_fsb / (p_fsb - p_opt) : 1.0;

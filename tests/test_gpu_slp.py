@@ -107,3 +107,84 @@ def test_lp_full_size_device_memory():
     assert np.array_equal(s_d.cpu().numpy(), s_h)
     assert info_d == info_h
     lp.close()
+
+
+def test_slp_iterations_match_oracle():
+    """Three iterations of Algorithm 2 on a small multiresolution cantilever
+    (6x4x4 elements, 2^3 densities and one design variable per element,
+    rmin = 1.1, V_max = 0.3 of the volume): projection, solve, compliance and
+    gradient, the chain rule W^T, the LP step, the trial solve and the
+    accept/reject decision, all through the library, against the same
+    iterations composed from the oracle.  The designs agree to the solves'
+    accuracy (rtol 1e-11)."""
+    need_gpu()
+    import torch
+    import workloads as W
+    from oracle import fem, projection as P, solve
+    from paper_2311_05595_amd import api
+    nel, n, d, rmin = (6, 4, 4), 2, 1, 1.1
+    mask, f = W.make_problem("cantilever", *nel, 1, 1)
+    prob = api.Problem(nel, mask, f, nsub=n, nlevels=2)
+    pr = api.Projection(nel, n, d, rmin)
+    lp = api.LP(pr.nx)
+    rng = np.random.default_rng(5)
+    x0 = rng.uniform(0.2, 0.4, pr.nx)
+    vmax = 0.3 * np.prod(nel)
+    v = np.full(pr.nrho, 1.0 / n ** 3)
+    a = pr.apply_transpose(v)                      # volume gradient W^T v
+    Wm = P.projection_matrix(nel, n, d, rmin)
+    a_o = Wm.T @ v
+    Ks = fem.sub_element_matrices(1, n)
+    mat = dict(E0=1.0, Emin=1e-9, penal=3.0)
+
+    def gpu_eval(x):
+        prob.set_densities(pr.apply(x))
+        prob.solve(rtol=1e-11, maxit=2000, warm_start=False)
+        c, dc = prob.compliance_sensitivity()
+        return c[-1], pr.apply_transpose(dc)
+
+    def oracle_eval(x):
+        rho = (Wm @ x).reshape(P.lattice_shape(nel, n))
+        _, _, c, dc = solve.solve_problem(rho, mask, f, nel, 1, n, Ks, **mat)
+        return c.sum(), Wm.T @ dc
+
+    assert np.abs(a - a_o).max() <= 1e-13 * np.abs(a_o).max()
+    xg, xo = x0.copy(), x0.copy()
+    ctrl = api.slp_ctrl(0.1, delta_min=1e-3, box_inf=1.0)
+    delta, tmax, hist, k = 0.1, 1.0, [1.0], 0
+    fg, gg = gpu_eval(xg)
+    fo, go = oracle_eval(xo)
+    for it in range(3):
+        assert abs(fg - fo) <= 1e-9 * fo
+        # LP step at the current design
+        cg = float(a @ xg) - vmax
+        sg, info = lp.solve(gg, a, xg, -cg, ctrl.delta)
+        co = float(a_o @ xo) - vmax
+        so, lam_o, ok_o = slp.lp_step(go, a_o, xo, -co, delta)
+        assert info["feasible"] == ok_o
+        assert np.abs(sg - so).max() <= 1e-7 * delta
+        # trial point and decision
+        fg1, gg1 = gpu_eval(xg + sg)
+        fo1, go1 = oracle_eval(xo + so)
+        acc, th, ar, pr_ = api.slp_decide(ctrl, fg, fg1, cg, float(a @ (xg + sg)) - vmax,
+                                          info["gts"], info["ats"], info["s_inf"])
+        _, _, pf, po = slp.merit_reductions(1.0, fo, fo1, go, so, co,
+                                            float(a_o @ (xo + so)) - vmax, a_o)
+        th_o = slp.theta_update(k, hist, tmax, pf, po)
+        ar_o, pr_o, _, _ = slp.merit_reductions(th_o, fo, fo1, go, so, co,
+                                                float(a_o @ (xo + so)) - vmax, a_o)
+        acc_o, delta = slp.trust_update(ar_o, pr_o, delta, float(np.abs(so).max()), 1.0, 1e-3)
+        assert acc == acc_o and th == pytest.approx(th_o, rel=1e-6)
+        assert ctrl.delta == pytest.approx(delta, rel=1e-6)
+        if acc_o:
+            xg, fg, gg = xg + sg, fg1, gg1
+            xo, fo, go = xo + so, fo1, go1
+            hist.append(th_o)
+            tmax, k = 1.0, k + 1
+        else:
+            tmax = th_o
+        assert np.abs(xg - xo).max() <= 1e-7
+    assert k >= 1  # at least one step was taken
+    lp.close()
+    pr.close()
+    prob.close()

@@ -122,4 +122,9 @@ def test_merit_reductions_identities():
     ar, pr, pf, po = slp.merit_reductions(0.3, 2.0, 1.5, g, s, 0.0, 0.0, a)
     assert ar == pytest.approx(0.3 * 0.5)
     assert pr == pytest.approx(-0.3 * (g @ s) - 0.7 * 0.5 * (a @ s) ** 2)
-    assert pf == pytest.approx(-0.5 * (a @ s) ** 2) and po == pytest.approx(g @ s)
+    assert pf == pytest.approx(-0.5 * (a @ s) ** 2) and po == pytest.approx(-(g @ s))
+    # theta_sup is the largest theta with P_red >= P_fsb / 2
+    for pf_, po_ in [(2.0, 0.5), (1.0, -3.0), (0.5, 0.1)]:
+        th = slp.theta_update(0, [1.0], 1.0, pf_, po_)
+        if th < 1.0:
+            assert th * po_ + (1 - th) * pf_ == pytest.approx(0.5 * pf_)

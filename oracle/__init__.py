@@ -29,7 +29,10 @@ What it computes (the plain definitions, in FP64):
                the chain rule of Sec. 3.4;
 * ``slp``      the SLP step of Sec. 4: the LP subproblem with the volume
                constraint and the trust region (a fractional knapsack), the
-               artificial problem, and the step control of Algorithm 2.
+               artificial problem, and the step control of Algorithm 2;
+* ``threshold`` the density thresholding of Sec. 5: rounding, the
+               density-value strategy, the angle condition and the Heaviside
+               projection with its volume-preserving threshold.
 
 Parity status of every function is listed in its module docstring.
 """

@@ -20,6 +20,11 @@ on a sample).
 
 `--lp` times the SLP step's LP subproblem (Sec. 4.1) over the 524,288 design
 variables of that lattice and prints its own JSON line.
+
+`--threshold` times the density thresholding of Sec. 5 on the 4,194,304
+densities of that lattice: the rule based on the density values (the
+printed line), the Heaviside projection with Newton's volume-preserving
+threshold and the angle condition's cosine (in `config`).
 """
 
 import argparse
@@ -572,6 +577,69 @@ def run_lp(args):
     print(json.dumps(out), flush=True)
 
 
+def run_threshold(args):
+    import torch
+    from paper_2311_05595_amd import api
+
+    n = 64 * 32 * 32 * 64  # the density lattice of the 64x32x32 mesh, 4^3 sub-elements each
+    rng = np.random.default_rng(31)
+    rho = np.clip(rng.beta(0.7, 1.2, n), 0.0, 1.0)
+    vfrac, beta = 0.3, 8.0
+    dev = torch.device("cuda:0")
+    rd = torch.tensor(rho, device=dev)
+    od = torch.empty(n, dtype=torch.float64, device=dev)
+    lp = api.LP(n)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            r = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, r
+
+    t_sel, _ = timed(lambda: lp.density_threshold(rd, vfrac, out=od))
+    t_hv, (_, eta, iters) = timed(lambda: lp.heaviside(rd, beta, out=od))
+    t_cos, _ = timed(lambda: lp.angle_cos(rd, od))
+    nbytes = 16.0 * n  # the densities read and the 0/1 design written
+    out = {
+        "metric": "density thresholdings/s (top-k rule of the density values)",
+        "value": round(1.0 / t_sel, 1), "unit": "thresholdings/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_sel * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"thresholding of {n} densities (64x32x32 elements, 4^3 "
+                               f"sub-elements each), v_frac={vfrac}",
+                   "heaviside_ms": round(t_hv * 1e3, 4), "heaviside_beta": beta,
+                   "heaviside_eta": eta, "heaviside_newton_iters": iters,
+                   "angle_cos_ms": round(t_cos * 1e3, 4)},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / t_sel / 1e9, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(nbytes / t_sel / 1e9 / PEAK_HBM_GBS, 5), "traffic": None,
+                     "avg_us": round(t_sel * 1e6, 1), "alg_bytes_per_launch": nbytes,
+                     "note": "whole call: 29 kernel launches (8 radix passes of 3) and one "
+                             "host read of the selection state"},
+    }
+    if not args.no_cpu:
+        from oracle import threshold
+        t1 = time.perf_counter()
+        threshold.density_threshold(rho, vfrac)
+        dt = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        threshold.heaviside(rho, beta, threshold.eta_newton(rho, beta))
+        dt2 = time.perf_counter() - t2
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 4), "unit": "thresholdings/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's density-value rule on the same {n} "
+                                         f"densities, once ({dt:.2f} s, 1 host thread); its "
+                                         f"Heaviside projection with Newton's eta {dt2:.2f} s"}
+    lp.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -587,6 +655,8 @@ def main():
     ap.add_argument("--projection", action="store_true",
                     help="time the design-variable projection and its transpose")
     ap.add_argument("--lp", action="store_true", help="time the SLP step's LP subproblem")
+    ap.add_argument("--threshold", action="store_true",
+                    help="time the density thresholding and the Heaviside projection")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
     ap.add_argument("--session-solves", type=int, default=5, help="c5: solves per session")
     ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second")
@@ -595,6 +665,12 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.threshold:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        run_threshold(args)
         return
     if args.lp:
         if args.gpus != 1:

@@ -301,6 +301,39 @@ int mgcg_lp_set_stream(mgcg_lp* lp, void* stream);
 int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x, double b,
                   double delta, double x_l, double x_u, double* s, mgcg_lp_info* info, int mem);
 
+/* Density thresholding of Sec. 5, on the scratch of an LP object of n values
+ * (same mem, stream and synchronisation rules as mgcg_lp_solve; each call
+ * returns when its results are written).
+ *
+ * mgcg_lp_select_top (the strategy based on the density values, Sec. 5.1):
+ * out_i = 1 for the k largest v_i, equal values taken in increasing index
+ * order, and 0 for the rest (k = floor(v_frac n) for a volume fraction
+ * v_frac).  MGCG_EINVAL for k outside 0..n or a non-finite v_i.
+ *
+ * mgcg_threshold_round (Sec. 5, before either strategy): out_i = 1 where
+ * rho_i >= hi, 0 where rho_i <= lo, rho_i otherwise (0.95 and 0.05 in the
+ * paper).  out may equal rho.
+ *
+ * mgcg_angle_cos (the angle condition of Sec. 5.2): *cosine =
+ * -gL^T d / (|gL| |d|), NaN when either vector is zero; the condition holds
+ * when it exceeds cos(theta_max), theta_max = 89.9 degrees.
+ *
+ * mgcg_heaviside (Sec. 5.4): out_i = h(rho_i, beta, eta) =
+ * (tanh(beta eta) + tanh(beta (rho_i - eta))) / (tanh(beta eta) +
+ * tanh(beta (1 - eta))) with eta the zero of f(eta) = sum h - sum rho (cells of
+ * equal volume), found by Newton's method from eta = 1/2 that keeps the
+ * bracket of f's sign change and bisects when a step leaves it; stops at
+ * |delta eta| <= 1e-14 or |f| <= 1e-13 sum rho, at most 100 iterations (each
+ * one reduction pass and one read-back).  *eta and *iters (may be NULL) get
+ * the threshold and the iteration count.  MGCG_EINVAL for beta not positive
+ * and finite. */
+int mgcg_lp_select_top(mgcg_lp* lp, const double* v, int64_t k, double* out, int mem);
+int mgcg_threshold_round(mgcg_lp* lp, const double* rho, double lo, double hi, double* out,
+                         int mem);
+int mgcg_angle_cos(mgcg_lp* lp, const double* gL, const double* d, double* cosine, int mem);
+int mgcg_heaviside(mgcg_lp* lp, const double* rho, double beta, double* out, double* eta,
+                   int32_t* iters, int mem);
+
 /* Step control of Algorithm 2 (host only).  After a trial step s of the LP:
  * f0 = f(x), f1 = f(x + s), c0 = c(x), c1 = c(x + s) (the constraint's value),
  * gts = g^T s, ats = a^T s, s_inf = |s|_inf.  Computes theta_k =

@@ -6,6 +6,7 @@ current torch stream.
 """
 
 import ctypes as C
+import math
 
 import numpy as np
 
@@ -378,31 +379,80 @@ class LP:
         except Exception:
             pass
 
-    def solve(self, g, a, x, b, delta, x_l=0.0, x_u=1.0, out=None):
-        pg, mem, kg = _ptr(g)
-        pa, _, ka = _ptr(a)
-        px, _, kx = _ptr(x)
-        for k in (kg, ka, kx):
-            if (k.numel() if mem == MGCG_MEM_DEVICE else k.size) != self.n:
+    def _vectors(self, *vs):
+        """Pointers of equal-length vectors, their memory kind, keep-alives."""
+        ps, keep = [], []
+        mem = None
+        for v in vs:
+            p, m, k = _ptr(v)
+            if mem is not None and m != mem:
+                raise ValueError("mixed host and device vectors")
+            mem = m
+            if (k.numel() if m == MGCG_MEM_DEVICE else k.size) != self.n:
                 raise ValueError("vector length does not match the LP size")
+            ps.append(p)
+            keep.append(k)
         if mem == MGCG_MEM_DEVICE:
             torch = _torch()
             cur = torch.cuda.current_stream().cuda_stream
             if cur != getattr(self, "_stream", 0):
                 check(self._lib.mgcg_lp_set_stream(self._h, C.c_void_p(cur)))
                 self._stream = cur
+        return ps, mem, keep
+
+    def _out(self, out, mem, like):
+        if mem == MGCG_MEM_DEVICE:
+            torch = _torch()
             if out is None:
-                out = torch.empty(self.n, dtype=torch.float64, device=kg.device)
-            ps = C.c_void_p(out.data_ptr())
-        else:
-            out = np.empty(self.n) if out is None else out
-            ps = C.c_void_p(out.ctypes.data)
+                out = torch.empty(self.n, dtype=torch.float64, device=like.device)
+            return out, C.c_void_p(out.data_ptr())
+        out = np.empty(self.n) if out is None else out
+        return out, C.c_void_p(out.ctypes.data)
+
+    def solve(self, g, a, x, b, delta, x_l=0.0, x_u=1.0, out=None):
+        (pg, pa, px), mem, keep = self._vectors(g, a, x)
+        out, ps = self._out(out, mem, keep[0])
         info = _abi.mgcg_lp_info()
         check(self._lib.mgcg_lp_solve(self._h, pg, pa, px, float(b), float(delta), float(x_l),
                                       float(x_u), ps, C.byref(info), mem))
         return out, {"lambda": info.lambda_, "gts": info.gts, "ats": info.ats,
                      "s_inf": info.s_inf, "budget": info.budget,
                      "feasible": bool(info.feasible)}
+
+    def select_top(self, v, k, out=None):
+        """1 for the k largest values (equal values in index order), 0 else."""
+        (pv,), mem, keep = self._vectors(v)
+        out, po = self._out(out, mem, keep[0])
+        check(self._lib.mgcg_lp_select_top(self._h, pv, int(k), po, mem))
+        return out
+
+    def density_threshold(self, rho, vfrac, out=None):
+        """The strategy based on the density values (Sec. 5.1): the
+        floor(vfrac n) highest densities to 1, the rest to 0."""
+        return self.select_top(rho, int(math.floor(vfrac * self.n)), out)
+
+    def pre_round(self, rho, lo=0.05, hi=0.95, out=None):
+        (pr,), mem, keep = self._vectors(rho)
+        out, po = self._out(out, mem, keep[0])
+        check(self._lib.mgcg_threshold_round(self._h, pr, float(lo), float(hi), po, mem))
+        return out
+
+    def angle_cos(self, gL, d):
+        """-gL^T d / (|gL| |d|) (the angle condition of Sec. 5.2)."""
+        (pg, pd), mem, _ = self._vectors(gL, d)
+        c = C.c_double()
+        check(self._lib.mgcg_angle_cos(self._h, pg, pd, C.byref(c), mem))
+        return c.value
+
+    def heaviside(self, rho, beta, out=None):
+        """Smooth Heaviside projection with the volume-preserving threshold
+        (Sec. 5.4); returns (h, eta, Newton iterations)."""
+        (pr,), mem, keep = self._vectors(rho)
+        out, po = self._out(out, mem, keep[0])
+        eta, it = C.c_double(), C.c_int32()
+        check(self._lib.mgcg_heaviside(self._h, pr, float(beta), po, C.byref(eta), C.byref(it),
+                                       mem))
+        return out, eta.value, it.value
 
 
 def slp_ctrl(delta0, delta_min=1e-3, box_inf=1.0, N=1e6):

@@ -395,6 +395,44 @@ int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x
   })
 }
 
+int mgcg_lp_select_top(mgcg_lp* lp, const double* v, int64_t k, double* out, int mem) {
+  NEED(lp);
+  GUARD({
+    lp->impl->select_top(v, (long)k, out, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_threshold_round(mgcg_lp* lp, const double* rho, double lo, double hi, double* out,
+                         int mem) {
+  NEED(lp);
+  GUARD({
+    lp->impl->round_bounds(rho, lo, hi, out, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_angle_cos(mgcg_lp* lp, const double* gL, const double* d, double* cosine, int mem) {
+  NEED(lp);
+  NEED(cosine);
+  GUARD({
+    *cosine = lp->impl->angle_cos(gL, d, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_heaviside(mgcg_lp* lp, const double* rho, double beta, double* out, double* eta,
+                   int32_t* iters, int mem) {
+  NEED(lp);
+  GUARD({
+    int it = 0;
+    const double e = lp->impl->heaviside(rho, beta, out, mem, &it);
+    if (eta) *eta = e;
+    if (iters) *iters = it;
+    return MGCG_OK;
+  })
+}
+
 int mgcg_slp_decide(mgcg_slp_ctrl* ctrl, double f0, double f1, double c0, double c1, double gts,
                     double ats, double s_inf, double* theta, double* a_red, double* p_red) {
   NEED(ctrl);

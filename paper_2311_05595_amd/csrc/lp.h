@@ -16,8 +16,15 @@ class Lp {
   void solve(const double* g, const double* a, const double* x, double b, double delta, double xl,
              double xu, double* s, mgcg_lp_info* info, int mem);
   long size() const { return n_; }
+  // thresholding of Sec. 5 on n values
+  void select_top(const double* v, long k, double* out, int mem);
+  void round_bounds(const double* r, double lo, double hi, double* out, int mem);
+  double angle_cos(const double* gl, const double* d, int mem);
+  double heaviside(const double* r, double beta, double* out, int mem, int* iters);
 
  private:
+  void stage_io(int mem, int nin, const double* const* in, const double** din, double* out,
+                double** dout, void** stage);
   static double key_ratio_host(unsigned long long k);
   long n_;
   int device_;

@@ -395,6 +395,138 @@ __global__ __launch_bounds__(LP_BS) void k_lp_info(int nb, const double* __restr
   }
 }
 
+// ---- thresholding of Sec. 5 on the same scratch
+
+// Keys of the values (descending) with unit capacities: the radix select then
+// picks the k-th largest value, equal values in index order.
+__global__ __launch_bounds__(LP_BS) void k_sel_prep(long n, const double* __restrict__ v,
+                                                    unsigned long long* __restrict__ key,
+                                                    double* __restrict__ cap, LpState* st) {
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  if (i < n) {
+    const double vi = v[i];
+    if (!isfinite(vi)) st->bad = 1;
+    key[i] = ratio_key(isfinite(vi) ? vi : 0.0);
+    cap[i] = 1.0;
+  }
+}
+__global__ void k_sel_budget(double k, LpState* st) {
+  if (threadIdx.x == 0) {
+    st->remaining = k;
+    st->budget = k;
+    st->prefix = 0ull;
+    st->feasible = 1;
+  }
+}
+// 1 for the k largest values (keys below the critical key, and the first
+// ones of the tied group in index order), 0 for the rest.
+__global__ __launch_bounds__(LP_BS) void k_sel_fill(long n, const unsigned long long* __restrict__ key,
+                                                    const double* __restrict__ toff,
+                                                    const LpState* st, double* __restrict__ out) {
+  __shared__ double wsum[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  const unsigned long long T = st->prefix;
+  const double R = st->remaining;
+  const unsigned long long k = i < n ? key[i] : ~0ull;
+  const double tc = (i < n && k == T) ? 1.0 : 0.0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double incl = tc;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double o = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += o;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  double before = toff[blockIdx.x];
+  for (int j = 0; j < w; ++j) before += wsum[j];
+  before += incl - tc;
+  if (i < n) out[i] = k < T ? 1.0 : (k > T ? 0.0 : (R - before >= 1.0 ? 1.0 : 0.0));
+}
+
+// Rounding of the densities very close to 0 or 1.
+// (out may be r: each item is read, then written, by one thread)
+__global__ __launch_bounds__(LP_BS) void k_round(long n, const double* r, double lo, double hi,
+                                                 double* out) {
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  if (i < n) {
+    const double v = r[i];
+    out[i] = v >= hi ? 1.0 : (v <= lo ? 0.0 : v);
+  }
+}
+
+// Block partials of three sums: a^T b, a^T a, b^T b.
+__global__ __launch_bounds__(LP_BS) void k_dot3(long n, const double* __restrict__ a,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ part) {
+  __shared__ double sh[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  const double x = i < n ? a[i] : 0.0, y = i < n ? b[i] : 0.0;
+  const double s0 = block_sum_lp(x * y, sh);
+  const double s1 = block_sum_lp(x * x, sh);
+  const double s2 = block_sum_lp(y * y, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s0;
+    part[gridDim.x + blockIdx.x] = s1;
+    part[2 * gridDim.x + blockIdx.x] = s2;
+  }
+}
+// The three sums from the block partials, in block order.
+__global__ __launch_bounds__(LP_BS) void k_sum3(int nb, const double* __restrict__ part,
+                                                double* __restrict__ out) {
+  __shared__ double sh[LP_BS / 64];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < nb; j += LP_BS)
+    for (int q = 0; q < 3; ++q) s[q] += part[q * nb + j];
+  for (int q = 0; q < 3; ++q) {
+    const double t = block_sum_lp(s[q], sh);
+    if (threadIdx.x == 0) out[q] = t;
+  }
+}
+
+// Smooth Heaviside projection (Sec. 5.4):
+//   h = (tanh(beta eta) + tanh(beta (rho - eta))) / (tanh(beta eta) + tanh(beta (1 - eta)))
+// and its derivative in eta; per block the partial sums of h, dh/deta and rho
+// (Newton's method on the volume runs on the host).
+__device__ __forceinline__ void heaviside_at(double r, double beta, double eta, double te,
+                                             double t1, double& h, double& dh) {
+  const double tr = tanh(beta * (r - eta));
+  const double num = te + tr, den = te + t1;
+  const double dnum = beta * (1.0 - te * te) - beta * (1.0 - tr * tr);
+  const double dden = beta * (1.0 - te * te) - beta * (1.0 - t1 * t1);
+  h = num / den;
+  dh = (dnum * den - num * dden) / (den * den);
+}
+__global__ __launch_bounds__(LP_BS) void k_hv_sums(long n, const double* __restrict__ r, double beta,
+                                                   double eta, double* __restrict__ part) {
+  __shared__ double sh[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  const double te = tanh(beta * eta), t1 = tanh(beta * (1.0 - eta));
+  double h = 0.0, dh = 0.0, ri = 0.0;
+  if (i < n) {
+    ri = r[i];
+    heaviside_at(ri, beta, eta, te, t1, h, dh);
+  }
+  const double s0 = block_sum_lp(h, sh);
+  const double s1 = block_sum_lp(dh, sh);
+  const double s2 = block_sum_lp(ri, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s0;
+    part[gridDim.x + blockIdx.x] = s1;
+    part[2 * gridDim.x + blockIdx.x] = s2;
+  }
+}
+__global__ __launch_bounds__(LP_BS) void k_hv_apply(long n, const double* __restrict__ r, double beta,
+                                                    double eta, double* __restrict__ out) {
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  if (i < n) {
+    const double te = tanh(beta * eta), t1 = tanh(beta * (1.0 - eta));
+    double h, dh;
+    heaviside_at(r[i], beta, eta, te, t1, h, dh);
+    out[i] = h;
+  }
+}
+
 }  // namespace
 
 Lp::Lp(long n, int device) : n_(n), device_(device) {
@@ -543,6 +675,153 @@ double Lp::key_ratio_host(unsigned long long k) {
   double r;
   std::memcpy(&r, &u, 8);
   return r;
+}
+
+
+// ---- thresholding (Sec. 5) on the same scratch
+
+namespace {
+struct Staged {
+  void* p = nullptr;
+  ~Staged() {
+    if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+// Device copies of host inputs (count vectors of n) and a device output.
+void Lp::stage_io(int mem, int nin, const double* const* in, const double** din, double* out,
+                  double** dout, void** stage) {
+  if (mem != MGCG_MEM_HOST && mem != MGCG_MEM_DEVICE) throw Error(MGCG_EINVAL, "bad mem flag");
+  for (int q = 0; q < nin; ++q)
+    if (!in[q]) throw Error(MGCG_EINVAL, "null vector");
+  if (mem == MGCG_MEM_DEVICE) {
+    for (int q = 0; q < nin; ++q) din[q] = in[q];
+    if (dout) *dout = out;
+    return;
+  }
+  if (hipMalloc(stage, (size_t)n_ * 8 * (nin + 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    *stage = nullptr;
+    throw Error(MGCG_ENOMEM, "staging allocation failed");
+  }
+  double* base = (double*)*stage;
+  for (int q = 0; q < nin; ++q) {
+    MGCG_HIP(hipMemcpyAsync(base + q * n_, in[q], (size_t)n_ * 8, hipMemcpyHostToDevice, stream_));
+    din[q] = base + q * n_;
+  }
+  if (dout) *dout = base + nin * n_;
+}
+
+void Lp::select_top(const double* v, long k, double* out, int mem) {
+  if (!out) throw Error(MGCG_EINVAL, "null vector");
+  if (k < 0 || k > n_) throw Error(MGCG_EINVAL, "k outside 0..n");
+  MGCG_HIP(hipSetDevice(device_));
+  Staged sg;
+  const double* din[1];
+  double* dout = nullptr;
+  const double* in[1] = {v};
+  stage_io(mem, 1, in, din, out, &dout, &sg.p);
+  LpState* st = (LpState*)st_;
+  MGCG_HIP(hipMemsetAsync(st, 0, sizeof(LpState), stream_));
+  hipLaunchKernelGGL(k_sel_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], key_, cap_, st);
+  hipLaunchKernelGGL(k_sel_budget, dim3(1), dim3(64), 0, stream_, (double)k, st);
+  for (int d = 0; d < 8; ++d) {
+    hipLaunchKernelGGL(k_lp_hist, dim3(nb_), dim3(LP_BS), 0, stream_, n_, d,
+                       (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
+                       bins_);
+    hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nb_, (const double*)bins_,
+                       red_);
+    hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_, st);
+  }
+  hipLaunchKernelGGL(k_lp_tiesum, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
+                     (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st, tsum_);
+  hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_);
+  hipLaunchKernelGGL(k_sel_fill, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
+                     (const unsigned long long*)key_, (const double*)tsum_, (const LpState*)st, dout);
+  MGCG_HIP(hipGetLastError());
+  MGCG_HIP(hipMemcpyAsync(hst_, st, sizeof(LpState), hipMemcpyDeviceToHost, stream_));
+  if (mem == MGCG_MEM_HOST)
+    MGCG_HIP(hipMemcpyAsync(out, dout, (size_t)n_ * 8, hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  LpState h;
+  std::memcpy(&h, hst_, sizeof h);
+  if (h.bad) throw Error(MGCG_EINVAL, "non-finite value");
+}
+
+void Lp::round_bounds(const double* r, double lo, double hi, double* out, int mem) {
+  if (!out) throw Error(MGCG_EINVAL, "null vector");
+  MGCG_HIP(hipSetDevice(device_));
+  Staged sg;
+  const double* din[1];
+  double* dout = nullptr;
+  const double* in[1] = {r};
+  stage_io(mem, 1, in, din, out, &dout, &sg.p);
+  hipLaunchKernelGGL(k_round, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], lo, hi, dout);
+  MGCG_HIP(hipGetLastError());
+  if (mem == MGCG_MEM_HOST)
+    MGCG_HIP(hipMemcpyAsync(out, dout, (size_t)n_ * 8, hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+}
+
+double Lp::angle_cos(const double* gl, const double* d, int mem) {
+  MGCG_HIP(hipSetDevice(device_));
+  Staged sg;
+  const double* din[2];
+  const double* in[2] = {gl, d};
+  stage_io(mem, 2, in, din, nullptr, nullptr, &sg.p);
+  hipLaunchKernelGGL(k_dot3, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], din[1], part_);
+  hipLaunchKernelGGL(k_sum3, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, info_);
+  MGCG_HIP(hipGetLastError());
+  MGCG_HIP(hipMemcpyAsync(hst_, info_, 24, hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  double v[3];
+  std::memcpy(v, hst_, sizeof v);
+  return -v[0] / (std::sqrt(v[1]) * std::sqrt(v[2]));
+}
+
+double Lp::heaviside(const double* r, double beta, double* out, int mem, int* iters) {
+  if (!out) throw Error(MGCG_EINVAL, "null vector");
+  if (!(beta > 0.0) || !std::isfinite(beta)) throw Error(MGCG_EINVAL, "beta must be positive");
+  MGCG_HIP(hipSetDevice(device_));
+  Staged sg;
+  const double* din[1];
+  double* dout = nullptr;
+  const double* in[1] = {r};
+  stage_io(mem, 1, in, din, out, &dout, &sg.p);
+  // Newton's method on f(eta) = sum h - sum rho from eta = 1/2 with the
+  // bracket of the sign change (f(0) > 0 > f(1)); the midpoint when a step
+  // leaves the bracket; stop at |delta eta| <= 1e-14 or |f| <= 1e-13 sum rho
+  double lo = 0.0, hi = 1.0, eta = 0.5;
+  int it = 0;
+  for (; it < 100; ++it) {
+    hipLaunchKernelGGL(k_hv_sums, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], beta, eta,
+                       part_);
+    hipLaunchKernelGGL(k_sum3, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, info_);
+    MGCG_HIP(hipGetLastError());
+    MGCG_HIP(hipMemcpyAsync(hst_, info_, 24, hipMemcpyDeviceToHost, stream_));
+    MGCG_HIP(hipStreamSynchronize(stream_));
+    double v[3];
+    std::memcpy(v, hst_, sizeof v);
+    const double f = v[0] - v[2];
+    if (std::fabs(f) <= 1e-13 * v[2]) break;
+    if (f > 0.0)
+      lo = eta;
+    else
+      hi = eta;
+    double nxt = v[1] != 0.0 ? eta - f / v[1] : 0.5 * (lo + hi);
+    if (!(lo < nxt && nxt < hi)) nxt = 0.5 * (lo + hi);
+    const bool done = std::fabs(nxt - eta) <= 1e-14;
+    eta = nxt;
+    if (done) break;
+  }
+  hipLaunchKernelGGL(k_hv_apply, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], beta, eta, dout);
+  MGCG_HIP(hipGetLastError());
+  if (mem == MGCG_MEM_HOST)
+    MGCG_HIP(hipMemcpyAsync(out, dout, (size_t)n_ * 8, hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  if (iters) *iters = it;
+  return eta;
 }
 
 // ---- step control of Algorithm 2 (host)

@@ -24,7 +24,8 @@ variables of that lattice and prints its own JSON line.
 `--threshold` times the density thresholding of Sec. 5 on the 4,194,304
 densities of that lattice: the rule based on the density values (the
 printed line), the Heaviside projection with Newton's volume-preserving
-threshold and the angle condition's cosine (in `config`).
+threshold, the angle condition's cosine and the strategy based on the
+gradient of the Lagrangian (in `config`).
 """
 
 import argparse
@@ -603,6 +604,10 @@ def run_threshold(args):
     t_sel, _ = timed(lambda: lp.density_threshold(rd, vfrac, out=od))
     t_hv, (_, eta, iters) = timed(lambda: lp.heaviside(rd, beta, out=od))
     t_cos, _ = timed(lambda: lp.angle_cos(rd, od))
+    gl = rng.standard_normal(n) * np.exp(2.0 * rng.standard_normal(n))
+    rr = np.where(rho >= 0.95, 1.0, np.where(rho <= 0.05, 0.0, rho))
+    rrd, gld = torch.tensor(rr, device=dev), torch.tensor(gl, device=dev)
+    t_lg, (_, alpha_t) = timed(lambda: lp.lagrangian_threshold(rrd, gld, out=od))
     nbytes = 16.0 * n  # the densities read and the 0/1 design written
     out = {
         "metric": "density thresholdings/s (top-k rule of the density values)",
@@ -615,7 +620,8 @@ def run_threshold(args):
                                f"sub-elements each), v_frac={vfrac}",
                    "heaviside_ms": round(t_hv * 1e3, 4), "heaviside_beta": beta,
                    "heaviside_eta": eta, "heaviside_newton_iters": iters,
-                   "angle_cos_ms": round(t_cos * 1e3, 4)},
+                   "angle_cos_ms": round(t_cos * 1e3, 4),
+                   "lagrangian_ms": round(t_lg * 1e3, 4), "lagrangian_alpha": alpha_t},
         "roofline": {"bound": "hbm", "achieved": round(nbytes / t_sel / 1e9, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(nbytes / t_sel / 1e9 / PEAK_HBM_GBS, 5), "traffic": None,

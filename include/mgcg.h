@@ -327,6 +327,21 @@ int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x
  * one reduction pass and one read-back).  *eta and *iters (may be NULL) get
  * the threshold and the iteration count.  MGCG_EINVAL for beta not positive
  * and finite. */
+/* mgcg_threshold_lagrangian (the strategy based on the gradient of the
+ * Lagrangian, Sec. 5.2), on densities rho already rounded near 0 and 1 and
+ * gL = grad L with respect to them: alpha_i is the step at which
+ * rho_i - alpha gL_i reaches 0 (gL_i > 0) or 1 (gL_i < 0), infinite for
+ * gL_i = 0.  *alpha gets alpha~, the largest alpha_i > 0 such that no density
+ * with alpha_j <= alpha_i breaks a safeguard (reaching 1 needs rho_j >= v_u,
+ * reaching 0 needs rho_j <= v_l; 0.3 and 0.7 in the paper) and the angle
+ * condition holds for d = rho~ - rho at theta_max_deg (89.9); 0 when there is
+ * none.  out_i = 0 or 1 (its bound) where alpha_i <= alpha~, else
+ * rho_i - alpha~ gL_i, within [0, 1]; out = rho when alpha~ = 0.  The cosine
+ * is nonincreasing in alpha; the admissible interval is searched over the
+ * bits of alpha in 16 device passes.  MGCG_EINVAL for non-finite inputs. */
+int mgcg_threshold_lagrangian(mgcg_lp* lp, const double* rho, const double* gL, double v_u,
+                              double v_l, double theta_max_deg, double* out, double* alpha,
+                              int mem);
 int mgcg_lp_select_top(mgcg_lp* lp, const double* v, int64_t k, double* out, int mem);
 int mgcg_threshold_round(mgcg_lp* lp, const double* rho, double lo, double hi, double* out,
                          int mem);

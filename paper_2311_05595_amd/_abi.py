@@ -112,6 +112,9 @@ EXPORTS = {
     "mgcg_lp_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                 C.c_double, C.c_double, C.c_double, C.c_void_p,
                                 C.POINTER(mgcg_lp_info), C.c_int]),
+    "mgcg_threshold_lagrangian": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                            C.c_double, C.c_double, C.c_void_p,
+                                            C.POINTER(C.c_double), C.c_int]),
     "mgcg_lp_select_top": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int]),
     "mgcg_threshold_round": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                        C.c_void_p, C.c_int]),

@@ -444,6 +444,16 @@ class LP:
         check(self._lib.mgcg_angle_cos(self._h, pg, pd, C.byref(c), mem))
         return c.value
 
+    def lagrangian_threshold(self, rho, gL, v_u=0.3, v_l=0.7, theta_max_deg=89.9, out=None):
+        """The strategy based on the gradient of the Lagrangian (Sec. 5.2) on
+        pre-rounded densities; returns (rho~, alpha~)."""
+        (pr, pg), mem, keep = self._vectors(rho, gL)
+        out, po = self._out(out, mem, keep[0])
+        a = C.c_double()
+        check(self._lib.mgcg_threshold_lagrangian(self._h, pr, pg, float(v_u), float(v_l),
+                                                  float(theta_max_deg), po, C.byref(a), mem))
+        return out, a.value
+
     def heaviside(self, rho, beta, out=None):
         """Smooth Heaviside projection with the volume-preserving threshold
         (Sec. 5.4); returns (h, eta, Newton iterations)."""

@@ -1,5 +1,6 @@
 // extern "C" boundary: argument checks, exception-to-status translation and
 // the thread-local error message.
+#include <cmath>
 #include <cstring>
 #include <string>
 
@@ -391,6 +392,18 @@ int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x
   NEED(lp);
   GUARD({
     lp->impl->solve(g, a, x, b, delta, x_l, x_u, s, info, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_threshold_lagrangian(mgcg_lp* lp, const double* rho, const double* gL, double v_u,
+                              double v_l, double theta_max_deg, double* out, double* alpha,
+                              int mem) {
+  NEED(lp);
+  GUARD({
+    const double cmax = std::cos(theta_max_deg * (M_PI / 180.0));
+    const double a = lp->impl->lagrangian(rho, gL, v_u, v_l, cmax, out, mem);
+    if (alpha) *alpha = a;
     return MGCG_OK;
   })
 }

@@ -21,14 +21,19 @@ class Lp {
   void round_bounds(const double* r, double lo, double hi, double* out, int mem);
   double angle_cos(const double* gl, const double* d, int mem);
   double heaviside(const double* r, double beta, double* out, int mem, int* iters);
+  double lagrangian(const double* rho, const double* gl, double vu, double vl, double cmax,
+                    double* out, int mem);
 
  private:
   void stage_io(int mem, int nin, const double* const* in, const double** din, double* out,
                 double** dout, void** stage);
   static double key_ratio_host(unsigned long long k);
+  static void hist_shape(int nb, int* ch, int* nh);
   long n_;
   int device_;
-  int nb_ = 0, nr_ = 0;
+  int nb_ = 0, nr_ = 0;  // blocks of LP_BS items; rows of the first bin reduction
+  int ch_ = 1, nh_ = 0;  // chunks per block and blocks of the digit passes
+  int ns_ = 0;           // blocks of the grid-stride sums
   size_t bytes_ = 0;
   hipStream_t stream_ = nullptr;  // the null stream unless set
   void* arena_ = nullptr;

@@ -27,6 +27,8 @@ namespace {
 
 constexpr int LP_BS = 256;    // threads per block; also items per block
 constexpr int LP_ROWS = 64;   // partial-bin rows summed per block of the first reduction
+constexpr int LP_SUM_BLOCKS = 1024;
+constexpr int LP_CH = 8;             // most chunks of LP_BS items per block of the digit passes  // blocks of the grid-stride sums of the thresholding
 
 struct LpState {
   unsigned long long prefix;  // key digits picked so far (high bits)
@@ -121,33 +123,124 @@ __global__ __launch_bounds__(LP_BS) void k_lp_budget(long n, int nb, double b,
   }
 }
 
-// Pass over digit d (bits 63 - 8d .. 56 - 8d): per block, the capacity sum of
-// the items whose higher digits equal the prefix, per value of digit d.
-__global__ __launch_bounds__(LP_BS) void k_lp_hist(long n, int d,
+// Pass over digit d (bits 63 - 8d .. 56 - 8d): per block of ch (<= LP_CH)
+// consecutive chunks of LP_BS items, the capacity sum of the items whose
+// higher digits equal the prefix, per value of digit d, in a fixed order.
+// The keys (and capacities) of all chunks are loaded first.  Each chunk is then
+// sorted by digit in LDS, stably: the lanes of a wave with the same digit come
+// from eight ballots of the digit's bits, their rank is the count of such
+// lanes below, and a block-wide scan of the per-wave counts gives each digit's
+// first slot.  A segmented scan within each wave sums the runs of equal digits;
+// thread t adds the (at most four) wave pieces of digit t's run, chunk after
+// chunk.  UNIT: every capacity is 1 (not read).
+template <bool UNIT>
+__global__ __launch_bounds__(LP_BS) void k_lp_hist(long n, int d, int ch,
                                                    const unsigned long long* __restrict__ key,
                                                    const double* __restrict__ cap,
                                                    const LpState* st, double* __restrict__ bins) {
-  __shared__ unsigned long long sk[LP_BS];
-  __shared__ double sc[LP_BS];
-  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  static_assert(LP_BS == 256, "one thread per digit value");
+  __shared__ int pos[LP_BS / 64][256];  // per wave: count of each digit, then its first slot
+  __shared__ int wtot[LP_BS / 64];
+  __shared__ int first_s[256];          // first slot of each digit
+  __shared__ int sdig[LP_BS];           // digit of each slot
+  __shared__ double sval[LP_BS];        // capacity of each slot, then the run's running sum
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const unsigned long long pre = st->prefix;
   const int shift = 56 - 8 * d;
-  unsigned long long k = ~0ull;
-  double c = 0.0;
-  if (i < n) {
-    k = key[i];
-    c = cap[i];
+  const unsigned long long lower = (1ull << lane) - 1ull;
+  const long base = (long)blockIdx.x * ch * LP_BS + t;
+  unsigned long long kk[LP_CH];
+  bool mm[LP_CH];
+  double cc[LP_CH];
+#pragma unroll
+  for (int c = 0; c < LP_CH; ++c) {
+    const long i = base + (long)c * LP_BS;
+    kk[c] = (c < ch && i < n) ? key[i] : 0ull;
   }
-  // items outside the prefix get an impossible digit (256)
-  const bool match = i < n && (d == 0 || (k >> (shift + 8)) == (pre >> (shift + 8)));
-  sk[threadIdx.x] = match ? ((k >> shift) & 255ull) : 256ull;
-  sc[threadIdx.x] = c;
-  __syncthreads();
-  const unsigned long long mine = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < LP_CH; ++c) {
+    const long i = base + (long)c * LP_BS;
+    mm[c] = c < ch && i < n && (d == 0 || (kk[c] >> (shift + 8)) == (pre >> (shift + 8)));
+    cc[c] = UNIT ? 1.0 : (mm[c] ? cap[i] : 0.0);
+  }
   double s = 0.0;
-#pragma unroll 16
-  for (int j = 0; j < LP_BS; ++j) s += sk[j] == mine ? sc[j] : 0.0;
-  bins[(long)blockIdx.x * 256 + threadIdx.x] = s;
+#pragma unroll
+  for (int c = 0; c < LP_CH; ++c) {
+    if (c >= ch) break;
+    const bool match = mm[c];
+    const int dig = (int)((kk[c] >> shift) & 255ull);
+#pragma unroll
+    for (int q = 0; q < LP_BS / 64; ++q) pos[q][t] = 0;
+    unsigned long long same = __ballot(match);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const int on = (dig >> bit) & 1;
+      const unsigned long long m = __ballot(on);
+      same &= on ? m : ~m;
+    }
+    const int rank = __popcll(same & lower);
+    __syncthreads();
+    if (match && rank == 0) pos[w][dig] = __popcll(same);
+    __syncthreads();
+    int cnt[LP_BS / 64], tot = 0;
+#pragma unroll
+    for (int q = 0; q < LP_BS / 64; ++q) {
+      cnt[q] = pos[q][t];
+      tot += cnt[q];
+    }
+    int incl = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int first = incl - tot, total = 0;
+#pragma unroll
+    for (int q = 0; q < LP_BS / 64; ++q) {
+      if (q < w) first += wtot[q];
+      total += wtot[q];
+    }
+    first_s[t] = first;
+    int run = first;
+#pragma unroll
+    for (int q = 0; q < LP_BS / 64; ++q) {
+      pos[q][t] = run;
+      run += cnt[q];
+    }
+    __syncthreads();
+    if (match) {
+      const int slot = pos[w][dig] + rank;
+      sval[slot] = cc[c];
+      sdig[slot] = dig;
+    }
+    __syncthreads();
+    // segmented inclusive scan of the slots within each wave (runs of one digit)
+    double v = 0.0;
+    int seg0 = 64;
+    if (t < total) {
+      v = sval[t];
+      const int f = first_s[sdig[t]] - 64 * w;
+      seg0 = f > 0 ? f : 0;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double o = __shfl_up(v, off, 64);
+      if (lane - off >= seg0) v += o;
+    }
+    sval[t] = v;
+    __syncthreads();
+    if (tot > 0) {
+      const int end = first + tot;
+      for (int q = first >> 6; q <= (end - 1) >> 6; ++q) {
+        const int last = end < 64 * q + 64 ? end : 64 * q + 64;
+        s += sval[last - 1];
+      }
+    }
+    __syncthreads();
+  }
+  bins[(long)blockIdx.x * 256 + t] = s;
 }
 
 // Rows [LP_ROWS j, LP_ROWS (j + 1)) of the per-block bins summed per digit.
@@ -236,29 +329,59 @@ __global__ __launch_bounds__(LP_BS) void k_lp_tiesum(long n, const unsigned long
   if (threadIdx.x == 0) tsum[blockIdx.x] = s;
 }
 
-// Exclusive scan of the per-block tied capacities (one block, in order).
+// Exclusive scan of the per-block tied capacities (one block, in order): tiles
+// of LP_BS * 8 entries staged in LDS with coalesced loads, each thread's eight
+// consecutive entries summed, a block scan of those sums, the tile's total
+// carried to the next tile.
 __global__ __launch_bounds__(LP_BS) void k_lp_tiescan(int nb, double* __restrict__ tsum) {
-  __shared__ double chunk[LP_BS];
-  const int per = (nb + LP_BS - 1) / LP_BS;
-  const int j0 = threadIdx.x * per, j1 = min(j0 + per, nb);
-  double s = 0.0;
-  for (int j = j0; j < j1; ++j) s += tsum[j];
-  chunk[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    for (int t = 0; t < LP_BS; ++t) {
-      const double v = chunk[t];
-      chunk[t] = run;
-      run += v;
+  constexpr int PER = 8, TILE = LP_BS * PER;
+  __shared__ double tile[TILE];
+  __shared__ double wt[LP_BS / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  double carry = 0.0;
+  for (int base = 0; base < nb; base += TILE) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = base + q * LP_BS + t;
+      tile[q * LP_BS + t] = j < nb ? tsum[j] : 0.0;
     }
-  }
-  __syncthreads();
-  double run = chunk[threadIdx.x];
-  for (int j = j0; j < j1; ++j) {
-    const double v = tsum[j];
-    tsum[j] = run;
-    run += v;
+    __syncthreads();
+    double v[PER], sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      v[q] = tile[t * PER + q];
+      sum += v[q];
+    }
+    double incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    if (lane == 63) wt[w] = incl;
+    __syncthreads();
+    double pre = carry, tile_total = 0.0;
+#pragma unroll
+    for (int q = 0; q < LP_BS / 64; ++q) {
+      if (q < w) pre += wt[q];
+      tile_total += wt[q];
+    }
+    pre += excl;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      tile[t * PER + q] = pre;
+      pre += v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = base + q * LP_BS + t;
+      if (j < nb) tsum[j] = tile[q * LP_BS + t];
+    }
+    carry += tile_total;
+    __syncthreads();
   }
 }
 
@@ -455,16 +578,23 @@ __global__ __launch_bounds__(LP_BS) void k_round(long n, const double* r, double
   }
 }
 
-// Block partials of three sums: a^T b, a^T a, b^T b.
+// Block partials of three sums: a^T b, a^T a, b^T b (grid-stride: each thread
+// adds its items in a fixed order).
 __global__ __launch_bounds__(LP_BS) void k_dot3(long n, const double* __restrict__ a,
                                                 const double* __restrict__ b,
                                                 double* __restrict__ part) {
   __shared__ double sh[LP_BS / 64];
-  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
-  const double x = i < n ? a[i] : 0.0, y = i < n ? b[i] : 0.0;
-  const double s0 = block_sum_lp(x * y, sh);
-  const double s1 = block_sum_lp(x * x, sh);
-  const double s2 = block_sum_lp(y * y, sh);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const long stride = (long)gridDim.x * LP_BS;
+  for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
+    const double x = a[i], y = b[i];
+    s0 += x * y;
+    s1 += x * x;
+    s2 += y * y;
+  }
+  s0 = block_sum_lp(s0, sh);
+  s1 = block_sum_lp(s1, sh);
+  s2 = block_sum_lp(s2, sh);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s0;
     part[gridDim.x + blockIdx.x] = s1;
@@ -500,16 +630,20 @@ __device__ __forceinline__ void heaviside_at(double r, double beta, double eta, 
 __global__ __launch_bounds__(LP_BS) void k_hv_sums(long n, const double* __restrict__ r, double beta,
                                                    double eta, double* __restrict__ part) {
   __shared__ double sh[LP_BS / 64];
-  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
   const double te = tanh(beta * eta), t1 = tanh(beta * (1.0 - eta));
-  double h = 0.0, dh = 0.0, ri = 0.0;
-  if (i < n) {
-    ri = r[i];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const long stride = (long)gridDim.x * LP_BS;
+  for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
+    const double ri = r[i];
+    double h, dh;
     heaviside_at(ri, beta, eta, te, t1, h, dh);
+    s0 += h;
+    s1 += dh;
+    s2 += ri;
   }
-  const double s0 = block_sum_lp(h, sh);
-  const double s1 = block_sum_lp(dh, sh);
-  const double s2 = block_sum_lp(ri, sh);
+  s0 = block_sum_lp(s0, sh);
+  s1 = block_sum_lp(s1, sh);
+  s2 = block_sum_lp(s2, sh);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s0;
     part[gridDim.x + blockIdx.x] = s1;
@@ -527,12 +661,242 @@ __global__ __launch_bounds__(LP_BS) void k_hv_apply(long n, const double* __rest
   }
 }
 
+
+// ---- the strategy based on the gradient of the Lagrangian (Sec. 5.2)
+//
+// alpha_i: the step at which rho_i - alpha g_i reaches 0 (g_i > 0) or 1
+// (g_i < 0); inf for g_i = 0.  With m_i = min(alpha, alpha_i) the step's
+// cosine with -g is sum g^2 m / (|g| sqrt(sum g^2 m^2)), nonincreasing in
+// alpha, so the admissible steps form an interval: the largest alpha (as a
+// double) below the first safeguard violation whose cosine passes is found
+// by a 16-way search over the bits of alpha (16 passes of two sums at 15
+// points each), and alpha~ is the largest alpha_i > 0 up to it.
+
+struct LgState {
+  unsigned long long lo, hi;  // search bracket (bits of non-negative doubles): lo passes, hi not
+  double viol;                // smallest alpha_i of a density the safeguards forbid to round
+  double wsum;                // |g|^2
+  double amax;                // largest finite alpha_i
+  double alpha;               // alpha~
+};
+static_assert(sizeof(LgState) <= 256, "the state shares the LP state's slot");
+constexpr int LG_PTS = 15;    // interior points of the search per pass
+
+__device__ __forceinline__ double lg_alpha(double r, double g) {
+  return g > 0.0 ? r / g : (g < 0.0 ? (1.0 - r) / -g : INFINITY);
+}
+
+__device__ __forceinline__ double block_min_lp(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = INFINITY;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < LP_BS / 64; ++i) t = fmin(t, sh[i]);
+  return t;
+}
+__device__ __forceinline__ double block_max_lp(double v, double* sh) {
+  return -block_min_lp(-v, sh);
+}
+
+// alpha, g^2 and block partials of the violation minimum, |g|^2 and max alpha.
+__global__ __launch_bounds__(LP_BS) void k_lg_prep(long n, const double* __restrict__ rho,
+                                                   const double* __restrict__ g, double vu,
+                                                   double vl, double* __restrict__ alpha,
+                                                   double* __restrict__ w,
+                                                   double* __restrict__ part, LpState* st) {
+  __shared__ double sh[LP_BS / 64];
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  double vmin = INFINITY, ws = 0.0, am = 0.0;
+  if (i < n) {
+    const double r = rho[i], gi = g[i];
+    if (!isfinite(r) || !isfinite(gi)) st->bad = 1;
+    const double a = lg_alpha(r, gi);
+    alpha[i] = a;
+    w[i] = gi * gi;
+    ws = gi * gi;
+    if ((gi < 0.0 && r < vu) || (gi > 0.0 && r > vl)) vmin = a;
+    if (isfinite(a)) am = a;
+  }
+  vmin = block_min_lp(vmin, sh);
+  ws = block_sum_lp(ws, sh);
+  am = block_max_lp(am, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = vmin;
+    part[gridDim.x + blockIdx.x] = ws;
+    part[2 * gridDim.x + blockIdx.x] = am;
+  }
+}
+
+__global__ __launch_bounds__(LP_BS) void k_lg_init(int nb, const double* __restrict__ part,
+                                                   LgState* st) {
+  __shared__ double sh[LP_BS / 64];
+  double vmin = INFINITY, ws = 0.0, am = 0.0;
+  for (int j = threadIdx.x; j < nb; j += LP_BS) {
+    vmin = fmin(vmin, part[j]);
+    ws += part[nb + j];
+    am = fmax(am, part[2 * nb + j]);
+  }
+  vmin = block_min_lp(vmin, sh);
+  ws = block_sum_lp(ws, sh);
+  am = block_max_lp(am, sh);
+  if (threadIdx.x == 0) {
+    st->viol = vmin;
+    st->wsum = ws;
+    st->amax = am;
+    st->alpha = 0.0;
+    st->lo = 0ull;
+    // every alpha_i beyond amax gives the cosine at amax: search [0, nextafter(amax))
+    const double cap = fmin(vmin, nextafter(am, INFINITY));
+    st->hi = am > 0.0 ? (unsigned long long)__double_as_longlong(cap) : 0ull;
+  }
+}
+
+__device__ __forceinline__ double lg_point(unsigned long long lo, unsigned long long hi, int p) {
+  const unsigned long long d = hi - lo;
+  const unsigned long long x = lo + (d >> 4) * (unsigned long long)p + (((d & 15ull) * p) >> 4);
+  return __longlong_as_double((long long)x);
+}
+
+// Block partials of sum g^2 m and sum g^2 m^2 at the LG_PTS interior points.
+__global__ __launch_bounds__(LP_BS) void k_lg_split(long n, const double* __restrict__ alpha,
+                                                    const double* __restrict__ w,
+                                                    const LgState* st, double* __restrict__ part) {
+  __shared__ double sh[LP_BS / 64][2 * LG_PTS];
+  const unsigned long long lo = st->lo, hi = st->hi;
+  double x[LG_PTS], s1[LG_PTS], s2[LG_PTS];
+#pragma unroll
+  for (int p = 0; p < LG_PTS; ++p) {
+    x[p] = lg_point(lo, hi, p + 1);
+    s1[p] = 0.0;
+    s2[p] = 0.0;
+  }
+  const long stride = (long)gridDim.x * LP_BS;
+  if (hi - lo > 1ull) {
+    for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
+      const double a = alpha[i], wi = w[i];
+#pragma unroll
+      for (int p = 0; p < LG_PTS; ++p) {
+        const double m = fmin(x[p], a);
+        const double wm = wi * m;
+        s1[p] += wm;
+        s2[p] += wm * m;
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < LG_PTS; ++p) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1[p] += __shfl_down(s1[p], off, 64);
+      s2[p] += __shfl_down(s2[p], off, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < LG_PTS; ++p) {
+      sh[wv][p] = s1[p];
+      sh[wv][LG_PTS + p] = s2[p];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * LG_PTS) {
+    double t = 0.0;
+    for (int q = 0; q < LP_BS / 64; ++q) t += sh[q][threadIdx.x];
+    part[(long)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// The two sums at each point (8 threads per sum, strided, then combined in
+// a fixed order), the angle test and the new bracket.
+__global__ __launch_bounds__(LP_BS) void k_lg_pick(int nblk, const double* __restrict__ part,
+                                                   double cmax, LgState* st) {
+  __shared__ double tot[2 * LG_PTS];
+  const int t = threadIdx.x, q = t >> 3, r = t & 7;
+  const unsigned long long lo = st->lo, hi = st->hi;
+  if (hi - lo <= 1ull) return;  // converged (uniform)
+  double s = 0.0;
+  if (q < 2 * LG_PTS)
+    for (int j = r; j < nblk; j += 8) s += part[(long)q * nblk + j];
+#pragma unroll
+  for (int off = 4; off > 0; off >>= 1) s += __shfl_down(s, off, 8);
+  if (q < 2 * LG_PTS && r == 0) tot[q] = s;
+  __syncthreads();
+  if (t == 0) {
+    const double gn = sqrt(st->wsum);
+    unsigned long long nlo = lo, nhi = hi;
+    for (int p = 0; p < LG_PTS; ++p) {
+      const double xp = lg_point(lo, hi, p + 1);
+      const unsigned long long xb = (unsigned long long)__double_as_longlong(xp);
+      if (xb <= nlo || xb >= nhi) continue;
+      const double c = tot[p] / (gn * sqrt(tot[LG_PTS + p]));
+      if (c > cmax)
+        nlo = xb;
+      else
+        nhi = xb;
+    }
+    st->lo = nlo;
+    st->hi = nhi;
+  }
+}
+
+// alpha~ = the largest alpha_i in (0, lo]: block partial maxima, then one block.
+__global__ __launch_bounds__(LP_BS) void k_lg_best(long n, const double* __restrict__ alpha,
+                                                   const LgState* st, double* __restrict__ part) {
+  __shared__ double sh[LP_BS / 64];
+  const double lim = __longlong_as_double((long long)st->lo);
+  double b = 0.0;
+  const long stride = (long)gridDim.x * LP_BS;
+  for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
+    const double a = alpha[i];
+    if (a > 0.0 && a <= lim) b = fmax(b, a);
+  }
+  b = block_max_lp(b, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+__global__ __launch_bounds__(LP_BS) void k_lg_best_fin(int nblk, const double* __restrict__ part,
+                                                       LgState* st) {
+  __shared__ double sh[LP_BS / 64];
+  double b = 0.0;
+  for (int j = threadIdx.x; j < nblk; j += LP_BS) b = fmax(b, part[j]);
+  b = block_max_lp(b, sh);
+  if (threadIdx.x == 0) st->alpha = b;
+}
+
+// rho~: the bound for alpha_i <= alpha~, rho - alpha~ g (multiply, then
+// subtract) for the rest, clipped to [0, 1].
+__global__ __launch_bounds__(LP_BS) void k_lg_apply(long n, const double* __restrict__ rho,
+                                                    const double* __restrict__ g,
+                                                    const double* __restrict__ alpha,
+                                                    const LgState* st, double* __restrict__ out) {
+#pragma clang fp contract(off)
+  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
+  if (i >= n) return;
+  const double at = st->alpha;
+  const double r = rho[i], gi = g[i];
+  double v;
+  if (at == 0.0) {
+    v = r;
+  } else if (gi != 0.0 && alpha[i] <= at) {
+    v = gi > 0.0 ? 0.0 : 1.0;
+  } else {
+    const double step = at * gi;
+    v = r - step;
+  }
+  out[i] = fmin(fmax(v, 0.0), 1.0);
+}
 }  // namespace
 
 Lp::Lp(long n, int device) : n_(n), device_(device) {
   if (n < 1 || n > (1L << 31)) throw Error(MGCG_EINVAL, "LP size must lie in 1..2^31");
   nb_ = (int)((n + LP_BS - 1) / LP_BS);
-  nr_ = (nb_ + LP_ROWS - 1) / LP_ROWS;
+  hist_shape(nb_, &ch_, &nh_);
+  nr_ = (nh_ + LP_ROWS - 1) / LP_ROWS;
+  ns_ = nb_ < LP_SUM_BLOCKS ? nb_ : LP_SUM_BLOCKS;
   MGCG_HIP(hipSetDevice(device_));
   bytes_ = device_bytes(n);
   if (hipMalloc(&arena_, bytes_) != hipSuccess) {
@@ -549,7 +913,7 @@ Lp::Lp(long n, int device) : n_(n), device_(device) {
   key_ = (unsigned long long*)take((size_t)n * 8);
   cap_ = (double*)take((size_t)n * 8);
   part_ = (double*)take((size_t)nb_ * 3 * 8);
-  bins_ = (double*)take((size_t)nb_ * 256 * 8);
+  bins_ = (double*)take((size_t)nh_ * 256 * 8);
   red_ = (double*)take((size_t)nr_ * 256 * 8);
   tsum_ = (double*)take((size_t)nb_ * 8);
   info_ = (double*)take(4 * 8);
@@ -562,10 +926,22 @@ Lp::Lp(long n, int device) : n_(n), device_(device) {
   }
 }
 
+// Chunks of LP_BS items per block of the digit passes: enough blocks to fill
+// the chip (about 1024), at most 8 chunks each.
+void Lp::hist_shape(int nb, int* ch, int* nh) {
+  int c = nb / 1024;
+  c = c < 1 ? 1 : (c > LP_CH ? LP_CH : c);
+  *ch = c;
+  *nh = (nb + c - 1) / c;
+}
+
 size_t Lp::device_bytes(long n) {
-  const long nb = (n + LP_BS - 1) / LP_BS, nr = (nb + LP_ROWS - 1) / LP_ROWS;
+  const long nb = (n + LP_BS - 1) / LP_BS;
+  int ch, nh;
+  hist_shape((int)nb, &ch, &nh);
+  const long nr = (nh + LP_ROWS - 1) / LP_ROWS;
   auto r = [](size_t b) { return (b + 255) / 256 * 256; };
-  return r((size_t)n * 8) * 2 + r((size_t)nb * 24) + r((size_t)nb * 2048) + r((size_t)nr * 2048) +
+  return r((size_t)n * 8) * 2 + r((size_t)nb * 24) + r((size_t)nh * 2048) + r((size_t)nr * 2048) +
          r((size_t)nb * 8) + r(32) + r(sizeof(LpState));
 }
 
@@ -629,10 +1005,10 @@ void Lp::solve(const double* g, const double* a, const double* x, double b, doub
   const bool feasible = h.feasible != 0;
   if (feasible) {
     for (int d = 0; d < 8; ++d) {
-      hipLaunchKernelGGL(k_lp_hist, dim3(nb_), dim3(LP_BS), 0, stream_, n_, d,
+      hipLaunchKernelGGL(k_lp_hist<false>, dim3(nh_), dim3(LP_BS), 0, stream_, n_, d, ch_,
                          (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
                          bins_);
-      hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nb_,
+      hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nh_,
                          (const double*)bins_, red_);
       hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_,
                          st);
@@ -727,10 +1103,10 @@ void Lp::select_top(const double* v, long k, double* out, int mem) {
   hipLaunchKernelGGL(k_sel_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], key_, cap_, st);
   hipLaunchKernelGGL(k_sel_budget, dim3(1), dim3(64), 0, stream_, (double)k, st);
   for (int d = 0; d < 8; ++d) {
-    hipLaunchKernelGGL(k_lp_hist, dim3(nb_), dim3(LP_BS), 0, stream_, n_, d,
+    hipLaunchKernelGGL(k_lp_hist<true>, dim3(nh_), dim3(LP_BS), 0, stream_, n_, d, ch_,
                        (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
                        bins_);
-    hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nb_, (const double*)bins_,
+    hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nh_, (const double*)bins_,
                        red_);
     hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_, st);
   }
@@ -770,8 +1146,8 @@ double Lp::angle_cos(const double* gl, const double* d, int mem) {
   const double* din[2];
   const double* in[2] = {gl, d};
   stage_io(mem, 2, in, din, nullptr, nullptr, &sg.p);
-  hipLaunchKernelGGL(k_dot3, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], din[1], part_);
-  hipLaunchKernelGGL(k_sum3, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, info_);
+  hipLaunchKernelGGL(k_dot3, dim3(ns_), dim3(LP_BS), 0, stream_, n_, din[0], din[1], part_);
+  hipLaunchKernelGGL(k_sum3, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)part_, info_);
   MGCG_HIP(hipGetLastError());
   MGCG_HIP(hipMemcpyAsync(hst_, info_, 24, hipMemcpyDeviceToHost, stream_));
   MGCG_HIP(hipStreamSynchronize(stream_));
@@ -795,9 +1171,9 @@ double Lp::heaviside(const double* r, double beta, double* out, int mem, int* it
   double lo = 0.0, hi = 1.0, eta = 0.5;
   int it = 0;
   for (; it < 100; ++it) {
-    hipLaunchKernelGGL(k_hv_sums, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], beta, eta,
+    hipLaunchKernelGGL(k_hv_sums, dim3(ns_), dim3(LP_BS), 0, stream_, n_, din[0], beta, eta,
                        part_);
-    hipLaunchKernelGGL(k_sum3, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, info_);
+    hipLaunchKernelGGL(k_sum3, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)part_, info_);
     MGCG_HIP(hipGetLastError());
     MGCG_HIP(hipMemcpyAsync(hst_, info_, 24, hipMemcpyDeviceToHost, stream_));
     MGCG_HIP(hipStreamSynchronize(stream_));
@@ -822,6 +1198,53 @@ double Lp::heaviside(const double* r, double beta, double* out, int mem, int* it
   MGCG_HIP(hipStreamSynchronize(stream_));
   if (iters) *iters = it;
   return eta;
+}
+
+
+double Lp::lagrangian(const double* rho, const double* gl, double vu, double vl, double cmax,
+                      double* out, int mem) {
+  if (!out) throw Error(MGCG_EINVAL, "null vector");
+  if (!std::isfinite(vu) || !std::isfinite(vl) || !std::isfinite(cmax))
+    throw Error(MGCG_EINVAL, "non-finite safeguard or angle");
+  MGCG_HIP(hipSetDevice(device_));
+  Staged sg;
+  const double* din[2];
+  double* dout = nullptr;
+  const double* in[2] = {rho, gl};
+  stage_io(mem, 2, in, din, out, &dout, &sg.p);
+  LpState* st = (LpState*)st_;
+  LgState* lg = (LgState*)st_;
+  double* alpha = (double*)key_;
+  MGCG_HIP(hipMemsetAsync(st, 0, sizeof(LpState), stream_));
+  hipLaunchKernelGGL(k_lg_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], din[1], vu, vl,
+                     alpha, cap_, part_, st);
+  MGCG_HIP(hipGetLastError());
+  MGCG_HIP(hipMemcpyAsync(hst_, st, sizeof(LpState), hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  LpState h;
+  std::memcpy(&h, hst_, sizeof h);
+  if (h.bad) throw Error(MGCG_EINVAL, "non-finite density or gradient");
+  hipLaunchKernelGGL(k_lg_init, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, lg);
+  for (int pass = 0; pass < 16; ++pass) {
+    hipLaunchKernelGGL(k_lg_split, dim3(ns_), dim3(LP_BS), 0, stream_, n_, (const double*)alpha,
+                       (const double*)cap_, (const LgState*)lg, bins_);
+    hipLaunchKernelGGL(k_lg_pick, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)bins_,
+                       cmax, lg);
+  }
+  hipLaunchKernelGGL(k_lg_best, dim3(ns_), dim3(LP_BS), 0, stream_, n_, (const double*)alpha,
+                     (const LgState*)lg, part_);
+  hipLaunchKernelGGL(k_lg_best_fin, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)part_,
+                     lg);
+  hipLaunchKernelGGL(k_lg_apply, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], din[1],
+                     (const double*)alpha, (const LgState*)lg, dout);
+  MGCG_HIP(hipGetLastError());
+  if (mem == MGCG_MEM_HOST)
+    MGCG_HIP(hipMemcpyAsync(out, dout, (size_t)n_ * 8, hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipMemcpyAsync(hst_, lg, sizeof(LgState), hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  LgState r;
+  std::memcpy(&r, hst_, sizeof r);
+  return r.alpha;
 }
 
 // ---- step control of Algorithm 2 (host)

@@ -152,3 +152,91 @@ def test_threshold_full_size_device_memory():
     c = lp.angle_cos(d - 0.5, torch.tensor(0.5 - rho, device="cuda"))
     assert abs(c - T.angle_cos(rho - 0.5, 0.5 - rho)) <= 4 * n * EPS
     lp.close()
+
+
+def _lagrangian_case(n, seed, kind):
+    rng = np.random.default_rng(seed)
+    if kind == "bind":
+        rho = np.full(n, 0.5)
+        g = np.where(np.arange(n) % 2 == 0, 1e-6, -1e-6)
+        rho[0], g[0] = 0.94, -1e3
+        return rho, g
+    if kind == "box":   # no safeguard can bind: the angle condition decides
+        rho = rng.uniform(0.3, 0.7, n)
+        g = rng.standard_normal(n) * np.exp(3.0 * rng.standard_normal(n))
+        return rho, g
+    rho = T.pre_round(rng.beta(0.6, 0.6, n))
+    g = rng.standard_normal(n) * rng.exponential(1.0, n) ** 3
+    g[rng.random(n) < 0.05] = 0.0
+    if kind == "ties":
+        rho, g = np.round(rho, 1), np.round(g, 1)
+    return rho, g
+
+
+@pytest.mark.parametrize("n,seed,kind", [
+    (1, 0, "mixed"), (2, 1, "box"), (7, 2, "mixed"), (300, 3, "mixed"), (257, 4, "ties"),
+    (2000, 5, "box"), (3001, 0, "bind"), (6001, 0, "bind"), (1500, 6, "mixed")])
+def test_lagrangian_threshold_matches_oracle(n, seed, kind):
+    """alpha~ is one of the alpha_i, the same quotient on both sides: compared
+    exactly, and rho~ (bounds, or rho - alpha~ g rounded after the product)
+    bit for bit."""
+    need_gpu()
+    from paper_2311_05595_amd import api
+    rho, g = _lagrangian_case(n, seed, kind)
+    lp = api.LP(n)
+    out, a = lp.lagrangian_threshold(rho, g)
+    ref, a_o = T.lagrangian_threshold(rho, g)
+    assert a == a_o
+    assert np.array_equal(out, ref)
+    lp.close()
+
+
+def test_lagrangian_threshold_degenerate():
+    """No gradient, or every density already at the bound it would reach:
+    alpha~ = 0 and rho~ = rho."""
+    need_gpu()
+    from paper_2311_05595_amd import api
+    n = 513
+    lp = api.LP(n)
+    rho = np.random.default_rng(3).uniform(0, 1, n)
+    out, a = lp.lagrangian_threshold(rho, np.zeros(n))
+    assert a == 0.0 and np.array_equal(out, rho)
+    rho = np.where(np.arange(n) % 2 == 0, 0.0, 1.0)
+    g = np.where(rho == 0.0, 1.0, -1.0)
+    out, a = lp.lagrangian_threshold(rho, g)
+    assert a == 0.0 and np.array_equal(out, rho)
+    lp.close()
+
+
+def test_lagrangian_threshold_full_size():
+    """4,194,304 densities in device memory, heavy-tailed gradients: alpha~
+    passes the angle test and the safeguards, and the next larger alpha_i
+    breaks one of them (the cosine from its closed form,
+    sum g^2 m / (|g| sqrt(sum g^2 m^2)), m_i = min(alpha, alpha_i))."""
+    need_gpu()
+    import torch
+    from paper_2311_05595_amd import api
+    n = 64 * 32 * 32 * 64
+    rng = np.random.default_rng(13)
+    rho = T.pre_round(np.clip(rng.beta(0.7, 1.2, n), 0.0, 1.0))
+    g = rng.standard_normal(n) * np.exp(2.0 * rng.standard_normal(n))
+    lp = api.LP(n)
+    out, a = lp.lagrangian_threshold(torch.tensor(rho, device="cuda"),
+                                     torch.tensor(g, device="cuda"))
+    out = out.cpu().numpy()
+    alpha = T.lagrangian_alphas(rho, g)
+    w = g * g
+    cmax = math.cos(math.radians(89.9))
+    bad = ((g < 0) & (rho < 0.3)) | ((g > 0) & (rho > 0.7))
+    viol = alpha[bad].min() if bad.any() else np.inf
+
+    def cos(x):
+        m = np.minimum(x, alpha)
+        return np.sum(w * m) / (math.sqrt(w.sum()) * math.sqrt(np.sum(w * m * m)))
+
+    assert a > 0.0 and a < viol and cos(a) > cmax
+    nxt = alpha[np.isfinite(alpha) & (alpha > a)].min()
+    assert nxt >= viol or cos(nxt) <= cmax
+    idx = np.random.default_rng(14).choice(n, 4096, replace=False)
+    assert np.array_equal(out[idx], T.lagrangian_step(rho[idx], g[idx], a))
+    lp.close()

@@ -163,11 +163,37 @@ __global__ __launch_bounds__(LP_BS) void k_lp_hist(long n, int d, int ch,
     mm[c] = c < ch && i < n && (d == 0 || (kk[c] >> (shift + 8)) == (pre >> (shift + 8)));
     cc[c] = UNIT ? 1.0 : (mm[c] ? cap[i] : 0.0);
   }
+  if (UNIT) {
+    // unit capacities: the sums are counts, exact in any order; one LDS
+    // atomic per run of equal digits in a wave
+    __shared__ int hcount[256];
+    hcount[t] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < LP_CH; ++c) {
+      if (c >= ch) break;
+      const bool match = mm[c];
+      const int dig = (int)((kk[c] >> shift) & 255ull);
+      unsigned long long same = __ballot(match);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const int on = (dig >> bit) & 1;
+        const unsigned long long m = __ballot(on);
+        same &= on ? m : ~m;
+      }
+      if (match && (same & lower) == 0ull) atomicAdd(&hcount[dig], __popcll(same));
+    }
+    __syncthreads();
+    bins[(long)blockIdx.x * 256 + t] = (double)hcount[t];
+    return;
+  }
   double s = 0.0;
 #pragma unroll
   for (int c = 0; c < LP_CH; ++c) {
     if (c >= ch) break;
     const bool match = mm[c];
+    // a chunk with no item inside the prefix adds nothing (block-uniform)
+    if (!__syncthreads_or(match)) continue;
     const int dig = (int)((kk[c] >> shift) & 255ull);
 #pragma unroll
     for (int q = 0; q < LP_BS / 64; ++q) pos[q][t] = 0;
@@ -318,13 +344,14 @@ __global__ __launch_bounds__(LP_BS) void k_lp_pick(int nrows, int d, const doubl
 }
 
 // Capacity of the tied items (key == the critical key) per block.
+template <bool UNIT>
 __global__ __launch_bounds__(LP_BS) void k_lp_tiesum(long n, const unsigned long long* __restrict__ key,
                                                      const double* __restrict__ cap,
                                                      const LpState* st, double* __restrict__ tsum) {
   __shared__ double sh[LP_BS / 64];
   const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
   const unsigned long long T = st->prefix;
-  const double c = (i < n && key[i] == T) ? cap[i] : 0.0;
+  const double c = (i < n && key[i] == T) ? (UNIT ? 1.0 : cap[i]) : 0.0;
   const double s = block_sum_lp(c, sh);
   if (threadIdx.x == 0) tsum[blockIdx.x] = s;
 }
@@ -520,17 +547,16 @@ __global__ __launch_bounds__(LP_BS) void k_lp_info(int nb, const double* __restr
 
 // ---- thresholding of Sec. 5 on the same scratch
 
-// Keys of the values (descending) with unit capacities: the radix select then
-// picks the k-th largest value, equal values in index order.
+// Keys of the values (descending); the capacities are 1 (never stored): the
+// radix select then picks the k-th largest value, equal values in index order.
 __global__ __launch_bounds__(LP_BS) void k_sel_prep(long n, const double* __restrict__ v,
                                                     unsigned long long* __restrict__ key,
-                                                    double* __restrict__ cap, LpState* st) {
+                                                    LpState* st) {
   const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
   if (i < n) {
     const double vi = v[i];
     if (!isfinite(vi)) st->bad = 1;
     key[i] = ratio_key(isfinite(vi) ? vi : 0.0);
-    cap[i] = 1.0;
   }
 }
 __global__ void k_sel_budget(double k, LpState* st) {
@@ -618,25 +644,28 @@ __global__ __launch_bounds__(LP_BS) void k_sum3(int nb, const double* __restrict
 //   h = (tanh(beta eta) + tanh(beta (rho - eta))) / (tanh(beta eta) + tanh(beta (1 - eta)))
 // and its derivative in eta; per block the partial sums of h, dh/deta and rho
 // (Newton's method on the volume runs on the host).
+// h and dh/deta at one density; inv = 1 / (tanh(beta eta) + tanh(beta (1 - eta)))
+// (the sums of Newton's method multiply by it; the projected values divide).
 __device__ __forceinline__ void heaviside_at(double r, double beta, double eta, double te,
-                                             double t1, double& h, double& dh) {
+                                             double t1, double inv, double& h, double& dh) {
   const double tr = tanh(beta * (r - eta));
   const double num = te + tr, den = te + t1;
   const double dnum = beta * (1.0 - te * te) - beta * (1.0 - tr * tr);
   const double dden = beta * (1.0 - te * te) - beta * (1.0 - t1 * t1);
-  h = num / den;
-  dh = (dnum * den - num * dden) / (den * den);
+  h = num * inv;
+  dh = (dnum * den - num * dden) * (inv * inv);
 }
 __global__ __launch_bounds__(LP_BS) void k_hv_sums(long n, const double* __restrict__ r, double beta,
                                                    double eta, double* __restrict__ part) {
   __shared__ double sh[LP_BS / 64];
   const double te = tanh(beta * eta), t1 = tanh(beta * (1.0 - eta));
+  const double inv = 1.0 / (te + t1);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   const long stride = (long)gridDim.x * LP_BS;
   for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
     const double ri = r[i];
     double h, dh;
-    heaviside_at(ri, beta, eta, te, t1, h, dh);
+    heaviside_at(ri, beta, eta, te, t1, inv, h, dh);
     s0 += h;
     s1 += dh;
     s2 += ri;
@@ -652,13 +681,11 @@ __global__ __launch_bounds__(LP_BS) void k_hv_sums(long n, const double* __restr
 }
 __global__ __launch_bounds__(LP_BS) void k_hv_apply(long n, const double* __restrict__ r, double beta,
                                                     double eta, double* __restrict__ out) {
-  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
-  if (i < n) {
-    const double te = tanh(beta * eta), t1 = tanh(beta * (1.0 - eta));
-    double h, dh;
-    heaviside_at(r[i], beta, eta, te, t1, h, dh);
-    out[i] = h;
-  }
+  const double te = tanh(beta * eta), t1 = tanh(beta * (1.0 - eta));
+  const double den = te + t1;
+  const long stride = (long)gridDim.x * LP_BS;
+  for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride)
+    out[i] = (te + tanh(beta * (r[i] - eta))) / den;
 }
 
 
@@ -709,17 +736,17 @@ __global__ __launch_bounds__(LP_BS) void k_lg_prep(long n, const double* __restr
                                                    double* __restrict__ w,
                                                    double* __restrict__ part, LpState* st) {
   __shared__ double sh[LP_BS / 64];
-  const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
   double vmin = INFINITY, ws = 0.0, am = 0.0;
-  if (i < n) {
+  const long stride = (long)gridDim.x * LP_BS;
+  for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
     const double r = rho[i], gi = g[i];
     if (!isfinite(r) || !isfinite(gi)) st->bad = 1;
     const double a = lg_alpha(r, gi);
     alpha[i] = a;
     w[i] = gi * gi;
-    ws = gi * gi;
-    if ((gi < 0.0 && r < vu) || (gi > 0.0 && r > vl)) vmin = a;
-    if (isfinite(a)) am = a;
+    ws += gi * gi;
+    if ((gi < 0.0 && r < vu) || (gi > 0.0 && r > vl)) vmin = fmin(vmin, a);
+    if (isfinite(a)) am = fmax(am, a);
   }
   vmin = block_min_lp(vmin, sh);
   ws = block_sum_lp(ws, sh);
@@ -821,7 +848,13 @@ __global__ __launch_bounds__(LP_BS) void k_lg_pick(int nblk, const double* __res
   if (hi - lo <= 1ull) return;  // converged (uniform)
   double s = 0.0;
   if (q < 2 * LG_PTS)
-    for (int j = r; j < nblk; j += 8) s += part[(long)q * nblk + j];
+    for (int j = r; j < nblk; j += 8 * 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = j + 8 * u < nblk ? part[(long)q * nblk + j + 8 * u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += v[u];
+    }
 #pragma unroll
   for (int off = 4; off > 0; off >>= 1) s += __shfl_down(s, off, 8);
   if (q < 2 * LG_PTS && r == 0) tot[q] = s;
@@ -1013,7 +1046,7 @@ void Lp::solve(const double* g, const double* a, const double* x, double b, doub
       hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_,
                          st);
     }
-    hipLaunchKernelGGL(k_lp_tiesum, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
+    hipLaunchKernelGGL(k_lp_tiesum<false>, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
                        (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
                        tsum_);
     hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_);
@@ -1100,7 +1133,7 @@ void Lp::select_top(const double* v, long k, double* out, int mem) {
   stage_io(mem, 1, in, din, out, &dout, &sg.p);
   LpState* st = (LpState*)st_;
   MGCG_HIP(hipMemsetAsync(st, 0, sizeof(LpState), stream_));
-  hipLaunchKernelGGL(k_sel_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], key_, cap_, st);
+  hipLaunchKernelGGL(k_sel_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], key_, st);
   hipLaunchKernelGGL(k_sel_budget, dim3(1), dim3(64), 0, stream_, (double)k, st);
   for (int d = 0; d < 8; ++d) {
     hipLaunchKernelGGL(k_lp_hist<true>, dim3(nh_), dim3(LP_BS), 0, stream_, n_, d, ch_,
@@ -1110,7 +1143,7 @@ void Lp::select_top(const double* v, long k, double* out, int mem) {
                        red_);
     hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_, st);
   }
-  hipLaunchKernelGGL(k_lp_tiesum, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
+  hipLaunchKernelGGL(k_lp_tiesum<true>, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
                      (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st, tsum_);
   hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_);
   hipLaunchKernelGGL(k_sel_fill, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
@@ -1191,7 +1224,7 @@ double Lp::heaviside(const double* r, double beta, double* out, int mem, int* it
     eta = nxt;
     if (done) break;
   }
-  hipLaunchKernelGGL(k_hv_apply, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], beta, eta, dout);
+  hipLaunchKernelGGL(k_hv_apply, dim3(ns_), dim3(LP_BS), 0, stream_, n_, din[0], beta, eta, dout);
   MGCG_HIP(hipGetLastError());
   if (mem == MGCG_MEM_HOST)
     MGCG_HIP(hipMemcpyAsync(out, dout, (size_t)n_ * 8, hipMemcpyDeviceToHost, stream_));
@@ -1216,7 +1249,7 @@ double Lp::lagrangian(const double* rho, const double* gl, double vu, double vl,
   LgState* lg = (LgState*)st_;
   double* alpha = (double*)key_;
   MGCG_HIP(hipMemsetAsync(st, 0, sizeof(LpState), stream_));
-  hipLaunchKernelGGL(k_lg_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, din[0], din[1], vu, vl,
+  hipLaunchKernelGGL(k_lg_prep, dim3(ns_), dim3(LP_BS), 0, stream_, n_, din[0], din[1], vu, vl,
                      alpha, cap_, part_, st);
   MGCG_HIP(hipGetLastError());
   MGCG_HIP(hipMemcpyAsync(hst_, st, sizeof(LpState), hipMemcpyDeviceToHost, stream_));
@@ -1224,7 +1257,7 @@ double Lp::lagrangian(const double* rho, const double* gl, double vu, double vl,
   LpState h;
   std::memcpy(&h, hst_, sizeof h);
   if (h.bad) throw Error(MGCG_EINVAL, "non-finite density or gradient");
-  hipLaunchKernelGGL(k_lg_init, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, lg);
+  hipLaunchKernelGGL(k_lg_init, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)part_, lg);
   for (int pass = 0; pass < 16; ++pass) {
     hipLaunchKernelGGL(k_lg_split, dim3(ns_), dim3(LP_BS), 0, stream_, n_, (const double*)alpha,
                        (const double*)cap_, (const LgState*)lg, bins_);

@@ -31,8 +31,12 @@ What it computes (the plain definitions, in FP64):
                constraint and the trust region (a fractional knapsack), the
                artificial problem, and the step control of Algorithm 2;
 * ``threshold`` the density thresholding of Sec. 5: rounding, the
-               density-value strategy, the angle condition and the Heaviside
-               projection with its volume-preserving threshold.
+               density-value strategy, the angle condition, the strategy
+               based on the gradient of the Lagrangian and the Heaviside
+               projection with its volume-preserving threshold;
+* ``fixing``   the choice of fixed variables of Sec. 6.1: void and solid
+               elements, the surrounded rule, fixed design variables and
+               suppressed nodes of the raised degree.
 
 Parity status of every function is listed in its module docstring.
 """

@@ -26,6 +26,9 @@ densities of that lattice: the rule based on the density values (the
 printed line), the Heaviside projection with Newton's volume-preserving
 threshold, the angle condition's cosine and the strategy based on the
 gradient of the Lagrangian (in `config`).
+
+`--fixing` times the choice of fixed variables of Sec. 6.1 on that mesh
+(4^3 densities, 2^3 design cells per element, the Q2 node lattice).
 """
 
 import argparse
@@ -646,6 +649,69 @@ def run_threshold(args):
     print(json.dumps(out), flush=True)
 
 
+def run_fixing(args):
+    import torch
+    import workloads as W
+    from paper_2311_05595_amd import api
+
+    nel, n, d, order = (64, 32, 32), 4, 2, 2
+    rng = np.random.default_rng(41)
+    # void, solid and mixed regions at the element scale
+    from workloads import fields
+    blobs = fields.gaussian_random_field((nel[2], nel[1], nel[0]), 41)
+    lo, hi = np.quantile(blobs, [0.4, 0.7])
+    up = lambda a, m: np.repeat(np.repeat(np.repeat(a, m, 0), m, 1), m, 2)
+    kind = up(np.where(blobs < lo, 0, np.where(blobs > hi, 2, 1)), n)
+    rho = np.where(kind == 0, 1e-7, np.where(kind == 2, 0.95, 0.5))
+    grad = rng.uniform(-1e-6, 1e-6, (d * nel[2], d * nel[1], d * nel[0]))
+    mask, _ = W.make_problem("cantilever", *nel, order, 1)
+    dev = torch.device("cuda:0")
+    rd, gd = torch.tensor(rho, device=dev), torch.tensor(grad, device=dev)
+    m0 = torch.tensor(mask, device=dev)
+    dm = m0.clone()
+    for _ in range(args.warmup):
+        dm.copy_(m0)
+        api.fix_variables(nel, n, d, order, rd, gd, dm)
+    torch.cuda.synchronize()
+    t = 0.0
+    for _ in range(args.steps):
+        dm.copy_(m0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, cnt = api.fix_variables(nel, n, d, order, rd, gd, dm)
+        t += time.perf_counter() - t0
+    t /= args.steps
+    nn = (order * nel[0] + 1) * (order * nel[1] + 1) * (order * nel[2] + 1)
+    nelt = nel[0] * nel[1] * nel[2]
+    nbytes = 8.0 * rho.size + 8.0 * grad.size + nelt + grad.size + 3.0 * nn
+    out = {
+        "metric": "fixings/s (void and solid elements, fixed design variables, suppressed Q2 DOFs)",
+        "value": round(1.0 / t, 1), "unit": "fixings/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"64x32x32 elements, 4^3 densities and 2^3 design cells each, "
+                               f"Q2 lattice {2 * nel[0] + 1}x{2 * nel[1] + 1}x{2 * nel[2] + 1}",
+                   "counts": cnt},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 5),
+                     "traffic": None, "avg_us": round(t * 1e6, 1), "alg_bytes_per_launch": nbytes,
+                     "note": "whole call: 8 launches, one scratch allocation and one read-back"},
+    }
+    if not args.no_cpu:
+        from oracle import fixing
+        t1 = time.perf_counter()
+        fk = fixing.surrounded(fixing.classify(rho, grad, nel, n, d))
+        fixing.dof_mask(mask, fixing.suppressed_nodes(fk, order))
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 4), "unit": "fixings/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the oracle on the same lattices, once ({dt:.2f} s, "
+                                         f"1 host thread)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -661,6 +727,8 @@ def main():
     ap.add_argument("--projection", action="store_true",
                     help="time the design-variable projection and its transpose")
     ap.add_argument("--lp", action="store_true", help="time the SLP step's LP subproblem")
+    ap.add_argument("--fixing", action="store_true",
+                    help="time the choice of fixed variables before the degree is raised")
     ap.add_argument("--threshold", action="store_true",
                     help="time the density thresholding and the Heaviside projection")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
@@ -671,6 +739,12 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.fixing:
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        run_fixing(args)
         return
     if args.threshold:
         if args.gpus != 1:

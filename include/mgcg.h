@@ -372,6 +372,42 @@ typedef struct mgcg_slp_ctrl {
 int mgcg_slp_decide(mgcg_slp_ctrl* ctrl, double f0, double f1, double c0, double c1, double gts,
                     double ats, double s_inf, double* theta, double* a_red, double* p_red);
 
+/* ---- Variables fixed before the degree of the elements is raised (Sec. 6.1)
+ *
+ * An element is void when all its n^3 densities are <= rho_l and all its d^3
+ * design-gradient components are >= -eps_grad, solid when all densities are
+ * >= rho_u and all gradient components <= eps_grad (the paper: 1e-6, 0.9,
+ * 1e-6).  It is fixed when every element sharing a node with it (inside the
+ * domain) is of its kind.  Outputs:
+ *   elem_kind     uint8[nelx*nely*nelz]  0 free, 1 fixed void, 2 fixed solid;
+ *   design_fixed  uint8[d^3 * nel]       1 for the design variables of fixed
+ *                                        elements (the design lattice, x fastest);
+ *   dof_mask      uint8[3 * nn]          in/out: the DOFs of every node of the
+ *                 lattice of degree `order` whose elements are all fixed void
+ *                 are set to 1, the rest are left as passed (pass the supports;
+ *                 the result is the fixed-DOF mask of the problem of that degree).
+ * rho is the density lattice (n cells per element and axis), grad_x the
+ * design gradient df/dx (d per element and axis), both FP64, x fastest.
+ * mem selects host or device memory for all arrays; the call runs on the
+ * null stream, allocates its own scratch and returns when done.  counts may
+ * be NULL.  MGCG_EINVAL for a bad geometry (mesh >= 1, n and d in 1..64, order
+ * 1 or 2), non-finite thresholds or NULL arrays. */
+typedef struct mgcg_fix_desc {
+  int32_t nelx, nely, nelz;
+  int32_t nsub;   /* n: density cells per element and axis */
+  int32_t ndes;   /* d: design cells per element and axis */
+  int32_t order;  /* degree of the displacement lattice whose nodes are suppressed */
+  double rho_l, rho_u, eps_grad;
+} mgcg_fix_desc;
+typedef struct mgcg_fix_counts {
+  int64_t void_elems, solid_elems; /* fixed elements of each kind */
+  int64_t fixed_design;            /* fixed design variables */
+  int64_t suppressed_nodes;        /* nodes whose DOFs were set in dof_mask */
+} mgcg_fix_counts;
+int mgcg_fix_variables(const mgcg_fix_desc* desc, const double* rho, const double* grad_x,
+                       uint8_t* elem_kind, uint8_t* design_fixed, uint8_t* dof_mask,
+                       mgcg_fix_counts* counts, int mem);
+
 #ifdef __cplusplus
 }
 #endif

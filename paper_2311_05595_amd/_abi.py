@@ -61,6 +61,17 @@ class mgcg_slp_ctrl(C.Structure):
                 ("k", C.c_int32), ("pad", C.c_int32)]
 
 
+class mgcg_fix_desc(C.Structure):
+    _fields_ = [("nelx", C.c_int32), ("nely", C.c_int32), ("nelz", C.c_int32),
+                ("nsub", C.c_int32), ("ndes", C.c_int32), ("order", C.c_int32),
+                ("rho_l", C.c_double), ("rho_u", C.c_double), ("eps_grad", C.c_double)]
+
+
+class mgcg_fix_counts(C.Structure):
+    _fields_ = [("void_elems", C.c_int64), ("solid_elems", C.c_int64),
+                ("fixed_design", C.c_int64), ("suppressed_nodes", C.c_int64)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "mgcg_last_error": (C.c_char_p, []),
@@ -122,6 +133,9 @@ EXPORTS = {
                                  C.c_int]),
     "mgcg_heaviside": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                  C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int]),
+    "mgcg_fix_variables": (C.c_int, [C.POINTER(mgcg_fix_desc), C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(mgcg_fix_counts), C.c_int]),
     "mgcg_slp_decide": (C.c_int, [C.POINTER(mgcg_slp_ctrl), C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double),

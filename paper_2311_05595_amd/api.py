@@ -482,5 +482,44 @@ def slp_decide(ctrl, f0, f1, c0, c1, gts, ats, s_inf):
     return bool(r), th.value, ar.value, pr.value
 
 
-__all__ = ["Problem", "Server", "Projection", "LP", "slp_ctrl", "slp_decide", "admission_plan", "device_bytes", "make_desc",
+def fix_variables(nel, nsub, ndes, order, rho, grad_x, dof_mask, rho_l=1e-6, rho_u=0.9,
+                  eps_grad=1e-6):
+    """Variables fixed before the degree is raised (Sec. 6.1, mgcg_fix_variables).
+
+    rho and grad_x: numpy arrays or contiguous float64 device tensors of the
+    density and design lattices; dof_mask: the supports' uint8 mask of the
+    lattice of degree `order` (host or device like rho), updated in place.
+    Returns (elem_kind, design_fixed, dof_mask, counts dict)."""
+    desc = _abi.mgcg_fix_desc(int(nel[0]), int(nel[1]), int(nel[2]), int(nsub), int(ndes),
+                              int(order), float(rho_l), float(rho_u), float(eps_grad))
+    pr, mem, kr = _ptr(rho)
+    pg, mem_g, _ = _ptr(grad_x)
+    if mem_g != mem:
+        raise ValueError("mixed host and device arrays")
+    nelt = int(nel[0]) * int(nel[1]) * int(nel[2])
+    nx = nelt * int(ndes) ** 3
+    nn = (order * nel[0] + 1) * (order * nel[1] + 1) * (order * nel[2] + 1)
+    if mem == MGCG_MEM_DEVICE:
+        torch = _torch()
+        if dof_mask.dtype != torch.uint8 or not dof_mask.is_contiguous() or dof_mask.numel() != 3 * nn:
+            raise ValueError("dof_mask must be a contiguous uint8 tensor of 3 entries per node")
+        _inputs_ready(mem)
+        kind = torch.empty(nelt, dtype=torch.uint8, device=kr.device)
+        des = torch.empty(nx, dtype=torch.uint8, device=kr.device)
+        pk, pd, pm = (C.c_void_p(t.data_ptr()) for t in (kind, des, dof_mask))
+    else:
+        if not (isinstance(dof_mask, np.ndarray) and dof_mask.dtype == np.uint8 and
+                dof_mask.flags.c_contiguous and dof_mask.size == 3 * nn):
+            raise ValueError("dof_mask must be a contiguous uint8 array of 3 entries per node")
+        kind = np.empty(nelt, dtype=np.uint8)
+        des = np.empty(nx, dtype=np.uint8)
+        pk, pd, pm = (C.c_void_p(a.ctypes.data) for a in (kind, des, dof_mask))
+    cnt = _abi.mgcg_fix_counts()
+    check(load().mgcg_fix_variables(C.byref(desc), pr, pg, pk, pd, pm, C.byref(cnt), mem))
+    return kind, des, dof_mask, {"void_elems": cnt.void_elems, "solid_elems": cnt.solid_elems,
+                                 "fixed_design": cnt.fixed_design,
+                                 "suppressed_nodes": cnt.suppressed_nodes}
+
+
+__all__ = ["Problem", "Server", "Projection", "LP", "slp_ctrl", "slp_decide", "fix_variables", "admission_plan", "device_bytes", "make_desc",
            "make_proj_desc", "proj_device_bytes", "_abi"]

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmgcg.so")
 SOURCES = ["element.cpp", "k_apply.hip", "k_setup.hip", "problem.hip", "capi.hip", "server.hip",
-           "proj.hip", "lp.hip"]
+           "proj.hip", "lp.hip", "fix.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -453,3 +453,20 @@ int mgcg_slp_decide(mgcg_slp_ctrl* ctrl, double f0, double f1, double c0, double
 }
 
 }  // extern "C"
+
+// ---- variables fixed before raising the degree
+#include "fix.h"
+
+extern "C" {
+
+int mgcg_fix_variables(const mgcg_fix_desc* desc, const double* rho, const double* grad_x,
+                       uint8_t* elem_kind, uint8_t* design_fixed, uint8_t* dof_mask,
+                       mgcg_fix_counts* counts, int mem) {
+  NEED(desc);
+  GUARD({
+    mgcg::fix_variables(*desc, rho, grad_x, elem_kind, design_fixed, dof_mask, counts, mem);
+    return MGCG_OK;
+  })
+}
+
+}  // extern "C"

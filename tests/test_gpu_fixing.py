@@ -1,0 +1,129 @@
+"""GPU parity of the choice of fixed variables (Sec. 6.1) against the oracle,
+through the C ABI: element kinds, fixed design variables and the suppressed
+DOFs of the raised degree are 0/1 decisions from FP64 comparisons and
+integer neighbourhoods, compared bit for bit; and one step of the adaptive
+strategy (Q1 solve, fixing, Q2 solve with the suppressed DOFs) against the
+oracle's solve with the same mask."""
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import fixing as F
+from tests.helpers import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _field(nel, n, d, seed):
+    """Densities with void, solid and mixed regions (smooth blobs at the
+    element scale, varied inside the elements) and a small design gradient
+    with some entries beyond +-eps."""
+    nelx, nely, nelz = nel
+    rng = np.random.default_rng(seed)
+    blobs = ndimage.gaussian_filter(rng.random((nelz, nely, nelx)), 1.5)
+    lo, hi = np.quantile(blobs, [0.4, 0.7])
+    up = lambda a, m: np.repeat(np.repeat(np.repeat(a, m, 0), m, 1), m, 2)
+    kind = up(np.where(blobs < lo, 0, np.where(blobs > hi, 2, 1)), n)
+    rho = np.where(kind == 0, rng.uniform(0, 1e-6, kind.shape),
+                   np.where(kind == 2, rng.uniform(0.9, 1.0, kind.shape),
+                            rng.uniform(0.0, 1.0, kind.shape)))
+    rho[rng.random(rho.shape) < 0.002] = 0.5      # stray intermediate densities
+    grad = rng.uniform(-1e-6, 1e-6, (d * nelz, d * nely, d * nelx))
+    grad[rng.random(grad.shape) < 0.01] *= 10.0   # some vetoes
+    return rho, grad
+
+
+def _oracle(nel, n, d, order, rho, grad, mask):
+    fk = F.surrounded(F.classify(rho, grad, nel, n, d))
+    nodes = F.suppressed_nodes(fk, order)
+    return fk, F.fixed_design(fk, d), F.dof_mask(mask, nodes), nodes
+
+
+@pytest.mark.parametrize("nel,n,d,order,seed", [
+    ((1, 1, 1), 1, 1, 1, 0), ((5, 3, 7), 2, 1, 1, 1), ((5, 3, 7), 2, 2, 2, 2),
+    ((12, 6, 6), 4, 2, 2, 3), ((12, 6, 6), 1, 1, 2, 4), ((9, 8, 5), 3, 3, 1, 5)])
+def test_fixing_matches_oracle(nel, n, d, order, seed):
+    need_gpu()
+    import workloads as W
+    from paper_2311_05595_amd import api
+    rho, grad = _field(nel, n, d, seed)
+    mask, _ = W.make_problem("cantilever", *nel, order, 1)
+    fk, fd, m_o, nodes = _oracle(nel, n, d, order, rho, grad, mask)
+    m = mask.copy()
+    kind, des, m, cnt = api.fix_variables(nel, n, d, order, rho, grad, m)
+    assert np.array_equal(kind, fk.reshape(-1))
+    assert np.array_equal(des, fd.reshape(-1))
+    assert np.array_equal(m, m_o)
+    assert cnt == {"void_elems": int((fk == F.VOID).sum()), "solid_elems": int((fk == F.SOLID).sum()),
+                   "fixed_design": int(fd.sum()), "suppressed_nodes": int(nodes.sum())}
+
+
+def test_fixing_full_size_device_memory():
+    """The 64x32x32 mesh, 4^3 densities and 2^3 design cells per element,
+    suppressed nodes on the Q2 lattice (129x65x65), arrays in device memory."""
+    need_gpu()
+    import torch
+    import workloads as W
+    from paper_2311_05595_amd import api
+    nel, n, d, order = (64, 32, 32), 4, 2, 2
+    rho, grad = _field(nel, n, d, 6)
+    mask, _ = W.make_problem("cantilever", *nel, order, 1)
+    fk, fd, m_o, nodes = _oracle(nel, n, d, order, rho, grad, mask)
+    dm = torch.tensor(mask, device="cuda")
+    kind, des, dm, cnt = api.fix_variables(nel, n, d, order, torch.tensor(rho, device="cuda"),
+                                           torch.tensor(grad, device="cuda"), dm)
+    assert np.array_equal(kind.cpu().numpy(), fk.reshape(-1))
+    assert np.array_equal(des.cpu().numpy(), fd.reshape(-1))
+    assert np.array_equal(dm.cpu().numpy(), m_o)
+    assert cnt["suppressed_nodes"] == int(nodes.sum()) > 0
+
+
+def test_fixing_rejects_bad_input():
+    need_gpu()
+    from paper_2311_05595_amd import api
+    from paper_2311_05595_amd._abi import MGCGError
+    rho, grad = _field((4, 4, 4), 1, 1, 7)
+    m = np.zeros(3 * 9 ** 3, dtype=np.uint8)
+    with pytest.raises(MGCGError):
+        api.fix_variables((4, 4, 4), 1, 1, 3, rho, grad, np.zeros(3 * 13 ** 3, dtype=np.uint8))
+    with pytest.raises(MGCGError):
+        api.fix_variables((4, 4, 4), 1, 1, 2, rho, grad, m, rho_l=float("nan"))
+    api.fix_variables((4, 4, 4), 1, 1, 2, rho, grad, m)
+
+
+def test_adaptive_step_q1_to_q2():
+    """One step of the adaptive strategy (Sec. 6): the Q1 solution's
+    densities (a void block in the top layers of a cantilever) and gradient
+    fix elements; the Q2 problem with the suppressed DOFs solves to the same
+    compliance as the full Q2 problem (within 1e-6, E_min = 1e-9) and to the
+    oracle's direct solve with the same mask (rtol of the solve)."""
+    need_gpu()
+    import workloads as W
+    from oracle import fem, solve
+    from paper_2311_05595_amd import api
+    nel, n = (8, 6, 4), 1
+    rho = np.ones((4, 6, 8))
+    rho[:, 3:, 2:7] = 1e-7
+    m1, f1 = W.make_problem("cantilever", *nel, 1, 1)
+    p1 = api.Problem(nel, m1, f1, order=1, nsub=n, nlevels=2)
+    p1.set_densities(rho.reshape(-1))
+    p1.solve(rtol=1e-10, maxit=2000, warm_start=False)
+    _, dc = p1.compliance_sensitivity()
+    p1.close()
+    m2, f2 = W.make_problem("cantilever", *nel, 2, 1)
+    ms = m2.copy()
+    _, _, ms, cnt = api.fix_variables(nel, n, n, 2, rho, dc.reshape(-1), ms)
+    assert cnt["suppressed_nodes"] > 0 and ms.sum() > m2.sum()
+    comp = {}
+    for name, mk in (("full", m2), ("fixed", ms)):
+        p2 = api.Problem(nel, mk, f2, order=2, nsub=n, nlevels=2)
+        p2.set_densities(rho.reshape(-1))
+        p2.solve(rtol=1e-10, maxit=4000, warm_start=False)
+        c, _ = p2.compliance_sensitivity()
+        comp[name] = float(c[-1])  # the total over the load cases
+        p2.close()
+    assert abs(comp["fixed"] - comp["full"]) <= 1e-6 * comp["full"]
+    Ks = fem.sub_element_matrices(2, n)
+    _, _, c_o, _ = solve.solve_problem(rho, ms, f2, nel, 2, n, Ks, E0=1.0, Emin=1e-9, penal=3.0)
+    assert abs(comp["fixed"] - c_o.sum()) <= 1e-8 * c_o.sum()

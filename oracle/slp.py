@@ -27,6 +27,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   B < 0, s = u' if B exceeds the capacity.  Reading: the upper bound of the
   shrunk box printed as max{0.8 delta; x_u - x_i} is taken as the min, the
   mirror image of the lower bound.
+* Fixed design variables (Sec. 6.1) take l = u = 0, the alternative the
+  paper gives to removing them from the LP.
 * Step control of Algorithm 2: the predicted and actual reductions of the
   merit function psi = theta f + (1 - theta) phi, phi = |c|^2 / 2, the penalty
   parameter update (eqs. (theta1), (theta2)) and the trust-region radius
@@ -45,22 +47,27 @@ the theta and delta rules.
 import numpy as np
 
 
-def lp_bounds(x, delta, xl=0.0, xu=1.0):
-    """(l, u) of problem (Pstar)."""
+def lp_bounds(x, delta, xl=0.0, xu=1.0, fixed=None):
+    """(l, u) of problem (Pstar); fixed variables get l = u = 0 (Sec. 6.1)."""
     x = np.asarray(x, dtype=np.float64)
-    return np.maximum(-delta, xl - x), np.minimum(delta, xu - x)
+    l, u = np.maximum(-delta, xl - x), np.minimum(delta, xu - x)
+    if fixed is not None:
+        f = np.asarray(fixed) != 0
+        l, u = np.where(f, 0.0, l), np.where(f, 0.0, u)
+    return l, u
 
 
-def lp_step(g, a, x, b, delta, xl=0.0, xu=1.0):
+def lp_step(g, a, x, b, delta, xl=0.0, xu=1.0, fixed=None):
     """Solution of the LP subproblem: (s, lambda, feasible).
 
     g: objective gradient, a: constraint gradient (> 0), b: right-hand side
-    (a^T s = b), delta: trust-region radius."""
+    (a^T s = b), delta: trust-region radius, fixed: optional mask of
+    variables held at s = 0 (the fixed design variables of Sec. 6.1)."""
     g = np.asarray(g, dtype=np.float64)
     a = np.asarray(a, dtype=np.float64)
     if np.any(a <= 0.0):
         raise ValueError("the constraint gradient must be positive")
-    l, u = lp_bounds(x, delta, xl, xu)
+    l, u = lp_bounds(x, delta, xl, xu, fixed)
     B = b - float(np.dot(a, l))
     cap = a * (u - l)
     # a budget within the rounding of its sums of 0 or of the capacity is the
@@ -68,7 +75,7 @@ def lp_step(g, a, x, b, delta, xl=0.0, xu=1.0):
     tau = 2 * g.size * np.finfo(np.float64).eps * (float(np.abs(a * l).sum()) + float(cap.sum()))
     if B < -tau or B > cap.sum() + tau:
         # artificial problem with the box shrunk to 0.8 delta
-        l2, u2 = lp_bounds(x, 0.8 * delta, xl, xu)
+        l2, u2 = lp_bounds(x, 0.8 * delta, xl, xu, fixed)
         return (l2.copy() if B < 0.0 else u2.copy()), float("nan"), False
     B = min(max(B, 0.0), float(cap.sum()))
     r = -g / a

@@ -128,3 +128,20 @@ def test_merit_reductions_identities():
         th = slp.theta_update(0, [1.0], 1.0, pf_, po_)
         if th < 1.0:
             assert th * po_ + (1 - th) * pf_ == pytest.approx(0.5 * pf_)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_lp_fixed_variables_against_linprog(seed):
+    """Fixed variables (Sec. 6.1) held at zero: the same optimum as linprog
+    with the bounds (0, 0) for them, and s = 0 there."""
+    n = 200
+    g, a, x, _, delta = _instance(n, 20 + seed, delta=0.1)
+    fixed = (np.random.default_rng(seed).random(n) < 0.3).astype(np.uint8)
+    l, u = slp.lp_bounds(x, delta, fixed=fixed)
+    assert np.all(l[fixed == 1] == 0.0) and np.all(u[fixed == 1] == 0.0)
+    b = (a @ l) + 0.41 * (a @ (u - l))
+    s, lam, ok = slp.lp_step(g, a, x, b, delta, fixed=fixed)
+    ref = linprog(g, A_eq=a[None, :], b_eq=[b], bounds=list(zip(l, u)), method="highs")
+    assert ok and ref.status == 0
+    assert abs(g @ s - ref.fun) <= 1e-9 * abs(ref.fun)
+    assert np.all(s[fixed == 1] == 0.0)

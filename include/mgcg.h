@@ -300,6 +300,14 @@ int mgcg_lp_destroy(mgcg_lp* lp);
 int mgcg_lp_set_stream(mgcg_lp* lp, void* stream);
 int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x, double b,
                   double delta, double x_l, double x_u, double* s, mgcg_lp_info* info, int mem);
+/* The same LP with fixed variables (Sec. 6.1: the design variables of fixed
+ * void and solid elements, e.g. design_fixed of mgcg_fix_variables): where
+ * fixed[i] != 0, l_i = u_i = 0, so s_i = 0 and the variable adds no capacity
+ * (also in the artificial problem).  fixed is uint8[n] in the same memory as
+ * the vectors; MGCG_EINVAL for a NULL fixed. */
+int mgcg_lp_solve_fixed(mgcg_lp* lp, const double* g, const double* a, const double* x,
+                        const uint8_t* fixed, double b, double delta, double x_l, double x_u,
+                        double* s, mgcg_lp_info* info, int mem);
 
 /* Density thresholding of Sec. 5, on the scratch of an LP object of n values
  * (same mem, stream and synchronisation rules as mgcg_lp_solve; each call

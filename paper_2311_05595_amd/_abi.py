@@ -136,6 +136,9 @@ EXPORTS = {
     "mgcg_fix_variables": (C.c_int, [C.POINTER(mgcg_fix_desc), C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(mgcg_fix_counts), C.c_int]),
+    "mgcg_lp_solve_fixed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_double, C.c_double, C.c_double, C.c_double,
+                                      C.c_void_p, C.POINTER(mgcg_lp_info), C.c_int]),
     "mgcg_slp_decide": (C.c_int, [C.POINTER(mgcg_slp_ctrl), C.c_double, C.c_double, C.c_double,
                                   C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.POINTER(C.c_double), C.POINTER(C.c_double),

@@ -409,12 +409,26 @@ class LP:
         out = np.empty(self.n) if out is None else out
         return out, C.c_void_p(out.ctypes.data)
 
-    def solve(self, g, a, x, b, delta, x_l=0.0, x_u=1.0, out=None):
+    def solve(self, g, a, x, b, delta, x_l=0.0, x_u=1.0, out=None, fixed=None):
+        """fixed: optional uint8 mask (numpy or device tensor, like g) of
+        variables held at s = 0 (Sec. 6.1)."""
         (pg, pa, px), mem, keep = self._vectors(g, a, x)
         out, ps = self._out(out, mem, keep[0])
         info = _abi.mgcg_lp_info()
-        check(self._lib.mgcg_lp_solve(self._h, pg, pa, px, float(b), float(delta), float(x_l),
-                                      float(x_u), ps, C.byref(info), mem))
+        if fixed is None:
+            check(self._lib.mgcg_lp_solve(self._h, pg, pa, px, float(b), float(delta),
+                                          float(x_l), float(x_u), ps, C.byref(info), mem))
+        else:
+            if _is_device_tensor(fixed):
+                if fixed.dtype != _torch().uint8 or not fixed.is_contiguous():
+                    raise TypeError("device fixed flags must be contiguous uint8")
+                pf, mem_f, kf = C.c_void_p(fixed.data_ptr()), MGCG_MEM_DEVICE, fixed
+            else:
+                pf, mem_f, kf = _ptr(fixed, dtype=np.uint8)
+            if mem_f != mem or (kf.numel() if mem == MGCG_MEM_DEVICE else kf.size) != self.n:
+                raise ValueError("fixed must be n flags in the vectors' memory")
+            check(self._lib.mgcg_lp_solve_fixed(self._h, pg, pa, px, pf, float(b), float(delta),
+                                                float(x_l), float(x_u), ps, C.byref(info), mem))
         return out, {"lambda": info.lambda_, "gts": info.gts, "ats": info.ats,
                      "s_inf": info.s_inf, "budget": info.budget,
                      "feasible": bool(info.feasible)}

@@ -391,7 +391,18 @@ int mgcg_lp_solve(mgcg_lp* lp, const double* g, const double* a, const double* x
                   double delta, double x_l, double x_u, double* s, mgcg_lp_info* info, int mem) {
   NEED(lp);
   GUARD({
-    lp->impl->solve(g, a, x, b, delta, x_l, x_u, s, info, mem);
+    lp->impl->solve(g, a, x, nullptr, b, delta, x_l, x_u, s, info, mem);
+    return MGCG_OK;
+  })
+}
+
+int mgcg_lp_solve_fixed(mgcg_lp* lp, const double* g, const double* a, const double* x,
+                        const uint8_t* fixed, double b, double delta, double x_l, double x_u,
+                        double* s, mgcg_lp_info* info, int mem) {
+  NEED(lp);
+  NEED(fixed);
+  GUARD({
+    lp->impl->solve(g, a, x, fixed, b, delta, x_l, x_u, s, info, mem);
     return MGCG_OK;
   })
 }

@@ -13,8 +13,10 @@ class Lp {
   ~Lp();
   static size_t device_bytes(long n);
   void set_stream(hipStream_t s);
-  void solve(const double* g, const double* a, const double* x, double b, double delta, double xl,
-             double xu, double* s, mgcg_lp_info* info, int mem);
+  // fixed (may be NULL): variables held at s = 0 (l = u = 0)
+  void solve(const double* g, const double* a, const double* x, const unsigned char* fixed,
+             double b, double delta, double xl, double xu, double* s, mgcg_lp_info* info,
+             int mem);
   long size() const { return n_; }
   // thresholding of Sec. 5 on n values
   void select_top(const double* v, long k, double* out, int mem);

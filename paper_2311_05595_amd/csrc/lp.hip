@@ -68,6 +68,7 @@ __global__ __launch_bounds__(LP_BS) void k_lp_prep(long n, const double* __restr
                                                    const double* __restrict__ a,
                                                    const double* __restrict__ x, double delta,
                                                    double xl, double xu,
+                                                   const unsigned char* __restrict__ fixed,
                                                    unsigned long long* __restrict__ key,
                                                    double* __restrict__ cap,
                                                    double* __restrict__ part, LpState* st) {
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(LP_BS) void k_lp_prep(long n, const double* __restr
   double al = 0.0, c = 0.0, aal = 0.0;
   if (i < n) {
     const double gi = g[i], ai = a[i], xi = x[i];
-    const double l = fmax(-delta, xl - xi), u = fmin(delta, xu - xi);
+    const bool fx = fixed && fixed[i];
+    const double l = fx ? 0.0 : fmax(-delta, xl - xi), u = fx ? 0.0 : fmin(delta, xu - xi);
     const bool ok = ai > 0.0 && isfinite(ai) && isfinite(gi) && isfinite(xi) && l <= u;
     if (!ok) st->bad = 1;
     c = ok ? ai * (u - l) : 0.0;
@@ -418,6 +420,7 @@ __global__ __launch_bounds__(LP_BS) void k_lp_fill(long n, const double* __restr
                                                    const double* __restrict__ a,
                                                    const double* __restrict__ x, double delta,
                                                    double xl, double xu,
+                                                   const unsigned char* __restrict__ fixed,
                                                    const unsigned long long* __restrict__ key,
                                                    const double* __restrict__ cap,
                                                    const double* __restrict__ toff,
@@ -434,8 +437,9 @@ __global__ __launch_bounds__(LP_BS) void k_lp_fill(long n, const double* __restr
     gi = g[i];
     ai = a[i];
     const double xi = x[i];
-    l = fmax(-delta, xl - xi);
-    u = fmin(delta, xu - xi);
+    const bool fx = fixed && fixed[i];
+    l = fx ? 0.0 : fmax(-delta, xl - xi);
+    u = fx ? 0.0 : fmin(delta, xu - xi);
     k = key[i];
     c = cap[i];
   }
@@ -487,7 +491,8 @@ __global__ __launch_bounds__(LP_BS) void k_lp_fill(long n, const double* __restr
 __global__ __launch_bounds__(LP_BS) void k_lp_box(long n, const double* __restrict__ g,
                                                   const double* __restrict__ a,
                                                   const double* __restrict__ x, double delta,
-                                                  double xl, double xu, int upper,
+                                                  double xl, double xu,
+                                                  const unsigned char* __restrict__ fixed, int upper,
                                                   double* __restrict__ s,
                                                   double* __restrict__ part) {
   __shared__ double sh[LP_BS / 64];
@@ -497,7 +502,8 @@ __global__ __launch_bounds__(LP_BS) void k_lp_box(long n, const double* __restri
     gi = g[i];
     ai = a[i];
     const double xi = x[i];
-    si = upper ? fmin(0.8 * delta, xu - xi) : fmax(-0.8 * delta, xl - xi);
+    si = (fixed && fixed[i]) ? 0.0
+                             : (upper ? fmin(0.8 * delta, xu - xi) : fmax(-0.8 * delta, xl - xi));
     s[i] = si;
   }
   const double p0 = block_sum_lp(gi * si, sh);
@@ -991,8 +997,9 @@ void Lp::set_stream(hipStream_t s) {
   stream_ = s;
 }
 
-void Lp::solve(const double* g, const double* a, const double* x, double b, double delta, double xl,
-               double xu, double* s, mgcg_lp_info* info, int mem) {
+void Lp::solve(const double* g, const double* a, const double* x, const unsigned char* fixed,
+               double b, double delta, double xl, double xu, double* s, mgcg_lp_info* info,
+               int mem) {
   if (!g || !a || !x || !s) throw Error(MGCG_EINVAL, "null vector");
   if (mem != MGCG_MEM_HOST && mem != MGCG_MEM_DEVICE) throw Error(MGCG_EINVAL, "bad mem flag");
   if (!(delta > 0.0) || !std::isfinite(delta) || !std::isfinite(b) || !std::isfinite(xl) ||
@@ -1009,7 +1016,7 @@ void Lp::solve(const double* g, const double* a, const double* x, double b, doub
     }
   } fr{stage};
   if (mem == MGCG_MEM_HOST) {
-    if (hipMalloc(&stage, (size_t)n_ * 8 * 4) != hipSuccess) {
+    if (hipMalloc(&stage, (size_t)n_ * 8 * 4 + (fixed ? (size_t)n_ : 0)) != hipSuccess) {
       (void)hipGetLastError();
       stage = nullptr;
       throw Error(MGCG_ENOMEM, "LP staging allocation failed");
@@ -1022,11 +1029,16 @@ void Lp::solve(const double* g, const double* a, const double* x, double b, doub
     da = base + n_;
     dx = base + 2 * n_;
     ds = base + 3 * n_;
+    if (fixed) {
+      unsigned char* df = (unsigned char*)(base + 4 * n_);
+      MGCG_HIP(hipMemcpyAsync(df, fixed, (size_t)n_, hipMemcpyHostToDevice, stream_));
+      fixed = df;
+    }
   }
   LpState* st = (LpState*)st_;
   MGCG_HIP(hipMemsetAsync(st, 0, sizeof(LpState), stream_));
   hipLaunchKernelGGL(k_lp_prep, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
-                     key_, cap_, part_, st);
+                     fixed, key_, cap_, part_, st);
   hipLaunchKernelGGL(k_lp_budget, dim3(1), dim3(LP_BS), 0, stream_, n_, nb_, b,
                      (const double*)part_, st);
   MGCG_HIP(hipGetLastError());
@@ -1051,10 +1063,12 @@ void Lp::solve(const double* g, const double* a, const double* x, double b, doub
                        tsum_);
     hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_);
     hipLaunchKernelGGL(k_lp_fill, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
+                       fixed,
                        (const unsigned long long*)key_, (const double*)cap_, (const double*)tsum_,
                        (const LpState*)st, ds, part_);
   } else {
     hipLaunchKernelGGL(k_lp_box, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
+                       fixed,
                        h.budget > h.capsum ? 1 : 0, ds, part_);
   }
   hipLaunchKernelGGL(k_lp_info, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, info_);

@@ -188,3 +188,37 @@ def test_slp_iterations_match_oracle():
     lp.close()
     pr.close()
     prob.close()
+
+
+@pytest.mark.parametrize("n,seed,frac,mem", [(257, 11, 0.37, "host"), (70001, 12, 0.55, "host"),
+                                            (70001, 13, 0.2, "device"), (3000, 14, -1.0, "host")])
+def test_lp_fixed_variables_match_oracle(n, seed, frac, mem):
+    """Fixed design variables (Sec. 6.1) held at s = 0, against the oracle's
+    LP with l = u = 0 there (frac < 0: an infeasible budget, the artificial
+    problem)."""
+    need_gpu()
+    import torch
+    from paper_2311_05595_amd import api
+    g, a, x, b, delta = _instance(n, seed, frac=max(frac, 0.0))
+    fixed = (np.random.default_rng(seed).random(n) < 0.3).astype(np.uint8)
+    l, u = slp.lp_bounds(x, delta, fixed=fixed)
+    b = float(a @ l + frac * (a @ (u - l))) if frac >= 0 else float(a @ l) - 1.0
+    lp = api.LP(n)
+    if mem == "device":
+        t = lambda v: torch.tensor(v, device="cuda")
+        s, info = lp.solve(t(g), t(a), t(x), b, delta, fixed=t(fixed))
+        s = s.cpu().numpy()
+    else:
+        s, info = lp.solve(g, a, x, b, delta, fixed=fixed)
+    s_o, lam_o, ok_o = slp.lp_step(g, a, x, b, delta, fixed=fixed)
+    assert info["feasible"] == ok_o
+    assert np.all(s[fixed == 1] == 0.0)
+    diff = np.flatnonzero(s != s_o)
+    assert diff.size <= 1
+    if diff.size:
+        k = diff[0]
+        l2, u2 = slp.lp_bounds(x, delta, fixed=fixed)
+        assert abs(s[k] - s_o[k]) <= 2 * n * np.finfo(float).eps * float(np.sum(a * (u2 - l2))) / a[k]
+    if ok_o:
+        assert info["lambda"] == lam_o
+    lp.close()

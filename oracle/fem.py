@@ -18,6 +18,15 @@ K^(e_i) per density sub-element, each computed once for a regular mesh).
 * Quadrature: p+1 Gauss-Legendre points per axis on each sub-box, which is
   exact for the polynomial integrand of degree <= 2p per axis.
 
+* Quadratic serendipity element (20 nodes, Sec. 2.1): the vertices and edge
+  midpoints of the 27-node layout, with the textbook shape functions
+  (vertex: (1 + xi xi_a)(1 + eta eta_a)(1 + zeta zeta_a)(xi xi_a + eta eta_a
+  + zeta zeta_a - 2) / 8; edge midpoint with xi_a = 0: (1 - xi^2)(1 + eta
+  eta_a)(1 + zeta zeta_a) / 4, and likewise).  Its matrices keep the 81-DOF
+  layout of the 27-node element with zero rows and columns at the 6 face
+  centres and the body centre, which a problem then fixes; 3 Gauss points
+  per axis integrate them exactly.
+
 Pins (tests/test_oracle_fem.py): symmetry; rank 3*n_e - 6 (Table 1: 18, 75,
 186); six rigid-body modes in the null space; the hand-derived diagonal
 (D11 + 2G)/9 of the unit Q1 cube; the strain energy of a uniform strain field
@@ -71,22 +80,65 @@ def elasticity_matrix(E=1.0, nu=0.3):
     return D
 
 
-def strain_displacement(order, xi, eta, zeta, half=(0.5, 0.5, 0.5)):
+def serendipity_node(a):
+    """True for the 20 nodes (vertices, edge midpoints) of the 27-node layout."""
+    ax, ay, az = a % 3, (a // 3) % 3, a // 9
+    return (ax == 1) + (ay == 1) + (az == 1) <= 1
+
+
+def serendipity_shapes(xi, eta, zeta):
+    """Values [27] and local gradients [27, 3] of the 20-node serendipity
+    shape functions in the 27-node layout (zero at the 7 other nodes)."""
+    N = np.zeros(27)
+    G = np.zeros((27, 3))
+    for a in range(27):
+        if not serendipity_node(a):
+            continue
+        c = (a % 3 - 1, (a // 3) % 3 - 1, a // 9 - 1)
+        t = (xi, eta, zeta)
+        if all(ci != 0 for ci in c):
+            f = [1.0 + t[d] * c[d] for d in range(3)]
+            s = t[0] * c[0] + t[1] * c[1] + t[2] * c[2] - 2.0
+            N[a] = f[0] * f[1] * f[2] * s / 8.0
+            for d in range(3):
+                o = [f[e] for e in range(3) if e != d]
+                G[a, d] = c[d] * o[0] * o[1] * (s + f[d]) / 8.0
+        else:
+            m = [d for d in range(3) if c[d] == 0][0]   # the axis of the midpoint
+            f = [1.0 - t[d] ** 2 if d == m else 1.0 + t[d] * c[d] for d in range(3)]
+            df = [-2.0 * t[d] if d == m else c[d] for d in range(3)]
+            N[a] = f[0] * f[1] * f[2] / 4.0
+            G[a, 0] = df[0] * f[1] * f[2] / 4.0
+            G[a, 1] = f[0] * df[1] * f[2] / 4.0
+            G[a, 2] = f[0] * f[1] * df[2] / 4.0
+    return N, G
+
+
+def strain_displacement(order, xi, eta, zeta, half=(0.5, 0.5, 0.5), family="lagrange"):
     """B (6 x 3*n_e) at one local point of an element of half-sizes
-    (l, h, w)."""
-    _, val, der = lagrange_1d(order)
-    vx, vy, vz = val(xi), val(eta), val(zeta)
-    dx, dy, dz = der(xi) / half[0], der(eta) / half[1], der(zeta) / half[2]
+    (l, h, w); family "serendipity" (order 2) keeps the 27-node layout."""
     p1 = order + 1
     nen = p1 ** 3
     B = np.zeros((6, 3 * nen))
+    if family == "serendipity":
+        if order != 2:
+            raise ValueError("the serendipity element here is quadratic")
+        _, G = serendipity_shapes(xi, eta, zeta)
+        G = G / np.asarray(half)
+    else:
+        _, val, der = lagrange_1d(order)
+        vx, vy, vz = val(xi), val(eta), val(zeta)
+        dx, dy, dz = der(xi) / half[0], der(eta) / half[1], der(zeta) / half[2]
     for az in range(p1):
         for ay in range(p1):
             for ax in range(p1):
                 a = ax + p1 * (ay + p1 * az)
-                gx = dx[ax] * vy[ay] * vz[az]
-                gy = vx[ax] * dy[ay] * vz[az]
-                gz = vx[ax] * vy[ay] * dz[az]
+                if family == "serendipity":
+                    gx, gy, gz = G[a]
+                else:
+                    gx = dx[ax] * vy[ay] * vz[az]
+                    gy = vx[ax] * dy[ay] * vz[az]
+                    gz = vx[ax] * vy[ay] * dz[az]
                 u, v, w = 3 * a, 3 * a + 1, 3 * a + 2
                 B[0, u] = gx
                 B[1, v] = gy
@@ -97,7 +149,7 @@ def strain_displacement(order, xi, eta, zeta, half=(0.5, 0.5, 0.5)):
     return B
 
 
-def sub_element_matrices(order, nsub, nu=0.3, E=1.0, half=(0.5, 0.5, 0.5)):
+def sub_element_matrices(order, nsub, nu=0.3, E=1.0, half=(0.5, 0.5, 0.5), family="lagrange"):
     """The n^3 matrices K^(e_i) of one displacement element (Sec. 3.3), as an
     array [n^3, 3n_e, 3n_e]; sub-element i = sx + n*(sy + n*sz)."""
     D = elasticity_matrix(E, nu)
@@ -119,16 +171,27 @@ def sub_element_matrices(order, nsub, nu=0.3, E=1.0, half=(0.5, 0.5, 0.5)):
                         for qx, wx in zip(gp, gw):
                             B = strain_displacement(
                                 order, mid[0] + rad[0] * qx, mid[1] + rad[1] * qy,
-                                mid[2] + rad[2] * qz, half)
+                                mid[2] + rad[2] * qz, half, family)
                             wgt = wx * wy * wz * rad[0] * rad[1] * rad[2] * jac
                             K += wgt * (B.T @ D @ B)
                 out[sx + nsub * (sy + nsub * sz)] = K
     return out
 
 
-def element_matrix(order, nu=0.3, E=1.0):
+def element_matrix(order, nu=0.3, E=1.0, family="lagrange"):
     """Single-resolution element stiffness, integral over the whole element."""
-    return sub_element_matrices(order, 1, nu, E)[0]
+    return sub_element_matrices(order, 1, nu, E, family=family)[0]
+
+
+def serendipity_dof_mask(nel):
+    """DOF mask (3 per node) of the 27-node lattice of a mesh marking the face
+    centres and body centres, which no serendipity element uses."""
+    nelx, nely, nelz = nel
+    i = np.arange(2 * nelx + 1) % 2
+    j = np.arange(2 * nely + 1) % 2
+    k = np.arange(2 * nelz + 1) % 2
+    odd = k[:, None, None] + j[None, :, None] + i[None, None, :]
+    return np.repeat((odd >= 2).reshape(-1), 3).astype(np.uint8)
 
 
 def local_node_coords(order):

@@ -67,6 +67,14 @@ extern "C" {
 #define MGCG_FP64 0  /* FP64 everywhere */
 #define MGCG_MIXED 1 /* FP32 V-cycle inside an FP64 CG (FP64 coarsest Cholesky) */
 
+/* Element families (Sec. 2.1).  MGCG_SERENDIPITY needs order 2: the 20-node
+ * quadratic serendipity element (vertices and edge midpoints).  It runs on
+ * the 27-node lattice of order 2; the DOFs of face centres and body centres,
+ * which no serendipity element uses, are fixed by the library (their loads
+ * ignored, their displacements 0). */
+#define MGCG_LAGRANGE 0
+#define MGCG_SERENDIPITY 1
+
 #define MGCG_MEM_HOST 0
 #define MGCG_MEM_DEVICE 1
 
@@ -86,6 +94,8 @@ typedef struct mgcg_desc {
   int32_t pre, post;        /* weighted-Jacobi sweeps before / after the coarse correction */
   double E0, Emin, nu, penal; /* solid modulus, void modulus, Poisson ratio, SIMP p */
   double omega;             /* Jacobi weight */
+  int32_t family;           /* MGCG_LAGRANGE or MGCG_SERENDIPITY (order 2) */
+  int32_t pad;
 } mgcg_desc;
 
 /* Result of one solve. */

@@ -34,7 +34,8 @@ class mgcg_desc(C.Structure):
                 ("order", C.c_int32), ("nsub", C.c_int32), ("nlevels", C.c_int32),
                 ("nrhs", C.c_int32), ("precision", C.c_int32), ("pre", C.c_int32),
                 ("post", C.c_int32), ("E0", C.c_double), ("Emin", C.c_double),
-                ("nu", C.c_double), ("penal", C.c_double), ("omega", C.c_double)]
+                ("nu", C.c_double), ("penal", C.c_double), ("omega", C.c_double),
+                ("family", C.c_int32), ("pad", C.c_int32)]
 
 
 class mgcg_info(C.Structure):

@@ -66,10 +66,49 @@ void basis_1d(int p, double t, double* l, double* d) {
   }
 }
 
+// Local gradients of the 20-node serendipity shape functions at (t0, t1, t2),
+// written into the 27-node layout (zero at face and body centres).  Node a
+// has local coordinates c_d = a_d - 1 in {-1, 0, 1}.  A vertex function is
+// (1 + c0 t0)(1 + c1 t1)(1 + c2 t2)(c0 t0 + c1 t1 + c2 t2 - 2) / 8; an edge
+// midpoint with c_m = 0 has (1 - t_m^2) times the two linear factors, / 4.
+void serendipity_grad(const double t[3], double* grad) {
+  for (int a = 0; a < 27; ++a) {
+    const int c[3] = {a % 3 - 1, (a / 3) % 3 - 1, a / 9 - 1};
+    const int zeros = (c[0] == 0) + (c[1] == 0) + (c[2] == 0);
+    double* g = &grad[3 * a];
+    g[0] = g[1] = g[2] = 0.0;
+    if (zeros == 0) {
+      double f[3];
+      for (int d = 0; d < 3; ++d) f[d] = 1.0 + c[d] * t[d];
+      const double s = c[0] * t[0] + c[1] * t[1] + c[2] * t[2] - 2.0;
+      for (int d = 0; d < 3; ++d) {
+        const double others = f[(d + 1) % 3] * f[(d + 2) % 3];
+        g[d] = 0.125 * c[d] * others * (s + f[d]);
+      }
+    } else if (zeros == 1) {
+      double f[3], df[3];
+      for (int d = 0; d < 3; ++d) {
+        if (c[d] == 0) {
+          f[d] = 1.0 - t[d] * t[d];
+          df[d] = -2.0 * t[d];
+        } else {
+          f[d] = 1.0 + c[d] * t[d];
+          df[d] = c[d];
+        }
+      }
+      g[0] = 0.25 * df[0] * f[1] * f[2];
+      g[1] = 0.25 * f[0] * df[1] * f[2];
+      g[2] = 0.25 * f[0] * f[1] * df[2];
+    }
+  }
+}
+
 }  // namespace
 
-std::vector<double> sub_element_matrices(int order, int nsub, double nu) {
+std::vector<double> sub_element_matrices(int order, int nsub, double nu, int family) {
   if (order < 1 || order > 2 || nsub < 1) throw std::invalid_argument("element order/nsub");
+  if (family != 0 && !(family == 1 && order == 2))
+    throw std::invalid_argument("the serendipity element is quadratic");
   const int p1 = order + 1;
   const int nen = p1 * p1 * p1;
   const int nd = 3 * nen;
@@ -97,21 +136,27 @@ std::vector<double> sub_element_matrices(int order, int nsub, double nu) {
           for (int qy = 0; qy < p1; ++qy)
             for (int qx = 0; qx < p1; ++qx) {
               const int q[3] = {qx, qy, qz};
-              double L[3][4], D[3][4];
+              double L[3][4], D[3][4], tq[3];
               double wq = jac;
               for (int d = 0; d < 3; ++d) {
                 double t = lo[d] + half[d] * (gx[q[d]] + 1.0);
+                tq[d] = t;
                 basis_1d(order, t, L[d], D[d]);
                 wq *= gw[q[d]] * half[d];
               }
-              for (int az = 0; az < p1; ++az)
-                for (int ay = 0; ay < p1; ++ay)
-                  for (int ax = 0; ax < p1; ++ax) {
-                    int a = ax + p1 * (ay + p1 * az);
-                    grad[3 * a + 0] = dxi_dx * D[0][ax] * L[1][ay] * L[2][az];
-                    grad[3 * a + 1] = dxi_dx * L[0][ax] * D[1][ay] * L[2][az];
-                    grad[3 * a + 2] = dxi_dx * L[0][ax] * L[1][ay] * D[2][az];
-                  }
+              if (family == 1) {
+                serendipity_grad(tq, grad.data());
+                for (double& v : grad) v *= dxi_dx;
+              } else {
+                for (int az = 0; az < p1; ++az)
+                  for (int ay = 0; ay < p1; ++ay)
+                    for (int ax = 0; ax < p1; ++ax) {
+                      int a = ax + p1 * (ay + p1 * az);
+                      grad[3 * a + 0] = dxi_dx * D[0][ax] * L[1][ay] * L[2][az];
+                      grad[3 * a + 1] = dxi_dx * L[0][ax] * D[1][ay] * L[2][az];
+                      grad[3 * a + 2] = dxi_dx * L[0][ax] * L[1][ay] * D[2][az];
+                    }
+              }
               for (int a = 0; a < nen; ++a)
                 for (int b = 0; b < nen; ++b) {
                   const double* ga = &grad[3 * a];

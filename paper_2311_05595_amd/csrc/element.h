@@ -10,7 +10,9 @@ namespace mgcg {
 // Poisson ratio nu, as [n^3][nd][nd] row-major, nd = 3 * (order+1)^3.
 // Sub-element i = sx + n*(sy + n*sz); local node a = ax + (p+1)*(ay + (p+1)*az);
 // local DOF 3a + c.
-std::vector<double> sub_element_matrices(int order, int nsub, double nu);
+// family 0: Lagrange (8 or 27 nodes); 1: quadratic serendipity (order 2, the
+// 20 nodes in the 27-node layout, zero rows and columns elsewhere)
+std::vector<double> sub_element_matrices(int order, int nsub, double nu, int family = 0);
 
 // Trilinear weight of coarse vertex b (bits x,y,z of b in {0,1}) at the
 // node with coarse-local lattice position (px,py,pz) in {0,1,2}^3 (spacing

@@ -44,6 +44,8 @@ void validate(const mgcg_desc& d) {
   if (!(d.nu > -1.0 && d.nu < 0.5)) bad("nu must be in (-1, 0.5)");
   if (!(d.penal >= 1.0 && d.penal <= 10.0)) bad("penal must be in [1, 10]");
   if (d.order == 2 && d.nlevels < 2) bad("quadratic elements need nlevels >= 2");
+  if (d.family != MGCG_LAGRANGE && !(d.family == MGCG_SERENDIPITY && d.order == 2))
+    bad("family must be Lagrange, or serendipity with order 2");
 }
 
 }  // namespace
@@ -215,6 +217,14 @@ Problem::Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int d
       if (mask[3 * n + c]) m |= (uint8_t)(1 << c);
     hmask_[n] = m;
   }
+  if (d_.family == MGCG_SERENDIPITY) {
+    // face and body centres of the 27-node lattice (two or three odd indices)
+    const Lat L0 = lv_[0].L;
+    for (long n = 0; n < L0.nn(); ++n) {
+      const long i = n % L0.nx, j = (n / L0.nx) % L0.ny, k = n / ((long)L0.nx * L0.ny);
+      if ((i & 1) + (j & 1) + (k & 1) >= 2) hmask_[n] = 7;
+    }
+  }
   for (size_t l = 1; l < lv_.size(); ++l) {
     const Lat F = lv_[l - 1].L, C = lv_[l].L;
     const int stride = 2;  // both Q1 halving and the Q2 -> vertex lattice step
@@ -228,7 +238,7 @@ Problem::Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int d
   hf_.assign(f, f + (size_t)d_.nrhs * nd0);
   for (int r = 0; r < d_.nrhs; ++r)
     for (long i = 0; i < nd0; ++i)
-      if (mask[i]) hf_[(size_t)r * nd0 + i] = 0.0;
+      if ((hmask_[i / 3] >> (i % 3)) & 1) hf_[(size_t)r * nd0 + i] = 0.0;
   for (double v : hf_)
     if (!std::isfinite(v)) throw Error(MGCG_EINVAL, "non-finite load");
   // coarsest free DOF list
@@ -241,7 +251,7 @@ Problem::Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int d
         hfree_.push_back((int)(3 * n + c));
       }
   nc_ = (int)hfree_.size();
-  hKsub_ = sub_element_matrices(d_.order, d_.nsub, d_.nu);
+  hKsub_ = sub_element_matrices(d_.order, d_.nsub, d_.nu, d_.family);
   B_.resize(lv_.size());
   if (lv_.size() >= 2) build_linear_galerkin();
   // unit trilinear element as 10 class values; must reproduce the quadrature

@@ -44,6 +44,10 @@ def test_desc_validation_and_sizes():
     assert api.device_bytes(nel=(24, 12, 12), nrhs=5) == 0
     assert api.device_bytes(nel=(24, 12, 12), order=3) == 0
     assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=1) == 0
+    # the serendipity family is quadratic only
+    assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2, family="serendipity") > 0
+    assert api.device_bytes(nel=(4, 2, 2), order=1, nlevels=2, family="serendipity") == 0
+    assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2, family=2) == 0
     # bytes grow with precision, nrhs and nsub
     b64 = api.device_bytes(nel=(32, 16, 16), nlevels=3)
     b2 = api.device_bytes(nel=(32, 16, 16), nlevels=3, nrhs=2)

@@ -7,7 +7,7 @@ operators, Jacobi data, coarsest Cholesky), a warm-started MGCG solve to a
 1e-8 relative residual, and compliance + sensitivity.  The ten perturbed
 fields are generated and uploaded before timing; steps cycle through them.
 
-Prints one JSON line (see the fields below).  `--config c3|c4` times the
+Prints one JSON line (see the fields below).  `--config c3|c4|c4s` times the
 other single-GPU workloads the same way (not the default line).
 `--copy-probe MIB` only runs the library's plain copy kernel on MIB MiB
 (the calibration run for the HBM byte counters) and exits.
@@ -153,9 +153,12 @@ def cpu_baseline(cfg, rho_fields, budget_s=25.0):
     from workloads import configs as CF
     mask, f = CF.problem(cfg)
     nel, order, nsub = cfg["nel"], cfg["order"], cfg["nsub"]
+    family = cfg.get("family", "lagrange")
+    if family == "serendipity":
+        mask = np.maximum(mask, fem.serendipity_dof_mask(nel))
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        Ks = fem.sub_element_matrices(order, nsub)
+        Ks = fem.sub_element_matrices(order, nsub, family=family)
         K = assemble.stiffness(rho_fields[0], nel, order, nsub, Ks)
         A0 = assemble.level_operator(K, mask)
         H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, order), cfg["nlevels"])
@@ -221,7 +224,8 @@ def run(args):
     dfields = [torch.tensor(r.ravel(), dtype=torch.float64, device=dev) for r in fields]
     prob = api.Problem(cfg["nel"], mask, f, order=cfg["order"], nsub=cfg["nsub"],
                        nlevels=cfg["nlevels"], precision=args.precision or cfg["precision"],
-                       omega=cfg["omega"], pre=cfg["pre"], post=cfg["post"])
+                       omega=cfg["omega"], pre=cfg["pre"], post=cfg["post"],
+                       family=cfg.get("family", "lagrange"))
     prob.use_torch_stream()
     dc = torch.empty(prob.nrho, dtype=torch.float64, device=dev)
     free = int((mask == 0).sum()) * prob.nrhs

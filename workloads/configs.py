@@ -33,6 +33,13 @@ CONFIGS = {
                nel=(48, 24, 24), order=2, nsub=4, nlevels=5, nrhs=2,
                precision="mixed", omega=0.6, pre=1, post=1,
                field="grf", seed=4),
+    # the quadratic serendipity element on the c4 mesh, tip load only (the
+    # top pressure's consistent loads fall on face centres, which that element
+    # does not have)
+    "c4s": dict(name="cantilever S2 48x24x24 n=4 mixed", kind="cantilever",
+                nel=(48, 24, 24), order=2, nsub=4, nlevels=5, nrhs=1,
+                precision="mixed", omega=0.6, pre=1, post=1,
+                field="grf", seed=4, family="serendipity"),
 }
 
 SERVE_MESHES = [(32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48), (128, 64, 64)]

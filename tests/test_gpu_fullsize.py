@@ -23,10 +23,11 @@ def _run(name, rtol):
     mask, f = CF.problem(cfg)
     rho = CF.densities(cfg)
     nel, order, nsub = cfg["nel"], cfg["order"], cfg["nsub"]
+    family = cfg.get("family", "lagrange")
     print(f"[fullsize] {cfg['name']} rtol={rtol}", flush=True)
     p = api.Problem(nel, mask, f, order=order, nsub=nsub, nlevels=cfg["nlevels"],
                     precision=cfg["precision"], omega=cfg["omega"], pre=cfg["pre"],
-                    post=cfg["post"])
+                    post=cfg["post"], family=family)
     p.use_torch_stream()
     p.set_densities(torch.tensor(rho.ravel(), dtype=torch.float64, device="cuda"))
     info = p.solve(rtol=rtol, maxit=5000, warm_start=False)
@@ -34,7 +35,9 @@ def _run(name, rtol):
     u = p.displacement()
     c, dc = p.compliance_sensitivity()
     p.close()
-    Ks = fem.sub_element_matrices(order, nsub)
+    Ks = fem.sub_element_matrices(order, nsub, family=family)
+    if family == "serendipity":   # the library fixes the unused face and body centres
+        mask = np.maximum(mask, fem.serendipity_dof_mask(nel))
     Ku = assemble.apply(rho, nel, order, nsub, Ks, u, **MAT)
     free = mask == 0
     for l in range(cfg["nrhs"]):
@@ -70,3 +73,8 @@ def test_cantilever_64x32x32_n4_mixed():
 def test_cantilever_q2_48x24x24_n4_two_load_cases_mixed():
     need_gpu()
     _run("c4", 1e-8)
+
+
+def test_cantilever_serendipity_48x24x24_n4_mixed():
+    need_gpu()
+    _run("c4s", 1e-8)

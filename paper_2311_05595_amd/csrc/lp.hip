@@ -711,9 +711,15 @@ struct LgState {
   double wsum;                // |g|^2
   double amax;                // largest finite alpha_i
   double alpha;               // alpha~
+  // after the compaction: the sums of the items below the bracket
+  // (sum g^2 alpha, sum g^2 alpha^2), the weight above it (sum g^2) and the
+  // number of items inside it, which alone are read from then on
+  double c1, c2, whi;
+  double mid;
 };
 static_assert(sizeof(LgState) <= 256, "the state shares the LP state's slot");
 constexpr int LG_PTS = 15;    // interior points of the search per pass
+constexpr int LG_FULL = 4;    // passes over every item before the compaction
 
 __device__ __forceinline__ double lg_alpha(double r, double g) {
   return g > 0.0 ? r / g : (g < 0.0 ? (1.0 - r) / -g : INFINITY);
@@ -781,6 +787,10 @@ __global__ __launch_bounds__(LP_BS) void k_lg_init(int nb, const double* __restr
     st->wsum = ws;
     st->amax = am;
     st->alpha = 0.0;
+    st->c1 = 0.0;
+    st->c2 = 0.0;
+    st->whi = 0.0;
+    st->mid = 0.0;
     st->lo = 0ull;
     // every alpha_i beyond amax gives the cosine at amax: search [0, nextafter(amax))
     const double cap = fmin(vmin, nextafter(am, INFINITY));
@@ -796,7 +806,7 @@ __device__ __forceinline__ double lg_point(unsigned long long lo, unsigned long 
 
 // Block partials of sum g^2 m and sum g^2 m^2 at the LG_PTS interior points.
 __global__ __launch_bounds__(LP_BS) void k_lg_split(long n, const double* __restrict__ alpha,
-                                                    const double* __restrict__ w,
+                                                    const double* __restrict__ w, int step,
                                                     const LgState* st, double* __restrict__ part) {
   __shared__ double sh[LP_BS / 64][2 * LG_PTS];
   const unsigned long long lo = st->lo, hi = st->hi;
@@ -810,7 +820,7 @@ __global__ __launch_bounds__(LP_BS) void k_lg_split(long n, const double* __rest
   const long stride = (long)gridDim.x * LP_BS;
   if (hi - lo > 1ull) {
     for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
-      const double a = alpha[i], wi = w[i];
+      const double a = alpha[i * step], wi = w[i * step];
 #pragma unroll
       for (int p = 0; p < LG_PTS; ++p) {
         const double m = fmin(x[p], a);
@@ -872,7 +882,10 @@ __global__ __launch_bounds__(LP_BS) void k_lg_pick(int nblk, const double* __res
       const double xp = lg_point(lo, hi, p + 1);
       const unsigned long long xb = (unsigned long long)__double_as_longlong(xp);
       if (xb <= nlo || xb >= nhi) continue;
-      const double c = tot[p] / (gn * sqrt(tot[LG_PTS + p]));
+      // the items outside the bracket once compacted (zeros before)
+      const double s1 = tot[p] + (st->c1 + xp * st->whi);
+      const double s2 = tot[LG_PTS + p] + (st->c2 + xp * xp * st->whi);
+      const double c = s1 / (gn * sqrt(s2));
       if (c > cmax)
         nlo = xb;
       else
@@ -880,6 +893,114 @@ __global__ __launch_bounds__(LP_BS) void k_lg_pick(int nblk, const double* __res
     }
     st->lo = nlo;
     st->hi = nhi;
+  }
+}
+
+// Compaction of the search once the bracket (lo, hi) is narrow: items below
+// it enter every later sum as constants (g^2 alpha, g^2 alpha^2), items above
+// it as g^2 x and g^2 x^2; only the items inside are kept, in index order.
+__device__ __forceinline__ int lg_side(double a, unsigned long long lo, unsigned long long hi) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(a);
+  return b <= lo ? -1 : (b >= hi ? 1 : 0);
+}
+__global__ __launch_bounds__(LP_BS) void k_lg_cls(long n, const double* __restrict__ alpha,
+                                                  const double* __restrict__ w, const LgState* st,
+                                                  double* __restrict__ part,
+                                                  double* __restrict__ counts) {
+  __shared__ double sh[LP_BS / 64];
+  const unsigned long long lo = st->lo, hi = st->hi;
+  double cnt = 0.0, c1 = 0.0, c2 = 0.0, wh = 0.0;
+  const long stride = (long)gridDim.x * LP_BS;
+  for (long i = (long)blockIdx.x * LP_BS + threadIdx.x; i < n; i += stride) {
+    const double a = alpha[i], wi = w[i];
+    const int sd = lg_side(a, lo, hi);
+    if (sd < 0) {
+      c1 += wi * a;
+      c2 += wi * a * a;
+    } else if (sd > 0) {
+      wh += wi;
+    } else {
+      cnt += 1.0;
+    }
+  }
+  cnt = block_sum_lp(cnt, sh);
+  c1 = block_sum_lp(c1, sh);
+  c2 = block_sum_lp(c2, sh);
+  wh = block_sum_lp(wh, sh);
+  if (threadIdx.x == 0) {
+    counts[blockIdx.x] = cnt;
+    part[gridDim.x + blockIdx.x] = c1;
+    part[2 * gridDim.x + blockIdx.x] = c2;
+    part[3 * gridDim.x + blockIdx.x] = wh;
+  }
+}
+// The constants and the number of items inside the bracket, in block order
+// (the per-block counts are then scanned in place by k_lp_tiescan).
+__global__ __launch_bounds__(LP_BS) void k_lg_cls_fin(int nblk, const double* __restrict__ part,
+                                                      const double* __restrict__ counts,
+                                                      LgState* st) {
+  __shared__ double sh[LP_BS / 64];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < nblk; j += LP_BS) {
+    v[0] += counts[j];
+    for (int q = 1; q < 4; ++q) v[q] += part[q * nblk + j];
+  }
+  const double m = block_sum_lp(v[0], sh);
+  const double c1 = block_sum_lp(v[1], sh);
+  const double c2 = block_sum_lp(v[2], sh);
+  const double wh = block_sum_lp(v[3], sh);
+  if (threadIdx.x == 0) {
+    st->c1 = c1;
+    st->c2 = c2;
+    st->whi = wh;
+    st->mid = m;
+  }
+}
+// The items inside the bracket as (alpha, g^2) pairs, in the order of the
+// grid-stride walk of k_lg_cls (block by block, then iteration, then thread).
+__global__ __launch_bounds__(LP_BS) void k_lg_cmp_write(long n, const double* __restrict__ alpha,
+                                                        const double* __restrict__ w,
+                                                        const LgState* st,
+                                                        const double* __restrict__ off,
+                                                        double* __restrict__ pairs) {
+  __shared__ int wc[LP_BS / 64];
+  const unsigned long long lo = st->lo, hi = st->hi;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long pos = (long)off[blockIdx.x];
+  const long stride = (long)gridDim.x * LP_BS;
+  for (long base = (long)blockIdx.x * LP_BS; base < n; base += stride) {
+    const long i = base + threadIdx.x;
+    double a = 0.0, wi = 0.0;
+    bool in = false;
+    if (i < n) {
+      a = alpha[i];
+      wi = w[i];
+      in = lg_side(a, lo, hi) == 0;
+    }
+    const unsigned long long m = __ballot(in);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wc[wv] = __popcll(m);
+    __syncthreads();
+    long before = 0, total = 0;
+    for (int q = 0; q < LP_BS / 64; ++q) {
+      if (q < wv) before += wc[q];
+      total += wc[q];
+    }
+    if (in) {
+      const long j = pos + before + below;
+      pairs[2 * j] = a;
+      pairs[2 * j + 1] = wi;
+    }
+    pos += total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_lg_uncompact(LgState* st) {
+  if (threadIdx.x == 0) {
+    st->c1 = 0.0;
+    st->c2 = 0.0;
+    st->whi = 0.0;
   }
 }
 
@@ -1272,11 +1393,50 @@ double Lp::lagrangian(const double* rho, const double* gl, double vu, double vl,
   std::memcpy(&h, hst_, sizeof h);
   if (h.bad) throw Error(MGCG_EINVAL, "non-finite density or gradient");
   hipLaunchKernelGGL(k_lg_init, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)part_, lg);
-  for (int pass = 0; pass < 16; ++pass) {
+  // bins_ holds the split partials (2 LG_PTS per block) in front and, after
+  // LG_FULL passes over every item, the items still inside the bracket
+  double* pairs = bins_ + (size_t)2 * LG_PTS * ns_;
+  const long cap_pairs = ((long)nh_ * 256 - 2L * LG_PTS * ns_) / 2;
+  int pass = 0;
+  for (; pass < LG_FULL; ++pass) {
     hipLaunchKernelGGL(k_lg_split, dim3(ns_), dim3(LP_BS), 0, stream_, n_, (const double*)alpha,
-                       (const double*)cap_, (const LgState*)lg, bins_);
+                       (const double*)cap_, 1, (const LgState*)lg, bins_);
     hipLaunchKernelGGL(k_lg_pick, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)bins_,
                        cmax, lg);
+  }
+  hipLaunchKernelGGL(k_lg_cls, dim3(ns_), dim3(LP_BS), 0, stream_, n_, (const double*)alpha,
+                     (const double*)cap_, (const LgState*)lg, bins_, part_);
+  hipLaunchKernelGGL(k_lg_cls_fin, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)bins_,
+                     (const double*)part_, lg);
+  hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, ns_, part_);
+  MGCG_HIP(hipGetLastError());
+  MGCG_HIP(hipMemcpyAsync(hst_, lg, sizeof(LgState), hipMemcpyDeviceToHost, stream_));
+  MGCG_HIP(hipStreamSynchronize(stream_));
+  LgState mid;
+  std::memcpy(&mid, hst_, sizeof mid);
+  const long m = (long)mid.mid;
+  if (m <= cap_pairs) {
+    hipLaunchKernelGGL(k_lg_cmp_write, dim3(ns_), dim3(LP_BS), 0, stream_, n_,
+                       (const double*)alpha, (const double*)cap_, (const LgState*)lg,
+                       (const double*)part_, pairs);
+    long nsc = (m + LP_BS * 4 - 1) / (LP_BS * 4);
+    nsc = nsc < 1 ? 1 : (nsc > ns_ ? ns_ : nsc);
+    for (; pass < 16; ++pass) {
+      hipLaunchKernelGGL(k_lg_split, dim3(nsc), dim3(LP_BS), 0, stream_, m,
+                         (const double*)pairs, (const double*)pairs + 1, 2, (const LgState*)lg,
+                         bins_);
+      hipLaunchKernelGGL(k_lg_pick, dim3(1), dim3(LP_BS), 0, stream_, (int)nsc,
+                         (const double*)bins_, cmax, lg);
+    }
+  } else {
+    // too many items left inside the bracket for the scratch: no compaction
+    hipLaunchKernelGGL(k_lg_uncompact, dim3(1), dim3(64), 0, stream_, lg);
+    for (; pass < 16; ++pass) {
+      hipLaunchKernelGGL(k_lg_split, dim3(ns_), dim3(LP_BS), 0, stream_, n_, (const double*)alpha,
+                         (const double*)cap_, 1, (const LgState*)lg, bins_);
+      hipLaunchKernelGGL(k_lg_pick, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)bins_,
+                         cmax, lg);
+    }
   }
   hipLaunchKernelGGL(k_lg_best, dim3(ns_), dim3(LP_BS), 0, stream_, n_, (const double*)alpha,
                      (const LgState*)lg, part_);

@@ -240,3 +240,18 @@ def test_lagrangian_threshold_full_size():
     idx = np.random.default_rng(14).choice(n, 4096, replace=False)
     assert np.array_equal(out[idx], T.lagrangian_step(rho[idx], g[idx], a))
     lp.close()
+
+
+def test_lagrangian_threshold_all_equal_steps():
+    """Every density at the same step (rho = 0.5, g = 1): the bracket keeps
+    all of them inside, more than the compaction's scratch holds, so the
+    search stays on the full arrays; alpha~ = 0.5 and every density goes to 0."""
+    need_gpu()
+    from paper_2311_05595_amd import api
+    n = 1000
+    rho, g = np.full(n, 0.5), np.ones(n)
+    lp = api.LP(n)
+    out, a = lp.lagrangian_threshold(rho, g)
+    ref, a_o = T.lagrangian_threshold(rho, g)
+    assert a == a_o == 0.5 and np.array_equal(out, ref) and np.all(out == 0.0)
+    lp.close()

@@ -109,7 +109,7 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n, "launches": 5}), flush=True)
 
 
-def fine_apply_model(nel, nsub, order, nrhs=1):
+def fine_apply_model(nel, nsub, order, nrhs=1, family="lagrange"):
     """The finest-level operator of a workload and the algorithmic work of one
     CG apply q = A p with it (per launch = all elements and load cases):
     * trilinear, one density per element (matrix-free, unit element matrix
@@ -119,7 +119,9 @@ def fine_apply_model(nel, nsub, order, nrhs=1):
       symmetric half: 14 blocks of 3x3 per node): bytes: the 126 stencil
       coefficients per node, read p, write q.  Bound: HBM.
     * triquadratic (stored symmetric 81x81 element matrices): bytes: the
-      3321 distinct coefficients per element, read p, write q.  Bound: HBM."""
+      3321 distinct coefficients per element, read p, write q.  Bound: HBM.
+    * quadratic serendipity (stored symmetric 60x60 element matrices): the
+      1830 distinct coefficients per element, read p, write q.  Bound: HBM."""
     nx, ny, nz = nel
     nelem = nx * ny * nz
     nn = (order * nx + 1) * (order * ny + 1) * (order * nz + 1)
@@ -134,6 +136,12 @@ def fine_apply_model(nel, nsub, order, nrhs=1):
                     kernel="finest-level CG apply q = A p, 27-point stencil (FP64)",
                     per_unit="126 x 8 B of coefficients per node + 48 B of vectors per node "
                              "and load case")
+    if family == "serendipity":
+        return dict(bound="hbm", flops=2.0 * 3600 * nelem * nrhs, bytes=vec + 8.0 * 1830 * nelem,
+                    kernel="finest-level CG apply q = A p, stored symmetric 60x60 serendipity "
+                           "element matrices (FP64)",
+                    per_unit="1830 x 8 B of element matrix (distinct entries) per element + 48 B "
+                             "of vectors per node and load case")
     return dict(bound="hbm", flops=2.0 * 6561 * nelem * nrhs, bytes=vec + 8.0 * 3321 * nelem,
                 kernel="finest-level CG apply q = A p, stored symmetric 81x81 element matrices "
                        "(FP64)",
@@ -257,7 +265,8 @@ def run(args):
     kms, kn = prob.kernel_timing(0)
     prob.set_kernel_timing(0, False)
 
-    m = fine_apply_model(cfg["nel"], cfg["nsub"], cfg["order"], prob.nrhs)
+    m = fine_apply_model(cfg["nel"], cfg["nsub"], cfg["order"], prob.nrhs,
+                         cfg.get("family", "lagrange"))
     avg_s = (kms / kn) * 1e-3 if kn else float("nan")
     if m["bound"] == "alu":
         achieved, peak, unit = m["flops"] / avg_s / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"

@@ -414,6 +414,94 @@ __global__ __launch_bounds__(BS) void k_eq2_elem(OpEQ2<T> op, In in, int nrhs,
   (void)by;
 }
 
+// First pass for serendipity elements: the same scheme over their 60 DOFs,
+// four elements per block (240 of 256 threads busy).  Row i is D[0][i],
+// D[s][i] and D[s][i - s] for s = 1..29, and D[30][i] once (columns i + 30
+// and i - 30 coincide mod 60).  y_e is written at the DOFs of the 27-node
+// layout; the 7 other nodes of each element are fixed, and the gather
+// replaces their rows by the input.
+constexpr int ES_EPB = 4;
+template <typename T, int NR, class In>
+__global__ __launch_bounds__(BS) void k_es2_elem(OpEQ2<T> op, In in, int nrhs,
+                                                  const CgScalars* gate, int gate_state) {
+  const Gate g = gate_load(gate, nrhs, gate_state);
+  if (gate_state == CG_CHECK && !gate_open(g)) return;
+  __shared__ T ue[NR][ES_EPB][60];
+  int bx, by;
+  xcd_tile(bx, by);
+  const Lat L = op.L;
+  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
+  const long nel = (long)nex * ney * nez;
+  const int le = threadIdx.x / 60, row = threadIdx.x - 60 * le;
+  const long e = (long)bx * ES_EPB + le;
+  const bool on = le < ES_EPB && e < nel;
+  const int b = on ? s2_node(row / 3) : 0, comp = row - 3 * (row / 3);
+  if (on) {
+    const int ex = (int)(e % nex), ey = (int)((e / nex) % ney), ez = (int)(e / ((long)nex * ney));
+    const int bxl = b % 3, byl = (b / 3) % 3, bzl = b / 9;
+    const long node = (2 * ex + bxl) + (long)L.nx * ((2 * ey + byl) + (long)L.ny * (2 * ez + bzl));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T v[3];
+      in.load(r, node, v);
+      ue[r][le][row] = v[comp];
+    }
+  }
+  __syncthreads();
+  if (!gate_open(g) || !on) return;
+  const T* D = op.Ke + (size_t)e * S2_PACKED;
+  T acc[NR][2];
+  const T d0 = D[row];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    acc[r][0] = d0 * ue[r][le][row];
+    acc[r][1] = T(0);
+  }
+  // 4 batches of 8 diagonals (s = 1..32; 31 and 32 do not exist),
+  // double-buffered like the 27-node pass
+  T kb[2][16];
+  auto issue = [&](int bt, T (&k)[16]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int sd = 1 + 8 * bt + q;
+      if (sd > 30) continue;
+      int jm = row - sd;
+      jm += jm < 0 ? 60 : 0;
+      k[2 * q] = D[sd * 60 + row];
+      if (sd < 30) k[2 * q + 1] = D[sd * 60 + jm];
+    }
+  };
+  issue(0, kb[0]);
+#pragma unroll
+  for (int bt = 0; bt < 4; ++bt) {
+    if (bt + 1 < 4) issue(bt + 1, kb[(bt + 1) & 1]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int sd = 1 + 8 * bt + q;
+      if (sd > 30) continue;
+      pin(kb[bt & 1][2 * q]);
+      if (sd < 30) pin(kb[bt & 1][2 * q + 1]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int sd = 1 + 8 * bt + q;
+      if (sd > 30) continue;
+      int jp = row + sd, jm = row - sd;
+      jp -= jp >= 60 ? 60 : 0;
+      jm += jm < 0 ? 60 : 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        acc[r][0] = fma(kb[bt & 1][2 * q], ue[r][le][jp], acc[r][0]);
+        if (sd < 30) acc[r][1] = fma(kb[bt & 1][2 * q + 1], ue[r][le][jm], acc[r][1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    op.Y[((size_t)r * nel + e) * 81 + 3 * b + comp] = acc[r][0] + acc[r][1];
+  (void)by;
+}
+
 // ------------------------------------------------------------ epilogues
 // pre(r, node) loads the epilogue's operands and is called before the
 // operator's gathers, so that those loads travel with them; put() then only
@@ -949,11 +1037,22 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
                           EQ_EPB - 1) / EQ_EPB);
     hipEvent_t t_stop = g_time_stop;
     g_time_stop = nullptr;
-    switch (nrhs) {
-      case 1: launch_op(k_eq2_elem<T, 1, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
-      case 2: launch_op(k_eq2_elem<T, 2, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
-      case 3: launch_op(k_eq2_elem<T, 3, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
-      default: launch_op(k_eq2_elem<T, 4, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+    if (op.s2) {
+      const int ns = (int)(((long)(op.L.nx - 1) / 2 * ((op.L.ny - 1) / 2) * ((op.L.nz - 1) / 2) +
+                            ES_EPB - 1) / ES_EPB);
+      switch (nrhs) {
+        case 1: launch_op(k_es2_elem<T, 1, In>, dim3(ns, 1), st, op, in, nrhs, gate, gate_state); break;
+        case 2: launch_op(k_es2_elem<T, 2, In>, dim3(ns, 1), st, op, in, nrhs, gate, gate_state); break;
+        case 3: launch_op(k_es2_elem<T, 3, In>, dim3(ns, 1), st, op, in, nrhs, gate, gate_state); break;
+        default: launch_op(k_es2_elem<T, 4, In>, dim3(ns, 1), st, op, in, nrhs, gate, gate_state); break;
+      }
+    } else {
+      switch (nrhs) {
+        case 1: launch_op(k_eq2_elem<T, 1, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+        case 2: launch_op(k_eq2_elem<T, 2, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+        case 3: launch_op(k_eq2_elem<T, 3, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+        default: launch_op(k_eq2_elem<T, 4, In>, dim3(ne, 1), st, op, in, nrhs, gate, gate_state); break;
+      }
     }
     g_time_stop = t_stop;
     const OpEQ2Y<T> gy{op.L, op.Y, op.mask};

@@ -126,6 +126,31 @@ void setup_pack_q2(const double* K, T* D, long nel, hipStream_t st) {
 template void setup_pack_q2<double>(const double*, double*, long, hipStream_t);
 template void setup_pack_q2<float>(const double*, float*, long, hipStream_t);
 
+// The same for serendipity elements: the 60 rows and columns of their DOFs
+// (DOF 3k + c of serendipity node k is DOF 3 s2_node(k) + c of the 27-node
+// layout), D[e][s][i] = K[e][i][(i + s) mod 60], s = 0..30.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pack_s2(const double* __restrict__ K, T* D, long nel) {
+  const long t = (long)blockIdx.x * BS + threadIdx.x;
+  if (t >= nel * S2_PACKED) return;
+  const long e = t / S2_PACKED;
+  const int q = (int)(t - e * S2_PACKED), s = q / 60, i = q - 60 * s;
+  int j = i + s;
+  j -= j >= 60 ? 60 : 0;
+  const int di = 3 * s2_node(i / 3) + i % 3, dj = 3 * s2_node(j / 3) + j % 3;
+  D[t] = (T)K[(size_t)e * 6561 + 81 * di + dj];
+}
+
+template <typename T>
+void setup_pack_s2(const double* K, T* D, long nel, hipStream_t st) {
+  const long n = nel * S2_PACKED;
+  hipLaunchKernelGGL(k_pack_s2<T>, dim3((unsigned)((n + BS - 1) / BS)), dim3(BS), 0, st, K, D,
+                     nel);
+  MGCG_HIP(hipGetLastError());
+}
+template void setup_pack_s2<double>(const double*, double*, long, hipStream_t);
+template void setup_pack_s2<float>(const double*, float*, long, hipStream_t);
+
 // ------------------------------------------------------------ Galerkin
 // One block per coarse element.  Children have nodes at coarse-local lattice
 // positions in {0,1,2}^3; W[a][b] = trilinear weight of coarse vertex b at

@@ -48,12 +48,26 @@ struct OpST {
 // Ke[e][s][i] = K_e[i][(i + s) mod 81] for s = 0..40, i = 0..80 (each entry
 // of the symmetric matrix once).
 constexpr int Q2_PACKED = 41 * 81;
+// The 20-node serendipity element's 60 DOFs by wrapped diagonals, s = 0..30
+// (the diagonal s = 30 holds each of its values twice).
+constexpr int S2_PACKED = 31 * 60;
+// Node of the 27-node layout (a = ax + 3 ay + 9 az) of serendipity node k
+// (0..19, in increasing a): the vertices and edge midpoints, those with at
+// most one local coordinate at the middle.
+__host__ __device__ inline int s2_node(int k) {
+  int a = 0;
+  for (int m = -1;; ++a) {
+    const int mid = (a % 3 == 1) + ((a / 3) % 3 == 1) + (a / 9 == 1);
+    if (mid <= 1 && ++m == k) return a;
+  }
+}
 template <typename T>
 struct OpEQ2 {
   Lat L;
   const T* Ke;
   const uint8_t* mask;
   T* Y;  // element products K_e u_e, [load case][element][81] (scratch of the apply)
+  int s2;  // serendipity elements: Ke holds S2_PACKED values per element
 };
 
 // Reduction scratch: one partial sum per block and value, in regions that
@@ -204,6 +218,8 @@ void setup_simp(const double* rho, double* E, float* E32, long n, double E0, dou
 // Full symmetric 81x81 element matrices K[e] -> wrapped diagonals (OpEQ2).
 template <typename T>
 void setup_pack_q2(const double* K, T* D, long nel, hipStream_t st);
+template <typename T>
+void setup_pack_s2(const double* K, T* D, long nel, hipStream_t st);
 void setup_effective(int order, int nsub, int nelx, int nely, int nelz, const double* E,
                      const double* Ksub, const uint8_t* mask, Lat L, double* Keff, hipStream_t st);
 // Galerkin coarse element matrices (24x24 Q1-type) of a coarse element grid.

@@ -433,7 +433,7 @@ FineOp Problem::fine_op() const {
   const Lat L = lv_[0].L;
   A.mf = OpMF<double>::make(L, E_, kv64_, B_[0].mask);
   A.st = OpST<double>{L, vbytes_ == 8 ? (const double*)B_[0].coefV : B_[0].coef64};
-  A.eq2 = OpEQ2<double>{L, Kq2_, B_[0].mask, Yeq_};
+  A.eq2 = OpEQ2<double>{L, Kq2_, B_[0].mask, Yeq_, d_.family == MGCG_SERENDIPITY};
   return A;
 }
 
@@ -446,10 +446,10 @@ VOps<T> Problem::vops(int l) const {
   v.invD = (const T*)B_[l].invD;
   if constexpr (sizeof(T) == 8) {
     v.mf = OpMF<T>::make(v.L, E_, kv64_, B_[l].mask);
-    v.eq2 = OpEQ2<T>{v.L, Kq2_, B_[l].mask, (T*)Yeq_};
+    v.eq2 = OpEQ2<T>{v.L, Kq2_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY};
   } else {
     v.mf = OpMF<T>::make(v.L, E32_, kv32_, B_[l].mask);
-    v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask, (T*)Yeq_};
+    v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY};
   }
   v.st = OpST<T>{v.L, (const T*)B_[l].coefV};
   return v;
@@ -525,8 +525,13 @@ void Problem::do_set_densities() {
       setup_diag_eq2<T>(L0, Keff_, B_[0].mask, (T*)B_[0].invD, B_[0].diag64, d_.omega, kTheta, st);
       {
         const long nel0 = (long)d_.nelx * d_.nely * d_.nelz;
-        setup_pack_q2<double>(Keff_, Kq2_, nel0, st);
-        if (mixed) setup_pack_q2<float>(Keff_, Keff32_, nel0, st);
+        if (d_.family == MGCG_SERENDIPITY) {
+          setup_pack_s2<double>(Keff_, Kq2_, nel0, st);
+          if (mixed) setup_pack_s2<float>(Keff_, Keff32_, nel0, st);
+        } else {
+          setup_pack_q2<double>(Keff_, Kq2_, nel0, st);
+          if (mixed) setup_pack_q2<float>(Keff_, Keff32_, nel0, st);
+        }
       }
       break;
   }

@@ -222,3 +222,20 @@ def test_lp_fixed_variables_match_oracle(n, seed, frac, mem):
     if ok_o:
         assert info["lambda"] == lam_o
     lp.close()
+
+
+def test_lp_every_variable_fixed():
+    """All variables fixed: no capacity, so the LP is feasible only for a zero
+    budget (s = 0); otherwise the artificial problem, also s = 0."""
+    need_gpu()
+    from paper_2311_05595_amd import api
+    n = 513
+    g, a, x, _, delta = _instance(n, 21)
+    fixed = np.ones(n, dtype=np.uint8)
+    lp = api.LP(n)
+    for b in (0.0, 0.3):
+        s, info = lp.solve(g, a, x, b, delta, fixed=fixed)
+        s_o, _, ok_o = slp.lp_step(g, a, x, b, delta, fixed=fixed)
+        assert info["feasible"] == ok_o == (b == 0.0)
+        assert np.all(s == 0.0) and np.all(s_o == 0.0)
+    lp.close()

@@ -255,3 +255,20 @@ def test_lagrangian_threshold_all_equal_steps():
     ref, a_o = T.lagrangian_threshold(rho, g)
     assert a == a_o == 0.5 and np.array_equal(out, ref) and np.all(out == 0.0)
     lp.close()
+
+
+@pytest.mark.parametrize("value", [0.0, 0.3, 1.0])
+def test_heaviside_constant_densities(value):
+    """Equal densities: for 0 every eta keeps the (zero) volume and Newton
+    stops at its start; otherwise eta is where h(value) = value."""
+    need_gpu()
+    from paper_2311_05595_amd import api
+    n = 777
+    rho = np.full(n, value)
+    lp = api.LP(n)
+    h, eta, it = lp.heaviside(rho, 8.0)
+    eta_o = T.eta_newton(rho, 8.0)
+    assert abs(eta - eta_o) <= 1e-10
+    assert np.abs(h - T.heaviside(rho, 8.0, eta)).max() <= 1e-14
+    assert abs(h.sum() - rho.sum()) <= 1e-9 * max(rho.sum(), 1.0)
+    lp.close()

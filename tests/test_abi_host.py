@@ -164,3 +164,38 @@ def test_slp_step_control_matches_oracle():
         assert ctrl.k == k
     assert api._abi.load().mgcg_lp_device_bytes(0) == 0
     assert api._abi.load().mgcg_lp_device_bytes(524288) > 524288 * 16
+
+
+def test_new_entry_points_reject_bad_arguments_before_any_device_work():
+    """Argument checks of the thresholding, fixing and fixed-LP entry points
+    run on the host: NULL handles, bad geometry and bad thresholds return
+    MGCG_EINVAL without touching a device."""
+    import ctypes as C
+    lib, abi = _lib()
+    EINVAL = abi.MGCG_EINVAL
+    null = C.c_void_p(0)
+    d = C.c_double()
+    it = C.c_int32()
+    info = abi.mgcg_lp_info()
+    assert lib.mgcg_lp_select_top(null, null, 0, null, 0) == EINVAL
+    assert lib.mgcg_threshold_round(null, null, 0.05, 0.95, null, 0) == EINVAL
+    assert lib.mgcg_angle_cos(null, null, null, C.byref(d), 0) == EINVAL
+    assert lib.mgcg_heaviside(null, null, 1.0, null, C.byref(d), C.byref(it), 0) == EINVAL
+    assert lib.mgcg_threshold_lagrangian(null, null, null, 0.3, 0.7, 89.9, null, C.byref(d), 0) == EINVAL
+    assert lib.mgcg_lp_solve_fixed(null, null, null, null, null, 0.0, 0.1, 0.0, 1.0, null,
+                                   C.byref(info), 0) == EINVAL
+    assert lib.mgcg_fix_variables(None, null, null, null, null, null, None, 0) == EINVAL
+    rho = np.zeros(8)
+    buf = np.zeros(3 * 27, dtype=np.uint8)
+    p = lambda a: C.c_void_p(a.ctypes.data)
+    for desc in (abi.mgcg_fix_desc(2, 2, 2, 1, 1, 3, 1e-6, 0.9, 1e-6),      # order 3
+                 abi.mgcg_fix_desc(0, 2, 2, 1, 1, 1, 1e-6, 0.9, 1e-6),      # empty mesh
+                 abi.mgcg_fix_desc(2, 2, 2, 65, 1, 1, 1e-6, 0.9, 1e-6),     # n > 64
+                 abi.mgcg_fix_desc(2, 2, 2, 1, 1, 1, float("nan"), 0.9, 1e-6)):
+        assert lib.mgcg_fix_variables(C.byref(desc), p(rho), p(rho), p(buf), p(buf), p(buf),
+                                      None, abi.MGCG_MEM_HOST) == EINVAL
+    good = abi.mgcg_fix_desc(2, 2, 2, 1, 1, 1, 1e-6, 0.9, 1e-6)
+    assert lib.mgcg_fix_variables(C.byref(good), p(rho), p(rho), p(buf), p(buf), p(buf), None,
+                                  7) == EINVAL   # bad memory flag
+    assert lib.mgcg_fix_variables(C.byref(good), null, p(rho), p(buf), p(buf), p(buf), None,
+                                  abi.MGCG_MEM_HOST) == EINVAL

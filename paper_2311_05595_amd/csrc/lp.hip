@@ -141,6 +141,7 @@ __global__ __launch_bounds__(LP_BS) void k_lp_hist(long n, int d, int ch,
                                                    const double* __restrict__ cap,
                                                    const LpState* st, double* __restrict__ bins) {
   static_assert(LP_BS == 256, "one thread per digit value");
+  if (!st->feasible) return;  // the artificial problem's box end instead
   __shared__ int pos[LP_BS / 64][256];  // per wave: count of each digit, then its first slot
   __shared__ int wtot[LP_BS / 64];
   __shared__ int first_s[256];          // first slot of each digit
@@ -273,7 +274,8 @@ __global__ __launch_bounds__(LP_BS) void k_lp_hist(long n, int d, int ch,
 
 // Rows [LP_ROWS j, LP_ROWS (j + 1)) of the per-block bins summed per digit.
 __global__ __launch_bounds__(LP_BS) void k_lp_reduce(int nb, const double* __restrict__ bins,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, const LpState* st) {
+  if (!st->feasible) return;
   const int r0 = blockIdx.x * LP_ROWS;
   const int r1 = min(r0 + LP_ROWS, nb);
   double s = 0.0;
@@ -292,6 +294,7 @@ __global__ __launch_bounds__(LP_BS) void k_lp_reduce(int nb, const double* __res
 // ratios first) whose running capacity reaches the remaining budget.
 __global__ __launch_bounds__(LP_BS) void k_lp_pick(int nrows, int d, const double* __restrict__ part,
                                                    LpState* st) {
+  if (!st->feasible) return;
   __shared__ double wtot[LP_BS / 64];
   __shared__ int first[LP_BS / 64], lastb[LP_BS / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -350,6 +353,7 @@ template <bool UNIT>
 __global__ __launch_bounds__(LP_BS) void k_lp_tiesum(long n, const unsigned long long* __restrict__ key,
                                                      const double* __restrict__ cap,
                                                      const LpState* st, double* __restrict__ tsum) {
+  if (!st->feasible) return;
   __shared__ double sh[LP_BS / 64];
   const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
   const unsigned long long T = st->prefix;
@@ -362,7 +366,9 @@ __global__ __launch_bounds__(LP_BS) void k_lp_tiesum(long n, const unsigned long
 // of LP_BS * 8 entries staged in LDS with coalesced loads, each thread's eight
 // consecutive entries summed, a block scan of those sums, the tile's total
 // carried to the next tile.
-__global__ __launch_bounds__(LP_BS) void k_lp_tiescan(int nb, double* __restrict__ tsum) {
+__global__ __launch_bounds__(LP_BS) void k_lp_tiescan(int nb, double* __restrict__ tsum,
+                                                      const LpState* st) {
+  if (st && !st->feasible) return;
   constexpr int PER = 8, TILE = LP_BS * PER;
   __shared__ double tile[TILE];
   __shared__ double wt[LP_BS / 64];
@@ -426,6 +432,7 @@ __global__ __launch_bounds__(LP_BS) void k_lp_fill(long n, const double* __restr
                                                    const double* __restrict__ toff,
                                                    const LpState* st, double* __restrict__ s,
                                                    double* __restrict__ part) {
+  if (!st->feasible) return;
   __shared__ double sh[LP_BS / 64];
   __shared__ double wsum[LP_BS / 64];
   const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
@@ -492,9 +499,11 @@ __global__ __launch_bounds__(LP_BS) void k_lp_box(long n, const double* __restri
                                                   const double* __restrict__ a,
                                                   const double* __restrict__ x, double delta,
                                                   double xl, double xu,
-                                                  const unsigned char* __restrict__ fixed, int upper,
-                                                  double* __restrict__ s,
+                                                  const unsigned char* __restrict__ fixed,
+                                                  const LpState* st, double* __restrict__ s,
                                                   double* __restrict__ part) {
+  if (st->feasible) return;  // the LP's own solution instead
+  const int upper = st->budget > st->capsum;
   __shared__ double sh[LP_BS / 64];
   const long i = (long)blockIdx.x * LP_BS + threadIdx.x;
   double gi = 0.0, ai = 0.0, si = 0.0;
@@ -1162,36 +1171,28 @@ void Lp::solve(const double* g, const double* a, const double* x, const unsigned
                      fixed, key_, cap_, part_, st);
   hipLaunchKernelGGL(k_lp_budget, dim3(1), dim3(LP_BS), 0, stream_, n_, nb_, b,
                      (const double*)part_, st);
-  MGCG_HIP(hipGetLastError());
-  MGCG_HIP(hipMemcpyAsync(hst_, st, sizeof(LpState), hipMemcpyDeviceToHost, stream_));
-  MGCG_HIP(hipStreamSynchronize(stream_));
-  LpState h;
-  std::memcpy(&h, hst_, sizeof(LpState));
-  if (h.bad) throw Error(MGCG_EINVAL, "LP input with a non-positive constraint gradient or a non-finite value");
-  const bool feasible = h.feasible != 0;
-  if (feasible) {
-    for (int d = 0; d < 8; ++d) {
-      hipLaunchKernelGGL(k_lp_hist<false>, dim3(nh_), dim3(LP_BS), 0, stream_, n_, d, ch_,
-                         (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
-                         bins_);
-      hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nh_,
-                         (const double*)bins_, red_);
-      hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_,
-                         st);
-    }
-    hipLaunchKernelGGL(k_lp_tiesum<false>, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
+  // both branches are launched; the feasibility flag in the state selects,
+  // on the device, which one runs (no host round trip in between)
+  for (int d = 0; d < 8; ++d) {
+    hipLaunchKernelGGL(k_lp_hist<false>, dim3(nh_), dim3(LP_BS), 0, stream_, n_, d, ch_,
                        (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
-                       tsum_);
-    hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_);
-    hipLaunchKernelGGL(k_lp_fill, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
-                       fixed,
-                       (const unsigned long long*)key_, (const double*)cap_, (const double*)tsum_,
-                       (const LpState*)st, ds, part_);
-  } else {
-    hipLaunchKernelGGL(k_lp_box, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
-                       fixed,
-                       h.budget > h.capsum ? 1 : 0, ds, part_);
+                       bins_);
+    hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nh_,
+                       (const double*)bins_, red_, (const LpState*)st);
+    hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_,
+                       st);
   }
+  hipLaunchKernelGGL(k_lp_tiesum<false>, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
+                     (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
+                     tsum_);
+  hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_,
+                     (const LpState*)st);
+  hipLaunchKernelGGL(k_lp_fill, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
+                     fixed,
+                     (const unsigned long long*)key_, (const double*)cap_, (const double*)tsum_,
+                     (const LpState*)st, ds, part_);
+  hipLaunchKernelGGL(k_lp_box, dim3(nb_), dim3(LP_BS), 0, stream_, n_, dg, da, dx, delta, xl, xu,
+                     fixed, (const LpState*)st, ds, part_);
   hipLaunchKernelGGL(k_lp_info, dim3(1), dim3(LP_BS), 0, stream_, nb_, (const double*)part_, info_);
   MGCG_HIP(hipGetLastError());
   if (mem == MGCG_MEM_HOST)
@@ -1199,16 +1200,19 @@ void Lp::solve(const double* g, const double* a, const double* x, const unsigned
   MGCG_HIP(hipMemcpyAsync(hst_, info_, 3 * 8, hipMemcpyDeviceToHost, stream_));
   MGCG_HIP(hipMemcpyAsync((char*)hst_ + 64, st, sizeof(LpState), hipMemcpyDeviceToHost, stream_));
   MGCG_HIP(hipStreamSynchronize(stream_));
+  LpState e;
+  std::memcpy(&e, (char*)hst_ + 64, sizeof e);
+  // (on bad input every kernel ran on sanitised values: capacity 0, ratio 0)
+  if (e.bad) throw Error(MGCG_EINVAL, "LP input with a non-positive constraint gradient or a non-finite value");
+  const bool feasible = e.feasible != 0;
   if (info) {
     double v[3];
     std::memcpy(v, hst_, sizeof v);
-    LpState e;
-    std::memcpy(&e, (char*)hst_ + 64, sizeof e);
     info->gts = v[0];
     info->ats = v[1];
     info->s_inf = v[2];
     info->feasible = feasible ? 1 : 0;
-    info->budget = h.budget;
+    info->budget = e.budget;
     info->lambda = feasible ? key_ratio_host(e.prefix) : std::nan("");
   }
 }
@@ -1275,12 +1279,13 @@ void Lp::select_top(const double* v, long k, double* out, int mem) {
                        (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st,
                        bins_);
     hipLaunchKernelGGL(k_lp_reduce, dim3(nr_), dim3(LP_BS), 0, stream_, nh_, (const double*)bins_,
-                       red_);
+                       red_, (const LpState*)st);
     hipLaunchKernelGGL(k_lp_pick, dim3(1), dim3(LP_BS), 0, stream_, nr_, d, (const double*)red_, st);
   }
   hipLaunchKernelGGL(k_lp_tiesum<true>, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
                      (const unsigned long long*)key_, (const double*)cap_, (const LpState*)st, tsum_);
-  hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_);
+  hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, nb_, tsum_,
+                     (const LpState*)st);
   hipLaunchKernelGGL(k_sel_fill, dim3(nb_), dim3(LP_BS), 0, stream_, n_,
                      (const unsigned long long*)key_, (const double*)tsum_, (const LpState*)st, dout);
   MGCG_HIP(hipGetLastError());
@@ -1408,7 +1413,8 @@ double Lp::lagrangian(const double* rho, const double* gl, double vu, double vl,
                      (const double*)cap_, (const LgState*)lg, bins_, part_);
   hipLaunchKernelGGL(k_lg_cls_fin, dim3(1), dim3(LP_BS), 0, stream_, ns_, (const double*)bins_,
                      (const double*)part_, lg);
-  hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, ns_, part_);
+  hipLaunchKernelGGL(k_lp_tiescan, dim3(1), dim3(LP_BS), 0, stream_, ns_, part_,
+                     (const LpState*)nullptr);
   MGCG_HIP(hipGetLastError());
   MGCG_HIP(hipMemcpyAsync(hst_, lg, sizeof(LgState), hipMemcpyDeviceToHost, stream_));
   MGCG_HIP(hipStreamSynchronize(stream_));

@@ -578,8 +578,8 @@ def run_lp(args):
         "roofline": {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 5),
                      "traffic": None, "avg_us": round(t * 1e6, 1), "alg_bytes_per_launch": nbytes,
-                     "note": "whole call: 30 kernel launches (8 radix passes of 3) and two "
-                             "host reads of the budget and the result"},
+                     "note": "whole call: 31 kernel launches (8 radix passes of 3) and one "
+                             "host read of the result"},
     }
     if not args.no_cpu:
         from oracle import slp

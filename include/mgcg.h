@@ -291,7 +291,9 @@ int mgcg_proj_apply_transpose(mgcg_proj* pr, const double* g, double* gx, int me
  * An LP object holds device scratch for n variables (mgcg_lp_device_bytes);
  * g, a, x, s are FP64 [n] in host or device memory (mem); device-memory calls
  * run on the object's stream (the null stream unless set) and return when
- * the results are written (the call reads the budget back once).  Errors:
+ * the results are written (one read-back at the end; the feasibility test
+ * picks the LP's solution or the artificial problem's on the device).  On
+ * bad input the outputs are undefined and the error is returned.  Errors:
  * MGCG_EINVAL for n outside 1..2^31, delta not positive, non-finite b,
  * x_l > x_u, or any a_i <= 0 or non-finite input. */
 typedef struct mgcg_lp mgcg_lp;

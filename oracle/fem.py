@@ -32,7 +32,11 @@ Pins (tests/test_oracle_fem.py): symmetry; rank 3*n_e - 6 (Table 1: 18, 75,
 (D11 + 2G)/9 of the unit Q1 cube; the strain energy of a uniform strain field
 equals (volume) * eps^T D eps (closed form per strain state); sum of the
 sub-element matrices equals the single-element matrix; each sub-matrix
-carries exactly its sub-volume's share of a uniform-strain energy.
+carries exactly its sub-volume's share of a uniform-strain energy; the
+energy of the bilinear fields (xy, 0, 0), (0, yz, 0), (0, 0, zx), which
+varies with position, matches the closed form on every sub-box, which fixes
+each sub-matrix to its box; and the same closed form over single density
+cells of an assembled mesh fixes the density lattice's placement.
 """
 
 import numpy as np

@@ -35,7 +35,11 @@ operator with twice the element size (K scales with h in 3-D); the masked
 Galerkin operator is symmetric with identity rows on fixed DOFs and positive
 definite on free ones; the capped Jacobi sweep has spectral radius < 1 and
 the V-cycle is symmetric positive definite even on a rough field where the
-plain omega = 0.6 sweep diverges; mgcg agrees with the direct solve.
+plain omega = 0.6 sweep diverges; without smoothing the cycle is the exact
+coarse correction, so M A is the A-orthogonal projector onto the range of
+the prolongations (idempotent, which fixes the scale of the transfers); with
+one sweep before and after, I - M A is the product of the sweep's and the
+coarse correction's error propagators; mgcg agrees with the direct solve.
 """
 
 import numpy as np

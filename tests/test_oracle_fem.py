@@ -108,3 +108,82 @@ def test_scaling_with_element_size():
     K1 = fem.sub_element_matrices(1, 1, NU, half=(0.5, 0.5, 0.5))[0]
     K2 = fem.sub_element_matrices(1, 1, NU, half=(1.0, 1.0, 1.0))[0]
     assert np.abs(K2 - 2 * K1).max() < 1e-14
+
+
+# Bilinear displacement fields whose energy density depends on position, one
+# per pair of axes: u = (xy, 0, 0) has eps_xx = y and gamma_xy = x, so its
+# energy density is (M y^2 + G x^2)/2; (0, yz, 0) and (0, 0, zx) are its
+# cyclic images.  M != G, so swapping two axes of a sub-box changes its energy.
+def _bilinear_field(coords, comp):
+    x, y, z = coords[:, 0], coords[:, 1], coords[:, 2]
+    u = np.zeros((coords.shape[0], 3))
+    u[:, comp] = (x * y, y * z, z * x)[comp]
+    return u.ravel()
+
+
+def _box_energy(comp, lo, hi):
+    """Integral of the field's energy density over the box [lo, hi]: with
+    (a, b) the axes of the field's two factors (the strain along a is the b
+    coordinate, the shear gamma_ab is the a coordinate), the density is
+    (M t_b^2 + G t_a^2)/2, integrated in closed form."""
+    a, b = ((0, 1), (1, 2), (2, 0))[comp]
+    vol = np.prod(np.subtract(hi, lo))
+
+    def sq(ax):  # integral of t_ax^2 over the box
+        return vol / (hi[ax] - lo[ax]) * (hi[ax] ** 3 - lo[ax] ** 3) / 3.0
+
+    return 0.5 * (M * sq(b) + G * sq(a))
+
+
+@pytest.mark.parametrize("order,nsub", [(1, 2), (1, 4), (2, 2), (2, 4)])
+def test_sub_element_placement(order, nsub):
+    """Sec. 3.3 eq. (7): K^(e_i) integrates over sub-box i = sx + n (sy + n sz),
+    which covers [sx/n, (sx+1)/n] x [sy/n, ...] x [sz/n, ...] of the unit
+    element.  Position-dependent energies fix each sub-matrix to its box
+    (the sub-element sum and uniform strains cannot: they are symmetric
+    under permutations of the boxes)."""
+    Ks = fem.sub_element_matrices(order, nsub, NU)
+    coords = fem.local_node_coords(order)
+    for comp in range(3):
+        u = _bilinear_field(coords, comp)
+        for sz in range(nsub):
+            for sy in range(nsub):
+                for sx in range(nsub):
+                    lo = np.array([sx, sy, sz], dtype=float) / nsub
+                    hi = lo + 1.0 / nsub
+                    e = 0.5 * u @ Ks[sx + nsub * (sy + nsub * sz)] @ u
+                    assert abs(e - _box_energy(comp, lo, hi)) < 1e-14, (comp, sx, sy, sz)
+
+
+@pytest.mark.parametrize("order,nsub", [(1, 2), (2, 2), (1, 3)])
+def test_density_cell_placement(order, nsub):
+    """The density lattice (C order [n nelz][n nely][n nelx]) against the
+    geometry: with E = rho^p (Emin = 0) and a single solid density cell, the
+    assembled energy of a global bilinear field is the closed-form energy of
+    that cell's box in the mesh's coordinates (element (ex, ey, ez) at the
+    origin (ex, ey, ez), cell (ix, iy, iz) on [ix/n, (ix+1)/n] x ...)."""
+    from oracle import assemble
+
+    nel = (3, 2, 2)
+    Ks = fem.sub_element_matrices(order, nsub, NU)
+    dims = assemble.node_dims(nel, order)
+    t = [np.linspace(0.0, nel[d], dims[d]) for d in range(3)]
+    Z, Y, X = np.meshgrid(t[2], t[1], t[0], indexing="ij")
+    coords = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    lat = tuple(nsub * v for v in nel)
+    rng = np.random.default_rng(11)
+    cells = rng.choice(int(np.prod(lat)), size=6, replace=False)
+    for cell in cells:
+        rho = np.zeros(int(np.prod(lat)))
+        rho[cell] = 1.0
+        K = assemble.stiffness(rho, nel, order, nsub, Ks, E0=1.0, Emin=0.0)
+        ix = cell % lat[0]
+        iy = (cell // lat[0]) % lat[1]
+        iz = cell // (lat[0] * lat[1])
+        lo = np.array([ix, iy, iz], dtype=float) / nsub
+        hi = lo + 1.0 / nsub
+        for comp in range(3):
+            u = _bilinear_field(coords, comp)
+            e = 0.5 * u @ (K @ u)
+            ref = _box_energy(comp, lo, hi)
+            assert abs(e - ref) < 1e-12 * max(1.0, ref), (cell, comp)

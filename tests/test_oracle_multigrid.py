@@ -121,3 +121,61 @@ def test_mgcg_matches_direct(kind, order, nel, nlev):
     for l in range(2):
         assert info[l][1] <= 1e-10
         assert np.linalg.norm(um[l] - ud[l]) <= 1e-7 * np.linalg.norm(ud[l])
+
+
+def _rough_hierarchy(nel, nlev, seed=4):
+    mask, _ = W.make_problem("cantilever", *nel, 1, 1)
+    rho = W.uniform_field((nel[2], nel[1], nel[0]), seed, 0.001, 1.0)
+    K = assemble.stiffness(rho, nel, 1, 1, fem.sub_element_matrices(1, 1), **MAT)
+    H = multigrid.Hierarchy(assemble.level_operator(K, mask), mask,
+                            assemble.node_dims(nel, 1), nlev)
+    return H, mask
+
+
+def _vcycle_full(H, **kw):
+    n = H.A[0].shape[0]
+    return np.stack([multigrid.vcycle(H, e, **kw) for e in np.eye(n)], axis=1)
+
+
+@pytest.mark.parametrize("nel,nlev", [((4, 2, 2), 2), ((8, 4, 4), 3)])
+def test_coarse_correction_is_an_a_orthogonal_projector(nel, nlev):
+    """Algorithm 1 without smoothing (pre = post = 0) is the coarse-grid
+    correction alone: M = Q A_c^-1 Q^T with Q the product of the masked
+    prolongations and A_c = Q^T A Q on the coarse free DOFs (Galerkin,
+    Sec. 2.3).  Then M A is the A-orthogonal projector onto range(Q): it is
+    idempotent, A M A is symmetric, and M A reproduces every coarse field.
+    A restriction or prolongation off by a factor (full weighting's 1/8, say)
+    scales M A and breaks idempotency."""
+    H, mask = _rough_hierarchy(nel, nlev)
+    A = H.A[0].toarray()
+    Mm = _vcycle_full(H, pre=0, post=0)
+    MA = Mm @ A
+    scale = np.abs(MA).max()
+    assert np.abs(MA @ MA - MA).max() < 1e-9 * scale
+    AMA = A @ MA
+    assert np.abs(AMA - AMA.T).max() < 1e-9 * np.abs(AMA).max()
+    Q = H.P[0].toarray()
+    for P in H.P[1:]:
+        Q = Q @ P.toarray()
+    free_c = np.flatnonzero(H.mask[-1] == 0)
+    Qf = Q[:, free_c]
+    assert np.abs(MA @ Qf - Qf).max() < 1e-9 * max(1.0, np.abs(Qf).max())
+    # the projector's rank is the number of free coarsest DOFs
+    assert np.linalg.matrix_rank(MA, tol=1e-8 * scale) == len(free_c)
+
+
+def test_two_grid_error_propagation_composes_the_steps():
+    """Algorithm 1 on two levels, one pre- and one post-sweep from x = 0:
+    the error propagator I - M A is the product (I - S A)(I - C A)(I - S A)
+    of the weighted-Jacobi sweep S = W D^-1 and the exact coarse correction
+    C (itself the projector above), in that order."""
+    H, mask = _rough_hierarchy((4, 2, 2), 2)
+    A = H.A[0].toarray()
+    n = A.shape[0]
+    wd = multigrid.smoother_weights(H, 0.6)[0]
+    S = np.eye(n) - wd[:, None] * A
+    C = _vcycle_full(H, pre=0, post=0)
+    Mm = _vcycle_full(H, pre=1, post=1, omega=0.6)
+    lhs = np.eye(n) - Mm @ A
+    rhs = S @ (np.eye(n) - C @ A) @ S
+    assert np.abs(lhs - rhs).max() < 1e-9

@@ -3,7 +3,7 @@
 A step = one SLP-like iteration of the optimisation loop on the
 96x48x48 trilinear cantilever (0.69M DOF, 5 multigrid levels, FP64): operator
 refresh from a perturbed density field (SIMP moduli, Galerkin coarse
-operators, Jacobi data, coarsest Cholesky), a warm-started MGCG solve to a
+operators, Jacobi data, coarsest inverse), a warm-started MGCG solve to a
 1e-8 relative residual, and compliance + sensitivity.  The ten perturbed
 fields are generated and uploaded before timing; steps cycle through them.
 

@@ -13,8 +13,10 @@
  *   - the solve by CG preconditioned with geometric multigrid (Sec. 2.3,
  *     Algorithm 1 applied recursively as a V-cycle; coarse element = 2x2x2
  *     fine elements, trilinear prolongation P, restriction R = P^T,
- *     weighted-Jacobi smoothing, Galerkin coarse operators, dense Cholesky
- *     on the coarsest mesh; stop on the relative residual, Sec. 7.2.1;
+ *     weighted-Jacobi smoothing, Galerkin coarse operators, an exact dense
+ *     FP64 solve on the coarsest mesh (the paper factors it by Cholesky;
+ *     here its explicit inverse by blocked Gauss-Jordan elimination, applied
+ *     as one matvec per cycle); stop on the relative residual, Sec. 7.2.1;
  *     warm start from the previous solution, Sec. 7.2.1);
  *   - compliance c = f^T u (problem (2)) and its gradient with respect to the
  *     densities, Sec. 3.4: dc/drho_i = -p rho_i^{p-1} (E0 - Emin)
@@ -65,7 +67,7 @@ extern "C" {
 #define MGCG_ESTATE (-7)     /* call out of order (e.g. solve before densities) */
 
 #define MGCG_FP64 0  /* FP64 everywhere */
-#define MGCG_MIXED 1 /* FP32 V-cycle inside an FP64 CG (FP64 coarsest Cholesky) */
+#define MGCG_MIXED 1 /* FP32 V-cycle inside an FP64 CG (FP64 coarsest inverse) */
 
 /* Element families (Sec. 2.1).  MGCG_SERENDIPITY needs order 2: the 20-node
  * quadratic serendipity element (vertices and edge midpoints).  It runs on
@@ -129,13 +131,19 @@ int mgcg_problem_destroy(mgcg_problem* p);
 /* Run all later work of this problem on `stream` (a hipStream_t, e.g. the
  * current torch stream; NULL = the library's own stream). */
 int mgcg_set_stream(mgcg_problem* p, void* stream);
+/* The hipStream_t the problem's work runs on (*stream): the one set above,
+ * else the library's own stream of this problem (created by this call if
+ * needed; no device memory is allocated).  Device inputs are read in order
+ * on this stream, so a caller producing them on another stream makes this
+ * one wait for it (an event) before passing them. */
+int mgcg_get_stream(mgcg_problem* p, void** stream);
 
 /* Allocate the device hierarchy now (otherwise done on first use). */
 int mgcg_problem_allocate(mgcg_problem* p);
 
 /* Densities rho[n_rho] (FP64, host or device): SIMP moduli, fine operator,
- * Galerkin coarse operators, Jacobi diagonals and the coarsest Cholesky
- * factor (the multigrid refresh of Sec. 7.2).  MGCG_EINVAL if any density is
+ * Galerkin coarse operators, Jacobi diagonals and the coarsest level's
+ * explicit FP64 inverse (the multigrid refresh of Sec. 7.2).  MGCG_EINVAL if any density is
  * NaN or outside [0, 1] (detected on the device; the previous operator is
  * then invalid and must be refreshed before the next solve). */
 int mgcg_set_densities(mgcg_problem* p, const double* rho, int mem);
@@ -171,7 +179,7 @@ int mgcg_restrict(mgcg_problem* p, int level, const double* fine, double* coarse
 int mgcg_prolong(mgcg_problem* p, int level, const double* coarse, double* fine, int mem);
 /* z = M r: one V-cycle in the problem's precision. */
 int mgcg_precondition(mgcg_problem* p, const double* r, double* z, int mem);
-/* x = A_c^{-1} b on the coarsest level via the Cholesky factor. */
+/* x = A_c^{-1} b on the coarsest level (a matvec with its explicit inverse). */
 int mgcg_coarse_solve(mgcg_problem* p, const double* b, double* x, int mem);
 
 /* ---- Kernel timing (HIP events around each launch of one kernel) ----
@@ -191,10 +199,18 @@ int mgcg_copy_bytes(mgcg_problem* p, const void* src, void* dst, size_t bytes);
  * budget; a problem submitted again while resident keeps its memory
  * (warm start).  The server does not own problems. */
 int mgcg_server_create(int device, size_t hbm_budget, int max_slots, mgcg_server** out);
+/* Requests still running are abandoned: the call waits only for the work
+ * already enqueued on their problems' streams (no further iterations), and
+ * those problems are left idle with the last iterate as u. */
 int mgcg_server_destroy(mgcg_server* s);
-/* Queue one solve of p with densities rho (host FP64, copied now).
- * MGCG_EBUDGET if p alone exceeds the budget. */
-int mgcg_server_submit(mgcg_server* s, mgcg_problem* p, const double* rho, double rtol,
+/* Queue one solve of p with densities rho (FP64 [n_rho] in density-lattice
+ * order), copied before the call returns: mem = MGCG_MEM_HOST copies into
+ * host memory held by the request; MGCG_MEM_DEVICE copies device to device,
+ * in order on p's stream (mgcg_get_stream), into a stream-ordered device
+ * buffer of the request, which is freed in order on that stream when the
+ * request ends.  MGCG_EBUDGET if p alone exceeds the budget; MGCG_EINVAL for
+ * another device's problem or a bad mem. */
+int mgcg_server_submit(mgcg_server* s, mgcg_problem* p, const double* rho, int mem, double rtol,
                        int maxit, int warm_start, uint64_t* ticket);
 /* Admit what fits, launch the next chunk of every active solve, retire the
  * finished ones.  *active / *queued receive the counts after the step. */

@@ -82,6 +82,7 @@ EXPORTS = {
                                       C.POINTER(C.c_void_p)]),
     "mgcg_problem_destroy": (C.c_int, [C.c_void_p]),
     "mgcg_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mgcg_get_stream": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "mgcg_problem_allocate": (C.c_int, [C.c_void_p]),
     "mgcg_set_densities": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mgcg_solve": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.POINTER(mgcg_info)]),
@@ -102,8 +103,8 @@ EXPORTS = {
     "mgcg_copy_bytes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "mgcg_server_create": (C.c_int, [C.c_int, C.c_size_t, C.c_int, C.POINTER(C.c_void_p)]),
     "mgcg_server_destroy": (C.c_int, [C.c_void_p]),
-    "mgcg_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
-                                     C.c_int, C.POINTER(C.c_uint64)]),
+    "mgcg_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
+                                     C.c_int, C.c_int, C.POINTER(C.c_uint64)]),
     "mgcg_server_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "mgcg_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(mgcg_info),
                                    C.POINTER(C.c_double)]),

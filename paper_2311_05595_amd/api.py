@@ -42,11 +42,27 @@ def _ptr(a, dtype=np.float64):
 
 
 def _inputs_ready(mem):
-    """A problem runs on its own stream unless given a non-default torch
-    stream, and that stream does not wait for torch's default (null) stream:
-    finish the torch work that produced a device input before handing it over."""
+    """For calls that run on the null stream: unless torch's current stream
+    is the null stream itself, finish the torch work that produced a device
+    input before handing it over."""
     if mem == MGCG_MEM_DEVICE:
-        _torch().cuda.current_stream().synchronize()
+        cur = _torch().cuda.current_stream()
+        if cur.cuda_stream != 0:
+            cur.synchronize()
+
+
+def _order_after_torch(mem, stream_ptr):
+    """A device input produced on torch's current stream is read on the
+    stream `stream_ptr` (a hipStream_t): nothing to do when they are the same
+    stream; otherwise that stream waits for torch's on the device (an event),
+    without a host synchronisation."""
+    if mem != MGCG_MEM_DEVICE:
+        return
+    torch = _torch()
+    cur = torch.cuda.current_stream()
+    if cur.cuda_stream == stream_ptr:
+        return
+    torch.cuda.ExternalStream(stream_ptr, device=cur.device).wait_stream(cur)
 
 
 def _info(i):
@@ -125,9 +141,15 @@ class Problem:
     def use_torch_stream(self):
         self.set_stream(_torch().cuda.current_stream().cuda_stream)
 
+    def stream(self):
+        """The hipStream_t (int) the problem's work runs on."""
+        s = C.c_void_p()
+        check(self._lib.mgcg_get_stream(self._h, C.byref(s)))
+        return s.value or 0
+
     def set_densities(self, rho):
         p, mem, keep = _ptr(rho)
-        _inputs_ready(mem)
+        _order_after_torch(mem, self.stream() if mem == MGCG_MEM_DEVICE else 0)
         if (keep.numel() if mem == MGCG_MEM_DEVICE else keep.size) != self.nrho:
             raise ValueError("density count does not match the mesh")
         check(self._lib.mgcg_set_densities(self._h, p, mem))
@@ -148,7 +170,7 @@ class Problem:
 
     def set_initial_guess(self, u):
         p, mem, _k = _ptr(u)
-        _inputs_ready(mem)
+        _order_after_torch(mem, self.stream() if mem == MGCG_MEM_DEVICE else 0)
         check(self._lib.mgcg_set_initial_guess(self._h, p, mem))
 
     def compliance_sensitivity(self, dc_out=None, want_dc=True):
@@ -268,10 +290,16 @@ class Server:
             pass
 
     def submit(self, problem, rho, rtol=1e-8, maxit=1000, warm_start=True):
-        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        """rho: a numpy array, or a contiguous float64 device tensor (copied
+        on the device, in order after torch's current stream)."""
+        p, mem, keep = _ptr(rho)
+        if (keep.numel() if mem == MGCG_MEM_DEVICE else keep.size) != problem.nrho:
+            raise ValueError("density count does not match the mesh")
+        if mem == MGCG_MEM_DEVICE:
+            _order_after_torch(mem, problem.stream())
         t = C.c_uint64()
-        check(self._lib.mgcg_server_submit(self._h, problem.handle, C.c_void_p(rho.ctypes.data),
-                                           rtol, maxit, 1 if warm_start else 0, C.byref(t)))
+        check(self._lib.mgcg_server_submit(self._h, problem.handle, p, mem, rtol, maxit,
+                                           1 if warm_start else 0, C.byref(t)))
         return t.value
 
     def step(self):

@@ -101,6 +101,18 @@ int mgcg_set_stream(mgcg_problem* p, void* stream) {
   })
 }
 
+int mgcg_get_stream(mgcg_problem* p, void** stream) {
+  NEED(p);
+  if (!stream) {
+    mgcg::set_error("null argument");
+    return MGCG_EINVAL;
+  }
+  GUARD({
+    *stream = (void*)p->impl->ensure_stream();
+    return MGCG_OK;
+  })
+}
+
 int mgcg_problem_allocate(mgcg_problem* p) {
   NEED(p);
   GUARD({

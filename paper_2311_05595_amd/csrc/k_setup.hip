@@ -1,6 +1,8 @@
 // Operator refresh after a density update (Sec. 7.2: the smoother data,
-// the system matrix of every mesh level and the Cholesky factor of the
-// coarsest one are recomputed at each optimisation iteration), plus the
+// the system matrix of every mesh level and the exact coarsest solve are
+// recomputed at each optimisation iteration; the paper factors the coarsest
+// matrix by Cholesky, here its explicit inverse is built by blocked
+// Gauss-Jordan elimination), plus the
 // compliance and sensitivity kernels (Sec. 3.4).
 #include <utility>
 

@@ -7,14 +7,20 @@
 // budget B = b - a^T l is used; the variable that reaches it is raised
 // partially, and its ratio is the multiplier of the constraint.
 //
-// The order is never sorted.  The critical ratio is found by a radix select
-// over 64-bit keys that order the ratios from high to low: eight passes of
-// eight bits, each building per-block sums of the capacities a (u - l) per
-// key digit (a thread per digit walks the block's items in index order, so
-// the sums are fixed-order), reducing them in a fixed order and picking the
-// digit where the running capacity reaches the remaining budget.  Variables
-// above the critical key go to u, below to l; the tied group at the key shares
-// what is left of the budget in index order through a block-wise scan.
+// The order is never sorted globally.  The critical ratio is found by a radix
+// select over 64-bit keys that order the ratios from high to low: eight
+// passes of eight bits.  Each pass builds per-block sums of the capacities
+// a (u - l) per key digit: a block loads chunks of 256 items, sorts each chunk
+// by digit in LDS (ranks from ballots of the digit's bits, slots from a scan
+// of per-wave counts), and sums each digit's run with a segmented scan inside
+// each wave, so every sum is taken in a fixed order.  The sums are reduced in
+// a fixed order and the pass picks the digit where the running capacity
+// reaches the remaining budget.  Variables above the critical key go to u,
+// below to l; the tied group at the key shares what is left of the budget in
+// index order through a block-wise scan.  A feasibility flag in the device
+// state selects, without a host round trip, between that solution and the
+// box end of the artificial problem (Sec. 4.2) when the budget lies outside
+// the box's range.
 #include <cmath>
 #include <cstring>
 #include <string>

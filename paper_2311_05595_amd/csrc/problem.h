@@ -58,6 +58,9 @@ class Problem {
 
   void set_stream(hipStream_t s);
   hipStream_t stream() const { return stream_; }
+  // The stream the problem runs on (its own, created now, unless one was set);
+  // no device memory is allocated.
+  hipStream_t ensure_stream();
   int device() const { return device_; }
 
   void set_densities(const double* rho, int mem);
@@ -71,6 +74,9 @@ class Problem {
   void solve_chunk(int iters);             // enqueue iterations + state readback
   bool solve_poll(bool block);             // true when every load case finished
   int solve_finish(mgcg_info* info);       // fills info; returns status
+  // Gives up a solve: waits for the work already enqueued on the stream and
+  // leaves the problem idle (its u is whatever the last iteration wrote).
+  void solve_abort();
   int suggest_chunk() const;
   bool solve_pending() const { return chunk_pending_; }
 

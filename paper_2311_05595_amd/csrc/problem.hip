@@ -306,14 +306,20 @@ void Problem::release() {
 void Problem::set_stream(hipStream_t s) {
   MGCG_HIP(hipSetDevice(device_));
   if (stream_) MGCG_HIP(hipStreamSynchronize(stream_));
-  stream_ = s ? s : own_stream_;
+  stream_ = s;
+  ensure_stream();
+}
+
+hipStream_t Problem::ensure_stream() {
+  MGCG_HIP(hipSetDevice(device_));
+  if (!own_stream_) MGCG_HIP(hipStreamCreateWithFlags(&own_stream_, hipStreamNonBlocking));
+  if (!stream_) stream_ = own_stream_;
+  return stream_;
 }
 
 void Problem::allocate() {
   if (arena_) return;
-  MGCG_HIP(hipSetDevice(device_));
-  if (!own_stream_) MGCG_HIP(hipStreamCreateWithFlags(&own_stream_, hipStreamNonBlocking));
-  if (!stream_) stream_ = own_stream_;
+  ensure_stream();
   bytes_ = layout(d_, lv_, nullptr, nullptr);
   char* base = nullptr;
   if (hipMalloc(&base, bytes_) != hipSuccess) {
@@ -550,7 +556,7 @@ void Problem::do_set_densities() {
     setup_stencil<T>(lv_[l].L, B_[l].KE, B_[l].mask, (T*)B_[l].coefV, (T*)B_[l].invD, B_[l].diag64,
                      d_.omega, kTheta, st);
   }
-  // coarsest: dense Cholesky and explicit inverse
+  // coarsest: dense operator and its explicit inverse (blocked Gauss-Jordan)
   const int lc = L - 1;
   const int src = (lc == 0) ? lv_[0].kind : OP_ST27;
   const double* KE = (lc == 0) ? Keff_ : B_[lc].KE;
@@ -748,6 +754,13 @@ bool Problem::solve_poll(bool block) {
     active_ = any;
   }
   return !active_;
+}
+
+void Problem::solve_abort() {
+  MGCG_HIP(hipSetDevice(device_));
+  if (stream_) MGCG_HIP(hipStreamSynchronize(stream_));
+  chunk_pending_ = false;
+  active_ = false;
 }
 
 int Problem::suggest_chunk() const {

@@ -31,7 +31,7 @@ class Server {
  public:
   Server(int device, size_t budget, int max_slots);
   ~Server();
-  uint64_t submit(Problem* p, const double* rho, double rtol, int maxit, int warm);
+  uint64_t submit(Problem* p, const double* rho, int mem, double rtol, int maxit, int warm);
   void step(int* active, int* queued);
   int poll(uint64_t ticket, mgcg_info* info, double* latency_ms);
   void release(Problem* p);
@@ -41,7 +41,8 @@ class Server {
   struct Req {
     uint64_t ticket;
     Problem* p;
-    std::vector<double> rho;
+    std::vector<double> rho;   // host densities (submitted from host memory)
+    double* drho = nullptr;    // device copy (submitted from device memory), stream-ordered
     double rtol;
     int maxit;
     int warm;
@@ -51,6 +52,8 @@ class Server {
   };
   bool busy(Problem* p) const;
   void admit();
+  void finish(Req* r, int status);
+  static void free_staging(Req* r);
 
   int device_;
   size_t budget_;

@@ -5,6 +5,7 @@
 #include "server.h"
 
 #include <algorithm>
+#include <memory>
 
 namespace mgcg {
 
@@ -37,16 +38,38 @@ Server::Server(int device, size_t budget, int max_slots)
 }
 
 Server::~Server() {
-  for (Req* r : queue_) delete r;
+  // A running request may be mid-solve: wait only for the work already
+  // queued on its stream (no new chunk is launched), then drop it.
   for (Req* r : running_) {
     try {
-      while (!r->p->solve_poll(true)) {
-      }
+      r->p->solve_abort();
     } catch (...) {
     }
+    free_staging(r);
+    delete r;
+  }
+  for (Req* r : queue_) {
+    free_staging(r);
     delete r;
   }
   for (auto& kv : done_) delete kv.second;
+}
+
+// The device copy of a request's densities is released in stream order on
+// its problem's stream, after every kernel that reads it.
+void Server::free_staging(Req* r) {
+  if (r->drho) {
+    (void)hipFreeAsync(r->drho, r->p->stream());
+    r->drho = nullptr;
+  }
+}
+
+void Server::finish(Req* r, int status) {
+  r->status = status;
+  r->info.status = status;
+  r->t_done = std::chrono::steady_clock::now();
+  free_staging(r);
+  done_[r->ticket] = r;
 }
 
 bool Server::busy(Problem* p) const {
@@ -55,20 +78,30 @@ bool Server::busy(Problem* p) const {
   return false;
 }
 
-uint64_t Server::submit(Problem* p, const double* rho, double rtol, int maxit, int warm) {
+uint64_t Server::submit(Problem* p, const double* rho, int mem, double rtol, int maxit, int warm) {
   if (p->device() != device_) throw Error(MGCG_EINVAL, "problem lives on another device");
+  if (mem != MGCG_MEM_HOST && mem != MGCG_MEM_DEVICE) throw Error(MGCG_EINVAL, "bad memory kind");
   const size_t need = Problem::device_bytes(p->desc());
   if (need > budget_) throw Error(MGCG_EBUDGET, "problem exceeds the server's memory budget");
-  Req* r = new Req;
-  r->ticket = next_++;
+  std::unique_ptr<Req> r(new Req);
   r->p = p;
-  r->rho.assign(rho, rho + p->nrho());
+  if (mem == MGCG_MEM_HOST) {
+    r->rho.assign(rho, rho + p->nrho());
+  } else {
+    // copied now, in order on the problem's stream: the caller's buffer may
+    // be reused once this returns
+    const size_t bytes = (size_t)p->nrho() * sizeof(double);
+    hipStream_t st = p->ensure_stream();
+    MGCG_HIP(hipMallocAsync((void**)&r->drho, bytes, st));
+    MGCG_HIP(hipMemcpyAsync(r->drho, rho, bytes, hipMemcpyDeviceToDevice, st));
+  }
+  r->ticket = next_++;
   r->rtol = rtol;
   r->maxit = maxit;
   r->warm = warm;
   r->t_submit = std::chrono::steady_clock::now();
-  queue_.push_back(r);
-  return r->ticket;
+  queue_.push_back(r.get());
+  return r.release()->ticket;
 }
 
 void Server::admit() {
@@ -91,19 +124,24 @@ void Server::admit() {
       rest.push_back(r);
       continue;
     }
-    if (!resident_.count(r->p)) {
-      r->p->allocate();
-      resident_[r->p] = r->p->bytes();
-      in_use_ += r->p->bytes();
-    }
+    // every failure (the allocation included) ends this request only; the
+    // loop always completes, so no request is both admitted and queued
     try {
-      r->p->set_densities_async(r->rho.data(), MGCG_MEM_HOST);
+      if (!resident_.count(r->p)) {
+        r->p->allocate();
+        resident_[r->p] = r->p->bytes();
+        in_use_ += r->p->bytes();
+      }
+      if (r->drho)
+        r->p->set_densities_async(r->drho, MGCG_MEM_DEVICE);
+      else
+        r->p->set_densities_async(r->rho.data(), MGCG_MEM_HOST);
       r->p->solve_begin(r->rtol, r->maxit, r->warm != 0);
       running_.push_back(r);
     } catch (const Error& e) {
-      r->status = e.code;
-      r->t_done = std::chrono::steady_clock::now();
-      done_[r->ticket] = r;
+      finish(r, e.code);
+    } catch (const std::exception&) {
+      finish(r, MGCG_ENOMEM);
     }
   }
   queue_.swap(rest);
@@ -126,9 +164,7 @@ void Server::step(int* active, int* queued) {
       finished = true;
     }
     if (finished) {
-      r->t_done = std::chrono::steady_clock::now();
-      r->info.status = r->status;
-      done_[r->ticket] = r;
+      finish(r, r->status);
       running_.erase(running_.begin() + i);
     } else {
       ++i;
@@ -202,14 +238,14 @@ int mgcg_server_destroy(mgcg_server* s) {
   })
 }
 
-int mgcg_server_submit(mgcg_server* s, mgcg_problem* p, const double* rho, double rtol, int maxit,
-                       int warm_start, uint64_t* ticket) {
+int mgcg_server_submit(mgcg_server* s, mgcg_problem* p, const double* rho, int mem, double rtol,
+                       int maxit, int warm_start, uint64_t* ticket) {
   if (!s || !p || !rho || !ticket) {
     mgcg::set_error("null argument");
     return MGCG_EINVAL;
   }
   SGUARD({
-    *ticket = s->impl->submit(mgcg::problem_impl(p), rho, rtol, maxit, warm_start);
+    *ticket = s->impl->submit(mgcg::problem_impl(p), rho, mem, rtol, maxit, warm_start);
     return MGCG_OK;
   })
 }

@@ -1,6 +1,6 @@
 """Continuous batching: requests of different sizes, load-case counts and
 precisions admitted by HBM budget, overlapping on the device; every result
-must equal the same solve run alone."""
+must equal the same solve run alone, and the oracle's direct solve."""
 
 import numpy as np
 import pytest
@@ -36,10 +36,22 @@ def _fields(spec, seed):
     return [base, W.perturb(base, seed + 1000)]  # a session: cold solve, then a warm re-solve
 
 
+def _oracle(spec, rho):
+    """The oracle's direct solve of one request: u per load case and c."""
+    import workloads as W
+    from oracle import assemble, fem, solve
+    kind, nel, order, nsub, nlev, nrhs, prec = spec
+    mask, f = W.make_problem(kind, *nel, order, nrhs)
+    K = assemble.stiffness(rho, nel, order, nsub, fem.sub_element_matrices(order, nsub),
+                           E0=1.0, Emin=1e-9, penal=3.0)
+    u = solve.solve_direct(K, mask, f)
+    return u, solve.compliance(f, u)
+
+
 def test_alone_equals_mix_and_budget():
     need_gpu()
     from paper_2311_05595_amd import api
-    rtol = 1e-10
+    rtol = 1e-12
     # alone: each session on its own, one after the other
     alone = []
     for k, spec in enumerate(SPECS):
@@ -62,7 +74,7 @@ def test_alone_equals_mix_and_budget():
     tickets = {}
     for k, p in enumerate(probs):
         tickets[srv.submit(p, fields[k][0], rtol=rtol, maxit=3000, warm_start=False)] = (k, 0)
-    results, lat = {}, []
+    results, comp, lat = {}, {}, []
     max_active, saw_queue = 0, False
     guard = 0
     while tickets:
@@ -79,6 +91,7 @@ def test_alone_equals_mix_and_budget():
             assert st == 0, (k, j, st)
             lat.append(ms)
             results[(k, j)] = probs[k].displacement().copy()
+            comp[(k, j)] = probs[k].compliance_sensitivity(want_dc=False)[0]
             if j == 0:  # the session's warm-started second solve
                 tickets[srv.submit(probs[k], fields[k][1], rtol=rtol, maxit=3000,
                                    warm_start=True)] = (k, 1)
@@ -90,6 +103,11 @@ def test_alone_equals_mix_and_budget():
     for k in range(len(SPECS)):
         for j in range(2):
             assert rel(results[(k, j)], alone[k][j]) <= 1e-12, (SPECS[k], j)
+            # and the oracle: u within 1e-8, c within 1e-9, per load case
+            u_ref, c_ref = _oracle(SPECS[k], fields[k][j])
+            for lc in range(SPECS[k][5]):
+                assert rel(results[(k, j)][lc], u_ref[lc]) <= 1e-8, (SPECS[k], j, lc)
+                assert abs(comp[(k, j)][lc] - c_ref[lc]) <= 1e-9 * abs(c_ref[lc]), (SPECS[k], j)
     lat = np.sort(lat)
     assert lat[0] > 0.0 and np.percentile(lat, 99) >= np.percentile(lat, 50)
     srv.close()
@@ -108,4 +126,58 @@ def test_budget_rejects_oversized_request():
         srv.submit(p, _fields(spec, 1)[0])
     assert e.value.code == MGCG_EBUDGET
     srv.close()
+    p.close()
+
+
+def test_device_submit_equals_host_submit():
+    """Densities submitted from device memory (copied on the device, in order
+    after torch's stream) give the same solve as host densities."""
+    need_gpu()
+    import torch
+    from paper_2311_05595_amd import api
+    spec = SPECS[1]
+    fields = _fields(spec, 77)
+    out = []
+    for dev in (False, True):
+        p = _problem(spec)
+        srv = api.Server(4 * p.device_bytes(), max_slots=2)
+        us = []
+        for j, rho in enumerate(fields):
+            src = torch.tensor(rho.ravel(), dtype=torch.float64, device="cuda") if dev else rho
+            t = srv.submit(p, src, rtol=1e-12, maxit=3000, warm_start=j > 0)
+            if dev:
+                src.fill_(-1.0)  # the caller may reuse its buffer once submit returns
+            while True:
+                srv.step()
+                r = srv.poll(t)
+                if r is not None:
+                    break
+            assert r[0] == 0
+            us.append(p.displacement().copy())
+        srv.release(p)
+        srv.close()
+        p.close()
+        out.append(us)
+    for j in range(2):
+        assert rel(out[1][j], out[0][j]) <= 1e-14
+    u_ref, _ = _oracle(spec, fields[1])
+    assert rel(out[1][1], u_ref) <= 1e-8
+
+
+def test_destroy_with_running_request_returns():
+    """Destroying a server while a request is mid-solve waits only for the
+    work already queued, and the problem stays usable."""
+    need_gpu()
+    from paper_2311_05595_amd import api
+    spec = SPECS[5]
+    p = _problem(spec)
+    rho = _fields(spec, 5)[0]
+    srv = api.Server(2 * p.device_bytes(), max_slots=1)
+    t = srv.submit(p, rho, rtol=1e-14, maxit=5000, warm_start=False)
+    active, _ = srv.step()
+    assert active == 1 and srv.poll(t) is None
+    srv.close()  # must return although the solve has not converged
+    p.set_densities(rho)
+    info = p.solve(rtol=1e-10, maxit=3000, warm_start=False)
+    assert info["status"] == 0
     p.close()

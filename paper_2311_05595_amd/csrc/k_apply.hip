@@ -7,6 +7,7 @@
 // eq. (7) reorganised so that each output is written exactly once.  Fused
 // epilogues turn the product into a residual, a weighted-Jacobi update
 // (Algorithm 1, smoothing steps) or a CG step with its dot product.
+#include <algorithm>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -895,6 +896,290 @@ void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars*
   }
 }
 
+// Matrix-free trilinear apply, z-marching over element layers, each element
+// product in the element's tensor Haar basis (q1table.h: K0 u = T K_h T^T u,
+// 45 nonzeros in K_h instead of 576 in K0).
+//
+// A block owns ZM_NB consecutive nodes (i + nx j) of a node plane and a range
+// of planes [k0, k1).  Plane index p covers the nodes p0 .. p0 + ZM_NB - 1 of
+// every plane in the range; the elements that touch them have their lower
+// corner at plane indices p0 - nx - 1 .. p0 + ZM_NB - 1 ("columns" c = 0 ..
+// ZM_NB + nx).  The block walks the element layers L = k0 - 1 .. k1 - 1
+// (between node planes L and L + 1):
+//  * the node plane L + 1 sits in LDS (staged with coalesced loads while
+//    the previous layer was being computed);
+//  * each column's element reads its top face (4 nodes) and takes its 2-D
+//    Haar transform; the bottom face's transform is kept in registers from
+//    the previous layer, so every node plane is read and transformed once
+//    per column;
+//  * the z transform, the sparse K_h product, the modulus, the inverse z
+//    transform and the inverse 2-D transform give the element's 8 corner
+//    values;
+//  * node t of the block owns column t + nx + 1 (its element with lower
+//    corner at the node) and reads the corners of the other three elements
+//    around it from LDS: the bottom corners finish node plane L, the top
+//    corners start node plane L + 1.
+// Elements off the mesh (a column past the last element of a row, layers -1
+// and nz - 1) read modulus 0, so their products vanish; node values off the
+// lattice only meet such elements.  Inputs vanish on fixed DOFs; fixed rows
+// return 0.
+constexpr int ZM_NB = 256;  // nodes (= threads) per block and plane
+
+// 2-D Haar transform of an element face (nodes c, c + 1, c + nx, c + nx + 1
+// of a staged plane, xyz interleaved): f[comp][q], q = mx + 2 my.
+template <typename T>
+__device__ __forceinline__ void zm_face(const T* pl, int c, int nx, T f[3][4]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const T u00 = pl[3 * c + q], u10 = pl[3 * (c + 1) + q];
+    const T u01 = pl[3 * (c + nx) + q], u11 = pl[3 * (c + nx + 1) + q];
+    const T a = u00 + u10, b = u10 - u00, cc = u01 + u11, d = u11 - u01;
+    f[q][0] = a + cc;
+    f[q][1] = b + d;
+    f[q][2] = cc - a;
+    f[q][3] = d - b;
+  }
+}
+
+// One element: bottom face fb (registers), top face ft, modulus E ->
+// corner values of the bottom face gb[comp][corner] and top face gt, corner
+// = ax + 2 ay.
+template <typename T>
+__device__ __forceinline__ void zm_element(const Q1HaarVals<T>& hv, const T (&fb)[3][4],
+                                           const T (&ft)[3][4], T E, T gb[3][4], T gt[3][4]) {
+  // mode coefficients c[3 m + comp], m = q + 4 mz (the constant mode m = 0
+  // is never used)
+  T cm[24];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cm[3 * q + k] = fb[k][q] + ft[k][q];
+      cm[3 * (q + 4) + k] = ft[k][q] - fb[k][q];
+    }
+  T y[24];
+#pragma unroll
+  for (int i = 0; i < 24; ++i) {
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < 24; ++j) {
+      const int cl = kQ1H.cls[i * 24 + j];
+      if (cl < 0) continue;
+      const T h = kQ1H.sgn[i * 24 + j] > 0 ? hv.v[cl] : -hv.v[cl];
+      acc = first ? h * cm[j] : fma(h, cm[j], acc);
+      first = false;
+    }
+    y[i] = first ? T(0) : E * acc;
+  }
+  // inverse z (node 0: s - d, node 1: s + d), then the inverse 2-D transform
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T b[4], t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      b[q] = y[3 * q + k] - y[3 * (q + 4) + k];
+      t[q] = y[3 * q + k] + y[3 * (q + 4) + k];
+    }
+    {
+      const T p = b[0] - b[2], r = b[1] - b[3], u = b[0] + b[2], v = b[1] + b[3];
+      gb[k][0] = p - r;
+      gb[k][1] = p + r;
+      gb[k][2] = u - v;
+      gb[k][3] = u + v;
+    }
+    {
+      const T p = t[0] - t[2], r = t[1] - t[3], u = t[0] + t[2], v = t[1] + t[3];
+      gt[k][0] = p - r;
+      gt[k][1] = p + r;
+      gt[k][2] = u - v;
+      gt[k][3] = u + v;
+    }
+  }
+}
+
+// VPT: staged values per thread and plane (3 (ZM_NB + 2 nx + 2) <= VPT ZM_NB).
+template <int VPT>
+struct ZmShape {
+  static constexpr int max_nx = (VPT * ZM_NB / 3 - ZM_NB - 2) / 2;
+};
+inline int zm_vpt(const Lat& L) {
+  if (L.nx <= ZmShape<6>::max_nx) return 6;
+  if (L.nx <= ZmShape<9>::max_nx) return 9;
+  return 0;  // not supported by the z-marching kernel
+}
+inline bool mf_zm_fits(const Lat& L) { return zm_vpt(L) != 0 && L.nx + 1 <= ZM_NB; }
+
+// Blocks per plane and planes per block.  Planes per block trade the one
+// redundant element layer per block against enough blocks for the 256 CUs
+// (about two per CU).
+struct ZmGrid {
+  int bpp, kz, nzc;
+  int blocks() const { return bpp * nzc; }
+};
+inline ZmGrid zm_grid(const Lat& L) {
+  ZmGrid g;
+  const long P = (long)L.nx * L.ny;
+  g.bpp = (int)((P + ZM_NB - 1) / ZM_NB);
+  const int target = 512;
+  int nzc = std::max(1, std::min(L.nz, (target + g.bpp - 1) / g.bpp));
+  g.kz = (L.nz + nzc - 1) / nzc;
+  if (g.kz < 2) g.kz = std::min(2, L.nz);
+  g.nzc = (L.nz + g.kz - 1) / g.kz;
+  return g;
+}
+
+template <typename T, class Ep, int VPT>
+__global__ __launch_bounds__(ZM_NB) void k_apply_mf_zm(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs,
+                                                       const CgScalars* gate, int gate_state,
+                                                       double* part, int bpp, int kz) {
+  __shared__ T pl[VPT * ZM_NB];           // the staged node plane (xyz interleaved)
+  __shared__ T cor[2][3][3][ZM_NB];       // [face][corner (1,0) (0,1) (1,1)][comp][node]
+  int bx, r;
+  xcd_tile(bx, r);
+  const Gate g = gate_load(gate, nrhs, gate_state);
+  const int gr = PerRhs<Ep>::v ? r : -1;
+  if constexpr (GateEarly<Ep>::v) {
+    if (!gate_open(g, gr)) return;
+  }
+  const Lat L = op.L;
+  const int nx = L.nx, ny = L.ny, nz = L.nz, P = nx * ny;
+  const int ex1 = nx - 1, ey1 = ny - 1, ez1 = nz - 1;
+  const int bp = bx % bpp, zc = bx / bpp;
+  const int p0 = bp * ZM_NB, k0 = zc * kz, k1 = min(nz, k0 + kz);
+  const int t = threadIdx.x;
+  const int sbase = p0 - nx - 1;             // plane index of staged node / column 0
+  const int nstage = 3 * (ZM_NB + 2 * nx + 2);
+  const __amdgpu_buffer_rsrc_t rx =
+      make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
+  // staged values of plane k (0 off the lattice's planes)
+  T stage[VPT];
+  auto load_plane = [&](int k) {
+    const bool on = k >= 0 && k < nz;
+    const int base = (3 * (k * P + sbase) + t) * (int)sizeof(T);  // may be negative: reads 0
+#pragma unroll
+    for (int m = 0; m < VPT; ++m)
+      stage[m] = bload<T>(rx, on ? base + m * ZM_NB * (int)sizeof(T) : kBufOOB, 0);
+  };
+  auto store_plane = [&]() {
+#pragma unroll
+    for (int m = 0; m < VPT; ++m) {
+      const int q = t + m * ZM_NB;
+      if (q < nstage) pl[q] = stage[m];
+    }
+  };
+  // the thread's element columns: A = t + nx + 1 (lower corner at its own
+  // node), B = t for t <= nx
+  const int cA = t + nx + 1, cB = t;
+  const bool hasB = t <= nx;
+  auto col_base = [&](int c) {  // element index in a layer, or -1 off the mesh
+    const int e = sbase + c;
+    if (e < 0 || e >= P) return -1;
+    const int j = e / nx, i = e - j * nx;
+    return (i < ex1 && j < ey1) ? i + ex1 * j : -1;
+  };
+  const int ebA = col_base(cA), ebB = hasB ? col_base(cB) : -1;
+  const int lstride = ex1 * ey1;
+  auto e_off = [&](int eb, int layer) {
+    return (eb >= 0 && layer >= 0 && layer < ez1) ? (eb + lstride * layer) * (int)sizeof(T)
+                                                  : kBufOOB;
+  };
+  const int node = p0 + t;
+  const bool node_on = node < P;
+  const int nodec = node_on ? node : P - 1;
+
+  // prologue: plane k0 - 1 gives the first bottom faces
+  load_plane(k0 - 1);
+  store_plane();
+  __syncthreads();
+  T fA[3][4], fB[3][4];
+  zm_face(pl, cA, nx, fA);
+  if (hasB) zm_face(pl, cB, nx, fB);
+  load_plane(k0);
+  T EA = bload<T>(re, e_off(ebA, k0 - 1), 0);
+  T EB = bload<T>(re, e_off(ebB, k0 - 1), 0);
+  __syncthreads();
+  store_plane();
+  __syncthreads();
+
+  T acc[3] = {T(0), T(0), T(0)};
+  double a0 = 0.0, a1 = 0.0;
+  for (int Ly = k0 - 1; Ly < k1; ++Ly) {
+    // prefetch: the next node plane, the next layer's moduli, this step's
+    // epilogue operands and supports
+    if (Ly + 1 < k1) load_plane(Ly + 2);
+    const T EAn = bload<T>(re, e_off(ebA, Ly + 1), 0);
+    const T EBn = bload<T>(re, e_off(ebB, Ly + 1), 0);
+    const bool out = Ly >= k0;
+    const size_t gnode = (size_t)(out ? Ly : k0) * P + nodec;
+    typename Ep::Pre pv{};
+    uint8_t mself = 0;
+    if (out) {
+      pv = ep.pre(r, (long)gnode);
+      mself = op.mask[gnode];
+    }
+    // element products: corners to LDS, the own element's (0,0) corners kept
+    T ownb[3], ownt[3];
+    {
+      T ft[3][4], gb[3][4], gt[3][4];
+      zm_face(pl, cA, nx, ft);
+      zm_element<T>(op.hv, fA, ft, EA, gb, gt);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ownb[k] = gb[k][0];
+        ownt[k] = gt[k][0];
+        fA[k][0] = ft[k][0]; fA[k][1] = ft[k][1]; fA[k][2] = ft[k][2]; fA[k][3] = ft[k][3];
+      }
+      const int i10 = cA - nx, i01 = cA - 1, i11 = cA;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (i10 < ZM_NB) { cor[0][0][k][i10] = gb[k][1]; cor[1][0][k][i10] = gt[k][1]; }
+        if (i01 < ZM_NB) { cor[0][1][k][i01] = gb[k][2]; cor[1][1][k][i01] = gt[k][2]; }
+        if (i11 < ZM_NB) { cor[0][2][k][i11] = gb[k][3]; cor[1][2][k][i11] = gt[k][3]; }
+      }
+    }
+    if (hasB) {
+      T ft[3][4], gb[3][4], gt[3][4];
+      zm_face(pl, cB, nx, ft);
+      zm_element<T>(op.hv, fB, ft, EB, gb, gt);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        fB[k][0] = ft[k][0]; fB[k][1] = ft[k][1]; fB[k][2] = ft[k][2]; fB[k][3] = ft[k][3];
+      }
+      const int i10 = cB - nx, i01 = cB - 1, i11 = cB;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (i10 >= 0) { cor[0][0][k][i10] = gb[k][1]; cor[1][0][k][i10] = gt[k][1]; }
+        if (i01 >= 0) { cor[0][1][k][i01] = gb[k][2]; cor[1][1][k][i01] = gt[k][2]; }
+        cor[0][2][k][i11] = gb[k][3];
+        cor[1][2][k][i11] = gt[k][3];
+      }
+    }
+    __syncthreads();
+    // node t: the bottom corners finish plane Ly, the top ones start Ly + 1
+    T ax[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T v = acc[k] + ((ownb[k] + cor[0][0][k][t]) + (cor[0][1][k][t] + cor[0][2][k][t]));
+      ax[k] = ((mself >> k) & 1) ? T(0) : v;
+      acc[k] = (ownt[k] + cor[1][0][k][t]) + (cor[1][1][k][t] + cor[1][2][k][t]);
+    }
+    if (out) {
+      if (Ly == k0 && !gate_open(g, gr)) return;  // uniform: before the first store
+      if (node_on) ep.put(r, (long)gnode, ax, pv, a0, a1);
+    }
+    if (Ly + 1 < k1) store_plane();
+    EA = EAn;
+    EB = EBn;
+    __syncthreads();
+  }
+  if constexpr (Ep::RED) {
+    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
+                   part + (size_t)(4 + r) * MAX_BLOCKS + bx);
+  }
+}
+
 // Stencil operators: the LPN waves of a block share 64 consecutive nodes,
 // wave w summing the stencil blocks w, w + LPN, ... (coalesced loads, part of
 // the load chain per lane, LPN x the waves of one-thread-per-node); the
@@ -975,9 +1260,11 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
   }
 }
 
-int apply_blocks(int kind, long nn, bool fp64) {
-  (void)fp64;  // every matrix-free variant in use maps one node per thread
+int apply_blocks(int kind, const Lat& L, bool fp64) {
+  (void)fp64;  // both precisions use the same grids
+  const long nn = L.nn();
   if (kind == OP_ST27) return (int)((nn + ST_NODES - 1) / ST_NODES);
+  if (kind == OP_MF_Q1 && mf_zm_fits(L)) return zm_grid(L).blocks();
   return nblocks(nn);
 }
 
@@ -1062,14 +1349,20 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
               gate_state, part);
   } else {
     static_assert(std::is_same<Op, OpMF<T>>::value, "operator kind");
-    const int nb = nblocks(nn);
-    if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-    if (mf_lds_fits(op.L)) {
-      // rows of up to 212 nodes: the block's neighbourhood staged in LDS
-      const size_t lds = (size_t)9 * mf_lds_range(op.L) * sizeof(T);
-      launch_op_lds(k_apply_mf_lds<T, Ep>, dim3(nb, nrhs), lds, st, op, in, ep, nrhs, gate,
-                    gate_state, part);
+    if (mf_zm_fits(op.L)) {
+      const ZmGrid zg = zm_grid(op.L);
+      const int nb = zg.blocks();
+      if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+      if (zm_vpt(op.L) == 6)
+        launch_op_b(k_apply_mf_zm<T, Ep, 6>, dim3(nb, nrhs), dim3(ZM_NB), st, op, in, ep, nrhs,
+                    gate, gate_state, part, zg.bpp, zg.kz);
+      else
+        launch_op_b(k_apply_mf_zm<T, Ep, 9>, dim3(nb, nrhs), dim3(ZM_NB), st, op, in, ep, nrhs,
+                    gate, gate_state, part, zg.bpp, zg.kz);
     } else {
+      // rows of more than 255 nodes: neighbours gathered from global memory
+      const int nb = nblocks(nn);
+      if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
       launch_op(k_apply<T, Op, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state,
                 part);
     }
@@ -1120,7 +1413,7 @@ static void fine_dispatch(const FineOp& A, const In& in, const Ep& ep, int nrhs,
   }
 }
 
-static int fine_blocks(const FineOp& A) { return apply_blocks(A.kind, A.lat().nn(), true); }
+static int fine_blocks(const FineOp& A) { return apply_blocks(A.kind, A.lat(), true); }
 
 __global__ void k_fin_init(CgScalars* cs, int nrhs, const double* part, int nb) {
   __shared__ double sh[BS / 64];
@@ -1593,7 +1886,7 @@ void v_jacobi_prolong(const VOps<T>& v, const VOps<T>& vc, const T* b, const T* 
   const int lr = ST_NODES + 2 * v.L.nx + 2;
   const size_t lds = (size_t)9 * lr * sizeof(T);
   if (lds > 64 * 1024) throw Error(-1, "level too wide for the fused prolongation");
-  hipLaunchKernelGGL(k_st_jacobi_prolong<T>, dim3(apply_blocks(OP_ST27, nn, sizeof(T) == 8), nrhs),
+  hipLaunchKernelGGL(k_st_jacobi_prolong<T>, dim3(apply_blocks(OP_ST27, v.L, sizeof(T) == 8), nrhs),
                      dim3(StShape<7>::threads), lds, st, v.st, x, e, vc.L, v.mask, b, v.invD, omega,
                      xo, nrhs, cs);
   MGCG_HIP(hipGetLastError());

@@ -23,13 +23,14 @@ struct OpMF {
   Lat L;
   const T* E;
   Q1Vals<T> kv;
+  Q1HaarVals<T> hv;  // the same matrix in the element's Haar basis (class values)
   const uint8_t* mask;
   // byte strides between nodes of neighbouring rows / planes of a vector and
   // between elements of neighbouring rows / planes of E (set by make())
   int sy, sz, ey, ez;
-  static OpMF make(Lat L, const T* E, Q1Vals<T> kv, const uint8_t* mask) {
+  static OpMF make(Lat L, const T* E, Q1Vals<T> kv, Q1HaarVals<T> hv, const uint8_t* mask) {
     const int sn = 3 * (int)sizeof(T);
-    return OpMF{L, E, kv, mask, L.nx * sn, L.nx * L.ny * sn, (L.nx - 1) * (int)sizeof(T),
+    return OpMF{L, E, kv, hv, mask, L.nx * sn, L.nx * L.ny * sn, (L.nx - 1) * (int)sizeof(T),
                 (L.nx - 1) * (L.ny - 1) * (int)sizeof(T)};
   }
 };
@@ -73,9 +74,9 @@ struct OpEQ2 {
 // Reduction scratch: one partial sum per block and value, in regions that
 // stay untouched until their consumer has read them:
 //   partials[region * RED_REGION + v * MAX_BLOCKS + block], v < 8.
-// Workgroups (and hence reduction partials) of one operator apply on a
-// lattice of nn nodes: kind OpKind, fp64 = the FP64 instantiation.
-int apply_blocks(int kind, long nn, bool fp64);
+// Workgroups (and hence reduction partials) of one operator apply on the
+// lattice L: kind OpKind, fp64 = the FP64 instantiation.
+int apply_blocks(int kind, const Lat& L, bool fp64);
 
 // Attach the events to the next operator launch on this thread (they then
 // hold that kernel's own start and end timestamps).

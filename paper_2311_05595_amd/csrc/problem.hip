@@ -267,6 +267,28 @@ Problem::Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int d
       mx = std::max(mx, std::fabs(k0[q]));
     }
     if (err > 1e-14 * mx) throw Error(MGCG_EINVAL, "element table does not match the quadrature");
+    // the Haar-basis form: T^T K0 T / 64 from the quadrature matrix must
+    // match the class values on the structure, and vanish off it
+    hv64_ = q1_haar_values(nu / ((1.0 + nu) * (1.0 - 2.0 * nu)), 1.0 / (2.0 * (1.0 + nu)));
+    for (int k = 0; k < 16; ++k) hv32_.v[k] = (float)hv64_.v[k];
+    auto Th = [](int a, int m) {
+      int p = 1;
+      for (int d = 0; d < 3; ++d) p *= (((m >> d) & 1) && !((a >> d) & 1)) ? -1 : 1;
+      return p;
+    };
+    double herr = 0.0;
+    for (int i = 0; i < 24; ++i)
+      for (int j = 0; j < 24; ++j) {
+        double h = 0.0;
+        for (int a = 0; a < 8; ++a)
+          for (int b = 0; b < 8; ++b)
+            h += Th(a, i / 3) * Th(b, j / 3) * k0[(3 * a + i % 3) * 24 + 3 * b + j % 3];
+        h /= 64.0;
+        const int q = i * 24 + j;
+        const double v = kQ1H.cls[q] < 0 ? 0.0 : kQ1H.sgn[q] * hv64_.v[kQ1H.cls[q]];
+        herr = std::max(herr, std::fabs(v - h));
+      }
+    if (herr > 1e-14 * mx) throw Error(MGCG_EINVAL, "Haar element table does not match the quadrature");
   }
 }
 
@@ -430,14 +452,14 @@ void Problem::build_linear_galerkin() {
 // partial sums its reducing epilogues produce), in FP64 or in the V-cycle
 // precision.
 int Problem::nblocks_fine(bool fp64) const {
-  return apply_blocks(lv_[0].kind, lv_[0].L.nn(), fp64);
+  return apply_blocks(lv_[0].kind, lv_[0].L, fp64);
 }
 
 FineOp Problem::fine_op() const {
   FineOp A{};
   A.kind = lv_[0].kind;
   const Lat L = lv_[0].L;
-  A.mf = OpMF<double>::make(L, E_, kv64_, B_[0].mask);
+  A.mf = OpMF<double>::make(L, E_, kv64_, hv64_, B_[0].mask);
   A.st = OpST<double>{L, vbytes_ == 8 ? (const double*)B_[0].coefV : B_[0].coef64};
   A.eq2 = OpEQ2<double>{L, Kq2_, B_[0].mask, Yeq_, d_.family == MGCG_SERENDIPITY};
   return A;
@@ -451,10 +473,10 @@ VOps<T> Problem::vops(int l) const {
   v.mask = B_[l].mask;
   v.invD = (const T*)B_[l].invD;
   if constexpr (sizeof(T) == 8) {
-    v.mf = OpMF<T>::make(v.L, E_, kv64_, B_[l].mask);
+    v.mf = OpMF<T>::make(v.L, E_, kv64_, hv64_, B_[l].mask);
     v.eq2 = OpEQ2<T>{v.L, Kq2_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY};
   } else {
-    v.mf = OpMF<T>::make(v.L, E32_, kv32_, B_[l].mask);
+    v.mf = OpMF<T>::make(v.L, E32_, kv32_, hv32_, B_[l].mask);
     v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY};
   }
   v.st = OpST<T>{v.L, (const T*)B_[l].coefV};

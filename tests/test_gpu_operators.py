@@ -129,3 +129,50 @@ def test_mixed_precision_matrix_free_fine_operator():
     for l in range(4):
         assert rel(z[l], multigrid.vcycle(c.H, r[l], omega=c.omega)) <= 1e-4
     p.close()
+
+
+# Matrix-free trilinear apply on lattices that span several node ranges per
+# plane (ragged last range), several plane chunks, both staging widths of the
+# z-marching kernel (rows up to 127 and up to 255 nodes) and the widest row it
+# takes, plus rows of more than 255 nodes (the gather kernel).
+MF_LATTICES = [
+    ("cantilever", (40, 12, 10), 2, 1),   # 41 x 13 nodes per plane: 3 ranges, ragged
+    ("torsion", (24, 20, 30), 2, 3),      # 31 node planes: several chunks, 3 load cases
+    ("mbb", (130, 4, 6), 2, 2),           # 131-node rows
+    ("cantilever", (254, 2, 4), 2, 1),    # 255-node rows (the widest staged)
+    ("cantilever", (256, 2, 2), 2, 4),    # 257-node rows: gather kernel, 4 load cases
+    ("cantilever", (1, 1, 1), 1, 1),      # one element
+]
+
+
+@pytest.mark.parametrize("kind,nel,nlev,nrhs", MF_LATTICES,
+                         ids=[f"{k}-{'x'.join(map(str, n))}-r{r}" for k, n, _, r in MF_LATTICES])
+def test_matrix_free_apply_lattices(kind, nel, nlev, nrhs):
+    need_gpu()
+    for prec, tol in (("fp64", 1e-13), ("mixed", 5e-6)):
+        c = Case(kind, nel, 1, 1, nlev, nrhs, field="uniform", seed=17, precision=prec)
+        p = c.problem()
+        p.set_densities(c.rho)
+        x = _rand(p.ndof, nrhs, 3)
+        ref = (c.H.A[0] @ x.T).T
+        scale = np.abs(ref).max()
+        assert np.abs(p.apply(0, x) - ref).max() <= 1e-13 * scale
+        if prec == "mixed":
+            assert np.abs(p.apply(0, x, "mixed") - ref).max() <= tol * scale
+        p.close()
+
+
+def test_vcycle_matches_algorithm1_multi_range():
+    """The V-cycle (its fused finest-level epilogues included) on a lattice of
+    several node ranges and plane chunks."""
+    need_gpu()
+    from oracle import multigrid
+    c = Case("cantilever", (40, 12, 10), 1, 1, 2, 2, seed=23)
+    p = c.problem()
+    p.set_densities(c.rho)
+    r = _rand(p.ndof, 2, 29)
+    r[:, c.mask.astype(bool)] = 0.0
+    z = p.precondition(r)
+    for l in range(2):
+        assert rel(z[l], multigrid.vcycle(c.H, r[l], omega=c.omega)) <= 1e-9
+    p.close()

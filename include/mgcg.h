@@ -138,6 +138,17 @@ int mgcg_set_stream(mgcg_problem* p, void* stream);
  * one wait for it (an event) before passing them. */
 int mgcg_get_stream(mgcg_problem* p, void** stream);
 
+/* How the PCG iterations are launched: MGCG_LAUNCH_EAGER (the default)
+ * launches the kernels one by one; MGCG_LAUNCH_GRAPH replays one captured
+ * iteration, a HIP graph of its kernel launches (no memset or copy nodes),
+ * built at the first chunk after allocation.  Same kernels, same arguments,
+ * same results (on one MI355X the replay was not faster: the host keeps
+ * ahead of the GPU either way).  Kernel timing (mgcg_set_kernel_timing)
+ * always launches eagerly.  MGCG_EINVAL for another mode. */
+#define MGCG_LAUNCH_EAGER 0
+#define MGCG_LAUNCH_GRAPH 1
+int mgcg_set_launch_mode(mgcg_problem* p, int mode);
+
 /* Allocate the device hierarchy now (otherwise done on first use). */
 int mgcg_problem_allocate(mgcg_problem* p);
 
@@ -149,9 +160,20 @@ int mgcg_problem_allocate(mgcg_problem* p);
 int mgcg_set_densities(mgcg_problem* p, const double* rho, int mem);
 
 /* Solve K u = f for every load case to ||f - K u|| <= rtol ||f|| (true FP64
- * residual), at most maxit PCG iterations.  warm_start != 0 starts from the
- * current u (the previous solution or mgcg_set_initial_guess), else from 0.
+ * residual), at most maxit PCG iterations.  Initial guess (warm_start):
+ *   MGCG_COLD (0)         zero;
+ *   MGCG_WARM_SCALED (1)  the current u (the previous solution, Sec. 7.2, or
+ *                         mgcg_set_initial_guess) times the factor
+ *                         alpha = f^T u / u^T K u that minimises the energy
+ *                         1/2 x^T K x - f^T x along u, per load case (alpha
+ *                         = 0 when u^T K u <= 0): never worse in energy than
+ *                         either zero or u itself, and alpha = 1 when u
+ *                         already solves the system;
+ *   MGCG_WARM_PLAIN (2)   the current u as it is.
  * info may be NULL.  Blocks until done. */
+#define MGCG_COLD 0
+#define MGCG_WARM_SCALED 1
+#define MGCG_WARM_PLAIN 2
 int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_info* info);
 
 /* u[nrhs*ndof] FP64 (zero on fixed DOFs). */

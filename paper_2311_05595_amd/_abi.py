@@ -83,6 +83,7 @@ EXPORTS = {
     "mgcg_problem_destroy": (C.c_int, [C.c_void_p]),
     "mgcg_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mgcg_get_stream": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mgcg_set_launch_mode": (C.c_int, [C.c_void_p, C.c_int]),
     "mgcg_problem_allocate": (C.c_int, [C.c_void_p]),
     "mgcg_set_densities": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mgcg_solve": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.POINTER(mgcg_info)]),

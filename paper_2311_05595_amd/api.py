@@ -65,6 +65,14 @@ def _order_after_torch(mem, stream_ptr):
     torch.cuda.ExternalStream(stream_ptr, device=cur.device).wait_stream(cur)
 
 
+def _warm(w):
+    """warm_start argument: True / "scaled" (the previous solution scaled by
+    the energy-minimising factor), "plain" (as it is), False / "cold"."""
+    if isinstance(w, str):
+        return {"cold": 0, "scaled": 1, "plain": 2}[w]
+    return 1 if w else 0
+
+
 def _info(i):
     return dict(status=i.status, iters=list(i.iters), rel_res=list(i.rel_res),
                 replacements=i.replacements, t_setup_ms=i.t_setup_ms, t_solve_ms=i.t_solve_ms)
@@ -141,6 +149,10 @@ class Problem:
     def use_torch_stream(self):
         self.set_stream(_torch().cuda.current_stream().cuda_stream)
 
+    def set_launch_mode(self, mode):
+        """"graph" (replay one captured PCG iteration) or "eager"."""
+        check(self._lib.mgcg_set_launch_mode(self._h, {"eager": 0, "graph": 1}[mode]))
+
     def stream(self):
         """The hipStream_t (int) the problem's work runs on."""
         s = C.c_void_p()
@@ -157,7 +169,7 @@ class Problem:
     def solve(self, rtol=1e-8, maxit=1000, warm_start=True, allow_notconv=False):
         info = mgcg_info()
         allow = (MGCG_OK, MGCG_ENOTCONV) if allow_notconv else (MGCG_OK,)
-        check(self._lib.mgcg_solve(self._h, rtol, maxit, 1 if warm_start else 0, C.byref(info)),
+        check(self._lib.mgcg_solve(self._h, rtol, maxit, _warm(warm_start), C.byref(info)),
               allow)
         return _info(info)
 
@@ -299,7 +311,7 @@ class Server:
             _order_after_torch(mem, problem.stream())
         t = C.c_uint64()
         check(self._lib.mgcg_server_submit(self._h, problem.handle, p, mem, rtol, maxit,
-                                           1 if warm_start else 0, C.byref(t)))
+                                           _warm(warm_start), C.byref(t)))
         return t.value
 
     def step(self):

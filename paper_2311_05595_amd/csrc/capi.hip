@@ -113,6 +113,14 @@ int mgcg_get_stream(mgcg_problem* p, void** stream) {
   })
 }
 
+int mgcg_set_launch_mode(mgcg_problem* p, int mode) {
+  NEED(p);
+  GUARD({
+    p->impl->set_launch_mode(mode);
+    return MGCG_OK;
+  })
+}
+
 int mgcg_problem_allocate(mgcg_problem* p) {
   NEED(p);
   GUARD({
@@ -132,7 +140,11 @@ int mgcg_set_densities(mgcg_problem* p, const double* rho, int mem) {
 
 int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_info* info) {
   NEED(p);
-  GUARD({ return p->impl->solve(rtol, maxit, warm_start != 0, info); })
+  if (warm_start < MGCG_COLD || warm_start > MGCG_WARM_PLAIN) {
+    mgcg::set_error("warm_start must be MGCG_COLD, MGCG_WARM_SCALED or MGCG_WARM_PLAIN");
+    return MGCG_EINVAL;
+  }
+  GUARD({ return p->impl->solve(rtol, maxit, warm_start, info); })
 }
 
 int mgcg_get_displacement(mgcg_problem* p, double* u, int mem) {
@@ -491,5 +503,6 @@ int mgcg_fix_variables(const mgcg_fix_desc* desc, const double* rho, const doubl
     return MGCG_OK;
   })
 }
+
 
 }  // extern "C"

@@ -117,6 +117,31 @@ __device__ __forceinline__ void block_partial2(double a0, double a1, double* d0,
   __syncthreads();
 }
 
+// The same for blocks of NT threads (a multiple of 64).
+template <int NT>
+__device__ __forceinline__ void block_partial2_nt(double a0, double a1, double* d0, double* d1) {
+  __shared__ double sh2n[2][NT / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  if (lane == 0) {
+    sh2n[0][wid] = a0;
+    sh2n[1][wid] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      t0 += sh2n[0][w];
+      t1 += sh2n[1][w];
+    }
+    *d0 = t0;
+    *d1 = t1;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ bool any_state(const CgScalars* cs, int nrhs, int state) {
   if (!cs) return true;
   for (int r = 0; r < nrhs; ++r)

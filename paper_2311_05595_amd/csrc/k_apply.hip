@@ -900,30 +900,31 @@ void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars*
 // product in the element's tensor Haar basis (q1table.h: K0 u = T K_h T^T u,
 // 45 nonzeros in K_h instead of 576 in K0).
 //
-// A block owns ZM_NB consecutive nodes (i + nx j) of a node plane and a range
-// of planes [k0, k1).  Plane index p covers the nodes p0 .. p0 + ZM_NB - 1 of
-// every plane in the range; the elements that touch them have their lower
-// corner at plane indices p0 - nx - 1 .. p0 + ZM_NB - 1 ("columns" c = 0 ..
-// ZM_NB + nx).  The block walks the element layers L = k0 - 1 .. k1 - 1
-// (between node planes L and L + 1):
-//  * the node plane L + 1 sits in LDS (staged with coalesced loads while
-//    the previous layer was being computed);
-//  * each column's element reads its top face (4 nodes) and takes its 2-D
-//    Haar transform; the bottom face's transform is kept in registers from
-//    the previous layer, so every node plane is read and transformed once
-//    per column;
+// A block owns ZM_NB consecutive nodes p0 .. p0 + ZM_NB - 1 (plane index
+// i + nx j) of the node planes k0 .. k1 - 1 (at most KZ of them).  The
+// elements that touch those nodes have their lower corner at plane indices
+// p0 - nx - 1 .. p0 + ZM_NB - 1, the block's "columns" c = 0 .. ZM_NB + nx;
+// thread c computes column c.  The block walks the element layers
+// L = k0 - 1 .. k1 - 1 (between node planes L and L + 1):
+//  * every node plane the block needs (k0 - 1 .. k1) and every layer's
+//    moduli are loaded into registers at the start, so the kernel waits for
+//    memory once; each step moves one plane into LDS;
+//  * each column's element reads its top face (4 nodes) from LDS and takes
+//    its 2-D Haar transform; the bottom face's transform is kept from the
+//    previous layer, so every node plane is transformed once per column;
 //  * the z transform, the sparse K_h product, the modulus, the inverse z
-//    transform and the inverse 2-D transform give the element's 8 corner
-//    values;
-//  * node t of the block owns column t + nx + 1 (its element with lower
-//    corner at the node) and reads the corners of the other three elements
-//    around it from LDS: the bottom corners finish node plane L, the top
-//    corners start node plane L + 1.
+//    transform and the inverse 2-D transform give the element's corner
+//    values, which go to LDS;
+//  * thread c = nx + 1 + m, which owns the element with lower corner at node
+//    p0 + m, finishes that node: its own (0,0) corners and the other three
+//    elements' corners from LDS; the bottom corners complete node plane L
+//    (epilogue and store), the top ones start node plane L + 1.
 // Elements off the mesh (a column past the last element of a row, layers -1
 // and nz - 1) read modulus 0, so their products vanish; node values off the
 // lattice only meet such elements.  Inputs vanish on fixed DOFs; fixed rows
 // return 0.
-constexpr int ZM_NB = 256;  // nodes (= threads) per block and plane
+constexpr int ZM_NB = 256;  // nodes per block and plane
+constexpr int ZM_KZ = 4;    // node planes per block, at most
 
 // 2-D Haar transform of an element face (nodes c, c + 1, c + nx, c + nx + 1
 // of a staged plane, xyz interleaved): f[comp][q], q = mx + 2 my.
@@ -998,21 +999,23 @@ __device__ __forceinline__ void zm_element(const Q1HaarVals<T>& hv, const T (&fb
   }
 }
 
-// VPT: staged values per thread and plane (3 (ZM_NB + 2 nx + 2) <= VPT ZM_NB).
-template <int VPT>
+// Threads per block (one element column each) and staged values per thread
+// and plane, by row length: NT >= ZM_NB + nx + 1, VPT NT >= 3 (ZM_NB + 2 nx + 2).
+template <int NT>
 struct ZmShape {
-  static constexpr int max_nx = (VPT * ZM_NB / 3 - ZM_NB - 2) / 2;
+  static constexpr int max_nx = NT - ZM_NB - 1;
+  static constexpr int vpt = (3 * (ZM_NB + 2 * max_nx + 2) + NT - 1) / NT;
 };
-inline int zm_vpt(const Lat& L) {
-  if (L.nx <= ZmShape<6>::max_nx) return 6;
-  if (L.nx <= ZmShape<9>::max_nx) return 9;
-  return 0;  // not supported by the z-marching kernel
+inline int zm_threads(const Lat& L) {
+  if (L.nx <= ZmShape<384>::max_nx) return 384;
+  if (L.nx <= ZmShape<512>::max_nx) return 512;
+  return 0;  // rows too long for the z-marching kernel
 }
-inline bool mf_zm_fits(const Lat& L) { return zm_vpt(L) != 0 && L.nx + 1 <= ZM_NB; }
+inline bool mf_zm_fits(const Lat& L) { return zm_threads(L) != 0; }
 
-// Blocks per plane and planes per block.  Planes per block trade the one
-// redundant element layer per block against enough blocks for the 256 CUs
-// (about two per CU).
+// Blocks per plane and planes per block: up to ZM_KZ planes per block (the
+// first element layer of a block is recomputed by the block below), fewer
+// when that leaves the 256 CUs without a block each.
 struct ZmGrid {
   int bpp, kz, nzc;
   int blocks() const { return bpp * nzc; }
@@ -1021,20 +1024,23 @@ inline ZmGrid zm_grid(const Lat& L) {
   ZmGrid g;
   const long P = (long)L.nx * L.ny;
   g.bpp = (int)((P + ZM_NB - 1) / ZM_NB);
-  const int target = 512;
-  int nzc = std::max(1, std::min(L.nz, (target + g.bpp - 1) / g.bpp));
-  g.kz = (L.nz + nzc - 1) / nzc;
-  if (g.kz < 2) g.kz = std::min(2, L.nz);
+#ifndef ZM_TARGET_BLOCKS
+#define ZM_TARGET_BLOCKS 256
+#endif
+  const int chunks = std::max(1, (ZM_TARGET_BLOCKS + g.bpp - 1) / g.bpp);
+  g.kz = std::max(1, std::min(ZM_KZ, (L.nz + chunks - 1) / chunks));
   g.nzc = (L.nz + g.kz - 1) / g.kz;
   return g;
 }
 
-template <typename T, class Ep, int VPT>
-__global__ __launch_bounds__(ZM_NB) void k_apply_mf_zm(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs,
-                                                       const CgScalars* gate, int gate_state,
-                                                       double* part, int bpp, int kz) {
-  __shared__ T pl[VPT * ZM_NB];           // the staged node plane (xyz interleaved)
-  __shared__ T cor[2][3][3][ZM_NB];       // [face][corner (1,0) (0,1) (1,1)][comp][node]
+template <typename T, class Ep, int NT>
+__global__ __launch_bounds__(NT) void k_apply_mf_zm(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs,
+                                                    const CgScalars* gate, int gate_state,
+                                                    double* part, int bpp, int kz) {
+  constexpr int VPT = ZmShape<NT>::vpt;
+  constexpr int KZ = ZM_KZ;
+  __shared__ T pl[2][VPT * NT];           // two node planes (xyz interleaved)
+  __shared__ T cor[2][2][3][3][ZM_NB];    // [buffer][face][corner (1,0) (0,1) (1,1)][comp][node]
   int bx, r;
   xcd_tile(bx, r);
   const Gate g = gate_load(gate, nrhs, gate_state);
@@ -1047,136 +1053,160 @@ __global__ __launch_bounds__(ZM_NB) void k_apply_mf_zm(OpMF<T> op, InPlain<T> in
   const int ex1 = nx - 1, ey1 = ny - 1, ez1 = nz - 1;
   const int bp = bx % bpp, zc = bx / bpp;
   const int p0 = bp * ZM_NB, k0 = zc * kz, k1 = min(nz, k0 + kz);
+  const int nsteps = k1 - k0 + 1;            // element layers k0 - 1 .. k1 - 1
   const int t = threadIdx.x;
   const int sbase = p0 - nx - 1;             // plane index of staged node / column 0
-  const int nstage = 3 * (ZM_NB + 2 * nx + 2);
+  const int ne = ZM_NB + nx + 1;             // columns
   const __amdgpu_buffer_rsrc_t rx =
       make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
   const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
-  // staged values of plane k (0 off the lattice's planes)
-  T stage[VPT];
-  auto load_plane = [&](int k) {
-    const bool on = k >= 0 && k < nz;
+  // the column's element (index within a layer, or -1 off the mesh)
+  int eb = -1;
+  if (t < ne) {
+    const int e = sbase + t;
+    if (e >= 0 && e < P) {
+      const int j = e / nx, i = e - j * nx;
+      if (i < ex1 && j < ey1) eb = i + ex1 * j;
+    }
+  }
+  const int lstride = ex1 * ey1;
+  // the node this thread finishes (m = t - nx - 1 in 0 .. ZM_NB - 1)
+  const int m = t - nx - 1;
+  const bool node_thr = m >= 0 && m < ZM_NB;
+  const int node = p0 + m;
+  const bool node_on = node_thr && node < P;
+  const int nodec = node_on ? node : 0;
+
+  // every load of the block, issued together in the order of use (loads
+  // complete in issue order, so a wait for one is a wait for those before
+  // it): plane k0 - 1 + q, then the moduli of layer k0 - 1 + q (planes past
+  // k1 or off the lattice, and layers off the mesh, read 0), and the
+  // epilogue operands and supports of the output planes after the planes
+  // their step needs, PD planes ahead: small operand sets for every plane,
+  // larger ones two planes ahead.  Every thread loads the operands from a
+  // valid node (the last plane repeated), so no load sits under a branch: a
+  // loaded value merged at a branch would be waited for there.
+  constexpr int PD = sizeof(typename Ep::Pre) <= 6 * sizeof(double) ? KZ : 2;
+  T stage[KZ + 2][VPT];
+  T Ev[KZ + 1];
+  typename Ep::Pre pvq[KZ];
+  uint8_t mq[KZ];
+  auto load_pre = [&](int j) {
+    const size_t gn = (size_t)min(k0 + j, nz - 1) * P + nodec;
+    pvq[j] = ep.pre(r, (long)gn);
+    mq[j] = op.mask[gn];
+  };
+#pragma unroll
+  for (int q = 0; q < KZ + 2; ++q) {
+    const int k = k0 - 1 + q;
+    const bool on = k >= 0 && k <= k1 && k < nz;
     const int base = (3 * (k * P + sbase) + t) * (int)sizeof(T);  // may be negative: reads 0
 #pragma unroll
-    for (int m = 0; m < VPT; ++m)
-      stage[m] = bload<T>(rx, on ? base + m * ZM_NB * (int)sizeof(T) : kBufOOB, 0);
-  };
-  auto store_plane = [&]() {
-#pragma unroll
-    for (int m = 0; m < VPT; ++m) {
-      const int q = t + m * ZM_NB;
-      if (q < nstage) pl[q] = stage[m];
+    for (int v = 0; v < VPT; ++v)
+      stage[q][v] = bload<T>(rx, on ? base + v * NT * (int)sizeof(T) : kBufOOB, 0);
+    if (q < KZ + 1) {
+      const int layer = k0 - 1 + q;
+      const bool eon = eb >= 0 && layer >= 0 && layer < ez1 && q < nsteps;
+      Ev[q] = bload<T>(re, eon ? (eb + lstride * layer) * (int)sizeof(T) : kBufOOB, 0);
     }
+    // the operands of output plane j are used in step j + 1, after plane
+    // j + 1 is staged
+    if (q >= 2 && q - 2 < PD) load_pre(q - 2);
+    asm volatile("" ::: "memory");  // keeps the issue order of the groups
+  }
+  // unconditional: a buffer holds VPT NT values, of which the first
+  // 3 (ZM_NB + 2 nx + 2) are read (a store under a branch would let the
+  // compiler move its load into that branch, behind a wait for every load
+  // issued before)
+  auto store_plane = [&](int b, const T (&sv)[VPT]) {
+#pragma unroll
+    for (int v = 0; v < VPT; ++v) pl[b][t + v * NT] = sv[v];
   };
-  // the thread's element columns: A = t + nx + 1 (lower corner at its own
-  // node), B = t for t <= nx
-  const int cA = t + nx + 1, cB = t;
-  const bool hasB = t <= nx;
-  auto col_base = [&](int c) {  // element index in a layer, or -1 off the mesh
-    const int e = sbase + c;
-    if (e < 0 || e >= P) return -1;
-    const int j = e / nx, i = e - j * nx;
-    return (i < ex1 && j < ey1) ? i + ex1 * j : -1;
-  };
-  const int ebA = col_base(cA), ebB = hasB ? col_base(cB) : -1;
-  const int lstride = ex1 * ey1;
-  auto e_off = [&](int eb, int layer) {
-    return (eb >= 0 && layer >= 0 && layer < ez1) ? (eb + lstride * layer) * (int)sizeof(T)
-                                                  : kBufOOB;
-  };
-  const int node = p0 + t;
-  const bool node_on = node < P;
-  const int nodec = node_on ? node : P - 1;
+  // prologue: planes k0 - 1 and k0 staged, the bottom faces of the first layer
+  store_plane(0, stage[0]);
+  store_plane(1, stage[1]);
+  __syncthreads();
+  T fb[3][4];
+  if (t < ne) zm_face(pl[0], t, nx, fb);
+  __syncthreads();  // pl[0] is restaged in step 0
 
-  // prologue: plane k0 - 1 gives the first bottom faces
-  load_plane(k0 - 1);
-  store_plane();
-  __syncthreads();
-  T fA[3][4], fB[3][4];
-  zm_face(pl, cA, nx, fA);
-  if (hasB) zm_face(pl, cB, nx, fB);
-  load_plane(k0);
-  T EA = bload<T>(re, e_off(ebA, k0 - 1), 0);
-  T EB = bload<T>(re, e_off(ebB, k0 - 1), 0);
-  __syncthreads();
-  store_plane();
-  __syncthreads();
-
+  // Step s computes layer L = k0 - 1 + s (its top plane k0 + s is in
+  // pl[(s + 1) & 1]) and writes its corners to cor[s & 1]; the node phase of
+  // layer L - 1 reads cor[(s - 1) & 1] in the same step, and plane k0 + s + 1
+  // is staged into pl[s & 1] (read by step s - 1): one barrier per step.
   T acc[3] = {T(0), T(0), T(0)};
+  T ownb[3] = {T(0), T(0), T(0)}, ownt[3] = {T(0), T(0), T(0)};
   double a0 = 0.0, a1 = 0.0;
-  for (int Ly = k0 - 1; Ly < k1; ++Ly) {
-    // prefetch: the next node plane, the next layer's moduli, this step's
-    // epilogue operands and supports
-    if (Ly + 1 < k1) load_plane(Ly + 2);
-    const T EAn = bload<T>(re, e_off(ebA, Ly + 1), 0);
-    const T EBn = bload<T>(re, e_off(ebB, Ly + 1), 0);
-    const bool out = Ly >= k0;
-    const size_t gnode = (size_t)(out ? Ly : k0) * P + nodec;
-    typename Ep::Pre pv{};
-    uint8_t mself = 0;
-    if (out) {
-      pv = ep.pre(r, (long)gnode);
-      mself = op.mask[gnode];
-    }
-    // element products: corners to LDS, the own element's (0,0) corners kept
-    T ownb[3], ownt[3];
-    {
-      T ft[3][4], gb[3][4], gt[3][4];
-      zm_face(pl, cA, nx, ft);
-      zm_element<T>(op.hv, fA, ft, EA, gb, gt);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        ownb[k] = gb[k][0];
-        ownt[k] = gt[k][0];
-        fA[k][0] = ft[k][0]; fA[k][1] = ft[k][1]; fA[k][2] = ft[k][2]; fA[k][3] = ft[k][3];
-      }
-      const int i10 = cA - nx, i01 = cA - 1, i11 = cA;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if (i10 < ZM_NB) { cor[0][0][k][i10] = gb[k][1]; cor[1][0][k][i10] = gt[k][1]; }
-        if (i01 < ZM_NB) { cor[0][1][k][i01] = gb[k][2]; cor[1][1][k][i01] = gt[k][2]; }
-        if (i11 < ZM_NB) { cor[0][2][k][i11] = gb[k][3]; cor[1][2][k][i11] = gt[k][3]; }
-      }
-    }
-    if (hasB) {
-      T ft[3][4], gb[3][4], gt[3][4];
-      zm_face(pl, cB, nx, ft);
-      zm_element<T>(op.hv, fB, ft, EB, gb, gt);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        fB[k][0] = ft[k][0]; fB[k][1] = ft[k][1]; fB[k][2] = ft[k][2]; fB[k][3] = ft[k][3];
-      }
-      const int i10 = cB - nx, i01 = cB - 1, i11 = cB;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if (i10 >= 0) { cor[0][0][k][i10] = gb[k][1]; cor[1][0][k][i10] = gt[k][1]; }
-        if (i01 >= 0) { cor[0][1][k][i01] = gb[k][2]; cor[1][1][k][i01] = gt[k][2]; }
-        cor[0][2][k][i11] = gb[k][3];
-        cor[1][2][k][i11] = gt[k][3];
-      }
-    }
-    __syncthreads();
-    // node t: the bottom corners finish plane Ly, the top ones start Ly + 1
+  // node phase of layer k0 - 1 + j: its bottom corners finish plane
+  // k0 - 1 + j (an output for j >= 1), its top ones start k0 + j
+  auto node_phase = [&](int j) {
+    const int cb = j & 1;
+    const bool out = j >= 1;
+    const int jo = j >= 1 ? j - 1 : 0;  // the output plane's slot
+    const uint8_t mself = out ? mq[jo] : 0;
     T ax[3];
+    if (node_thr) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T v = acc[k] + ((ownb[k] + cor[cb][0][0][k][m]) +
+                              (cor[cb][0][1][k][m] + cor[cb][0][2][k][m]));
+        ax[k] = ((mself >> k) & 1) ? T(0) : v;
+        acc[k] = (ownt[k] + cor[cb][1][0][k][m]) + (cor[cb][1][1][k][m] + cor[cb][1][2][k][m]);
+      }
+    }
+    if (out) {  // j is a compile-time constant here
+      const size_t gnode = (size_t)(k0 + j - 1) * P + nodec;
+      if (node_on) ep.put(r, (long)gnode, ax, pvq[jo], a0, a1);
+      if (jo + PD < KZ) load_pre(jo + PD);
+    }
+  };
+#pragma unroll
+  for (int s = 0; s < KZ + 1; ++s) {
+    if (s >= nsteps) break;  // uniform
+    T nb_[3], nt_[3];  // this layer's own (0,0) corners, for its node phase
+    if (t < ne) {
+      T ft[3][4], gb[3][4], gt[3][4];
+      zm_face(pl[(s + 1) & 1], t, nx, ft);
+      zm_element<T>(op.hv, fb, ft, Ev[s], gb, gt);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        nb_[k] = gb[k][0];
+        nt_[k] = gt[k][0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fb[k][q] = ft[k][q];
+      }
+      const int cb = s & 1;
+      const int i10 = t - nx, i01 = t - 1, i11 = t;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (i10 >= 0 && i10 < ZM_NB) { cor[cb][0][0][k][i10] = gb[k][1]; cor[cb][1][0][k][i10] = gt[k][1]; }
+        if (i01 >= 0 && i01 < ZM_NB) { cor[cb][0][1][k][i01] = gb[k][2]; cor[cb][1][1][k][i01] = gt[k][2]; }
+        if (i11 < ZM_NB) { cor[cb][0][2][k][i11] = gb[k][3]; cor[cb][1][2][k][i11] = gt[k][3]; }
+      }
+    }
+    if (s >= 1) {
+      if (s == 2 && !gate_open(g, gr)) return;  // uniform: before the first store
+      node_phase(s - 1);
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const T v = acc[k] + ((ownb[k] + cor[0][0][k][t]) + (cor[0][1][k][t] + cor[0][2][k][t]));
-      ax[k] = ((mself >> k) & 1) ? T(0) : v;
-      acc[k] = (ownt[k] + cor[1][0][k][t]) + (cor[1][1][k][t] + cor[1][2][k][t]);
+      ownb[k] = nb_[k];
+      ownt[k] = nt_[k];
     }
-    if (out) {
-      if (Ly == k0 && !gate_open(g, gr)) return;  // uniform: before the first store
-      if (node_on) ep.put(r, (long)gnode, ax, pv, a0, a1);
-    }
-    if (Ly + 1 < k1) store_plane();
-    EA = EAn;
-    EB = EBn;
+    if (s + 2 < KZ + 2) store_plane(s & 1, stage[s + 2]);
     __syncthreads();
   }
+  // the last layer's node phase
+  {
+    const int jl = nsteps - 1;
+    if (jl <= 1 && !gate_open(g, gr)) return;  // no store yet (uniform)
+#pragma unroll
+    for (int j = 1; j < KZ + 1; ++j)
+      if (j == jl) node_phase(j);
+  }
   if constexpr (Ep::RED) {
-    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
-                   part + (size_t)(4 + r) * MAX_BLOCKS + bx);
+    block_partial2_nt<NT>(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
+                          part + (size_t)(4 + r) * MAX_BLOCKS + bx);
   }
 }
 
@@ -1353,11 +1383,11 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
       const ZmGrid zg = zm_grid(op.L);
       const int nb = zg.blocks();
       if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-      if (zm_vpt(op.L) == 6)
-        launch_op_b(k_apply_mf_zm<T, Ep, 6>, dim3(nb, nrhs), dim3(ZM_NB), st, op, in, ep, nrhs,
+      if (zm_threads(op.L) == 384)
+        launch_op_b(k_apply_mf_zm<T, Ep, 384>, dim3(nb, nrhs), dim3(384), st, op, in, ep, nrhs,
                     gate, gate_state, part, zg.bpp, zg.kz);
       else
-        launch_op_b(k_apply_mf_zm<T, Ep, 9>, dim3(nb, nrhs), dim3(ZM_NB), st, op, in, ep, nrhs,
+        launch_op_b(k_apply_mf_zm<T, Ep, 512>, dim3(nb, nrhs), dim3(512), st, op, in, ep, nrhs,
                     gate, gate_state, part, zg.bpp, zg.kz);
     } else {
       // rows of more than 255 nodes: neighbours gathered from global memory
@@ -1448,6 +1478,85 @@ void cg_init_residual(const FineOp& A, const double* f, const double* x, double*
   double* part = red.partials + RED_INIT * RED_REGION;
   fine_dispatch(A, InPlain<double>{x, nd}, EpInitResid{f, r, nd, nrhs}, nrhs, nullptr, 0, st, part);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(BS), 0, st, cs, nrhs, part, fine_blocks(A));
+  MGCG_HIP(hipGetLastError());
+}
+
+// Warm start scaled along the previous solution: the minimiser of the energy
+// J(a x) = a^2/2 x^T A x - a f^T x is a = f^T x / x^T A x, and x^T A x =
+// x^T (f - r) with the residual r = f - A x already computed; J(a x) is then
+// at most min(J(0), J(x)).  Fixed-order block partials, no atomics.
+__global__ __launch_bounds__(BS) void k_warm_dots(const double* __restrict__ f,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ r, long ndof,
+                                                  int nrhs, double* part) {
+  for (int rr = 0; rr < nrhs; ++rr) {
+    const size_t o = (size_t)rr * ndof;
+    double fx = 0.0, xr = 0.0;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
+      const double xv = x[o + i];
+      fx = fma(f[o + i], xv, fx);
+      xr = fma(xv, r[o + i], xr);
+    }
+    block_partial2(fx, xr, part + (size_t)rr * MAX_BLOCKS + blockIdx.x,
+                   part + (size_t)(4 + rr) * MAX_BLOCKS + blockIdx.x);
+  }
+}
+
+__device__ __forceinline__ double warm_alpha(double fx, double xr) {
+  const double xax = fx - xr;  // x^T A x
+  const double a = fx / xax;
+  return (xax > 0.0 && isfinite(a)) ? a : 0.0;
+}
+
+__global__ __launch_bounds__(BS) void k_warm_scale(const double* __restrict__ f, double* x,
+                                                   double* r, long ndof, int nrhs,
+                                                   const double* part, int nbp, double* part2) {
+  __shared__ double sh[BS / 64];
+  for (int rr = 0; rr < nrhs; ++rr) {
+    const double fx = block_sum(part + (size_t)rr * MAX_BLOCKS, nbp, sh);
+    const double xr = block_sum(part + (size_t)(4 + rr) * MAX_BLOCKS, nbp, sh);
+    const double a = warm_alpha(fx, xr);
+    const size_t o = (size_t)rr * ndof;
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * BS + threadIdx.x; i < ndof; i += (long)gridDim.x * BS) {
+      const double rn = (1.0 - a) * f[o + i] + a * r[o + i];
+      x[o + i] = a * x[o + i];
+      r[o + i] = rn;
+      s = fma(rn, rn, s);
+    }
+    block_partial1(s, part2 + (size_t)rr * MAX_BLOCKS + blockIdx.x);
+  }
+}
+
+__global__ void k_fin_warm(CgScalars* cs, int nrhs, const double* part2, int nb) {
+  __shared__ double sh[BS / 64];
+  for (int r = 0; r < nrhs; ++r) {
+    const double rr = block_sum(part2 + (size_t)r * MAX_BLOCKS, nb, sh);
+    if (threadIdx.x == 0) {
+      CgScalars& c = cs[r];
+      if (c.state != CG_ACTIVE && c.state != CG_DONE) continue;  // breakdown stays
+      c.rr = rr;
+      c.rr_best = rr;
+      if (!isfinite(rr))
+        c.state = CG_BREAKDOWN;
+      else if (c.ff == 0.0 || rr <= c.tol2)
+        c.state = CG_DONE;
+      else
+        c.state = CG_ACTIVE;
+    }
+  }
+}
+
+void cg_scale_warm(const double* f, double* x, double* r, long ndof, int nrhs, CgScalars* cs,
+                   RedBuf red, hipStream_t st) {
+  const int nb = vec_grid(ndof);
+  double* part = red.partials + RED_INIT * RED_REGION;  // read by k_fin_init before
+  double* part2 = red.partials + RED_RR * RED_REGION;
+  hipLaunchKernelGGL(k_warm_dots, dim3(nb), dim3(BS), 0, st, f, (const double*)x,
+                     (const double*)r, ndof, nrhs, part);
+  hipLaunchKernelGGL(k_warm_scale, dim3(nb), dim3(BS), 0, st, f, x, r, ndof, nrhs,
+                     (const double*)part, nb, part2);
+  hipLaunchKernelGGL(k_fin_warm, dim3(1), dim3(BS), 0, st, cs, nrhs, (const double*)part2, nb);
   MGCG_HIP(hipGetLastError());
 }
 

@@ -113,6 +113,12 @@ void cg_reset(CgScalars* cs, int nrhs, double rtol2, int maxit, int replace_ever
               hipStream_t st);
 void cg_init_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
                       CgScalars* cs, RedBuf red, hipStream_t st);
+// After cg_init_residual from a warm start x (r = f - A x): x <- alpha x,
+// r <- f - alpha A x = (1 - alpha) f + alpha r with alpha = f.x / x.(f - r)
+// per load case (0 unless x^T A x > 0 and alpha is finite); ||r||^2 and the
+// state are refreshed.
+void cg_scale_warm(const double* f, double* x, double* r, long ndof, int nrhs, CgScalars* cs,
+                   RedBuf red, hipStream_t st);
 void cg_apply_alpha(const FineOp& A, const double* p, double* q, int nrhs, CgScalars* cs,
                     RedBuf red, hipStream_t st);
 // nbq: blocks per load case of the apply that produced the p.q partials.

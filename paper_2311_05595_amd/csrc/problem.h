@@ -68,9 +68,9 @@ class Problem {
   // next solve finishes.
   void set_densities_async(const double* rho, int mem);
   // Blocking solve.
-  int solve(double rtol, int maxit, bool warm, mgcg_info* info);
+  int solve(double rtol, int maxit, int warm, mgcg_info* info);
   // Non-blocking pieces used by the server.
-  void solve_begin(double rtol, int maxit, bool warm);
+  void solve_begin(double rtol, int maxit, int warm);  // warm: MGCG_COLD / _WARM_SCALED / _WARM_PLAIN
   void solve_chunk(int iters);             // enqueue iterations + state readback
   bool solve_poll(bool block);             // true when every load case finished
   int solve_finish(mgcg_info* info);       // fills info; returns status
@@ -93,6 +93,10 @@ class Problem {
   void precondition(const double* r, double* z, int mem);
   void coarse_solve(const double* b, double* x, int mem);
 
+  // MGCG_LAUNCH_GRAPH: the PCG iterations of a chunk replay one captured
+  // iteration (a HIP graph of its kernels); MGCG_LAUNCH_EAGER: launched one
+  // by one (always while kernel timing is on).
+  void set_launch_mode(int mode);
   void set_timing(bool on, int kernel = 0);
   void get_timing(int kernel, double* ms, long long* launches);
   void copy(const void* src, void* dst, size_t bytes);
@@ -112,6 +116,8 @@ class Problem {
   template <typename T> void do_set_densities();
   template <typename T> void do_apply_v(int level, const double* x, double* y);
   void iteration();
+  void build_iter_graph();
+  void drop_iter_graph();
   void build_linear_galerkin();
   FineOp fine_op() const;
   int nblocks_fine(bool fp64) const;
@@ -195,6 +201,8 @@ class Problem {
   bool active_ = false;
   int replace_every_ = 0;  // periodic residual replacement off: only at convergence
   bool pending_check_ = false;
+  int launch_mode_ = MGCG_LAUNCH_EAGER;
+  hipGraphExec_t iter_exec_ = nullptr;  // one PCG iteration, captured
   KernelTimer timer_;
 };
 

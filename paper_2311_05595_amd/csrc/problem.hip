@@ -303,6 +303,7 @@ void Problem::release() {
   if (!arena_) return;
   hipSetDevice(device_);
   if (stream_) hipStreamSynchronize(stream_);
+  drop_iter_graph();
   for (auto& e : timer_.pool) {
     hipEventDestroy(e.first);
     hipEventDestroy(e.second);
@@ -707,7 +708,7 @@ void Problem::iteration() {
   ++iter_launched_;
 }
 
-void Problem::solve_begin(double rtol, int maxit, bool warm) {
+void Problem::solve_begin(double rtol, int maxit, int warm) {
   if (!have_ops_) throw Error(MGCG_ESTATE, "set_densities must precede solve");
   if (!(rtol > 0.0) || maxit < 1) throw Error(MGCG_EINVAL, "need rtol > 0 and maxit >= 1");
   MGCG_HIP(hipSetDevice(device_));
@@ -718,9 +719,11 @@ void Problem::solve_begin(double rtol, int maxit, bool warm) {
   rtol_ = rtol;
   maxit_ = maxit;
   t0_ = std::chrono::steady_clock::now();
-  if (!warm || !have_u_) fill<double>(x_, 0.0, R * nd, st);
+  const bool from_u = warm != MGCG_COLD && have_u_;
+  if (!from_u) fill<double>(x_, 0.0, R * nd, st);
   cg_reset(cs_, R, rtol * rtol, maxit, replace_every_, vbytes_ == 4 ? 1 : 0, st);
   cg_init_residual(A, f_, x_, r_, R, cs_, red_, st);
+  if (from_u && warm == MGCG_WARM_SCALED) cg_scale_warm(f_, x_, r_, nd, R, cs_, red_, st);
   fill<double>(p_, 0.0, R * nd, st);
   fill<double>(rold_, 0.0, R * nd, st);
   iter_launched_ = -1;
@@ -737,10 +740,65 @@ void Problem::solve_begin(double rtol, int maxit, bool warm) {
 
 void Problem::solve_chunk(int iters) {
   hipStream_t st = stream_;
-  for (int i = 0; i < iters; ++i) iteration();
+  if (launch_mode_ == MGCG_LAUNCH_GRAPH && !timer_.enabled) {
+    if (!iter_exec_) build_iter_graph();
+    for (int i = 0; i < iters; ++i) MGCG_HIP(hipGraphLaunch(iter_exec_, st));
+    iter_launched_ += iters;
+  } else {
+    for (int i = 0; i < iters; ++i) iteration();
+  }
   MGCG_HIP(hipMemcpyAsync(hcs_, cs_, 4 * sizeof(CgScalars), hipMemcpyDeviceToHost, st));
   MGCG_HIP(hipEventRecord(ev_chunk_, st));
   chunk_pending_ = true;
+}
+
+// Every kernel of an iteration takes the same arguments in every iteration
+// (buffers of the arena, operator data; the iteration's parity and the
+// per-load-case state live on the device), so one captured iteration serves
+// every later one until the arena is released.  The capture runs on a
+// private stream (the problem's own may be the null stream, which cannot be
+// captured); the graph holds kernel nodes only.
+void Problem::build_iter_graph() {
+  hipStream_t cap = nullptr;
+  MGCG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipStream_t saved = stream_;
+  const int saved_it = iter_launched_;
+  hipGraph_t g = nullptr;
+  stream_ = cap;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    try {
+      iteration();
+    } catch (...) {
+      (void)hipStreamEndCapture(cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      stream_ = saved;
+      iter_launched_ = saved_it;
+      (void)hipStreamDestroy(cap);
+      throw;
+    }
+    e = hipStreamEndCapture(cap, &g);
+  }
+  stream_ = saved;
+  iter_launched_ = saved_it;
+  if (e == hipSuccess) e = hipGraphInstantiate(&iter_exec_, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) {
+    iter_exec_ = nullptr;
+    throw Error(MGCG_EDEVICE, std::string("capturing the PCG iteration: ") + hipGetErrorString(e));
+  }
+}
+
+void Problem::drop_iter_graph() {
+  if (iter_exec_) (void)hipGraphExecDestroy(iter_exec_);
+  iter_exec_ = nullptr;
+}
+
+void Problem::set_launch_mode(int mode) {
+  if (mode != MGCG_LAUNCH_EAGER && mode != MGCG_LAUNCH_GRAPH)
+    throw Error(MGCG_EINVAL, "launch mode must be MGCG_LAUNCH_EAGER or MGCG_LAUNCH_GRAPH");
+  launch_mode_ = mode;
 }
 
 bool Problem::solve_poll(bool block) {
@@ -831,7 +889,7 @@ int Problem::solve_finish(mgcg_info* info) {
   return status;
 }
 
-int Problem::solve(double rtol, int maxit, bool warm, mgcg_info* info) {
+int Problem::solve(double rtol, int maxit, int warm, mgcg_info* info) {
   solve_begin(rtol, maxit, warm);
   solve_poll(true);
   while (active_) {

@@ -81,6 +81,7 @@ bool Server::busy(Problem* p) const {
 uint64_t Server::submit(Problem* p, const double* rho, int mem, double rtol, int maxit, int warm) {
   if (p->device() != device_) throw Error(MGCG_EINVAL, "problem lives on another device");
   if (mem != MGCG_MEM_HOST && mem != MGCG_MEM_DEVICE) throw Error(MGCG_EINVAL, "bad memory kind");
+  if (warm < MGCG_COLD || warm > MGCG_WARM_PLAIN) throw Error(MGCG_EINVAL, "bad warm-start mode");
   const size_t need = Problem::device_bytes(p->desc());
   if (need > budget_) throw Error(MGCG_EBUDGET, "problem exceeds the server's memory budget");
   std::unique_ptr<Req> r(new Req);
@@ -136,7 +137,7 @@ void Server::admit() {
         r->p->set_densities_async(r->drho, MGCG_MEM_DEVICE);
       else
         r->p->set_densities_async(r->rho.data(), MGCG_MEM_HOST);
-      r->p->solve_begin(r->rtol, r->maxit, r->warm != 0);
+      r->p->solve_begin(r->rtol, r->maxit, r->warm);
       running_.push_back(r);
     } catch (const Error& e) {
       finish(r, e.code);

@@ -138,6 +138,7 @@ def test_mixed_precision_matrix_free_fine_operator():
 MF_LATTICES = [
     ("cantilever", (40, 12, 10), 2, 1),   # 41 x 13 nodes per plane: 3 ranges, ragged
     ("torsion", (24, 20, 30), 2, 3),      # 31 node planes: several chunks, 3 load cases
+    ("cantilever", (40, 12, 100), 3, 1),  # two planes per block, ragged last chunk
     ("mbb", (130, 4, 6), 2, 2),           # 131-node rows
     ("cantilever", (254, 2, 4), 2, 1),    # 255-node rows (the widest staged)
     ("cantilever", (256, 2, 2), 2, 4),    # 257-node rows: gather kernel, 4 load cases

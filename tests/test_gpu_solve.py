@@ -128,3 +128,61 @@ def test_zero_load_and_unsupported_body():
         p.solve(rtol=1e-10, warm_start=False)
     assert e.value.code == MGCG_EBREAKDOWN
     p.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replay_equals_eager_launches(prec):
+    """The captured PCG iteration replayed as a HIP graph gives bit-identical
+    iterates to launching the same kernels one by one, over several solves
+    with the library's own eager work (operator refreshes, warm starts, host
+    reads) between the replays."""
+    need_gpu()
+    import workloads as W
+    c = Case("cantilever", (16, 8, 8), 1, 1, 3, 2, seed=31, precision=prec)
+    fields = [c.rho, W.perturb(c.rho, 311), W.perturb(c.rho, 312)]
+    runs = []
+    for mode in ("eager", "graph"):
+        p = c.problem()
+        p.set_launch_mode(mode)
+        out = []
+        for j, rho in enumerate(fields):
+            p.set_densities(rho)
+            info = p.solve(rtol=1e-10, maxit=3000, warm_start=j > 0)
+            assert info["status"] == 0
+            out.append((info["iters"][:2], p.displacement().copy(),
+                        p.compliance_sensitivity(want_dc=False)[0].copy()))
+        p.close()
+        runs.append(out)
+    for (ie, ue, ce), (ig, ug, cg) in zip(*runs):
+        assert ie == ig
+        assert np.array_equal(ue, ug)
+        assert np.array_equal(ce, cg)
+    ud = c.direct()
+    assert rel(runs[1][0][1][0], ud[0]) <= U_TOL
+
+
+def test_scaled_warm_start():
+    """The scaled warm start multiplies the previous u by the energy
+    minimiser f.u / u^T K u: from 2 u* (u* converged) it lands on u* and
+    stops at once, where the plain warm start iterates; from a converged u*
+    it is the plain warm start.  Both reach the direct solve."""
+    need_gpu()
+    c = Case("cantilever", (16, 8, 8), 1, 1, 3, 2, seed=41)
+    p = c.problem()
+    p.set_densities(c.rho)
+    assert p.solve(rtol=1e-10, maxit=3000, warm_start="cold")["status"] == 0
+    u = p.displacement().copy()
+    p.set_initial_guess(2.0 * u)
+    i_scaled = p.solve(rtol=2e-10, maxit=3000, warm_start="scaled")
+    assert max(i_scaled["iters"][:2]) <= 1
+    p.set_initial_guess(2.0 * u)
+    i_plain = p.solve(rtol=2e-10, maxit=3000, warm_start="plain")
+    assert min(i_plain["iters"][:2]) >= 5
+    ud = c.direct()
+    for l in range(2):
+        assert rel(p.displacement()[l], ud[l]) <= U_TOL
+    # a zero guess: the factor is 0 (x^T K x = 0), a cold start
+    p.set_initial_guess(np.zeros_like(u))
+    i0 = p.solve(rtol=1e-10, maxit=3000, warm_start="scaled")
+    assert i0["status"] == 0 and rel(p.displacement()[0], ud[0]) <= U_TOL
+    p.close()

@@ -466,6 +466,25 @@ int mgcg_fix_variables(const mgcg_fix_desc* desc, const double* rho, const doubl
                        uint8_t* elem_kind, uint8_t* design_fixed, uint8_t* dof_mask,
                        mgcg_fix_counts* counts, int mem);
 
+/* The same choice for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): every
+ * array, counts_dev included, is device memory of the current device, and
+ * the call only enqueues kernels and one device-to-device copy on `stream`
+ * (NULL: the null stream), without allocating, freeing or synchronising.
+ * Outputs as for mgcg_fix_variables; counts_dev receives int64[4] = void
+ * elements, solid elements, fixed design variables, suppressed nodes (in
+ * stream order).  Its scratch (raw element kinds, block partials, counts) is
+ * a static array of MGCG_FIX_SCRATCH_BYTES per GPU, held until the process
+ * ends and shared by every call on that GPU: calls that overlap on one GPU
+ * race (serialise them on one stream).  MGCG_EINVAL as for
+ * mgcg_fix_variables, and when the mesh needs more scratch than the limit:
+ * nel + 8 (2 ceil(nel/256) + ceil(d^3 nel/256) + ceil(nn/256)) bytes, each
+ * part rounded up to 256, plus 256. */
+#define MGCG_FIX_SCRATCH_BYTES (16 << 20)
+int mgcg_fix_variables_noalloc(const mgcg_fix_desc* desc, const double* rho, const double* grad_x,
+                               uint8_t* elem_kind, uint8_t* design_fixed, uint8_t* dof_mask,
+                               int64_t* counts_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -139,6 +139,9 @@ EXPORTS = {
     "mgcg_fix_variables": (C.c_int, [C.POINTER(mgcg_fix_desc), C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(mgcg_fix_counts), C.c_int]),
+    "mgcg_fix_variables_noalloc": (C.c_int, [C.POINTER(mgcg_fix_desc), C.c_void_p, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_void_p]),
     "mgcg_lp_solve_fixed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_double, C.c_double, C.c_double, C.c_double,
                                       C.c_void_p, C.POINTER(mgcg_lp_info), C.c_int]),

@@ -504,5 +504,15 @@ int mgcg_fix_variables(const mgcg_fix_desc* desc, const double* rho, const doubl
   })
 }
 
+int mgcg_fix_variables_noalloc(const mgcg_fix_desc* desc, const double* rho, const double* grad_x,
+                               uint8_t* elem_kind, uint8_t* design_fixed, uint8_t* dof_mask,
+                               int64_t* counts_dev, void* stream) {
+  NEED(desc);
+  GUARD({
+    mgcg::fix_variables_noalloc(*desc, rho, grad_x, elem_kind, design_fixed, dof_mask, counts_dev,
+                                (hipStream_t)stream);
+    return MGCG_OK;
+  })
+}
 
 }  // extern "C"

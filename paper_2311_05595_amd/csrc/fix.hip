@@ -9,6 +9,9 @@
 // come from fixed-order block partials.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "fix.h"
 
@@ -194,11 +197,9 @@ int nblocks(long items) { return (int)((items + FX_BS - 1) / FX_BS); }
 
 }  // namespace
 
-void fix_variables(const mgcg_fix_desc& d, const double* rho, const double* grad,
-                   unsigned char* kind_out, unsigned char* design_out, unsigned char* mask,
-                   mgcg_fix_counts* counts, int mem) {
-  if (mem != MGCG_MEM_HOST && mem != MGCG_MEM_DEVICE) throw Error(MGCG_EINVAL, "bad mem flag");
-  if (!rho || !grad || !kind_out || !design_out || !mask) throw Error(MGCG_EINVAL, "null array");
+namespace {
+
+FixGeom check_geometry(const mgcg_fix_desc& d) {
   if (d.nelx < 1 || d.nely < 1 || d.nelz < 1 || d.nsub < 1 || d.nsub > 64 || d.ndes < 1 ||
       d.ndes > 64 || (d.order != 1 && d.order != 2))
     throw Error(MGCG_EINVAL, "bad fixing geometry (mesh >= 1, n and d in 1..64, order 1 or 2)");
@@ -209,43 +210,41 @@ void fix_variables(const mgcg_fix_desc& d, const double* rho, const double* grad
   if ((double)g.nel() * d.nsub * d.nsub * d.nsub > lim || (double)g.nel() * d.ndes * d.ndes * d.ndes > lim ||
       3.0 * g.nn() > lim)
     throw Error(MGCG_EINVAL, "fixing lattices above 2^31 - 1 entries");
-  const long nel = g.nel(), nrho = g.nrho(), nx = g.nx(), nn = g.nn();
-  const int be = nblocks(nel), bx = nblocks(nx), bn = nblocks(nn);
-  hipStream_t st = nullptr;
-  // scratch: raw kinds, fixed kinds (unless the output is on the device),
-  // block partials, the four counts; host inputs and outputs staged
+  return g;
+}
+
+// Device scratch of one call: the raw kinds (a byte per element), the block
+// partials of the four counts and the counts themselves, 256-byte slots.
+struct FixScratch {
+  size_t o_raw, o_part, o_cnt, bytes;
+  int be, bx, bn;
+};
+FixScratch scratch_plan(const FixGeom& g) {
+  FixScratch s{};
+  s.be = nblocks(g.nel());
+  s.bx = nblocks(g.nx());
+  s.bn = nblocks(g.nn());
   size_t off = 0;
   auto slot = [&](size_t b) {
     const size_t o = off;
     off += (b + 255) / 256 * 256;
     return o;
   };
-  const size_t o_raw = slot(nel), o_part = slot(8 * (size_t)(2 * be + bx + bn)), o_cnt = slot(32);
-  size_t o_rho = 0, o_grad = 0, o_kind = 0, o_des = 0, o_mask = 0;
-  if (mem == MGCG_MEM_HOST) {
-    o_rho = slot(8 * (size_t)nrho);
-    o_grad = slot(8 * (size_t)nx);
-    o_kind = slot(nel);
-    o_des = slot(nx);
-    o_mask = slot(3 * (size_t)nn);
-  }
-  DevBuf buf;
-  char* base = (char*)buf.get(off);
-  unsigned char* raw = (unsigned char*)(base + o_raw);
-  long long* part = (long long*)(base + o_part);
-  long long* cnt = (long long*)(base + o_cnt);
-  const double *drho = rho, *dgrad = grad;
-  unsigned char *dkind = kind_out, *ddes = design_out, *dmask = mask;
-  if (mem == MGCG_MEM_HOST) {
-    drho = (const double*)(base + o_rho);
-    dgrad = (const double*)(base + o_grad);
-    dkind = (unsigned char*)(base + o_kind);
-    ddes = (unsigned char*)(base + o_des);
-    dmask = (unsigned char*)(base + o_mask);
-    MGCG_HIP(hipMemcpyAsync((void*)drho, rho, 8 * (size_t)nrho, hipMemcpyHostToDevice, st));
-    MGCG_HIP(hipMemcpyAsync((void*)dgrad, grad, 8 * (size_t)nx, hipMemcpyHostToDevice, st));
-    MGCG_HIP(hipMemcpyAsync(dmask, mask, 3 * (size_t)nn, hipMemcpyHostToDevice, st));
-  }
+  s.o_raw = slot((size_t)g.nel());
+  s.o_part = slot(8 * (size_t)(2 * s.be + s.bx + s.bn));
+  s.o_cnt = slot(32);
+  s.bytes = off;
+  return s;
+}
+
+// The kernels of one call, on stream st, all arrays on the device; base: the
+// scratch of scratch_plan(g); counts (4 int64) written to cnt.
+void fix_launch(const FixGeom& g, const mgcg_fix_desc& d, const FixScratch& sp, char* base,
+                const double* drho, const double* dgrad, unsigned char* dkind, unsigned char* ddes,
+                unsigned char* dmask, long long* cnt, hipStream_t st) {
+  unsigned char* raw = (unsigned char*)(base + sp.o_raw);
+  long long* part = (long long*)(base + sp.o_part);
+  const int be = sp.be, bx = sp.bx, bn = sp.bn;
   long long* pv = part;               // 2 per element block
   long long* pd = part + 2 * be;      // design blocks
   long long* pn = pd + bx;            // node blocks
@@ -262,6 +261,75 @@ void fix_variables(const mgcg_fix_desc& d, const double* rho, const double* grad
   hipLaunchKernelGGL(k_fix_sum, dim3(1), dim3(FX_BS), 0, st, bx, 1, 0, (const long long*)pd, cnt + 2);
   hipLaunchKernelGGL(k_fix_sum, dim3(1), dim3(FX_BS), 0, st, bn, 1, 0, (const long long*)pn, cnt + 3);
   MGCG_HIP(hipGetLastError());
+}
+
+// Scratch of the entry point that allocates nothing: one array per GPU, held
+// until the process ends.  Every call on a GPU shares it (calls that overlap
+// on one GPU race); each call writes all of what it reads back, so nothing
+// needs clearing between calls.
+static __device__ __align__(256) unsigned char scratch[MGCG_FIX_SCRATCH_BYTES];
+
+// Device address of that GPU's array (the host-side name is only a stand-in
+// for the symbol), looked up once per device with the device current.
+char* scratch_address(int dev) {
+  static std::mutex mu;
+  static std::vector<char*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev < 0) throw Error(MGCG_EDEVICE, "no current device");
+  if ((size_t)dev >= addr.size()) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(MGCG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[dev] = (char*)p;
+  }
+  return addr[dev];
+}
+
+}  // namespace
+
+void fix_variables(const mgcg_fix_desc& d, const double* rho, const double* grad,
+                   unsigned char* kind_out, unsigned char* design_out, unsigned char* mask,
+                   mgcg_fix_counts* counts, int mem) {
+  if (mem != MGCG_MEM_HOST && mem != MGCG_MEM_DEVICE) throw Error(MGCG_EINVAL, "bad mem flag");
+  if (!rho || !grad || !kind_out || !design_out || !mask) throw Error(MGCG_EINVAL, "null array");
+  const FixGeom g = check_geometry(d);
+  const long nel = g.nel(), nrho = g.nrho(), nx = g.nx(), nn = g.nn();
+  hipStream_t st = nullptr;
+  // scratch: raw kinds, block partials, the four counts; host inputs and
+  // outputs staged behind them
+  const FixScratch sp = scratch_plan(g);
+  size_t off = sp.bytes;
+  auto slot = [&](size_t b) {
+    const size_t o = off;
+    off += (b + 255) / 256 * 256;
+    return o;
+  };
+  size_t o_rho = 0, o_grad = 0, o_kind = 0, o_des = 0, o_mask = 0;
+  if (mem == MGCG_MEM_HOST) {
+    o_rho = slot(8 * (size_t)nrho);
+    o_grad = slot(8 * (size_t)nx);
+    o_kind = slot(nel);
+    o_des = slot(nx);
+    o_mask = slot(3 * (size_t)nn);
+  }
+  DevBuf buf;
+  char* base = (char*)buf.get(off);
+  long long* cnt = (long long*)(base + sp.o_cnt);
+  const double *drho = rho, *dgrad = grad;
+  unsigned char *dkind = kind_out, *ddes = design_out, *dmask = mask;
+  if (mem == MGCG_MEM_HOST) {
+    drho = (const double*)(base + o_rho);
+    dgrad = (const double*)(base + o_grad);
+    dkind = (unsigned char*)(base + o_kind);
+    ddes = (unsigned char*)(base + o_des);
+    dmask = (unsigned char*)(base + o_mask);
+    MGCG_HIP(hipMemcpyAsync((void*)drho, rho, 8 * (size_t)nrho, hipMemcpyHostToDevice, st));
+    MGCG_HIP(hipMemcpyAsync((void*)dgrad, grad, 8 * (size_t)nx, hipMemcpyHostToDevice, st));
+    MGCG_HIP(hipMemcpyAsync(dmask, mask, 3 * (size_t)nn, hipMemcpyHostToDevice, st));
+  }
+  fix_launch(g, d, sp, base, drho, dgrad, dkind, ddes, dmask, cnt, st);
   if (mem == MGCG_MEM_HOST) {
     MGCG_HIP(hipMemcpyAsync(kind_out, dkind, nel, hipMemcpyDeviceToHost, st));
     MGCG_HIP(hipMemcpyAsync(design_out, ddes, nx, hipMemcpyDeviceToHost, st));
@@ -276,6 +344,27 @@ void fix_variables(const mgcg_fix_desc& d, const double* rho, const double* grad
     counts->fixed_design = hc[2];
     counts->suppressed_nodes = hc[3];
   }
+}
+
+void fix_variables_noalloc(const mgcg_fix_desc& d, const double* rho, const double* grad,
+                           unsigned char* kind_out, unsigned char* design_out, unsigned char* mask,
+                           int64_t* counts_dev, hipStream_t st) {
+  if (!rho || !grad || !kind_out || !design_out || !mask || !counts_dev)
+    throw Error(MGCG_EINVAL, "null array");
+  const FixGeom g = check_geometry(d);
+  const FixScratch sp = scratch_plan(g);
+  if (sp.bytes > (size_t)MGCG_FIX_SCRATCH_BYTES)
+    throw Error(MGCG_EINVAL, "mesh needs " + std::to_string(sp.bytes) +
+                                 " bytes of scratch, above the static limit of " +
+                                 std::to_string((long long)MGCG_FIX_SCRATCH_BYTES));
+  int dev = -1;
+  MGCG_HIP(hipGetDevice(&dev));
+  char* base = scratch_address(dev);
+  // the counts are summed into the scratch, then copied device to device
+  // into the caller's array, in stream order
+  long long* cnt = (long long*)(base + sp.o_cnt);
+  fix_launch(g, d, sp, base, rho, grad, kind_out, design_out, mask, cnt, st);
+  MGCG_HIP(hipMemcpyAsync(counts_dev, cnt, 4 * sizeof(long long), hipMemcpyDeviceToDevice, st));
 }
 
 }  // namespace mgcg

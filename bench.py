@@ -7,8 +7,18 @@ operators, Jacobi data, coarsest inverse), a warm-started MGCG solve to a
 1e-8 relative residual, and compliance + sensitivity.  The ten perturbed
 fields are generated and uploaded before timing; steps cycle through them.
 
-Prints one JSON line (see the fields below).  `--config c3|c4|c4s` times the
-other single-GPU workloads the same way (not the default line).
+Prints one JSON line.  Besides the contract's keys:
+* `roofline`: the finest-level CG apply (per-launch HIP events on the
+  library's stream over the timed steps) against its algorithmic work;
+* `accuracy`: FP64 and mixed-precision solves of one field (warm-started as
+  in the timed steps, and cold) against the oracle's MG-CG reference run to
+  a tight residual: relative errors of u and c, iterations;
+* `cpu_baseline`: the oracle's cold solve from that same run (setup + the
+  iterations it needed to 1e-8), on one host thread, with the host's CPU;
+* `served`: the served mix (the fifth workload) on the FP64 and the mixed
+  path, at the frozen Poisson rate and at capacity (`--no-served` skips it).
+`--config c1|c3|c4|c4s` times the other single-GPU workloads the same way
+(not the default line; no served legs), `--config c5` the served mix alone.
 `--copy-probe MIB` only runs the library's plain copy kernel on MIB MiB
 (the calibration run for the HBM byte counters) and exits.
 
@@ -149,15 +159,30 @@ def fine_apply_model(nel, nsub, order, nrhs=1, family="lagrange"):
                          "vectors per node and load case")
 
 
-def cpu_baseline(cfg, rho_fields, budget_s=25.0):
-    """The oracle on the same workload: assemble K, build the Galerkin
-    hierarchy and run its MGCG on the first perturbed field (warm start from
-    the oracle's own solution of the base field is not affordable); stops
-    after `budget_s` of CG iterations and extrapolates the remaining
-    iterations from the observed residual decay."""
+def host_info():
+    """The host the oracle runs on: logical CPUs and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def oracle_reference(cfg, rho, rtol_ref=1e-12, max_iters=400, budget_s=60.0):
+    """The oracle on one density field of the workload, on one host thread:
+    assemble K, build the Galerkin hierarchy and run its MG-preconditioned CG
+    (Algorithm 1, the same stopping rule) from zero to rel. residual
+    `rtol_ref` (or the iteration / time cap).  Returns the reference
+    solution u*, c* = f.u*, and the timings that give the CPU baseline: the
+    setup time, the time per CG iteration and the iteration at which the
+    residual first fell below 1e-8 (a cold solve)."""
     from threadpoolctl import threadpool_limits
     from oracle import assemble, fem, multigrid
-    import scipy.linalg as sla  # noqa: F401
     from workloads import configs as CF
     mask, f = CF.problem(cfg)
     nel, order, nsub = cfg["nel"], cfg["order"], cfg["nsub"]
@@ -167,51 +192,67 @@ def cpu_baseline(cfg, rho_fields, budget_s=25.0):
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         Ks = fem.sub_element_matrices(order, nsub, family=family)
-        K = assemble.stiffness(rho_fields[0], nel, order, nsub, Ks)
+        K = assemble.stiffness(rho, nel, order, nsub, Ks)
         A0 = assemble.level_operator(K, mask)
         H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, order), cfg["nlevels"])
         weights = multigrid.smoother_weights(H, cfg["omega"])
         t_setup = time.perf_counter() - t0
-        # preconditioned CG, same stopping rule, timed per iteration
-        b = f[0].copy()
-        b[mask.astype(bool)] = 0.0
-        x = np.zeros_like(b)
-        r = b.copy()
-        nf = np.linalg.norm(b)
-        z = multigrid.vcycle(H, r, weights=weights)
-        p = z.copy()
-        rz = r @ z
-        hist = [np.linalg.norm(r) / nf]
+        us, it8, its, res = [], None, 0, 0.0
         t1 = time.perf_counter()
-        it = 0
-        while time.perf_counter() - t1 < budget_s and hist[-1] > 1e-8:
-            q = H.A[0] @ p
-            a = rz / (p @ q)
-            x += a * p
-            r -= a * q
-            it += 1
-            hist.append(np.linalg.norm(r) / nf)
+        for lc in range(f.shape[0]):
+            b = f[lc].copy()
+            b[mask.astype(bool)] = 0.0
+            x = np.zeros_like(b)
+            r = b.copy()
+            nf = np.linalg.norm(b)
             z = multigrid.vcycle(H, r, weights=weights)
-            rzn = r @ z
-            p = z + (rzn / rz) * p
-            rz = rzn
-        t_iter = (time.perf_counter() - t1) / max(it, 1)
-    if hist[-1] <= 1e-8:
-        need = it
-    else:
-        k = max(1, it // 2)
-        rate = (math.log(hist[-1]) - math.log(hist[k])) / max(it - k, 1)
-        need = it + (math.log(1e-8) - math.log(hist[-1])) / rate if rate < 0 else float("inf")
-    t_solve = t_setup + need * t_iter
-    if cfg["nrhs"] > 1:
-        t_solve *= cfg["nrhs"]  # load cases solved one after the other
-    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
-                sample=(f"oracle (NumPy/SciPy FP64, 1 thread) on the same system "
-                        f"({cfg['name']}, load case 1 timed, x{cfg['nrhs']} load cases): "
-                        f"assembly+Galerkin hierarchy {t_setup:.1f} s, {it} MG-preconditioned "
-                        f"CG iterations timed ({t_iter:.3f} s each, rel. residual "
-                        f"{hist[-1]:.1e}); solve time extrapolated to 1e-8 "
-                        f"({need:.0f} iterations) = {t_solve:.1f} s"))
+            p = z.copy()
+            rz = r @ z
+            it = 0
+            while it < max_iters and time.perf_counter() - t1 < budget_s:
+                q = H.A[0] @ p
+                a = rz / (p @ q)
+                x += a * p
+                r -= a * q
+                it += 1
+                rel = np.linalg.norm(r) / nf
+                if lc == 0 and it8 is None and rel <= 1e-8:
+                    it8 = it
+                if rel <= rtol_ref:
+                    r = b - H.A[0] @ x  # the true residual decides
+                    if np.linalg.norm(r) / nf <= rtol_ref:
+                        break
+                z = multigrid.vcycle(H, r, weights=weights)
+                rzn = r @ z
+                p = z + (rzn / rz) * p
+                rz = rzn
+            its += it
+            res = max(res, np.linalg.norm(b - H.A[0] @ x) / nf)
+            us.append(x)
+        t_iter = (time.perf_counter() - t1) / max(its, 1)
+    u = np.stack(us)
+    c = float(np.einsum("ld,ld->", f, u))
+    return dict(u=u, c=c, t_setup=t_setup, t_iter=t_iter, iters=its, it8=it8, rel_res=res,
+                rtol=rtol_ref)
+
+
+def cpu_baseline_from(ref, cfg):
+    """The oracle's cold solve to 1e-8 on one host thread (setup + the CG
+    iterations it needed), from the reference run."""
+    need = ref["it8"] if ref["it8"] is not None else float("nan")
+    t_solve = (ref["t_setup"] + need * ref["t_iter"]) * cfg["nrhs"]
+    out = dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
+               sample=(f"oracle (NumPy/SciPy FP64, 1 thread; BLAS limited to 1) on one density "
+                       f"field of the workload ({cfg['name']}), cold start: assembly + Galerkin "
+                       f"hierarchy {ref['t_setup']:.1f} s, {need} MG-preconditioned CG "
+                       f"iterations to rel. residual 1e-8 at {ref['t_iter']:.3f} s each "
+                       f"(timed inside a run to {ref['rtol']:.0e}, {ref['iters']} iterations); "
+                       f"x{cfg['nrhs']} load cases = {t_solve:.1f} s per solve.  The GPU steps "
+                       f"are warm-started; the GPU's cold solve of the same field is "
+                       f"accuracy.fp64.cold"))
+    out.update(host_info())
+    out["threads"] = 1
+    return out
 
 
 def run(args):
@@ -303,12 +344,93 @@ def run(args):
         "roofline": roofline,
     }
     if not args.no_cpu:
-        log("timing the oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, fields, budget_s=args.cpu_budget)
+        log("oracle reference solve on the host ...")
+        ref = oracle_reference(cfg, fields[0], budget_s=args.cpu_budget)
+        out["accuracy"] = accuracy_legs(args, cfg, mask, f, base, fields[0], prob, ref)
+        out["cpu_baseline"] = cpu_baseline_from(ref, cfg)
+    if not args.no_served and args.config == "c2":
+        # the served mix on both paths: Poisson arrivals at the frozen rate
+        # (throughput = offered load; latency differs), then every request
+        # queued at once (capacity: solves/s differ)
+        out["served"] = {}
+        for leg in ("fp64", "mixed"):
+            entry = {}
+            for mode, rate, nreq in (("poisson", 0.0, args.requests),
+                                     ("capacity", 1000.0, args.requests // 2)):
+                log(f"served mix, {leg}, {mode} ...")
+                sv = served_mix(args, leg, rate=rate, requests=nreq)
+                entry[mode] = {"solves_s": sv["value"], "p50_ms": sv["p50_ms"],
+                               "p99_ms": sv["p99_ms"], "dof_cg_iter_per_s": sv["dof_cg_iter_per_s"],
+                               "not_converged": sv["not_converged"], "solves": sv["steps"],
+                               "elapsed_s": sv["elapsed_s"], "rate": sv["rate"]}
+            out["served"][leg] = entry
+        out["served"]["workload"] = (f"served mix: {args.requests} requests (cantilever / MBB / "
+                                     f"torsion; meshes 32x16x16 ... 128x64x64; n in 1,2,4; 1-4 "
+                                     f"load cases), {args.session_solves} warm-started solves per "
+                                     f"session, HBM budget {args.budget_gb} GB, {args.slots} "
+                                     f"slots; poisson: arrivals at the frozen rate; capacity: "
+                                     f"the first {args.requests // 2} requests queued at once")
     print(json.dumps(out), flush=True)
 
 
+def accuracy_legs(args, cfg, mask, f, base, rho, prob, ref):
+    """FP64 and mixed-precision solves of one field of the workload against
+    the oracle's reference solution u* (its MG-CG run to a tight residual):
+    the warm-started solve as in the timed steps (from the solution of the
+    previous design), then a cold solve of the same field."""
+    import torch
+    from paper_2311_05595_amd import api
+    dev = torch.device("cuda:0")
+    bench_prec = args.precision or cfg["precision"]
+    ustar, cstar = ref["u"], ref["c"]
+    out = {"reference": {"solver": "oracle MG-preconditioned CG (FP64, 1 thread)",
+                         "rel_res": float(f"{ref['rel_res']:.3g}"), "iters": ref["iters"],
+                         "iters_to_1e-8": ref["it8"]}}
+    drho = torch.tensor(rho.ravel(), dtype=torch.float64, device=dev)
+    for leg in ("fp64", "mixed"):
+        if leg == bench_prec:
+            q = prob
+        else:
+            q = api.Problem(cfg["nel"], mask, f, order=cfg["order"], nsub=cfg["nsub"],
+                            nlevels=cfg["nlevels"], precision=leg, omega=cfg["omega"],
+                            pre=cfg["pre"], post=cfg["post"], family=cfg.get("family", "lagrange"))
+            q.use_torch_stream()
+            q.set_densities(torch.tensor(base.ravel(), dtype=torch.float64, device=dev))
+            q.solve(rtol=args.rtol, maxit=args.maxit, warm_start=False)
+        q.set_densities(drho)
+        iw = q.solve(rtol=args.rtol, maxit=args.maxit, warm_start=True)
+        uw = q.displacement()
+        cw = float(q.compliance_sensitivity(want_dc=False)[0][q.nrhs])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ic = q.solve(rtol=args.rtol, maxit=args.maxit, warm_start=False)
+        torch.cuda.synchronize()
+        t_cold = time.perf_counter() - t0
+        uc = q.displacement()
+        cc = float(q.compliance_sensitivity(want_dc=False)[0][q.nrhs])
+        nu = np.linalg.norm(ustar)
+        out[leg] = {
+            "rtol": args.rtol,
+            "warm": {"u_rel_err": float(f"{np.linalg.norm(uw - ustar) / nu:.3g}"),
+                     "c_rel_err": float(f"{abs(cw - cstar) / abs(cstar):.3g}"),
+                     "iters": max(iw["iters"][:q.nrhs]),
+                     "rel_res": float(f"{max(iw['rel_res'][:q.nrhs]):.3g}")},
+            "cold": {"u_rel_err": float(f"{np.linalg.norm(uc - ustar) / nu:.3g}"),
+                     "c_rel_err": float(f"{abs(cc - cstar) / abs(cstar):.3g}"),
+                     "iters": max(ic["iters"][:q.nrhs]),
+                     "rel_res": float(f"{max(ic['rel_res'][:q.nrhs]):.3g}"),
+                     "solve_ms": round(t_cold * 1e3, 3)},
+        }
+        if q is not prob:
+            q.close()
+    return out
+
+
 def run_served(args):
+    print(json.dumps(served_mix(args, args.precision or "mixed")), flush=True)
+
+
+def served_mix(args, prec, rate=None, requests=None):
     """The served mix: sessions of warm-started solves over requests of
     different meshes, density subdivisions, structures and load-case counts,
     arriving as a Poisson process and admitted by an HBM budget.
@@ -323,9 +445,10 @@ def run_served(args):
     import workloads as W
     from workloads import configs as CF
     from paper_2311_05595_amd import api
-    prec = args.precision or "mixed"
-    n = args.requests
-    rate = args.rate if args.rate else CF.SERVE_RATE[prec]
+    n = requests or args.requests
+    if rate is None:
+        rate = args.rate
+    rate = rate if rate else CF.SERVE_RATE[prec]
     reqs = CF.serve_requests(n, seed=5, rate=rate, solves_per_session=args.session_solves)
     bases = CF.serve_base_fields(reqs)
     log(f"served mix: {n} requests x {args.session_solves} solves, {len(bases)} base fields, "
@@ -419,8 +542,9 @@ def run_served(args):
         "not_converged": len(failed),
         "dof_cg_iter_per_s": float(f"{dof_iters / elapsed:.4g}"),
         "elapsed_s": round(elapsed, 3),
+        "rate": rate,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 PROJ_WORKLOAD = dict(nel=(64, 32, 32), nsub=4, ndes=2, rmin=1.5)
@@ -735,7 +859,10 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=60.0,
+                    help="seconds of oracle CG iterations for the reference solve")
+    ap.add_argument("--no-served", action="store_true",
+                    help="default line without the served FP64-vs-mixed legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     ap.add_argument("--projection", action="store_true",
                     help="time the design-variable projection and its transpose")

@@ -19,9 +19,14 @@ class Compliance(torch.autograd.Function):
         r = rho.detach().to(torch.float64).contiguous()
         problem.set_densities(r)
         info = problem.solve(rtol=rtol, maxit=maxit, warm_start=warm_start)
-        dc = torch.empty(problem.nrho, dtype=torch.float64, device=rho.device)
-        c, _ = problem.compliance_sensitivity(dc_out=dc)
-        ctx.save_for_backward(dc)
+        # the adjoint kernel runs with the forward solve (the problem's u may
+        # change before backward), and only when a gradient is wanted
+        if ctx.needs_input_grad[0]:
+            dc = torch.empty(problem.nrho, dtype=torch.float64, device=rho.device)
+            c, _ = problem.compliance_sensitivity(dc_out=dc)
+            ctx.save_for_backward(dc)
+        else:
+            c, _ = problem.compliance_sensitivity(want_dc=False)
         ctx.shape = rho.shape
         ctx.dtype = rho.dtype
         ctx.info = info

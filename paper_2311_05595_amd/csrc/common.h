@@ -100,6 +100,9 @@ struct CgScalars {
   double rr_best;  // smallest true ||r||^2 seen at a check
   int stall;       // consecutive checks without progress
   int bad;         // non-finite r^T z seen
+  double rr_min;   // smallest recurrence ||r||^2 since the last true-residual check
+  int since;       // iterations since rr_min last fell by 10 %
+  int restart;     // 1: the next direction is z alone (beta = 0), after a replacement
 };
 
 }  // namespace mgcg

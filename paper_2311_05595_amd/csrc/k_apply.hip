@@ -1462,6 +1462,9 @@ __global__ void k_fin_init(CgScalars* cs, int nrhs, const double* part, int nb) 
       c.rr_best = rr;
       c.stall = 0;
       c.bad = 0;
+      c.rr_min = rr;
+      c.since = 0;
+      c.restart = 0;
       if (!isfinite(rr) || !isfinite(ff))
         c.state = CG_BREAKDOWN;
       else if (ff == 0.0 || rr <= c.tol2)
@@ -1537,6 +1540,8 @@ __global__ void k_fin_warm(CgScalars* cs, int nrhs, const double* part2, int nb)
       if (c.state != CG_ACTIVE && c.state != CG_DONE) continue;  // breakdown stays
       c.rr = rr;
       c.rr_best = rr;
+      c.rr_min = rr;
+      c.since = 0;
       if (!isfinite(rr))
         c.state = CG_BREAKDOWN;
       else if (c.ff == 0.0 || rr <= c.tol2)
@@ -1658,16 +1663,21 @@ __global__ void k_fin_rr(CgScalars* cs, int nrhs, const double* part, int nb) {
     // the scalars the test needs travel with the partial sums
     int state = state_of(cs, r), it = cs_int(cs, r, CS_OFF(iters)),
         bad = cs_int(cs, r, CS_OFF(bad)), maxit = cs_int(cs, r, CS_OFF(maxit)),
-        every = cs_int(cs, r, CS_OFF(replace_every));
-    double pq = cs_dbl(cs, r, CS_OFF(pq)), tol2 = cs_dbl(cs, r, CS_OFF(tol2));
+        every = cs_int(cs, r, CS_OFF(replace_every)), since = cs_int(cs, r, CS_OFF(since)),
+        reps = cs_int(cs, r, CS_OFF(replacements));
+    double pq = cs_dbl(cs, r, CS_OFF(pq)), tol2 = cs_dbl(cs, r, CS_OFF(tol2)),
+           rmin = cs_dbl(cs, r, CS_OFF(rr_min));
     const double s = block_sum_loads(part + (size_t)r * MAX_BLOCKS, nb);
     pin(state);
     pin(it);
     pin(bad);
     pin(maxit);
     pin(every);
+    pin(since);
+    pin(reps);
     pin(pq);
     pin(tol2);
+    pin(rmin);
     const double rr = block_sum_finish(s, sh);
     if (state != CG_ACTIVE) continue;  // uniform
     if (threadIdx.x == 0) {
@@ -1675,9 +1685,19 @@ __global__ void k_fin_rr(CgScalars* cs, int nrhs, const double* part, int nb) {
       c.rr = rr;
       it += 1;
       c.iters = it;
+      c.restart = 0;  // consumed by this iteration's direction update
+      const bool progress = rr < 0.81 * rmin;
+      if (progress) c.rr_min = rr;
+      c.since = progress ? 0 : since + 1;
+      // Below the attainable accuracy the recurrence residual no longer
+      // tracks the true one: after a replacement it can sit above the
+      // tolerance, or grow.  Either sends the iteration to a true-residual
+      // check, where the stall count ends it.
+      const bool stuck = reps > 0 && since + 1 >= 32;
+      const bool grows = !(rr <= 1e8 * rmin);
       if (!(pq > 0.0) || !isfinite(pq) || bad || !isfinite(rr))
         c.state = CG_BREAKDOWN;
-      else if (rr <= tol2 || it >= maxit || (every > 0 && it % every == 0))
+      else if (rr <= tol2 || it >= maxit || (every > 0 && it % every == 0) || stuck || grows)
         c.state = CG_CHECK;
     }
     __syncthreads();
@@ -1716,14 +1736,20 @@ __global__ void k_fin_true(CgScalars* cs, int nrhs, const double* part, int nb) 
       } else {
         c.stall += 1;
       }
-      if (!isfinite(rr) || rr > 1e30 * c.ff)
+      if (!isfinite(rr) || rr > 1e30 * c.ff) {
         c.state = CG_BREAKDOWN;
-      else if (rr <= c.tol2)
+      } else if (rr <= c.tol2) {
         c.state = CG_DONE;
-      else if (c.iters >= c.maxit || c.stall >= 3)
+      } else if (c.iters >= c.maxit || c.stall >= 3) {
         c.state = CG_MAXIT;
-      else
+      } else {
+        // continue from the true residual with a fresh direction: the old
+        // one belongs to the recurrence it replaces
         c.state = CG_ACTIVE;
+        c.rr_min = rr;
+        c.since = 0;
+        c.restart = 1;
+      }
     }
     __syncthreads();
   }
@@ -1810,7 +1836,8 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
   for (int rr = 0; rr < 4; ++rr) {
     if (rr >= nrhs) continue;
     // scalars loaded first, tested once the first operands are on their way
-    int state = state_of(cs, rr), it = cs_int(cs, rr, CS_OFF(iters));
+    int state = state_of(cs, rr), it = cs_int(cs, rr, CS_OFF(iters)),
+        restart = cs_int(cs, rr, CS_OFF(restart));
     double rz0 = cs_dbl(cs, rr, CS_OFF(rzs)), rz1 = cs_dbl(cs, rr, CS_OFF(rzs) + 8);
     const size_t o = (size_t)rr * ndof;
     const size_t nb = (size_t)ndof * sizeof(double);
@@ -1832,6 +1859,7 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
     const double sm = flexible ? block_sum_loads(part + (size_t)(4 + rr) * MAX_BLOCKS, nbz) : 0.0;
     pin(state);
     pin(it);
+    pin(restart);
     pin(rz0);
     pin(rz1);
     const double rzn = block_sum_finish(sn, sh);
@@ -1841,7 +1869,7 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
     const double rzo = par ? rz1 : rz0;
     const bool ok = isfinite(rzn) && isfinite(rzm);
     const double num = flexible ? (rzn - rzm) : rzn;
-    const double b = (!ok || rzo == 0.0) ? 0.0 : num / rzo;
+    const double b = (!ok || rzo == 0.0 || restart) ? 0.0 : num / rzo;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cs[rr].rzs[par ^ 1] = rzn;
       cs[rr].beta = b;
@@ -2386,6 +2414,8 @@ __global__ void k_cg_reset(CgScalars* cs, int nrhs, double rtol2, int maxit, int
   cs[r].state = CG_ACTIVE;
   cs[r].iters = 0;
   cs[r].replacements = 0;
+  cs[r].restart = 0;
+  cs[r].since = 0;
 }
 
 void cg_reset(CgScalars* cs, int nrhs, double rtol2, int maxit, int replace_every, int flexible,

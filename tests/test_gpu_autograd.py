@@ -74,3 +74,50 @@ def test_gradient_matches_central_differences(seed):
     an = float(g @ v)
     assert abs(fd - an) <= 1e-6 * abs(an) + 5e-14 * abs(comp.item()) / h
     p.close()
+
+
+def test_gradient_central_differences_64x32x32_n4_mixed():
+    """The multiresolution workload at its full size (64x32x32 elements, 4^3
+    densities each, 4.2M densities, mixed precision): 32 seeded density
+    fields (the workload's random field with seeded +-0.05 perturbations),
+    each with a directional central difference (h = 1e-6) along a seeded
+    Rademacher direction against dc.v from the adjoint kernel.  Compliance
+    values from the energy-corrected c~ (second order in the solve error);
+    bound as above with the rounding of c over ~2e5 terms."""
+    need_gpu()
+    import torch
+    import workloads as W
+    from workloads import configs as CF
+    from paper_2311_05595_amd import api, autograd
+    cfg = CF.config("c3")
+    mask, f = CF.problem(cfg)
+    base = CF.densities(cfg)
+    p = api.Problem(cfg["nel"], mask, f, order=1, nsub=cfg["nsub"], nlevels=cfg["nlevels"],
+                    precision=cfg["precision"], omega=cfg["omega"])
+    h = 1e-6
+    worst = 0.0
+    for k in range(32):
+        rho = W.perturb(base, 3000 + k)
+        print(f"[fd c3] field {k}", flush=True)
+        t = torch.tensor(rho.ravel(), dtype=torch.float64, device="cuda", requires_grad=True)
+        comp = autograd.compliance(t, p, rtol=1e-9, maxit=3000, warm_start=False)
+        comp.backward()
+        g = t.grad.detach().cpu().numpy()
+        v = np.random.default_rng(3100 + k).choice([-1.0, 1.0], size=rho.size)
+        # densities within h of a bound (the field is clipped to [1e-3, 1])
+        # do not move: both perturbed fields stay admissible
+        v[(rho.ravel() > 1.0 - h) | (rho.ravel() < h)] = 0.0
+        vals = []
+        for s in (1.0, -1.0):
+            r = torch.tensor(rho.ravel() + s * h * v, dtype=torch.float64, device="cuda")
+            p.set_densities(r)
+            info = p.solve(rtol=1e-9, maxit=3000, warm_start=True)
+            assert info["status"] == 0
+            vals.append(_compliance_energy(p, f))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = float(g @ v)
+        bound = 1e-6 * abs(an) + 2e-13 * abs(comp.item()) / h
+        worst = max(worst, abs(fd - an) / bound)
+        assert abs(fd - an) <= bound, (k, fd, an)
+    print(f"[fd c3] worst |fd - dc.v| / bound = {worst:.3f}", flush=True)
+    p.close()

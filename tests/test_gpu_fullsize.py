@@ -78,3 +78,41 @@ def test_cantilever_q2_48x24x24_n4_two_load_cases_mixed():
 def test_cantilever_serendipity_48x24x24_n4_mixed():
     need_gpu()
     _run("c4s", 1e-8)
+
+
+def test_error_vs_oracle_mgcg_64x32x32_n4_mixed():
+    """The multiresolution workload at full size against the oracle's own
+    solution (its MG-preconditioned CG on the assembled operator, run until
+    its true residual stops falling, here ~1e-11): the mixed-precision GPU
+    solve at rel. residual 1e-10 within 1e-8 in u and 1e-9 in c."""
+    need_gpu()
+    import torch
+    from workloads import configs as CF
+    from oracle import fem, solve
+    from paper_2311_05595_amd import api
+    cfg = CF.config("c3")
+    mask, f = CF.problem(cfg)
+    rho = CF.densities(cfg)
+    nel, nsub = cfg["nel"], cfg["nsub"]
+    p = api.Problem(nel, mask, f, order=1, nsub=nsub, nlevels=cfg["nlevels"],
+                    precision=cfg["precision"], omega=cfg["omega"])
+    p.use_torch_stream()
+    p.set_densities(torch.tensor(rho.ravel(), dtype=torch.float64, device="cuda"))
+    info = p.solve(rtol=1e-9, maxit=5000, warm_start=False)
+    assert info["status"] == 0
+    u = p.displacement()
+    c, _ = p.compliance_sensitivity(want_dc=False)
+    p.close()
+    Ks = fem.sub_element_matrices(1, nsub)
+    K = solve.stiffness(rho, nel, 1, nsub, Ks, **MAT)
+    us, info_o = solve.solve_mgcg(K, mask, f, solve.node_dims(nel, 1), cfg["nlevels"],
+                                  rtol=3e-11, omega=cfg["omega"], maxit=400)
+    res_o = info_o[0][1]
+    print(f"[fullsize] oracle MG-CG reference: true rel. residual {res_o:.2e}", flush=True)
+    assert res_o <= 1e-9
+    eu = rel(u[0], us[0])
+    cs = float(f[0] @ us[0])
+    ec = abs(c[0] - cs) / abs(cs)
+    print(f"[fullsize] c3 mixed at 1e-9: |u - u*|/|u*| = {eu:.2e}, |c - c*|/c* = {ec:.2e}",
+          flush=True)
+    assert eu <= 1e-8 and ec <= 1e-9

@@ -2,8 +2,10 @@
 oracle: the library's own serendipity matrices on the 27-node lattice with
 the face and body centres fixed, solved by MGCG, against the oracle's direct
 solve with its own serendipity matrices and the same fixed DOFs.  The solve
-stops at a relative residual of 1e-10; displacements, compliance and dc/drho
-agree to what that residual leaves (rtol 1e-7 on u, 1e-9 on c)."""
+runs to a relative residual of 1e-12 (or its attainable accuracy, at most
+2e-12); displacements and dc/drho agree to
+1e-8 (relative 2-norm) and the compliance to 1e-9, per load case, with up to
+four load cases in one solve."""
 
 import numpy as np
 import pytest
@@ -13,34 +15,40 @@ from tests.helpers import need_gpu
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("nel,n,nlevels,precision,seed", [
-    ((8, 4, 4), 1, 2, "fp64", 0), ((8, 4, 4), 2, 3, "fp64", 1), ((6, 4, 2), 1, 2, "mixed", 2),
-    ((5, 3, 3), 2, 2, "fp64", 3)])
-def test_serendipity_solve_matches_oracle(nel, n, nlevels, precision, seed):
+@pytest.mark.parametrize("nel,n,nlevels,precision,seed,nrhs", [
+    ((8, 4, 4), 1, 2, "fp64", 0, 1), ((8, 4, 4), 2, 3, "fp64", 1, 1),
+    ((6, 4, 2), 1, 2, "mixed", 2, 1), ((5, 3, 3), 2, 2, "fp64", 3, 1),
+    ((6, 2, 2), 1, 2, "fp64", 4, 3), ((4, 2, 2), 2, 2, "mixed", 5, 4)])
+def test_serendipity_solve_matches_oracle(nel, n, nlevels, precision, seed, nrhs):
     need_gpu()
     import workloads as W
     from oracle import fem, solve
     from paper_2311_05595_amd import api
-    mask, f = W.make_problem("cantilever", *nel, 2, 1)
+    mask, f = W.make_problem("cantilever", *nel, 2, nrhs)
     rng = np.random.default_rng(seed)
     rho = rng.uniform(0.1, 1.0, (n * nel[2], n * nel[1], n * nel[0]))
     p = api.Problem(nel, mask, f, order=2, nsub=n, nlevels=nlevels, precision=precision,
                     family="serendipity")
     p.set_densities(rho.reshape(-1))
-    info = p.solve(rtol=1e-10, maxit=4000, warm_start=False)
-    u = p.displacement().reshape(-1)
+    # 1e-12 is at the attainable accuracy of some of these cases (the true
+    # residual stalls near 1.2e-12, where the solve ends as not converged)
+    info = p.solve(rtol=1e-12, maxit=4000, warm_start=False, allow_notconv=True)
+    assert max(info["rel_res"][:nrhs]) <= 2e-12
+    u = p.displacement()
     c, dc = p.compliance_sensitivity()
     p.close()
     ms = np.maximum(mask, fem.serendipity_dof_mask(nel))
     Ks = fem.sub_element_matrices(2, n, family="serendipity")
     _, u_o, c_o, dc_o = solve.solve_problem(rho, ms, f, nel, 2, n, Ks, E0=1.0, Emin=1e-9,
                                             penal=3.0)
-    u_o = np.asarray(u_o).reshape(-1)
-    assert np.all(u[ms.astype(bool)] == 0.0)
-    assert np.abs(u - u_o).max() <= 1e-7 * np.abs(u_o).max()
+    u_o = np.asarray(u_o).reshape(nrhs, -1)
+    for lc in range(nrhs):
+        assert np.all(u[lc][ms.astype(bool)] == 0.0)
+        assert np.linalg.norm(u[lc] - u_o[lc]) <= 1e-8 * np.linalg.norm(u_o[lc]), lc
+        assert abs(c[lc] - c_o[lc]) <= 1e-9 * abs(c_o[lc]), lc
     assert abs(c[-1] - c_o.sum()) <= 1e-9 * c_o.sum()
     dc_o = np.asarray(dc_o).reshape(-1)
-    assert np.abs(dc.reshape(-1) - dc_o).max() <= 1e-7 * np.abs(dc_o).max()
+    assert np.linalg.norm(dc.reshape(-1) - dc_o) <= 1e-8 * np.linalg.norm(dc_o)
 
 
 def test_serendipity_differs_from_lagrange():

@@ -22,6 +22,9 @@ SOLVE_CASES = [
     ("cantilever", (10, 6, 6), 1, 1, 1, 1, "grf", "fp64"),        # single level: dense solve
     ("cantilever", (6, 2, 2), 1, 1, 2, 4, "uniform", "mixed"),    # four load cases, ragged
     ("torsion", (16, 8, 8), 1, 1, 4, 4, "uniform", "fp64"),
+    # triquadratic elements with three and four load cases in one solve
+    ("cantilever", (6, 4, 4), 2, 2, 3, 3, "grf", "mixed"),
+    ("torsion", (4, 2, 2), 2, 1, 2, 4, "uniform", "fp64"),
 ]
 
 

@@ -857,7 +857,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--maxit", type=int, default=1000)
+    ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=60.0,
                     help="seconds of oracle CG iterations for the reference solve")

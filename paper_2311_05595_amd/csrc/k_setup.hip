@@ -780,9 +780,179 @@ __global__ __launch_bounds__(BS) void k_sens(int nsub, int nelx, int nely, int n
   dc[di] = -penal * pow(r, penal - 1.0) * E0mEmin * w;
 }
 
+// With 4^3 sub-elements the 64 quadratic forms of an element are one
+// contraction: w_s = sum_l u_l^T K_s u_l = sum_{i <= j} U[k(i,j)] Kp[k(i,j)][s]
+// with U = sum_l u_l u_l^T (symmetric, packed row by row, i <= j) and Kp[k][s]
+// = K_s[i][j] times 2 off the diagonal (built once per mesh, sens_pack).
+// Over a block of SP_EL = 16 elements this is a (16 x NK) by (NK x 64)
+// product, run on the FP64 matrix cores (16x16x4 MFMA): the elements are the
+// rows, the 64 sub-elements four column tiles (tile t, column n holds
+// s = 4 n + t, so a lane's four B values are one 32-byte segment of a Kp
+// row), four packed pairs per step.  A lane forms its A value U[e][k] from
+// u_e staged in LDS, at the LDS offsets of (i, j) that a table beside Kp
+// holds; Kp streams from L2 (1.7 MB for Q2) in chunks of SP_PF steps, one
+// chunk ahead, in two register sets that alternate.  For Q2 the block's
+// WPB = 4 waves split the packed pairs and add their tiles in a fixed order.
+// Kp and the table are padded (zero rows, offset 0) to an even number of
+// chunks per wave plus the prefetch overrun.
+constexpr int SP_EL = 16;  // elements per block
+constexpr int SP_PF = 4;   // steps per Kp chunk
+template <int ORDER>
+struct SensShape {
+  static constexpr int ND = 3 * (ORDER + 1) * (ORDER + 1) * (ORDER + 1);
+  static constexpr int NK = ND * (ND + 1) / 2;
+  static constexpr int WPB = ORDER == 1 ? 1 : 4;
+  static constexpr int QUANT = 4 * WPB * SP_PF * 2;
+  static constexpr int NKP = (NK + QUANT - 1) / QUANT * QUANT;  // pairs the waves walk
+  static constexpr int STEPS = NKP / (4 * WPB);                 // steps per wave
+  static constexpr int ROWS = NKP + 4 * SP_PF;                  // + the prefetch overrun
+};
+
+long sens_packed_doubles(int order) {
+  const long rows = order == 1 ? SensShape<1>::ROWS : SensShape<2>::ROWS;
+  return rows * 64 + rows / 2;  // Kp rows, then one 32-bit offset pair per row
+}
+
+void sens_pack(int order, const double* Ksub, std::vector<double>& out) {
+  const int nd = order == 1 ? SensShape<1>::ND : SensShape<2>::ND;
+  const long rows = order == 1 ? SensShape<1>::ROWS : SensShape<2>::ROWS;
+  out.assign((size_t)sens_packed_doubles(order), 0.0);
+  uint32_t* tab = reinterpret_cast<uint32_t*>(out.data() + rows * 64);
+  long k = 0;
+  for (int i = 0; i < nd; ++i)
+    for (int j = i; j < nd; ++j, ++k) {
+      for (int s = 0; s < 64; ++s)
+        out[(size_t)k * 64 + s] = (i == j ? 1.0 : 2.0) * Ksub[(size_t)s * nd * nd + (size_t)i * nd + j];
+      // byte offsets of u[i] and u[j] in the staged [DOF][element] block
+      tab[k] = (uint32_t)(i * SP_EL * 8) | ((uint32_t)(j * SP_EL * 8) << 16);
+    }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int ORDER, int NRHS>
+__global__ __launch_bounds__(64 * SensShape<ORDER>::WPB) void k_sens_mfma(
+    int nelx, int nely, int nelz, Lat L, const double* __restrict__ rho,
+    const double* __restrict__ u, long ndof, const double* __restrict__ Kp, double E0mEmin,
+    double penal, double* __restrict__ dc) {
+  using S = SensShape<ORDER>;
+  constexpr int P1 = ORDER + 1, ND = S::ND, WPB = S::WPB, NT = 64 * WPB;
+  constexpr int NU = NRHS * ND * SP_EL, NR = WPB * SP_EL * 64;
+  constexpr int NCH = S::STEPS / SP_PF;  // chunks per wave (even)
+  static_assert(NCH % 2 == 0, "two alternating register sets");
+  static_assert(ND * SP_EL * 8 < 65536, "16-bit LDS offsets");
+  __shared__ double sh[NU > NR ? NU : NR];
+  __shared__ uint32_t tab[S::NKP];
+  const long nel = (long)nelx * nely * nelz;
+  const long e0 = (long)blockIdx.x * SP_EL;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint32_t* tabg = reinterpret_cast<const uint32_t*>(Kp + (size_t)S::ROWS * 64);
+  for (int q = t; q < S::NKP; q += NT) tab[q] = tabg[q];
+  // u_e of the block's elements, [load case][local DOF][element]; elements
+  // past the mesh read 0
+  for (int q = t; q < NU; q += NT) {
+    const int m = q & (SP_EL - 1), d = (q / SP_EL) % ND, r = q / (SP_EL * ND);
+    const long e = e0 + m;
+    double v = 0.0;
+    if (e < nel) {
+      const int ex = (int)(e % nelx), ey = (int)((e / nelx) % nely),
+                ez = (int)(e / ((long)nelx * nely));
+      const int a = d / 3, c = d % 3;
+      const int ax = a % P1, ay = (a / P1) % P1, az = a / (P1 * P1);
+      const long node =
+          (ORDER * ex + ax) + (long)L.nx * ((ORDER * ey + ay) + (long)L.ny * (ORDER * ez + az));
+      v = u[(size_t)r * ndof + 3 * node + c];
+    }
+    sh[q] = v;
+  }
+  __syncthreads();
+  // lane (m, kk): A row m (element e0 + m) and B column m (sub-elements
+  // 4 m .. 4 m + 3, one per tile) at pair k0 + 4 step + kk
+  const int m = lane & 15, kk = lane >> 4;
+  const int k0 = w * S::STEPS * 4 + kk;
+  const char* ub = reinterpret_cast<const char*>(sh) + m * 8;
+  const double4* kb = reinterpret_cast<const double4*>(Kp) + (size_t)k0 * 16 + m;
+  v4d acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto fetch = [&](double4* b, int c) {
+#pragma unroll
+    for (int p = 0; p < SP_PF; ++p) b[p] = kb[(size_t)(c * SP_PF + p) * 64];
+  };
+  auto run = [&](const double4* b, int c) {
+#pragma unroll
+    for (int p = 0; p < SP_PF; ++p) {
+      const uint32_t ij = tab[k0 + 4 * (c * SP_PF + p)];
+      const int oi = (int)(ij & 0xffffu), oj = (int)(ij >> 16);
+      double a = 0.0;
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r)
+        a = fma(*reinterpret_cast<const double*>(ub + oi + r * ND * SP_EL * 8),
+                *reinterpret_cast<const double*>(ub + oj + r * ND * SP_EL * 8), a);
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[p].x, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[p].y, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[p].z, acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[p].w, acc[3], 0, 0, 0);
+    }
+  };
+  double4 b0[SP_PF], b1[SP_PF];
+  fetch(b0, 0);
+  for (int c = 0; c < NCH; c += 2) {
+    fetch(b1, c + 1);
+    run(b0, c);
+    fetch(b0, c + 2);  // (the last one reads the zero overrun rows)
+    run(b1, c + 1);
+  }
+  __syncthreads();  // every wave is done with the staged u
+  // result value v of a lane is row kk + 4 v, column m of its tile (the
+  // FP64 16x16x4 output layout): w[s][element] per wave
+  double* red = sh + w * SP_EL * 64;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[(4 * m + q) * SP_EL + kk + 4 * v] = acc[q][v];
+  __syncthreads();
+  // outputs in density-lattice order within each (sy, sz) row: sub-element
+  // x fastest, then element
+  for (int q = t; q < SP_EL * 64; q += NT) {
+    const int sx = q & 3, mm = (q >> 2) & (SP_EL - 1), syz = q >> 6;
+    const int s = sx + 4 * syz;
+    double v = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < WPB; ++ww) v += sh[ww * SP_EL * 64 + s * SP_EL + mm];
+    const long e = e0 + mm;
+    if (e >= nel) continue;
+    const int ex = (int)(e % nelx), ey = (int)((e / nelx) % nely), ez = (int)(e / ((long)nelx * nely));
+    const int sy = syz & 3, sz = syz >> 2;
+    const long di =
+        (4 * ex + sx) + (long)(4 * nelx) * ((4 * ey + sy) + (long)(4 * nely) * (4 * ez + sz));
+    dc[di] = -penal * pow(rho[di], penal - 1.0) * E0mEmin * v;
+  }
+}
+
+template <int ORDER>
+static void launch_sens_mfma(int nelx, int nely, int nelz, Lat L, const double* rho,
+                             const double* u, long ndof, int nrhs, const double* Kp,
+                             double E0mEmin, double penal, double* dc, hipStream_t st) {
+  const dim3 g(nblocks((long)nelx * nely * nelz, SP_EL)), b(64 * SensShape<ORDER>::WPB);
+  auto kern = nrhs == 1   ? k_sens_mfma<ORDER, 1>
+              : nrhs == 2 ? k_sens_mfma<ORDER, 2>
+              : nrhs == 3 ? k_sens_mfma<ORDER, 3>
+                          : k_sens_mfma<ORDER, 4>;
+  hipLaunchKernelGGL(kern, g, b, 0, st, nelx, nely, nelz, L, rho, u, ndof, Kp, E0mEmin, penal, dc);
+}
+
 void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const double* rho,
-                 const double* u, long ndof, int nrhs, const double* Ksub, double /*scale_p*/,
+                 const double* u, long ndof, int nrhs, const double* Ksub, const double* Kp,
                  double E0mEmin, double penal, double* dc, hipStream_t st) {
+  if (nsub == 4 && Kp) {
+    if (order == 1)
+      launch_sens_mfma<1>(nelx, nely, nelz, L, rho, u, ndof, nrhs, Kp, E0mEmin, penal, dc, st);
+    else
+      launch_sens_mfma<2>(nelx, nely, nelz, L, rho, u, ndof, nrhs, Kp, E0mEmin, penal, dc, st);
+    MGCG_HIP(hipGetLastError());
+    return;
+  }
   const dim3 grid(nblocks((long)nelx * nely * nelz), nsub * nsub * nsub);
   if (order == 1)
     hipLaunchKernelGGL(k_sens<1>, grid, dim3(BS), 0, st, nsub, nelx, nely, nelz, L, rho, u, ndof,

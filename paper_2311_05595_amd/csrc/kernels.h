@@ -4,6 +4,8 @@
 #include "common.h"
 #include "q1table.h"
 
+#include <vector>
+
 namespace mgcg {
 
 // Node lattice of a level.
@@ -274,8 +276,14 @@ double* setup_coarse_inverse(double* A, double* B, double* D, double* diag0, int
 // Compliance and sensitivity.
 void comp_dot(const double* f, const double* u, long ndof, int nrhs, double* out, RedBuf red,
               hipStream_t st);
+// dc/drho (Sec. 3.4); Kp: the packed form of Ksub for 4^3 sub-elements
+// (sens_pack: sens_packed_doubles(order) values), or null.
+long sens_packed_doubles(int order);
+// Ksub [64][nd][nd] -> the packed sub-element matrices of the sensitivity
+// contraction and their pair table.
+void sens_pack(int order, const double* Ksub, std::vector<double>& out);
 void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const double* rho,
-                 const double* u, long ndof, int nrhs, const double* Ksub, double scale_p,
+                 const double* u, long ndof, int nrhs, const double* Ksub, const double* Kp,
                  double E0mEmin, double penal, double* dc, hipStream_t st);
 
 // Timing-free plain copy (for traffic calibration).

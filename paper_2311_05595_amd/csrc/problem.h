@@ -135,6 +135,7 @@ class Problem {
   std::vector<size_t> hmask_off_;
   std::vector<double> hf_;
   std::vector<double> hKsub_;
+  std::vector<double> hKp_;
   std::vector<int> hfree_;      // coarsest free DOF list
   std::vector<double> hG_;      // linear Galerkin matrices of the first coarse level [M][576]
   std::vector<int> hmasked_;    // first-coarse-level elements with supported child DOFs
@@ -157,6 +158,7 @@ class Problem {
   Q1HaarVals<double> hv64_{};  // the same in the element's Haar basis
   Q1HaarVals<float> hv32_{};
   double* Ksub_ = nullptr;   // [n^3][nd*nd]
+  double* Kp_ = nullptr;     // n = 4: the packed sub-element matrices (sens_pack)
   double* K0_ = nullptr;     // [576] (MF)
   float* K032_ = nullptr;
   double* Keff_ = nullptr;   // level-0 effective element matrices (ST27: 576, EQ2: 6561)

@@ -113,6 +113,7 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   TAKE(E_, double, nrho);
   if (mixed && lv[0].kind == OP_MF_Q1) TAKE(E32_, float, nrho);
   TAKE(Ksub_, double, ns3 * ndl * ndl);
+  if (d.nsub == 4) TAKE(Kp_, double, sens_packed_doubles(d.order));
   TAKE(K0_, double, 576);
   if (mixed) TAKE(K032_, float, 576);
   TAKE(x_, double, R * nd0);
@@ -362,6 +363,12 @@ void Problem::allocate() {
     MGCG_HIP(hipMemcpyAsync(B_[l].mask, &hmask_[hmask_off_[l]], lv_[l].L.nn(), hipMemcpyHostToDevice,
                             stream_));
   MGCG_HIP(hipMemcpyAsync(f_, hf_.data(), hf_.size() * sizeof(double), hipMemcpyHostToDevice, stream_));
+  if (Kp_) {
+    // the 64 sub-element matrices packed for the sensitivity contraction
+    sens_pack(d_.order, hKsub_.data(), hKp_);
+    MGCG_HIP(hipMemcpyAsync(Kp_, hKp_.data(), hKp_.size() * sizeof(double), hipMemcpyHostToDevice,
+                            stream_));
+  }
   MGCG_HIP(hipMemcpyAsync(Ksub_, hKsub_.data(), hKsub_.size() * sizeof(double), hipMemcpyHostToDevice,
                           stream_));
   {
@@ -937,7 +944,7 @@ void Problem::compliance_sensitivity(double* c, double* dc, int mem) {
   if (dc) {
     double* out = mem == MGCG_MEM_DEVICE ? dc : dcbuf_;
     sens_kernel(d_.order, d_.nsub, d_.nelx, d_.nely, d_.nelz, lv_[0].L, rho_, x_, nd, R,
-                lv_[0].kind == OP_MF_Q1 ? K0_ : Ksub_, 0.0, d_.E0 - d_.Emin, d_.penal, out, st);
+                lv_[0].kind == OP_MF_Q1 ? K0_ : Ksub_, Kp_, d_.E0 - d_.Emin, d_.penal, out, st);
     if (mem != MGCG_MEM_DEVICE)
       MGCG_HIP(hipMemcpyAsync(dc, dcbuf_, nrho() * sizeof(double), hipMemcpyDeviceToHost, st));
   }

@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("nel,n,nlevels,precision,seed,nrhs", [
     ((8, 4, 4), 1, 2, "fp64", 0, 1), ((8, 4, 4), 2, 3, "fp64", 1, 1),
     ((6, 4, 2), 1, 2, "mixed", 2, 1), ((5, 3, 3), 2, 2, "fp64", 3, 1),
-    ((6, 2, 2), 1, 2, "fp64", 4, 3), ((4, 2, 2), 2, 2, "mixed", 5, 4)])
+    ((6, 2, 2), 1, 2, "fp64", 4, 3), ((4, 2, 2), 2, 2, "mixed", 5, 4),
+    ((4, 2, 2), 4, 2, "fp64", 6, 2)])
 def test_serendipity_solve_matches_oracle(nel, n, nlevels, precision, seed, nrhs):
     need_gpu()
     import workloads as W

@@ -25,6 +25,14 @@ SOLVE_CASES = [
     # triquadratic elements with three and four load cases in one solve
     ("cantilever", (6, 4, 4), 2, 2, 3, 3, "grf", "mixed"),
     ("torsion", (4, 2, 2), 2, 1, 2, 4, "uniform", "fp64"),
+    # 4^3 sub-elements of a triquadratic element (the packed sensitivity
+    # contraction), two load cases, ragged element blocks
+    ("cantilever", (6, 2, 2), 2, 4, 2, 2, "grf", "fp64"),
+    ("mbb", (4, 2, 2), 2, 4, 2, 1, "grf", "mixed"),
+    ("cantilever", (4, 2, 2), 2, 4, 2, 3, "grf", "fp64"),
+    # bilinear elements with 4^3 sub-elements and four load cases, 30
+    # elements (a ragged last block of the contraction)
+    ("torsion", (5, 3, 2), 1, 4, 1, 4, "grf", "fp64"),
 ]
 
 

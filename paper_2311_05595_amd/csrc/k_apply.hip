@@ -90,119 +90,6 @@ __device__ __forceinline__ void node_ijk(long node, const Lat& L, int& i, int& j
   k = (int)kk;
 }
 
-// sum_e E_e (K0 u_e) rows of the node for the 8 elements around it, FP64:
-// 24 independent accumulators (8 elements x 3 rows), local node b outermost,
-// so consecutive FMAs never depend on each other.  u: the 3x3x3 neighbour
-// values (index dx + 3 (dy + 3 dz)); E: moduli of the elements (ox, oy, oz).
-__device__ __forceinline__ void mf_rows_fp64(const Q1Vals<double>& kv, const double (&u)[27][3],
-                                             const double (&Ev)[8], double acc[3]) {
-  double t[8][3];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = 0.0;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
-#pragma unroll
-    for (int e = 0; e < 3; ++e)
-#pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
-        const int s = (ox + bx) + 3 * ((oy + by) + 3 * (oz + bz));
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int q = (3 * a + c) * 24 + 3 * b + e;
-          const double kk = kQ1.sgn[q] > 0 ? kv.v[kQ1.cls[q]] : -kv.v[kQ1.cls[q]];
-          t[o][c] = fma(kk, u[s][e], t[o][c]);
-        }
-      }
-  }
-#pragma unroll
-  for (int o = 0; o < 8; ++o)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = fma(Ev[o], t[o][c], acc[c]);
-}
-
-// Matrix-free trilinear apply at node (i,j,k): the three rows of
-// sum_e E_e K0 u_e over the (up to) 8 elements around the node, K0 entries
-// taken from the 10 class values (scalar registers) with compile-time class
-// and sign.  Inputs vanish on fixed DOFs; fixed rows return 0 (= input).
-template <typename T, class In>
-__device__ __forceinline__ void ax_mf(const OpMF<T>& op, const In& in, int r, int i, int j, int k,
-                                      T y[3]) {
-  const Lat L = op.L;
-  const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
-  const auto xb = in.buf(r);
-  const int node = i + L.nx * (j + L.ny * k);
-  const uint8_t mself = op.mask[node];
-  // Neighbour (dx, dy, dz) sits at a fixed offset from the node; no bounds
-  // checks: a neighbour off the lattice either lies outside the buffer (reads
-  // 0) or wraps onto a finite value of another row, and in both cases it only
-  // enters elements outside the mesh, whose moduli are 0 below.  Per (dy, dz)
-  // row the centre offset is the base (never negative when the row is inside
-  // the lattice), the right neighbour an immediate offset on it, the left one
-  // its own subtraction.
-  // (The byte strides come from the host, so that the compiler keeps one
-  // add per row instead of re-associating into a multiply per row.)
-  constexpr int SN = 3 * sizeof(T);
-  const int sy = op.sy, sz = op.sz;
-  const int noff = node * SN;
-  T u[27][3];
-#pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
-      const int c = noff + ((dz - 1) * sz + (dy - 1) * sy);
-      const int s = 3 * (dy + 3 * dz);
-      xb.load(c - SN, u[s]);
-      xb.load(c, u[s + 1]);
-      xb.load(c + SN, u[s + 2]);
-    }
-  // the 8 element moduli, loaded with the nodal values; elements outside
-  // the mesh read 0 (the only place where the mesh boundary is tested)
-  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
-  const bool vx[2] = {i >= 1, i < ex1}, vy[2] = {j >= 1, j < ey1}, vz[2] = {k >= 1, k < ez1};
-  const int eoff = ((i - 1) + ex1 * ((j - 1) + ey1 * (k - 1))) * (int)sizeof(T);
-  const int ey_ = op.ey, ez_ = op.ez;
-  T Ev[8];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) {
-    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-    const bool ok = vx[ox] && vy[oy] && vz[oz];
-    Ev[o] = bload<T>(re, ok ? eoff + (ox * (int)sizeof(T) + oy * ey_ + oz * ez_) : kBufOOB, 0);
-  }
-  T acc[3] = {T(0), T(0), T(0)};
-  if constexpr (sizeof(T) == 8) {
-    mf_rows_fp64(op.kv, u, Ev, acc);
-  } else {
-    // FP32: element by element keeps registers low (occupancy 8)
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-      const T Ee = Ev[o];
-      const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
-      T t[3] = {T(0), T(0), T(0)};
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
-        const int s = (ox + bx) + 3 * ((oy + by) + 3 * (oz + bz));
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            const int q = (3 * a + c) * 24 + 3 * b + e;
-            const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
-            t[c] = fma(kk, u[s][e], t[c]);
-          }
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] = fma(Ee, t[c], acc[c]);
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) y[c] = ((mself >> c) & 1) ? T(0) : acc[c];
-}
-
 // The blocks b = part, part + LPN, ... of the stencil apply (partial sum of
 // one node's rows).  `part` is wave-uniform, so every coefficient row offset
 // is a scalar.  The loop has no branches: a block index past the table (and
@@ -264,14 +151,6 @@ __device__ __forceinline__ void ax_st_part(const OpST<T>& op, const In& in, int 
   y[0] = acc[0];
   y[1] = acc[1];
   y[2] = acc[2];
-}
-
-// Dispatch by operator struct type.
-template <typename T, class In>
-__device__ __forceinline__ void ax_any(const OpMF<T>& op, const In& in, int r, long node, T y[3]) {
-  int i, j, k;
-  node_ijk(node, op.L, i, j, k);
-  ax_mf(op, in, r, i, j, k, y);
 }
 
 // Second pass of the stored-matrix triquadratic apply: a node sums the rows
@@ -713,7 +592,6 @@ template <> struct PerRhs<EpTrueResid> { static constexpr bool v = true; };
 // per block (value a0 at row r, a1 at row 4 + r of the region); the
 // consumers sum them in a fixed order (no atomics).
 template <class Op> struct Waves { static constexpr int w = 4; };
-template <typename T> struct Waves<OpMF<T>> { static constexpr int w = 2; };
 
 template <typename T, class Op, class In, class Ep>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(Waves<Op>::w)))
@@ -742,211 +620,34 @@ void k_apply(Op op, In in, Ep ep, int nrhs, const CgScalars* gate, int gate_stat
   }
 }
 
-// Matrix-free apply (FP64 or FP32) with the block's neighbourhood staged in
-// LDS.  The
-// 256 consecutive nodes of a block touch, on each of the three node planes
-// around them, one contiguous range of 256 + 2 nx + 2 nodes.  The block
-// loads those three ranges with coalesced loads (about 16 per thread instead
-// of the 27 two-part gathers per node that keep the address unit busy), and
-// every thread then reads its 27 neighbours from LDS.  Off-lattice
-// neighbours: as in ax_mf (they only meet elements of zero modulus).
-// Dynamic LDS: 3 planes x 3 lr doubles; the staging covers up to
-// MF_LDS_VALS x BS values per plane.
-constexpr int MF_LDS_VALS = 8;
-inline int mf_lds_range(const Lat& L) { return BS + 2 * L.nx + 2; }
-inline bool mf_lds_fits(const Lat& L) { return 3 * mf_lds_range(L) <= MF_LDS_VALS * BS; }
-
-template <typename T, class Ep>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void k_apply_mf_lds(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars* gate,
-                    int gate_state, double* part) {
-  extern __shared__ __align__(16) unsigned char sh_raw[];
-  T* sh = reinterpret_cast<T*>(sh_raw);
-  int bx, r;
-  xcd_tile(bx, r);
-  const Gate g = gate_load(gate, nrhs, gate_state);
-  const int gr = PerRhs<Ep>::v ? r : -1;
-  if constexpr (GateEarly<Ep>::v) {
-    if (!gate_open(g, gr)) return;
-  }
-  const Lat L = op.L;
-  const int nn = (int)L.nn();
-  const int nx = L.nx, P = L.nx * L.ny;
-  const int lr = BS + 2 * nx + 2, nd3 = 3 * lr;
-  const int n0 = bx * BS;
-  const int t_ = threadIdx.x;
-  // stage: plane sgi (dz = sgi - 1) holds nodes [n0 + dz P - nx - 1, + lr)
-  const __amdgpu_buffer_rsrc_t rx =
-      make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
-  // 8-byte loads: each value is range-checked on its own (values off the
-  // vector read exactly 0)
-  // (a value past its plane's range is still loaded, from the vector or as
-  // 0 beyond it, and simply not stored: no per-load select)
-  T v[3][MF_LDS_VALS];
-  const int off0 = (3 * (n0 - P - nx - 1) + t_) * (int)sizeof(T);  // may be negative
-  const int pstride = 3 * P * (int)sizeof(T);
-#pragma unroll
-  for (int sgi = 0; sgi < 3; ++sgi)
-#pragma unroll
-    for (int m = 0; m < MF_LDS_VALS; ++m)
-      v[sgi][m] = bload<T>(rx, off0 + (sgi * pstride + m * BS * (int)sizeof(T)), 0);
-  const int node = n0 + t_;
-  const int nodec = node < nn ? node : nn - 1;  // tail threads compute a copy, store nothing
-  int i, j, k;
-  node_ijk(nodec, L, i, j, k);
-  const uint8_t mself = op.mask[nodec];
-  // small epilogue operand sets (three values) are loaded with the stage, so
-  // that their latency hides behind the arithmetic; larger ones would push
-  // the kernel past 128 registers and load after it
-  constexpr bool kEarly = sizeof(typename Ep::Pre) <= 3 * sizeof(double);  // 3 FP64 / 6 FP32
-  typename Ep::Pre pv{};
-  if constexpr (kEarly) pv = ep.pre(r, nodec);
-  // the 8 element moduli (elements outside the mesh read 0)
-  const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
-  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
-  const bool vx[2] = {i >= 1, i < ex1}, vy[2] = {j >= 1, j < ey1}, vz[2] = {k >= 1, k < ez1};
-  const int eoff = ((i - 1) + ex1 * ((j - 1) + ey1 * (k - 1))) * (int)sizeof(T);
-  T Ev[8];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) {
-    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-    const bool ok = vx[ox] && vy[oy] && vz[oz];
-    Ev[o] = bload<T>(re, ok ? eoff + (ox * (int)sizeof(T) + oy * op.ey + oz * op.ez) : kBufOOB, 0);
-  }
-  // the stage's LDS writes come after every global load of the prologue, so
-  // that all of those loads are in flight together
-#pragma unroll
-  for (int sgi = 0; sgi < 3; ++sgi)
-#pragma unroll
-    for (int m = 0; m < MF_LDS_VALS; ++m) {
-      const int q = t_ + m * BS;
-      if (q < nd3) sh[sgi * nd3 + q] = v[sgi][m];
-    }
-  __syncthreads();
-  if (!gate_open(g, gr)) return;  // uniform: the block's loads are done
-  // Neighbour rows (dy, dz) of 3 nodes are read from LDS one at a time and
-  // folded into the 24 element partial sums, so only one row is live in
-  // registers (four waves fit per SIMD: every wave of a 0.7M-DOF apply is
-  // resident at once).  Node (dx, dy, dz) is local node b = s - o of each
-  // element o that contains it.
-  // One row of lookahead: the reads of row w + 1 are issued before the
-  // arithmetic of row w; compiler memory fences keep further reads from
-  // being hoisted (which would make all 27 nodes live again).
-  T t[8][3];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) t[o][0] = t[o][1] = t[o][2] = T(0);
-  auto read_row = [&](int w, T (&ur)[3][3]) {
-    const int dz = w / 3, dy = w % 3;
-    const T* row = sh + dz * nd3 + 3 * (t_ + nx + (dy - 1) * nx);
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ur[dx][c] = row[3 * dx + c];
-  };
-  T ur[2][3][3];
-  read_row(0, ur[0]);
-#pragma unroll
-  for (int w = 0; w < 9; ++w) {
-    if (w + 1 < 9) read_row(w + 1, ur[(w + 1) & 1]);
-    asm volatile("" ::: "memory");
-    const int dz = w / 3, dy = w % 3;
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-        const int bx = dx - ox, by = dy - oy, bz = dz - oz;
-        if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
-        const int b = bx + 2 * by + 4 * bz;
-        const int a = (1 - ox) + 2 * (1 - oy) + 4 * (1 - oz);
-#pragma unroll
-        for (int e = 0; e < 3; ++e)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const int q = (3 * a + c) * 24 + 3 * b + e;
-            const T kk = kQ1.sgn[q] > 0 ? op.kv.v[kQ1.cls[q]] : -op.kv.v[kQ1.cls[q]];
-            t[o][c] = fma(kk, ur[w & 1][dx][e], t[o][c]);
-          }
-      }
-    // the fence consumes the accumulators: this row's arithmetic completes
-    // before the next reads are issued
-    asm volatile(""
-                 : "+v"(t[0][0]), "+v"(t[0][1]), "+v"(t[0][2]), "+v"(t[1][0]), "+v"(t[1][1]),
-                   "+v"(t[1][2]), "+v"(t[2][0]), "+v"(t[2][1]), "+v"(t[2][2]), "+v"(t[3][0]),
-                   "+v"(t[3][1]), "+v"(t[3][2]), "+v"(t[4][0]), "+v"(t[4][1]), "+v"(t[4][2]),
-                   "+v"(t[5][0]), "+v"(t[5][1]), "+v"(t[5][2]), "+v"(t[6][0]), "+v"(t[6][1]),
-                   "+v"(t[6][2]), "+v"(t[7][0]), "+v"(t[7][1]), "+v"(t[7][2])
-                 :
-                 : "memory");
-  }
-  T acc[3] = {T(0), T(0), T(0)};
-#pragma unroll
-  for (int o = 0; o < 8; ++o)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = fma(Ev[o], t[o][c], acc[c]);
-  if constexpr (!kEarly) pv = ep.pre(r, nodec);
-  T ax[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) ax[c] = ((mself >> c) & 1) ? T(0) : acc[c];
-  double a0 = 0.0, a1 = 0.0;
-  if (node < nn) ep.put(r, node, ax, pv, a0, a1);
-  if constexpr (Ep::RED) {
-    block_partial2(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
-                   part + (size_t)(4 + r) * MAX_BLOCKS + bx);
-  }
-}
-
-// Matrix-free trilinear apply, z-marching over element layers, each element
-// product in the element's tensor Haar basis (q1table.h: K0 u = T K_h T^T u,
-// 45 nonzeros in K_h instead of 576 in K0).
-//
-// A block owns ZM_NB consecutive nodes p0 .. p0 + ZM_NB - 1 (plane index
-// i + nx j) of the node planes k0 .. k1 - 1 (at most KZ of them).  The
-// elements that touch those nodes have their lower corner at plane indices
-// p0 - nx - 1 .. p0 + ZM_NB - 1, the block's "columns" c = 0 .. ZM_NB + nx;
-// thread c computes column c.  The block walks the element layers
-// L = k0 - 1 .. k1 - 1 (between node planes L and L + 1):
-//  * every node plane the block needs (k0 - 1 .. k1) and every layer's
-//    moduli are loaded into registers at the start, so the kernel waits for
-//    memory once; each step moves one plane into LDS;
-//  * each column's element reads its top face (4 nodes) from LDS and takes
-//    its 2-D Haar transform; the bottom face's transform is kept from the
-//    previous layer, so every node plane is transformed once per column;
-//  * the z transform, the sparse K_h product, the modulus, the inverse z
-//    transform and the inverse 2-D transform give the element's corner
-//    values, which go to LDS;
-//  * thread c = nx + 1 + m, which owns the element with lower corner at node
-//    p0 + m, finishes that node: its own (0,0) corners and the other three
-//    elements' corners from LDS; the bottom corners complete node plane L
-//    (epilogue and store), the top ones start node plane L + 1.
-// Elements off the mesh (a column past the last element of a row, layers -1
-// and nz - 1) read modulus 0, so their products vanish; node values off the
-// lattice only meet such elements.  Inputs vanish on fixed DOFs; fixed rows
-// return 0.
-constexpr int ZM_NB = 256;  // nodes per block and plane
-constexpr int ZM_KZ = 4;    // node planes per block, at most
-
-// 2-D Haar transform of an element face (nodes c, c + 1, c + nx, c + nx + 1
-// of a staged plane, xyz interleaved): f[comp][q], q = mx + 2 my.
-template <typename T>
-__device__ __forceinline__ void zm_face(const T* pl, int c, int nx, T f[3][4]) {
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const T u00 = pl[3 * c + q], u10 = pl[3 * (c + 1) + q];
-    const T u01 = pl[3 * (c + nx) + q], u11 = pl[3 * (c + nx + 1) + q];
-    const T a = u00 + u10, b = u10 - u00, cc = u01 + u11, d = u11 - u01;
-    f[q][0] = a + cc;
-    f[q][1] = b + d;
-    f[q][2] = cc - a;
-    f[q][3] = d - b;
-  }
-}
-
-// One element: bottom face fb (registers), top face ft, modulus E ->
+// Matrix-free trilinear apply by independent wave tiles (no LDS, no block
+// barrier until the final partial sums).  A wave takes an 8 x 8 tile of
+// element columns, lane (li, lj) = (lane & 7, lane >> 3) the column with
+// lower corner node (WT_OWN tx - 1 + li, WT_OWN ty - 1 + lj), and marches
+// through the element layers of a chunk of node planes:
+//  * each lane loads the top face of its element (4 nodes x 3 components,
+//    one layer ahead) and takes its 2-D Haar transform; the bottom face's
+//    transform is kept from the previous layer;
+//  * the element product in the Haar basis gives its corner values
+//    (haar_element);
+//  * node (i, j) of a face sums the corners of elements (i, j), (i - 1, j),
+//    (i, j - 1), (i - 1, j - 1): a shift by one lane in x (DPP within rows of
+//    16 lanes) and one by eight lanes in y (a lane permute) bring them to the
+//    lane of element (i, j), which owns that node when li, lj >= 1 (7 x 7
+//    nodes per tile);
+//  * a layer's bottom corners finish node plane L (the epilogue stores it),
+//    its top corners start plane L + 1.
+// Elements off the mesh read modulus 0 (their products vanish; node values
+// off the lattice only meet such elements).  Inputs vanish on fixed DOFs;
+// fixed rows return 0.  Any lattice size; the chunk height kz sets the
+// number of waves.
+// One element in its tensor Haar basis (q1table.h: K0 u = T K_h T^T u, 45
+// nonzeros in K_h instead of 576 in K0): bottom face fb and top face ft as
+// 2-D Haar modes f[comp][q], q = mx + 2 my, modulus E ->
 // corner values of the bottom face gb[comp][corner] and top face gt, corner
 // = ax + 2 ay.
 template <typename T>
-__device__ __forceinline__ void zm_element(const Q1HaarVals<T>& hv, const T (&fb)[3][4],
+__device__ __forceinline__ void haar_element(const Q1HaarVals<T>& hv, const T (&fb)[3][4],
                                            const T (&ft)[3][4], T E, T gb[3][4], T gt[3][4]) {
   // mode coefficients c[3 m + comp], m = q + 4 mz (the constant mode m = 0
   // is never used)
@@ -999,48 +700,76 @@ __device__ __forceinline__ void zm_element(const Q1HaarVals<T>& hv, const T (&fb
   }
 }
 
-// Threads per block (one element column each) and staged values per thread
-// and plane, by row length: NT >= ZM_NB + nx + 1, VPT NT >= 3 (ZM_NB + 2 nx + 2).
-template <int NT>
-struct ZmShape {
-  static constexpr int max_nx = NT - ZM_NB - 1;
-  static constexpr int vpt = (3 * (ZM_NB + 2 * max_nx + 2) + NT - 1) / NT;
-};
-inline int zm_threads(const Lat& L) {
-  if (L.nx <= ZmShape<384>::max_nx) return 384;
-  if (L.nx <= ZmShape<512>::max_nx) return 512;
-  return 0;  // rows too long for the z-marching kernel
-}
-inline bool mf_zm_fits(const Lat& L) { return zm_threads(L) != 0; }
+constexpr int WT_OWN = 7;  // owned nodes per tile and direction
+constexpr int WT_WAVES = 4;  // independent waves per block
 
-// Blocks per plane and planes per block: up to ZM_KZ planes per block (the
-// first element layer of a block is recomputed by the block below), fewer
-// when that leaves the 256 CUs without a block each.
-struct ZmGrid {
-  int bpp, kz, nzc;
-  int blocks() const { return bpp * nzc; }
-};
-inline ZmGrid zm_grid(const Lat& L) {
-  ZmGrid g;
-  const long P = (long)L.nx * L.ny;
-  g.bpp = (int)((P + ZM_NB - 1) / ZM_NB);
-#ifndef ZM_TARGET_BLOCKS
-#define ZM_TARGET_BLOCKS 256
+__device__ __forceinline__ int wt_shx32(int v) {  // lane - 1 within rows of 16 (row start: 0)
+  return __builtin_amdgcn_mov_dpp(v, 0x111, 0xf, 0xf, true);
+}
+__device__ __forceinline__ double wt_shx(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = wt_shx32((int)b), hi = wt_shx32((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float wt_shx(float v) {
+  return __builtin_bit_cast(float, wt_shx32(__builtin_bit_cast(int, v)));
+}
+// value of lane - 8 (lanes 0 .. 7: their own); addr = 4 max(lane - 8, 0)
+__device__ __forceinline__ double wt_shy(double v, int addr) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float wt_shy(float v, int addr) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+
+// Resident waves per SIMD the kernel is built for (FP64 / FP32 register
+// budgets: 168 / 128 VGPRs).
+#ifndef WT_WPE64
+#define WT_WPE64 2
 #endif
-  const int chunks = std::max(1, (ZM_TARGET_BLOCKS + g.bpp - 1) / g.bpp);
-  g.kz = std::max(1, std::min(ZM_KZ, (L.nz + chunks - 1) / chunks));
+template <typename T>
+struct WtShape {
+  static constexpr int wpe = sizeof(T) == 8 ? WT_WPE64 : 4;
+};
+struct WtGrid {
+  int ntx, nty, kz, nzc;
+  long waves() const { return (long)ntx * nty * nzc; }
+  int blocks() const { return (int)((waves() + WT_WAVES - 1) / WT_WAVES); }
+};
+// Chunk height: a wave of a chunk of kz planes computes kz + 1 element
+// layers, and the chip holds 1024 wpe waves at once; the height that
+// minimises (rounds of resident waves) x (layers per wave) plus a prologue
+// of about half a layer, within the reduction buffer's block count.
+inline WtGrid wt_grid(const Lat& L, bool fp64) {
+  WtGrid g;
+  g.ntx = (L.nx + WT_OWN - 1) / WT_OWN;
+  g.nty = (L.ny + WT_OWN - 1) / WT_OWN;
+  const long tiles = (long)g.ntx * g.nty;
+  const long slots = 1024L * (fp64 ? WtShape<double>::wpe : WtShape<float>::wpe);
+  double best = 0.0;
+  g.kz = 0;
+  for (int kz = 1; kz <= 32; ++kz) {
+    const long nzc = (L.nz + kz - 1) / kz, waves = tiles * nzc;
+    if ((waves + WT_WAVES - 1) / WT_WAVES > MAX_BLOCKS) continue;
+    const double cost = (double)((waves + slots - 1) / slots) * (kz + 1.5);
+    if (g.kz == 0 || cost < best) {
+      best = cost;
+      g.kz = kz;
+    }
+  }
+  if (g.kz == 0) g.kz = 32;  // (the launch rejects a grid past the buffer)
   g.nzc = (L.nz + g.kz - 1) / g.kz;
   return g;
 }
 
-template <typename T, class Ep, int NT>
-__global__ __launch_bounds__(NT) void k_apply_mf_zm(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs,
-                                                    const CgScalars* gate, int gate_state,
-                                                    double* part, int bpp, int kz) {
-  constexpr int VPT = ZmShape<NT>::vpt;
-  constexpr int KZ = ZM_KZ;
-  __shared__ T pl[2][VPT * NT];           // two node planes (xyz interleaved)
-  __shared__ T cor[2][2][3][3][ZM_NB];    // [buffer][face][corner (1,0) (0,1) (1,1)][comp][node]
+template <typename T, class Ep>
+__global__ __launch_bounds__(64 * WT_WAVES)
+__attribute__((amdgpu_waves_per_eu(WtShape<T>::wpe, WtShape<T>::wpe)))
+void k_apply_mf_wt(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars* gate,
+                   int gate_state, double* part, int ntx, int nty, int kz, int nwaves) {
   int bx, r;
   xcd_tile(bx, r);
   const Gate g = gate_load(gate, nrhs, gate_state);
@@ -1048,165 +777,124 @@ __global__ __launch_bounds__(NT) void k_apply_mf_zm(OpMF<T> op, InPlain<T> in, E
   if constexpr (GateEarly<Ep>::v) {
     if (!gate_open(g, gr)) return;
   }
-  const Lat L = op.L;
-  const int nx = L.nx, ny = L.ny, nz = L.nz, P = nx * ny;
-  const int ex1 = nx - 1, ey1 = ny - 1, ez1 = nz - 1;
-  const int bp = bx % bpp, zc = bx / bpp;
-  const int p0 = bp * ZM_NB, k0 = zc * kz, k1 = min(nz, k0 + kz);
-  const int nsteps = k1 - k0 + 1;            // element layers k0 - 1 .. k1 - 1
-  const int t = threadIdx.x;
-  const int sbase = p0 - nx - 1;             // plane index of staged node / column 0
-  const int ne = ZM_NB + nx + 1;             // columns
-  const __amdgpu_buffer_rsrc_t rx =
-      make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
-  const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
-  // the column's element (index within a layer, or -1 off the mesh)
-  int eb = -1;
-  if (t < ne) {
-    const int e = sbase + t;
-    if (e >= 0 && e < P) {
-      const int j = e / nx, i = e - j * nx;
-      if (i < ex1 && j < ey1) eb = i + ex1 * j;
-    }
-  }
-  const int lstride = ex1 * ey1;
-  // the node this thread finishes (m = t - nx - 1 in 0 .. ZM_NB - 1)
-  const int m = t - nx - 1;
-  const bool node_thr = m >= 0 && m < ZM_NB;
-  const int node = p0 + m;
-  const bool node_on = node_thr && node < P;
-  const int nodec = node_on ? node : 0;
-
-  // every load of the block, issued together in the order of use (loads
-  // complete in issue order, so a wait for one is a wait for those before
-  // it): plane k0 - 1 + q, then the moduli of layer k0 - 1 + q (planes past
-  // k1 or off the lattice, and layers off the mesh, read 0), and the
-  // epilogue operands and supports of the output planes after the planes
-  // their step needs, PD planes ahead: small operand sets for every plane,
-  // larger ones two planes ahead.  Every thread loads the operands from a
-  // valid node (the last plane repeated), so no load sits under a branch: a
-  // loaded value merged at a branch would be waited for there.
-  constexpr int PD = sizeof(typename Ep::Pre) <= 6 * sizeof(double) ? KZ : 2;
-  T stage[KZ + 2][VPT];
-  T Ev[KZ + 1];
-  typename Ep::Pre pvq[KZ];
-  uint8_t mq[KZ];
-  auto load_pre = [&](int j) {
-    const size_t gn = (size_t)min(k0 + j, nz - 1) * P + nodec;
-    pvq[j] = ep.pre(r, (long)gn);
-    mq[j] = op.mask[gn];
-  };
-#pragma unroll
-  for (int q = 0; q < KZ + 2; ++q) {
-    const int k = k0 - 1 + q;
-    const bool on = k >= 0 && k <= k1 && k < nz;
-    const int base = (3 * (k * P + sbase) + t) * (int)sizeof(T);  // may be negative: reads 0
-#pragma unroll
-    for (int v = 0; v < VPT; ++v)
-      stage[q][v] = bload<T>(rx, on ? base + v * NT * (int)sizeof(T) : kBufOOB, 0);
-    if (q < KZ + 1) {
-      const int layer = k0 - 1 + q;
-      const bool eon = eb >= 0 && layer >= 0 && layer < ez1 && q < nsteps;
-      Ev[q] = bload<T>(re, eon ? (eb + lstride * layer) * (int)sizeof(T) : kBufOOB, 0);
-    }
-    // the operands of output plane j are used in step j + 1, after plane
-    // j + 1 is staged
-    if (q >= 2 && q - 2 < PD) load_pre(q - 2);
-    asm volatile("" ::: "memory");  // keeps the issue order of the groups
-  }
-  // unconditional: a buffer holds VPT NT values, of which the first
-  // 3 (ZM_NB + 2 nx + 2) are read (a store under a branch would let the
-  // compiler move its load into that branch, behind a wait for every load
-  // issued before)
-  auto store_plane = [&](int b, const T (&sv)[VPT]) {
-#pragma unroll
-    for (int v = 0; v < VPT; ++v) pl[b][t + v * NT] = sv[v];
-  };
-  // prologue: planes k0 - 1 and k0 staged, the bottom faces of the first layer
-  store_plane(0, stage[0]);
-  store_plane(1, stage[1]);
-  __syncthreads();
-  T fb[3][4];
-  if (t < ne) zm_face(pl[0], t, nx, fb);
-  __syncthreads();  // pl[0] is restaged in step 0
-
-  // Step s computes layer L = k0 - 1 + s (its top plane k0 + s is in
-  // pl[(s + 1) & 1]) and writes its corners to cor[s & 1]; the node phase of
-  // layer L - 1 reads cor[(s - 1) & 1] in the same step, and plane k0 + s + 1
-  // is staged into pl[s & 1] (read by step s - 1): one barrier per step.
-  T acc[3] = {T(0), T(0), T(0)};
-  T ownb[3] = {T(0), T(0), T(0)}, ownt[3] = {T(0), T(0), T(0)};
+  const int lane = threadIdx.x & 63;
+  // wave-uniform tile coordinates (scalar arithmetic)
+  const int wv = bx * WT_WAVES + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   double a0 = 0.0, a1 = 0.0;
-  // node phase of layer k0 - 1 + j: its bottom corners finish plane
-  // k0 - 1 + j (an output for j >= 1), its top ones start k0 + j
-  auto node_phase = [&](int j) {
-    const int cb = j & 1;
-    const bool out = j >= 1;
-    const int jo = j >= 1 ? j - 1 : 0;  // the output plane's slot
-    const uint8_t mself = out ? mq[jo] : 0;
-    T ax[3];
-    if (node_thr) {
+  if (wv < nwaves) {
+    const Lat L = op.L;
+    const int nx = L.nx, ny = L.ny, nz = L.nz, P = nx * ny;
+    const int ex1 = nx - 1, ey1 = ny - 1, ez1 = nz - 1;
+    const int tx = wv % ntx, ty = (wv / ntx) % nty, zc = wv / (ntx * nty);
+    const int li = lane & 7, lj = lane >> 3;
+    const int i = WT_OWN * tx - 1 + li, j = WT_OWN * ty - 1 + lj;
+    const int yaddr = 4 * max(lane - 8, 0);
+    const int k0 = zc * kz, k1 = min(nz, k0 + kz);
+    const int nsteps = k1 - k0 + 1;  // element layers k0 - 1 .. k1 - 1
+    const bool owner = li >= 1 && lj >= 1 && i < nx && j < ny;
+    const int nodec = owner ? i + nx * j : 0;  // plane index of the owned node
+    const __amdgpu_buffer_rsrc_t rx =
+        make_rsrc(in.x + (size_t)r * in.ndof, (size_t)in.ndof * sizeof(T));
+    const __amdgpu_buffer_rsrc_t re = make_rsrc(op.E, (size_t)ex1 * ey1 * ez1 * sizeof(T));
+    const bool eon = i >= 0 && i < ex1 && j >= 0 && j < ey1;
+    // byte offsets of node (i, j) and (i, j + 1) in plane 0 (negative, or
+    // past the end of the vector: the loads read 0)
+    constexpr int SZ = (int)sizeof(T);
+    const int xo0 = 3 * (i + nx * j) * SZ, xo1 = xo0 + 3 * nx * SZ;
+    const int planeb = 3 * P * SZ;
+    const unsigned eo = eon ? (unsigned)((i + ex1 * j) * SZ) : (unsigned)kBufOOB;
+    const int lstrideb = ex1 * ey1 * SZ;
+    // top face of layer L (node plane L + 1).  Planes off the lattice (the
+    // layers below plane 0 and above the last) are replaced by a plane on
+    // it: those layers' elements have modulus 0.
+    auto load_face = [&](int k, T (&v)[12]) {
+      const int ko = min(max(k, 0), nz - 1) * planeb;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const T v = acc[k] + ((ownb[k] + cor[cb][0][0][k][m]) +
-                              (cor[cb][0][1][k][m] + cor[cb][0][2][k][m]));
-        ax[k] = ((mself >> k) & 1) ? T(0) : v;
-        acc[k] = (ownt[k] + cor[cb][1][0][k][m]) + (cor[cb][1][1][k][m] + cor[cb][1][2][k][m]);
+      for (int c = 0; c < 6; ++c) {
+        v[c] = bload<T>(rx, xo0 + ko + c * SZ, 0);
+        v[6 + c] = bload<T>(rx, xo1 + ko + c * SZ, 0);
       }
-    }
-    if (out) {  // j is a compile-time constant here
-      const size_t gnode = (size_t)(k0 + j - 1) * P + nodec;
-      if (node_on) ep.put(r, (long)gnode, ax, pvq[jo], a0, a1);
-      if (jo + PD < KZ) load_pre(jo + PD);
-    }
-  };
+    };
+    auto load_E = [&](int layer) {
+      const bool on = layer >= 0 && layer < ez1;  // uniform
+      // (an element off the mesh: an offset at or past kBufOOB, read as 0)
+      const T e = bload<T>(re, (int)(eo + (unsigned)(min(max(layer, 0), ez1 - 1) * lstrideb)), 0);
+      return on ? e : T(0);
+    };
+    // 2-D Haar transform of a face from its 4 nodes (q = mx + 2 my)
+    auto face = [&](const T (&v)[12], T (&f)[3][4]) {
 #pragma unroll
-  for (int s = 0; s < KZ + 1; ++s) {
-    if (s >= nsteps) break;  // uniform
-    T nb_[3], nt_[3];  // this layer's own (0,0) corners, for its node phase
-    if (t < ne) {
-      T ft[3][4], gb[3][4], gt[3][4];
-      zm_face(pl[(s + 1) & 1], t, nx, ft);
-      zm_element<T>(op.hv, fb, ft, Ev[s], gb, gt);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        nb_[k] = gb[k][0];
-        nt_[k] = gt[k][0];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) fb[k][q] = ft[k][q];
+      for (int c = 0; c < 3; ++c) {
+        const T u00 = v[c], u10 = v[3 + c], u01 = v[6 + c], u11 = v[9 + c];
+        const T a = u00 + u10, b = u10 - u00, cc = u01 + u11, d = u11 - u01;
+        f[c][0] = a + cc;
+        f[c][1] = b + d;
+        f[c][2] = cc - a;
+        f[c][3] = d - b;
       }
-      const int cb = s & 1;
-      const int i10 = t - nx, i01 = t - 1, i11 = t;
+    };
+    // node value of this lane's node from the four elements' corners
+    auto gather = [&](const T (&gc)[3][4], T (&out)[3]) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        if (i10 >= 0 && i10 < ZM_NB) { cor[cb][0][0][k][i10] = gb[k][1]; cor[cb][1][0][k][i10] = gt[k][1]; }
-        if (i01 >= 0 && i01 < ZM_NB) { cor[cb][0][1][k][i01] = gb[k][2]; cor[cb][1][1][k][i01] = gt[k][2]; }
-        if (i11 < ZM_NB) { cor[cb][0][2][k][i11] = gb[k][3]; cor[cb][1][2][k][i11] = gt[k][3]; }
+      for (int c = 0; c < 3; ++c) {
+        const T A = gc[c][0] + wt_shx(gc[c][1]);
+        const T B = gc[c][2] + wt_shx(gc[c][3]);
+        out[c] = A + wt_shy(B, yaddr);
       }
+    };
+    // two top faces in flight (layer k0 - 1 + s has its top plane in slot
+    // s & 1, the next layer's loads are issued before its product) and two
+    // face transforms (bottom and top swap roles every layer)
+    T v[2][12];
+    T Ev[2];
+    T f[2][3][4];
+    {
+      T v0[12];
+      load_face(k0 - 1, v0);
+      load_face(k0, v[0]);
+      Ev[0] = load_E(k0 - 1);
+      face(v0, f[1]);
     }
-    if (s >= 1) {
-      if (s == 2 && !gate_open(g, gr)) return;  // uniform: before the first store
-      node_phase(s - 1);
-    }
+    typename Ep::Pre pv = ep.pre(r, (long)min(k0, nz - 1) * P + nodec);
+    uint8_t mk = op.mask[(size_t)min(k0, nz - 1) * P + nodec];
+    T acc[3] = {T(0), T(0), T(0)};
+    // layer k0 - 1 + s: top face in slot q = s & 1, bottom transform in
+    // f[q ^ 1], its own transform to f[q]
+    auto step = [&](int s, int q) {
+      // (unconditional: past the last layer the clamped plane is read and
+      // never used, so every step issues the same loads)
+      load_face(k0 + s + 1, v[q ^ 1]);
+      Ev[q ^ 1] = load_E(k0 + s);
+      T gb[3][4], gt[3][4];
+      face(v[q], f[q]);
+      haar_element<T>(op.hv, f[q ^ 1], f[q], Ev[q], gb, gt);
+      T bot[3], top[3];
+      gather(gb, bot);
+      gather(gt, top);
+      if (s >= 1) {  // node plane k0 - 1 + s is complete
+        const int kp = k0 - 1 + s;
+        T ax[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      ownb[k] = nb_[k];
-      ownt[k] = nt_[k];
-    }
-    if (s + 2 < KZ + 2) store_plane(s & 1, stage[s + 2]);
-    __syncthreads();
-  }
-  // the last layer's node phase
-  {
-    const int jl = nsteps - 1;
-    if (jl <= 1 && !gate_open(g, gr)) return;  // no store yet (uniform)
+        for (int c = 0; c < 3; ++c) ax[c] = ((mk >> c) & 1) ? T(0) : acc[c] + bot[c];
+        if (owner) ep.put(r, (long)kp * P + nodec, ax, pv, a0, a1);
+        const int kn = min(kp + 1, nz - 1);  // (past the chunk: read, unused)
+        pv = ep.pre(r, (long)kn * P + nodec);
+        mk = op.mask[(size_t)kn * P + nodec];
+      }
 #pragma unroll
-    for (int j = 1; j < KZ + 1; ++j)
-      if (j == jl) node_phase(j);
+      for (int c = 0; c < 3; ++c) acc[c] = top[c];
+    };
+    if (!gate_open(g, gr)) return;  // uniform over the block
+    for (int s = 0; s < nsteps; s += 2) {
+      step(s, 0);
+      if (s + 1 < nsteps) step(s + 1, 1);
+    }
+  } else {
+    if (!gate_open(g, gr)) return;  // uniform over the block
   }
   if constexpr (Ep::RED) {
-    block_partial2_nt<NT>(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
-                          part + (size_t)(4 + r) * MAX_BLOCKS + bx);
+    block_partial2_nt<64 * WT_WAVES>(a0, a1, part + (size_t)r * MAX_BLOCKS + bx,
+                                     part + (size_t)(4 + r) * MAX_BLOCKS + bx);
   }
 }
 
@@ -1291,10 +979,9 @@ void k_apply_st(OpST<T> op, In in, Ep ep, int nrhs,
 }
 
 int apply_blocks(int kind, const Lat& L, bool fp64) {
-  (void)fp64;  // both precisions use the same grids
   const long nn = L.nn();
   if (kind == OP_ST27) return (int)((nn + ST_NODES - 1) / ST_NODES);
-  if (kind == OP_MF_Q1 && mf_zm_fits(L)) return zm_grid(L).blocks();
+  if (kind == OP_MF_Q1) return wt_grid(L, fp64).blocks();
   return nblocks(nn);
 }
 
@@ -1379,23 +1066,11 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
               gate_state, part);
   } else {
     static_assert(std::is_same<Op, OpMF<T>>::value, "operator kind");
-    if (mf_zm_fits(op.L)) {
-      const ZmGrid zg = zm_grid(op.L);
-      const int nb = zg.blocks();
-      if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-      if (zm_threads(op.L) == 384)
-        launch_op_b(k_apply_mf_zm<T, Ep, 384>, dim3(nb, nrhs), dim3(384), st, op, in, ep, nrhs,
-                    gate, gate_state, part, zg.bpp, zg.kz);
-      else
-        launch_op_b(k_apply_mf_zm<T, Ep, 512>, dim3(nb, nrhs), dim3(512), st, op, in, ep, nrhs,
-                    gate, gate_state, part, zg.bpp, zg.kz);
-    } else {
-      // rows of more than 255 nodes: neighbours gathered from global memory
-      const int nb = nblocks(nn);
-      if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
-      launch_op(k_apply<T, Op, In, Ep>, dim3(nb, nrhs), st, op, in, ep, nrhs, gate, gate_state,
-                part);
-    }
+    const WtGrid wg = wt_grid(op.L, sizeof(T) == 8);
+    const int nb = wg.blocks();
+    if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+    launch_op_b(k_apply_mf_wt<T, Ep>, dim3(nb, nrhs), dim3(64 * WT_WAVES), st, op, in, ep, nrhs,
+                gate, gate_state, part, wg.ntx, wg.nty, wg.kz, (int)wg.waves());
   }
 }
 

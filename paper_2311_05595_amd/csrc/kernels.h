@@ -16,24 +16,18 @@ struct Lat {
 };
 
 // Matrix-free trilinear operator: elements (nx-1)(ny-1)(nz-1), modulus E per
-// element, the shared unit element matrix as its 10 coefficient-class values
+// element, the shared unit element matrix in its Haar basis as class values
 // (kept in scalar registers), supports in mask (bit c of a node's byte =
 // component c fixed).  Inputs must vanish on fixed DOFs (every solver vector
-// does); fixed rows return the input (identity).
+// does); fixed rows return 0.
 template <typename T>
 struct OpMF {
   Lat L;
   const T* E;
-  Q1Vals<T> kv;
-  Q1HaarVals<T> hv;  // the same matrix in the element's Haar basis (class values)
+  Q1HaarVals<T> hv;
   const uint8_t* mask;
-  // byte strides between nodes of neighbouring rows / planes of a vector and
-  // between elements of neighbouring rows / planes of E (set by make())
-  int sy, sz, ey, ez;
-  static OpMF make(Lat L, const T* E, Q1Vals<T> kv, Q1HaarVals<T> hv, const uint8_t* mask) {
-    const int sn = 3 * (int)sizeof(T);
-    return OpMF{L, E, kv, hv, mask, L.nx * sn, L.nx * L.ny * sn, (L.nx - 1) * (int)sizeof(T),
-                (L.nx - 1) * (L.ny - 1) * (int)sizeof(T)};
+  static OpMF make(Lat L, const T* E, Q1HaarVals<T> hv, const uint8_t* mask) {
+    return OpMF{L, E, hv, mask};
   }
 };
 

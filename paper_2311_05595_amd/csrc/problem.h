@@ -153,8 +153,6 @@ class Problem {
   double* rho_ = nullptr;
   double* E_ = nullptr;
   float* E32_ = nullptr;
-  Q1Vals<double> kv64_{};   // unit trilinear element (10 class values)
-  Q1Vals<float> kv32_{};
   Q1HaarVals<double> hv64_{};  // the same in the element's Haar basis
   Q1HaarVals<float> hv32_{};
   double* Ksub_ = nullptr;   // [n^3][nd*nd]

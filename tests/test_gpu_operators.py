@@ -5,7 +5,7 @@ blocks and ragged tails."""
 import numpy as np
 import pytest
 
-from helpers import Case, need_gpu, rel
+from helpers import MAT, Case, need_gpu, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -131,17 +131,17 @@ def test_mixed_precision_matrix_free_fine_operator():
     p.close()
 
 
-# Matrix-free trilinear apply on lattices that span several node ranges per
-# plane (ragged last range), several plane chunks, both staging widths of the
-# z-marching kernel (rows up to 127 and up to 255 nodes) and the widest row it
-# takes, plus rows of more than 255 nodes (the gather kernel).
+# Matrix-free trilinear apply (wave tiles of 7 x 7 owned nodes) on lattices
+# with ragged tiles in x and y, many plane chunks, long rows, several load
+# cases and a single element.
 MF_LATTICES = [
-    ("cantilever", (40, 12, 10), 2, 1),   # 41 x 13 nodes per plane: 3 ranges, ragged
-    ("torsion", (24, 20, 30), 2, 3),      # 31 node planes: several chunks, 3 load cases
-    ("cantilever", (40, 12, 100), 3, 1),  # two planes per block, ragged last chunk
+    ("cantilever", (40, 12, 10), 2, 1),   # 41 x 13 nodes per plane: ragged tiles
+    ("torsion", (24, 20, 30), 2, 3),      # 21 = 3 x 7 node rows: whole tiles, 3 load cases
+    ("cantilever", (40, 12, 100), 3, 1),  # 101 node planes
     ("mbb", (130, 4, 6), 2, 2),           # 131-node rows
-    ("cantilever", (254, 2, 4), 2, 1),    # 255-node rows (the widest staged)
-    ("cantilever", (256, 2, 2), 2, 4),    # 257-node rows: gather kernel, 4 load cases
+    ("cantilever", (254, 2, 4), 2, 1),    # 255-node rows
+    ("cantilever", (256, 2, 2), 2, 4),    # 257-node rows, 4 load cases
+    ("cantilever", (6, 6, 6), 1, 1),      # one tile
     ("cantilever", (1, 1, 1), 1, 1),      # one element
 ]
 
@@ -157,6 +157,38 @@ def test_matrix_free_apply_lattices(kind, nel, nlev, nrhs):
         x = _rand(p.ndof, nrhs, 3)
         ref = (c.H.A[0] @ x.T).T
         scale = np.abs(ref).max()
+        assert np.abs(p.apply(0, x) - ref).max() <= 1e-13 * scale
+        if prec == "mixed":
+            assert np.abs(p.apply(0, x, "mixed") - ref).max() <= tol * scale
+        p.close()
+
+
+# Lattices on which the chunk height chosen for the chip's occupancy is
+# more than one plane (FP64 / FP32 chunks: 2 / 1, 3 / 2, 3 with a 2-plane
+# last chunk / 2, 3 with a whole last chunk / 2): odd and even layer counts
+# per wave and ragged last chunks.  Reference: the oracle's element-by-
+# element K u with the supports applied.
+MF_CHUNK_LATTICES = [((64, 32, 64), 5), ((96, 48, 48), 5), ((96, 64, 40), 4), ((80, 40, 80), 4)]
+
+
+@pytest.mark.parametrize("nel,nlev", MF_CHUNK_LATTICES,
+                         ids=["x".join(map(str, n)) for n, _ in MF_CHUNK_LATTICES])
+def test_matrix_free_apply_chunk_heights(nel, nlev):
+    need_gpu()
+    import workloads as W
+    from oracle import assemble, fem
+    from paper_2311_05595_amd import api
+    mask, f = W.make_problem("cantilever", *nel, 1, 2)
+    rho = np.random.default_rng(41).uniform(0.05, 1.0, nel[::-1])
+    x = _rand(mask.size, 2, 43)
+    x[:, mask.astype(bool)] = 0.0
+    ref = assemble.apply(rho, nel, 1, 1, fem.sub_element_matrices(1, 1), x, **MAT)
+    ref[:, mask.astype(bool)] = 0.0
+    scale = np.abs(ref).max()
+    for prec, tol in (("fp64", 1e-13), ("mixed", 5e-6)):
+        print(f"[mf chunks] {nel} {prec}", flush=True)
+        p = api.Problem(nel, mask, f, order=1, nsub=1, nlevels=nlev, precision=prec)
+        p.set_densities(rho.ravel())
         assert np.abs(p.apply(0, x) - ref).max() <= 1e-13 * scale
         if prec == "mixed":
             assert np.abs(p.apply(0, x, "mixed") - ref).max() <= tol * scale

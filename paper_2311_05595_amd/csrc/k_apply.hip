@@ -842,31 +842,28 @@ void k_apply_mf_wt(OpMF<T> op, InPlain<T> in, Ep ep, int nrhs, const CgScalars* 
         out[c] = A + wt_shy(B, yaddr);
       }
     };
-    // two top faces in flight (layer k0 - 1 + s has its top plane in slot
-    // s & 1, the next layer's loads are issued before its product) and two
-    // face transforms (bottom and top swap roles every layer)
-    T v[2][12];
+    // one face in flight: a layer transforms its top face, then loads the
+    // next layer's (used one layer later); two face transforms (bottom and
+    // top swap roles every layer) and two moduli
+    T v[12];
     T Ev[2];
     T f[2][3][4];
-    {
-      T v0[12];
-      load_face(k0 - 1, v0);
-      load_face(k0, v[0]);
-      Ev[0] = load_E(k0 - 1);
-      face(v0, f[1]);
-    }
+    load_face(k0 - 1, v);
+    face(v, f[1]);
+    load_face(k0, v);
+    Ev[0] = load_E(k0 - 1);
     typename Ep::Pre pv = ep.pre(r, (long)min(k0, nz - 1) * P + nodec);
     uint8_t mk = op.mask[(size_t)min(k0, nz - 1) * P + nodec];
     T acc[3] = {T(0), T(0), T(0)};
-    // layer k0 - 1 + s: top face in slot q = s & 1, bottom transform in
-    // f[q ^ 1], its own transform to f[q]
+    // layer k0 - 1 + s (q = s & 1): bottom transform in f[q ^ 1], its top
+    // face's transform to f[q], modulus in Ev[q]
     auto step = [&](int s, int q) {
+      face(v, f[q]);
       // (unconditional: past the last layer the clamped plane is read and
       // never used, so every step issues the same loads)
-      load_face(k0 + s + 1, v[q ^ 1]);
+      load_face(k0 + s + 1, v);
       Ev[q ^ 1] = load_E(k0 + s);
       T gb[3][4], gt[3][4];
-      face(v[q], f[q]);
       haar_element<T>(op.hv, f[q ^ 1], f[q], Ev[q], gb, gt);
       T bot[3], top[3];
       gather(gb, bot);

@@ -22,6 +22,10 @@ Prints one JSON line.  Besides the contract's keys:
 `--copy-probe MIB` only runs the library's plain copy kernel on MIB MiB
 (the calibration run for the HBM byte counters) and exits.
 
+`--apply-sweep` times the matrix-free CG apply of the trilinear cantilever
+on lattices from 96x48x48 to 224x112x112 elements (FP64 and mixed) and
+prints one JSON line with its fraction of the FP64 peak per lattice.
+
 `--projection` times the design-variable projection rho = W x and its
 transpose W^T g (Sec. 3.2 eq. (5), Sec. 3.4) on the 64x32x32 mesh with 4^3
 density and 2^3 design cells per element, rmin = 1.5, and prints its own
@@ -157,6 +161,46 @@ def fine_apply_model(nel, nsub, order, nrhs=1, family="lagrange"):
                        "(FP64)",
                 per_unit="3321 x 8 B of element matrix (distinct entries) per element + 48 B of "
                          "vectors per node and load case")
+
+
+def apply_sweep(args):
+    """The finest-level matrix-free CG apply of the trilinear cantilever on
+    growing lattices (single density per element, seeded uniform densities in
+    [0.1, 1]): 60 PCG iterations per lattice and precision, the apply's mean
+    duration from HIP events on the library's stream, against the FP64 peak.
+    Prints one JSON line; not the default line."""
+    import torch
+    import workloads as W
+    from paper_2311_05595_amd import api
+    rows = []
+    for nel, nl in [((96, 48, 48), 5), ((128, 64, 64), 6), ((160, 80, 80), 5),
+                    ((192, 96, 96), 6), ((224, 112, 112), 5)]:
+        for prec in ("fp64", "mixed"):
+            mask, f = W.make_problem("cantilever", *nel, 1, 1)
+            p = api.Problem(nel, mask, f, order=1, nsub=1, nlevels=nl, precision=prec)
+            p.use_torch_stream()
+            rho = np.random.default_rng(0).uniform(0.1, 1.0, nel[::-1]).ravel()
+            p.set_densities(torch.tensor(rho, dtype=torch.float64, device="cuda"))
+            p.solve(rtol=1e-30, maxit=10, warm_start=False, allow_notconv=True)
+            torch.cuda.synchronize()
+            p.set_kernel_timing(0, True)
+            t0 = time.perf_counter()
+            p.solve(rtol=1e-30, maxit=60, warm_start=False, allow_notconv=True)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ms, n = p.kernel_timing(0)
+            p.set_kernel_timing(0, False)
+            p.close()
+            m = fine_apply_model(nel, 1, 1)
+            avg = ms / n * 1e-3
+            tf = m["flops"] / avg / 1e12
+            rows.append({"nel": list(nel), "precision": prec, "dof": 3 * (nel[0] + 1) * (nel[1] + 1) * (nel[2] + 1),
+                         "apply_us": round(avg * 1e6, 2), "TFLOP_s": round(tf, 2),
+                         "frac": round(tf / PEAK_FP64_TFLOPS, 3), "us_per_iteration": round(el / 60 * 1e6, 1)})
+            print(f"[sweep] {nel} {prec}: {avg * 1e6:.2f} us, frac {tf / PEAK_FP64_TFLOPS:.3f}", flush=True)
+    print(json.dumps({"metric": "finest-level CG apply, matrix-free trilinear, vs lattice size",
+                      "kernel": "finest-level CG apply q = A p (FP64)", "per_unit": "1152 flop per element",
+                      "peak_TFLOP_s": PEAK_FP64_TFLOPS, "rows": rows}), flush=True)
 
 
 def host_info():
@@ -871,6 +915,8 @@ def main():
                     help="time the choice of fixed variables before the degree is raised")
     ap.add_argument("--threshold", action="store_true",
                     help="time the density thresholding and the Heaviside projection")
+    ap.add_argument("--apply-sweep", action="store_true",
+                    help="time the matrix-free CG apply on lattices of 0.7M to 8.6M DOF")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
     ap.add_argument("--session-solves", type=int, default=5, help="c5: solves per session")
     ap.add_argument("--rate", type=float, default=0.0, help="c5: arrivals per second")
@@ -879,6 +925,9 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.apply_sweep:
+        apply_sweep(args)
         return
     if args.fixing:
         if args.gpus != 1:

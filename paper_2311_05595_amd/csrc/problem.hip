@@ -89,6 +89,10 @@ void Problem::plan_levels(const mgcg_desc& d, std::vector<LevelPlan>& lv) {
   }
   if ((long)d.nelx * d.nely * d.nelz * d.nsub * d.nsub * d.nsub * 8 >= kMaxBufferBytes)
     throw Error(MGCG_EINVAL, "mesh too large: the density field would exceed 2 GiB");
+  // the finest level's reducing applies write one partial sum per block
+  if (!lv.empty() && (apply_blocks(lv[0].kind, lv[0].L, true) > MAX_BLOCKS ||
+                      apply_blocks(lv[0].kind, lv[0].L, false) > MAX_BLOCKS))
+    throw Error(MGCG_EINVAL, "mesh too large: the finest level exceeds the reduction buffer's blocks");
 }
 
 // One layout routine serves both the byte count and the pointer assignment.

@@ -25,6 +25,17 @@
   residual, restriction, coarse solve (exact on the coarsest level),
   prolongation and correction, post-smoothing).  This is the preconditioner
   M as a plain linear map, for testing the HIP V-cycle.
+* Smoother on a quadratic finest level (Sec. 7.5 prefers SSOR there): a
+  symmetric Gauss-Seidel in multicolour order.  Nodes of the quadratic
+  lattice are coloured by (i mod 3, j mod 3, k mod 3); two nodes of one
+  colour are at least three lattice steps apart in some axis, while a
+  quadratic element spans two, so they share no element and their rows do
+  not couple.  A forward sweep updates colour 0 .. 26 and, within a colour,
+  component x, y, z (each DOF from the latest values, relaxation 1); the
+  backward sweep runs colours and components in reverse.  Read as one
+  forward sweep before and one backward sweep after the coarse correction,
+  so the V-cycle stays symmetric.  Coarser (trilinear) levels keep the
+  capped Jacobi sweep.
 * ``mgcg``: the conjugate gradient method preconditioned by that V-cycle
   (the paper's solver, Sec. 2.3 and 7.2), stopping on
   ||f - K u|| <= rtol ||f||; used where a direct factorisation is too large.
@@ -40,6 +51,11 @@ coarse correction, so M A is the A-orthogonal projector onto the range of
 the prolongations (idempotent, which fixes the scale of the transfers); with
 one sweep before and after, I - M A is the product of the sweep's and the
 coarse correction's error propagators; mgcg agrees with the direct solve.
+The multicolour Gauss-Seidel sweep equals x + (D + L)^-1 (b - A x) (and
+the backward one the upper-triangle form) with A ordered by gs_order,
+computed by a sparse triangular solve, and its colour classes do not
+couple; the V-cycle with it is symmetric positive definite and its MG-CG
+reaches the direct solve in fewer iterations than with the Jacobi sweep.
 """
 
 import numpy as np
@@ -141,9 +157,47 @@ def smoother_weights(H, omega, theta=THETA):
     return out
 
 
-def vcycle(H, b, level=0, omega=0.6, pre=1, post=1, weights=None):
+def node_colours(dims):
+    """Colour (i mod 3) + 3 (j mod 3) + 9 (k mod 3) of every node of the
+    lattice dims = (nx, ny, nz), x fastest."""
+    nx, ny, nz = dims
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return ((i % 3) + 3 * (j % 3) + 9 * (k % 3)).ravel()
+
+
+def gs_order(dims):
+    """The DOFs in forward sweep order: colour-major, then component, then
+    node index."""
+    col = node_colours(dims)
+    out = []
+    for c in range(27):
+        nodes = np.nonzero(col == c)[0]
+        for comp in range(3):
+            out.append(3 * nodes + comp)
+    return out
+
+
+def gs_sweep(A, b, x, dims, backward=False):
+    """One Gauss-Seidel sweep (relaxation 1) in multicolour order; every
+    group of the order holds DOFs whose rows do not couple, so each group
+    is updated at once from the latest values.  Fixed DOFs are identity
+    rows with b = 0 and stay 0."""
+    A = A.tocsr()
+    d = A.diagonal()
+    x = x.copy()
+    groups = gs_order(dims)
+    if backward:
+        groups = groups[::-1]
+    for idx in groups:
+        x[idx] += (b[idx] - A[idx, :] @ x) / d[idx]
+    return x
+
+
+def vcycle(H, b, level=0, omega=0.6, pre=1, post=1, weights=None, smoother="jacobi"):
     """z = M b: Algorithm 1 recursively, from a zero initial guess, with the
-    capped Jacobi weights (computed once per hierarchy when not given)."""
+    capped Jacobi weights (computed once per hierarchy when not given).
+    smoother="gs": the multicolour Gauss-Seidel sweeps on the finest level
+    (forward before, backward after the coarse correction)."""
     if weights is None:
         weights = getattr(H, "_weights", {}).get(omega)
         if weights is None:
@@ -153,18 +207,19 @@ def vcycle(H, b, level=0, omega=0.6, pre=1, post=1, weights=None):
         return sla.cho_solve(H.coarse_cho, b)
     A = H.A[level]
     wd = weights[level]
+    gs = smoother == "gs" and level == 0
     x = np.zeros_like(b)
     for _ in range(pre):
-        x = jacobi(A, wd, b, x)
+        x = gs_sweep(A, b, x, H.dims[0]) if gs else jacobi(A, wd, b, x)
     r = b - A @ x
     e = vcycle(H, H.P[level].T @ r, level + 1, omega, pre, post, weights)
     x = x + H.P[level] @ e
     for _ in range(post):
-        x = jacobi(A, wd, b, x)
+        x = gs_sweep(A, b, x, H.dims[0], backward=True) if gs else jacobi(A, wd, b, x)
     return x
 
 
-def mgcg(H, f, x0=None, rtol=1e-12, maxit=2000, omega=0.6, pre=1, post=1):
+def mgcg(H, f, x0=None, rtol=1e-12, maxit=2000, omega=0.6, pre=1, post=1, smoother="jacobi"):
     """Preconditioned CG on A_0 x = f with M = vcycle; returns (x, iters,
     final true relative residual)."""
     A = H.A[0]
@@ -175,7 +230,7 @@ def mgcg(H, f, x0=None, rtol=1e-12, maxit=2000, omega=0.6, pre=1, post=1):
     r = f - A @ x
     if np.linalg.norm(r) <= rtol * nf:
         return x, 0, np.linalg.norm(r) / nf
-    z = vcycle(H, r, 0, omega, pre, post)
+    z = vcycle(H, r, 0, omega, pre, post, smoother=smoother)
     p = z.copy()
     rz = r @ z
     it = 0
@@ -190,7 +245,7 @@ def mgcg(H, f, x0=None, rtol=1e-12, maxit=2000, omega=0.6, pre=1, post=1):
             if np.linalg.norm(r_true) <= rtol * nf:
                 break
             r = r_true
-        z = vcycle(H, r, 0, omega, pre, post)
+        z = vcycle(H, r, 0, omega, pre, post, smoother=smoother)
         rz_new = r @ z
         p = z + (rz_new / rz) * p
         rz = rz_new

@@ -179,3 +179,79 @@ def test_two_grid_error_propagation_composes_the_steps():
     lhs = np.eye(n) - Mm @ A
     rhs = S @ (np.eye(n) - C @ A) @ S
     assert np.abs(lhs - rhs).max() < 1e-9
+
+
+def _q2_hierarchy(nel, nsub, nlev, seed=5, family="lagrange"):
+    mask, f = W.make_problem("cantilever", *nel, 2, 1)
+    if family == "serendipity":
+        mask = np.maximum(mask, fem.serendipity_dof_mask(nel))
+    rho = W.gaussian_random_field((nsub * nel[2], nsub * nel[1], nsub * nel[0]), seed, corr=3.0)
+    K = assemble.stiffness(rho, nel, 2, nsub, fem.sub_element_matrices(2, nsub, family=family), **MAT)
+    A0 = assemble.level_operator(K, mask)
+    H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, 2), nlev)
+    b = f[0].copy()
+    b[mask.astype(bool)] = 0.0
+    return H, mask, b
+
+
+@pytest.mark.parametrize("nel,nsub", [((2, 2, 2), 1), ((4, 2, 2), 2), ((3, 2, 3), 1)])
+def test_gs_sweep_is_the_triangular_solve(nel, nsub):
+    """A Gauss-Seidel sweep with relaxation 1 in a given order is
+    x + (D + L)^-1 (b - A x), L the strictly lower triangle of A with rows
+    and columns in that order (the backward sweep: the upper triangle).  The
+    oracle updates a whole colour-component group at once, which equals the
+    sequential sweep only if the group's rows do not couple: an order whose
+    colours repeat every two nodes would fail."""
+    from scipy.sparse.linalg import spsolve_triangular
+    H, mask, _ = _q2_hierarchy(nel, nsub, 1)
+    A = H.A[0].tocsr()
+    n = A.shape[0]
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(n)
+    x = rng.standard_normal(n)
+    b[mask.astype(bool)] = 0.0
+    x[mask.astype(bool)] = 0.0
+    perm = np.concatenate(multigrid.gs_order(H.dims[0]))
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    Ap = A[perm][:, perm].tocsr()
+    r = (b - A @ x)[perm]
+    lower = sp.tril(Ap, format="csr")
+    upper = sp.triu(Ap, format="csr")
+    want_f = x.copy()
+    want_f[perm] += spsolve_triangular(lower, r, lower=True)
+    want_b = x.copy()
+    want_b[perm] += spsolve_triangular(upper, r, lower=False)
+    got_f = multigrid.gs_sweep(A, b, x, H.dims[0])
+    got_b = multigrid.gs_sweep(A, b, x, H.dims[0], backward=True)
+    scale = np.abs(want_f).max()
+    assert np.abs(got_f - want_f).max() <= 1e-11 * scale
+    assert np.abs(got_b - want_b).max() <= 1e-11 * np.abs(want_b).max()
+    # the colour classes of a quadratic lattice do not couple
+    col = multigrid.node_colours(H.dims[0])
+    for c in range(27):
+        nodes = np.flatnonzero(col == c)
+        dofs = (3 * nodes[:, None] + np.arange(3)).ravel()
+        blk = A[dofs][:, dofs].tocoo()
+        assert np.all(blk.row // 3 == blk.col // 3)
+
+
+@pytest.mark.parametrize("family", ["lagrange", "serendipity"])
+def test_gs_vcycle_is_spd_and_beats_jacobi(family):
+    """The V-cycle with the forward sweep before and the backward sweep after
+    the coarse correction is symmetric positive definite (the backward sweep
+    is the forward one's adjoint), and MG-CG with it reaches the direct
+    solve, on a rough field, in fewer iterations than with the capped Jacobi
+    sweep (Sec. 7.5)."""
+    H, mask, b = _q2_hierarchy((4, 2, 2), 2, 2, family=family)
+    Mm = _vcycle_full(H, smoother="gs")
+    assert np.abs(Mm - Mm.T).max() <= 1e-10 * np.abs(Mm).max()
+    free = np.flatnonzero(mask == 0)
+    ev = np.linalg.eigvalsh(0.5 * (Mm + Mm.T)[np.ix_(free, free)])
+    assert ev.min() > 0.0
+    xd = np.zeros_like(b)
+    xd[free] = np.linalg.solve(H.A[0].toarray()[np.ix_(free, free)], b[free])
+    xg, itg, res = multigrid.mgcg(H, b, rtol=1e-10, smoother="gs")
+    _, itj, _ = multigrid.mgcg(H, b, rtol=1e-10)
+    assert res <= 1e-10
+    assert np.linalg.norm(xg - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert itg < itj

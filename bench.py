@@ -315,10 +315,11 @@ def run(args):
     fields = [W.perturb(base, s) for s in seeds]
     dev = torch.device("cuda:0")
     dfields = [torch.tensor(r.ravel(), dtype=torch.float64, device=dev) for r in fields]
+    smoother = args.smoother or cfg.get("smoother", "jacobi")
     prob = api.Problem(cfg["nel"], mask, f, order=cfg["order"], nsub=cfg["nsub"],
                        nlevels=cfg["nlevels"], precision=args.precision or cfg["precision"],
                        omega=cfg["omega"], pre=cfg["pre"], post=cfg["post"],
-                       family=cfg.get("family", "lagrange"))
+                       family=cfg.get("family", "lagrange"), smoother=smoother)
     prob.use_torch_stream()
     dc = torch.empty(prob.nrho, dtype=torch.float64, device=dev)
     free = int((mask == 0).sum()) * prob.nrhs
@@ -378,7 +379,7 @@ def run(args):
         "config": {"workload": cfg["name"] + ", warm-started over 10 seeded +-0.05 density "
                    "perturbations; step = refresh + solve + compliance/sensitivity",
                    "nel": list(cfg["nel"]), "free_dof": free, "levels": cfg["nlevels"],
-                   "rtol": args.rtol},
+                   "rtol": args.rtol, "smoother": smoother},
         "dof_cg_iter_per_s": round(free * sum(iters) / elapsed, 1),
         "pcg_iters_mean": round(float(np.mean(iters)), 2),
         "p50_ms": round(lat_s[len(lat_s) // 2], 3),
@@ -437,7 +438,8 @@ def accuracy_legs(args, cfg, mask, f, base, rho, prob, ref):
         else:
             q = api.Problem(cfg["nel"], mask, f, order=cfg["order"], nsub=cfg["nsub"],
                             nlevels=cfg["nlevels"], precision=leg, omega=cfg["omega"],
-                            pre=cfg["pre"], post=cfg["post"], family=cfg.get("family", "lagrange"))
+                            pre=cfg["pre"], post=cfg["post"], family=cfg.get("family", "lagrange"),
+                            smoother=args.smoother or cfg.get("smoother", "jacobi"))
             q.use_torch_stream()
             q.set_densities(torch.tensor(base.ravel(), dtype=torch.float64, device=dev))
             q.solve(rtol=args.rtol, maxit=args.maxit, warm_start=False)
@@ -900,6 +902,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--smoother", default=None, choices=[None, "jacobi", "gauss-seidel"],
+                    help="finest-level smoother (default: the workload's)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true")

@@ -76,6 +76,17 @@ extern "C" {
  * ignored, their displacements 0). */
 #define MGCG_LAGRANGE 0
 #define MGCG_SERENDIPITY 1
+/* Finest-level smoother (Sec. 7.5 prefers SSOR for quadratic elements):
+ * MGCG_SMOOTH_GAUSS_SEIDEL is a symmetric Gauss-Seidel sweep in multicolour
+ * order on the quadratic node lattice (nodes coloured by their lattice
+ * indices mod 3, so that nodes of one colour share no element; colours
+ * 0..26 and, within a node, components x, y, z), relaxation 1: pre forward
+ * sweeps before and post backward sweeps after the coarse correction, so
+ * the V-cycle stays symmetric.  Coarser levels keep the Jacobi sweep (omega).
+ * It stores each element's 81x81 matrix once more, by node, in the V-cycle
+ * precision (6561 values per element). */
+#define MGCG_SMOOTH_JACOBI 0
+#define MGCG_SMOOTH_GAUSS_SEIDEL 1
 
 #define MGCG_MEM_HOST 0
 #define MGCG_MEM_DEVICE 1
@@ -97,7 +108,9 @@ typedef struct mgcg_desc {
   double E0, Emin, nu, penal; /* solid modulus, void modulus, Poisson ratio, SIMP p */
   double omega;             /* Jacobi weight */
   int32_t family;           /* MGCG_LAGRANGE or MGCG_SERENDIPITY (order 2) */
-  int32_t pad;
+  int32_t smoother;         /* finest-level smoother: MGCG_SMOOTH_JACOBI (0, the
+                               capped weighted Jacobi of every level) or, for
+                               order 2 with nlevels >= 2, MGCG_SMOOTH_GAUSS_SEIDEL */
 } mgcg_desc;
 
 /* Result of one solve. */

@@ -35,7 +35,7 @@ class mgcg_desc(C.Structure):
                 ("nrhs", C.c_int32), ("precision", C.c_int32), ("pre", C.c_int32),
                 ("post", C.c_int32), ("E0", C.c_double), ("Emin", C.c_double),
                 ("nu", C.c_double), ("penal", C.c_double), ("omega", C.c_double),
-                ("family", C.c_int32), ("pad", C.c_int32)]
+                ("family", C.c_int32), ("smoother", C.c_int32)]
 
 
 class mgcg_info(C.Structure):

@@ -81,12 +81,16 @@ def _info(i):
 _FAMILY = {"lagrange": 0, "serendipity": 1}
 
 
+_SMOOTHER = {"jacobi": 0, "gauss-seidel": 1}
+
+
 def make_desc(nel, order=1, nsub=1, nlevels=3, nrhs=1, precision="fp64", E0=1.0, Emin=1e-9,
-              nu=0.3, penal=3.0, omega=0.6, pre=1, post=1, family="lagrange"):
+              nu=0.3, penal=3.0, omega=0.6, pre=1, post=1, family="lagrange", smoother="jacobi"):
     return mgcg_desc(nel[0], nel[1], nel[2], order, nsub, nlevels, nrhs,
                      _PREC[precision] if isinstance(precision, str) else int(precision),
                      pre, post, E0, Emin, nu, penal, omega,
-                     _FAMILY[family] if isinstance(family, str) else int(family), 0)
+                     _FAMILY[family] if isinstance(family, str) else int(family),
+                     _SMOOTHER[smoother] if isinstance(smoother, str) else int(smoother))
 
 
 def device_bytes(**kw):
@@ -98,14 +102,14 @@ class Problem:
 
     def __init__(self, nel, mask, f, order=1, nsub=1, nlevels=3, precision="fp64", E0=1.0,
                  Emin=1e-9, nu=0.3, penal=3.0, omega=0.6, pre=1, post=1, device=0,
-                 family="lagrange"):
+                 family="lagrange", smoother="jacobi"):
         lib = load()
         f = np.atleast_2d(np.ascontiguousarray(f, dtype=np.float64))
         self.nrhs = f.shape[0]
         self.nel = tuple(nel)
         self.order, self.nsub, self.nlevels = order, nsub, nlevels
         self.desc = make_desc(nel, order, nsub, nlevels, self.nrhs, precision, E0, Emin, nu,
-                              penal, omega, pre, post, family)
+                              penal, omega, pre, post, family, smoother)
         self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
         self.f = f
         dims = [order * n + 1 for n in nel]

@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmgcg.so")
-SOURCES = ["element.cpp", "k_apply.hip", "k_setup.hip", "problem.hip", "capi.hip", "server.hip",
-           "proj.hip", "lp.hip", "fix.hip"]
+SOURCES = ["element.cpp", "k_apply.hip", "k_setup.hip", "k_smooth.hip", "problem.hip", "capi.hip",
+           "server.hip", "proj.hip", "lp.hip", "fix.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

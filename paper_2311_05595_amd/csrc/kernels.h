@@ -158,6 +158,19 @@ struct VOps {
 template <typename T>
 void v_prepare0(const double* r, T* b0, const T* wD, T* x0, long ndof, int nrhs,
                 const CgScalars* cs, hipStream_t st);
+// One multicolour Gauss-Seidel sweep (relaxation 1) in place on the
+// quadratic finest level: 27 launches, one per node colour (lattice indices
+// mod 3), colours and a node's components in increasing order, or both
+// reversed (backward).  Kn: element rows by node (setup_rows_by_node).
+template <typename T>
+void v_gauss_seidel(const Lat& L, const T* Kn, const T* Dn, const uint8_t* mask, const T* b, T* x,
+                    bool backward, int nrhs, const CgScalars* cs, hipStream_t st);
+// Kn[((e * 27 + a) * 81 + j) * 3 + c] = Keff[e][3a + c][j] in precision T.
+template <typename T>
+void setup_rows_by_node(const double* Keff, T* Kn, long nel, hipStream_t st);
+// Dn[node * 9 + 3 c + c'] = the node's 3x3 diagonal block, summed over its elements.
+template <typename T>
+void setup_gs_diag(const Lat& L, const T* Kn, T* Dn, hipStream_t st);
 // xo = x + omega invD (b - A x)
 template <typename T>
 void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs,

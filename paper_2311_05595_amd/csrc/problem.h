@@ -112,6 +112,10 @@ class Problem {
                                     bool x0_ready = false);
   void precondition_and_direction(bool x0_ready = false);
   VPrep vprep() const;
+  // the finest level smooths by multicolour Gauss-Seidel
+  bool gs_smoother() const {
+    return d_.smoother == MGCG_SMOOTH_GAUSS_SEIDEL && lv_.size() > 1 && Kn_ != nullptr;
+  }
   template <typename T> VOps<T> vops(int level) const;
   template <typename T> void do_set_densities();
   template <typename T> void do_apply_v(int level, const double* x, double* y);
@@ -163,6 +167,8 @@ class Problem {
   double* Kq2_ = nullptr;    // EQ2: the same by wrapped diagonals (Q2_PACKED per element)
   float* Keff32_ = nullptr;  // EQ2 mixed copy
   double* Yeq_ = nullptr;    // EQ2 element products (FP64 or FP32 view), [nrhs][nel][81]
+  void* Kn_ = nullptr;       // Gauss-Seidel smoother: element rows by node, V-cycle precision
+  void* Dn_ = nullptr;       // and each node's 3x3 diagonal block
   double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr, *rold_ = nullptr;
   CgScalars* cs_ = nullptr;
   RedBuf red_{nullptr};

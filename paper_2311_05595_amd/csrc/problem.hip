@@ -46,6 +46,8 @@ void validate(const mgcg_desc& d) {
   if (d.order == 2 && d.nlevels < 2) bad("quadratic elements need nlevels >= 2");
   if (d.family != MGCG_LAGRANGE && !(d.family == MGCG_SERENDIPITY && d.order == 2))
     bad("family must be Lagrange, or serendipity with order 2");
+  if (d.smoother != MGCG_SMOOTH_JACOBI && !(d.smoother == MGCG_SMOOTH_GAUSS_SEIDEL && d.order == 2))
+    bad("smoother must be Jacobi, or Gauss-Seidel with order 2");
 }
 
 }  // namespace
@@ -137,6 +139,11 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
     TAKE(Kq2_, double, nel0 * Q2_PACKED);       // wrapped diagonals (applies)
     if (mixed) TAKE(Keff32_, float, nel0 * Q2_PACKED);
     TAKE(Yeq_, double, R * nel0 * 81);
+    // the Gauss-Seidel smoother's rows by node, in the V-cycle precision
+    if (d.smoother == MGCG_SMOOTH_GAUSS_SEIDEL) {
+      TAKE(Kn_, char, nel0 * 6561 * (mixed ? sizeof(float) : sizeof(double)));
+      TAKE(Dn_, char, lv[0].L.nn() * 9 * (mixed ? sizeof(float) : sizeof(double)));
+    }
   }
   for (int l = 0; l < L; ++l) {
     const long nn = lv[l].L.nn(), nd = lv[l].L.ndof();
@@ -566,6 +573,10 @@ void Problem::do_set_densities() {
           setup_pack_q2<double>(Keff_, Kq2_, nel0, st);
           if (mixed) setup_pack_q2<float>(Keff_, Keff32_, nel0, st);
         }
+        if (Kn_) {
+          setup_rows_by_node<T>(Keff_, (T*)Kn_, nel0, st);
+          setup_gs_diag<T>(L0, (const T*)Kn_, (T*)Dn_, st);
+        }
       }
       break;
   }
@@ -618,18 +629,31 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
     if (l > 0) bl[l] = (const T*)B_[l].b;
   }
   // level-0 input and its first sweep from zero (the coarse levels get theirs
-  // from the restriction)
-  if (L > 1 && !x0_ready)
+  // from the restriction); the Gauss-Seidel smoother sweeps in place from a
+  // zeroed level-0 iterate
+  const bool gs0 = gs_smoother();
+  if (gs0) {
+    if constexpr (sizeof(T) == 4)
+      convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
+    fill<T>(cur[0], T(0), R * lv_[0].L.ndof(), st);
+  } else if (L > 1 && !x0_ready) {
     v_prepare0<T>(r_in, sizeof(T) == 8 ? nullptr : (T*)B_[0].b, (const T*)B_[0].invD, cur[0],
                   lv_[0].L.ndof(), R, cs, st);
-  else if constexpr (sizeof(T) == 4)
+  } else if constexpr (sizeof(T) == 4) {
     convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
+  }
   for (int l = 0; l < L - 1; ++l) {
     const VOps<T> v = vops<T>(l);
     T* rl = (T*)B_[l].r;
-    for (int s = 1; s < d_.pre; ++s) {
-      v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
-      std::swap(cur[l], oth[l]);
+    if (l == 0 && gs0) {
+      for (int s = 0; s < d_.pre; ++s)
+        v_gauss_seidel<T>(lv_[0].L, (const T*)Kn_, (const T*)Dn_, B_[0].mask, bl[0], cur[0], false, R,
+                          cs, st);
+    } else {
+      for (int s = 1; s < d_.pre; ++s) {
+        v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
+        std::swap(cur[l], oth[l]);
+      }
     }
     if (l == 0) timed_begin(1);
     v_residual<T>(v, bl[l], cur[l], rl, R, cs, st);
@@ -656,6 +680,12 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
     if (!fuse_p)
       v_prolong<T>(lv_[l].L, lv_[l + 1].L, B_[l].mask, B_[l + 1].mask, cur[l + 1], cur[l], R, true,
                    cs, st);
+    if (l == 0 && gs0) {
+      for (int s = 0; s < d_.post; ++s)
+        v_gauss_seidel<T>(lv_[0].L, (const T*)Kn_, (const T*)Dn_, B_[0].mask, bl[0], cur[0], true, R,
+                          cs, st);
+      continue;
+    }
     for (int s = 0; s < d_.post; ++s) {
       if (l == 0) timed_begin(2);
       if (s == 0 && fuse_p)
@@ -676,8 +706,9 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
 // sweep on a multilevel hierarchy the r.z products come fused out of the last
 // finest-level sweep; otherwise a separate dot kernel computes them.
 VPrep Problem::vprep() const {
-  // the residual producers write the V-cycle's level-0 input (multilevel only)
-  if (lv_.size() < 2) return VPrep{nullptr, nullptr, nullptr, 0};
+  // the residual producers write the V-cycle's level-0 input (multilevel
+  // only; the Gauss-Seidel smoother starts from zero itself)
+  if (lv_.size() < 2 || gs_smoother()) return VPrep{nullptr, nullptr, nullptr, 0};
   return VPrep{B_[0].invD, B_[0].xa, vbytes_ == 4 ? B_[0].b : nullptr, vbytes_ == 4 ? 1 : 0};
 }
 
@@ -685,7 +716,7 @@ void Problem::precondition_and_direction(bool x0_ready) {
   hipStream_t st = stream_;
   const long nd = lv_[0].L.ndof();
   const int R = d_.nrhs;
-  const bool fuse = d_.post >= 1 && lv_.size() > 1;
+  const bool fuse = d_.post >= 1 && lv_.size() > 1 && !gs_smoother();
   const int nbz = fuse ? nblocks_fine(vbytes_ == 8) : cg_beta_blocks(nd);
   if (vbytes_ == 8) {
     vcycle<double>(r_, 1, fuse, x0_ready);

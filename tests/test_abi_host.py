@@ -53,6 +53,11 @@ def test_desc_validation_and_sizes():
     b2 = api.device_bytes(nel=(32, 16, 16), nlevels=3, nrhs=2)
     assert b2 > b64
     assert api.device_bytes(nel=(32, 16, 16), nlevels=3, nsub=2) > b64
+    # the Gauss-Seidel smoother needs quadratic elements
+    assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2, smoother="gauss-seidel") > \
+        api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2)
+    assert api.device_bytes(nel=(4, 2, 2), order=1, nlevels=2, smoother="gauss-seidel") == 0
+    assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2, smoother=2) == 0
     # a stencil finest level past the reduction buffer's 16,384 blocks of 64
     # nodes (161 x 81 x 81 nodes) is rejected up front, one within it is not
     assert api.device_bytes(nel=(160, 80, 80), nlevels=5, nsub=2) == 0

@@ -92,6 +92,7 @@ extern "C" {
 #define MGCG_MEM_DEVICE 1
 
 typedef struct mgcg_problem mgcg_problem;
+typedef struct mgcg_ctx mgcg_ctx;
 typedef struct mgcg_server mgcg_server;
 
 /* Problem description.  Elements are unit cubes. */
@@ -132,6 +133,23 @@ int mgcg_version(void);
  * mgcg_problem_create + first use allocates).  0 on invalid desc. */
 size_t mgcg_problem_device_bytes(const mgcg_desc* desc);
 
+/* A context: a device and an HBM budget shared by the problems created in it
+ * (mgcg_problem_create_in).  A problem's device memory (exactly
+ * mgcg_problem_device_bytes of its desc) is charged when it is allocated (at
+ * its first mgcg_set_densities / solve / allocate, or by a server's
+ * admission) and refunded when it is destroyed; an allocation the budget
+ * cannot hold fails with MGCG_EBUDGET and allocates nothing.  hbm_budget_bytes
+ * = 0: no limit.  The context owns nothing but the accounting; destroying it
+ * while any of its problems lives is MGCG_EINVAL.  Thread-safe. */
+int mgcg_ctx_create(mgcg_ctx** out, int device, size_t hbm_budget_bytes);
+int mgcg_ctx_destroy(mgcg_ctx* ctx);
+/* Bytes charged now, the budget, and the number of live problems (any
+ * output may be null). */
+int mgcg_ctx_usage(mgcg_ctx* ctx, size_t* in_use, size_t* budget, int32_t* problems);
+/* mgcg_problem_create on the context's device, charged to its budget. */
+int mgcg_problem_create_in(mgcg_ctx* ctx, const mgcg_desc* desc, const uint8_t* fixed_mask,
+                           const double* f, mgcg_problem** out);
+
 /* Validate desc and copy the supports and loads (host arrays):
  *   fixed_mask  uint8[ndof]       nonzero = DOF fixed (Sec. 6.1);
  *   f           double[nrhs*ndof] nodal loads (entries on fixed DOFs ignored).
@@ -171,6 +189,11 @@ int mgcg_problem_allocate(mgcg_problem* p);
  * NaN or outside [0, 1] (detected on the device; the previous operator is
  * then invalid and must be refreshed before the next solve). */
 int mgcg_set_densities(mgcg_problem* p, const double* rho, int mem);
+
+/* The same from FP32 densities (host or device, [n_rho]), converted to FP64
+ * on their way in (Sec. 2 eq. (1) is then evaluated in FP64 as above).
+ * MGCG_EINVAL for null arguments; otherwise as mgcg_set_densities. */
+int mgcg_set_densities_f32(mgcg_problem* p, const float* rho, int mem);
 
 /* Solve K u = f for every load case to ||f - K u|| <= rtol ||f|| (true FP64
  * residual), at most maxit PCG iterations.  Initial guess (warm_start):

@@ -86,6 +86,13 @@ EXPORTS = {
     "mgcg_set_launch_mode": (C.c_int, [C.c_void_p, C.c_int]),
     "mgcg_problem_allocate": (C.c_int, [C.c_void_p]),
     "mgcg_set_densities": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "mgcg_set_densities_f32": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "mgcg_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_size_t]),
+    "mgcg_ctx_destroy": (C.c_int, [C.c_void_p]),
+    "mgcg_ctx_usage": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                 C.POINTER(C.c_int32)]),
+    "mgcg_problem_create_in": (C.c_int, [C.c_void_p, C.POINTER(mgcg_desc), C.c_void_p,
+                                         C.c_void_p, C.POINTER(C.c_void_p)]),
     "mgcg_solve": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.POINTER(mgcg_info)]),
     "mgcg_get_displacement": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mgcg_set_initial_guess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),

@@ -30,12 +30,19 @@ def _is_device_tensor(a):
     return isinstance(a, torch.Tensor) and a.is_cuda
 
 
+def _is_float32(a):
+    if _is_device_tensor(a):
+        return a.dtype == _torch().float32
+    return getattr(a, "dtype", None) == np.float32
+
+
 def _ptr(a, dtype=np.float64):
     """(pointer, mem flag, keep-alive) for a numpy array or a device tensor."""
     if _is_device_tensor(a):
         torch = _torch()
-        if a.dtype != torch.float64 or not a.is_contiguous():
-            raise TypeError("device tensors must be contiguous float64")
+        want = torch.float32 if dtype == np.float32 else torch.float64
+        if a.dtype != want or not a.is_contiguous():
+            raise TypeError(f"device tensors must be contiguous {want}")
         return C.c_void_p(a.data_ptr()), MGCG_MEM_DEVICE, a
     arr = np.ascontiguousarray(a, dtype=dtype)
     return C.c_void_p(arr.ctypes.data), MGCG_MEM_HOST, arr
@@ -97,12 +104,34 @@ def device_bytes(**kw):
     return load().mgcg_problem_device_bytes(C.byref(make_desc(**kw)))
 
 
+class Context:
+    """A device and an HBM budget (bytes; 0: none) shared by the problems
+    created with ctx=this context (mgcg_ctx_* in include/mgcg.h)."""
+
+    def __init__(self, device=0, budget=0):
+        self._lib = load()
+        h = C.c_void_p()
+        check(self._lib.mgcg_ctx_create(C.byref(h), device, budget))
+        self._h = h
+
+    def usage(self):
+        """(bytes charged, budget, live problems)."""
+        a, b, n = C.c_size_t(), C.c_size_t(), C.c_int32()
+        check(self._lib.mgcg_ctx_usage(self._h, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            check(self._lib.mgcg_ctx_destroy(self._h))
+            self._h = None
+
+
 class Problem:
     """One equilibrium problem K(rho) u = f (all load cases) on one GPU."""
 
     def __init__(self, nel, mask, f, order=1, nsub=1, nlevels=3, precision="fp64", E0=1.0,
                  Emin=1e-9, nu=0.3, penal=3.0, omega=0.6, pre=1, post=1, device=0,
-                 family="lagrange", smoother="jacobi"):
+                 family="lagrange", smoother="jacobi", ctx=None):
         lib = load()
         f = np.atleast_2d(np.ascontiguousarray(f, dtype=np.float64))
         self.nrhs = f.shape[0]
@@ -118,8 +147,13 @@ class Problem:
         if self.mask.size != self.ndof or f.shape[1] != self.ndof:
             raise ValueError("mask/f size does not match the mesh")
         h = C.c_void_p()
-        check(lib.mgcg_problem_create(C.byref(self.desc), C.c_void_p(self.mask.ctypes.data),
-                                      C.c_void_p(f.ctypes.data), device, C.byref(h)))
+        if ctx is None:
+            check(lib.mgcg_problem_create(C.byref(self.desc), C.c_void_p(self.mask.ctypes.data),
+                                          C.c_void_p(f.ctypes.data), device, C.byref(h)))
+        else:
+            check(lib.mgcg_problem_create_in(ctx._h, C.byref(self.desc),
+                                             C.c_void_p(self.mask.ctypes.data),
+                                             C.c_void_p(f.ctypes.data), C.byref(h)))
         self._h = h
         self._lib = lib
 
@@ -164,11 +198,17 @@ class Problem:
         return s.value or 0
 
     def set_densities(self, rho):
-        p, mem, keep = _ptr(rho)
+        """rho: [n_rho] float64, or float32 (converted to FP64 by the
+        library), as a numpy array or a contiguous device tensor."""
+        f32 = _is_float32(rho)
+        p, mem, keep = _ptr(rho, np.float32 if f32 else np.float64)
         _order_after_torch(mem, self.stream() if mem == MGCG_MEM_DEVICE else 0)
         if (keep.numel() if mem == MGCG_MEM_DEVICE else keep.size) != self.nrho:
             raise ValueError("density count does not match the mesh")
-        check(self._lib.mgcg_set_densities(self._h, p, mem))
+        if f32:
+            check(self._lib.mgcg_set_densities_f32(self._h, p, mem))
+        else:
+            check(self._lib.mgcg_set_densities(self._h, p, mem))
 
     def solve(self, rtol=1e-8, maxit=1000, warm_start=True, allow_notconv=False):
         info = mgcg_info()

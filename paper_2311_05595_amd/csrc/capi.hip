@@ -2,6 +2,7 @@
 // the thread-local error message.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "problem.h"
@@ -45,6 +46,9 @@ using mgcg::Problem;
 struct mgcg_problem {
   Problem* impl;
 };
+struct mgcg_ctx {
+  mgcg::Budget b;
+};
 
 extern "C" {
 
@@ -79,6 +83,76 @@ int mgcg_problem_create(const mgcg_desc* d, const uint8_t* mask, const double* f
       throw;
     }
     *out = p;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_ctx_create(mgcg_ctx** out, int device, size_t hbm_budget_bytes) {
+  NEED(out);
+  GUARD({
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    if (device < 0 || (ndev > 0 && device >= ndev)) throw Error(MGCG_EINVAL, "bad device index");
+    auto* c = new mgcg_ctx;
+    c->b.device = device;
+    c->b.budget = hbm_budget_bytes;
+    *out = c;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_ctx_destroy(mgcg_ctx* c) {
+  if (!c) return MGCG_OK;
+  GUARD({
+    int n;
+    {
+      std::lock_guard<std::mutex> g(c->b.m);
+      n = c->b.problems;
+    }
+    if (n > 0) throw Error(MGCG_EINVAL, "problems of this context are still alive");
+    delete c;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_ctx_usage(mgcg_ctx* c, size_t* in_use, size_t* budget, int32_t* problems) {
+  NEED(c);
+  GUARD({
+    std::lock_guard<std::mutex> g(c->b.m);
+    if (in_use) *in_use = c->b.in_use;
+    if (budget) *budget = c->b.budget;
+    if (problems) *problems = c->b.problems;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_problem_create_in(mgcg_ctx* c, const mgcg_desc* d, const uint8_t* mask, const double* f,
+                           mgcg_problem** out) {
+  NEED(c);
+  NEED(d);
+  NEED(mask);
+  NEED(f);
+  NEED(out);
+  GUARD({
+    auto* p = new mgcg_problem{nullptr};
+    try {
+      p->impl = new Problem(*d, mask, f, c->b.device);
+      p->impl->attach_budget(&c->b);
+    } catch (...) {
+      delete p->impl;
+      delete p;
+      throw;
+    }
+    *out = p;
+    return MGCG_OK;
+  })
+}
+
+int mgcg_set_densities_f32(mgcg_problem* p, const float* rho, int mem) {
+  NEED(p);
+  NEED(rho);
+  GUARD({
+    p->impl->set_densities_f32(rho, mem);
     return MGCG_OK;
   })
 }

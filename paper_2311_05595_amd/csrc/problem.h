@@ -3,6 +3,7 @@
 
 #include <chrono>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mgcg.h"
@@ -43,6 +44,30 @@ struct KernelTimer {
   long long launches = 0;
 };
 
+// The HBM budget of a context (mgcg_ctx): the device bytes its problems hold
+// may not exceed it (0: no limit).  Thread-safe.
+struct Budget {
+  std::mutex m;
+  int device = 0;
+  size_t budget = 0;
+  size_t in_use = 0;
+  int problems = 0;
+  bool charge(size_t b) {
+    std::lock_guard<std::mutex> g(m);
+    if (budget && in_use + b > budget) return false;
+    in_use += b;
+    return true;
+  }
+  void refund(size_t b) {
+    std::lock_guard<std::mutex> g(m);
+    in_use -= b;
+  }
+  void attach(int d) {
+    std::lock_guard<std::mutex> g(m);
+    problems += d;
+  }
+};
+
 class Problem {
  public:
   Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int device);
@@ -63,7 +88,12 @@ class Problem {
   hipStream_t ensure_stream();
   int device() const { return device_; }
 
+  // charge this problem's device memory to a context's budget (before the
+  // first allocation; the problem counts as attached until destroyed)
+  void attach_budget(Budget* b);
   void set_densities(const double* rho, int mem);
+  // the same from FP32 densities (converted to FP64 on the way in)
+  void set_densities_f32(const float* rho, int mem);
   // Enqueue the refresh without waiting; the density check happens when the
   // next solve finishes.
   void set_densities_async(const double* rho, int mem);
@@ -167,6 +197,7 @@ class Problem {
   double* Kq2_ = nullptr;    // EQ2: the same by wrapped diagonals (Q2_PACKED per element)
   float* Keff32_ = nullptr;  // EQ2 mixed copy
   double* Yeq_ = nullptr;    // EQ2 element products (FP64 or FP32 view), [nrhs][nel][81]
+  Budget* budget_ = nullptr;  // context budget this problem is charged to, or null
   void* Kn_ = nullptr;       // Gauss-Seidel smoother: element rows by node, V-cycle precision
   void* Dn_ = nullptr;       // and each node's 3x3 diagonal block
   double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr, *rold_ = nullptr;

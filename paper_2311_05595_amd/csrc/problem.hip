@@ -303,6 +303,14 @@ Problem::~Problem() {
     release();
   } catch (...) {
   }
+  if (budget_) budget_->attach(-1);
+}
+
+void Problem::attach_budget(Budget* b) {
+  if (arena_) throw Error(MGCG_EINVAL, "the problem already holds device memory");
+  if (budget_) budget_->attach(-1);
+  budget_ = b;
+  if (b) b->attach(1);
 }
 
 void Problem::release() {
@@ -323,6 +331,7 @@ void Problem::release() {
   hcs_ = nullptr;
   hipFree(arena_);
   arena_ = nullptr;
+  if (budget_) budget_->refund(bytes_);
   if (own_stream_) {
     if (stream_ == own_stream_) stream_ = nullptr;
     hipStreamDestroy(own_stream_);
@@ -350,9 +359,13 @@ void Problem::allocate() {
   if (arena_) return;
   ensure_stream();
   bytes_ = layout(d_, lv_, nullptr, nullptr);
+  if (budget_ && !budget_->charge(bytes_))
+    throw Error(MGCG_EBUDGET, "the context's HBM budget cannot hold " + std::to_string(bytes_) +
+                                  " more bytes");
   char* base = nullptr;
   if (hipMalloc(&base, bytes_) != hipSuccess) {
     (void)hipGetLastError();
+    if (budget_) budget_->refund(bytes_);
     throw Error(MGCG_ENOMEM, "device allocation of " + std::to_string(bytes_) + " bytes failed");
   }
   arena_ = base;
@@ -521,14 +534,28 @@ void Problem::set_densities(const double* rho, int mem) {
   check_bad(0);
 }
 
+void Problem::set_densities_f32(const float* rho, int mem) {
+  allocate();
+  MGCG_HIP(hipSetDevice(device_));
+  const long n = nrho();
+  if (mem == MGCG_MEM_HOST) {
+    const std::vector<double> h(rho, rho + n);
+    set_densities(h.data(), MGCG_MEM_HOST);
+    return;
+  }
+  convert<float, double>(rho, rho_, n, stream_);
+  set_densities(nullptr, MGCG_MEM_DEVICE);  // rho_ holds them already
+}
+
 void Problem::set_densities_async(const double* rho, int mem) {
   allocate();
   MGCG_HIP(hipSetDevice(device_));
   const long n = nrho();
   MGCG_HIP(hipEventRecord(ev_s0_, stream_));
-  MGCG_HIP(hipMemcpyAsync(rho_, rho, n * sizeof(double),
-                          mem == MGCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                          stream_));
+  if (rho)
+    MGCG_HIP(hipMemcpyAsync(rho_, rho, n * sizeof(double),
+                            mem == MGCG_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            stream_));
   fill<int>(bad_, 0, 4, stream_);
   if (vbytes_ == 8)
     do_set_densities<double>();

@@ -22,7 +22,7 @@ def _lib():
 
 def _header_symbols():
     src = open(os.path.join(ROOT, "include", "mgcg.h")).read()
-    return sorted(set(re.findall(r"\b(mgcg_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mgcg_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol():
@@ -208,3 +208,27 @@ def test_new_entry_points_reject_bad_arguments_before_any_device_work():
                                   7) == EINVAL   # bad memory flag
     assert lib.mgcg_fix_variables(C.byref(good), null, p(rho), p(buf), p(buf), p(buf), None,
                                   abi.MGCG_MEM_HOST) == EINVAL
+
+
+def test_context_accounting_without_a_device():
+    """A context starts empty; a problem created in it counts as attached
+    (no device memory until first use), and the context refuses to go while
+    the problem lives."""
+    import numpy as np
+    import workloads as W
+    from paper_2311_05595_amd import api
+    lib, abi = _lib()
+    ctx = api.Context(device=0, budget=1 << 20)
+    assert ctx.usage() == (0, 1 << 20, 0)
+    mask, f = W.make_problem("cantilever", 4, 2, 2, 1, 1)
+    p = api.Problem((4, 2, 2), mask, f, nlevels=2, ctx=ctx)
+    assert ctx.usage() == (0, 1 << 20, 1)
+    assert lib.mgcg_ctx_destroy(ctx._h) == abi.MGCG_EINVAL
+    p.close()
+    assert ctx.usage() == (0, 1 << 20, 0)
+    ctx.close()
+    # null arguments
+    assert lib.mgcg_problem_create_in(None, None, None, None, None) == abi.MGCG_EINVAL
+    assert lib.mgcg_set_densities_f32(None, None, 0) == abi.MGCG_EINVAL
+    assert lib.mgcg_ctx_usage(None, None, None, None) == abi.MGCG_EINVAL
+    del np

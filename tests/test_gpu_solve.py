@@ -197,3 +197,27 @@ def test_scaled_warm_start():
     i0 = p.solve(rtol=1e-10, maxit=3000, warm_start="scaled")
     assert i0["status"] == 0 and rel(p.displacement()[0], ud[0]) <= U_TOL
     p.close()
+
+
+@pytest.mark.parametrize("field,order,nsub", [("void", 1, 1), ("binary", 1, 2), ("binary", 2, 1)])
+def test_densities_at_their_bounds(field, order, nsub):
+    """Densities exactly 0 and 1: an all-void body (every modulus E_min, the
+    operator 1e-9 of the solid one) and a random 0/1 design; u and c against
+    the oracle's direct solve."""
+    need_gpu()
+    c = Case("cantilever", (6, 4, 4), order, nsub, 2, 1, seed=71)
+    if field == "void":
+        c.rho = np.zeros_like(c.rho)
+    else:
+        c.rho = (np.random.default_rng(72).uniform(size=c.rho.shape) < 0.5).astype(np.float64)
+    p = c.problem()
+    p.set_densities(c.rho)
+    info = p.solve(rtol=1e-10, maxit=3000, warm_start=False)
+    assert info["status"] == 0
+    u = p.displacement()
+    cc, _ = p.compliance_sensitivity(want_dc=False)
+    p.close()
+    ud = c.direct()
+    assert rel(u[0], ud[0]) <= U_TOL
+    cref = c.compliance(ud)
+    assert abs(cc[0] - cref[0]) <= C_TOL * abs(cref[0])

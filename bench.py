@@ -238,7 +238,7 @@ def oracle_reference(cfg, rho, rtol_ref=1e-12, max_iters=400, budget_s=60.0):
         Ks = fem.sub_element_matrices(order, nsub, family=family)
         K = assemble.stiffness(rho, nel, order, nsub, Ks)
         A0 = assemble.level_operator(K, mask)
-        H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, order), cfg["nlevels"])
+        H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, order), cfg["nlevels"], order0=order)
         weights = multigrid.smoother_weights(H, cfg["omega"])
         t_setup = time.perf_counter() - t0
         us, it8, its, res = [], None, 0, 0.0

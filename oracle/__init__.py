@@ -8,7 +8,8 @@ gradient here is computed afresh from the paper's formulas.
 
 What it computes (the plain definitions, in FP64):
 
-* ``fem``      element stiffness of Lagrange hexahedra by Gauss quadrature,
+* ``fem``      element stiffness of Lagrange (degree 1-3) and serendipity
+               (degree 2-3) hexahedra by Gauss quadrature (Sec. 2.1),
                including the sub-element matrices of the multiresolution
                element (Sec. 3.3, unnumbered split of the integral, and
                eq. (7));

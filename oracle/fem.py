@@ -26,9 +26,20 @@ K^(e_i) per density sub-element, each computed once for a regular mesh).
   layout of the 27-node element with zero rows and columns at the 6 face
   centres and the body centre, which a problem then fixes; 3 Gauss points
   per axis integrate them exactly.
+* Cubic serendipity element (32 nodes, Sec. 2.1): the vertices and the two
+  third-points of every edge of the 64-node layout (local coordinates -1,
+  -1/3, 1/3, 1 per axis), with the textbook shape functions (vertex:
+  (1 + xi xi_a)(1 + eta eta_a)(1 + zeta zeta_a)(9 (xi^2 + eta^2 + zeta^2)
+  - 19) / 64; edge node with |xi_a| = 1/3: 9 (1 - xi^2)(1 + 9 xi xi_a)(1 +
+  eta eta_a)(1 + zeta zeta_a) / 64, and likewise).  Its matrices keep the
+  192-DOF layout of the 64-node element with zero rows and columns at the 24
+  face-interior and 8 body-interior nodes; the shape functions have degree
+  3 per axis, so 4 Gauss points per axis integrate the products of their
+  gradients exactly.
 
-Pins (tests/test_oracle_fem.py): symmetry; rank 3*n_e - 6 (Table 1: 18, 75,
-186); six rigid-body modes in the null space; the hand-derived diagonal
+Pins (tests/test_oracle_fem.py, tests/test_oracle_serendipity.py): symmetry;
+rank 3*n_e - 6 (Table 1: 18, 75, 186; the same rule gives 54 and 90 for
+the serendipity elements); six rigid-body modes in the null space; the hand-derived diagonal
 (D11 + 2G)/9 of the unit Q1 cube; the strain energy of a uniform strain field
 equals (volume) * eps^T D eps (closed form per strain state); sum of the
 sub-element matrices equals the single-element matrix; each sub-matrix
@@ -84,19 +95,21 @@ def elasticity_matrix(E=1.0, nu=0.3):
     return D
 
 
-def serendipity_node(a):
-    """True for the 20 nodes (vertices, edge midpoints) of the 27-node layout."""
-    ax, ay, az = a % 3, (a // 3) % 3, a // 9
-    return (ax == 1) + (ay == 1) + (az == 1) <= 1
+def serendipity_node(a, order=2):
+    """True for the nodes of the serendipity element of the given degree (2:
+    20 nodes, 3: 32 nodes) in the (order+1)^3 Lagrange layout: the vertices
+    and the edge nodes, i.e. at most one local index strictly inside the
+    element's edge."""
+    p1 = order + 1
+    idx = (a % p1, (a // p1) % p1, a // (p1 * p1))
+    return sum(0 < t < order for t in idx) <= 1
 
 
-def serendipity_shapes(xi, eta, zeta):
-    """Values [27] and local gradients [27, 3] of the 20-node serendipity
-    shape functions in the 27-node layout (zero at the 7 other nodes)."""
+def _serendipity2(xi, eta, zeta):
     N = np.zeros(27)
     G = np.zeros((27, 3))
     for a in range(27):
-        if not serendipity_node(a):
+        if not serendipity_node(a, 2):
             continue
         c = (a % 3 - 1, (a // 3) % 3 - 1, a // 9 - 1)
         t = (xi, eta, zeta)
@@ -118,16 +131,56 @@ def serendipity_shapes(xi, eta, zeta):
     return N, G
 
 
+def _serendipity3(xi, eta, zeta):
+    N = np.zeros(64)
+    G = np.zeros((64, 3))
+    t = (xi, eta, zeta)
+    for a in range(64):
+        if not serendipity_node(a, 3):
+            continue
+        c = [-1.0 + 2.0 * q / 3.0 for q in (a % 4, (a // 4) % 4, a // 16)]
+        inner = [d for d in range(3) if abs(c[d]) < 1.0]
+        if not inner:
+            f = [1.0 + t[d] * c[d] for d in range(3)]
+            s = 9.0 * (t[0] ** 2 + t[1] ** 2 + t[2] ** 2) - 19.0
+            N[a] = f[0] * f[1] * f[2] * s / 64.0
+            for d in range(3):
+                o = [f[e] for e in range(3) if e != d]
+                G[a, d] = o[0] * o[1] * (c[d] * s + f[d] * 18.0 * t[d]) / 64.0
+        else:
+            m = inner[0]                                  # the axis of the edge
+            f = [(1.0 - t[d] ** 2) * (1.0 + 9.0 * c[d] * t[d]) if d == m
+                 else 1.0 + t[d] * c[d] for d in range(3)]
+            df = [-2.0 * t[d] * (1.0 + 9.0 * c[d] * t[d]) + 9.0 * c[d] * (1.0 - t[d] ** 2)
+                  if d == m else c[d] for d in range(3)]
+            N[a] = 9.0 * f[0] * f[1] * f[2] / 64.0
+            G[a, 0] = 9.0 * df[0] * f[1] * f[2] / 64.0
+            G[a, 1] = 9.0 * f[0] * df[1] * f[2] / 64.0
+            G[a, 2] = 9.0 * f[0] * f[1] * df[2] / 64.0
+    return N, G
+
+
+def serendipity_shapes(xi, eta, zeta, order=2):
+    """Values [(p+1)^3] and local gradients [(p+1)^3, 3] of the serendipity
+    shape functions of degree p = order (2: 20 nodes, 3: 32 nodes) in the
+    Lagrange layout of the same degree (zero at the nodes the element does
+    not have)."""
+    if order == 2:
+        return _serendipity2(xi, eta, zeta)
+    if order == 3:
+        return _serendipity3(xi, eta, zeta)
+    raise ValueError("serendipity elements here have degree 2 or 3")
+
+
 def strain_displacement(order, xi, eta, zeta, half=(0.5, 0.5, 0.5), family="lagrange"):
     """B (6 x 3*n_e) at one local point of an element of half-sizes
-    (l, h, w); family "serendipity" (order 2) keeps the 27-node layout."""
+    (l, h, w); family "serendipity" (order 2 or 3) keeps the Lagrange layout
+    of its degree."""
     p1 = order + 1
     nen = p1 ** 3
     B = np.zeros((6, 3 * nen))
     if family == "serendipity":
-        if order != 2:
-            raise ValueError("the serendipity element here is quadratic")
-        _, G = serendipity_shapes(xi, eta, zeta)
+        _, G = serendipity_shapes(xi, eta, zeta, order)
         G = G / np.asarray(half)
     else:
         _, val, der = lagrange_1d(order)
@@ -187,15 +240,17 @@ def element_matrix(order, nu=0.3, E=1.0, family="lagrange"):
     return sub_element_matrices(order, 1, nu, E, family=family)[0]
 
 
-def serendipity_dof_mask(nel):
-    """DOF mask (3 per node) of the 27-node lattice of a mesh marking the face
-    centres and body centres, which no serendipity element uses."""
+def serendipity_dof_mask(nel, order=2):
+    """DOF mask (3 per node) of the Lagrange lattice of degree `order` of a
+    mesh, marking the face-interior and body-interior nodes (two or three
+    lattice indices strictly inside an element's edge), which no
+    serendipity element uses."""
     nelx, nely, nelz = nel
-    i = np.arange(2 * nelx + 1) % 2
-    j = np.arange(2 * nely + 1) % 2
-    k = np.arange(2 * nelz + 1) % 2
-    odd = k[:, None, None] + j[None, :, None] + i[None, None, :]
-    return np.repeat((odd >= 2).reshape(-1), 3).astype(np.uint8)
+    i = (np.arange(order * nelx + 1) % order != 0).astype(int)
+    j = (np.arange(order * nely + 1) % order != 0).astype(int)
+    k = (np.arange(order * nelz + 1) % order != 0).astype(int)
+    inner = k[:, None, None] + j[None, :, None] + i[None, None, :]
+    return np.repeat((inner >= 2).reshape(-1), 3).astype(np.uint8)
 
 
 def local_node_coords(order):

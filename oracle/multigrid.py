@@ -2,11 +2,15 @@
 
 * Coarse mesh: every coarse element holds 2x2x2 fine elements (Sec. 2.3);
   on the node lattice the coarse node (I, J, K) coincides with the fine node
-  (2I, 2J, 2K).  A quadratic fine mesh (lattice spacing 1/2) coarsens onto
-  the vertex lattice of the same elements, then on as for linear meshes.
+  (2I, 2J, 2K).  A fine mesh of degree p >= 2 (lattice spacing 1/p)
+  coarsens first onto the vertex lattice of the same elements (coarse node
+  I on fine node pI), then on as for linear meshes.
 * Prolongation P: linear (trilinear) interpolation on the node lattice,
   per displacement component (Sec. 2.3: linear interpolation for Lagrange
-  elements); 1-D weights 1 at coincident nodes and 1/2, 1/2 at midpoints;
+  elements; for serendipity elements the paper interpolates with the
+  element's shape functions, which on the vertex lattice are the trilinear
+  ones); 1-D weights 1 at coincident nodes and, for a fine node q/r of
+  the way from coarse node I to I + 1 (ratio r = 2 or 3), 1 - q/r and q/r;
   the 3-D operator is the Kronecker product of the three 1-D ones.
   Restriction R = P^T (Sec. 2.3).
 * Supports: a coarse DOF is fixed when its coincident fine DOF is fixed;
@@ -25,14 +29,15 @@
   residual, restriction, coarse solve (exact on the coarsest level),
   prolongation and correction, post-smoothing).  This is the preconditioner
   M as a plain linear map, for testing the HIP V-cycle.
-* Smoother on a quadratic finest level (Sec. 7.5 prefers SSOR there): a
-  symmetric Gauss-Seidel in multicolour order.  Nodes of the quadratic
-  lattice are coloured by (i mod 3, j mod 3, k mod 3); two nodes of one
-  colour are at least three lattice steps apart in some axis, while a
-  quadratic element spans two, so they share no element and their rows do
-  not couple.  A forward sweep updates colour 0 .. 26 and, within a colour,
-  component x, y, z (each DOF from the latest values, relaxation 1); the
-  backward sweep runs colours and components in reverse.  Read as one
+* Smoother on a quadratic or cubic finest level (Sec. 7.5 prefers SSOR
+  there): a symmetric Gauss-Seidel in multicolour order.  Nodes of the
+  lattice of degree p are coloured by (i mod (p+1), j mod (p+1), k mod
+  (p+1)); two nodes of one colour are at least p + 1 lattice steps apart in
+  some axis, while an element spans p, so they share no element and their
+  rows do not couple.  A forward sweep updates colour 0 .. (p+1)^3 - 1 and,
+  within a colour, component x, y, z (each DOF from the latest values,
+  relaxation 1); the backward sweep runs colours and components in
+  reverse.  Read as one
   forward sweep before and one backward sweep after the coarse correction,
   so the V-cycle stays symmetric.  Coarser (trilinear) levels keep the
   capped Jacobi sweep.
@@ -41,7 +46,8 @@
   ||f - K u|| <= rtol ||f||; used where a direct factorisation is too large.
 
 Pins (tests/test_oracle_multigrid.py): P reproduces multilinear fields
-exactly; Galerkin of a constant-modulus operator equals the rediscretised
+exactly, for halving and for the cubic lattice's ratio-3 step (weights 1,
+2/3, 1/3); Galerkin of a constant-modulus operator equals the rediscretised
 operator with twice the element size (K scales with h in 3-D); the masked
 Galerkin operator is symmetric with identity rows on fixed DOFs and positive
 definite on free ones; the capped Jacobi sweep has spectral radius < 1 and
@@ -50,12 +56,15 @@ plain omega = 0.6 sweep diverges; without smoothing the cycle is the exact
 coarse correction, so M A is the A-orthogonal projector onto the range of
 the prolongations (idempotent, which fixes the scale of the transfers); with
 one sweep before and after, I - M A is the product of the sweep's and the
-coarse correction's error propagators; mgcg agrees with the direct solve.
+coarse correction's error propagators; the projector identity holds for a
+cubic finest level too (Lagrange and serendipity); mgcg agrees with the
+direct solve (linear, quadratic and cubic elements).
 The multicolour Gauss-Seidel sweep equals x + (D + L)^-1 (b - A x) (and
 the backward one the upper-triangle form) with A ordered by gs_order,
 computed by a sparse triangular solve, and its colour classes do not
-couple; the V-cycle with it is symmetric positive definite and its MG-CG
-reaches the direct solve in fewer iterations than with the Jacobi sweep.
+couple (those of one colour fewer per axis do); the V-cycle with it is
+symmetric positive definite and its MG-CG reaches the direct solve, for
+quadratic elements in fewer iterations than with the Jacobi sweep.
 """
 
 import numpy as np
@@ -63,42 +72,44 @@ import scipy.sparse as sp
 import scipy.linalg as sla
 
 
-def prolong_1d(nc):
-    """1-D interpolation from a lattice of nc nodes to one of 2(nc-1)+1."""
-    nf = 2 * (nc - 1) + 1
+def prolong_1d(nc, ratio=2):
+    """1-D linear interpolation from a lattice of nc nodes to one of
+    ratio (nc-1) + 1."""
+    nf = ratio * (nc - 1) + 1
     rows, cols, vals = [], [], []
     for I in range(nc):
-        rows.append(2 * I); cols.append(I); vals.append(1.0)
+        rows.append(ratio * I); cols.append(I); vals.append(1.0)
         if I + 1 < nc:
-            rows += [2 * I + 1, 2 * I + 1]
-            cols += [I, I + 1]
-            vals += [0.5, 0.5]
+            for q in range(1, ratio):
+                rows += [ratio * I + q, ratio * I + q]
+                cols += [I, I + 1]
+                vals += [1.0 - q / ratio, q / ratio]
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
 
 
-def coarse_dims(dims):
+def coarse_dims(dims, ratio=2):
     for d in dims:
-        if (d - 1) % 2 != 0 or d < 3:
-            raise ValueError(f"lattice {dims} cannot be coarsened")
-    return tuple((d - 1) // 2 + 1 for d in dims)
+        if (d - 1) % ratio != 0 or d < ratio + 1:
+            raise ValueError(f"lattice {dims} cannot be coarsened by {ratio}")
+    return tuple((d - 1) // ratio + 1 for d in dims)
 
 
-def prolongation(dims_c):
-    """DOF prolongation from coarse lattice dims_c (x, y, z) to its 2x
-    refinement, unmasked."""
-    Px, Py, Pz = (prolong_1d(d) for d in dims_c)
+def prolongation(dims_c, ratio=2):
+    """DOF prolongation from coarse lattice dims_c (x, y, z) to its
+    refinement by `ratio`, unmasked."""
+    Px, Py, Pz = (prolong_1d(d, ratio) for d in dims_c)
     Pn = sp.kron(Pz, sp.kron(Py, Px))
     return sp.kron(Pn, sp.identity(3)).tocsr()
 
 
-def coarse_mask(mask_f, dims_f):
+def coarse_mask(mask_f, dims_f, ratio=2):
     nx, ny, nz = dims_f
     m = np.asarray(mask_f).reshape(nz, ny, nx, 3)
-    return np.ascontiguousarray(m[::2, ::2, ::2, :]).ravel()
+    return np.ascontiguousarray(m[::ratio, ::ratio, ::ratio, :]).ravel()
 
 
-def masked_prolongation(dims_c, mask_f, mask_c):
-    P = prolongation(dims_c)
+def masked_prolongation(dims_c, mask_f, mask_c, ratio=2):
+    P = prolongation(dims_c, ratio)
     Zf = sp.diags((np.asarray(mask_f) == 0).astype(np.float64))
     Zc = sp.diags((np.asarray(mask_c) == 0).astype(np.float64))
     return (Zf @ P @ Zc).tocsr()
@@ -110,17 +121,23 @@ def galerkin(A_f, Pm, mask_c):
 
 
 class Hierarchy:
-    """Level operators A_l, masks, prolongations and diagonals."""
+    """Level operators A_l, masks, prolongations and diagonals.  order0 is
+    the element degree of the finest level: degree 3 coarsens first by 3
+    (onto its vertex lattice), every other step halves the lattice; the
+    multicolour Gauss-Seidel sweep of that level uses order0 + 1 colours
+    per axis."""
 
-    def __init__(self, A0, mask0, dims0, nlevels):
+    def __init__(self, A0, mask0, dims0, nlevels, order0=1):
         self.A = [A0.tocsr()]
         self.mask = [np.asarray(mask0, dtype=np.uint8)]
         self.dims = [tuple(dims0)]
         self.P = []
-        for _ in range(1, nlevels):
-            dc = coarse_dims(self.dims[-1])
-            mc = coarse_mask(self.mask[-1], self.dims[-1])
-            Pm = masked_prolongation(dc, self.mask[-1], mc)
+        self.gs_period = order0 + 1
+        for l in range(1, nlevels):
+            ratio = 3 if (l == 1 and order0 == 3) else 2
+            dc = coarse_dims(self.dims[-1], ratio)
+            mc = coarse_mask(self.mask[-1], self.dims[-1], ratio)
+            Pm = masked_prolongation(dc, self.mask[-1], mc, ratio)
             self.P.append(Pm)
             self.A.append(galerkin(self.A[-1], Pm, mc))
             self.mask.append(mc)
@@ -157,27 +174,28 @@ def smoother_weights(H, omega, theta=THETA):
     return out
 
 
-def node_colours(dims):
-    """Colour (i mod 3) + 3 (j mod 3) + 9 (k mod 3) of every node of the
-    lattice dims = (nx, ny, nz), x fastest."""
+def node_colours(dims, period=3):
+    """Colour (i mod m) + m (j mod m) + m^2 (k mod m), m = period, of every
+    node of the lattice dims = (nx, ny, nz), x fastest."""
     nx, ny, nz = dims
+    m = period
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    return ((i % 3) + 3 * (j % 3) + 9 * (k % 3)).ravel()
+    return ((i % m) + m * (j % m) + m * m * (k % m)).ravel()
 
 
-def gs_order(dims):
+def gs_order(dims, period=3):
     """The DOFs in forward sweep order: colour-major, then component, then
     node index."""
-    col = node_colours(dims)
+    col = node_colours(dims, period)
     out = []
-    for c in range(27):
+    for c in range(period ** 3):
         nodes = np.nonzero(col == c)[0]
         for comp in range(3):
             out.append(3 * nodes + comp)
     return out
 
 
-def gs_sweep(A, b, x, dims, backward=False):
+def gs_sweep(A, b, x, dims, backward=False, period=3):
     """One Gauss-Seidel sweep (relaxation 1) in multicolour order; every
     group of the order holds DOFs whose rows do not couple, so each group
     is updated at once from the latest values.  Fixed DOFs are identity
@@ -185,7 +203,7 @@ def gs_sweep(A, b, x, dims, backward=False):
     A = A.tocsr()
     d = A.diagonal()
     x = x.copy()
-    groups = gs_order(dims)
+    groups = gs_order(dims, period)
     if backward:
         groups = groups[::-1]
     for idx in groups:
@@ -209,13 +227,14 @@ def vcycle(H, b, level=0, omega=0.6, pre=1, post=1, weights=None, smoother="jaco
     wd = weights[level]
     gs = smoother == "gs" and level == 0
     x = np.zeros_like(b)
+    m = getattr(H, "gs_period", 3)
     for _ in range(pre):
-        x = gs_sweep(A, b, x, H.dims[0]) if gs else jacobi(A, wd, b, x)
+        x = gs_sweep(A, b, x, H.dims[0], period=m) if gs else jacobi(A, wd, b, x)
     r = b - A @ x
     e = vcycle(H, H.P[level].T @ r, level + 1, omega, pre, post, weights)
     x = x + H.P[level] @ e
     for _ in range(post):
-        x = gs_sweep(A, b, x, H.dims[0], backward=True) if gs else jacobi(A, wd, b, x)
+        x = gs_sweep(A, b, x, H.dims[0], backward=True, period=m) if gs else jacobi(A, wd, b, x)
     return x
 
 

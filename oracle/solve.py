@@ -47,11 +47,11 @@ def solve_direct(K, mask, f):
     return u
 
 
-def solve_mgcg(K, mask, f, dims, nlevels, x0=None, rtol=1e-12, omega=0.6, maxit=2000):
+def solve_mgcg(K, mask, f, dims, nlevels, x0=None, rtol=1e-12, omega=0.6, maxit=2000, order=1):
     A0 = level_operator(K, mask)
     f = np.atleast_2d(f).copy()
     f[:, np.asarray(mask) != 0] = 0.0
-    H = Hierarchy(A0, mask, dims, nlevels)
+    H = Hierarchy(A0, mask, dims, nlevels, order0=order)
     u = np.zeros_like(f)
     info = []
     for l in range(f.shape[0]):
@@ -92,7 +92,7 @@ def solve_problem(rho, mask, f, nel, order, nsub, Ksub, E0=1.0, Emin=1e-9, penal
     if method == "direct":
         u = solve_direct(K, mask, f)
     else:
-        u, _ = solve_mgcg(K, mask, f, node_dims(nel, order), nlevels, rtol=rtol)
+        u, _ = solve_mgcg(K, mask, f, node_dims(nel, order), nlevels, rtol=rtol, order=order)
     c = compliance(f, u)
     dc = sensitivity(rho, u, nel, order, nsub, Ksub, E0, Emin, penal)
     return K, u, c, dc

@@ -58,7 +58,7 @@ class Case:
     def H(self):
         if self._H is None:
             A0 = assemble.level_operator(self.K, self.mask)
-            self._H = multigrid.Hierarchy(A0, self.mask, self.dims, self.nlevels)
+            self._H = multigrid.Hierarchy(A0, self.mask, self.dims, self.nlevels, order0=self.order)
         return self._H
 
     def problem(self, **kw):

@@ -34,7 +34,7 @@ def test_rank_matches_table1(order, golden_dir):
     assert np.linalg.matrix_rank(K, tol=1e-10 * np.abs(K).max()) == rank
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_symmetric_and_rigid_modes(order):
     K = fem.element_matrix(order, NU)
     assert np.abs(K - K.T).max() < 1e-15
@@ -68,7 +68,7 @@ STRAINS = {
 }
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 @pytest.mark.parametrize("name", list(STRAINS))
 def test_uniform_strain_energy(order, name):
     """A linear displacement field has uniform strain; Lagrange elements
@@ -79,7 +79,7 @@ def test_uniform_strain_energy(order, name):
     assert abs(0.5 * u @ K @ u - wdens) < 1e-13
 
 
-@pytest.mark.parametrize("order,nsub", [(1, 2), (1, 3), (1, 4), (2, 2), (2, 4)])
+@pytest.mark.parametrize("order,nsub", [(1, 2), (1, 3), (1, 4), (2, 2), (2, 4), (3, 2)])
 def test_sub_elements_split_the_integral(order, nsub):
     """Sec. 3.3: the element integral is the sum of the n^3 sub-box integrals,
     and each sub-box carries 1/n^3 of a uniform-strain energy (which fixes the
@@ -135,7 +135,7 @@ def _box_energy(comp, lo, hi):
     return 0.5 * (M * sq(b) + G * sq(a))
 
 
-@pytest.mark.parametrize("order,nsub", [(1, 2), (1, 4), (2, 2), (2, 4)])
+@pytest.mark.parametrize("order,nsub", [(1, 2), (1, 4), (2, 2), (2, 4), (3, 2)])
 def test_sub_element_placement(order, nsub):
     """Sec. 3.3 eq. (7): K^(e_i) integrates over sub-box i = sx + n (sy + n sz),
     which covers [sx/n, (sx+1)/n] x [sy/n, ...] x [sz/n, ...] of the unit

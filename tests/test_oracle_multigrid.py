@@ -30,6 +30,29 @@ def test_prolongation_reproduces_multilinear_fields():
     assert np.allclose(np.asarray(P.sum(1)).ravel(), 1.0)
 
 
+def test_ratio_three_prolongation_reproduces_multilinear_fields():
+    """The cubic lattice's first coarsening (onto its vertex lattice, every
+    third node): the same exactness for multilinear fields, with the fine
+    node q/3 of the way between two coarse nodes weighted 1 - q/3, q/3."""
+    dc = (3, 2, 4)
+    P = multigrid.prolongation(dc, 3)
+    df = tuple(3 * (d - 1) + 1 for d in dc)
+    assert P.shape == (3 * np.prod(df), 3 * np.prod(dc))
+
+    def field(dims, scale):
+        nx, ny, nz = dims
+        k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        x, y, z = i.ravel() * scale, j.ravel() * scale, k.ravel() * scale
+        return np.stack([(1 + 0.3 * x) * (2 - 0.1 * y) * (0.5 + z),
+                         x * y * z - 2 * x + 3,
+                         (x - 1) * (z + 0.25)], 1).ravel()
+
+    assert np.abs(P @ field(dc, 1.0) - field(df, 1.0 / 3.0)).max() < 1e-12
+    assert np.allclose(np.asarray(P.sum(1)).ravel(), 1.0)
+    P1 = multigrid.prolong_1d(2, 3).toarray()
+    assert np.allclose(P1, [[1, 0], [2 / 3, 1 / 3], [1 / 3, 2 / 3], [0, 1]])
+
+
 def test_galerkin_of_constant_modulus_is_rediscretisation():
     """For uniform E and no supports, P^T K_h P equals the operator assembled
     from elements of twice the size (which in 3-D is 2 * K0 per element)."""
@@ -132,6 +155,20 @@ def _rough_hierarchy(nel, nlev, seed=4):
     return H, mask
 
 
+def _cubic_hierarchy(nel, nlev, family="lagrange", seed=6, nsub=1):
+    mask, f = W.make_problem("cantilever", *nel, 3, 1)
+    if family == "serendipity":
+        mask = np.maximum(mask, fem.serendipity_dof_mask(nel, 3))
+    rho = W.uniform_field((nsub * nel[2], nsub * nel[1], nsub * nel[0]), seed, 0.001, 1.0)
+    K = assemble.stiffness(rho, nel, 3, nsub, fem.sub_element_matrices(3, nsub, family=family),
+                           **MAT)
+    H = multigrid.Hierarchy(assemble.level_operator(K, mask), mask, assemble.node_dims(nel, 3),
+                            nlev, order0=3)
+    b = f[0].copy()
+    b[mask.astype(bool)] = 0.0
+    return H, mask, b
+
+
 def _vcycle_full(H, **kw):
     n = H.A[0].shape[0]
     return np.stack([multigrid.vcycle(H, e, **kw) for e in np.eye(n)], axis=1)
@@ -164,6 +201,25 @@ def test_coarse_correction_is_an_a_orthogonal_projector(nel, nlev):
     assert np.linalg.matrix_rank(MA, tol=1e-8 * scale) == len(free_c)
 
 
+@pytest.mark.parametrize("family", ["lagrange", "serendipity"])
+def test_cubic_coarse_correction_is_an_a_orthogonal_projector(family):
+    """The same projector identity for a cubic finest level, whose first
+    coarsening takes every third lattice node: a transfer with the wrong
+    weights or scale would break it."""
+    H, mask, _ = _cubic_hierarchy((2, 2, 2), 2, family)
+    assert H.dims[1] == (3, 3, 3)
+    A = H.A[0].toarray()
+    Mm = _vcycle_full(H, pre=0, post=0)
+    MA = Mm @ A
+    scale = np.abs(MA).max()
+    assert np.abs(MA @ MA - MA).max() < 1e-9 * scale
+    AMA = A @ MA
+    assert np.abs(AMA - AMA.T).max() < 1e-9 * np.abs(AMA).max()
+    Qf = H.P[0].toarray()[:, np.flatnonzero(H.mask[1] == 0)]
+    assert np.abs(MA @ Qf - Qf).max() < 1e-9 * max(1.0, np.abs(Qf).max())
+    assert np.linalg.matrix_rank(MA, tol=1e-8 * scale) == Qf.shape[1]
+
+
 def test_two_grid_error_propagation_composes_the_steps():
     """Algorithm 1 on two levels, one pre- and one post-sweep from x = 0:
     the error propagator I - M A is the product (I - S A)(I - C A)(I - S A)
@@ -188,14 +244,16 @@ def _q2_hierarchy(nel, nsub, nlev, seed=5, family="lagrange"):
     rho = W.gaussian_random_field((nsub * nel[2], nsub * nel[1], nsub * nel[0]), seed, corr=3.0)
     K = assemble.stiffness(rho, nel, 2, nsub, fem.sub_element_matrices(2, nsub, family=family), **MAT)
     A0 = assemble.level_operator(K, mask)
-    H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, 2), nlev)
+    H = multigrid.Hierarchy(A0, mask, assemble.node_dims(nel, 2), nlev, order0=2)
     b = f[0].copy()
     b[mask.astype(bool)] = 0.0
     return H, mask, b
 
 
-@pytest.mark.parametrize("nel,nsub", [((2, 2, 2), 1), ((4, 2, 2), 2), ((3, 2, 3), 1)])
-def test_gs_sweep_is_the_triangular_solve(nel, nsub):
+@pytest.mark.parametrize("order,nel,nsub", [(2, (2, 2, 2), 1), (2, (4, 2, 2), 2),
+                                            (2, (3, 2, 3), 1), (3, (2, 2, 1), 1),
+                                            (3, (1, 2, 2), 2)])
+def test_gs_sweep_is_the_triangular_solve(order, nel, nsub):
     """A Gauss-Seidel sweep with relaxation 1 in a given order is
     x + (D + L)^-1 (b - A x), L the strictly lower triangle of A with rows
     and columns in that order (the backward sweep: the upper triangle).  The
@@ -203,7 +261,12 @@ def test_gs_sweep_is_the_triangular_solve(nel, nsub):
     sequential sweep only if the group's rows do not couple: an order whose
     colours repeat every two nodes would fail."""
     from scipy.sparse.linalg import spsolve_triangular
-    H, mask, _ = _q2_hierarchy(nel, nsub, 1)
+    if order == 2:
+        H, mask, _ = _q2_hierarchy(nel, nsub, 1)
+    else:
+        H, mask, _ = _cubic_hierarchy(nel, 1, nsub=nsub)
+    m = order + 1
+    assert H.gs_period == m
     A = H.A[0].tocsr()
     n = A.shape[0]
     rng = np.random.default_rng(11)
@@ -211,7 +274,7 @@ def test_gs_sweep_is_the_triangular_solve(nel, nsub):
     x = rng.standard_normal(n)
     b[mask.astype(bool)] = 0.0
     x[mask.astype(bool)] = 0.0
-    perm = np.concatenate(multigrid.gs_order(H.dims[0]))
+    perm = np.concatenate(multigrid.gs_order(H.dims[0], m))
     assert np.array_equal(np.sort(perm), np.arange(n))
     Ap = A[perm][:, perm].tocsr()
     r = (b - A @ x)[perm]
@@ -221,18 +284,27 @@ def test_gs_sweep_is_the_triangular_solve(nel, nsub):
     want_f[perm] += spsolve_triangular(lower, r, lower=True)
     want_b = x.copy()
     want_b[perm] += spsolve_triangular(upper, r, lower=False)
-    got_f = multigrid.gs_sweep(A, b, x, H.dims[0])
-    got_b = multigrid.gs_sweep(A, b, x, H.dims[0], backward=True)
+    got_f = multigrid.gs_sweep(A, b, x, H.dims[0], period=m)
+    got_b = multigrid.gs_sweep(A, b, x, H.dims[0], backward=True, period=m)
     scale = np.abs(want_f).max()
     assert np.abs(got_f - want_f).max() <= 1e-11 * scale
     assert np.abs(got_b - want_b).max() <= 1e-11 * np.abs(want_b).max()
-    # the colour classes of a quadratic lattice do not couple
-    col = multigrid.node_colours(H.dims[0])
-    for c in range(27):
+    # the colour classes of the lattice do not couple, while a period of
+    # one less than order + 1 would put coupled nodes in one class
+    col = multigrid.node_colours(H.dims[0], m)
+    for c in range(m ** 3):
         nodes = np.flatnonzero(col == c)
         dofs = (3 * nodes[:, None] + np.arange(3)).ravel()
         blk = A[dofs][:, dofs].tocoo()
         assert np.all(blk.row // 3 == blk.col // 3)
+    col = multigrid.node_colours(H.dims[0], m - 1)
+    coupled = False
+    for c in range((m - 1) ** 3):
+        nodes = np.flatnonzero(col == c)
+        dofs = (3 * nodes[:, None] + np.arange(3)).ravel()
+        blk = A[dofs][:, dofs].tocoo()
+        coupled |= bool(np.any((blk.row // 3 != blk.col // 3) & (blk.data != 0)))
+    assert coupled
 
 
 @pytest.mark.parametrize("family", ["lagrange", "serendipity"])
@@ -255,3 +327,37 @@ def test_gs_vcycle_is_spd_and_beats_jacobi(family):
     assert res <= 1e-10
     assert np.linalg.norm(xg - xd) <= 1e-8 * np.linalg.norm(xd)
     assert itg < itj
+
+
+@pytest.mark.parametrize("family", ["lagrange", "serendipity"])
+def test_cubic_gs_vcycle_is_spd_and_mgcg_reaches_the_direct_solve(family):
+    """The cubic hierarchy (first coarsening by 3, then halving) with the
+    4-colour-per-axis Gauss-Seidel sweep: the V-cycle is symmetric positive
+    definite, and MG-CG with either smoother reaches the direct solve."""
+    H, mask, b = _cubic_hierarchy((2, 1, 1), 2, family)
+    Mm = _vcycle_full(H, smoother="gs")
+    assert np.abs(Mm - Mm.T).max() <= 1e-10 * np.abs(Mm).max()
+    free = np.flatnonzero(mask == 0)
+    assert np.linalg.eigvalsh(0.5 * (Mm + Mm.T)[np.ix_(free, free)]).min() > 0.0
+    xd = np.zeros_like(b)
+    xd[free] = np.linalg.solve(H.A[0].toarray()[np.ix_(free, free)], b[free])
+    for sm in ("gs", "jacobi"):
+        x, it, res = multigrid.mgcg(H, b, rtol=1e-11, smoother=sm, maxit=4000)
+        assert res <= 1e-11
+        assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_cubic_mgcg_three_levels_matches_direct():
+    """Three levels (cubic -> vertex lattice -> halved) on an MBB-type
+    support with two load cases, through the oracle's solve entry."""
+    nel = (4, 2, 2)
+    mask, f = W.make_problem("mbb", *nel, 3, 2)
+    rho = W.gaussian_random_field((2 * nel[2], 2 * nel[1], 2 * nel[0]), 8, corr=3.0)
+    Ks = fem.sub_element_matrices(3, 2)
+    K = assemble.stiffness(rho, nel, 3, 2, Ks, **MAT)
+    ud = solve.solve_direct(K, mask, f)
+    um, info = solve.solve_mgcg(K, mask, f, assemble.node_dims(nel, 3), 3, rtol=1e-10,
+                                omega=0.5, order=3)
+    for l in range(2):
+        assert info[l][1] <= 1e-10
+        assert np.linalg.norm(um[l] - ud[l]) <= 1e-7 * np.linalg.norm(ud[l])

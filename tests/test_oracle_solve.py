@@ -40,7 +40,7 @@ def test_compliance_identity():
     assert np.all(c > 0)
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_patch_test(order):
     """Uniform material, a linear field prescribed on the boundary and no
     loads: the solution reproduces the linear field at interior nodes."""
@@ -120,7 +120,7 @@ def test_sensitivity_sign_and_identity():
 
 
 @pytest.mark.parametrize("nel,order,nsub", [((2, 1, 1), 1, 2), ((1, 1, 1), 2, 2),
-                                            ((3, 1, 2), 1, 1)])
+                                            ((3, 1, 2), 1, 1), ((1, 1, 1), 3, 2)])
 def test_sensitivity_central_differences(nel, order, nsub):
     """Entrywise central differences (h = 1e-6) of c = sum_l f_l^T u_l."""
     mask, f, rho, Ks = _setup(nel, order, nsub, nrhs=2, seed=5)
@@ -154,7 +154,7 @@ def test_rigid_modes_of_unsupported_assembly():
     assert spla.eigsh(A, k=1, which="SA", return_eigenvectors=False)[0] > 0
 
 
-@pytest.mark.parametrize("order,nsub", [(1, 1), (1, 2), (2, 2)])
+@pytest.mark.parametrize("order,nsub", [(1, 1), (1, 2), (2, 2), (3, 1)])
 def test_elementwise_apply(order, nsub):
     """K u without forming K: rigid-body modes give zero force, a linear
     field gives zero force at interior nodes (patch test), the map is

@@ -9,7 +9,8 @@ Every builder returns ``(mask, f)``:
 Distributed loads use consistent nodal weights of the element's shape
 functions on a uniform lattice: for linear elements the trapezoid weights
 (1/2 at the ends of each element edge), for quadratic elements Simpson's
-weights (1/6, 4/6, 1/6 per element).  Point loads are shared equally by the
+weights (1/6, 4/6, 1/6 per element), for cubic ones Simpson's 3/8 weights
+(1/8, 3/8, 3/8, 1/8 per element).  Point loads are shared equally by the
 nearest lattice nodes when the target point is not a node.
 """
 
@@ -29,8 +30,10 @@ def _line_weights(nel, order):
         per = np.array([0.5, 0.5])
     elif order == 2:
         per = np.array([1.0, 4.0, 1.0]) / 6.0
+    elif order == 3:
+        per = np.array([1.0, 3.0, 3.0, 1.0]) / 8.0
     else:
-        raise ValueError("order must be 1 or 2")
+        raise ValueError("order must be 1, 2 or 3")
     for e in range(nel):
         w[order * e: order * e + order + 1] += per
     return w

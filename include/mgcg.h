@@ -69,22 +69,23 @@ extern "C" {
 #define MGCG_FP64 0  /* FP64 everywhere */
 #define MGCG_MIXED 1 /* FP32 V-cycle inside an FP64 CG (FP64 coarsest inverse) */
 
-/* Element families (Sec. 2.1).  MGCG_SERENDIPITY needs order 2: the 20-node
- * quadratic serendipity element (vertices and edge midpoints).  It runs on
- * the 27-node lattice of order 2; the DOFs of face centres and body centres,
- * which no serendipity element uses, are fixed by the library (their loads
- * ignored, their displacements 0). */
+/* Element families (Sec. 2.1).  MGCG_SERENDIPITY needs order 2 or 3: the
+ * 20-node quadratic serendipity element (vertices and edge midpoints) or the
+ * 32-node cubic one (vertices and the two third-points of every edge).  It
+ * runs on the Lagrange lattice of its order; the DOFs of face-interior and
+ * body-interior nodes, which no serendipity element uses, are fixed by the
+ * library (their loads ignored, their displacements 0). */
 #define MGCG_LAGRANGE 0
 #define MGCG_SERENDIPITY 1
-/* Finest-level smoother (Sec. 7.5 prefers SSOR for quadratic elements):
- * MGCG_SMOOTH_GAUSS_SEIDEL is a symmetric Gauss-Seidel sweep in multicolour
- * order on the quadratic node lattice (nodes coloured by their lattice
- * indices mod 3, so that nodes of one colour share no element; colours
- * 0..26 and, within a node, components x, y, z), relaxation 1: pre forward
- * sweeps before and post backward sweeps after the coarse correction, so
- * the V-cycle stays symmetric.  Coarser levels keep the Jacobi sweep (omega).
- * It stores each element's 81x81 matrix once more, by node, in the V-cycle
- * precision (6561 values per element). */
+/* Finest-level smoother (Sec. 7.5 prefers SSOR for quadratic and cubic
+ * elements): MGCG_SMOOTH_GAUSS_SEIDEL is a symmetric Gauss-Seidel sweep in
+ * multicolour order on the node lattice of order p = 2 or 3 (nodes coloured
+ * by their lattice indices mod p + 1, so that nodes of one colour share no
+ * element; colours 0 .. (p+1)^3 - 1 and, within a node, components x, y, z),
+ * relaxation 1: pre forward sweeps before and post backward sweeps after the
+ * coarse correction, so the V-cycle stays symmetric.  Coarser levels keep
+ * the Jacobi sweep (omega).  It stores each element's matrix once more, by
+ * node, in the V-cycle precision (81^2 or 192^2 values per element). */
 #define MGCG_SMOOTH_JACOBI 0
 #define MGCG_SMOOTH_GAUSS_SEIDEL 1
 
@@ -98,7 +99,9 @@ typedef struct mgcg_server mgcg_server;
 /* Problem description.  Elements are unit cubes. */
 typedef struct mgcg_desc {
   int32_t nelx, nely, nelz; /* displacement elements per axis (>= 1) */
-  int32_t order;            /* 1: 8-node trilinear, 2: 27-node triquadratic */
+  int32_t order;            /* 1: 8-node trilinear, 2: 27-node triquadratic,
+                               3: 64-node tricubic (orders 2 and 3 coarsen first
+                               onto the vertex lattice of the same elements) */
   int32_t nsub;             /* density sub-elements per axis per element (n_mr >= 1) */
   int32_t nlevels;          /* multigrid levels including the finest (>= 1); every
                                coarsening needs even element counts on every axis */
@@ -108,10 +111,11 @@ typedef struct mgcg_desc {
   int32_t pre, post;        /* weighted-Jacobi sweeps before / after the coarse correction */
   double E0, Emin, nu, penal; /* solid modulus, void modulus, Poisson ratio, SIMP p */
   double omega;             /* Jacobi weight */
-  int32_t family;           /* MGCG_LAGRANGE or MGCG_SERENDIPITY (order 2) */
+  int32_t family;           /* MGCG_LAGRANGE or MGCG_SERENDIPITY (order 2 or 3) */
   int32_t smoother;         /* finest-level smoother: MGCG_SMOOTH_JACOBI (0, the
                                capped weighted Jacobi of every level) or, for
-                               order 2 with nlevels >= 2, MGCG_SMOOTH_GAUSS_SEIDEL */
+                               order 2 or 3 with nlevels >= 2,
+                               MGCG_SMOOTH_GAUSS_SEIDEL */
 } mgcg_desc;
 
 /* Result of one solve. */

@@ -32,6 +32,7 @@ enum OpKind : int {
   OP_MF_Q1 = 0,  // matrix-free trilinear elements: y = sum_e E_e K0 u_e (one density per element)
   OP_ST27 = 1,   // assembled 27-point stencil of 3x3 blocks (Q1-type lattice), symmetric half
   OP_EQ2 = 2,    // stored 81x81 element matrices of triquadratic elements
+  OP_EQ3 = 3,    // stored 192x192 (serendipity: 96x96) element matrices of tricubic elements
 };
 
 // Number of stored stencil blocks per node: the diagonal block and the 13

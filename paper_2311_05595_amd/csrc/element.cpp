@@ -1,5 +1,6 @@
-// Element stiffness of Lagrange hexahedra (Sec. 2 eq. (1); sub-box split of
-// Sec. 3.3), computed on the host once per problem.
+// Element stiffness of Lagrange (degree 1-3) and serendipity (degree 2-3)
+// hexahedra (Sec. 2 eq. (1), Sec. 2.1; sub-box split of Sec. 3.3), computed
+// on the host once per problem.
 //
 // For an isotropic material with Lame constants lambda, mu the element
 // bilinear form, written per pair of shape-function gradients g_a, g_b, is
@@ -7,7 +8,8 @@
 //                              + mu delta_ce (g_a . g_b),
 // which equals B^T D B for the Voigt D with engineering shear.  Each
 // sub-box of the n^3 split is integrated with (p+1)^3 Gauss-Legendre points
-// (exact for these polynomial integrands).  Unit element: x = xi / 2.
+// (exact for these polynomial integrands: the shape functions have degree
+// <= p per axis, the serendipity ones included).  Unit element: x = xi / 2.
 #include "element.h"
 
 #include <cmath>
@@ -103,12 +105,56 @@ void serendipity_grad(const double t[3], double* grad) {
   }
 }
 
+// Local gradients of the 32-node cubic serendipity shape functions at
+// (t0, t1, t2), in the 64-node layout (zero at face- and body-interior
+// nodes).  Node a has local coordinates c_d = -1 + 2 a_d / 3.  A vertex
+// function is (1 + c0 t0)(1 + c1 t1)(1 + c2 t2)(9 |t|^2 - 19) / 64; an edge
+// node with |c_m| = 1/3 has 9 (1 - t_m^2)(1 + 9 c_m t_m) times the two
+// linear factors, / 64.
+void serendipity3_grad(const double t[3], double* grad) {
+  for (int a = 0; a < 64; ++a) {
+    const int q[3] = {a % 4, (a / 4) % 4, a / 16};
+    double c[3];
+    int inner = 0, m = -1;
+    for (int d = 0; d < 3; ++d) {
+      c[d] = -1.0 + 2.0 * q[d] / 3.0;
+      if (q[d] == 1 || q[d] == 2) {
+        ++inner;
+        m = d;
+      }
+    }
+    double* g = &grad[3 * a];
+    g[0] = g[1] = g[2] = 0.0;
+    if (inner == 0) {
+      double f[3];
+      for (int d = 0; d < 3; ++d) f[d] = 1.0 + c[d] * t[d];
+      const double s = 9.0 * (t[0] * t[0] + t[1] * t[1] + t[2] * t[2]) - 19.0;
+      for (int d = 0; d < 3; ++d)
+        g[d] = f[(d + 1) % 3] * f[(d + 2) % 3] * (c[d] * s + 18.0 * t[d] * f[d]) / 64.0;
+    } else if (inner == 1) {
+      double f[3], df[3];
+      for (int d = 0; d < 3; ++d) {
+        if (d == m) {
+          f[d] = (1.0 - t[d] * t[d]) * (1.0 + 9.0 * c[d] * t[d]);
+          df[d] = -2.0 * t[d] * (1.0 + 9.0 * c[d] * t[d]) + 9.0 * c[d] * (1.0 - t[d] * t[d]);
+        } else {
+          f[d] = 1.0 + c[d] * t[d];
+          df[d] = c[d];
+        }
+      }
+      g[0] = 9.0 * df[0] * f[1] * f[2] / 64.0;
+      g[1] = 9.0 * f[0] * df[1] * f[2] / 64.0;
+      g[2] = 9.0 * f[0] * f[1] * df[2] / 64.0;
+    }
+  }
+}
+
 }  // namespace
 
 std::vector<double> sub_element_matrices(int order, int nsub, double nu, int family) {
-  if (order < 1 || order > 2 || nsub < 1) throw std::invalid_argument("element order/nsub");
-  if (family != 0 && !(family == 1 && order == 2))
-    throw std::invalid_argument("the serendipity element is quadratic");
+  if (order < 1 || order > 3 || nsub < 1) throw std::invalid_argument("element order/nsub");
+  if (family != 0 && !(family == 1 && order >= 2))
+    throw std::invalid_argument("serendipity elements have degree 2 or 3");
   const int p1 = order + 1;
   const int nen = p1 * p1 * p1;
   const int nd = 3 * nen;
@@ -145,7 +191,10 @@ std::vector<double> sub_element_matrices(int order, int nsub, double nu, int fam
                 wq *= gw[q[d]] * half[d];
               }
               if (family == 1) {
-                serendipity_grad(tq, grad.data());
+                if (order == 2)
+                  serendipity_grad(tq, grad.data());
+                else
+                  serendipity3_grad(tq, grad.data());
                 for (double& v : grad) v *= dxi_dx;
               } else {
                 for (int az = 0; az < p1; ++az)
@@ -174,10 +223,9 @@ std::vector<double> sub_element_matrices(int order, int nsub, double nu, int fam
   return out;
 }
 
-double trilinear_weight(int px, int py, int pz, int b) {
-  auto w1 = [](int pos, int bit) -> double {
-    if (pos == 1) return 0.5;
-    return (pos == 2 * bit) ? 1.0 : 0.0;
+double trilinear_weight(int px, int py, int pz, int b, int r) {
+  auto w1 = [r](int pos, int bit) -> double {
+    return bit ? (double)pos / r : (double)(r - pos) / r;
   };
   return w1(px, b & 1) * w1(py, (b >> 1) & 1) * w1(pz, (b >> 2) & 1);
 }

@@ -382,6 +382,150 @@ __global__ __launch_bounds__(BS) void k_es2_elem(OpEQ2<T> op, In in, int nrhs,
   (void)by;
 }
 
+// ------------------------------------------------------------ tricubic
+// Second pass on the cubic lattice: a node sums the rows of the element
+// products of the 1..8 elements that contain it (per axis: one element when
+// the index is inside an edge, else the two that meet there); fixed rows
+// return the input.  The serendipity element leaves the face- and
+// body-interior nodes' products unwritten: those nodes are fixed.
+template <typename T>
+struct OpEQ3Y {
+  Lat L;
+  const T* Y;
+  const uint8_t* mask;
+};
+template <typename T, class In>
+__device__ __forceinline__ void ax_any(const OpEQ3Y<T>& op, const In& in, int r, long node, T y[3]) {
+  const Lat L = op.L;
+  int i, j, k;
+  node_ijk(node, L, i, j, k);
+  const int nex = (L.nx - 1) / 3, ney = (L.ny - 1) / 3, nez = (L.nz - 1) / 3;
+  const long nel = (long)nex * ney * nez;
+  int es[3][2], as[3][2], ne[3];
+  const int p[3] = {i, j, k}, nmax[3] = {nex, ney, nez};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ne[d] = 0;
+    const int q = p[d] / 3, m = p[d] - 3 * q;
+    if (m) {
+      es[d][0] = q;
+      as[d][0] = m;
+      ne[d] = 1;
+    } else {
+      if (q - 1 >= 0) { es[d][ne[d]] = q - 1; as[d][ne[d]] = 3; ++ne[d]; }
+      if (q < nmax[d]) { es[d][ne[d]] = q; as[d][ne[d]] = 0; ++ne[d]; }
+    }
+  }
+  T acc[3] = {T(0), T(0), T(0)};
+  const T* Yr = op.Y + (size_t)r * nel * L3_ND;
+  for (int cz = 0; cz < ne[2]; ++cz)
+    for (int cy = 0; cy < ne[1]; ++cy)
+      for (int cx = 0; cx < ne[0]; ++cx) {
+        const long e = es[0][cx] + (long)nex * (es[1][cy] + (long)ney * es[2][cz]);
+        const int a = as[0][cx] + 4 * (as[1][cy] + 4 * as[2][cz]);
+        const T* ye = Yr + e * L3_ND + 3 * a;
+        acc[0] += ye[0];
+        acc[1] += ye[1];
+        acc[2] += ye[2];
+      }
+  const uint8_t m = op.mask[node];
+  if (m) {
+    T v[3];
+    in.load(r, node, v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if ((m >> c) & 1) acc[c] = v[c];
+  }
+  y[0] = acc[0];
+  y[1] = acc[1];
+  y[2] = acc[2];
+}
+
+// First pass: y_e = K_e u_e, one thread per (element, row) over the N DOFs
+// of the element (192 for the 64-node element, 96 for the 32-node
+// serendipity one), E3_BS / N elements per block.  K_e by wrapped
+// diagonals, D[s][i] = K_e[i][(i + s) mod N] for s = 0..N/2: row i is
+// D[0][i] u_i + sum_{s=1}^{N/2-1} (D[s][i] u_{i+s} + D[s][i-s] u_{i-s})
+// + D[N/2][i] u_{i+N/2} (columns i + N/2 and i - N/2 coincide).  At step s
+// an element's N threads read the N consecutive values D[s][*] once (the
+// rotated second read hits the same lines); each value serves every load
+// case, whose u_e are staged in LDS.  Batches of 8 diagonals, the loads of
+// batch b + 1 issued before the arithmetic of batch b.
+constexpr int E3_BS = 192;
+template <typename T, int NR, class In, int N>
+__global__ __launch_bounds__(E3_BS) void k_e3_elem(OpEQ2<T> op, In in, int nrhs,
+                                                    const CgScalars* gate, int gate_state) {
+  constexpr int EPB = E3_BS / N, H = N / 2, PK = (H + 1) * N, NBT = H / 8;
+  static_assert(EPB * N == E3_BS && NBT * 8 == H, "tile shape");
+  const Gate g = gate_load(gate, nrhs, gate_state);
+  if (gate_state == CG_CHECK && !gate_open(g)) return;
+  __shared__ T ue[NR][EPB][N];
+  int bx, by;
+  xcd_tile(bx, by);
+  const Lat L = op.L;
+  const int nex = (L.nx - 1) / 3, ney = (L.ny - 1) / 3, nez = (L.nz - 1) / 3;
+  const long nel = (long)nex * ney * nez;
+  const int le = threadIdx.x / N, row = threadIdx.x - N * le;
+  const long e = (long)bx * EPB + le;
+  const bool on = e < nel;
+  const int a = N == L3_ND ? row / 3 : s3_node(row / 3), comp = row - 3 * (row / 3);
+  if (on) {
+    const int ex = (int)(e % nex), ey = (int)((e / nex) % ney), ez = (int)(e / ((long)nex * ney));
+    const int ax = a % 4, ay = (a / 4) % 4, az = a / 16;
+    const long node = (3 * ex + ax) + (long)L.nx * ((3 * ey + ay) + (long)L.ny * (3 * ez + az));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T v[3];
+      in.load(r, node, v);
+      ue[r][le][row] = v[comp];
+    }
+  }
+  __syncthreads();
+  if (!gate_open(g) || !on) return;
+  const T* D = op.Ke + (size_t)e * PK;
+  T acc[NR][2];
+  const T d0 = D[row];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    acc[r][0] = d0 * ue[r][le][row];
+    acc[r][1] = T(0);
+  }
+  T kb[2][16];
+  auto issue = [&](int b, T (&k)[16]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int sd = 1 + 8 * b + q;
+      int jm = row - sd;
+      jm += jm < 0 ? N : 0;
+      k[2 * q] = D[sd * N + row];
+      k[2 * q + 1] = sd < H ? D[sd * N + jm] : T(0);
+    }
+  };
+  issue(0, kb[0]);
+#pragma unroll
+  for (int b = 0; b < NBT; ++b) {
+    if (b + 1 < NBT) issue(b + 1, kb[(b + 1) & 1]);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pin(kb[b & 1][q]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int sd = 1 + 8 * b + q;
+      int jp = row + sd, jm = row - sd;
+      jp -= jp >= N ? N : 0;
+      jm += jm < 0 ? N : 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        acc[r][0] = fma(kb[b & 1][2 * q], ue[r][le][jp], acc[r][0]);
+        if (sd < H) acc[r][1] = fma(kb[b & 1][2 * q + 1], ue[r][le][jm], acc[r][1]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    op.Y[((size_t)r * nel + e) * L3_ND + 3 * a + comp] = acc[r][0] + acc[r][1];
+  (void)by;
+}
+
 // ------------------------------------------------------------ epilogues
 // pre(r, node) loads the epilogue's operands and is called before the
 // operator's gathers, so that those loads travel with them; put() then only
@@ -1038,6 +1182,33 @@ static void run_apply(const Op& op, const In& in, const Ep& ep, int nrhs, const 
                           EQ_EPB - 1) / EQ_EPB);
     hipEvent_t t_stop = g_time_stop;
     g_time_stop = nullptr;
+    if (op.p == 3) {
+      const long nel3 = (long)((op.L.nx - 1) / 3) * ((op.L.ny - 1) / 3) * ((op.L.nz - 1) / 3);
+      if (op.s2) {
+        const dim3 g3((unsigned)((nel3 + E3_BS / S3_ND - 1) / (E3_BS / S3_ND)), 1);
+        switch (nrhs) {
+          case 1: launch_op_b(k_e3_elem<T, 1, In, S3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+          case 2: launch_op_b(k_e3_elem<T, 2, In, S3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+          case 3: launch_op_b(k_e3_elem<T, 3, In, S3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+          default: launch_op_b(k_e3_elem<T, 4, In, S3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+        }
+      } else {
+        const dim3 g3((unsigned)nel3, 1);
+        switch (nrhs) {
+          case 1: launch_op_b(k_e3_elem<T, 1, In, L3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+          case 2: launch_op_b(k_e3_elem<T, 2, In, L3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+          case 3: launch_op_b(k_e3_elem<T, 3, In, L3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+          default: launch_op_b(k_e3_elem<T, 4, In, L3_ND>, g3, dim3(E3_BS), st, op, in, nrhs, gate, gate_state); break;
+        }
+      }
+      g_time_stop = t_stop;
+      const OpEQ3Y<T> gy{op.L, op.Y, op.mask};
+      const int nb = nblocks(nn);
+      if (Ep::RED && nb > MAX_BLOCKS) throw Error(-1, "mesh too large for the reduction buffer");
+      launch_op(k_apply<T, OpEQ3Y<T>, In, Ep>, dim3(nb, nrhs), st, gy, in, ep, nrhs, gate,
+                gate_state, part);
+      return;
+    }
     if (op.s2) {
       const int ns = (int)(((long)(op.L.nx - 1) / 2 * ((op.L.ny - 1) / 2) * ((op.L.nz - 1) / 2) +
                             ES_EPB - 1) / ES_EPB);
@@ -1825,11 +1996,59 @@ __global__ __launch_bounds__(BS) void k_restrict(Lat F, Lat C, const uint8_t* __
   (void)mf;
 }
 
+// The cubic lattice's step onto its vertex lattice (coarse node I on fine
+// node 3I), R = P^T of the linear interpolation with 1-D weights 1 at
+// coincident nodes and (3 - |d|) / 3 at the fine nodes d = +-1, +-2 steps
+// away: one thread per coarse DOF over the 5x5x5 fine nodes around 3I.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_restrict3(Lat F, Lat C, const uint8_t* __restrict__ mc,
+                                                  const T* __restrict__ rf, T* bc,
+                                                  const T* __restrict__ wDc, T* xc, int nrhs,
+                                                  const CgScalars* cs) {
+  const Gate g = gate_load(cs, nrhs, CG_ACTIVE);
+  int bx, r;
+  xcd_tile(bx, r);  // r: load case
+  const long t = (long)bx * BS + threadIdx.x;
+  const long cnd = C.ndof();
+  if (t >= cnd) return;
+  const long node = t / 3;
+  const int c = (int)(t - 3 * node);
+  int I, J, K;
+  node_ijk(node, C, I, J, K);
+  const T* rr = rf + (size_t)r * F.ndof();
+  T acc = T(0);
+  for (int dz = -2; dz <= 2; ++dz) {
+    const int k = 3 * K + dz;
+    if ((unsigned)k >= (unsigned)F.nz) continue;
+    for (int dy = -2; dy <= 2; ++dy) {
+      const int j = 3 * J + dy;
+      if ((unsigned)j >= (unsigned)F.ny) continue;
+      const T wyz = T((3 - abs(dy)) * (3 - abs(dz))) / T(9);
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        const int i = 3 * I + dx;
+        if ((unsigned)i >= (unsigned)F.nx) continue;
+        acc = fma(wyz * T(3 - abs(dx)) / T(3), rr[3 * ((long)i + (long)F.nx * (j + (long)F.ny * k)) + c],
+                  acc);
+      }
+    }
+  }
+  if (!gate_open(g)) return;
+  const bool fixed = (mc[node] >> c) & 1;
+  const T bv = fixed ? T(0) : acc;
+  bc[(size_t)r * cnd + t] = bv;
+  if (xc) xc[(size_t)r * cnd + t] = wDc[t] * bv;
+}
+
 template <typename T>
 void v_restrict(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* rf,
                 T* bc, const T* wDc, T* xc, int nrhs, const CgScalars* cs, hipStream_t st) {
-  hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(coarse.ndof()), nrhs), dim3(BS), 0, st, fine, coarse,
-                     mask_f, mask_c, rf, bc, wDc, xc, nrhs, cs);
+  if (fine.nx - 1 == 3 * (coarse.nx - 1))
+    hipLaunchKernelGGL(k_restrict3<T>, dim3(nblocks(coarse.ndof()), nrhs), dim3(BS), 0, st, fine,
+                       coarse, mask_c, rf, bc, wDc, xc, nrhs, cs);
+  else
+    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(coarse.ndof()), nrhs), dim3(BS), 0, st, fine,
+                       coarse, mask_f, mask_c, rf, bc, wDc, xc, nrhs, cs);
   MGCG_HIP(hipGetLastError());
 }
 
@@ -1866,11 +2085,60 @@ __global__ __launch_bounds__(BS) void k_prolong(Lat F, Lat C, const uint8_t* __r
   for (int c = 0; c < 3; ++c) qv[c] = old[c] + (((mfn >> c) & 1) ? T(0) : pe[c]);
 }
 
+// The cubic lattice's prolongation from its vertex lattice: fine node i
+// lies q = i mod 3 steps past coarse node i / 3 and takes 1 - q/3 of it and
+// q/3 of the next, per axis.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_prolong3(Lat F, Lat C, const uint8_t* __restrict__ mf,
+                                                 const T* __restrict__ ec, T* xf, int nrhs,
+                                                 int accumulate, const CgScalars* cs) {
+  const Gate g = gate_load(cs, nrhs, CG_ACTIVE);
+  int bx, r;
+  xcd_tile(bx, r);  // r: load case
+  const long node = (long)bx * BS + threadIdx.x;
+  if (node >= F.nn()) return;
+  int i, j, k;
+  node_ijk(node, F, i, j, k);
+  const int p[3] = {i, j, k};
+  int c0[3], nc[3];
+  T w[3][2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c0[d] = p[d] / 3;
+    const int q = p[d] - 3 * c0[d];
+    nc[d] = q ? 2 : 1;
+    w[d][0] = T(3 - q) / T(3);
+    w[d][1] = T(q) / T(3);
+  }
+  const T* er = ec + (size_t)r * C.ndof();
+  T pe[3] = {T(0), T(0), T(0)};
+  for (int cz = 0; cz < nc[2]; ++cz)
+    for (int cy = 0; cy < nc[1]; ++cy)
+      for (int cx = 0; cx < nc[0]; ++cx) {
+        const T wt = w[0][cx] * w[1][cy] * w[2][cz];
+        const long cn = (c0[0] + cx) + (long)C.nx * ((c0[1] + cy) + (long)C.ny * (c0[2] + cz));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pe[c] = fma(wt, er[3 * cn + c], pe[c]);
+      }
+  if (!gate_open(g)) return;
+  const int mfn = mf[node];
+  T* qv = xf + (size_t)r * F.ndof() + 3 * node;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T add = ((mfn >> c) & 1) ? T(0) : pe[c];
+    qv[c] = accumulate ? qv[c] + add : add;
+  }
+}
+
 template <typename T>
 void v_prolong(Lat fine, Lat coarse, const uint8_t* mask_f, const uint8_t* mask_c, const T* ec,
                T* xf, int nrhs, bool accumulate, const CgScalars* cs, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(fine.nn()), nrhs), dim3(BS), 0, st, fine, coarse, mask_f,
-                     mask_c, ec, xf, nrhs, accumulate ? 1 : 0, cs);
+  if (fine.nx - 1 == 3 * (coarse.nx - 1))
+    hipLaunchKernelGGL(k_prolong3<T>, dim3(nblocks(fine.nn()), nrhs), dim3(BS), 0, st, fine, coarse,
+                       mask_f, ec, xf, nrhs, accumulate ? 1 : 0, cs);
+  else
+    hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(fine.nn()), nrhs), dim3(BS), 0, st, fine, coarse,
+                       mask_f, mask_c, ec, xf, nrhs, accumulate ? 1 : 0, cs);
   MGCG_HIP(hipGetLastError());
 }
 

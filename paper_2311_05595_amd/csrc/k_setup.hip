@@ -55,7 +55,7 @@ __global__ __launch_bounds__(BS) void k_effective(int order, int nsub, int nelx,
                                                   const uint8_t* __restrict__ mask, Lat L,
                                                   double* Keff) {
   const int ns3 = nsub * nsub * nsub;
-  const int nd = order == 1 ? 24 : 81;
+  const int nd = 3 * (order + 1) * (order + 1) * (order + 1);
   const int nd2 = nd * nd;
   const long nel = (long)nelx * nely * nelz;
   const long e0 = (long)blockIdx.y * EB;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(BS) void k_effective(int order, int nsub, int nelx,
 
 void setup_effective(int order, int nsub, int nelx, int nely, int nelz, const double* E,
                      const double* Ksub, const uint8_t* mask, Lat L, double* Keff, hipStream_t st) {
-  const int nd = order == 1 ? 24 : 81;
+  const int nd = 3 * (order + 1) * (order + 1) * (order + 1);
   const long nel = (long)nelx * nely * nelz;
   if (nsub * nsub * nsub > 64) throw Error(-1, "nsub > 4 is not supported");
   dim3 grid((nd * nd + BS - 1) / BS, (unsigned)((nel + EB - 1) / EB));
@@ -152,6 +152,38 @@ void setup_pack_s2(const double* K, T* D, long nel, hipStream_t st) {
 }
 template void setup_pack_s2<double>(const double*, double*, long, hipStream_t);
 template void setup_pack_s2<float>(const double*, float*, long, hipStream_t);
+
+// The same for tricubic elements: N = 192 DOFs of the 64-node element, or
+// the 96 of the 32-node serendipity one (DOF 3k + c of serendipity node k is
+// DOF 3 s3_node(k) + c of the 64-node layout), D[e][s][i] = K[e][i][(i + s)
+// mod N], s = 0..N/2.
+template <typename T, int N>
+__global__ __launch_bounds__(BS) void k_pack_e3(const double* __restrict__ K, T* D, long nel) {
+  constexpr int PK = (N / 2 + 1) * N;
+  const long t = (long)blockIdx.x * BS + threadIdx.x;
+  if (t >= nel * PK) return;
+  const long e = t / PK;
+  const int q = (int)(t - e * PK), s = q / N, i = q - N * s;
+  int j = i + s;
+  j -= j >= N ? N : 0;
+  const int di = N == L3_ND ? i : 3 * s3_node(i / 3) + i % 3;
+  const int dj = N == L3_ND ? j : 3 * s3_node(j / 3) + j % 3;
+  D[t] = (T)K[(size_t)e * L3_ND * L3_ND + (size_t)L3_ND * di + dj];
+}
+
+template <typename T>
+void setup_pack_e3(const double* K, T* D, long nel, int serendipity, hipStream_t st) {
+  const long n = nel * (serendipity ? S3_PACKED : L3_PACKED);
+  if (serendipity)
+    hipLaunchKernelGGL((k_pack_e3<T, S3_ND>), dim3((unsigned)((n + BS - 1) / BS)), dim3(BS), 0, st,
+                       K, D, nel);
+  else
+    hipLaunchKernelGGL((k_pack_e3<T, L3_ND>), dim3((unsigned)((n + BS - 1) / BS)), dim3(BS), 0, st,
+                       K, D, nel);
+  MGCG_HIP(hipGetLastError());
+}
+template void setup_pack_e3<double>(const double*, double*, long, int, hipStream_t);
+template void setup_pack_e3<float>(const double*, float*, long, int, hipStream_t);
 
 // ------------------------------------------------------------ Galerkin
 // One block per coarse element.  Children have nodes at coarse-local lattice
@@ -241,13 +273,52 @@ __global__ __launch_bounds__(BS) void k_galerkin(int src_kind, Lat F, const doub
   }
 }
 
+// A cubic fine element onto its own 8 vertices: W[a][b] = trilinear weight
+// of vertex b at local node a (positions 0..3 of 3 per axis), KE = W^T Kc W
+// with Kc (192x192, supported rows and columns already zero) read from
+// global memory: T = Kc W (192 x 24) in LDS, then W^T T.
+__global__ __launch_bounds__(BS) void k_galerkin_e3(const double* __restrict__ Kc, int ncx, int ncy,
+                                                    double* KE, const int* __restrict__ elist) {
+  __shared__ double sT[L3_ND * 24];
+  __shared__ double sW[64 * 8];
+  const long E_id = elist ? elist[blockIdx.x] : blockIdx.x;
+  for (int t = threadIdx.x; t < 64 * 8; t += BS) {
+    const int a = t / 8, b = t % 8;
+    const int ax = a % 4, ay = (a / 4) % 4, az = a / 16;
+    auto w1 = [](int pos, int bit) { return bit ? pos / 3.0 : (3 - pos) / 3.0; };
+    sW[t] = w1(ax, b & 1) * w1(ay, (b >> 1) & 1) * w1(az, b >> 2);
+  }
+  __syncthreads();
+  const double* K = Kc + (size_t)E_id * L3_ND * L3_ND;
+  for (int t = threadIdx.x; t < L3_ND * 24; t += BS) {
+    const int row = t / 24, col = t % 24;
+    const int b = col / 3, j = col % 3;
+    double acc = 0.0;
+    for (int a2 = 0; a2 < 64; ++a2) acc += K[(size_t)row * L3_ND + 3 * a2 + j] * sW[a2 * 8 + b];
+    sT[t] = acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 576; t += BS) {
+    const int row = t / 24, col = t % 24;
+    const int b = row / 3, i = row % 3;
+    double acc = 0.0;
+    for (int a = 0; a < 64; ++a) acc += sW[a * 8 + b] * sT[(3 * a + i) * 24 + col];
+    KE[(size_t)E_id * 576 + t] = acc;
+  }
+  (void)ncx;
+  (void)ncy;
+}
+
 void setup_galerkin(int src_kind, Lat fine, const double* E, const double* K0, const double* Kc,
                     const uint8_t* mask_f, int ncx, int ncy, int ncz, double* KE,
                     const int* elist, int n_elist, hipStream_t st) {
   const long nce = elist ? n_elist : (long)ncx * ncy * ncz;
   if (nce <= 0) return;
-  hipLaunchKernelGGL(k_galerkin, dim3((unsigned)nce), dim3(BS), 0, st, src_kind, fine, E, K0, Kc,
-                     mask_f, ncx, ncy, ncz, KE, elist);
+  if (src_kind == OP_EQ3)
+    hipLaunchKernelGGL(k_galerkin_e3, dim3((unsigned)nce), dim3(BS), 0, st, Kc, ncx, ncy, KE, elist);
+  else
+    hipLaunchKernelGGL(k_galerkin, dim3((unsigned)nce), dim3(BS), 0, st, src_kind, fine, E, K0, Kc,
+                       mask_f, ncx, ncy, ncz, KE, elist);
   MGCG_HIP(hipGetLastError());
 }
 
@@ -450,24 +521,26 @@ template void setup_diag_mf<double>(Lat, const double*, const double*, const uin
 template void setup_diag_mf<float>(Lat, const double*, const double*, const uint8_t*, float*,
                                    double*, double, double, hipStream_t);
 
-// Jacobi data of the stored triquadratic operator: the row of a node couples
-// the nodes within two lattice steps; entries shared by several elements
-// are summed before taking absolute values.
-template <typename T>
-__global__ __launch_bounds__(BS) void k_diag_eq2(Lat L, const double* __restrict__ Ke,
-                                                 const uint8_t* __restrict__ mask, T* wD,
-                                                 double* diag64, double omega, double theta) {
+// Jacobi data of the stored operators of degree P = 2 or 3: the row of a
+// node couples the nodes within P lattice steps; entries shared by several
+// elements are summed before taking absolute values.
+template <typename T, int P>
+__global__ __launch_bounds__(BS) void k_diag_ep(Lat L, const double* __restrict__ Ke,
+                                                const uint8_t* __restrict__ mask, T* wD,
+                                                double* diag64, double omega, double theta) {
+  constexpr int P1 = P + 1, ND = 3 * P1 * P1 * P1, W = 2 * P + 1, CENTER = (W * W * W) / 2;
   const long node = (long)blockIdx.x * BS + threadIdx.x;
   if (node >= L.nn()) return;
   const int i = (int)(node % L.nx), j = (int)((node / L.nx) % L.ny), k = (int)(node / ((long)L.nx * L.ny));
-  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
+  const int nex = (L.nx - 1) / P, ney = (L.ny - 1) / P, nez = (L.nz - 1) / P;
   int exs[2], axs[2], nxe = 0, eys[2], ays[2], nye = 0, ezs[2], azs[2], nze = 0;
   auto axis = [](int p, int ne, int* es, int* as, int& n) {
     n = 0;
-    if (p & 1) { es[0] = (p - 1) / 2; as[0] = 1; n = 1; }
+    const int q = p / P, m = p - P * q;
+    if (m) { es[0] = q; as[0] = m; n = 1; }
     else {
-      if (p / 2 - 1 >= 0) { es[n] = p / 2 - 1; as[n] = 2; ++n; }
-      if (p / 2 < ne) { es[n] = p / 2; as[n] = 0; ++n; }
+      if (q - 1 >= 0) { es[n] = q - 1; as[n] = P; ++n; }
+      if (q < ne) { es[n] = q; as[n] = 0; ++n; }
     }
   };
   axis(i, nex, exs, axs, nxe);
@@ -475,8 +548,8 @@ __global__ __launch_bounds__(BS) void k_diag_eq2(Lat L, const double* __restrict
   axis(k, nez, ezs, azs, nze);
   const uint8_t mi = mask[node];
   double rs[3] = {0.0, 0.0, 0.0}, dg[3] = {0.0, 0.0, 0.0};
-  for (int q = 0; q < 125; ++q) {
-    const int dx = q % 5 - 2, dy = (q / 5) % 5 - 2, dz = q / 25 - 2;
+  for (int q = 0; q < W * W * W; ++q) {
+    const int dx = q % W - P, dy = (q / W) % W - P, dz = q / (W * W) - P;
     double blk[9];
     for (int t = 0; t < 9; ++t) blk[t] = 0.0;
     bool any = false;
@@ -484,21 +557,22 @@ __global__ __launch_bounds__(BS) void k_diag_eq2(Lat L, const double* __restrict
       for (int cy = 0; cy < nye; ++cy)
         for (int cx = 0; cx < nxe; ++cx) {
           const int bx = axs[cx] + dx, by = ays[cy] + dy, bz = azs[cz] + dz;
-          if ((unsigned)bx > 2u || (unsigned)by > 2u || (unsigned)bz > 2u) continue;
+          if ((unsigned)bx > (unsigned)P || (unsigned)by > (unsigned)P || (unsigned)bz > (unsigned)P)
+            continue;
           any = true;
           const long e = exs[cx] + (long)nex * (eys[cy] + (long)ney * ezs[cz]);
-          const int a = axs[cx] + 3 * (ays[cy] + 3 * azs[cz]), bb = bx + 3 * (by + 3 * bz);
+          const int a = axs[cx] + P1 * (ays[cy] + P1 * azs[cz]), bb = bx + P1 * (by + P1 * bz);
           for (int c = 0; c < 3; ++c)
             for (int e2 = 0; e2 < 3; ++e2)
-              blk[3 * c + e2] += Ke[(size_t)e * 6561 + (3 * a + c) * 81 + 3 * bb + e2];
+              blk[3 * c + e2] += Ke[(size_t)e * ND * ND + (size_t)(3 * a + c) * ND + 3 * bb + e2];
         }
     if (!any) continue;
     for (int c = 0; c < 3; ++c)
       for (int e2 = 0; e2 < 3; ++e2) {
         double v = blk[3 * c + e2];  // supported rows/columns are zero in Ke
-        if (q == 62 && c == e2 && ((mi >> c) & 1)) v = 1.0;
+        if (q == CENTER && c == e2 && ((mi >> c) & 1)) v = 1.0;
         rs[c] += fabs(v);
-        if (q == 62 && c == e2) dg[c] = v;
+        if (q == CENTER && c == e2) dg[c] = v;
       }
   }
   for (int c = 0; c < 3; ++c)
@@ -508,7 +582,7 @@ __global__ __launch_bounds__(BS) void k_diag_eq2(Lat L, const double* __restrict
 template <typename T>
 void setup_diag_eq2(Lat L, const double* Ke, const uint8_t* mask, T* wD, double* diag64,
                     double omega, double theta, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_eq2<T>, dim3(nblocks(L.nn())), dim3(BS), 0, st, L, Ke, mask, wD,
+  hipLaunchKernelGGL((k_diag_ep<T, 2>), dim3(nblocks(L.nn())), dim3(BS), 0, st, L, Ke, mask, wD,
                      diag64, omega, theta);
   MGCG_HIP(hipGetLastError());
 }
@@ -516,6 +590,18 @@ template void setup_diag_eq2<double>(Lat, const double*, const uint8_t*, double*
                                      double, hipStream_t);
 template void setup_diag_eq2<float>(Lat, const double*, const uint8_t*, float*, double*, double,
                                     double, hipStream_t);
+
+template <typename T>
+void setup_diag_e3(Lat L, const double* Ke, const uint8_t* mask, T* wD, double* diag64,
+                   double omega, double theta, hipStream_t st) {
+  hipLaunchKernelGGL((k_diag_ep<T, 3>), dim3(nblocks(L.nn())), dim3(BS), 0, st, L, Ke, mask, wD,
+                     diag64, omega, theta);
+  MGCG_HIP(hipGetLastError());
+}
+template void setup_diag_e3<double>(Lat, const double*, const uint8_t*, double*, double*, double,
+                                    double, hipStream_t);
+template void setup_diag_e3<float>(Lat, const double*, const uint8_t*, float*, double*, double,
+                                   double, hipStream_t);
 
 // ------------------------------------------------------------ coarsest level
 // Dense operator of the coarsest level (row-major, stride ld) from its
@@ -780,7 +866,8 @@ __global__ __launch_bounds__(BS) void k_sens(int nsub, int nelx, int nely, int n
   dc[di] = -penal * pow(r, penal - 1.0) * E0mEmin * w;
 }
 
-// With 4^3 sub-elements the 64 quadratic forms of an element are one
+// With 4^3 sub-elements (and for cubic elements with any n^3 <= 64, the
+// columns past n^3 zero) the quadratic forms of an element are one
 // contraction: w_s = sum_l u_l^T K_s u_l = sum_{i <= j} U[k(i,j)] Kp[k(i,j)][s]
 // with U = sum_l u_l u_l^T (symmetric, packed row by row, i <= j) and Kp[k][s]
 // = K_s[i][j] times 2 off the diagonal (built once per mesh, sens_pack).
@@ -794,7 +881,10 @@ __global__ __launch_bounds__(BS) void k_sens(int nsub, int nelx, int nely, int n
 // chunk ahead, in two register sets that alternate.  For Q2 the block's
 // WPB = 4 waves split the packed pairs and add their tiles in a fixed order.
 // Kp and the table are padded (zero rows, offset 0) to an even number of
-// chunks per wave plus the prefetch overrun.
+// chunks per wave plus the prefetch overrun.  For cubic elements (18,528
+// pairs) the table stays in global memory and each chunk's offsets are
+// fetched with its Kp values: with u_e of four load cases staged, LDS could
+// not hold both.
 constexpr int SP_EL = 16;  // elements per block
 constexpr int SP_PF = 4;   // steps per Kp chunk
 template <int ORDER>
@@ -808,20 +898,26 @@ struct SensShape {
   static constexpr int ROWS = NKP + 4 * SP_PF;                  // + the prefetch overrun
 };
 
+static long sens_rows(int order) {
+  return order == 1 ? SensShape<1>::ROWS : order == 2 ? SensShape<2>::ROWS : SensShape<3>::ROWS;
+}
+
 long sens_packed_doubles(int order) {
-  const long rows = order == 1 ? SensShape<1>::ROWS : SensShape<2>::ROWS;
+  const long rows = sens_rows(order);
   return rows * 64 + rows / 2;  // Kp rows, then one 32-bit offset pair per row
 }
 
-void sens_pack(int order, const double* Ksub, std::vector<double>& out) {
-  const int nd = order == 1 ? SensShape<1>::ND : SensShape<2>::ND;
-  const long rows = order == 1 ? SensShape<1>::ROWS : SensShape<2>::ROWS;
+void sens_pack(int order, int nsub, const double* Ksub, std::vector<double>& out) {
+  const int nd = order == 1 ? SensShape<1>::ND : order == 2 ? SensShape<2>::ND : SensShape<3>::ND;
+  const long rows = sens_rows(order);
+  const int ns3 = nsub * nsub * nsub;
+  if (ns3 > 64) throw Error(-1, "at most 64 sub-elements");
   out.assign((size_t)sens_packed_doubles(order), 0.0);
   uint32_t* tab = reinterpret_cast<uint32_t*>(out.data() + rows * 64);
   long k = 0;
   for (int i = 0; i < nd; ++i)
     for (int j = i; j < nd; ++j, ++k) {
-      for (int s = 0; s < 64; ++s)
+      for (int s = 0; s < ns3; ++s)
         out[(size_t)k * 64 + s] = (i == j ? 1.0 : 2.0) * Ksub[(size_t)s * nd * nd + (size_t)i * nd + j];
       // byte offsets of u[i] and u[j] in the staged [DOF][element] block
       tab[k] = (uint32_t)(i * SP_EL * 8) | ((uint32_t)(j * SP_EL * 8) << 16);
@@ -832,22 +928,24 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <int ORDER, int NRHS>
 __global__ __launch_bounds__(64 * SensShape<ORDER>::WPB) void k_sens_mfma(
-    int nelx, int nely, int nelz, Lat L, const double* __restrict__ rho,
+    int nelx, int nely, int nelz, int nsub, Lat L, const double* __restrict__ rho,
     const double* __restrict__ u, long ndof, const double* __restrict__ Kp, double E0mEmin,
     double penal, double* __restrict__ dc) {
   using S = SensShape<ORDER>;
   constexpr int P1 = ORDER + 1, ND = S::ND, WPB = S::WPB, NT = 64 * WPB;
   constexpr int NU = NRHS * ND * SP_EL, NR = WPB * SP_EL * 64;
   constexpr int NCH = S::STEPS / SP_PF;  // chunks per wave (even)
+  constexpr bool TAB_LDS = ORDER < 3;
   static_assert(NCH % 2 == 0, "two alternating register sets");
   static_assert(ND * SP_EL * 8 < 65536, "16-bit LDS offsets");
   __shared__ double sh[NU > NR ? NU : NR];
-  __shared__ uint32_t tab[S::NKP];
+  __shared__ uint32_t tab[TAB_LDS ? S::NKP : 1];
   const long nel = (long)nelx * nely * nelz;
   const long e0 = (long)blockIdx.x * SP_EL;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const uint32_t* tabg = reinterpret_cast<const uint32_t*>(Kp + (size_t)S::ROWS * 64);
-  for (int q = t; q < S::NKP; q += NT) tab[q] = tabg[q];
+  if constexpr (TAB_LDS)
+    for (int q = t; q < S::NKP; q += NT) tab[q] = tabg[q];
   // u_e of the block's elements, [load case][local DOF][element]; elements
   // past the mesh read 0
   for (int q = t; q < NU; q += NT) {
@@ -875,14 +973,17 @@ __global__ __launch_bounds__(64 * SensShape<ORDER>::WPB) void k_sens_mfma(
   v4d acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-  auto fetch = [&](double4* b, int c) {
-#pragma unroll
-    for (int p = 0; p < SP_PF; ++p) b[p] = kb[(size_t)(c * SP_PF + p) * 64];
-  };
-  auto run = [&](const double4* b, int c) {
+  auto fetch = [&](double4* b, uint32_t* ijg, int c) {
 #pragma unroll
     for (int p = 0; p < SP_PF; ++p) {
-      const uint32_t ij = tab[k0 + 4 * (c * SP_PF + p)];
+      b[p] = kb[(size_t)(c * SP_PF + p) * 64];
+      if constexpr (!TAB_LDS) ijg[p] = tabg[k0 + 4 * (c * SP_PF + p)];
+    }
+  };
+  auto run = [&](const double4* b, const uint32_t* ijg, int c) {
+#pragma unroll
+    for (int p = 0; p < SP_PF; ++p) {
+      const uint32_t ij = TAB_LDS ? tab[k0 + 4 * (c * SP_PF + p)] : ijg[p];
       const int oi = (int)(ij & 0xffffu), oj = (int)(ij >> 16);
       double a = 0.0;
 #pragma unroll
@@ -896,12 +997,13 @@ __global__ __launch_bounds__(64 * SensShape<ORDER>::WPB) void k_sens_mfma(
     }
   };
   double4 b0[SP_PF], b1[SP_PF];
-  fetch(b0, 0);
+  uint32_t i0[SP_PF], i1[SP_PF];
+  fetch(b0, i0, 0);
   for (int c = 0; c < NCH; c += 2) {
-    fetch(b1, c + 1);
-    run(b0, c);
-    fetch(b0, c + 2);  // (the last one reads the zero overrun rows)
-    run(b1, c + 1);
+    fetch(b1, i1, c + 1);
+    run(b0, i0, c);
+    fetch(b0, i0, c + 2);  // (the last one reads the zero overrun rows)
+    run(b1, i1, c + 1);
   }
   __syncthreads();  // every wave is done with the staged u
   // result value v of a lane is row kk + 4 v, column m of its tile (the
@@ -914,24 +1016,25 @@ __global__ __launch_bounds__(64 * SensShape<ORDER>::WPB) void k_sens_mfma(
   __syncthreads();
   // outputs in density-lattice order within each (sy, sz) row: sub-element
   // x fastest, then element
-  for (int q = t; q < SP_EL * 64; q += NT) {
-    const int sx = q & 3, mm = (q >> 2) & (SP_EL - 1), syz = q >> 6;
-    const int s = sx + 4 * syz;
+  const int n = nsub;
+  for (int q = t; q < SP_EL * n * n * n; q += NT) {
+    const int sx = q % n, mm = (q / n) % SP_EL, syz = q / (n * SP_EL);
+    const int s = sx + n * syz;
     double v = 0.0;
 #pragma unroll
     for (int ww = 0; ww < WPB; ++ww) v += sh[ww * SP_EL * 64 + s * SP_EL + mm];
     const long e = e0 + mm;
     if (e >= nel) continue;
     const int ex = (int)(e % nelx), ey = (int)((e / nelx) % nely), ez = (int)(e / ((long)nelx * nely));
-    const int sy = syz & 3, sz = syz >> 2;
+    const int sy = syz % n, sz = syz / n;
     const long di =
-        (4 * ex + sx) + (long)(4 * nelx) * ((4 * ey + sy) + (long)(4 * nely) * (4 * ez + sz));
+        (n * ex + sx) + (long)(n * nelx) * ((n * ey + sy) + (long)(n * nely) * (n * ez + sz));
     dc[di] = -penal * pow(rho[di], penal - 1.0) * E0mEmin * v;
   }
 }
 
 template <int ORDER>
-static void launch_sens_mfma(int nelx, int nely, int nelz, Lat L, const double* rho,
+static void launch_sens_mfma(int nelx, int nely, int nelz, int nsub, Lat L, const double* rho,
                              const double* u, long ndof, int nrhs, const double* Kp,
                              double E0mEmin, double penal, double* dc, hipStream_t st) {
   const dim3 g(nblocks((long)nelx * nely * nelz, SP_EL)), b(64 * SensShape<ORDER>::WPB);
@@ -939,17 +1042,24 @@ static void launch_sens_mfma(int nelx, int nely, int nelz, Lat L, const double* 
               : nrhs == 2 ? k_sens_mfma<ORDER, 2>
               : nrhs == 3 ? k_sens_mfma<ORDER, 3>
                           : k_sens_mfma<ORDER, 4>;
-  hipLaunchKernelGGL(kern, g, b, 0, st, nelx, nely, nelz, L, rho, u, ndof, Kp, E0mEmin, penal, dc);
+  hipLaunchKernelGGL(kern, g, b, 0, st, nelx, nely, nelz, nsub, L, rho, u, ndof, Kp, E0mEmin,
+                     penal, dc);
 }
 
 void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const double* rho,
                  const double* u, long ndof, int nrhs, const double* Ksub, const double* Kp,
                  double E0mEmin, double penal, double* dc, hipStream_t st) {
+  if (order == 3) {
+    if (!Kp) throw Error(-1, "cubic elements need the packed sub-element matrices");
+    launch_sens_mfma<3>(nelx, nely, nelz, nsub, L, rho, u, ndof, nrhs, Kp, E0mEmin, penal, dc, st);
+    MGCG_HIP(hipGetLastError());
+    return;
+  }
   if (nsub == 4 && Kp) {
     if (order == 1)
-      launch_sens_mfma<1>(nelx, nely, nelz, L, rho, u, ndof, nrhs, Kp, E0mEmin, penal, dc, st);
+      launch_sens_mfma<1>(nelx, nely, nelz, 4, L, rho, u, ndof, nrhs, Kp, E0mEmin, penal, dc, st);
     else
-      launch_sens_mfma<2>(nelx, nely, nelz, L, rho, u, ndof, nrhs, Kp, E0mEmin, penal, dc, st);
+      launch_sens_mfma<2>(nelx, nely, nelz, 4, L, rho, u, ndof, nrhs, Kp, E0mEmin, penal, dc, st);
     MGCG_HIP(hipGetLastError());
     return;
   }

@@ -1,69 +1,84 @@
-// Multicolour Gauss-Seidel smoothing on the quadratic finest level.
+// Multicolour Gauss-Seidel smoothing on a quadratic or cubic finest level.
 //
-// Sec. 7.5 smooths quadratic elements by SSOR.  Its sweeps are sequential;
-// here the nodes of the quadratic lattice are coloured by (i mod 3, j mod 3,
-// k mod 3).  Two nodes of one colour are three or more lattice steps apart
-// along some axis, while an element spans two, so they share no element,
-// their rows do not couple, and all nodes of a colour are updated at once
-// from the latest values.  A forward sweep takes colours 0..26 (colour
-// c = ci + 3 cj + 9 ck) and a node's components x, y, z in that order; the
-// backward sweep reverses both.  The result is a Gauss-Seidel sweep
-// (relaxation 1) in that ordering of the DOFs.
+// Sec. 7.5 smooths quadratic and cubic elements by SSOR.  Its sweeps are
+// sequential; here the nodes of the lattice of degree P are coloured by
+// (i mod (P+1), j mod (P+1), k mod (P+1)).  Two nodes of one colour are
+// P + 1 or more lattice steps apart along some axis, while an element spans
+// P, so they share no element, their rows do not couple, and all nodes of a
+// colour are updated at once from the latest values.  A forward sweep takes
+// colours 0 .. (P+1)^3 - 1 (colour c = ci + (P+1) cj + (P+1)^2 ck) and a
+// node's components x, y, z in that order; the backward sweep reverses
+// both.  The result is a Gauss-Seidel sweep (relaxation 1) in that ordering
+// of the DOFs.
 //
-// Thirty-two lanes per node: its 1, 2, 4 or 8 elements' rows of the node (3 x
-// 81 values each, stored by node so that they are contiguous) times the
-// element's 81 values of x, split over the lanes; the three row sums are
-// summed across the group, then one lane updates the node's components in
-// order, each from the sums corrected by the components already updated
-// (with the node's 3x3 diagonal block, precomputed at refresh).  Fixed DOFs
-// (zero rows and columns in the element matrices) are skipped and stay 0.
+// A group of lanes per node (32 for the 27-node element, a wave for the
+// 64-node one): its 1, 2, 4 or 8 elements' rows of the node (3 x ND values
+// each, ND = 81 or 192, stored by node so that they are contiguous) times
+// the element's ND values of x, split over the lanes, one local node per
+// lane; the three row sums are summed across the group, then one lane
+// updates the node's components in order, each from the sums corrected by
+// the components already updated (with the node's 3x3 diagonal block,
+// precomputed at refresh).  Fixed DOFs (zero rows and columns in the element
+// matrices) are skipped and stay 0.
 #include "devutil.h"
 #include "kernels.h"
 
 namespace mgcg {
 
-template <typename T>
+template <int P>
+struct GsShape {
+  static constexpr int M = P + 1;                  // colours per axis
+  static constexpr int NEN = M * M * M;            // nodes per element
+  static constexpr int ND = 3 * NEN;               // DOFs per element
+  static constexpr int LPN = NEN <= 32 ? 32 : 64;  // lanes per node
+};
+constexpr int GS_WAVES = 4;  // waves per block
+
+template <typename T, int P>
 __global__ __launch_bounds__(BS) void k_rows_by_node(const double* __restrict__ Keff, T* Kn,
                                                      long nel) {
-  const long n = nel * 6561;
+  constexpr int ND = GsShape<P>::ND, ND2 = ND * ND;
+  const long n = nel * ND2;
   for (long q = (long)blockIdx.x * BS + threadIdx.x; q < n; q += (long)gridDim.x * BS) {
-    const long e = q / 6561;
-    const int w = (int)(q - e * 6561);
-    const int a = w / 243, rem = w - 243 * a, j = rem / 3, c = rem - 3 * j;
-    Kn[q] = (T)Keff[e * 6561 + (3 * a + c) * 81 + j];
+    const long e = q / ND2;
+    const int w = (int)(q - e * ND2);
+    const int a = w / (3 * ND), rem = w - 3 * ND * a, j = rem / 3, c = rem - 3 * j;
+    Kn[q] = (T)Keff[e * ND2 + (3 * a + c) * ND + j];
   }
 }
 
 template <typename T>
-void setup_rows_by_node(const double* Keff, T* Kn, long nel, hipStream_t st) {
-  long nb = (nel * 6561 + BS - 1) / BS;
+void setup_rows_by_node(int order, const double* Keff, T* Kn, long nel, hipStream_t st) {
+  const int nd = order == 3 ? GsShape<3>::ND : GsShape<2>::ND;
+  long nb = (nel * nd * nd + BS - 1) / BS;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(k_rows_by_node<T>, dim3((int)nb), dim3(BS), 0, st, Keff, Kn, nel);
+  if (order == 3)
+    hipLaunchKernelGGL((k_rows_by_node<T, 3>), dim3((int)nb), dim3(BS), 0, st, Keff, Kn, nel);
+  else
+    hipLaunchKernelGGL((k_rows_by_node<T, 2>), dim3((int)nb), dim3(BS), 0, st, Keff, Kn, nel);
   MGCG_HIP(hipGetLastError());
 }
-template void setup_rows_by_node<double>(const double*, double*, long, hipStream_t);
-template void setup_rows_by_node<float>(const double*, float*, long, hipStream_t);
+template void setup_rows_by_node<double>(int, const double*, double*, long, hipStream_t);
+template void setup_rows_by_node<float>(int, const double*, float*, long, hipStream_t);
 
-constexpr int GS_LPN = 32;     // lanes per node
-constexpr int GS_WAVES = 4;    // waves per block
-constexpr int GS_NPB = GS_WAVES * 64 / GS_LPN;  // nodes per block
-
-// Sum over the lanes of a node's group (every lane of the group gets it).
-template <typename T>
+// Sum over the LPN lanes of a node's group (every lane of the group gets it).
+template <int LPN, typename T>
 __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
-  for (int off = GS_LPN / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, GS_LPN);
+  for (int off = LPN / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LPN);
   return v;
 }
 
-// Elements along one axis that contain node index i of a quadratic lattice
-// with ne elements: the first one and how many (1 or 2).
+// Elements along one axis that contain node index i of a lattice of degree
+// P with ne elements: the first one and how many (1 or 2).
+template <int P>
 __device__ __forceinline__ void gs_axis(int i, int ne, int& e0, int& cnt) {
-  if (i & 1) {
-    e0 = i >> 1;
+  const int q = i / P;
+  if (i - P * q) {
+    e0 = q;
     cnt = 1;
   } else {
-    e0 = (i >> 1) - 1;
+    e0 = q - 1;
     cnt = 2;
     if (e0 < 0) {
       e0 = 0;
@@ -75,16 +90,17 @@ __device__ __forceinline__ void gs_axis(int i, int ne, int& e0, int& cnt) {
 
 // Each node's 3x3 diagonal block, summed over its elements:
 // Dn[node * 9 + 3 c + c'] = A[3 node + c][3 node + c'].
-template <typename T>
+template <typename T, int P>
 __global__ __launch_bounds__(BS) void k_gs_diag(Lat L, const T* __restrict__ Kn, T* Dn) {
+  using S = GsShape<P>;
   const int node = blockIdx.x * BS + threadIdx.x;
   if (node >= (int)L.nn()) return;
   const int i = node % L.nx, j = (node / L.nx) % L.ny, k = node / (L.nx * L.ny);
-  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
+  const int nex = (L.nx - 1) / P, ney = (L.ny - 1) / P, nez = (L.nz - 1) / P;
   int ex0, cx, ey0, cy, ez0, cz;
-  gs_axis(i, nex, ex0, cx);
-  gs_axis(j, ney, ey0, cy);
-  gs_axis(k, nez, ez0, cz);
+  gs_axis<P>(i, nex, ex0, cx);
+  gs_axis<P>(j, ney, ey0, cy);
+  gs_axis<P>(k, nez, ez0, cz);
   T d[9];
 #pragma unroll
   for (int v = 0; v < 9; ++v) d[v] = T(0);
@@ -92,8 +108,8 @@ __global__ __launch_bounds__(BS) void k_gs_diag(Lat L, const T* __restrict__ Kn,
     for (int ey = ey0; ey < ey0 + cy; ++ey)
       for (int ex = ex0; ex < ex0 + cx; ++ex) {
         const int e = ex + nex * (ey + ney * ez);
-        const int an = (i - 2 * ex) + 3 * ((j - 2 * ey) + 3 * (k - 2 * ez));
-        const T* kr = Kn + ((size_t)(e * 27 + an) * 81 + 3 * an) * 3;  // [column c'][row c]
+        const int an = (i - P * ex) + S::M * ((j - P * ey) + S::M * (k - P * ez));
+        const T* kr = Kn + ((size_t)(e * S::NEN + an) * S::ND + 3 * an) * 3;  // [column c'][row c]
 #pragma unroll
         for (int cp = 0; cp < 3; ++cp)
 #pragma unroll
@@ -104,42 +120,46 @@ __global__ __launch_bounds__(BS) void k_gs_diag(Lat L, const T* __restrict__ Kn,
 }
 
 template <typename T>
-void setup_gs_diag(const Lat& L, const T* Kn, T* Dn, hipStream_t st) {
-  hipLaunchKernelGGL(k_gs_diag<T>, dim3(nblocks(L.nn())), dim3(BS), 0, st, L, Kn, Dn);
+void setup_gs_diag(int order, const Lat& L, const T* Kn, T* Dn, hipStream_t st) {
+  if (order == 3)
+    hipLaunchKernelGGL((k_gs_diag<T, 3>), dim3(nblocks(L.nn())), dim3(BS), 0, st, L, Kn, Dn);
+  else
+    hipLaunchKernelGGL((k_gs_diag<T, 2>), dim3(nblocks(L.nn())), dim3(BS), 0, st, L, Kn, Dn);
   MGCG_HIP(hipGetLastError());
 }
-template void setup_gs_diag<double>(const Lat&, const double*, double*, hipStream_t);
-template void setup_gs_diag<float>(const Lat&, const float*, float*, hipStream_t);
+template void setup_gs_diag<double>(int, const Lat&, const double*, double*, hipStream_t);
+template void setup_gs_diag<float>(int, const Lat&, const float*, float*, hipStream_t);
 
-// One colour of a sweep.  A group of GS_LPN = 32 lanes per node.  Lane gl < 27
-// of the group takes the elements' local node aj = gl: for each element of
-// the node (slot (dx, dy, dz), up to 8) a 3x3 block of the node's rows (9
-// contiguous values of Kn) against local node aj's 3 values of x.  The loads
-// of SB slots are issued before their products (all 8 in FP32); slots past
-// the node's elements, and lanes 27..31, read valid data and count 0.
-
-template <typename T, int NR>
+// One colour of a sweep.  Lane gl < NEN of the node's group takes the
+// elements' local node aj = gl: for each element of the node (slot (dx, dy,
+// dz), up to 8) a 3x3 block of the node's rows (9 contiguous values of Kn)
+// against local node aj's 3 values of x.  The loads of SB slots are issued
+// before their products (all 8 in FP32); slots past the node's elements,
+// and lanes past NEN, read valid data and count 0.
+template <typename T, int NR, int P>
 __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_colour(Lat L, const T* __restrict__ Kn,
                                                              const T* __restrict__ Dn,
                                                              const uint8_t* __restrict__ mask,
                                                              const T* __restrict__ b, T* x, int ci,
                                                              int cj, int ck, int backward,
                                                              const CgScalars* cs) {
+  using S = GsShape<P>;
+  constexpr int M = S::M, LPN = S::LPN, NPB = GS_WAVES * 64 / LPN;
   constexpr int SB = sizeof(T) == 4 ? 8 : 4;  // slots per load batch
   const Gate g = gate_load(cs, NR, CG_ACTIVE);
-  const int lane = threadIdx.x & 63, gl = lane & (GS_LPN - 1);
-  const int mx = (L.nx - ci + 2) / 3, my = (L.ny - cj + 2) / 3, mz = (L.nz - ck + 2) / 3;
+  const int lane = threadIdx.x & 63, gl = lane & (LPN - 1);
+  const int mx = (L.nx - ci + M - 1) / M, my = (L.ny - cj + M - 1) / M, mz = (L.nz - ck + M - 1) / M;
   const int nnodes = mx * my * mz;
-  const int q0 = blockIdx.x * GS_NPB + (int)threadIdx.x / GS_LPN;
+  const int q0 = blockIdx.x * NPB + (int)threadIdx.x / LPN;
   const bool live = q0 < nnodes;  // the group's node exists (uniform per group)
   const int q = live ? q0 : 0;
   const int qx = q % mx, qy = (q / mx) % my, qz = q / (mx * my);
-  const int i = ci + 3 * qx, j = cj + 3 * qy, k = ck + 3 * qz;
-  const int nex = (L.nx - 1) / 2, ney = (L.ny - 1) / 2, nez = (L.nz - 1) / 2;
+  const int i = ci + M * qx, j = cj + M * qy, k = ck + M * qz;
+  const int nex = (L.nx - 1) / P, ney = (L.ny - 1) / P, nez = (L.nz - 1) / P;
   int ex0, cx, ey0, cy, ez0, cz;
-  gs_axis(i, nex, ex0, cx);
-  gs_axis(j, ney, ey0, cy);
-  gs_axis(k, nez, ez0, cz);
+  gs_axis<P>(i, nex, ex0, cx);
+  gs_axis<P>(j, ney, ey0, cy);
+  gs_axis<P>(k, nez, ez0, cz);
   const long ndof = L.ndof();
   const int node = i + L.nx * (j + L.ny * k);
   const int sxy = L.nx * L.ny;
@@ -159,9 +179,9 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_colour(Lat L, const T* __r
     m = mask[node];
   }
   // this lane's local node and its offset from an element's first node
-  const bool has = gl < 27;
+  const bool has = gl < S::NEN;
   const int aj = has ? gl : 0;
-  const int offn = aj % 3 + L.nx * ((aj / 3) % 3) + sxy * (aj / 9);
+  const int offn = aj % M + L.nx * ((aj / M) % M) + sxy * (aj / (M * M));
   T acc[NR][3];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -176,9 +196,9 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_colour(Lat L, const T* __r
       const bool sok = dx < cx && dy < cy && dz < cz;
       const int ex = ex0 + (sok ? dx : 0), ey = ey0 + (sok ? dy : 0), ez = ez0 + (sok ? dz : 0);
       const int e = ex + nex * (ey + ney * ez);
-      const int an = (i - 2 * ex) + 3 * ((j - 2 * ey) + 3 * (k - 2 * ez));  // the node in e
-      const int n0 = 2 * ex + L.nx * 2 * ey + sxy * 2 * ez;                  // e's first node
-      const T* kb = Kn + (size_t)(e * 27 + an) * 243;                        // [aj][c'][c]
+      const int an = (i - P * ex) + M * ((j - P * ey) + M * (k - P * ez));  // the node in e
+      const int n0 = P * ex + L.nx * P * ey + sxy * P * ez;                 // e's first node
+      const T* kb = Kn + (size_t)(e * S::NEN + an) * (3 * S::ND);           // [aj][c'][c]
       const T z = (sok && has) ? T(1) : T(0);
       const T* kr = kb + 9 * aj;
 #pragma unroll
@@ -203,7 +223,7 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_colour(Lat L, const T* __r
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[r][c] = group_sum(acc[r][c]);
+    for (int c = 0; c < 3; ++c) acc[r][c] = group_sum<LPN>(acc[r][c]);
   if (!gate_open(g)) return;  // uniform: before the first store
   if (gl == 0 && live) {
 #pragma unroll
@@ -226,28 +246,40 @@ __global__ __launch_bounds__(64 * GS_WAVES) void k_gs_colour(Lat L, const T* __r
   }
 }
 
-template <typename T>
-void v_gauss_seidel(const Lat& L, const T* Kn, const T* Dn, const uint8_t* mask, const T* b, T* x,
-                    bool backward, int nrhs, const CgScalars* cs, hipStream_t st) {
-  auto kern = nrhs == 1   ? k_gs_colour<T, 1>
-              : nrhs == 2 ? k_gs_colour<T, 2>
-              : nrhs == 3 ? k_gs_colour<T, 3>
-                          : k_gs_colour<T, 4>;
-  for (int t = 0; t < 27; ++t) {
-    const int c = backward ? 26 - t : t;
-    const int ci = c % 3, cj = (c / 3) % 3, ck = c / 9;
-    const long nodes = (long)((L.nx - ci + 2) / 3) * ((L.ny - cj + 2) / 3) * ((L.nz - ck + 2) / 3);
+template <typename T, int P>
+static void gs_sweep(const Lat& L, const T* Kn, const T* Dn, const uint8_t* mask, const T* b, T* x,
+                     bool backward, int nrhs, const CgScalars* cs, hipStream_t st) {
+  constexpr int M = P + 1, NC = M * M * M, NPB = GS_WAVES * 64 / GsShape<P>::LPN;
+  auto kern = nrhs == 1   ? k_gs_colour<T, 1, P>
+              : nrhs == 2 ? k_gs_colour<T, 2, P>
+              : nrhs == 3 ? k_gs_colour<T, 3, P>
+                          : k_gs_colour<T, 4, P>;
+  for (int t = 0; t < NC; ++t) {
+    const int c = backward ? NC - 1 - t : t;
+    const int ci = c % M, cj = (c / M) % M, ck = c / (M * M);
+    const long nodes = (long)((L.nx - ci + M - 1) / M) * ((L.ny - cj + M - 1) / M) *
+                       ((L.nz - ck + M - 1) / M);
     if (nodes == 0) continue;
-    const int nb = (int)((nodes + GS_NPB - 1) / GS_NPB);
+    const int nb = (int)((nodes + NPB - 1) / NPB);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(64 * GS_WAVES), 0, st, L, Kn, Dn, mask, b, x, ci, cj,
                        ck, backward ? 1 : 0, cs);
     MGCG_HIP(hipGetLastError());
   }
 }
-template void v_gauss_seidel<double>(const Lat&, const double*, const double*, const uint8_t*,
+
+template <typename T>
+void v_gauss_seidel(int order, const Lat& L, const T* Kn, const T* Dn, const uint8_t* mask,
+                    const T* b, T* x, bool backward, int nrhs, const CgScalars* cs,
+                    hipStream_t st) {
+  if (order == 3)
+    gs_sweep<T, 3>(L, Kn, Dn, mask, b, x, backward, nrhs, cs, st);
+  else
+    gs_sweep<T, 2>(L, Kn, Dn, mask, b, x, backward, nrhs, cs, st);
+}
+template void v_gauss_seidel<double>(int, const Lat&, const double*, const double*, const uint8_t*,
                                      const double*, double*, bool, int, const CgScalars*,
                                      hipStream_t);
-template void v_gauss_seidel<float>(const Lat&, const float*, const float*, const uint8_t*,
+template void v_gauss_seidel<float>(int, const Lat&, const float*, const float*, const uint8_t*,
                                     const float*, float*, bool, int, const CgScalars*, hipStream_t);
 
 }  // namespace mgcg

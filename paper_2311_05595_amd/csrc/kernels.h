@@ -58,13 +58,33 @@ __host__ __device__ inline int s2_node(int k) {
     if (mid <= 1 && ++m == k) return a;
   }
 }
+// Tricubic elements on the cubic node lattice (nx = 3*nelx + 1, ...): the
+// 64-node element's 192 DOFs, or the 32-node serendipity element's 96, by
+// wrapped diagonals s = 0..N/2 (N the DOF count; the diagonal s = N/2 holds
+// each of its values twice).
+constexpr int L3_ND = 192, S3_ND = 96;
+constexpr int L3_PACKED = (L3_ND / 2 + 1) * L3_ND;
+constexpr int S3_PACKED = (S3_ND / 2 + 1) * S3_ND;
+// Node of the 64-node layout (a = ax + 4 ay + 16 az) of serendipity node k
+// (0..31, in increasing a): the vertices and the edges' third-points, those
+// with at most one local index inside the edge (1 or 2).
+__host__ __device__ inline int s3_node(int k) {
+  int a = 0;
+  for (int m = -1;; ++a) {
+    const int ax = a % 4, ay = (a / 4) % 4, az = a / 16;
+    const int in = (ax == 1 || ax == 2) + (ay == 1 || ay == 2) + (az == 1 || az == 2);
+    if (in <= 1 && ++m == k) return a;
+  }
+}
+// Stored element matrices of degree p = 2 or 3 (OP_EQ2 / OP_EQ3).
 template <typename T>
 struct OpEQ2 {
   Lat L;
   const T* Ke;
   const uint8_t* mask;
-  T* Y;  // element products K_e u_e, [load case][element][81] (scratch of the apply)
-  int s2;  // serendipity elements: Ke holds S2_PACKED values per element
+  T* Y;  // element products K_e u_e, [load case][element][3 (p+1)^3] (scratch of the apply)
+  int s2;  // serendipity elements: Ke holds S2_PACKED (S3_PACKED) values per element
+  int p;   // element degree
 };
 
 // Reduction scratch: one partial sum per block and value, in regions that
@@ -158,19 +178,21 @@ struct VOps {
 template <typename T>
 void v_prepare0(const double* r, T* b0, const T* wD, T* x0, long ndof, int nrhs,
                 const CgScalars* cs, hipStream_t st);
-// One multicolour Gauss-Seidel sweep (relaxation 1) in place on the
-// quadratic finest level: 27 launches, one per node colour (lattice indices
-// mod 3), colours and a node's components in increasing order, or both
-// reversed (backward).  Kn: element rows by node (setup_rows_by_node).
+// One multicolour Gauss-Seidel sweep (relaxation 1) in place on a finest
+// level of degree order = 2 or 3: (order+1)^3 launches, one per node colour
+// (lattice indices mod order + 1), colours and a node's components in
+// increasing order, or both reversed (backward).  Kn: element rows by node
+// (setup_rows_by_node).
 template <typename T>
-void v_gauss_seidel(const Lat& L, const T* Kn, const T* Dn, const uint8_t* mask, const T* b, T* x,
-                    bool backward, int nrhs, const CgScalars* cs, hipStream_t st);
-// Kn[((e * 27 + a) * 81 + j) * 3 + c] = Keff[e][3a + c][j] in precision T.
+void v_gauss_seidel(int order, const Lat& L, const T* Kn, const T* Dn, const uint8_t* mask,
+                    const T* b, T* x, bool backward, int nrhs, const CgScalars* cs, hipStream_t st);
+// Kn[((e * NEN + a) * ND + j) * 3 + c] = Keff[e][3a + c][j] in precision T
+// (NEN = (order+1)^3 nodes, ND = 3 NEN DOFs per element).
 template <typename T>
-void setup_rows_by_node(const double* Keff, T* Kn, long nel, hipStream_t st);
+void setup_rows_by_node(int order, const double* Keff, T* Kn, long nel, hipStream_t st);
 // Dn[node * 9 + 3 c + c'] = the node's 3x3 diagonal block, summed over its elements.
 template <typename T>
-void setup_gs_diag(const Lat& L, const T* Kn, T* Dn, hipStream_t st);
+void setup_gs_diag(int order, const Lat& L, const T* Kn, T* Dn, hipStream_t st);
 // xo = x + omega invD (b - A x)
 template <typename T>
 void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs,
@@ -236,12 +258,17 @@ template <typename T>
 void setup_pack_q2(const double* K, T* D, long nel, hipStream_t st);
 template <typename T>
 void setup_pack_s2(const double* K, T* D, long nel, hipStream_t st);
+// Full symmetric 192x192 element matrices K[e] -> wrapped diagonals of the
+// 64-node element (serendipity = 0) or of the 32-node one's 96 DOFs.
+template <typename T>
+void setup_pack_e3(const double* K, T* D, long nel, int serendipity, hipStream_t st);
 void setup_effective(int order, int nsub, int nelx, int nely, int nelz, const double* E,
                      const double* Ksub, const uint8_t* mask, Lat L, double* Keff, hipStream_t st);
 // Galerkin coarse element matrices (24x24 Q1-type) of a coarse element grid.
 //  src kind OP_MF_Q1: children are E_c * K0 (child mask applied here);
 //  OP_ST27 (Q1-type elements with stored matrices Kc [nel_f][576], masks baked or applied);
-//  OP_EQ2: each coarse element is one quadratic fine element (81x81 -> 24x24).
+//  OP_EQ2: each coarse element is one quadratic fine element (81x81 -> 24x24);
+//  OP_EQ3: each coarse element is one cubic fine element (192x192 -> 24x24).
 // elist (optional): ids of the coarse elements to compute (count n_elist);
 // null computes all of them.
 void setup_galerkin(int src_kind, Lat fine, const double* E, const double* K0, const double* Kc,
@@ -250,7 +277,7 @@ void setup_galerkin(int src_kind, Lat fine, const double* E, const double* K0, c
 // First coarse level as a linear combination of precomputed matrices:
 // KE[e] = sum_m E[dens(e, m)] G[m], m over the B^3 density cells of a coarse
 // element (B = 2 nsub for trilinear children, nsub for one quadratic
-// element); valid where no child DOF is supported.
+// element of degree 2 or 3); valid where no child DOF is supported.
 void setup_galerkin_lin(const double* E, const double* G, int B, int nsub, int nelx, int nely,
                         int ncx, int ncy, int ncz, double* KE, hipStream_t st);
 // Assemble Q1-type element matrices into the half stencil, with the supports
@@ -266,6 +293,9 @@ void setup_diag_mf(Lat L, const double* E, const double* K0, const uint8_t* mask
 template <typename T>
 void setup_diag_eq2(Lat L, const double* Ke, const uint8_t* mask, T* wD, double* diag64,
                     double omega, double theta, hipStream_t st);
+template <typename T>
+void setup_diag_e3(Lat L, const double* Ke, const uint8_t* mask, T* wD, double* diag64,
+                   double omega, double theta, hipStream_t st);
 // Coarsest level: the dense operator over all of the level's DOFs (row
 // stride ld, a multiple of GJ_B; identity rows/columns at fixed DOFs and in
 // the padding) from its element matrices, and its inverse by blocked
@@ -283,12 +313,13 @@ double* setup_coarse_inverse(double* A, double* B, double* D, double* diag0, int
 // Compliance and sensitivity.
 void comp_dot(const double* f, const double* u, long ndof, int nrhs, double* out, RedBuf red,
               hipStream_t st);
-// dc/drho (Sec. 3.4); Kp: the packed form of Ksub for 4^3 sub-elements
-// (sens_pack: sens_packed_doubles(order) values), or null.
+// dc/drho (Sec. 3.4); Kp: the packed form of Ksub (sens_pack:
+// sens_packed_doubles(order) values) for 4^3 sub-elements, and for cubic
+// elements with any nsub; else null.
 long sens_packed_doubles(int order);
-// Ksub [64][nd][nd] -> the packed sub-element matrices of the sensitivity
-// contraction and their pair table.
-void sens_pack(int order, const double* Ksub, std::vector<double>& out);
+// Ksub [n^3][nd][nd] (n^3 <= 64) -> the packed sub-element matrices of the
+// sensitivity contraction (zero columns past n^3) and their pair table.
+void sens_pack(int order, int nsub, const double* Ksub, std::vector<double>& out);
 void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const double* rho,
                  const double* u, long ndof, int nrhs, const double* Ksub, const double* Kp,
                  double E0mEmin, double penal, double* dc, hipStream_t st);

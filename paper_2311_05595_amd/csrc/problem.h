@@ -13,7 +13,7 @@ namespace mgcg {
 
 struct LevelPlan {
   Lat L;
-  int kind;          // OP_MF_Q1 / OP_ST27 / OP_EQ2
+  int kind;          // OP_MF_Q1 / OP_ST27 / OP_EQ2 / OP_EQ3
   int ncx, ncy, ncz; // element grid of the level
 };
 

@@ -33,7 +33,7 @@ struct Arena {
 void validate(const mgcg_desc& d) {
   auto bad = [](const char* m) { throw Error(MGCG_EINVAL, m); };
   if (d.nelx < 1 || d.nely < 1 || d.nelz < 1) bad("element counts must be >= 1");
-  if (d.order != 1 && d.order != 2) bad("order must be 1 or 2");
+  if (d.order < 1 || d.order > 3) bad("order must be 1, 2 or 3");
   if (d.nsub < 1 || d.nsub > 4) bad("nsub must be 1..4");
   if (d.nlevels < 1 || d.nlevels > 12) bad("nlevels must be 1..12");
   if (d.nrhs < 1 || d.nrhs > 4) bad("nrhs must be 1..4");
@@ -43,11 +43,11 @@ void validate(const mgcg_desc& d) {
   if (!(d.E0 > 0.0) || !(d.Emin >= 0.0) || !(d.Emin < d.E0)) bad("need E0 > Emin >= 0");
   if (!(d.nu > -1.0 && d.nu < 0.5)) bad("nu must be in (-1, 0.5)");
   if (!(d.penal >= 1.0 && d.penal <= 10.0)) bad("penal must be in [1, 10]");
-  if (d.order == 2 && d.nlevels < 2) bad("quadratic elements need nlevels >= 2");
-  if (d.family != MGCG_LAGRANGE && !(d.family == MGCG_SERENDIPITY && d.order == 2))
-    bad("family must be Lagrange, or serendipity with order 2");
-  if (d.smoother != MGCG_SMOOTH_JACOBI && !(d.smoother == MGCG_SMOOTH_GAUSS_SEIDEL && d.order == 2))
-    bad("smoother must be Jacobi, or Gauss-Seidel with order 2");
+  if (d.order >= 2 && d.nlevels < 2) bad("quadratic and cubic elements need nlevels >= 2");
+  if (d.family != MGCG_LAGRANGE && !(d.family == MGCG_SERENDIPITY && d.order >= 2))
+    bad("family must be Lagrange, or serendipity with order 2 or 3");
+  if (d.smoother != MGCG_SMOOTH_JACOBI && !(d.smoother == MGCG_SMOOTH_GAUSS_SEIDEL && d.order >= 2))
+    bad("smoother must be Jacobi, or Gauss-Seidel with order 2 or 3");
 }
 
 }  // namespace
@@ -59,14 +59,14 @@ void Problem::plan_levels(const mgcg_desc& d, std::vector<LevelPlan>& lv) {
   LevelPlan l0;
   const int p = d.order;
   l0.L = Lat{p * d.nelx + 1, p * d.nely + 1, p * d.nelz + 1};
-  l0.kind = d.order == 2 ? OP_EQ2 : (d.nsub == 1 ? OP_MF_Q1 : OP_ST27);
+  l0.kind = d.order == 3 ? OP_EQ3 : d.order == 2 ? OP_EQ2 : (d.nsub == 1 ? OP_MF_Q1 : OP_ST27);
   l0.ncx = d.nelx;
   l0.ncy = d.nely;
   l0.ncz = d.nelz;
   lv.push_back(l0);
   int cx = d.nelx, cy = d.nely, cz = d.nelz;
   for (int l = 1; l < d.nlevels; ++l) {
-    if (!(l == 1 && d.order == 2)) {
+    if (!(l == 1 && d.order >= 2)) {  // degree >= 2: first onto the vertex lattice
       if (cx % 2 || cy % 2 || cz % 2)
         throw Error(MGCG_EINVAL, "too many levels: element counts must be even to coarsen");
       cx /= 2;
@@ -107,7 +107,7 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   const long nel0 = (long)d.nelx * d.nely * d.nelz;
   const long ns3 = (long)d.nsub * d.nsub * d.nsub;
   const long nrho = nel0 * ns3;
-  const int ndl = d.order == 1 ? 24 : 81;
+  const int ndl = 3 * (d.order + 1) * (d.order + 1) * (d.order + 1);
   const int L = (int)lv.size();
 #define TAKE(member, T, n)          \
   do {                              \
@@ -119,7 +119,7 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   TAKE(E_, double, nrho);
   if (mixed && lv[0].kind == OP_MF_Q1) TAKE(E32_, float, nrho);
   TAKE(Ksub_, double, ns3 * ndl * ndl);
-  if (d.nsub == 4) TAKE(Kp_, double, sens_packed_doubles(d.order));
+  if (d.nsub == 4 || d.order == 3) TAKE(Kp_, double, sens_packed_doubles(d.order));
   TAKE(K0_, double, 576);
   if (mixed) TAKE(K032_, float, 576);
   TAKE(x_, double, R * nd0);
@@ -134,6 +134,17 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   TAKE(bad_, int, 4);
   TAKE(dcbuf_, double, nrho);
   if (lv[0].kind == OP_ST27) TAKE(Keff_, double, nel0 * 576);
+  if (lv[0].kind == OP_EQ3) {
+    const long pk = d.family == MGCG_SERENDIPITY ? S3_PACKED : L3_PACKED;
+    TAKE(Keff_, double, nel0 * L3_ND * L3_ND);  // full matrices (setup)
+    TAKE(Kq2_, double, nel0 * pk);              // wrapped diagonals (applies)
+    if (mixed) TAKE(Keff32_, float, nel0 * pk);
+    TAKE(Yeq_, double, R * nel0 * L3_ND);
+    if (d.smoother == MGCG_SMOOTH_GAUSS_SEIDEL) {
+      TAKE(Kn_, char, nel0 * L3_ND * L3_ND * (mixed ? sizeof(float) : sizeof(double)));
+      TAKE(Dn_, char, lv[0].L.nn() * 9 * (mixed ? sizeof(float) : sizeof(double)));
+    }
+  }
   if (lv[0].kind == OP_EQ2) {
     TAKE(Keff_, double, nel0 * 6561);           // full matrices (setup)
     TAKE(Kq2_, double, nel0 * Q2_PACKED);       // wrapped diagonals (applies)
@@ -185,7 +196,7 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
     if (b) b->r = cv;
   }
   if (L >= 2) {
-    const int B = d.order == 2 ? d.nsub : 2 * d.nsub;
+    const int B = d.order >= 2 ? d.nsub : 2 * d.nsub;
     TAKE(G_, double, (size_t)B * B * B * 576);
     TAKE(dmasked_, int, (long)lv[1].ncx * lv[1].ncy * lv[1].ncz);
   }
@@ -230,16 +241,20 @@ Problem::Problem(const mgcg_desc& d, const uint8_t* mask, const double* f, int d
     hmask_[n] = m;
   }
   if (d_.family == MGCG_SERENDIPITY) {
-    // face and body centres of the 27-node lattice (two or three odd indices)
+    // face- and body-interior nodes of the lattice (two or three indices
+    // off the vertex lattice)
     const Lat L0 = lv_[0].L;
+    const int p = d_.order;
     for (long n = 0; n < L0.nn(); ++n) {
       const long i = n % L0.nx, j = (n / L0.nx) % L0.ny, k = n / ((long)L0.nx * L0.ny);
-      if ((i & 1) + (j & 1) + (k & 1) >= 2) hmask_[n] = 7;
+      if ((i % p != 0) + (j % p != 0) + (k % p != 0) >= 2) hmask_[n] = 7;
     }
   }
   for (size_t l = 1; l < lv_.size(); ++l) {
     const Lat F = lv_[l - 1].L, C = lv_[l].L;
-    const int stride = 2;  // both Q1 halving and the Q2 -> vertex lattice step
+    // Q1 halving and the Q2 -> vertex lattice step take every second node,
+    // the cubic -> vertex lattice step every third
+    const int stride = (l == 1 && d_.order == 3) ? 3 : 2;
     for (int k = 0; k < C.nz; ++k)
       for (int j = 0; j < C.ny; ++j)
         for (int i = 0; i < C.nx; ++i) {
@@ -383,7 +398,7 @@ void Problem::allocate() {
   MGCG_HIP(hipMemcpyAsync(f_, hf_.data(), hf_.size() * sizeof(double), hipMemcpyHostToDevice, stream_));
   if (Kp_) {
     // the 64 sub-element matrices packed for the sensitivity contraction
-    sens_pack(d_.order, hKsub_.data(), hKp_);
+    sens_pack(d_.order, d_.nsub, hKsub_.data(), hKp_);
     MGCG_HIP(hipMemcpyAsync(Kp_, hKp_.data(), hKp_.size() * sizeof(double), hipMemcpyHostToDevice,
                             stream_));
   }
@@ -420,7 +435,7 @@ void Problem::sync() { MGCG_HIP(hipStreamSynchronize(stream_)); }
 // explicit masked product.
 void Problem::build_linear_galerkin() {
   const int n = d_.nsub, p = d_.order;
-  const bool q2 = p == 2;
+  const bool q2 = p >= 2;  // one fine element of degree p per coarse element
   const int B = q2 ? n : 2 * n;
   gB_ = B;
   const int p1 = p + 1, nen = p1 * p1 * p1, nd = 3 * nen;
@@ -435,7 +450,7 @@ void Problem::build_linear_galerkin() {
     for (int a = 0; a < nen; ++a) {
       const int ax = a % p1, ay = (a / p1) % p1, az = a / (p1 * p1);
       for (int b = 0; b < 8; ++b)
-        W[(size_t)a * 8 + b] = q2 ? trilinear_weight(ax, ay, az, b)
+        W[(size_t)a * 8 + b] = q2 ? trilinear_weight(ax, ay, az, b, p)
                                   : trilinear_weight(cx + ax, cy + ay, cz + az, b);
     }
     double* G = &hG_[(size_t)m * 576];
@@ -456,18 +471,20 @@ void Problem::build_linear_galerkin() {
             G[(3 * b + i) * 24 + 3 * b2 + j] = s;
           }
   }
-  // coarse elements whose fine nodes (lattice 2E..2E+2) carry a support
+  // coarse elements whose fine nodes (lattice rE..rE+r, r = 3 for cubic
+  // elements, else 2) carry a support
   const Lat F = lv_[0].L;
   const LevelPlan& c1 = lv_[1];
+  const int r = p == 3 ? 3 : 2;
   hmasked_.clear();
   for (int EZ = 0; EZ < c1.ncz; ++EZ)
     for (int EY = 0; EY < c1.ncy; ++EY)
       for (int EX = 0; EX < c1.ncx; ++EX) {
         bool any = false;
-        for (int dz = 0; dz <= 2 && !any; ++dz)
-          for (int dy = 0; dy <= 2 && !any; ++dy)
-            for (int dx = 0; dx <= 2 && !any; ++dx) {
-              const long fn = (2 * EX + dx) + (long)F.nx * ((2 * EY + dy) + (long)F.ny * (2 * EZ + dz));
+        for (int dz = 0; dz <= r && !any; ++dz)
+          for (int dy = 0; dy <= r && !any; ++dy)
+            for (int dx = 0; dx <= r && !any; ++dx) {
+              const long fn = (r * EX + dx) + (long)F.nx * ((r * EY + dy) + (long)F.ny * (r * EZ + dz));
               if (hmask_[fn]) any = true;
             }
         if (any) hmasked_.push_back(EX + c1.ncx * (EY + c1.ncy * EZ));
@@ -487,7 +504,7 @@ FineOp Problem::fine_op() const {
   const Lat L = lv_[0].L;
   A.mf = OpMF<double>::make(L, E_, hv64_, B_[0].mask);
   A.st = OpST<double>{L, vbytes_ == 8 ? (const double*)B_[0].coefV : B_[0].coef64};
-  A.eq2 = OpEQ2<double>{L, Kq2_, B_[0].mask, Yeq_, d_.family == MGCG_SERENDIPITY};
+  A.eq2 = OpEQ2<double>{L, Kq2_, B_[0].mask, Yeq_, d_.family == MGCG_SERENDIPITY, d_.order};
   return A;
 }
 
@@ -500,10 +517,10 @@ VOps<T> Problem::vops(int l) const {
   v.invD = (const T*)B_[l].invD;
   if constexpr (sizeof(T) == 8) {
     v.mf = OpMF<T>::make(v.L, E_, hv64_, B_[l].mask);
-    v.eq2 = OpEQ2<T>{v.L, Kq2_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY};
+    v.eq2 = OpEQ2<T>{v.L, Kq2_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY, d_.order};
   } else {
     v.mf = OpMF<T>::make(v.L, E32_, hv32_, B_[l].mask);
-    v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY};
+    v.eq2 = OpEQ2<T>{v.L, Keff32_, B_[l].mask, (T*)Yeq_, d_.family == MGCG_SERENDIPITY, d_.order};
   }
   v.st = OpST<T>{v.L, (const T*)B_[l].coefV};
   return v;
@@ -588,6 +605,19 @@ void Problem::do_set_densities() {
                               B_[0].diag64, d_.omega, kTheta, st);
       }
       break;
+    case OP_EQ3: {
+      const long nel0 = (long)d_.nelx * d_.nely * d_.nelz;
+      const int ser = d_.family == MGCG_SERENDIPITY;
+      setup_effective(3, d_.nsub, d_.nelx, d_.nely, d_.nelz, E_, Ksub_, B_[0].mask, L0, Keff_, st);
+      setup_diag_e3<T>(L0, Keff_, B_[0].mask, (T*)B_[0].invD, B_[0].diag64, d_.omega, kTheta, st);
+      setup_pack_e3<double>(Keff_, Kq2_, nel0, ser, st);
+      if (mixed) setup_pack_e3<float>(Keff_, Keff32_, nel0, ser, st);
+      if (Kn_) {
+        setup_rows_by_node<T>(3, Keff_, (T*)Kn_, nel0, st);
+        setup_gs_diag<T>(3, L0, (const T*)Kn_, (T*)Dn_, st);
+      }
+      break;
+    }
     default:
       setup_effective(2, d_.nsub, d_.nelx, d_.nely, d_.nelz, E_, Ksub_, B_[0].mask, L0, Keff_, st);
       setup_diag_eq2<T>(L0, Keff_, B_[0].mask, (T*)B_[0].invD, B_[0].diag64, d_.omega, kTheta, st);
@@ -601,8 +631,8 @@ void Problem::do_set_densities() {
           if (mixed) setup_pack_q2<float>(Keff_, Keff32_, nel0, st);
         }
         if (Kn_) {
-          setup_rows_by_node<T>(Keff_, (T*)Kn_, nel0, st);
-          setup_gs_diag<T>(L0, (const T*)Kn_, (T*)Dn_, st);
+          setup_rows_by_node<T>(2, Keff_, (T*)Kn_, nel0, st);
+          setup_gs_diag<T>(2, L0, (const T*)Kn_, (T*)Dn_, st);
         }
       }
       break;
@@ -645,8 +675,9 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
   } else {
     b0 = (const T*)B_[0].b;
   }
-  // a small coarsest level takes the last restriction inside its solve
-  const bool fuse_cs = L > 1 && lv_[L - 1].L.ndof() <= CS_FUSE_MAX;
+  // a small coarsest level takes the last (halving) restriction inside its
+  // solve
+  const bool fuse_cs = L > 1 && lv_[L - 1].L.ndof() <= CS_FUSE_MAX && !(L == 2 && d_.order == 3);
   std::vector<T*> cur(L), oth(L);
   std::vector<const T*> bl(L);
   bl[0] = b0;
@@ -674,8 +705,8 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
     T* rl = (T*)B_[l].r;
     if (l == 0 && gs0) {
       for (int s = 0; s < d_.pre; ++s)
-        v_gauss_seidel<T>(lv_[0].L, (const T*)Kn_, (const T*)Dn_, B_[0].mask, bl[0], cur[0], false, R,
-                          cs, st);
+        v_gauss_seidel<T>(d_.order, lv_[0].L, (const T*)Kn_, (const T*)Dn_, B_[0].mask, bl[0], cur[0],
+                          false, R, cs, st);
     } else {
       for (int s = 1; s < d_.pre; ++s) {
         v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
@@ -709,8 +740,8 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
                    cs, st);
     if (l == 0 && gs0) {
       for (int s = 0; s < d_.post; ++s)
-        v_gauss_seidel<T>(lv_[0].L, (const T*)Kn_, (const T*)Dn_, B_[0].mask, bl[0], cur[0], true, R,
-                          cs, st);
+        v_gauss_seidel<T>(d_.order, lv_[0].L, (const T*)Kn_, (const T*)Dn_, B_[0].mask, bl[0], cur[0],
+                          true, R, cs, st);
       continue;
     }
     for (int s = 0; s < d_.post; ++s) {

@@ -42,10 +42,20 @@ def test_desc_validation_and_sizes():
     # odd element counts cannot be coarsened
     assert api.device_bytes(nel=(3, 2, 2), nlevels=2) == 0
     assert api.device_bytes(nel=(24, 12, 12), nrhs=5) == 0
-    assert api.device_bytes(nel=(24, 12, 12), order=3) == 0
+    assert api.device_bytes(nel=(24, 12, 12), order=4) == 0
     assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=1) == 0
-    # the serendipity family is quadratic only
+    assert api.device_bytes(nel=(4, 2, 2), order=3, nlevels=1) == 0
+    # cubic elements: 192x192 element matrices (full, packed, by node for the
+    # Gauss-Seidel smoother) and the packed sensitivity table for any nsub
+    b3 = api.device_bytes(nel=(4, 2, 2), order=3, nlevels=2)
+    assert b3 > 16 * 192 * 192 * 8
+    assert api.device_bytes(nel=(4, 2, 2), order=3, nlevels=3) > 0
+    assert api.device_bytes(nel=(4, 2, 2), order=3, nlevels=2, smoother="gauss-seidel") >= \
+        b3 + 16 * 192 * 192 * 8
+    # the serendipity family has degree 2 or 3
     assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2, family="serendipity") > 0
+    s3 = api.device_bytes(nel=(4, 2, 2), order=3, nlevels=2, family="serendipity")
+    assert 0 < s3 < b3
     assert api.device_bytes(nel=(4, 2, 2), order=1, nlevels=2, family="serendipity") == 0
     assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2, family=2) == 0
     # bytes grow with precision, nrhs and nsub
@@ -53,7 +63,7 @@ def test_desc_validation_and_sizes():
     b2 = api.device_bytes(nel=(32, 16, 16), nlevels=3, nrhs=2)
     assert b2 > b64
     assert api.device_bytes(nel=(32, 16, 16), nlevels=3, nsub=2) > b64
-    # the Gauss-Seidel smoother needs quadratic elements
+    # the Gauss-Seidel smoother needs quadratic or cubic elements
     assert api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2, smoother="gauss-seidel") > \
         api.device_bytes(nel=(4, 2, 2), order=2, nlevels=2)
     assert api.device_bytes(nel=(4, 2, 2), order=1, nlevels=2, smoother="gauss-seidel") == 0

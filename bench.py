@@ -17,8 +17,11 @@ Prints one JSON line.  Besides the contract's keys:
   iterations it needed to 1e-8), on one host thread, with the host's CPU;
 * `served`: the served mix (the fifth workload) on the FP64 and the mixed
   path, at the frozen Poisson rate and at capacity (`--no-served` skips it).
-`--config c1|c3|c4|c4s` times the other single-GPU workloads the same way
-(not the default line; no served legs), `--config c5` the served mix alone.
+`--config c1|c3|c4|c4s|c6|c6s` times the other single-GPU workloads the
+same way (not the default line; no served legs), `--config c5` the served
+mix alone.  `--launch fused` runs each solve as one launch (a workgroup per
+load case; small trilinear FP64 workloads such as c1), then without the
+per-kernel roofline.
 `--copy-probe MIB` only runs the library's plain copy kernel on MIB MiB
 (the calibration run for the HBM byte counters) and exits.
 
@@ -135,7 +138,10 @@ def fine_apply_model(nel, nsub, order, nrhs=1, family="lagrange"):
     * triquadratic (stored symmetric 81x81 element matrices): bytes: the
       3321 distinct coefficients per element, read p, write q.  Bound: HBM.
     * quadratic serendipity (stored symmetric 60x60 element matrices): the
-      1830 distinct coefficients per element, read p, write q.  Bound: HBM."""
+      1830 distinct coefficients per element, read p, write q.  Bound: HBM.
+    * tricubic (stored symmetric 192x192 element matrices, or 96x96 for the
+      32-node serendipity element): the 18528 (4656) distinct coefficients
+      per element, read p, write q.  Bound: HBM."""
     nx, ny, nz = nel
     nelem = nx * ny * nz
     nn = (order * nx + 1) * (order * ny + 1) * (order * nz + 1)
@@ -150,6 +156,15 @@ def fine_apply_model(nel, nsub, order, nrhs=1, family="lagrange"):
                     kernel="finest-level CG apply q = A p, 27-point stencil (FP64)",
                     per_unit="126 x 8 B of coefficients per node + 48 B of vectors per node "
                              "and load case")
+    if order == 3:
+        nd = 96 if family == "serendipity" else 192
+        kc = nd * (nd + 1) // 2
+        what = "serendipity " if family == "serendipity" else ""
+        return dict(bound="hbm", flops=2.0 * nd * nd * nelem * nrhs, bytes=vec + 8.0 * kc * nelem,
+                    kernel=f"finest-level CG apply q = A p, stored symmetric {nd}x{nd} {what}"
+                           "element matrices (FP64)",
+                    per_unit=f"{kc} x 8 B of element matrix (distinct entries) per element + 48 B "
+                             "of vectors per node and load case")
     if family == "serendipity":
         return dict(bound="hbm", flops=2.0 * 3600 * nelem * nrhs, bytes=vec + 8.0 * 1830 * nelem,
                     kernel="finest-level CG apply q = A p, stored symmetric 60x60 serendipity "
@@ -161,6 +176,57 @@ def fine_apply_model(nel, nsub, order, nrhs=1, family="lagrange"):
                        "(FP64)",
                 per_unit="3321 x 8 B of element matrix (distinct entries) per element + 48 B of "
                          "vectors per node and load case")
+
+
+def batch_bench(args):
+    """Many small problems (the c1 workload's mesh and settings, each with its
+    own seeded density field): every step refreshes all of them and solves
+    them warm-started to 1e-8, either one after another on the eager path or
+    all in one fused launch (mgcg_solve_batch, a workgroup per problem); the
+    solves are timed, the refreshes before them are not.  Prints one JSON
+    line with both rates; not the default line."""
+    import torch
+    import workloads as W
+    from workloads import configs as CF
+    from paper_2311_05595_amd import api
+    cfg = CF.config("c1")
+    mask, f = CF.problem(cfg)
+    n = args.batch
+    fields = [[W.perturb(W.uniform_field(cfg["nel"][::-1], 100 + i), 9000 + 31 * i + k)
+               for k in range(3)] for i in range(n)]
+    probs = [api.Problem(cfg["nel"], mask, f, nlevels=cfg["nlevels"], omega=cfg["omega"])
+             for _ in range(n)]
+    out = {"metric": "batched small-problem MGCG solves/s at 1e-8 rel. residual",
+           "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": cfg["name"] + f", {n} problems with their own seeded "
+                      "densities, warm-started", "problems": n, "steps": args.steps}}
+    for mode in ("eager", "fused"):
+        for p in probs:
+            p.set_launch_mode(mode)
+        iters = []
+
+        def step(k):
+            # the refresh of every problem, then the timed solves
+            for i, p in enumerate(probs):
+                p.set_densities(fields[i][k % 3].ravel())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "fused":
+                infos = api.solve_batch(probs, rtol=1e-8, maxit=2000, warm_start=k > 0)
+            else:
+                infos = [p.solve(rtol=1e-8, maxit=2000, warm_start=k > 0) for p in probs]
+            torch.cuda.synchronize()
+            iters.extend(i["iters"][0] for i in infos)
+            return time.perf_counter() - t0
+        step(0)
+        iters.clear()
+        el = sum(step(k) for k in range(1, args.steps + 1))
+        out[mode] = {"solves_s": round(n * args.steps / el, 2), "ms_per_step": round(el / args.steps * 1e3, 3),
+                     "pcg_iters_mean": round(float(np.mean(iters)), 2)}
+    out["value"] = out["fused"]["solves_s"]
+    for p in probs:
+        p.close()
+    print(json.dumps(out), flush=True)
 
 
 def apply_sweep(args):
@@ -232,7 +298,7 @@ def oracle_reference(cfg, rho, rtol_ref=1e-12, max_iters=400, budget_s=60.0):
     nel, order, nsub = cfg["nel"], cfg["order"], cfg["nsub"]
     family = cfg.get("family", "lagrange")
     if family == "serendipity":
-        mask = np.maximum(mask, fem.serendipity_dof_mask(nel))
+        mask = np.maximum(mask, fem.serendipity_dof_mask(nel, order))
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         Ks = fem.sub_element_matrices(order, nsub, family=family)
@@ -321,6 +387,7 @@ def run(args):
                        omega=cfg["omega"], pre=cfg["pre"], post=cfg["post"],
                        family=cfg.get("family", "lagrange"), smoother=smoother)
     prob.use_torch_stream()
+    prob.set_launch_mode(args.launch)
     dc = torch.empty(prob.nrho, dtype=torch.float64, device=dev)
     free = int((mask == 0).sum()) * prob.nrhs
     # cold solve of the base design (the optimisation's first iteration)
@@ -336,7 +403,9 @@ def run(args):
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
-    prob.set_kernel_timing(0, True)
+    # (kernel timing launches eagerly: a fused solve is timed whole)
+    timed = args.launch != "fused"
+    prob.set_kernel_timing(0, timed)
     lat, iters, statuses = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -359,7 +428,8 @@ def run(args):
     else:
         achieved, peak, unit = m["bytes"] / avg_s / 1e9, PEAK_HBM_GBS, "GB/s"
     traffic = committed_traffic() if cfg["name"] == CF.config("c2")["name"] else None
-    roofline = {"bound": m["bound"], "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+    roofline = None if not timed else {
+                "bound": m["bound"], "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": m["kernel"], "per_unit": m["per_unit"],
                 "avg_us": round(avg_s * 1e6, 3), "launches": kn,
@@ -379,7 +449,7 @@ def run(args):
         "config": {"workload": cfg["name"] + ", warm-started over 10 seeded +-0.05 density "
                    "perturbations; step = refresh + solve + compliance/sensitivity",
                    "nel": list(cfg["nel"]), "free_dof": free, "levels": cfg["nlevels"],
-                   "rtol": args.rtol, "smoother": smoother},
+                   "rtol": args.rtol, "smoother": smoother, "launch": args.launch},
         "dof_cg_iter_per_s": round(free * sum(iters) / elapsed, 1),
         "pcg_iters_mean": round(float(np.mean(iters)), 2),
         "p50_ms": round(lat_s[len(lat_s) // 2], 3),
@@ -905,6 +975,9 @@ def main():
     ap.add_argument("--smoother", default=None, choices=[None, "jacobi", "gauss-seidel"],
                     help="finest-level smoother (default: the workload's)")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--launch", default="eager", choices=["eager", "graph", "fused"],
+                    help="how the solve is launched (fused: one launch per solve, small "
+                         "trilinear FP64 workloads only; no per-kernel roofline then)")
     ap.add_argument("--maxit", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=60.0,
@@ -919,6 +992,9 @@ def main():
                     help="time the choice of fixed variables before the degree is raised")
     ap.add_argument("--threshold", action="store_true",
                     help="time the density thresholding and the Heaviside projection")
+    ap.add_argument("--batch", type=int, default=0, metavar="N",
+                    help="time N small (c1) problems solved eagerly one by one and in one "
+                         "fused multi-problem launch")
     ap.add_argument("--apply-sweep", action="store_true",
                     help="time the matrix-free CG apply on lattices of 0.7M to 8.6M DOF")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")
@@ -932,6 +1008,9 @@ def main():
         return
     if args.apply_sweep:
         apply_sweep(args)
+        return
+    if args.batch:
+        batch_bench(args)
         return
     if args.fixing:
         if args.gpus != 1:

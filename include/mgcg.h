@@ -178,10 +178,19 @@ int mgcg_get_stream(mgcg_problem* p, void** stream);
  * iteration, a HIP graph of its kernel launches (no memset or copy nodes),
  * built at the first chunk after allocation.  Same kernels, same arguments,
  * same results (on one MI355X the replay was not faster: the host keeps
- * ahead of the GPU either way).  Kernel timing (mgcg_set_kernel_timing)
- * always launches eagerly.  MGCG_EINVAL for another mode. */
+ * ahead of the GPU either way).  MGCG_LAUNCH_FUSED runs each mgcg_solve as
+ * one launch in which a single workgroup per load case does the whole PCG
+ * solve (Sec. 2.3, V-cycle of Algorithm 1 included) between workgroup
+ * barriers: for small problems, whose kernels cost their launch and ramp
+ * more than their work.  It needs trilinear elements with nsub = 1, FP64,
+ * the Jacobi smoother, 2..8 levels, at most 6000 finest-level nodes and at
+ * most 1024 coarsest DOFs (MGCG_EINVAL otherwise); the same iteration in
+ * another summation order, so results agree with the other modes to
+ * rounding.  The serving loop (mgcg_server_*) always launches eagerly, and
+ * so does a solve while kernel timing is on.  MGCG_EINVAL for another mode. */
 #define MGCG_LAUNCH_EAGER 0
 #define MGCG_LAUNCH_GRAPH 1
+#define MGCG_LAUNCH_FUSED 2
 int mgcg_set_launch_mode(mgcg_problem* p, int mode);
 
 /* Allocate the device hierarchy now (otherwise done on first use). */
@@ -215,6 +224,20 @@ int mgcg_set_densities_f32(mgcg_problem* p, const float* rho, int mem);
 #define MGCG_WARM_SCALED 1
 #define MGCG_WARM_PLAIN 2
 int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_info* info);
+
+/* Several small problems solved in one launch (batched multi-problem
+ * solve): every problem must fit MGCG_LAUNCH_FUSED (see above; its launch
+ * mode need not be set) and have its densities set, and all must live on
+ * one device; a workgroup per load case of every problem runs its whole
+ * PCG solve, so up to one problem per compute unit progresses at once.
+ * The launch goes on ps[0]'s stream after the work already enqueued on
+ * every problem's stream, and every problem's stream waits for it; the call
+ * returns when all are done.  infos (may be NULL) receives n results, in
+ * the order of ps.  Returns MGCG_OK, or the first problem's error status
+ * (MGCG_ENOTCONV, MGCG_EBREAKDOWN, ...) in ps order; MGCG_EINVAL for a
+ * problem that does not fit, n < 1 or mixed devices. */
+int mgcg_solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm_start,
+                     mgcg_info* infos);
 
 /* u[nrhs*ndof] FP64 (zero on fixed DOFs). */
 int mgcg_get_displacement(mgcg_problem* p, double* u, int mem);

@@ -94,6 +94,8 @@ EXPORTS = {
     "mgcg_problem_create_in": (C.c_int, [C.c_void_p, C.POINTER(mgcg_desc), C.c_void_p,
                                          C.c_void_p, C.POINTER(C.c_void_p)]),
     "mgcg_solve": (C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_int, C.POINTER(mgcg_info)]),
+    "mgcg_solve_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_double, C.c_int, C.c_int,
+                                   C.POINTER(mgcg_info)]),
     "mgcg_get_displacement": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mgcg_set_initial_guess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
     "mgcg_compliance_sensitivity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),

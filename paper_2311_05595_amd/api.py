@@ -85,6 +85,21 @@ def _info(i):
                 replacements=i.replacements, t_setup_ms=i.t_setup_ms, t_solve_ms=i.t_solve_ms)
 
 
+def solve_batch(problems, rtol=1e-8, maxit=1000, warm_start=True, allow_notconv=False):
+    """Solve several small problems in one launch (mgcg_solve_batch): each
+    must fit the fused solve and have its densities set.  Returns their info
+    dicts in order."""
+    problems = list(problems)
+    if not problems:
+        return []
+    lib = problems[0]._lib
+    hs = (C.c_void_p * len(problems))(*[p._h.value for p in problems])
+    infos = (mgcg_info * len(problems))()
+    allow = (MGCG_OK, MGCG_ENOTCONV) if allow_notconv else (MGCG_OK,)
+    check(lib.mgcg_solve_batch(hs, len(problems), rtol, maxit, _warm(warm_start), infos), allow)
+    return [_info(i) for i in infos]
+
+
 _FAMILY = {"lagrange": 0, "serendipity": 1}
 
 
@@ -188,8 +203,10 @@ class Problem:
         self.set_stream(_torch().cuda.current_stream().cuda_stream)
 
     def set_launch_mode(self, mode):
-        """"graph" (replay one captured PCG iteration) or "eager"."""
-        check(self._lib.mgcg_set_launch_mode(self._h, {"eager": 0, "graph": 1}[mode]))
+        """"eager", "graph" (replay one captured PCG iteration) or "fused"
+        (the whole solve in one launch, a workgroup per load case; small
+        trilinear FP64 problems only)."""
+        check(self._lib.mgcg_set_launch_mode(self._h, {"eager": 0, "graph": 1, "fused": 2}[mode]))
 
     def stream(self):
         """The hipStream_t (int) the problem's work runs on."""

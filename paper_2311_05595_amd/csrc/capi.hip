@@ -21,6 +21,7 @@ const char* get_error() { return g_err.c_str(); }
 
 using mgcg::Error;
 using mgcg::Problem;
+using mgcg::FzDesc;
 
 #define GUARD(body)                                 \
   try {                                             \
@@ -219,6 +220,86 @@ int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_inf
     return MGCG_EINVAL;
   }
   GUARD({ return p->impl->solve(rtol, maxit, warm_start, info); })
+}
+
+namespace {
+// One descriptor table per device, grown as needed and kept; batches share
+// it, so they run one at a time.
+struct BatchTable {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_batch_mu;
+std::vector<BatchTable> g_batch_tables;
+
+int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm_start,
+                mgcg_info* infos) {
+  std::lock_guard<std::mutex> g(g_batch_mu);
+  Problem* p0 = ps[0]->impl;
+  const int dev = p0->device();
+  for (int i = 0; i < n; ++i) {
+    if (ps[i]->impl->device() != dev) throw Error(MGCG_EINVAL, "batched problems must share a device");
+    if (!ps[i]->impl->fused_ok())
+      throw Error(MGCG_EINVAL, "a batched problem does not fit the fused solve");
+  }
+  MGCG_HIP(hipSetDevice(dev));
+  std::vector<FzDesc> all, one;
+  for (int i = 0; i < n; ++i) {
+    ps[i]->impl->fused_prepare(rtol, maxit, warm_start, one);
+    all.insert(all.end(), one.begin(), one.end());
+  }
+  if ((int)g_batch_tables.size() <= dev) g_batch_tables.resize(dev + 1);
+  BatchTable& tb = g_batch_tables[dev];
+  const size_t bytes = all.size() * sizeof(FzDesc);
+  hipStream_t st = p0->ensure_stream();
+  if (tb.bytes < bytes) {
+    if (tb.ptr) {
+      MGCG_HIP(hipDeviceSynchronize());
+      MGCG_HIP(hipFree(tb.ptr));
+      tb = BatchTable{};
+    }
+    MGCG_HIP(hipMalloc(&tb.ptr, bytes));
+    tb.bytes = bytes;
+  }
+  // the launch follows the work already on every problem's stream
+  std::vector<hipEvent_t> evs;
+  for (int i = 1; i < n; ++i) {
+    hipEvent_t e;
+    MGCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    evs.push_back(e);
+    MGCG_HIP(hipEventRecord(e, ps[i]->impl->ensure_stream()));
+    MGCG_HIP(hipStreamWaitEvent(st, e, 0));
+  }
+  MGCG_HIP(hipMemcpyAsync(tb.ptr, all.data(), bytes, hipMemcpyHostToDevice, st));
+  mgcg::fused_solve(static_cast<const FzDesc*>(tb.ptr), (int)all.size(), st);
+  hipEvent_t done;
+  MGCG_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+  MGCG_HIP(hipEventRecord(done, st));
+  for (int i = 1; i < n; ++i) MGCG_HIP(hipStreamWaitEvent(ps[i]->impl->stream(), done, 0));
+  int status = MGCG_OK;
+  for (int i = 0; i < n; ++i) {
+    const int si = ps[i]->impl->fused_finish(infos ? &infos[i] : nullptr);
+    if (status == MGCG_OK && si != MGCG_OK) status = si;
+  }
+  for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(done);
+  return status;
+}
+}  // namespace
+
+int mgcg_solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm_start,
+                     mgcg_info* infos) {
+  NEED(ps);
+  if (n < 1) {
+    mgcg::set_error("need n >= 1 problems");
+    return MGCG_EINVAL;
+  }
+  if (warm_start < MGCG_COLD || warm_start > MGCG_WARM_PLAIN) {
+    mgcg::set_error("warm_start must be MGCG_COLD, MGCG_WARM_SCALED or MGCG_WARM_PLAIN");
+    return MGCG_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) NEED(ps[i]);
+  GUARD({ return solve_batch(ps, n, rtol, maxit, warm_start, infos); })
 }
 
 int mgcg_get_displacement(mgcg_problem* p, double* u, int mem) {

@@ -2366,3 +2366,446 @@ void cg_reset(CgScalars* cs, int nrhs, double rtol2, int maxit, int replace_ever
 }
 
 }  // namespace mgcg
+
+namespace mgcg {
+
+// ------------------------------------------------------------ fused small solves
+// A whole PCG solve (Sec. 2.3: CG preconditioned by Algorithm 1) of one load
+// case of a small trilinear problem in one workgroup: every operator, the
+// V-cycle's levels, the coarsest inverse and the CG recurrences run between
+// workgroup barriers instead of kernel boundaries, and one launch takes
+// several problems and load cases, a workgroup each.  For meshes whose
+// kernels are too small to fill the chip, where the cost of a kernel is its
+// launch, ramp and drain (about 5 us), not its work.
+//
+// Finest level: matrix-free trilinear elements in their Haar basis
+// (haar_element), the element products added into LDS accumulators of
+// every node in 8 colour phases (elements of one colour, the parities of
+// their indices, share no node), so no atomics are needed and the sums
+// have a fixed order.  Coarse levels: the Galerkin stencils (ax_st_part).
+// Coarsest: the explicit inverse, a wave per row.  Dot products: fixed-order
+// workgroup sums.  The recurrences follow the device-gated CG: the
+// recurrence residual triggers a check of the true residual; a check that
+// fails replaces r and restarts the direction; three checks without a 10 %
+// decrease end the solve.
+constexpr int FZ_T = 512;
+constexpr int FZ_W = FZ_T / 64;
+
+__device__ __forceinline__ double fz_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < FZ_W; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// acc = K u on the finest level (before masking), in LDS.  A thread walks
+// its elements colour by colour (a barrier after each colour) and loads the
+// next element's 24 values and modulus before it computes the current one.
+__device__ __attribute__((noinline)) void fz_mf_apply(const FzDesc& d, const double* __restrict__ u,
+                                                      double* acc) {
+  const Lat L = d.lv[0].L;
+  const int nn = (int)L.nn();
+  for (int t = threadIdx.x; t < 3 * nn; t += FZ_T) acc[t] = 0.0;
+  __syncthreads();
+  const int ex1 = L.nx - 1, ey1 = L.ny - 1, ez1 = L.nz - 1;
+  const int P = L.nx * L.ny;
+  const int tid = threadIdx.x;
+  auto count = [&](int col) {  // this thread's elements of colour col
+    const int cx = col & 1, cy = (col >> 1) & 1, cz = col >> 2;
+    const int ne = ((ex1 - cx + 1) / 2) * ((ey1 - cy + 1) / 2) * ((ez1 - cz + 1) / 2);
+    return ne > tid ? (ne - tid + FZ_T - 1) / FZ_T : 0;
+  };
+  auto advance = [&](int& col, int& k) {
+    ++k;
+    while (col < 8 && k >= count(col)) {
+      ++col;
+      k = 0;
+    }
+  };
+  struct Item {
+    double v[24];  // bottom face nodes (i, j), (i+1, j), (i, j+1), (i+1, j+1), then the top face
+    double E;
+    int n0;
+  };
+  auto load = [&](int col, int k, Item& it) {
+    const int cx = col & 1, cy = (col >> 1) & 1, cz = col >> 2;
+    const int mx = (ex1 - cx + 1) / 2, my = (ey1 - cy + 1) / 2;
+    const int q = tid + k * FZ_T;
+    const int ex = cx + 2 * (q % mx), ey = cy + 2 * ((q / mx) % my), ez = cz + 2 * (q / (mx * my));
+    it.n0 = ex + L.nx * ey + P * ez;
+    it.E = d.E[ex + ex1 * (ey + ey1 * ez)];
+#pragma unroll
+    for (int zz = 0; zz < 2; ++zz)
+#pragma unroll
+      for (int cn = 0; cn < 4; ++cn) {
+        const int nb = it.n0 + zz * P + (cn & 1) + L.nx * (cn >> 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) it.v[12 * zz + 3 * cn + c] = u[3 * nb + c];
+      }
+  };
+  auto compute = [&](const Item& it) {
+    // 2-D Haar transforms of the two faces (q = mx + 2 my)
+    double fb[3][4], ft[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      {
+        const double u00 = it.v[c], u10 = it.v[3 + c], u01 = it.v[6 + c], u11 = it.v[9 + c];
+        const double a = u00 + u10, b = u10 - u00, cc = u01 + u11, dd = u11 - u01;
+        fb[c][0] = a + cc;
+        fb[c][1] = b + dd;
+        fb[c][2] = cc - a;
+        fb[c][3] = dd - b;
+      }
+      {
+        const double u00 = it.v[12 + c], u10 = it.v[15 + c], u01 = it.v[18 + c], u11 = it.v[21 + c];
+        const double a = u00 + u10, b = u10 - u00, cc = u01 + u11, dd = u11 - u01;
+        ft[c][0] = a + cc;
+        ft[c][1] = b + dd;
+        ft[c][2] = cc - a;
+        ft[c][3] = dd - b;
+      }
+    }
+    double gb[3][4], gt[3][4];
+    haar_element<double>(d.hv, fb, ft, it.E, gb, gt);
+#pragma unroll
+    for (int cn = 0; cn < 4; ++cn) {
+      const int nb = it.n0 + (cn & 1) + L.nx * (cn >> 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[3 * nb + c] += gb[c][cn];
+        acc[3 * (nb + P) + c] += gt[c][cn];
+      }
+    }
+  };
+  Item cur, nxt;
+  int pc = 0, pk = -1;
+  advance(pc, pk);
+  if (pc < 8) load(pc, pk, cur);
+  for (int col = 0; col < 8; ++col) {
+    const int n = count(col);
+    for (int k = 0; k < n; ++k) {
+      int nc = col, nk = k;
+      advance(nc, nk);
+      if (nc < 8) load(nc, nk, nxt);
+      compute(cur);
+      cur = nxt;
+    }
+    __syncthreads();
+  }
+}
+
+// Level-wide steps of the V-cycle, each its own (not inlined) function so
+// that the register budget of each is its own.
+#define FZ_STEP __device__ __attribute__((noinline))
+
+// y = A_l u (b null) or y = b - A_l u on a stencil level (identity rows
+// baked into the stencil).
+FZ_STEP void fz_st_apply(const FzLevel& lv, const double* u, const double* b, double* y) {
+  const int nn = (int)lv.L.nn();
+  const OpST<double> op{lv.L, lv.coef};
+  const InPlain<double> in{u, lv.L.ndof()};
+  for (int t = threadIdx.x; t < nn; t += FZ_T) {
+    int i, j, k;
+    node_ijk(t, lv.L, i, j, k);
+    // the 14 stored blocks two at a time (blocks part and part + 7), so that
+    // 48 values are in flight rather than all 336
+    double a[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int part = 0; part < 7; ++part) {
+      double ap[3];
+      ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, part, ap);
+      for (int c = 0; c < 3; ++c) a[c] += ap[c];
+    }
+    for (int c = 0; c < 3; ++c) y[3 * t + c] = b ? b[3 * t + c] - a[c] : a[c];
+  }
+  __syncthreads();
+}
+
+// b_c = R r_f (0 on fixed coarse DOFs); x_c = W D^-1 b_c when x is given.
+FZ_STEP void fz_restrict(const FzLevel& fl, const FzLevel& cl, double* b, double* x) {
+  const int nd = (int)cl.L.ndof();
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(fl.r, (size_t)fl.L.ndof() * sizeof(double));
+  for (int t = threadIdx.x; t < nd; t += FZ_T) {
+    const int node = t / 3, c = t - 3 * node;
+    int I, J, K;
+    node_ijk(node, cl.L, I, J, K);
+    const double bv = ((cl.mask[node] >> c) & 1) ? 0.0 : restrict_at<double>(fl.L, rf, I, J, K, c);
+    b[t] = bv;
+    if (x) x[t] = cl.wD[t] * bv;
+  }
+  __syncthreads();
+}
+
+// x_f += P x_c on the free fine DOFs.
+FZ_STEP void fz_prolong_add(const FzLevel& fl, const FzLevel& cl) {
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(cl.x, (size_t)cl.L.ndof() * sizeof(double));
+  for (int t = threadIdx.x; t < (int)fl.L.nn(); t += FZ_T) {
+    int i, j, k;
+    node_ijk(t, fl.L, i, j, k);
+    double pe[3];
+    prolong_at<double>(cl.L, re, i, j, k, true, pe);
+    const int m = fl.mask[t];
+    for (int c = 0; c < 3; ++c)
+      if (!((m >> c) & 1)) fl.x[3 * t + c] += pe[c];
+  }
+  __syncthreads();
+}
+
+// x = A_c^-1 b (b in LDS): a wave takes 8 rows at a time, the lanes split
+// the columns, and all of a lane's loads for the 8 rows (columns lane,
+// lane + 64, ...) are issued before the sums (past the row: offsets out of
+// range read 0).
+FZ_STEP void fz_coarse(const FzDesc& d, const FzLevel& cl, const double* sbc) {
+  constexpr int RB = 8, CB = FZ_MAX_COARSE / 64;
+  const int nd = (int)cl.L.ndof();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(d.Ainv, (size_t)d.ld * d.ld * sizeof(double));
+  const int ncb = (nd + 63) / 64;
+  for (int r0 = wid * RB; r0 < nd; r0 += FZ_W * RB) {
+    double s[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) s[q] = 0.0;
+    for (int cb = 0; cb < ncb; cb += 4) {
+      double a[4][RB], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = (cb + u) * 64 + lane;
+        const bool okc = c < nd;
+        bv[u] = okc ? sbc[c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const int row = r0 + q;
+          const int off = (okc && row < nd) ? (row * d.ld + c) * (int)sizeof(double) : kBufOOB;
+          a[u][q] = bload<double>(ra, off, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < RB; ++q) s[q] = fma(a[u][q], bv[u], s[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const double t = wave_sum(s[q]);
+      if (lane == 0 && r0 + q < nd) cl.x[r0 + q] = t;
+    }
+  }
+  (void)CB;
+  __syncthreads();
+}
+
+// x += W D^-1 (b - t) over a level's DOFs (t: A x, or b - A x when bt)
+FZ_STEP void fz_jacobi_update(const FzLevel& lv, const double* b, const double* t, bool fine,
+                              const double* acc) {
+  const int nd = (int)lv.L.ndof();
+  for (int q = threadIdx.x; q < nd; q += FZ_T) {
+    double ax;
+    if (fine)
+      ax = ((lv.mask[q / 3] >> (q % 3)) & 1) ? 0.0 : acc[q];
+    else
+      ax = t[q];
+    lv.x[q] += lv.wD[q] * (b[q] - ax);
+  }
+  __syncthreads();
+}
+
+// z = M r (Algorithm 1, V-cycle from a zero guess) into lv[0].x; r: the
+// level-0 residual (zero on fixed DOFs).
+FZ_STEP void fz_vcycle(const FzDesc& d, const double* r, double* acc, double* sbc) {
+  const int L = d.nlev;
+  const FzLevel& l0 = d.lv[0];
+  {
+    const int nd = (int)l0.L.ndof();
+    for (int t = threadIdx.x; t < nd; t += FZ_T) l0.x[t] = l0.wD[t] * r[t];
+    __syncthreads();
+    for (int s = 1; s < d.pre; ++s) {
+      fz_mf_apply(d, l0.x, acc);
+      fz_jacobi_update(l0, r, nullptr, true, acc);
+    }
+    fz_mf_apply(d, l0.x, acc);
+    for (int t = threadIdx.x; t < nd; t += FZ_T) {
+      const bool fx = (l0.mask[t / 3] >> (t % 3)) & 1;
+      l0.r[t] = fx ? 0.0 : r[t] - acc[t];
+    }
+    __syncthreads();
+  }
+  for (int l = 1; l < L; ++l) {
+    const FzLevel& fl = d.lv[l - 1];
+    const FzLevel& cl = d.lv[l];
+    if (l == L - 1) {
+      fz_restrict(fl, cl, sbc, nullptr);
+      fz_coarse(d, cl, sbc);
+      break;
+    }
+    fz_restrict(fl, cl, cl.b, cl.x);
+    for (int s = 1; s < d.pre; ++s) {
+      fz_st_apply(cl, cl.x, nullptr, cl.r);
+      fz_jacobi_update(cl, cl.b, cl.r, false, nullptr);
+    }
+    fz_st_apply(cl, cl.x, cl.b, cl.r);
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const FzLevel& fl = d.lv[l];
+    fz_prolong_add(fl, d.lv[l + 1]);
+    for (int s = 0; s < d.post; ++s) {
+      if (l == 0) {
+        fz_mf_apply(d, fl.x, acc);
+        fz_jacobi_update(fl, r, nullptr, true, acc);
+      } else {
+        fz_st_apply(fl, fl.x, nullptr, fl.r);
+        fz_jacobi_update(fl, fl.b, fl.r, false, nullptr);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(FZ_T) void k_fused_pcg(const FzDesc* __restrict__ descs) {
+  __shared__ double acc[3 * FZ_MAX_NODES];
+  __shared__ double sbc[FZ_MAX_COARSE];
+  __shared__ double sh[FZ_W];
+  // the descriptor in LDS: read there, it cannot alias the vectors written
+  __shared__ FzDesc sd;
+  {
+    const int* src = reinterpret_cast<const int*>(descs + blockIdx.x);
+    int* dst = reinterpret_cast<int*>(&sd);
+    for (int t = threadIdx.x; t < (int)(sizeof(FzDesc) / sizeof(int)); t += FZ_T) dst[t] = src[t];
+    __syncthreads();
+  }
+  const FzDesc& d = sd;
+  const int nd = (int)d.lv[0].L.ndof();
+  const uint8_t* mask = d.lv[0].mask;
+  double* x = d.x;
+  double* r = d.r;
+  double* p = d.p;
+  const double* f = d.f;
+  const double* z = d.lv[0].x;
+  auto fixed = [&](int t) { return (bool)((mask[t / 3] >> (t % 3)) & 1); };
+  // true residual r = f - A x into r; returns ||r||^2
+  auto true_residual = [&]() {
+    fz_mf_apply(d, x, acc);
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nd; t += FZ_T) {
+      const double v = fixed(t) ? 0.0 : f[t] - acc[t];
+      r[t] = v;
+      s = fma(v, v, s);
+    }
+    return fz_sum(s, sh);
+  };
+  double sf = 0.0;
+  for (int t = threadIdx.x; t < nd; t += FZ_T) sf = fma(f[t], f[t], sf);
+  const double ff = fz_sum(sf, sh);
+  const double tol2 = d.tol2 * ff;
+  double rr = true_residual();
+  if (d.scale_warm) {
+    // x <- a x with a = f.x / x.K x, x.K x = x.(f - r)
+    double s0 = 0.0, s1 = 0.0;
+    for (int t = threadIdx.x; t < nd; t += FZ_T) {
+      s0 = fma(f[t], x[t], s0);
+      s1 = fma(x[t], f[t] - r[t], s1);
+    }
+    const double fx = fz_sum(s0, sh), xkx = fz_sum(s1, sh);
+    if (xkx > 0.0 && isfinite(fx / xkx)) {
+      const double a = fx / xkx;
+      double s = 0.0;
+      for (int t = threadIdx.x; t < nd; t += FZ_T) {
+        x[t] *= a;
+        const double v = (1.0 - a) * f[t] + a * r[t];
+        r[t] = v;
+        s = fma(v, v, s);
+      }
+      rr = fz_sum(s, sh);
+    }
+  }
+  int state = CG_ACTIVE, it = 0, repl = 0, stall = 0;
+  double rr_best = rr;
+  if (!(rr <= tol2)) {
+    fz_vcycle(d, r, acc, sbc);
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nd; t += FZ_T) {
+      p[t] = z[t];
+      s = fma(r[t], z[t], s);
+    }
+    double rz = fz_sum(s, sh);
+    bool restart = false;
+    while (true) {
+      if (it >= d.maxit) {
+        state = CG_MAXIT;
+        break;
+      }
+      fz_mf_apply(d, p, acc);
+      double spq = 0.0;
+      for (int t = threadIdx.x; t < nd; t += FZ_T) spq = fma(p[t], fixed(t) ? 0.0 : acc[t], spq);
+      const double pq = fz_sum(spq, sh);
+      if (!(pq > 0.0) || !isfinite(rz)) {
+        state = CG_BREAKDOWN;
+        break;
+      }
+      const double alpha = rz / pq;
+      double srr = 0.0;
+      for (int t = threadIdx.x; t < nd; t += FZ_T) {
+        x[t] = fma(alpha, p[t], x[t]);
+        const double v = r[t] - alpha * (fixed(t) ? 0.0 : acc[t]);
+        r[t] = v;
+        srr = fma(v, v, srr);
+      }
+      rr = fz_sum(srr, sh);
+      ++it;
+      if (!isfinite(rr)) {
+        state = CG_BREAKDOWN;
+        break;
+      }
+      if (rr <= tol2) {
+        const double rt = true_residual();
+        if (rt <= tol2) {
+          rr = rt;
+          state = CG_DONE;
+          break;
+        }
+        ++repl;
+        restart = true;
+        if (rt < 0.81 * rr_best) {
+          rr_best = rt;
+          stall = 0;
+        } else if (++stall >= 3) {
+          rr = rt;
+          state = CG_MAXIT;
+          break;
+        }
+        rr = rt;
+      }
+      fz_vcycle(d, r, acc, sbc);
+      double srz = 0.0;
+      for (int t = threadIdx.x; t < nd; t += FZ_T) srz = fma(r[t], z[t], srz);
+      const double rzn = fz_sum(srz, sh);
+      const double beta = restart ? 0.0 : rzn / rz;
+      restart = false;
+      for (int t = threadIdx.x; t < nd; t += FZ_T) p[t] = fma(beta, p[t], z[t]);
+      __syncthreads();
+      rz = rzn;
+    }
+  } else {
+    state = CG_DONE;
+  }
+  if (threadIdx.x == 0) {
+    CgScalars& c = *d.cs;
+    c.ff = ff;
+    c.tol2 = tol2;
+    c.rr = rr;
+    c.iters = it;
+    c.state = state;
+    c.replacements = repl;
+  }
+}
+
+void fused_solve(const FzDesc* descs, int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fused_pcg, dim3(n), dim3(FZ_T), 0, st, descs);
+  MGCG_HIP(hipGetLastError());
+}
+
+}  // namespace mgcg

@@ -324,6 +324,42 @@ void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const
                  const double* u, long ndof, int nrhs, const double* Ksub, const double* Kp,
                  double E0mEmin, double penal, double* dc, hipStream_t st);
 
+// ---------------- fused small solves ----------------
+// One workgroup runs a whole PCG solve of one load case: trilinear
+// matrix-free finest level (nsub = 1) of at most FZ_MAX_NODES nodes (its
+// node sums live in LDS), stencil levels below, a coarsest level of at most
+// FZ_MAX_COARSE DOFs, FP64, Jacobi smoothing.  Vectors are the load case's
+// slices of the problem's own buffers.
+constexpr int FZ_MAXLEV = 8;
+constexpr int FZ_MAX_NODES = 6000;
+constexpr int FZ_MAX_COARSE = 1024;
+struct FzLevel {
+  Lat L;
+  const double* coef;  // stencil (levels >= 1)
+  const double* wD;    // W D^-1, 0 on fixed DOFs
+  const uint8_t* mask;
+  double* b;
+  double* x;
+  double* r;
+};
+struct FzDesc {
+  FzLevel lv[FZ_MAXLEV];
+  int nlev, pre, post, maxit;
+  int scale_warm;  // 1: start from x scaled by f.x / x.K x
+  double tol2;  // rtol^2 (scaled by ||f||^2 on the device)
+  const double* E;
+  Q1HaarVals<double> hv;
+  const double* Ainv;
+  int ld;
+  const double* f;
+  double* x;
+  double* r;
+  double* p;
+  CgScalars* cs;
+};
+// descs: n device descriptors, one workgroup each.
+void fused_solve(const FzDesc* descs, int n, hipStream_t st);
+
 // Timing-free plain copy (for traffic calibration).
 void copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t st);
 

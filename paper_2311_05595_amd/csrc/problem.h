@@ -125,8 +125,19 @@ class Problem {
 
   // MGCG_LAUNCH_GRAPH: the PCG iterations of a chunk replay one captured
   // iteration (a HIP graph of its kernels); MGCG_LAUNCH_EAGER: launched one
-  // by one (always while kernel timing is on).
+  // by one (always while kernel timing is on); MGCG_LAUNCH_FUSED: the whole
+  // solve in one launch, a workgroup per load case (fused_ok problems only).
   void set_launch_mode(int mode);
+  int launch_mode() const { return launch_mode_; }
+  // The problem fits the fused solve (trilinear nsub = 1, FP64, Jacobi, its
+  // finest and coarsest levels within the workgroup's LDS).
+  static bool fused_ok(const mgcg_desc& d, const std::vector<LevelPlan>& lv);
+  bool fused_ok() const { return fused_ok(d_, lv_); }
+  // Host descriptors of the fused solve of every load case (after
+  // fused_prepare, which also zeroes x for a cold start).
+  void fused_prepare(double rtol, int maxit, int warm, std::vector<FzDesc>& out);
+  // Bookkeeping after a fused solve ran on the device (scalars copied back).
+  int fused_finish(mgcg_info* info);
   void set_timing(bool on, int kernel = 0);
   void get_timing(int kernel, double* ms, long long* launches);
   void copy(const void* src, void* dst, size_t bytes);
@@ -150,6 +161,7 @@ class Problem {
   template <typename T> void do_set_densities();
   template <typename T> void do_apply_v(int level, const double* x, double* y);
   void iteration();
+  int solve_fused(double rtol, int maxit, int warm, mgcg_info* info);
   void build_iter_graph();
   void drop_iter_graph();
   void build_linear_galerkin();
@@ -215,6 +227,7 @@ class Problem {
   double* dcbuf_ = nullptr;  // [n_rho] sensitivity staging for host output
   void* zbuf_ = nullptr;     // level-0 V-cycle output of the last cycle
   CgScalars* hcs_ = nullptr; // pinned host copy
+  FzDesc* fz_ = nullptr;     // fused solve: one descriptor per load case (fused_ok problems)
 
   int nc_ = 0;
   bool have_ops_ = false;

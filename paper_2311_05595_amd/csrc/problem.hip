@@ -129,6 +129,7 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   TAKE(rold_, double, R * nd0);
   TAKE(tmp64_, double, R * nd0);
   TAKE(cs_, CgScalars, 4);
+  if (fused_ok(d, lv)) TAKE(fz_, FzDesc, R);
   TAKE(red_.partials, double, (size_t)RED_NREGIONS * RED_REGION);
   TAKE(compout_, double, 16);
   TAKE(bad_, int, 4);
@@ -890,9 +891,84 @@ void Problem::drop_iter_graph() {
 }
 
 void Problem::set_launch_mode(int mode) {
-  if (mode != MGCG_LAUNCH_EAGER && mode != MGCG_LAUNCH_GRAPH)
-    throw Error(MGCG_EINVAL, "launch mode must be MGCG_LAUNCH_EAGER or MGCG_LAUNCH_GRAPH");
+  if (mode != MGCG_LAUNCH_EAGER && mode != MGCG_LAUNCH_GRAPH && mode != MGCG_LAUNCH_FUSED)
+    throw Error(MGCG_EINVAL,
+                "launch mode must be MGCG_LAUNCH_EAGER, MGCG_LAUNCH_GRAPH or MGCG_LAUNCH_FUSED");
+  if (mode == MGCG_LAUNCH_FUSED && !fused_ok())
+    throw Error(MGCG_EINVAL,
+                "the fused solve needs trilinear elements with nsub = 1, FP64, the Jacobi smoother, "
+                "2..8 levels, at most 6000 finest-level nodes and 1024 coarsest DOFs");
   launch_mode_ = mode;
+}
+
+// ------------------------------------------------------------------ fused solve
+bool Problem::fused_ok(const mgcg_desc& d, const std::vector<LevelPlan>& lv) {
+  if (d.order != 1 || d.nsub != 1 || d.precision != MGCG_FP64 || d.smoother != MGCG_SMOOTH_JACOBI)
+    return false;
+  if (lv.size() < 2 || lv.size() > (size_t)FZ_MAXLEV) return false;
+  return lv[0].kind == OP_MF_Q1 && lv[0].L.nn() <= FZ_MAX_NODES &&
+         lv.back().L.ndof() <= FZ_MAX_COARSE;
+}
+
+void Problem::fused_prepare(double rtol, int maxit, int warm, std::vector<FzDesc>& out) {
+  if (!have_ops_) throw Error(MGCG_ESTATE, "set_densities must precede solve");
+  if (!(rtol > 0.0) || maxit < 1) throw Error(MGCG_EINVAL, "need rtol > 0 and maxit >= 1");
+  if (!fz_) throw Error(MGCG_EINVAL, "this problem does not fit the fused solve");
+  MGCG_HIP(hipSetDevice(device_));
+  const long nd = lv_[0].L.ndof();
+  const int R = d_.nrhs, L = (int)lv_.size();
+  rtol_ = rtol;
+  maxit_ = maxit;
+  t0_ = std::chrono::steady_clock::now();
+  const bool from_u = warm != MGCG_COLD && have_u_;
+  if (!from_u) fill<double>(x_, 0.0, R * nd, stream_);
+  timer_used_base_ = timer_.used;
+  out.assign(R, FzDesc{});
+  for (int r = 0; r < R; ++r) {
+    FzDesc& z = out[r];
+    z.nlev = L;
+    z.pre = d_.pre;
+    z.post = d_.post;
+    z.maxit = maxit;
+    z.scale_warm = from_u && warm == MGCG_WARM_SCALED ? 1 : 0;
+    z.tol2 = rtol * rtol;
+    z.E = E_;
+    z.hv = hv64_;
+    z.Ainv = Ainv_;
+    z.ld = coarse_ld(lv_.back().L.ndof());
+    z.f = f_ + r * nd;
+    z.x = x_ + r * nd;
+    z.r = r_ + r * nd;
+    z.p = p_ + r * nd;
+    z.cs = cs_ + r;
+    for (int l = 0; l < L; ++l) {
+      FzLevel& v = z.lv[l];
+      const long ndl = lv_[l].L.ndof();
+      v.L = lv_[l].L;
+      v.coef = l ? (const double*)B_[l].coefV : nullptr;
+      v.wD = (const double*)B_[l].invD;
+      v.mask = B_[l].mask;
+      v.b = (double*)B_[l].b + r * ndl;
+      v.x = (double*)B_[l].xa + r * ndl;
+      v.r = (double*)B_[l].r + r * ndl;
+    }
+  }
+}
+
+int Problem::fused_finish(mgcg_info* info) {
+  MGCG_HIP(hipMemcpyAsync(hcs_, cs_, 4 * sizeof(CgScalars), hipMemcpyDeviceToHost, stream_));
+  sync();
+  chunk_pending_ = false;
+  active_ = false;
+  return solve_finish(info);
+}
+
+int Problem::solve_fused(double rtol, int maxit, int warm, mgcg_info* info) {
+  std::vector<FzDesc> h;
+  fused_prepare(rtol, maxit, warm, h);
+  MGCG_HIP(hipMemcpyAsync(fz_, h.data(), h.size() * sizeof(FzDesc), hipMemcpyHostToDevice, stream_));
+  fused_solve(fz_, (int)h.size(), stream_);
+  return fused_finish(info);
 }
 
 bool Problem::solve_poll(bool block) {
@@ -984,6 +1060,7 @@ int Problem::solve_finish(mgcg_info* info) {
 }
 
 int Problem::solve(double rtol, int maxit, int warm, mgcg_info* info) {
+  if (launch_mode_ == MGCG_LAUNCH_FUSED && !timer_.enabled) return solve_fused(rtol, maxit, warm, info);
   solve_begin(rtol, maxit, warm);
   solve_poll(true);
   while (active_) {

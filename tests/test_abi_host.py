@@ -92,6 +92,34 @@ def test_problem_create_rejects_bad_input():
         api.Problem((4, 2, 2), mask, f, nlevels=2, omega=2.5)
 
 
+def test_fused_launch_mode_eligibility():
+    """The fused solve takes trilinear nsub = 1 FP64 Jacobi problems whose
+    finest level fits the workgroup's LDS; others are refused up front (no
+    device needed), and so is an empty or ineligible batch."""
+    from paper_2311_05595_amd import api
+    from paper_2311_05595_amd._abi import MGCGError
+    _lib()
+    mask, f = W.make_problem("cantilever", 8, 4, 4, 1, 2)
+    ok = api.Problem((8, 4, 4), mask, f, nlevels=3)
+    ok.set_launch_mode("fused")
+    ok.set_launch_mode("eager")
+    for kw in (dict(nsub=2), dict(precision="mixed"), dict(nlevels=1)):
+        p = api.Problem((8, 4, 4), mask, f, **{**dict(nlevels=3), **kw})
+        with pytest.raises(MGCGError):
+            p.set_launch_mode("fused")
+        with pytest.raises(MGCGError):
+            api.solve_batch([ok, p])
+        p.close()
+    big_mask, big_f = W.make_problem("cantilever", 32, 16, 16, 1, 1)  # 9537 nodes
+    big = api.Problem((32, 16, 16), big_mask, big_f, nlevels=4)
+    with pytest.raises(MGCGError):
+        big.set_launch_mode("fused")
+    big.close()
+    lib = ok._lib
+    assert lib.mgcg_solve_batch(None, 1, 1e-8, 10, 0, None) != 0
+    ok.close()
+
+
 def test_admission_plan_respects_budget_and_order():
     from paper_2311_05595_amd import api
     _lib()

@@ -27,7 +27,7 @@ def _run(name, rtol):
     print(f"[fullsize] {cfg['name']} rtol={rtol}", flush=True)
     p = api.Problem(nel, mask, f, order=order, nsub=nsub, nlevels=cfg["nlevels"],
                     precision=cfg["precision"], omega=cfg["omega"], pre=cfg["pre"],
-                    post=cfg["post"], family=family)
+                    post=cfg["post"], family=family, smoother=cfg.get("smoother", "jacobi"))
     p.use_torch_stream()
     p.set_densities(torch.tensor(rho.ravel(), dtype=torch.float64, device="cuda"))
     info = p.solve(rtol=rtol, maxit=5000, warm_start=False)
@@ -36,8 +36,8 @@ def _run(name, rtol):
     c, dc = p.compliance_sensitivity()
     p.close()
     Ks = fem.sub_element_matrices(order, nsub, family=family)
-    if family == "serendipity":   # the library fixes the unused face and body centres
-        mask = np.maximum(mask, fem.serendipity_dof_mask(nel))
+    if family == "serendipity":   # the library fixes the unused face- and body-interior nodes
+        mask = np.maximum(mask, fem.serendipity_dof_mask(nel, order))
     Ku = assemble.apply(rho, nel, order, nsub, Ks, u, **MAT)
     free = mask == 0
     for l in range(cfg["nrhs"]):
@@ -55,7 +55,10 @@ def _run(name, rtol):
         assert abs(cl - float(u[l] @ Ku[l])) <= 1.1 * np.linalg.norm(r) * np.linalg.norm(u[l])
     assert abs(c[-1] - c[:-1].sum()) <= 1e-12 * abs(c[-1])
     dref = solve.sensitivity(rho, u, nel, order, nsub, Ks, **MAT)
-    assert rel(dc, dref) <= 1e-12
+    # the same u on both sides: only the summation order of u_e^T K_s u_e
+    # differs (the device sums 300, 3,321 or 18,528 packed pairs per
+    # sub-element for Q1, Q2 and cubic elements)
+    assert rel(dc, dref) <= (1e-10 if order == 3 else 1e-12)
     assert np.all(dc <= 0.0)
     return info
 
@@ -116,3 +119,15 @@ def test_error_vs_oracle_mgcg_64x32x32_n4_mixed():
     print(f"[fullsize] c3 mixed at 1e-9: |u - u*|/|u*| = {eu:.2e}, |c - c*|/c* = {ec:.2e}",
           flush=True)
     assert eu <= 1e-8 and ec <= 1e-9
+
+
+def test_mbb_cubic_48x16x8_n4_mixed():
+    """The 64-node element on the displacement mesh of Sec. 7.5's quarter MBB
+    beam (533k DOFs), Gauss-Seidel smoothing on the finest level."""
+    need_gpu()
+    _run("c6", 1e-8)
+
+
+def test_mbb_cubic_serendipity_48x16x8_n4_mixed():
+    need_gpu()
+    _run("c6s", 1e-8)

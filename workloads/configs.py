@@ -1,4 +1,4 @@
-"""The five synthetic workloads of the MGCG hot path (sizes, material, solver
+"""The synthetic workloads of the MGCG hot path (sizes, material, solver
 settings and seeds), plus the served request mix.
 
 Material of every workload: E0 = 1, Emin = 1e-9, nu = 0.3, SIMP p = 3
@@ -40,6 +40,18 @@ CONFIGS = {
                 nel=(48, 24, 24), order=2, nsub=4, nlevels=5, nrhs=1,
                 precision="mixed", omega=0.6, pre=1, post=1,
                 field="grf", seed=4, family="serendipity"),
+    # cubic elements (Sec. 7.5 compares them on the MBB beam with n = 4):
+    # the displacement mesh of its quarter model, 48 x 16 x 8 elements
+    # (533k DOFs with the 64-node element), point load at the top centre,
+    # the finest level smoothed by the multicolour Gauss-Seidel sweep
+    "c6": dict(name="mbb L3 48x16x8 n=4 mixed", kind="mbb",
+               nel=(48, 16, 8), order=3, nsub=4, nlevels=4, nrhs=1,
+               precision="mixed", omega=0.6, pre=1, post=1,
+               field="grf", seed=6, smoother="gauss-seidel"),
+    "c6s": dict(name="mbb S3 48x16x8 n=4 mixed", kind="mbb",
+                nel=(48, 16, 8), order=3, nsub=4, nlevels=4, nrhs=1,
+                precision="mixed", omega=0.6, pre=1, post=1,
+                field="grf", seed=6, family="serendipity", smoother="gauss-seidel"),
 }
 
 SERVE_MESHES = [(32, 16, 16), (48, 24, 24), (64, 32, 32), (96, 48, 48), (128, 64, 64)]

@@ -2403,6 +2403,114 @@ __device__ __forceinline__ double fz_sum(double v, double* sh) {
   return t;
 }
 
+// Level-wide vector passes over a thread's DOFs (or nodes, where the fixed
+// DOFs matter: one mask byte per node), restrict-qualified and unrolled, so
+// that the loads of several DOFs are in flight together (a workgroup has too
+// few waves to hide a memory round trip per DOF).  acc: node sums in LDS,
+// masked here (fixed rows return 0; the vectors vanish on fixed DOFs).
+// n: DOFs (3 per node).
+// r = f - A x; returns the thread's part of ||r||^2
+__device__ __forceinline__ double fz_true_res(int n, const double* __restrict__ f,
+                                              const double* __restrict__ acc,
+                                              const uint8_t* __restrict__ m, double* __restrict__ r) {
+  double s = 0.0;
+#pragma unroll 4
+  for (int node = threadIdx.x; node < n / 3; node += FZ_T) {
+    const int mk = m[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int t = 3 * node + c;
+      const double v = ((mk >> c) & 1) ? 0.0 : f[t] - acc[t];
+      r[t] = v;
+      s = fma(v, v, s);
+    }
+  }
+  return s;
+}
+__device__ __forceinline__ double fz_dot(int n, const double* __restrict__ a, const double* __restrict__ b) {
+  double s = 0.0;
+#pragma unroll 8
+  for (int t = threadIdx.x; t < n; t += FZ_T) s = fma(a[t], b[t], s);
+  return s;
+}
+// p . (A p)
+__device__ __forceinline__ double fz_dot_acc(int n, const double* __restrict__ p,
+                                             const double* __restrict__ acc,
+                                             const uint8_t* __restrict__ m) {
+  double s = 0.0;
+#pragma unroll 4
+  for (int node = threadIdx.x; node < n / 3; node += FZ_T) {
+    const int mk = m[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int t = 3 * node + c;
+      s = fma(p[t], ((mk >> c) & 1) ? 0.0 : acc[t], s);
+    }
+  }
+  return s;
+}
+// x += alpha p, r -= alpha A p; returns the thread's part of ||r||^2
+__device__ __forceinline__ double fz_xr(int n, double alpha, const double* __restrict__ p,
+                                        const double* __restrict__ acc,
+                                        const uint8_t* __restrict__ m, double* __restrict__ x,
+                                        double* __restrict__ r) {
+  double s = 0.0;
+#pragma unroll 4
+  for (int node = threadIdx.x; node < n / 3; node += FZ_T) {
+    const int mk = m[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int t = 3 * node + c;
+      x[t] = fma(alpha, p[t], x[t]);
+      const double v = r[t] - alpha * (((mk >> c) & 1) ? 0.0 : acc[t]);
+      r[t] = v;
+      s = fma(v, v, s);
+    }
+  }
+  return s;
+}
+// p = z + beta p
+__device__ __forceinline__ void fz_pz(int n, double beta, const double* __restrict__ z,
+                                      double* __restrict__ p) {
+#pragma unroll 8
+  for (int t = threadIdx.x; t < n; t += FZ_T) p[t] = fma(beta, p[t], z[t]);
+}
+// x = w r
+__device__ __forceinline__ void fz_scale(int n, const double* __restrict__ w,
+                                         const double* __restrict__ r, double* __restrict__ x) {
+#pragma unroll 8
+  for (int t = threadIdx.x; t < n; t += FZ_T) x[t] = w[t] * r[t];
+}
+// out = r - A x
+__device__ __forceinline__ void fz_res0(int n, const double* __restrict__ r,
+                                        const double* __restrict__ acc,
+                                        const uint8_t* __restrict__ m, double* __restrict__ out) {
+#pragma unroll 4
+  for (int node = threadIdx.x; node < n / 3; node += FZ_T) {
+    const int mk = m[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int t = 3 * node + c;
+      out[t] = ((mk >> c) & 1) ? 0.0 : r[t] - acc[t];
+    }
+  }
+}
+// x += w (b - A x), A x from LDS node sums (fine, masked) or a vector (coarse)
+__device__ __forceinline__ void fz_jac(int n, const double* __restrict__ w, const double* __restrict__ b,
+                                       const double* __restrict__ ax, const uint8_t* __restrict__ m,
+                                       bool fine, double* __restrict__ x) {
+#pragma unroll 4
+  for (int node = threadIdx.x; node < n / 3; node += FZ_T) {
+    const int mk = fine ? m[node] : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int t = 3 * node + c;
+      const double a = ((mk >> c) & 1) ? 0.0 : ax[t];
+      x[t] = fma(w[t], b[t] - a, x[t]);
+    }
+  }
+}
+
 // acc = K u on the finest level (before masking), in LDS.  A thread walks
 // its elements colour by colour (a barrier after each colour) and loads the
 // next element's 24 values and modulus before it computes the current one.
@@ -2541,17 +2649,29 @@ FZ_STEP void fz_restrict(const FzLevel& fl, const FzLevel& cl, double* b, double
   __syncthreads();
 }
 
-// x_f += P x_c on the free fine DOFs.
+// x_f += P x_c on the free fine DOFs, two nodes per thread and pass (their
+// gathers issued before the updates).
 FZ_STEP void fz_prolong_add(const FzLevel& fl, const FzLevel& cl) {
+  constexpr int U = 2;
   const __amdgpu_buffer_rsrc_t re = make_rsrc(cl.x, (size_t)cl.L.ndof() * sizeof(double));
-  for (int t = threadIdx.x; t < (int)fl.L.nn(); t += FZ_T) {
-    int i, j, k;
-    node_ijk(t, fl.L, i, j, k);
-    double pe[3];
-    prolong_at<double>(cl.L, re, i, j, k, true, pe);
-    const int m = fl.mask[t];
-    for (int c = 0; c < 3; ++c)
-      if (!((m >> c) & 1)) fl.x[3 * t + c] += pe[c];
+  const int nn = (int)fl.L.nn();
+  for (int t0 = threadIdx.x; t0 < nn; t0 += U * FZ_T) {
+    double pe[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * FZ_T;
+      int i, j, k;
+      node_ijk(t < nn ? t : 0, fl.L, i, j, k);
+      prolong_at<double>(cl.L, re, i, j, k, t < nn, pe[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * FZ_T;
+      if (t >= nn) break;
+      const int m = fl.mask[t];
+      for (int c = 0; c < 3; ++c)
+        if (!((m >> c) & 1)) fl.x[3 * t + c] += pe[u][c];
+    }
   }
   __syncthreads();
 }
@@ -2599,18 +2719,11 @@ FZ_STEP void fz_coarse(const FzDesc& d, const FzLevel& cl, const double* sbc) {
   __syncthreads();
 }
 
-// x += W D^-1 (b - t) over a level's DOFs (t: A x, or b - A x when bt)
+// x += W D^-1 (b - A x) over a level's DOFs; A x in t (coarse) or in the
+// LDS node sums acc (fine)
 FZ_STEP void fz_jacobi_update(const FzLevel& lv, const double* b, const double* t, bool fine,
                               const double* acc) {
-  const int nd = (int)lv.L.ndof();
-  for (int q = threadIdx.x; q < nd; q += FZ_T) {
-    double ax;
-    if (fine)
-      ax = ((lv.mask[q / 3] >> (q % 3)) & 1) ? 0.0 : acc[q];
-    else
-      ax = t[q];
-    lv.x[q] += lv.wD[q] * (b[q] - ax);
-  }
+  fz_jac((int)lv.L.ndof(), lv.wD, b, fine ? acc : t, lv.mask, fine, lv.x);
   __syncthreads();
 }
 
@@ -2621,17 +2734,14 @@ FZ_STEP void fz_vcycle(const FzDesc& d, const double* r, double* acc, double* sb
   const FzLevel& l0 = d.lv[0];
   {
     const int nd = (int)l0.L.ndof();
-    for (int t = threadIdx.x; t < nd; t += FZ_T) l0.x[t] = l0.wD[t] * r[t];
+    fz_scale(nd, l0.wD, r, l0.x);
     __syncthreads();
     for (int s = 1; s < d.pre; ++s) {
       fz_mf_apply(d, l0.x, acc);
       fz_jacobi_update(l0, r, nullptr, true, acc);
     }
     fz_mf_apply(d, l0.x, acc);
-    for (int t = threadIdx.x; t < nd; t += FZ_T) {
-      const bool fx = (l0.mask[t / 3] >> (t % 3)) & 1;
-      l0.r[t] = fx ? 0.0 : r[t] - acc[t];
-    }
+    fz_res0(nd, r, acc, l0.mask, l0.r);
     __syncthreads();
   }
   for (int l = 1; l < L; ++l) {
@@ -2684,21 +2794,12 @@ __global__ __launch_bounds__(FZ_T) void k_fused_pcg(const FzDesc* __restrict__ d
   double* p = d.p;
   const double* f = d.f;
   const double* z = d.lv[0].x;
-  auto fixed = [&](int t) { return (bool)((mask[t / 3] >> (t % 3)) & 1); };
   // true residual r = f - A x into r; returns ||r||^2
   auto true_residual = [&]() {
     fz_mf_apply(d, x, acc);
-    double s = 0.0;
-    for (int t = threadIdx.x; t < nd; t += FZ_T) {
-      const double v = fixed(t) ? 0.0 : f[t] - acc[t];
-      r[t] = v;
-      s = fma(v, v, s);
-    }
-    return fz_sum(s, sh);
+    return fz_sum(fz_true_res(nd, f, acc, mask, r), sh);
   };
-  double sf = 0.0;
-  for (int t = threadIdx.x; t < nd; t += FZ_T) sf = fma(f[t], f[t], sf);
-  const double ff = fz_sum(sf, sh);
+  const double ff = fz_sum(fz_dot(nd, f, f), sh);
   const double tol2 = d.tol2 * ff;
   double rr = true_residual();
   if (d.scale_warm) {
@@ -2725,12 +2826,8 @@ __global__ __launch_bounds__(FZ_T) void k_fused_pcg(const FzDesc* __restrict__ d
   double rr_best = rr;
   if (!(rr <= tol2)) {
     fz_vcycle(d, r, acc, sbc);
-    double s = 0.0;
-    for (int t = threadIdx.x; t < nd; t += FZ_T) {
-      p[t] = z[t];
-      s = fma(r[t], z[t], s);
-    }
-    double rz = fz_sum(s, sh);
+    fz_pz(nd, 0.0, z, p);
+    double rz = fz_sum(fz_dot(nd, r, z), sh);
     bool restart = false;
     while (true) {
       if (it >= d.maxit) {
@@ -2738,22 +2835,13 @@ __global__ __launch_bounds__(FZ_T) void k_fused_pcg(const FzDesc* __restrict__ d
         break;
       }
       fz_mf_apply(d, p, acc);
-      double spq = 0.0;
-      for (int t = threadIdx.x; t < nd; t += FZ_T) spq = fma(p[t], fixed(t) ? 0.0 : acc[t], spq);
-      const double pq = fz_sum(spq, sh);
+      const double pq = fz_sum(fz_dot_acc(nd, p, acc, mask), sh);
       if (!(pq > 0.0) || !isfinite(rz)) {
         state = CG_BREAKDOWN;
         break;
       }
       const double alpha = rz / pq;
-      double srr = 0.0;
-      for (int t = threadIdx.x; t < nd; t += FZ_T) {
-        x[t] = fma(alpha, p[t], x[t]);
-        const double v = r[t] - alpha * (fixed(t) ? 0.0 : acc[t]);
-        r[t] = v;
-        srr = fma(v, v, srr);
-      }
-      rr = fz_sum(srr, sh);
+      rr = fz_sum(fz_xr(nd, alpha, p, acc, mask, x, r), sh);
       ++it;
       if (!isfinite(rr)) {
         state = CG_BREAKDOWN;
@@ -2779,12 +2867,10 @@ __global__ __launch_bounds__(FZ_T) void k_fused_pcg(const FzDesc* __restrict__ d
         rr = rt;
       }
       fz_vcycle(d, r, acc, sbc);
-      double srz = 0.0;
-      for (int t = threadIdx.x; t < nd; t += FZ_T) srz = fma(r[t], z[t], srz);
-      const double rzn = fz_sum(srz, sh);
+      const double rzn = fz_sum(fz_dot(nd, r, z), sh);
       const double beta = restart ? 0.0 : rzn / rz;
       restart = false;
-      for (int t = threadIdx.x; t < nd; t += FZ_T) p[t] = fma(beta, p[t], z[t]);
+      fz_pz(nd, beta, z, p);
       __syncthreads();
       rz = rzn;
     }

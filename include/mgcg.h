@@ -235,7 +235,8 @@ int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_inf
  * returns when all are done.  infos (may be NULL) receives n results, in
  * the order of ps.  Returns MGCG_OK, or the first problem's error status
  * (MGCG_ENOTCONV, MGCG_EBREAKDOWN, ...) in ps order; MGCG_EINVAL for a
- * problem that does not fit, n < 1 or mixed devices. */
+ * problem that does not fit, a problem listed twice, n < 1 or mixed
+ * devices. */
 int mgcg_solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm_start,
                      mgcg_info* infos);
 

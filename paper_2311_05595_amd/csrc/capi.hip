@@ -241,6 +241,8 @@ int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm
     if (ps[i]->impl->device() != dev) throw Error(MGCG_EINVAL, "batched problems must share a device");
     if (!ps[i]->impl->fused_ok())
       throw Error(MGCG_EINVAL, "a batched problem does not fit the fused solve");
+    for (int j = 0; j < i; ++j)
+      if (ps[j]->impl == ps[i]->impl) throw Error(MGCG_EINVAL, "a problem appears twice in the batch");
   }
   MGCG_HIP(hipSetDevice(dev));
   std::vector<FzDesc> all, one;

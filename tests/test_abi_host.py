@@ -117,6 +117,8 @@ def test_fused_launch_mode_eligibility():
     big.close()
     lib = ok._lib
     assert lib.mgcg_solve_batch(None, 1, 1e-8, 10, 0, None) != 0
+    with pytest.raises(MGCGError):
+        api.solve_batch([ok, ok])
     ok.close()
 
 

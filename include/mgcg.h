@@ -513,7 +513,7 @@ int mgcg_slp_decide(mgcg_slp_ctrl* ctrl, double f0, double f1, double c0, double
  * mem selects host or device memory for all arrays; the call runs on the
  * null stream, allocates its own scratch and returns when done.  counts may
  * be NULL.  MGCG_EINVAL for a bad geometry (mesh >= 1, n and d in 1..64, order
- * 1 or 2), non-finite thresholds or NULL arrays. */
+ * 1..3), non-finite thresholds or NULL arrays. */
 typedef struct mgcg_fix_desc {
   int32_t nelx, nely, nelz;
   int32_t nsub;   /* n: density cells per element and axis */

@@ -201,8 +201,8 @@ namespace {
 
 FixGeom check_geometry(const mgcg_fix_desc& d) {
   if (d.nelx < 1 || d.nely < 1 || d.nelz < 1 || d.nsub < 1 || d.nsub > 64 || d.ndes < 1 ||
-      d.ndes > 64 || (d.order != 1 && d.order != 2))
-    throw Error(MGCG_EINVAL, "bad fixing geometry (mesh >= 1, n and d in 1..64, order 1 or 2)");
+      d.ndes > 64 || d.order < 1 || d.order > 3)
+    throw Error(MGCG_EINVAL, "bad fixing geometry (mesh >= 1, n and d in 1..64, order 1..3)");
   if (!std::isfinite(d.rho_l) || !std::isfinite(d.rho_u) || !std::isfinite(d.eps_grad))
     throw Error(MGCG_EINVAL, "non-finite thresholds");
   FixGeom g{d.nelx, d.nely, d.nelz, d.nsub, d.ndes, d.order};

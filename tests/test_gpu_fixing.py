@@ -42,7 +42,8 @@ def _oracle(nel, n, d, order, rho, grad, mask):
 
 @pytest.mark.parametrize("nel,n,d,order,seed", [
     ((1, 1, 1), 1, 1, 1, 0), ((5, 3, 7), 2, 1, 1, 1), ((5, 3, 7), 2, 2, 2, 2),
-    ((12, 6, 6), 4, 2, 2, 3), ((12, 6, 6), 1, 1, 2, 4), ((9, 8, 5), 3, 3, 1, 5)])
+    ((12, 6, 6), 4, 2, 2, 3), ((12, 6, 6), 1, 1, 2, 4), ((9, 8, 5), 3, 3, 1, 5),
+    ((7, 5, 4), 2, 2, 3, 6)])
 def test_fixing_matches_oracle(nel, n, d, order, seed):
     need_gpu()
     import workloads as W
@@ -86,18 +87,21 @@ def test_fixing_rejects_bad_input():
     rho, grad = _field((4, 4, 4), 1, 1, 7)
     m = np.zeros(3 * 9 ** 3, dtype=np.uint8)
     with pytest.raises(MGCGError):
-        api.fix_variables((4, 4, 4), 1, 1, 3, rho, grad, np.zeros(3 * 13 ** 3, dtype=np.uint8))
+        api.fix_variables((4, 4, 4), 1, 1, 4, rho, grad, np.zeros(3 * 17 ** 3, dtype=np.uint8))
     with pytest.raises(MGCGError):
         api.fix_variables((4, 4, 4), 1, 1, 2, rho, grad, m, rho_l=float("nan"))
     api.fix_variables((4, 4, 4), 1, 1, 2, rho, grad, m)
 
 
-def test_adaptive_step_q1_to_q2():
+@pytest.mark.parametrize("order", [2, 3])
+def test_adaptive_step_raises_the_degree(order):
     """One step of the adaptive strategy (Sec. 6): the Q1 solution's
     densities (a void block in the top layers of a cantilever) and gradient
-    fix elements; the Q2 problem with the suppressed DOFs solves to the same
-    compliance as the full Q2 problem (within 1e-6, E_min = 1e-9) and to the
-    oracle's direct solve with the same mask (rtol of the solve)."""
+    fix elements; the problem of the raised degree (quadratic, or cubic: the
+    paper goes up to degree 3) with the suppressed DOFs solves to the same
+    compliance as the full problem of that degree (within 1e-6, E_min =
+    1e-9) and to the oracle's direct solve with the same mask (rtol of the
+    solve)."""
     need_gpu()
     import workloads as W
     from oracle import fem, solve
@@ -111,21 +115,22 @@ def test_adaptive_step_q1_to_q2():
     p1.solve(rtol=1e-10, maxit=2000, warm_start=False)
     _, dc = p1.compliance_sensitivity()
     p1.close()
-    m2, f2 = W.make_problem("cantilever", *nel, 2, 1)
+    m2, f2 = W.make_problem("cantilever", *nel, order, 1)
     ms = m2.copy()
-    _, _, ms, cnt = api.fix_variables(nel, n, n, 2, rho, dc.reshape(-1), ms)
+    _, _, ms, cnt = api.fix_variables(nel, n, n, order, rho, dc.reshape(-1), ms)
     assert cnt["suppressed_nodes"] > 0 and ms.sum() > m2.sum()
     comp = {}
     for name, mk in (("full", m2), ("fixed", ms)):
-        p2 = api.Problem(nel, mk, f2, order=2, nsub=n, nlevels=2)
+        p2 = api.Problem(nel, mk, f2, order=order, nsub=n, nlevels=2)
         p2.set_densities(rho.reshape(-1))
         p2.solve(rtol=1e-10, maxit=4000, warm_start=False)
         c, _ = p2.compliance_sensitivity()
         comp[name] = float(c[-1])  # the total over the load cases
         p2.close()
     assert abs(comp["fixed"] - comp["full"]) <= 1e-6 * comp["full"]
-    Ks = fem.sub_element_matrices(2, n)
-    _, _, c_o, _ = solve.solve_problem(rho, ms, f2, nel, 2, n, Ks, E0=1.0, Emin=1e-9, penal=3.0)
+    Ks = fem.sub_element_matrices(order, n)
+    _, _, c_o, _ = solve.solve_problem(rho, ms, f2, nel, order, n, Ks, E0=1.0, Emin=1e-9,
+                                       penal=3.0)
     assert abs(comp["fixed"] - c_o.sum()) <= 1e-8 * c_o.sum()
 
 

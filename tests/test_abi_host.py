@@ -237,7 +237,7 @@ def test_new_entry_points_reject_bad_arguments_before_any_device_work():
     rho = np.zeros(8)
     buf = np.zeros(3 * 27, dtype=np.uint8)
     p = lambda a: C.c_void_p(a.ctypes.data)
-    for desc in (abi.mgcg_fix_desc(2, 2, 2, 1, 1, 3, 1e-6, 0.9, 1e-6),      # order 3
+    for desc in (abi.mgcg_fix_desc(2, 2, 2, 1, 1, 4, 1e-6, 0.9, 1e-6),      # order 4
                  abi.mgcg_fix_desc(0, 2, 2, 1, 1, 1, 1e-6, 0.9, 1e-6),      # empty mesh
                  abi.mgcg_fix_desc(2, 2, 2, 65, 1, 1, 1e-6, 0.9, 1e-6),     # n > 64
                  abi.mgcg_fix_desc(2, 2, 2, 1, 1, 1, float("nan"), 0.9, 1e-6)):

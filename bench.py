@@ -200,7 +200,7 @@ def batch_bench(args):
            "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": cfg["name"] + f", {n} problems with their own seeded "
                       "densities, warm-started", "problems": n, "steps": args.steps}}
-    for mode in ("eager", "fused"):
+    for mode in args.batch_modes.split(","):
         for p in probs:
             p.set_launch_mode(mode)
         iters = []
@@ -223,7 +223,7 @@ def batch_bench(args):
         el = sum(step(k) for k in range(1, args.steps + 1))
         out[mode] = {"solves_s": round(n * args.steps / el, 2), "ms_per_step": round(el / args.steps * 1e3, 3),
                      "pcg_iters_mean": round(float(np.mean(iters)), 2)}
-    out["value"] = out["fused"]["solves_s"]
+    out["value"] = out.get("fused", out.get("eager", {})).get("solves_s")
     for p in probs:
         p.close()
     print(json.dumps(out), flush=True)
@@ -995,6 +995,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="N",
                     help="time N small (c1) problems solved eagerly one by one and in one "
                          "fused multi-problem launch")
+    ap.add_argument("--batch-modes", default="eager,fused",
+                    help="--batch: the launch modes to time, comma-separated")
     ap.add_argument("--apply-sweep", action="store_true",
                     help="time the matrix-free CG apply on lattices of 0.7M to 8.6M DOF")
     ap.add_argument("--requests", type=int, default=256, help="c5: number of requests")

@@ -231,8 +231,8 @@ int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_inf
  * one device; a workgroup per load case of every problem runs its whole
  * PCG solve, so up to one problem per compute unit progresses at once.
  * The launch goes on ps[0]'s stream after the work already enqueued on
- * every problem's stream, and every problem's stream waits for it; the call
- * returns when all are done.  infos (may be NULL) receives n results, in
+ * every problem's stream; the call returns when all are done, their
+ * results read back in one transfer.  infos (may be NULL) receives n results, in
  * the order of ps.  Returns MGCG_OK, or the first problem's error status
  * (MGCG_ENOTCONV, MGCG_EBREAKDOWN, ...) in ps order; MGCG_EINVAL for a
  * problem that does not fit, a problem listed twice, n < 1 or mixed

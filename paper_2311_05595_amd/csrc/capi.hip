@@ -22,6 +22,8 @@ const char* get_error() { return g_err.c_str(); }
 using mgcg::Error;
 using mgcg::Problem;
 using mgcg::FzDesc;
+using mgcg::FzGatherSrc;
+using mgcg::FzRecord;
 
 #define GUARD(body)                                 \
   try {                                             \
@@ -223,14 +225,19 @@ int mgcg_solve(mgcg_problem* p, double rtol, int maxit, int warm_start, mgcg_inf
 }
 
 namespace {
-// One descriptor table per device, grown as needed and kept; batches share
-// it, so they run one at a time.
+// One batch table per device, grown as needed and kept; batches share it, so
+// they run one at a time.  Device: the load cases' descriptors, the
+// problems' record sources and their packed records; pinned host: the same
+// layout (staging for the upload, then the records read back).
 struct BatchTable {
-  void* ptr = nullptr;
+  void* dev = nullptr;
+  void* host = nullptr;
   size_t bytes = 0;
 };
 std::mutex g_batch_mu;
 std::vector<BatchTable> g_batch_tables;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm_start,
                 mgcg_info* infos) {
@@ -250,41 +257,61 @@ int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm
     ps[i]->impl->fused_prepare(rtol, maxit, warm_start, one);
     all.insert(all.end(), one.begin(), one.end());
   }
+  const size_t o_src = align256(all.size() * sizeof(FzDesc));
+  const size_t o_rec = o_src + align256(n * sizeof(FzGatherSrc));
+  const size_t bytes = o_rec + n * sizeof(FzRecord);
   if ((int)g_batch_tables.size() <= dev) g_batch_tables.resize(dev + 1);
   BatchTable& tb = g_batch_tables[dev];
-  const size_t bytes = all.size() * sizeof(FzDesc);
   hipStream_t st = p0->ensure_stream();
   if (tb.bytes < bytes) {
-    if (tb.ptr) {
+    if (tb.dev) {
       MGCG_HIP(hipDeviceSynchronize());
-      MGCG_HIP(hipFree(tb.ptr));
+      MGCG_HIP(hipFree(tb.dev));
+      MGCG_HIP(hipHostFree(tb.host));
       tb = BatchTable{};
     }
-    MGCG_HIP(hipMalloc(&tb.ptr, bytes));
+    MGCG_HIP(hipMalloc(&tb.dev, bytes));
+    if (hipHostMalloc(&tb.host, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(tb.dev);
+      tb = BatchTable{};
+      throw Error(MGCG_ENOMEM, "batch table host buffer allocation failed");
+    }
     tb.bytes = bytes;
   }
-  // the launch follows the work already on every problem's stream
+  char* hb = static_cast<char*>(tb.host);
+  char* db = static_cast<char*>(tb.dev);
+  std::memcpy(hb, all.data(), all.size() * sizeof(FzDesc));
+  FzGatherSrc* hsrc = reinterpret_cast<FzGatherSrc*>(hb + o_src);
+  for (int i = 0; i < n; ++i) hsrc[i] = ps[i]->impl->gather_src();
+  // the launch follows the work still pending on every problem's stream
   std::vector<hipEvent_t> evs;
   for (int i = 1; i < n; ++i) {
+    hipStream_t si = ps[i]->impl->ensure_stream();
+    const hipError_t q = hipStreamQuery(si);
+    if (q == hipSuccess) continue;
+    if (q != hipErrorNotReady) MGCG_HIP(q);
+    (void)hipGetLastError();
     hipEvent_t e;
     MGCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     evs.push_back(e);
-    MGCG_HIP(hipEventRecord(e, ps[i]->impl->ensure_stream()));
+    MGCG_HIP(hipEventRecord(e, si));
     MGCG_HIP(hipStreamWaitEvent(st, e, 0));
   }
-  MGCG_HIP(hipMemcpyAsync(tb.ptr, all.data(), bytes, hipMemcpyHostToDevice, st));
-  mgcg::fused_solve(static_cast<const FzDesc*>(tb.ptr), (int)all.size(), st);
-  hipEvent_t done;
-  MGCG_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-  MGCG_HIP(hipEventRecord(done, st));
-  for (int i = 1; i < n; ++i) MGCG_HIP(hipStreamWaitEvent(ps[i]->impl->stream(), done, 0));
+  MGCG_HIP(hipMemcpyAsync(db, hb, o_rec, hipMemcpyHostToDevice, st));
+  mgcg::fused_solve(reinterpret_cast<const FzDesc*>(db), (int)all.size(), st);
+  FzRecord* drec = reinterpret_cast<FzRecord*>(db + o_rec);
+  mgcg::fused_gather(reinterpret_cast<const FzGatherSrc*>(db + o_src), n, drec, st);
+  MGCG_HIP(hipMemcpyAsync(hb + o_rec, drec, n * sizeof(FzRecord), hipMemcpyDeviceToHost, st));
+  // all done on return: later work on any problem's stream follows it
+  MGCG_HIP(hipStreamSynchronize(st));
+  const FzRecord* hrec = reinterpret_cast<const FzRecord*>(hb + o_rec);
   int status = MGCG_OK;
   for (int i = 0; i < n; ++i) {
-    const int si = ps[i]->impl->fused_finish(infos ? &infos[i] : nullptr);
+    const int si = ps[i]->impl->fused_finish(hrec[i], infos ? &infos[i] : nullptr);
     if (status == MGCG_OK && si != MGCG_OK) status = si;
   }
   for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-  (void)hipEventDestroy(done);
   return status;
 }
 }  // namespace

@@ -2894,4 +2894,20 @@ void fused_solve(const FzDesc* descs, int n, hipStream_t st) {
   MGCG_HIP(hipGetLastError());
 }
 
+// One workgroup per problem, one 32-bit word per thread.
+__global__ void k_fz_gather(const FzGatherSrc* src, int n, FzRecord* out) {
+  const FzGatherSrc g = src[blockIdx.x];
+  const int nw = g.nrhs * (int)(sizeof(CgScalars) / sizeof(int));
+  int* o = reinterpret_cast<int*>(out[blockIdx.x].cs);
+  const int* c = reinterpret_cast<const int*>(g.cs);
+  for (int t = threadIdx.x; t < nw; t += blockDim.x) o[t] = c[t];
+  if (threadIdx.x < 4) out[blockIdx.x].bad[threadIdx.x] = g.bad[threadIdx.x];
+}
+
+void fused_gather(const FzGatherSrc* src, int n, FzRecord* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fz_gather, dim3(n), dim3(64), 0, st, src, n, out);
+  MGCG_HIP(hipGetLastError());
+}
+
 }  // namespace mgcg

@@ -360,6 +360,21 @@ struct FzDesc {
 // descs: n device descriptors, one workgroup each.
 void fused_solve(const FzDesc* descs, int n, hipStream_t st);
 
+// End-of-solve records of a batch: where one problem's CG scalars (nrhs load
+// cases) and set-up flags (4 ints) live, and their packed copy.
+struct FzGatherSrc {
+  const CgScalars* cs;
+  const int* bad;
+  int nrhs, pad;
+};
+struct FzRecord {
+  CgScalars cs[4];
+  int bad[4];
+};
+static_assert(sizeof(CgScalars) % sizeof(int) == 0, "CG scalars copy as 32-bit words");
+// src, out: n device entries; one workgroup per problem copies its record.
+void fused_gather(const FzGatherSrc* src, int n, FzRecord* out, hipStream_t st);
+
 // Timing-free plain copy (for traffic calibration).
 void copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t st);
 

@@ -103,7 +103,9 @@ class Problem {
   void solve_begin(double rtol, int maxit, int warm);  // warm: MGCG_COLD / _WARM_SCALED / _WARM_PLAIN
   void solve_chunk(int iters);             // enqueue iterations + state readback
   bool solve_poll(bool block);             // true when every load case finished
-  int solve_finish(mgcg_info* info);       // fills info; returns status
+  // fills info; returns status.  bad: the set-up flags already on the host
+  // (else read back here when a set-up is pending its check).
+  int solve_finish(mgcg_info* info, const int* bad = nullptr);
   // Gives up a solve: waits for the work already enqueued on the stream and
   // leaves the problem idle (its u is whatever the last iteration wrote).
   void solve_abort();
@@ -138,6 +140,11 @@ class Problem {
   void fused_prepare(double rtol, int maxit, int warm, std::vector<FzDesc>& out);
   // Bookkeeping after a fused solve ran on the device (scalars copied back).
   int fused_finish(mgcg_info* info);
+  // Batched solves: where this problem's end-of-solve record lives on the
+  // device, and the bookkeeping from a record already copied to the host
+  // (after the launch's stream has been synchronised).
+  FzGatherSrc gather_src() const { return FzGatherSrc{cs_, bad_, d_.nrhs, 0}; }
+  int fused_finish(const FzRecord& rec, mgcg_info* info);
   void set_timing(bool on, int kernel = 0);
   void get_timing(int kernel, double* ms, long long* launches);
   void copy(const void* src, void* dst, size_t bytes);

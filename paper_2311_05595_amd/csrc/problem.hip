@@ -963,6 +963,13 @@ int Problem::fused_finish(mgcg_info* info) {
   return solve_finish(info);
 }
 
+int Problem::fused_finish(const FzRecord& rec, mgcg_info* info) {
+  std::memcpy(hcs_, rec.cs, d_.nrhs * sizeof(CgScalars));
+  chunk_pending_ = false;
+  active_ = false;
+  return solve_finish(info, rec.bad);
+}
+
 int Problem::solve_fused(double rtol, int maxit, int warm, mgcg_info* info) {
   std::vector<FzDesc> h;
   fused_prepare(rtol, maxit, warm, h);
@@ -1022,7 +1029,7 @@ int Problem::suggest_chunk() const {
   return std::max(1, std::min(n, std::max(left, 1)));
 }
 
-int Problem::solve_finish(mgcg_info* info) {
+int Problem::solve_finish(mgcg_info* info, const int* bad) {
   const auto t1 = std::chrono::steady_clock::now();
   int status = MGCG_OK;
   if (pending_check_) {
@@ -1030,8 +1037,12 @@ int Problem::solve_finish(mgcg_info* info) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev_s0_, ev_s1_) == hipSuccess) setup_ms_ = ms;
     int hb[4] = {0, 0, 0, 0};
-    MGCG_HIP(hipMemcpyAsync(hb, bad_, sizeof(hb), hipMemcpyDeviceToHost, stream_));
-    sync();
+    if (bad) {
+      std::memcpy(hb, bad, sizeof(hb));
+    } else {
+      MGCG_HIP(hipMemcpyAsync(hb, bad_, sizeof(hb), hipMemcpyDeviceToHost, stream_));
+      sync();
+    }
     if (hb[0] & 1) status = MGCG_EINVAL;
     else if (hb[0] & 2) status = MGCG_EBREAKDOWN;
   }

@@ -127,7 +127,7 @@ def test_autograd_chain_rule_matches_oracle():
     _, _, c_o, dc_o = solve.solve_problem(rho_o, mask, f, nel, 1, n, Ks, E0=1.0, Emin=1e-9,
                                           penal=3.0)
     gx_o = Wm.T @ dc_o
-    assert abs(float(c) - c_o.sum()) <= 1e-9 * c_o.sum()
+    assert abs(float(c.detach()) - c_o.sum()) <= 1e-9 * c_o.sum()
     assert np.abs(gx - gx_o).max() <= 1e-8 * np.abs(gx_o).max()
     pr.close()
     prob.close()

@@ -2612,16 +2612,48 @@ __device__ __attribute__((noinline)) void fz_mf_apply(const FzDesc& d, const dou
 #define FZ_STEP __device__ __attribute__((noinline))
 
 // y = A_l u (b null) or y = b - A_l u on a stencil level (identity rows
-// baked into the stencil).
-FZ_STEP void fz_st_apply(const FzLevel& lv, const double* u, const double* b, double* y) {
+// baked into the stencil).  The 14 stored blocks are taken in 7 parts
+// (blocks part and part + 7).  A work item is a node and two consecutive
+// parts (the last item one part), so that a level of a few hundred nodes
+// spreads over every thread and each thread waits for few rounds of loads;
+// the node range of a pair is padded to whole waves, so a wave's items share
+// their parts and the coefficient rows stay scalar.  The pair sums go to LDS
+// (slot, free while a stencil level runs) and each node adds its four in a
+// fixed order.  Levels whose sums do not fit take a node per thread and the
+// parts one after another.
+FZ_STEP void fz_st_apply(const FzLevel& lv, const double* u, const double* b, double* y,
+                         double* slot) {
   const int nn = (int)lv.L.nn();
   const OpST<double> op{lv.L, lv.coef};
   const InPlain<double> in{u, lv.L.ndof()};
+  const int nnp = (nn + 63) & ~63;
+  if (12 * nnp <= 3 * FZ_MAX_NODES) {
+    for (int q = threadIdx.x; q < 4 * nnp; q += FZ_T) {
+      const int pr = __builtin_amdgcn_readfirstlane(q / nnp);  // whole waves per pair
+      const int t = q - pr * nnp;
+      if (t < nn) {
+        int i, j, k;
+        node_ijk(t, lv.L, i, j, k);
+        double a[3], ap[3] = {0.0, 0.0, 0.0};
+        ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, 2 * pr, a);
+        if (pr < 3) ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, 2 * pr + 1, ap);
+        for (int c = 0; c < 3; ++c) slot[(3 * pr + c) * nnp + t] = a[c] + ap[c];
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nn; t += FZ_T)
+      for (int c = 0; c < 3; ++c) {
+        const double a = ((slot[c * nnp + t] + slot[(3 + c) * nnp + t]) + slot[(6 + c) * nnp + t]) +
+                         slot[(9 + c) * nnp + t];
+        y[3 * t + c] = b ? b[3 * t + c] - a : a;
+      }
+    __syncthreads();
+    return;
+  }
   for (int t = threadIdx.x; t < nn; t += FZ_T) {
     int i, j, k;
     node_ijk(t, lv.L, i, j, k);
-    // the 14 stored blocks two at a time (blocks part and part + 7), so that
-    // 48 values are in flight rather than all 336
+    // 48 values in flight per part rather than all 336
     double a[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
     for (int part = 0; part < 7; ++part) {
@@ -2754,10 +2786,10 @@ FZ_STEP void fz_vcycle(const FzDesc& d, const double* r, double* acc, double* sb
     }
     fz_restrict(fl, cl, cl.b, cl.x);
     for (int s = 1; s < d.pre; ++s) {
-      fz_st_apply(cl, cl.x, nullptr, cl.r);
+      fz_st_apply(cl, cl.x, nullptr, cl.r, acc);
       fz_jacobi_update(cl, cl.b, cl.r, false, nullptr);
     }
-    fz_st_apply(cl, cl.x, cl.b, cl.r);
+    fz_st_apply(cl, cl.x, cl.b, cl.r, acc);
   }
   for (int l = L - 2; l >= 0; --l) {
     const FzLevel& fl = d.lv[l];
@@ -2767,7 +2799,7 @@ FZ_STEP void fz_vcycle(const FzDesc& d, const double* r, double* acc, double* sb
         fz_mf_apply(d, fl.x, acc);
         fz_jacobi_update(fl, r, nullptr, true, acc);
       } else {
-        fz_st_apply(fl, fl.x, nullptr, fl.r);
+        fz_st_apply(fl, fl.x, nullptr, fl.r, acc);
         fz_jacobi_update(fl, fl.b, fl.r, false, nullptr);
       }
     }

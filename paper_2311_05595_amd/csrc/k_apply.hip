@@ -2618,51 +2618,34 @@ __device__ __attribute__((noinline)) void fz_mf_apply(const FzDesc& d, const dou
 // spreads over every thread and each thread waits for few rounds of loads;
 // the node range of a pair is padded to whole waves, so a wave's items share
 // their parts and the coefficient rows stay scalar.  The pair sums go to LDS
-// (slot, free while a stencil level runs) and each node adds its four in a
-// fixed order.  Levels whose sums do not fit take a node per thread and the
-// parts one after another.
+// (slot, the finest level's node sums, free while a stencil level runs; the
+// host admits stencil levels of at most FZ_MAX_ST_NODES padded nodes) and
+// each node adds its four in a fixed order.
 FZ_STEP void fz_st_apply(const FzLevel& lv, const double* u, const double* b, double* y,
                          double* slot) {
   const int nn = (int)lv.L.nn();
   const OpST<double> op{lv.L, lv.coef};
   const InPlain<double> in{u, lv.L.ndof()};
   const int nnp = (nn + 63) & ~63;
-  if (12 * nnp <= 3 * FZ_MAX_NODES) {
-    for (int q = threadIdx.x; q < 4 * nnp; q += FZ_T) {
-      const int pr = __builtin_amdgcn_readfirstlane(q / nnp);  // whole waves per pair
-      const int t = q - pr * nnp;
-      if (t < nn) {
-        int i, j, k;
-        node_ijk(t, lv.L, i, j, k);
-        double a[3], ap[3] = {0.0, 0.0, 0.0};
-        ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, 2 * pr, a);
-        if (pr < 3) ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, 2 * pr + 1, ap);
-        for (int c = 0; c < 3; ++c) slot[(3 * pr + c) * nnp + t] = a[c] + ap[c];
-      }
+  for (int q = threadIdx.x; q < 4 * nnp; q += FZ_T) {
+    const int pr = __builtin_amdgcn_readfirstlane(q / nnp);  // whole waves per pair
+    const int t = q - pr * nnp;
+    if (t < nn) {
+      int i, j, k;
+      node_ijk(t, lv.L, i, j, k);
+      double a[3], ap[3] = {0.0, 0.0, 0.0};
+      ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, 2 * pr, a);
+      if (pr < 3) ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, 2 * pr + 1, ap);
+      for (int c = 0; c < 3; ++c) slot[(3 * pr + c) * nnp + t] = a[c] + ap[c];
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nn; t += FZ_T)
-      for (int c = 0; c < 3; ++c) {
-        const double a = ((slot[c * nnp + t] + slot[(3 + c) * nnp + t]) + slot[(6 + c) * nnp + t]) +
-                         slot[(9 + c) * nnp + t];
-        y[3 * t + c] = b ? b[3 * t + c] - a : a;
-      }
-    __syncthreads();
-    return;
   }
-  for (int t = threadIdx.x; t < nn; t += FZ_T) {
-    int i, j, k;
-    node_ijk(t, lv.L, i, j, k);
-    // 48 values in flight per part rather than all 336
-    double a[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
-    for (int part = 0; part < 7; ++part) {
-      double ap[3];
-      ax_st_part<7, double, InPlain<double>>(op, in, 0, i, j, k, t, part, ap);
-      for (int c = 0; c < 3; ++c) a[c] += ap[c];
+  __syncthreads();
+  for (int t = threadIdx.x; t < nn; t += FZ_T)
+    for (int c = 0; c < 3; ++c) {
+      const double a = ((slot[c * nnp + t] + slot[(3 + c) * nnp + t]) + slot[(6 + c) * nnp + t]) +
+                       slot[(9 + c) * nnp + t];
+      y[3 * t + c] = b ? b[3 * t + c] - a : a;
     }
-    for (int c = 0; c < 3; ++c) y[3 * t + c] = b ? b[3 * t + c] - a[c] : a[c];
-  }
   __syncthreads();
 }
 

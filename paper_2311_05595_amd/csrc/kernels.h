@@ -333,6 +333,10 @@ void sens_kernel(int order, int nsub, int nelx, int nely, int nelz, Lat L, const
 constexpr int FZ_MAXLEV = 8;
 constexpr int FZ_MAX_NODES = 6000;
 constexpr int FZ_MAX_COARSE = 1024;
+// Stencil levels (node count padded to 64): their four pair sums per DOF
+// share the finest level's LDS node sums.  Finest lattices within
+// FZ_MAX_NODES that coarsen by 2 have at most 1,344 on their second level.
+constexpr int FZ_MAX_ST_NODES = FZ_MAX_NODES / 4;
 struct FzLevel {
   Lat L;
   const double* coef;  // stencil (levels >= 1)

@@ -906,6 +906,8 @@ bool Problem::fused_ok(const mgcg_desc& d, const std::vector<LevelPlan>& lv) {
   if (d.order != 1 || d.nsub != 1 || d.precision != MGCG_FP64 || d.smoother != MGCG_SMOOTH_JACOBI)
     return false;
   if (lv.size() < 2 || lv.size() > (size_t)FZ_MAXLEV) return false;
+  for (size_t l = 1; l + 1 < lv.size(); ++l)
+    if (((lv[l].L.nn() + 63) & ~63L) > FZ_MAX_ST_NODES) return false;
   return lv[0].kind == OP_MF_Q1 && lv[0].L.nn() <= FZ_MAX_NODES &&
          lv.back().L.ndof() <= FZ_MAX_COARSE;
 }

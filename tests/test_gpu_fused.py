@@ -18,6 +18,9 @@ CASES = [
     ("mbb", (12, 8, 4), 3, 2),
     ("torsion", (10, 6, 6), 2, 3),
     ("cantilever", (24, 12, 12), 3, 4),   # 4225 nodes: the small benchmark mesh
+    # 5577 nodes; its second level (833 nodes) fills 60 % of the LDS that the
+    # stencil levels' pair sums may take
+    ("cantilever", (32, 12, 12), 3, 2),
 ]
 
 

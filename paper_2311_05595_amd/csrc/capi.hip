@@ -239,6 +239,20 @@ std::vector<BatchTable> g_batch_tables;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Events of one batch call, destroyed on every way out of it.
+struct EventList {
+  std::vector<hipEvent_t> ev;
+  ~EventList() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  hipEvent_t add() {
+    hipEvent_t e;
+    MGCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev.push_back(e);
+    return e;
+  }
+};
+
 int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm_start,
                 mgcg_info* infos) {
   std::lock_guard<std::mutex> g(g_batch_mu);
@@ -285,16 +299,14 @@ int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm
   FzGatherSrc* hsrc = reinterpret_cast<FzGatherSrc*>(hb + o_src);
   for (int i = 0; i < n; ++i) hsrc[i] = ps[i]->impl->gather_src();
   // the launch follows the work still pending on every problem's stream
-  std::vector<hipEvent_t> evs;
+  EventList evs;
   for (int i = 1; i < n; ++i) {
     hipStream_t si = ps[i]->impl->ensure_stream();
     const hipError_t q = hipStreamQuery(si);
     if (q == hipSuccess) continue;
     if (q != hipErrorNotReady) MGCG_HIP(q);
     (void)hipGetLastError();
-    hipEvent_t e;
-    MGCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    evs.push_back(e);
+    const hipEvent_t e = evs.add();
     MGCG_HIP(hipEventRecord(e, si));
     MGCG_HIP(hipStreamWaitEvent(st, e, 0));
   }
@@ -311,7 +323,6 @@ int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm
     const int si = ps[i]->impl->fused_finish(hrec[i], infos ? &infos[i] : nullptr);
     if (status == MGCG_OK && si != MGCG_OK) status = si;
   }
-  for (hipEvent_t e : evs) (void)hipEventDestroy(e);
   return status;
 }
 }  // namespace

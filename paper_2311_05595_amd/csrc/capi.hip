@@ -284,7 +284,11 @@ int solve_batch(mgcg_problem* const* ps, int n, double rtol, int maxit, int warm
       MGCG_HIP(hipHostFree(tb.host));
       tb = BatchTable{};
     }
-    MGCG_HIP(hipMalloc(&tb.dev, bytes));
+    if (hipMalloc(&tb.dev, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      tb = BatchTable{};
+      throw Error(MGCG_ENOMEM, "batch table device allocation failed");
+    }
     if (hipHostMalloc(&tb.host, bytes, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(tb.dev);

@@ -699,7 +699,8 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
     v_prepare0<T>(r_in, sizeof(T) == 8 ? nullptr : (T*)B_[0].b, (const T*)B_[0].invD, cur[0],
                   lv_[0].L.ndof(), R, cs, st);
   } else if constexpr (sizeof(T) == 4) {
-    convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
+    // (with x0_ready the residual producers also wrote its FP32 copy)
+    if (!x0_ready) convert<double, float>(r_in, (float*)B_[0].b, R * lv_[0].L.ndof(), st);
   }
   for (int l = 0; l < L - 1; ++l) {
     const VOps<T> v = vops<T>(l);

@@ -612,7 +612,8 @@ struct EpJacobi {  // xo = x + wD (b - A x)  (weights folded into wD)
 };
 
 // The last finest-level sweep of the V-cycle: its output is z, so the CG dot
-// products r.z and r_old.z (partials per block) are accumulated here.
+// products r.z and, for the flexible beta of the FP32 V-cycle, q.z (with
+// r - r_old = -alpha q) are accumulated here (partials per block).
 template <typename T>
 struct EpJacobiDot {
   const T* b;
@@ -622,15 +623,17 @@ struct EpJacobiDot {
   T* xo;
   long ndof;
   const double* r;
-  const double* rold;
+  const double* q;  // the CG's A p (FP32 V-cycle only: the flexible beta)
   static constexpr bool RED = true;
   struct Pre {
     Pre3<T> b, x, d;
-    Pre3<double> r, ro;
+    Pre3<double> r, q;
   };
   __device__ Pre pre(int rr, long node) const {
     const size_t o = (size_t)rr * ndof + 3 * node;
-    return Pre{ld3(b + o), ld3(x + o), ld3(invD + 3 * node), ld3(r + o), ld3(rold + o)};
+    Pre pv{ld3(b + o), ld3(x + o), ld3(invD + 3 * node), ld3(r + o), {}};
+    if constexpr (sizeof(T) == 4) pv.q = ld3(q + o);
+    return pv;
   }
   __device__ void put(int rr, long node, const T ax[3], const Pre& pv, double& a0,
                       double& a1) const {
@@ -640,7 +643,7 @@ struct EpJacobiDot {
       const T z = pv.x.v[c] + omega * pv.d.v[c] * (pv.b.v[c] - ax[c]);
       xo[o + c] = z;
       a0 += pv.r.v[c] * (double)z;
-      a1 += pv.ro.v[c] * (double)z;
+      if constexpr (sizeof(T) == 4) a1 += pv.q.v[c] * (double)z;
     }
   }
 };
@@ -1608,11 +1611,13 @@ void cg_true_residual(const FineOp& A, const double* f, const double* x, double*
   MGCG_HIP(hipGetLastError());
 }
 
+// r.z and, for the FP32 V-cycle's flexible beta, q.z (partials per block).
 template <typename TZ>
 __global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
-                                             const double* __restrict__ rold,
+                                             const double* __restrict__ q,
                                              const TZ* __restrict__ z, long ndof, int nrhs,
                                              const CgScalars* cs, double* part) {
+  constexpr bool flexible = sizeof(TZ) == 4;
   if (!any_state(cs, nrhs, CG_ACTIVE)) return;
   double a0[4] = {0, 0, 0, 0}, a1[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -1620,7 +1625,7 @@ __global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
     if (rr >= nrhs || cs[rr].state != CG_ACTIVE) continue;
     const size_t o = (size_t)rr * ndof;
     const size_t nb = (size_t)ndof * sizeof(double);
-    const __amdgpu_buffer_rsrc_t br = make_rsrc(r + o, nb), bo = make_rsrc(rold + o, nb),
+    const __amdgpu_buffer_rsrc_t br = make_rsrc(r + o, nb), bo = make_rsrc(q + o, nb),
                                  bz = make_rsrc(z + o, (size_t)ndof * sizeof(TZ));
     double s0 = 0.0, s1 = 0.0;
     for (long i0 = (long)blockIdx.x * BS * VU + threadIdx.x; i0 < ndof;
@@ -1630,7 +1635,7 @@ __global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
       for (int k = 0; k < VU; ++k) {
         const long i = i0 + k * BS;
         rv[k] = bload<double>(br, (int)(i * sizeof(double)), 0);
-        ov[k] = bload<double>(bo, (int)(i * sizeof(double)), 0);
+        ov[k] = flexible ? bload<double>(bo, (int)(i * sizeof(double)), 0) : 0.0;
         zv[k] = (double)bload<TZ>(bz, (int)(i * sizeof(TZ)), 0);
       }
 #pragma unroll
@@ -1652,9 +1657,9 @@ __global__ __launch_bounds__(BS) void k_beta(const double* __restrict__ r,
 int cg_beta_blocks(long ndof) { return vec_grid(ndof); }
 
 template <typename TZ>
-void cg_beta(const double* r, const double* rold, const TZ* z, long ndof, int nrhs, CgScalars* cs,
+void cg_beta(const double* r, const double* q, const TZ* z, long ndof, int nrhs, CgScalars* cs,
              RedBuf red, hipStream_t st) {
-  hipLaunchKernelGGL(k_beta<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, r, rold, z, ndof, nrhs, cs,
+  hipLaunchKernelGGL(k_beta<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, r, q, z, ndof, nrhs, cs,
                      red.partials + RED_RZ * RED_REGION);
   MGCG_HIP(hipGetLastError());
 }
@@ -1663,17 +1668,17 @@ template void cg_beta<double>(const double*, const double*, const double*, long,
 template void cg_beta<float>(const double*, const double*, const float*, long, int, CgScalars*,
                              RedBuf, hipStream_t);
 
-// p = z + b p, r_old = r; b re-summed by every block: standard beta for the
-// symmetric FP64 V-cycle, flexible (Polak-Ribiere) beta for the FP32 one,
-// b = 0 for the first direction.
+// p = z + b p; b re-summed by every block: standard beta for the symmetric
+// FP64 V-cycle, flexible (Polak-Ribiere) beta for the FP32 one, whose
+// numerator (r - r_old).z is -alpha q.z (r - r_old = -alpha q), b = 0 for
+// the first direction and after a restart.
 template <typename TZ>
-__global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, double* p,
-                                                 const double* __restrict__ r, double* rold,
-                                                 long ndof, int nrhs, CgScalars* cs,
+__global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, double* p, long ndof,
+                                                 int nrhs, CgScalars* cs,
                                                  const double* __restrict__ part, int nbz) {
   __shared__ double sh[BS / 64];
   const long step = (long)gridDim.x * BS * VU;
-  // the FP32 V-cycle is the flexible one; r_old only feeds the flexible beta
+  // the FP32 V-cycle is the flexible one
   constexpr bool flexible = sizeof(TZ) == 4;
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
@@ -1681,19 +1686,19 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
     // scalars loaded first, tested once the first operands are on their way
     int state = state_of(cs, rr), it = cs_int(cs, rr, CS_OFF(iters)),
         restart = cs_int(cs, rr, CS_OFF(restart));
-    double rz0 = cs_dbl(cs, rr, CS_OFF(rzs)), rz1 = cs_dbl(cs, rr, CS_OFF(rzs) + 8);
+    double rz0 = cs_dbl(cs, rr, CS_OFF(rzs)), rz1 = cs_dbl(cs, rr, CS_OFF(rzs) + 8),
+           alpha = cs_dbl(cs, rr, CS_OFF(alpha));
     const size_t o = (size_t)rr * ndof;
     const size_t nb = (size_t)ndof * sizeof(double);
-    const __amdgpu_buffer_rsrc_t bp = make_rsrc(p + o, nb), br = make_rsrc(r + o, nb),
+    const __amdgpu_buffer_rsrc_t bp = make_rsrc(p + o, nb),
                                  bz = make_rsrc(z + o, (size_t)ndof * sizeof(TZ));
-    double pv[VU], zv[VU], rv[VU];
+    double pv[VU], zv[VU];
     auto fetch = [&](long i0) {
 #pragma unroll
       for (int k = 0; k < VU; ++k) {
         const long i = i0 + k * BS;
         pv[k] = bload<double>(bp, (int)(i * sizeof(double)), 0);
         zv[k] = (double)bload<TZ>(bz, (int)(i * sizeof(TZ)), 0);
-        rv[k] = flexible ? bload<double>(br, (int)(i * sizeof(double)), 0) : 0.0;
       }
     };
     long i0 = (long)blockIdx.x * BS * VU + threadIdx.x;
@@ -1705,13 +1710,14 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
     pin(restart);
     pin(rz0);
     pin(rz1);
+    pin(alpha);
     const double rzn = block_sum_finish(sn, sh);
-    const double rzm = flexible ? block_sum_finish(sm, sh) : 0.0;
+    const double qz = flexible ? block_sum_finish(sm, sh) : 0.0;
     if (state != CG_ACTIVE) continue;  // uniform
     const int par = it & 1;
     const double rzo = par ? rz1 : rz0;
-    const bool ok = isfinite(rzn) && isfinite(rzm);
-    const double num = flexible ? (rzn - rzm) : rzn;
+    const bool ok = isfinite(rzn) && isfinite(qz);
+    const double num = flexible ? -alpha * qz : rzn;
     const double b = (!ok || rzo == 0.0 || restart) ? 0.0 : num / rzo;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cs[rr].rzs[par ^ 1] = rzn;
@@ -1722,10 +1728,7 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
 #pragma unroll
       for (int k = 0; k < VU; ++k) {
         const long i = i0 + k * BS;
-        if (i < ndof) {
-          p[o + i] = zv[k] + b * pv[k];
-          if (flexible) rold[o + i] = rv[k];
-        }
+        if (i < ndof) p[o + i] = zv[k] + b * pv[k];
       }
       if (i0 + step < ndof) fetch(i0 + step);
     }
@@ -1733,16 +1736,16 @@ __global__ __launch_bounds__(BS) void k_update_p(const TZ* __restrict__ z, doubl
 }
 
 template <typename TZ>
-void cg_update_p(const TZ* z, double* p, const double* r, double* rold, long ndof, int nrhs,
-                 CgScalars* cs, RedBuf red, int nbz, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_p<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, z, p, r, rold, ndof,
-                     nrhs, cs, red.partials + RED_RZ * RED_REGION, nbz);
+void cg_update_p(const TZ* z, double* p, long ndof, int nrhs, CgScalars* cs, RedBuf red, int nbz,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_update_p<TZ>, dim3(vec_grid(ndof)), dim3(BS), 0, st, z, p, ndof, nrhs, cs,
+                     red.partials + RED_RZ * RED_REGION, nbz);
   MGCG_HIP(hipGetLastError());
 }
-template void cg_update_p<double>(const double*, double*, const double*, double*, long, int,
-                                  CgScalars*, RedBuf, int, hipStream_t);
-template void cg_update_p<float>(const float*, double*, const double*, double*, long, int,
-                                 CgScalars*, RedBuf, int, hipStream_t);
+template void cg_update_p<double>(const double*, double*, long, int, CgScalars*, RedBuf, int,
+                                  hipStream_t);
+template void cg_update_p<float>(const float*, double*, long, int, CgScalars*, RedBuf, int,
+                                 hipStream_t);
 
 // ------------------------------------------------------------ V-cycle
 template <typename T, class In, class Ep>
@@ -1874,9 +1877,9 @@ void v_jacobi_prolong(const VOps<T>& v, const VOps<T>& vc, const T* b, const T* 
 
 template <typename T>
 void v_jacobi_dot(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, const double* r,
-                  const double* rold, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st) {
+                  const double* q, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st) {
   const long nd = v.L.ndof();
-  const EpJacobiDot<T> ep{b, x, v.invD, omega, xo, nd, r, rold};
+  const EpJacobiDot<T> ep{b, x, v.invD, omega, xo, nd, r, q};
   double* part = red.partials + RED_RZ * RED_REGION;
   switch (v.kind) {
     case OP_MF_Q1: run_apply<T>(v.mf, InPlain<T>{x, nd}, ep, nrhs, cs, CG_ACTIVE, st, part); break;

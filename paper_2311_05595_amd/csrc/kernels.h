@@ -152,13 +152,13 @@ void cg_update_xr(const double* p, const double* q, double* x, double* r, long n
 void cg_true_residual(const FineOp& A, const double* f, const double* x, double* r, int nrhs,
                       CgScalars* cs, RedBuf red, VPrep vp, hipStream_t st);
 template <typename TZ>
-void cg_beta(const double* r, const double* rold, const TZ* z, long ndof, int nrhs, CgScalars* cs,
+void cg_beta(const double* r, const double* q, const TZ* z, long ndof, int nrhs, CgScalars* cs,
              RedBuf red, hipStream_t st);
 // nbz: number of r.z partials per load case (cg_beta_blocks, or the blocks of
 // the finest-level fused Jacobi sweep).
 template <typename TZ>
-void cg_update_p(const TZ* z, double* p, const double* r, double* rold, long ndof, int nrhs,
-                 CgScalars* cs, RedBuf red, int nbz, hipStream_t st);
+void cg_update_p(const TZ* z, double* p, long ndof, int nrhs, CgScalars* cs, RedBuf red, int nbz,
+                 hipStream_t st);
 int cg_beta_blocks(long ndof);
 
 // V-cycle level kernels in precision T (gated by any active CG state; cs may be null).
@@ -200,7 +200,7 @@ void v_jacobi(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, int nrhs
 // xo = x + wD (b - A x) and the CG partials r.z, r_old.z of xo (= z)
 template <typename T>
 void v_jacobi_dot(const VOps<T>& v, const T* b, const T* x, T* xo, T omega, const double* r,
-                  const double* rold, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st);
+                  const double* q, int nrhs, const CgScalars* cs, RedBuf red, hipStream_t st);
 // First post-smoothing sweep of a small stencil level fused with the
 // prolongation: xo = y + wD (b - A y) with y = x + P~ e (e on the coarser
 // level vc); y itself is not stored.

@@ -219,7 +219,7 @@ class Problem {
   Budget* budget_ = nullptr;  // context budget this problem is charged to, or null
   void* Kn_ = nullptr;       // Gauss-Seidel smoother: element rows by node, V-cycle precision
   void* Dn_ = nullptr;       // and each node's 3x3 diagonal block
-  double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr, *rold_ = nullptr;
+  double *x_ = nullptr, *r_ = nullptr, *p_ = nullptr, *q_ = nullptr;
   CgScalars* cs_ = nullptr;
   RedBuf red_{nullptr};
   double* compout_ = nullptr;

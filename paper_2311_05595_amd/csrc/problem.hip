@@ -126,7 +126,6 @@ size_t Problem::layout(const mgcg_desc& d, const std::vector<LevelPlan>& lv, cha
   TAKE(r_, double, R * nd0);
   TAKE(p_, double, R * nd0);
   TAKE(q_, double, R * nd0);
-  TAKE(rold_, double, R * nd0);
   TAKE(tmp64_, double, R * nd0);
   TAKE(cs_, CgScalars, 4);
   if (fused_ok(d, lv)) TAKE(fz_, FzDesc, R);
@@ -751,7 +750,7 @@ void Problem::vcycle(const double* r_in, int gate, bool fuse_dot, bool x0_ready)
       if (s == 0 && fuse_p)
         v_jacobi_prolong<T>(v, vops<T>(l + 1), bl[l], cur[l], oth[l], omega, cur[l + 1], R, cs, st);
       else if (l == 0 && fuse_dot && s == d_.post - 1)
-        v_jacobi_dot<T>(v, bl[l], cur[l], oth[l], omega, r_in, rold_, R, cs, red_, st);
+        v_jacobi_dot<T>(v, bl[l], cur[l], oth[l], omega, r_in, q_, R, cs, red_, st);
       else
         v_jacobi<T>(v, bl[l], cur[l], oth[l], omega, R, cs, st);
       if (l == 0) timed_end(2);
@@ -780,12 +779,12 @@ void Problem::precondition_and_direction(bool x0_ready) {
   const int nbz = fuse ? nblocks_fine(vbytes_ == 8) : cg_beta_blocks(nd);
   if (vbytes_ == 8) {
     vcycle<double>(r_, 1, fuse, x0_ready);
-    if (!fuse) cg_beta<double>(r_, rold_, (const double*)zbuf_, nd, R, cs_, red_, st);
-    cg_update_p<double>((const double*)zbuf_, p_, r_, rold_, nd, R, cs_, red_, nbz, st);
+    if (!fuse) cg_beta<double>(r_, q_, (const double*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<double>((const double*)zbuf_, p_, nd, R, cs_, red_, nbz, st);
   } else {
     vcycle<float>(r_, 1, fuse, x0_ready);
-    if (!fuse) cg_beta<float>(r_, rold_, (const float*)zbuf_, nd, R, cs_, red_, st);
-    cg_update_p<float>((const float*)zbuf_, p_, r_, rold_, nd, R, cs_, red_, nbz, st);
+    if (!fuse) cg_beta<float>(r_, q_, (const float*)zbuf_, nd, R, cs_, red_, st);
+    cg_update_p<float>((const float*)zbuf_, p_, nd, R, cs_, red_, nbz, st);
   }
 }
 
@@ -821,7 +820,7 @@ void Problem::solve_begin(double rtol, int maxit, int warm) {
   cg_init_residual(A, f_, x_, r_, R, cs_, red_, st);
   if (from_u && warm == MGCG_WARM_SCALED) cg_scale_warm(f_, x_, r_, nd, R, cs_, red_, st);
   fill<double>(p_, 0.0, R * nd, st);
-  fill<double>(rold_, 0.0, R * nd, st);
+  fill<double>(q_, 0.0, R * nd, st);  // read by the first direction's flexible beta
   iter_launched_ = -1;
   timer_used_base_ = timer_.used;
   precondition_and_direction();

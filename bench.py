@@ -372,7 +372,7 @@ def run(args):
     from paper_2311_05595_amd import api
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (a multi-GPU run is not supported); --gpus must be 1"}))
         sys.exit(2)
     cfg = CF.config(args.config)
     mask, f = CF.problem(cfg)
@@ -1016,30 +1016,30 @@ def main():
         return
     if args.fixing:
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            print(json.dumps({"error": "the benchmark runs on one GPU (a multi-GPU run is not supported); --gpus must be 1"}))
             sys.exit(2)
         run_fixing(args)
         return
     if args.threshold:
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            print(json.dumps({"error": "the benchmark runs on one GPU (a multi-GPU run is not supported); --gpus must be 1"}))
             sys.exit(2)
         run_threshold(args)
         return
     if args.lp:
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            print(json.dumps({"error": "the benchmark runs on one GPU (a multi-GPU run is not supported); --gpus must be 1"}))
             sys.exit(2)
         run_lp(args)
         return
     if args.projection:
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+            print(json.dumps({"error": "the benchmark runs on one GPU (a multi-GPU run is not supported); --gpus must be 1"}))
             sys.exit(2)
         run_projection(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (a multi-GPU run is not supported); --gpus must be 1"}))
         sys.exit(2)
     if args.config == "c5":
         run_served(args)

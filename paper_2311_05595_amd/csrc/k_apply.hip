@@ -2543,11 +2543,27 @@ __device__ __attribute__((noinline)) void fz_mf_apply(const FzDesc& d, const dou
     double E;
     int n0;
   };
+  // q = m quo + rem for q below 2^13 (the element count is at most 6,000):
+  // the single-precision estimate is off by at most one
+  auto divmod = [](int q, int m, int& quo, int& rem) {
+    quo = (int)((float)q * __builtin_amdgcn_rcpf((float)m));
+    rem = q - quo * m;
+    if (rem < 0) {
+      --quo;
+      rem += m;
+    } else if (rem >= m) {
+      ++quo;
+      rem -= m;
+    }
+  };
   auto load = [&](int col, int k, Item& it) {
     const int cx = col & 1, cy = (col >> 1) & 1, cz = col >> 2;
     const int mx = (ex1 - cx + 1) / 2, my = (ey1 - cy + 1) / 2;
     const int q = tid + k * FZ_T;
-    const int ex = cx + 2 * (q % mx), ey = cy + 2 * ((q / mx) % my), ez = cz + 2 * (q / (mx * my));
+    int qy, ix, qz, iy;
+    divmod(q, mx, qy, ix);
+    divmod(qy, my, qz, iy);
+    const int ex = cx + 2 * ix, ey = cy + 2 * iy, ez = cz + 2 * qz;
     it.n0 = ex + L.nx * ey + P * ez;
     it.E = d.E[ex + ex1 * (ey + ey1 * ez)];
 #pragma unroll
